@@ -1,0 +1,261 @@
+"""Interface geometry on the Cartesian grid (oracle; test-only).
+
+Follows Sec. 4.2 (grid, irregular nodes, grid-line/interface intersection points) and
+Sec. 4.3 (interpolation stencil).  The paper does not say how the interface is
+evaluated between markers, how intersections are located, or how nodes are labelled
+inside/outside; the readings used (identical on the GPU side, written independently):
+
+* grid: x_i = x0 + i h, y_j = y0 + j h, i, j = 0..N, h = side/N (Sec. 4.2: N intervals);
+* markers X_k at a_k = 2 pi k/M, counter-clockwise, outward normal (y_a, -x_a)/s_a (App. A);
+* between markers, every marker quantity is interpolated by the 6-point Lagrange
+  polynomial through markers k-2..k+3 in the local variable t = (a - a_k)/da in [0, 1];
+* a marker interval crosses the line y = y_j iff (y_k >= y_j) != (y_{k+1} >= y_j); the
+  crossing parameter solves y_P(t) = y_j by safeguarded Newton (bisection fallback);
+* node (i, j) lies in Omega+ iff the number of row-j crossings with xi < x_i is odd;
+* every marker must stay 3h away from the box boundary; a grid segment holding two
+  crossings, or a label change without a crossing, is a geometry error.
+
+Pinned by: exact crossings of straight/circular curves, label parity vs. a polar
+in/out test on a circle, arm counts (tests/test_oracle_geometry.py).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import spectral
+
+T_NODES = np.arange(-2.0, 4.0)       # Lagrange nodes t_m = m - 2, markers k-2..k+3
+
+
+class GeometryError(RuntimeError):
+    pass
+
+
+def lagrange6(t: np.ndarray):
+    """Weights l_m(t) and derivatives l_m'(t) of the 6-point Lagrange basis on t_m = m-2.
+
+    Returns arrays of shape t.shape + (6,)."""
+    t = np.asarray(t, dtype=np.float64)[..., None]
+    tm = T_NODES
+    w = np.ones(t.shape[:-1] + (6,))
+    dw = np.zeros(t.shape[:-1] + (6,))
+    for m in range(6):
+        denom = 1.0
+        for q in range(6):
+            if q != m:
+                denom *= (tm[m] - tm[q])
+        # l_m(t) = prod_{q != m} (t - t_q) / denom
+        prod = np.ones(t.shape[:-1])
+        for q in range(6):
+            if q != m:
+                prod = prod * (t[..., 0] - tm[q])
+        w[..., m] = prod / denom
+        # derivative: sum_r prod_{q != m, r} (t - t_q) / denom
+        d = np.zeros(t.shape[:-1])
+        for r in range(6):
+            if r == m:
+                continue
+            pr = np.ones(t.shape[:-1])
+            for q in range(6):
+                if q != m and q != r:
+                    pr = pr * (t[..., 0] - tm[q])
+            d = d + pr
+        dw[..., m] = d / denom
+    return w, dw
+
+
+def stencil_markers(k: np.ndarray, M: int) -> np.ndarray:
+    """Marker indices k-2..k+3 (periodic) for intervals k; shape k.shape + (6,)."""
+    return (np.asarray(k)[..., None] + np.arange(-2, 4)) % M
+
+
+@dataclass
+class Markers:
+    X: np.ndarray          # (2, M)
+    xa: np.ndarray
+    ya: np.ndarray
+    xaa: np.ndarray
+    yaa: np.ndarray
+    sa: np.ndarray
+    saa: np.ndarray
+
+    @property
+    def M(self) -> int:
+        return self.X.shape[1]
+
+    @property
+    def normal(self) -> np.ndarray:
+        return np.stack([self.ya, -self.xa]) / self.sa
+
+
+def marker_geometry(X: np.ndarray) -> Markers:
+    """Spectral derivatives of the marker positions (App. A: n = (y_a, -x_a)/s_a,
+    s_a = |X_a|; s_aa = (x_a x_aa + y_a y_aa)/s_a)."""
+    x, y = X
+    xa, ya = spectral.diff(x, 1), spectral.diff(y, 1)
+    xaa, yaa = spectral.diff(x, 2), spectral.diff(y, 2)
+    sa = np.hypot(xa, ya)
+    saa = (xa * xaa + ya * yaa) / sa
+    return Markers(X.copy(), xa, ya, xaa, yaa, sa, saa)
+
+
+def grid_coord(lo: float, h: float, i):
+    return lo + np.asarray(i, dtype=np.float64) * h
+
+
+def _newton_root(c: np.ndarray, target: np.ndarray, a: np.ndarray, b: np.ndarray):
+    """Solve P(t) = target on [0, 1] where P is the Lagrange polynomial with nodal
+    values c (shape (K, 6)); a = P(0) - target, b = P(1) - target have opposite
+    signs under the rule sign(v) = (v >= 0).  Safeguarded Newton: start from the
+    secant point, keep a bracket, bisect whenever Newton leaves it; stop when the
+    update is below 1e-12 (in t) or after 60 iterations."""
+    K = c.shape[0]
+    t = a / (a - b)
+    lo = np.zeros(K)
+    hi = np.ones(K)
+    sa = a >= 0.0
+    done = np.zeros(K, dtype=bool)
+    for _ in range(60):
+        w, dw = lagrange6(t)
+        f = np.sum(w * c, axis=1) - target
+        fp = np.sum(dw * c, axis=1)
+        same = (f >= 0.0) == sa
+        lo = np.where(same & ~done, t, lo)
+        hi = np.where(~same & ~done, t, hi)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tn = t - f / fp
+        bad = ~np.isfinite(tn) | (tn <= lo) | (tn >= hi)
+        tn = np.where(bad, 0.5 * (lo + hi), tn)
+        tn = np.where(f == 0.0, t, tn)
+        step = np.abs(tn - t)
+        t = np.where(done, t, tn)
+        done = done | (step <= 1e-12)
+        if done.all():
+            break
+    return t
+
+
+@dataclass
+class Crossings:
+    """Intersections of the interface with grid lines."""
+    line: np.ndarray       # j (horizontal lines y = y_j) or i (vertical lines x = x_i)
+    k: np.ndarray          # marker interval
+    t: np.ndarray          # local parameter in [0, 1]
+    pos: np.ndarray        # x-coordinate (horizontal lines) or y-coordinate (vertical)
+    seg: np.ndarray        # grid segment index: node index m with g_m <= pos < g_{m+1}
+
+
+def find_crossings(mk: Markers, lo: float, h: float, N: int, axis: int) -> Crossings:
+    """Crossings with lines y = y_j (axis=1: the varying coordinate is y) or x = x_i
+    (axis=0), lines 1..N-1 (Sec. 4.2: intersection point (xi, y_j))."""
+    M = mk.M
+    v = mk.X[axis]                 # coordinate compared with the line
+    other = mk.X[1 - axis]
+    k = np.arange(M)
+    v0, v1 = v, np.roll(v, -1)
+    vmin, vmax = np.minimum(v0, v1), np.maximum(v0, v1)
+    # lines g_j with vmin < g_j <= vmax  <=>  (v0 >= g) != (v1 >= g)
+    jl = np.floor((vmin - lo) / h).astype(np.int64) - 1
+    jh = np.floor((vmax - lo) / h).astype(np.int64) + 1
+    ks, js = [], []
+    for kk in range(M):
+        for j in range(max(jl[kk], 1), min(jh[kk], N - 1) + 1):
+            g = lo + j * h
+            if (v0[kk] >= g) != (v1[kk] >= g):
+                ks.append(kk)
+                js.append(j)
+    ks = np.array(ks, dtype=np.int64)
+    js = np.array(js, dtype=np.int64)
+    if ks.size == 0:
+        return Crossings(js, ks, np.zeros(0), np.zeros(0), js.copy())
+    g = lo + js * h
+    idx = stencil_markers(ks, M)
+    c = v[idx]
+    t = _newton_root(c, g, v0[ks] - g, v1[ks] - g)
+    w, _ = lagrange6(t)
+    pos = np.sum(w * other[idx], axis=1)
+    seg = np.floor((pos - lo) / h).astype(np.int64)
+    # exact placement: lo + seg*h <= pos < lo + (seg+1)*h
+    for _ in range(2):
+        seg = np.where(lo + (seg + 1) * h <= pos, seg + 1, seg)
+        seg = np.where(lo + seg * h > pos, seg - 1, seg)
+    return Crossings(js, ks, t, pos, seg)
+
+
+@dataclass
+class Geometry:
+    box: object            # workloads.Box-like (x0, y0, side, N)
+    mk: Markers
+    hx: Crossings          # horizontal-line crossings (pos = xi)
+    vx: Crossings          # vertical-line crossings (pos = eta)
+    inside: np.ndarray     # (N+1, N+1) bool, indexed [j, i]; True = Omega+
+    arms: dict = field(default_factory=dict)
+
+
+def build_geometry(X: np.ndarray, box) -> Geometry:
+    N, h = box.N, box.side / box.N
+    x0, y0 = box.x0, box.y0
+    mk = marker_geometry(np.asarray(X, dtype=np.float64))
+    margin = 3.0 * h
+    if (mk.X[0].min() < x0 + margin or mk.X[0].max() > x0 + box.side - margin or
+            mk.X[1].min() < y0 + margin or mk.X[1].max() > y0 + box.side - margin):
+        raise GeometryError("interface closer than 3h to the box boundary")
+    hx = find_crossings(mk, y0, h, N, axis=1)
+    vx = find_crossings(mk, x0, h, N, axis=0)
+    xi = grid_coord(x0, h, np.arange(N + 1))
+    inside = np.zeros((N + 1, N + 1), dtype=bool)
+    for j in range(1, N):
+        sel = hx.line == j
+        xs = np.sort(hx.pos[sel])
+        cnt = np.searchsorted(xs, xi, side="left")     # #{xi_c < x_i}
+        inside[j] = (cnt % 2) == 1
+    g = Geometry(box, mk, hx, vx, inside)
+    _check_and_build_arms(g)
+    return g
+
+
+def _check_and_build_arms(g: Geometry):
+    N = g.box.N
+    lab = g.inside
+    # horizontal segments: (i, j)-(i+1, j); crossings keyed by (j, seg)
+    hkey = g.hx.line * (N + 1) + g.hx.seg
+    vkey = g.vx.line * (N + 1) + g.vx.seg
+    if np.unique(hkey).size != hkey.size or np.unique(vkey).size != vkey.size:
+        raise GeometryError("a grid segment holds two interface crossings")
+    if (np.any((g.hx.seg < 0) | (g.hx.seg >= N)) or np.any((g.vx.seg < 0) | (g.vx.seg >= N))):
+        raise GeometryError("crossing outside the grid")
+    # label changes along rows <-> horizontal crossings
+    dh = lab[:, 1:] != lab[:, :-1]          # [j, i] segment (i, i+1)
+    dv = lab[1:, :] != lab[:-1, :]          # [j, i] segment (j, j+1) on column i
+    hset = np.zeros_like(dh)
+    hset[g.hx.line, g.hx.seg] = True
+    vset = np.zeros_like(dv)
+    vset[g.vx.seg, g.vx.line] = True
+    if not np.array_equal(dh, hset):
+        raise GeometryError("horizontal labels and crossings disagree")
+    if not np.array_equal(dv, vset):
+        raise GeometryError("vertical labels and crossings disagree")
+    # irregular arms P -> Q, P interior: list of (iP, jP, iQ, jQ, crossing id, horizontal?)
+    arms = []
+    for c in range(g.hx.line.size):
+        j, s = int(g.hx.line[c]), int(g.hx.seg[c])
+        for (ip, iq) in ((s, s + 1), (s + 1, s)):
+            if 1 <= ip <= N - 1:
+                arms.append((ip, j, iq, j, c, 1))
+    for c in range(g.vx.line.size):
+        i, s = int(g.vx.line[c]), int(g.vx.seg[c])
+        for (jp, jq) in ((s, s + 1), (s + 1, s)):
+            if 1 <= jp <= N - 1:
+                arms.append((i, jp, i, jq, c, 0))
+    g.arms = np.array(arms, dtype=np.int64).reshape(-1, 6)
+
+
+def interpolate_at(values: np.ndarray, k: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """6-point Lagrange interpolation of marker values (..., M) at (interval k, t)."""
+    M = values.shape[-1]
+    idx = stencil_markers(k, M)
+    w, _ = lagrange6(t)
+    return np.sum(w * values[..., idx], axis=-1)

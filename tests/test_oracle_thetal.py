@@ -1,0 +1,63 @@
+"""Pins for oracle.thetal (Sec. 5): circle growth law, area conservation, resampling."""
+import numpy as np
+import pytest
+
+from oracle import spectral
+from oracle import thetal as T
+from paper_2309_01068_amd import workloads as W
+
+
+def test_equal_arclength_resampling():
+    X = W.ellipse(256, 0.6, 0.4)
+    eta, L, Xb = T.equal_arclength_init(X)
+    Xr, theta, n, s = T.reconstruct(eta, L, Xb)
+    sa = np.hypot(spectral.diff(Xr[0]), spectral.diff(Xr[1]))
+    assert np.max(np.abs(sa - L / (2 * np.pi))) < 1e-9    # |X_a| = L/2pi: equal arclength
+    # reconstructed points lie on the ellipse
+    assert np.max(np.abs((Xr[0] / 0.6) ** 2 + (Xr[1] / 0.4) ** 2 - 1.0)) < 1e-10
+    # ellipse perimeter (Ramanujan II is accurate to ~1e-10 here)
+    a, b = 0.6, 0.4
+    hh = ((a - b) / (a + b)) ** 2
+    per = np.pi * (a + b) * (1 + 3 * hh / (10 + np.sqrt(4 - 3 * hh)))
+    assert abs(L - per) < 1e-8
+
+
+def test_circle_growth_law():
+    """A circle with injection J grows as R(t) = sqrt(R0^2 + 2 J t) (U = J/R)."""
+    R0 = 0.5
+    X = W.circle(64, R0)
+    eta, L, Xb = T.equal_arclength_init(X)
+    prm = T.HSParams(sigma=1e-3, J=1.0, tau=2e-3, box=W.box(-1.5, 1.5, 96))
+    st = T.HSState(eta, L, Xb)
+    for _ in range(10):
+        st, info = T.hs_step(st, prm)
+    R = st.L / (2 * np.pi)
+    assert abs(R - np.sqrt(R0 ** 2 + 2 * st.t)) < 2e-5
+    assert np.max(np.abs(st.Xbar)) < 1e-8
+    assert np.std(st.eta) < 1e-8
+
+
+@pytest.mark.slow
+def test_area_conserved_and_length_decreasing_without_injection():
+    X = W.polar_curve(lambda a: 0.8 + 0.2 * np.cos(4 * a), 128)
+    eta, L, Xb = T.equal_arclength_init(X)
+    prm = T.HSParams(sigma=1e-2, J=0.0, tau=2e-3, box=W.box(-1.5, 1.5, 96))
+    st = T.HSState(eta, L, Xb)
+    areas, lengths = [], []
+    for _ in range(12):
+        st, info = T.hs_step(st, prm)
+        areas.append(info.area)
+        lengths.append(info.length)
+    areas = np.array(areas)
+    assert np.max(np.abs(areas - areas[0])) < 1e-3 * areas[0]
+    assert np.all(np.diff(lengths) < 0)
+
+
+def test_ssd_linear_term_is_damping():
+    """The stiff term L_2 = lambda (2pi/L)^3 H[theta_aaa] has Fourier symbol -|k|^3 (Sec. 5.3)."""
+    M = 64
+    a = 2 * np.pi * np.arange(M) / M
+    for k in (1, 3, 10):
+        f = np.cos(k * a)
+        out = spectral.hilbert(spectral.diff(f, 3))
+        assert np.allclose(out, -k ** 3 * f, atol=1e-9)
