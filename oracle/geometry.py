@@ -13,7 +13,10 @@ inside/outside; the readings used (identical on the GPU side, written independen
   crossing parameter solves y_P(t) = y_j by safeguarded Newton (bisection fallback);
 * node (i, j) lies in Omega+ iff the number of row-j crossings with xi < x_i is odd;
 * every marker must stay 3h away from the box boundary; a grid segment holding two
-  crossings, or a label change without a crossing, is a geometry error.
+  crossings, or a label change without a crossing, is a geometry error;
+* a column crossing within 1e-9 h of a grid node may move to the adjacent column
+  segment so that it sits where the row-based labels change (the interface passes
+  through that node up to rounding).
 
 Pinned by: exact crossings of straight/circular curves, label parity vs. a polar
 in/out test on a circle, arm counts (tests/test_oracle_geometry.py).
@@ -217,16 +220,46 @@ def build_geometry(X: np.ndarray, box) -> Geometry:
     return g
 
 
+def _snap_vertical(g: Geometry):
+    """Assign each column crossing to the column segment whose end labels differ.
+
+    Labels come from row crossings, column crossings from a separate root solve, so when
+    the interface passes within rounding of a grid node the two can disagree by one
+    segment.  Reading: a column crossing lying within 1e-9 h of a segment end moves to
+    the neighbouring segment if only that one changes label; otherwise the geometry is
+    rejected."""
+    N, h = g.box.N, g.box.side / g.box.N
+    y0 = g.box.y0
+    lab = g.inside
+    tol = 1e-9 * h
+    seg = g.vx.seg.copy()
+    for c in range(seg.size):
+        i, s, eta = int(g.vx.line[c]), int(seg[c]), g.vx.pos[c]
+
+        def flips(t):
+            return 0 <= t <= N - 1 and lab[t, i] != lab[t + 1, i]
+        if flips(s):
+            continue
+        if eta - (y0 + s * h) <= tol and flips(s - 1):
+            seg[c] = s - 1
+        elif (y0 + (s + 1) * h) - eta <= tol and flips(s + 1):
+            seg[c] = s + 1
+        else:
+            raise GeometryError("vertical labels and crossings disagree")
+    g.vx.seg = seg
+
+
 def _check_and_build_arms(g: Geometry):
     N = g.box.N
     lab = g.inside
+    if np.any((g.hx.seg < 0) | (g.hx.seg >= N)) or np.any((g.vx.seg < 0) | (g.vx.seg >= N)):
+        raise GeometryError("crossing outside the grid")
+    _snap_vertical(g)
     # horizontal segments: (i, j)-(i+1, j); crossings keyed by (j, seg)
     hkey = g.hx.line * (N + 1) + g.hx.seg
     vkey = g.vx.line * (N + 1) + g.vx.seg
     if np.unique(hkey).size != hkey.size or np.unique(vkey).size != vkey.size:
         raise GeometryError("a grid segment holds two interface crossings")
-    if (np.any((g.hx.seg < 0) | (g.hx.seg >= N)) or np.any((g.vx.seg < 0) | (g.vx.seg >= N))):
-        raise GeometryError("crossing outside the grid")
     # label changes along rows <-> horizontal crossings
     dh = lab[:, 1:] != lab[:, :-1]          # [j, i] segment (i, i+1)
     dv = lab[1:, :] != lab[:-1, :]          # [j, i] segment (j, j+1) on column i

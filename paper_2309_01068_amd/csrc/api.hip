@@ -1,0 +1,285 @@
+// C ABI entry points: context life cycle, interface installation, apply, operator.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace kfbi {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int DBuf::ensure(size_t need) {
+  if (need <= bytes) return KFBI_OK;
+  if (p) {
+    hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  if (need == 0) return KFBI_OK;
+  hipError_t e = hipMalloc(&p, need);
+  if (e != hipSuccess) {
+    p = nullptr;
+    set_error("hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
+    return KFBI_E_NOMEM;
+  }
+  bytes = need;
+  return KFBI_OK;
+}
+
+void DBuf::release() {
+  if (p) hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+__global__ void k_sintab(int N, double* __restrict__ s64, float* __restrict__ s32) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= 2 * N) return;
+  const double v = sinpi(static_cast<double>(m) / N);
+  s64[m] = v;
+  s32[m] = static_cast<float>(v);
+}
+
+static int check_ctx(const kfbi_ctx* c, bool need_iface) {
+  if (!c) {
+    set_error("null context");
+    return KFBI_E_INVALID;
+  }
+  if (need_iface && !c->have_interface) {
+    set_error("no interface installed (call kfbi_set_interface first)");
+    return KFBI_E_STATE;
+  }
+  return KFBI_OK;
+}
+
+static void release_all(kfbi_ctx* c) {
+  DBuf* bufs[] = {&c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
+                  &c->vid,    &c->lab,    &c->armcnt, &c->rowsum,  &c->armrow, &c->armi,
+                  &c->armcoef, &c->armint, &c->intptr, &c->need,    &c->nodeidx, &c->nodei,
+                  &c->rowptr, &c->rows,   &c->mknode, &c->ext,     &c->gstat,  &c->mq,
+                  &c->armr,   &c->qpart,  &c->ring,   &c->sinT,    &c->sinT32, &c->gband,
+                  &c->nodeval, &c->tmpM,  &c->gV,     &c->gH,      &c->gsc,    &c->gpart,
+                  &c->gcnt,   &c->gw,     &c->gx,     &c->gr,      &c->gd};
+  for (DBuf* b : bufs) b->release();
+  for (int i = 0; i < kfbi_ctx::kProfPool; ++i)
+    if (c->prof_ev[i]) hipEventDestroy(c->prof_ev[i]);
+  if (c->hpin) hipHostFree(c->hpin);
+  c->hpin = nullptr;
+}
+
+}  // namespace kfbi
+
+using namespace kfbi;
+
+extern "C" {
+
+const char* kfbi_last_error(void) { return kfbi::g_err; }
+
+int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
+  if (!g || !out) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  *out = nullptr;
+  const int N = g->N;
+  if (N < 64 || N > 4096 || (N & (N - 1)) != 0) {
+    set_error("N must be a power of two in [64, 4096] (got %d)", N);
+    return KFBI_E_INVALID;
+  }
+  if (!(g->side > 0.0) || !(g->c2 >= 0.0) || !std::isfinite(g->x0) || !std::isfinite(g->y0)) {
+    set_error("invalid box or c2");
+    return KFBI_E_INVALID;
+  }
+  if (g->box_bc < KFBI_BOX_ZERO || g->box_bc > KFBI_BOX_FREESPACE) {
+    set_error("invalid box_bc %d", g->box_bc);
+    return KFBI_E_INVALID;
+  }
+  if (g->box_bc == KFBI_BOX_FREESPACE && g->c2 != 0.0) {
+    set_error("free-space box data is defined for the Laplacian (c2 == 0) only");
+    return KFBI_E_INVALID;
+  }
+  if (g->max_markers < 16 || g->max_markers > 4096) {
+    set_error("max_markers must be in [16, 4096]");
+    return KFBI_E_INVALID;
+  }
+  kfbi_ctx* c = new (std::nothrow) kfbi_ctx();
+  if (!c) {
+    set_error("out of host memory");
+    return KFBI_E_NOMEM;
+  }
+  c->x0 = g->x0;
+  c->y0 = g->y0;
+  c->side = g->side;
+  c->N = N;
+  c->h = g->side / N;
+  c->c2 = g->c2;
+  c->box_bc = g->box_bc;
+  c->max_markers = g->max_markers;
+  c->stream = static_cast<hipStream_t>(g->stream);
+  int st = KFBI_OK;
+  auto fail = [&](int code) {
+    release_all(c);
+    delete c;
+    return code;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    set_error("hipGetDevice failed");
+    return fail(KFBI_E_HIP);
+  }
+  const size_t n1sq = static_cast<size_t>(N + 1) * (N + 1);
+  const size_t n = N - 1;
+  const int Mx = g->max_markers;
+  if ((st = c->gstat.ensure(sizeof(GeoStatus))) ||
+      (st = c->hid.ensure(sizeof(int) * n1sq)) || (st = c->vid.ensure(sizeof(int) * n1sq)) ||
+      (st = c->lab.ensure(n1sq)) || (st = c->need.ensure(sizeof(int) * n1sq)) ||
+      (st = c->nodeidx.ensure(sizeof(int) * n1sq)) ||
+      (st = c->rowsum.ensure(sizeof(int) * (2 * (N + 1) + 2))) ||
+      (st = c->armrow.ensure(sizeof(int) * (N + 2))) ||
+      (st = c->rows.ensure(sizeof(int) * (N + 2))) ||
+      (st = c->rowptr.ensure(sizeof(int) * (N + 2))) ||
+      (st = c->nodei.ensure(sizeof(int) * 6 * Mx)) ||
+      (st = c->nodeval.ensure(sizeof(double) * 6 * Mx)) ||
+      (st = c->mq.ensure(sizeof(double) * 5 * Mx)) ||
+      (st = c->qpart.ensure(sizeof(double) * (Mx + 64))) ||
+      (st = c->ring.ensure(sizeof(double) * 4 * (N + 1))) ||
+      (st = c->sinT.ensure(sizeof(double) * 2 * N)) ||
+      (st = c->sinT32.ensure(sizeof(float) * 2 * N)) ||
+      (st = c->gband.ensure(sizeof(double) * n * N)) ||
+      (st = c->tmpM.ensure(sizeof(double) * 4 * Mx)))
+    return fail(st);
+  if (hipHostMalloc(&c->hpin, 4096, hipHostMallocDefault) != hipSuccess) {
+    set_error("hipHostMalloc failed");
+    return fail(KFBI_E_NOMEM);
+  }
+  hipLaunchKernelGGL(k_sintab, dim3((2 * N + 255) / 256), dim3(256), 0, c->stream, N,
+                     c->sinT.as<double>(), c->sinT32.as<float>());
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    set_error("sine table kernel failed");
+    return fail(KFBI_E_HIP);
+  }
+  *out = c;
+  return KFBI_OK;
+}
+
+int kfbi_destroy(kfbi_ctx* c) {
+  if (!c) return KFBI_OK;
+  hipStreamSynchronize(c->stream);
+  release_all(c);
+  delete c;
+  return KFBI_OK;
+}
+
+int kfbi_set_interface(kfbi_ctx* c, int M, const double* xy) {
+  KFBI_TRY(check_ctx(c, false));
+  if (!xy || M < 16 || M > c->max_markers || (M & 1)) {
+    set_error("M must be even and in [16, max_markers] with a non-null xy (M=%d)", M);
+    return KFBI_E_INVALID;
+  }
+  c->have_interface = 0;
+  const int st = geometry_setup(c, M, xy);
+  if (st != KFBI_OK) return st;
+  c->mk_chunk = M >= 2048 ? M / 256 : 8;
+  c->n_mk_blocks = (M + c->mk_chunk - 1) / c->mk_chunk;
+  c->have_interface = 1;
+  return KFBI_OK;
+}
+
+int kfbi_get_info(const kfbi_ctx* c, kfbi_info* info) {
+  KFBI_TRY(check_ctx(c, true));
+  if (!info) {
+    set_error("null info");
+    return KFBI_E_INVALID;
+  }
+  info->M = c->M;
+  info->n_cross_h = c->st.n_cross_h;
+  info->n_cross_v = c->st.n_cross_v;
+  info->n_arms = c->st.n_arms;
+  info->n_nodes = c->st.n_nodes;
+  info->n_rows = c->st.n_rows;
+  info->row_lo = c->st.row_lo;
+  info->row_hi = c->st.row_hi;
+  return KFBI_OK;
+}
+
+int kfbi_apply(kfbi_ctx* c, int layer, int precision, const double* dens, const double* ring,
+               const kfbi_out* out) {
+  KFBI_TRY(check_ctx(c, true));
+  if (!dens || !out) {
+    set_error("null density or output struct");
+    return KFBI_E_INVALID;
+  }
+  if (layer != KFBI_SINGLE && layer != KFBI_DOUBLE) {
+    set_error("invalid layer %d", layer);
+    return KFBI_E_INVALID;
+  }
+  if (precision != KFBI_FP64 && precision != KFBI_FP32) {
+    set_error("invalid precision %d", precision);
+    return KFBI_E_INVALID;
+  }
+  if ((c->box_bc == KFBI_BOX_USER) != (ring != nullptr)) {
+    set_error("ring values must be given exactly when box_bc == KFBI_BOX_USER");
+    return KFBI_E_INVALID;
+  }
+  return apply_impl(c, layer, precision, dens, ring, out, nullptr, nullptr, nullptr);
+}
+
+int kfbi_operator(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* x, double* y) {
+  KFBI_TRY(check_ctx(c, true));
+  if (!op || !x || !y) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  if ((op->layer != KFBI_SINGLE && op->layer != KFBI_DOUBLE) || op->side < KFBI_PLUS ||
+      op->side > KFBI_AVG || (precision != KFBI_FP64 && precision != KFBI_FP32)) {
+    set_error("invalid operator description");
+    return KFBI_E_INVALID;
+  }
+  if (c->box_bc == KFBI_BOX_USER) {
+    set_error("the boundary operator needs box data defined by the density (ZERO or FREESPACE)");
+    return KFBI_E_INVALID;
+  }
+  return apply_impl(c, op->layer, precision, x, nullptr, nullptr, op, x, y);
+}
+
+int kfbi_profile(kfbi_ctx* c, int on) {
+  KFBI_TRY(check_ctx(c, false));
+  if (on) {
+    for (int i = 0; i < kfbi_ctx::kProfPool; ++i)
+      if (!c->prof_ev[i]) KFBI_HIP(hipEventCreate(&c->prof_ev[i]));
+    KFBI_HIP(hipStreamSynchronize(c->stream));
+    c->prof_used = 0;
+    c->prof_count = 0;
+    for (double& v : c->prof_ms) v = 0.0;
+    c->prof_on = 1;
+  } else {
+    if (c->prof_on) KFBI_TRY(prof_flush(c));
+    c->prof_on = 0;
+  }
+  return KFBI_OK;
+}
+
+int kfbi_profile_read(kfbi_ctx* c, double* ms_total, long* napplies) {
+  KFBI_TRY(check_ctx(c, false));
+  if (!ms_total || !napplies) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  if (c->prof_on) KFBI_TRY(prof_flush(c));
+  for (int q = 0; q < 4; ++q) ms_total[q] = c->prof_ms[q];
+  *napplies = c->prof_count;
+  return KFBI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+// Internal declarations of the gfx950 KFBI library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/kfbi.h"
+
+namespace kfbi {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------- error plumbing
+void set_error(const char* fmt, ...);
+
+#define KFBI_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::kfbi::set_error("%s failed at %s:%d: %s", #call, __FILE__, __LINE__,        \
+                        hipGetErrorString(e_));                                     \
+      return KFBI_E_HIP;                                                            \
+    }                                                                               \
+  } while (0)
+
+#define KFBI_TRY(expr)               \
+  do {                               \
+    int s_ = (expr);                 \
+    if (s_ != KFBI_OK) return s_;    \
+  } while (0)
+
+// Device buffer that grows, never shrinks; freed by the context.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Per-crossing record (horizontal: line = j, pos = xi; vertical: line = i, pos = eta).
+struct Crossing {
+  int line;
+  int k;      // marker interval [a_k, a_{k+1}]
+  int seg;    // grid segment: node index m with g_m <= pos < g_{m+1}
+  int horiz;  // 1 = row crossing, 0 = column crossing
+  double t;   // local parameter in [0, 1]
+  double pos;
+};
+
+// Per-marker extraction data (Sec. 4.3), all FP64:
+//   W[3][6]  rows of the inverse 6x6 Taylor system giving v+, v+_x, v+_y from grid values
+//   E[3][5]  jump-correction part: maps the marker quantities (Phi, Phi_a, Phi_aa, Psi,
+//            Psi_a) to the contribution of chi(q_m) C(q_m) to (v+, v+_x, v+_y)
+//   D[3][5]  maps the same quantities to the jumps ([v], [v_x], [v_y]) at the marker
+//   nx, ny   outward unit normal; wq = s_a 2 pi / M (trapezoid weight)
+struct MarkerExt {
+  double W[18];
+  double E[15];
+  double D[15];
+  double nx, ny, wq, pad;
+};
+
+// Per-arm data (Sec. 4.2.1): correction value r = sum_m l_m sum_q coef_q Q_q(k-2+m).
+struct ArmCoef {
+  double l[6];
+  double coef[5];
+  int k;
+  int pad;
+};
+
+// Status words written by the geometry kernels.
+struct GeoStatus {
+  int err;          // 0 or an error code (1: two crossings in a segment, 2: label mismatch,
+                    // 3: margin, 4: capacity, 5: crossing outside grid)
+  int n_cross_h, n_cross_v;
+  int n_arms;
+  int n_nodes;
+  int n_rows;
+  int row_lo, row_hi;
+};
+
+}  // namespace kfbi
+
+struct kfbi_ctx {
+  // grid
+  double x0, y0, side, h;
+  int N;
+  double c2;
+  int box_bc;
+  int max_markers;
+  hipStream_t stream;
+  int device;
+
+  // interface sizes (host copies, valid after set_interface)
+  int M = 0;
+  int have_interface = 0;
+  kfbi::GeoStatus st{};
+  int d_M = 0;  // M for which the differentiation vectors are built
+
+  // geometry buffers
+  kfbi::DBuf X, geo, dvec, cnt, cross, hid, vid, lab, armcnt, rowsum, armrow, armi, armcoef,
+      armint, intptr, need, nodeidx, nodei, rowptr, rows, mknode, ext, gstat;
+  // per-apply buffers
+  kfbi::DBuf mq, armr, qpart, ring, sinT, sinT32, gband, nodeval, tmpM;
+  // gmres buffers
+  kfbi::DBuf gV, gH, gsc, gpart, gcnt, gw, gx, gr, gd;
+  // pinned host status
+  void* hpin = nullptr;
+
+  // stage profiling with HIP events (kfbi_profile)
+  int prof_on = 0;
+  static constexpr int kProfPool = 320;  // 64 applies x 5 events
+  hipEvent_t prof_ev[kProfPool] = {};
+  int prof_used = 0;
+  double prof_ms[4] = {0, 0, 0, 0};
+  long prof_count = 0;
+
+  // apply launch geometry (set by set_interface)
+  int mk_chunk = 8;   // markers per K1 block
+  int n_mk_blocks = 0;
+  int n_ring_blocks = 0;
+};
+
+namespace kfbi {
+// stage entry points (implemented in the .hip files)
+int geometry_setup(kfbi_ctx* c, int M, const double* xy);
+int apply_impl(kfbi_ctx* c, int layer, int precision, const double* dens, const double* ring_user,
+               const kfbi_out* out, const kfbi_bie* op, const double* x_for_op, double* y_op);
+int ensure_apply_buffers(kfbi_ctx* c);
+int prof_flush(kfbi_ctx* c);
+}  // namespace kfbi

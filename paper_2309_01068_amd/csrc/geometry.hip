@@ -1,0 +1,700 @@
+// Per-interface geometry on gfx950 (run once per time step by kfbi_set_interface).
+//
+// Sec. 4.2: grid, irregular nodes and the grid-line / interface intersection points;
+// Sec. 4.3: interpolation stencil {(0,0),(1,0),(0,1),(0,-1),(-1,0),(d1,d2)} around the
+// closest node; App. A.1: jump values from the interface data; Sec. 5.3 (remark):
+// derivatives of periodic interface quantities in Fourier space.
+//
+// Readings fixed here (the paper leaves them open): interface quantities between markers
+// come from the 6-point Lagrange polynomial through markers k-2..k+3; a marker interval
+// crosses the line g iff (v_k >= g) != (v_{k+1} >= g); the crossing is the root of the
+// Lagrange polynomial found by safeguarded Newton; node (i, j) is inside iff an odd number
+// of row-j crossings lie strictly left of x_i; closest node = floor(t + 1/2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "device_util.h"
+
+namespace kfbi {
+
+// --------------------------------------------------------------- differentiation vectors
+// Circulant form of Fourier differentiation on M equispaced samples (Nyquist mode dropped):
+//   f'(a_l)  = sum_m d1[(l - m) mod M] f_m,  d1[q] = -(2/M) sum_{k=1}^{M/2-1} k   sin(k a_q)
+//   f''(a_l) = sum_m d2[(l - m) mod M] f_m,  d2[q] = -(2/M) sum_{k=1}^{M/2-1} k^2 cos(k a_q)
+__global__ void k_diffvec(int M, double* __restrict__ d1, double* __restrict__ d2) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= M) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = 1; k < M / 2; ++k) {
+    const long long r = (static_cast<long long>(k) * q) % M;
+    double sn, cs;
+    sincospi(2.0 * static_cast<double>(r) / M, &sn, &cs);
+    s1 += k * sn;
+    s2 += static_cast<double>(k) * k * cs;
+  }
+  d1[q] = -2.0 * s1 / M;
+  d2[q] = -2.0 * s2 / M;
+}
+
+// Marker geometry: x_a, y_a, x_aa, y_aa, s_a, s_aa (App. A: n = (y_a, -x_a)/s_a) and the
+// 3h margin test against the box.
+__global__ void k_marker_geo(int M, const double* __restrict__ X, const double* __restrict__ d1,
+                             const double* __restrict__ d2, double* __restrict__ geo, double lox,
+                             double hix, double loy, double hiy, GeoStatus* st) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const double* x = X;
+  const double* y = X + M;
+  double xa = 0, ya = 0, xaa = 0, yaa = 0;
+  for (int m = 0; m < M; ++m) {
+    int q = k - m;
+    q += (q < 0) ? M : 0;
+    const double a1 = d1[q], a2 = d2[q], xm = x[m], ym = y[m];
+    xa += a1 * xm;
+    ya += a1 * ym;
+    xaa += a2 * xm;
+    yaa += a2 * ym;
+  }
+  const double sa = sqrt(xa * xa + ya * ya);
+  geo[k] = xa;
+  geo[M + k] = ya;
+  geo[2 * M + k] = xaa;
+  geo[3 * M + k] = yaa;
+  geo[4 * M + k] = sa;
+  geo[5 * M + k] = (xa * xaa + ya * yaa) / sa;
+  if (!(x[k] >= lox && x[k] <= hix && y[k] >= loy && y[k] <= hiy)) atomicMax(&st->err, 3);
+}
+
+// Lines g_j = lo + j h, j = 1..N-1, crossed by the marker interval (v0, v1).
+__device__ inline void line_range(double v0, double v1, double lo, double h, int N, int* jb,
+                                  int* je) {
+  const double vmin = fmin(v0, v1), vmax = fmax(v0, v1);
+  int a = static_cast<int>(floor((vmin - lo) / h)) - 1;
+  int b = static_cast<int>(floor((vmax - lo) / h)) + 1;
+  *jb = a < 1 ? 1 : a;
+  *je = b > N - 1 ? N - 1 : b;
+}
+
+__global__ void k_count_cross(int M, const double* __restrict__ X, double x0, double y0, double h,
+                              int N, int* __restrict__ cnt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const int k1 = (k + 1 == M) ? 0 : k + 1;
+  for (int ax = 0; ax < 2; ++ax) {
+    // ax = 0: rows y = y_j (compare y); ax = 1: columns x = x_i (compare x)
+    const double* v = (ax == 0) ? X + M : X;
+    const double lo = (ax == 0) ? y0 : x0;
+    const double v0 = v[k], v1 = v[k1];
+    int jb, je, c = 0;
+    line_range(v0, v1, lo, h, N, &jb, &je);
+    for (int j = jb; j <= je; ++j) {
+      const double g = lo + j * h;
+      c += ((v0 >= g) != (v1 >= g)) ? 1 : 0;
+    }
+    cnt[ax * M + k] = c;
+  }
+}
+
+// Single-block exclusive scan of n ints in place; total to *total.
+__global__ void k_scan_inplace(int n, int* __restrict__ a, int* __restrict__ total) {
+  __shared__ int scratch[17];
+  const int T = blockDim.x;
+  const int per = (n + T - 1) / T;
+  const int b = threadIdx.x * per;
+  const int e = min(n, b + per);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += a[i];
+  int tot;
+  int off = block_excl_scan(s, scratch, &tot);
+  for (int i = b; i < e; ++i) {
+    int v = a[i];
+    a[i] = off;
+    off += v;
+  }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
+// Safeguarded Newton for P(t) = g on [0, 1], P the Lagrange polynomial with nodal values c.
+__device__ inline double newton_root(const double* c, double g, double a, double b) {
+  double t = a / (a - b);
+  double lo = 0.0, hi = 1.0;
+  const bool sa = (a >= 0.0);
+  for (int it = 0; it < 60; ++it) {
+    double w[6], dw[6];
+    lagrange6(t, w, dw);
+    double f = -g, fp = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      f += w[m] * c[m];
+      fp += dw[m] * c[m];
+    }
+    const bool same = ((f >= 0.0) == sa);
+    if (same)
+      lo = t;
+    else
+      hi = t;
+    double tn = t - f / fp;
+    if (!isfinite(tn) || tn <= lo || tn >= hi) tn = 0.5 * (lo + hi);
+    if (f == 0.0) tn = t;
+    const double step = fabs(tn - t);
+    t = tn;
+    if (step <= 1e-12) break;
+  }
+  return t;
+}
+
+__global__ void k_fill_cross(int M, const double* __restrict__ X, double x0, double y0, double h,
+                             int N, const int* __restrict__ off, int nh, Crossing* __restrict__ cr,
+                             int cap, GeoStatus* st) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const int k1 = (k + 1 == M) ? 0 : k + 1;
+  for (int ax = 0; ax < 2; ++ax) {
+    const double* v = (ax == 0) ? X + M : X;
+    const double* o = (ax == 0) ? X : X + M;
+    const double lo = (ax == 0) ? y0 : x0;
+    const double olo = (ax == 0) ? x0 : y0;
+    const double v0 = v[k], v1 = v[k1];
+    double cv[6], co[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      int q = k - 2 + m;
+      q = (q < 0) ? q + M : (q >= M ? q - M : q);
+      cv[m] = v[q];
+      co[m] = o[q];
+    }
+    int jb, je;
+    line_range(v0, v1, lo, h, N, &jb, &je);
+    int slot = off[ax * M + k] + (ax == 0 ? 0 : nh);
+    for (int j = jb; j <= je; ++j) {
+      const double g = lo + j * h;
+      if ((v0 >= g) == (v1 >= g)) continue;
+      const double t = newton_root(cv, g, v0 - g, v1 - g);
+      double w[6];
+      lagrange6(t, w, nullptr);
+      double pos = 0.0;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) pos += w[m] * co[m];
+      int seg = static_cast<int>(floor((pos - olo) / h));
+      for (int r = 0; r < 2; ++r) {
+        if (olo + (seg + 1) * h <= pos) seg += 1;
+        if (olo + seg * h > pos) seg -= 1;
+      }
+      if (slot < cap) {
+        Crossing c;
+        c.line = j;
+        c.k = k;
+        c.seg = seg;
+        c.horiz = (ax == 0);
+        c.t = t;
+        c.pos = pos;
+        cr[slot] = c;
+      } else {
+        atomicMax(&st->err, 4);
+      }
+      ++slot;
+    }
+  }
+}
+
+// Mark row segments: hid[j*(N+1)+i] = crossing on row segment (i, i+1) of row j.
+__global__ void k_mark_h(int nh, const Crossing* __restrict__ cr, int N, int* __restrict__ hid,
+                         GeoStatus* st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nh) return;
+  const Crossing x = cr[c];
+  if (x.seg < 0 || x.seg > N - 1) {
+    atomicMax(&st->err, 5);
+    return;
+  }
+  const int old = atomicExch(&hid[x.line * (N + 1) + x.seg], c);
+  if (old != -1) atomicMax(&st->err, 1);
+}
+
+// Mark column segments after the labels exist: vid[j*(N+1)+i] = crossing on column i
+// between rows j and j+1.  A crossing within 1e-9 h of a segment end moves to the
+// neighbouring segment when only that one changes label (interface through a node up
+// to rounding); a crossing with no label change nearby is a geometry error.
+__global__ void k_mark_v(int nh, int nv, const Crossing* __restrict__ cr, int N, double y0,
+                         double h, const int8_t* __restrict__ lab, int* __restrict__ vid,
+                         GeoStatus* st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nv) return;
+  const Crossing x = cr[nh + c];
+  const int i = x.line, s = x.seg, n1 = N + 1;
+  if (s < 0 || s > N - 1) {
+    atomicMax(&st->err, 5);
+    return;
+  }
+  const double tol = 1e-9 * h;
+  auto flips = [&](int t) { return t >= 0 && t <= N - 1 && lab[t * n1 + i] != lab[(t + 1) * n1 + i]; };
+  int seg;
+  if (flips(s))
+    seg = s;
+  else if (x.pos - (y0 + s * h) <= tol && flips(s - 1))
+    seg = s - 1;
+  else if ((y0 + (s + 1) * h) - x.pos <= tol && flips(s + 1))
+    seg = s + 1;
+  else {
+    atomicMax(&st->err, 2);
+    return;
+  }
+  const int old = atomicExch(&vid[seg * n1 + i], nh + c);
+  if (old != -1) atomicMax(&st->err, 1);
+}
+
+// Labels per row: node (i, j) is in Omega+ iff #{row-j crossings with seg < i} is odd
+// (seg < i  <=>  xi < x_i).  One block per row.
+__global__ void k_label(int N, const int* __restrict__ hid, int8_t* __restrict__ lab) {
+  __shared__ int scratch[17];
+  const int j = blockIdx.x;
+  const int n1 = N + 1;
+  const int T = blockDim.x;
+  const int per = (n1 + T - 1) / T;
+  const int b = threadIdx.x * per, e = min(n1, b + per);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += (hid[j * n1 + i] >= 0);
+  int acc = block_excl_scan(s, scratch, nullptr);
+  for (int i = b; i < e; ++i) {
+    lab[j * n1 + i] = static_cast<int8_t>(acc & 1);
+    acc += (hid[j * n1 + i] >= 0);
+  }
+}
+
+// Irregular arms P -> Q (Sec. 4.2.1) of interior node P: neighbour Q with another label.
+// Order within a node: east, west, north, south.
+__device__ inline int node_arms(int i, int j, int N, const int8_t* lab, const int* hid,
+                                const int* vid, int* cid, int* qi, int* qj, GeoStatus* st) {
+  const int n1 = N + 1;
+  const int8_t lp = lab[j * n1 + i];
+  int na = 0;
+  const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
+  for (int d = 0; d < 4; ++d) {
+    const int ii = i + di[d], jj = j + dj[d];
+    if (lab[jj * n1 + ii] == lp) continue;
+    int c;
+    if (d == 0)
+      c = hid[j * n1 + i];
+    else if (d == 1)
+      c = hid[j * n1 + i - 1];
+    else if (d == 2)
+      c = vid[j * n1 + i];
+    else
+      c = vid[(j - 1) * n1 + i];
+    if (c < 0) {
+      atomicMax(&st->err, 2);
+      continue;
+    }
+    if (cid) {
+      cid[na] = c;
+      qi[na] = ii;
+      qj[na] = jj;
+    }
+    ++na;
+  }
+  return na;
+}
+
+__global__ void k_arm_rowcount(int N, const int8_t* __restrict__ lab, const int* __restrict__ hid,
+                               const int* __restrict__ vid, int* __restrict__ rowcnt, GeoStatus* st) {
+  __shared__ double scratch[16];
+  const int j = blockIdx.x + 1;  // interior rows 1..N-1
+  int s = 0;
+  for (int i = 1 + threadIdx.x; i <= N - 1; i += blockDim.x)
+    s += node_arms(i, j, N, lab, hid, vid, nullptr, nullptr, nullptr, st);
+  const double tot = block_sum<double>(static_cast<double>(s), scratch);
+  if (threadIdx.x == 0) rowcnt[j] = static_cast<int>(tot);
+}
+
+// Write arms of row j in (i, direction) order with their correction coefficients.
+// For arm P -> Q cut at the crossing with signed offset d = coord(Q) - crossing coord:
+//   T = [u] + d [u_s] + d^2/2 [u_ss],  RHS_P += -T/h^2 (P inside) or +T/h^2 (P outside),
+// T linear in (Phi, Phi_a, Phi_aa, Psi, Psi_a) at the crossing (App. A.1), each of which
+// is the 6-point Lagrange combination of marker values.
+__global__ void k_arm_fill(int N, double x0, double y0, double h, double c2, int M,
+                           const int8_t* __restrict__ lab, const int* __restrict__ hid,
+                           const int* __restrict__ vid, const int* __restrict__ rowoff,
+                           const Crossing* __restrict__ cr, const double* __restrict__ geo,
+                           int* __restrict__ armi, ArmCoef* __restrict__ armc,
+                           int* __restrict__ intcnt, GeoStatus* st) {
+  __shared__ int scratch[17];
+  const int j = blockIdx.x + 1;
+  const int n = N - 1;
+  const int T = blockDim.x;
+  const int per = (n + T - 1) / T;
+  const int b = 1 + threadIdx.x * per, e = min(N, b + per);  // i in [b, e)
+  int cnt = 0;
+  for (int i = b; i < e; ++i) cnt += node_arms(i, j, N, lab, hid, vid, nullptr, nullptr, nullptr, st);
+  int slot = rowoff[j] + block_excl_scan(cnt, scratch, nullptr);
+  const double* xa = geo;
+  const double* ya = geo + M;
+  const double* xaa = geo + 2 * M;
+  const double* yaa = geo + 3 * M;
+  const double ih2 = 1.0 / (h * h);
+  for (int i = b; i < e; ++i) {
+    int cid[4], qi[4], qj[4];
+    const int na = node_arms(i, j, N, lab, hid, vid, cid, qi, qj, st);
+    const double sgn = lab[j * (N + 1) + i] ? -ih2 : ih2;
+    for (int a = 0; a < na; ++a) {
+      const Crossing x = cr[cid[a]];
+      double w[6];
+      lagrange6(x.t, w, nullptr);
+      double g[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        int q = x.k - 2 + m;
+        q = (q < 0) ? q + M : (q >= M ? q - M : q);
+        g[0] += w[m] * xa[q];
+        g[1] += w[m] * ya[q];
+        g[2] += w[m] * xaa[q];
+        g[3] += w[m] * yaa[q];
+      }
+      const bool hz = x.horiz;
+      const double d = hz ? (x0 + qi[a] * h) - x.pos : (y0 + qj[a] * h) - x.pos;
+      ArmCoef ac;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) ac.l[m] = w[m];
+      for (int qv = 0; qv < 5; ++qv) {
+        double u[5] = {0, 0, 0, 0, 0};
+        u[qv] = 1.0;
+        double J[6];
+        jumps_closed(g[0], g[1], g[2], g[3], u[0], u[1], u[2], u[3], u[4], c2, J);
+        const double Tv = hz ? J[0] + d * J[1] + 0.5 * d * d * J[3]
+                             : J[0] + d * J[2] + 0.5 * d * d * J[4];
+        ac.coef[qv] = sgn * Tv;
+      }
+      ac.k = x.k;
+      ac.pad = 0;
+      armi[slot] = i;
+      armc[slot] = ac;
+      atomicAdd(&intcnt[x.k], 1);
+      ++slot;
+    }
+  }
+}
+
+__global__ void k_arm_by_interval(int na, const ArmCoef* __restrict__ armc,
+                                  const int* __restrict__ intoff, int* __restrict__ fill,
+                                  int* __restrict__ armint) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= na) return;
+  const int k = armc[a].k;
+  const int s = atomicAdd(&fill[k], 1);
+  armint[intoff[k] + s] = a;
+}
+
+// Gauss-Jordan inverse of a 6x6 matrix with partial pivoting (in registers).
+__device__ inline void inv6(double A[6][6], double R[6][6]) {
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) R[r][c] = (r == c) ? 1.0 : 0.0;
+  for (int c = 0; c < 6; ++c) {
+    int p = c;
+    double best = fabs(A[c][c]);
+    for (int r = c + 1; r < 6; ++r)
+      if (fabs(A[r][c]) > best) {
+        best = fabs(A[r][c]);
+        p = r;
+      }
+    if (p != c)
+      for (int q = 0; q < 6; ++q) {
+        double t = A[c][q];
+        A[c][q] = A[p][q];
+        A[p][q] = t;
+        t = R[c][q];
+        R[c][q] = R[p][q];
+        R[p][q] = t;
+      }
+    const double piv = 1.0 / A[c][c];
+    for (int q = 0; q < 6; ++q) {
+      A[c][q] *= piv;
+      R[c][q] *= piv;
+    }
+    for (int r = 0; r < 6; ++r) {
+      if (r == c) continue;
+      const double f = A[r][c];
+      if (f == 0.0) continue;
+      for (int q = 0; q < 6; ++q) {
+        A[r][q] -= f * A[c][q];
+        R[r][q] -= f * R[c][q];
+      }
+    }
+  }
+}
+
+// Sec. 4.3 extraction weights for every marker; marks the needed stencil nodes.
+__global__ void k_marker_ext(int M, const double* __restrict__ X, const double* __restrict__ geo,
+                             double x0, double y0, double h, int N, double c2,
+                             const int8_t* __restrict__ lab, MarkerExt* __restrict__ ext,
+                             int* __restrict__ need, int* __restrict__ stn) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const double px = X[k], py = X[M + k];
+  const int i0 = static_cast<int>(floor((px - x0) / h + 0.5));
+  const int j0 = static_cast<int>(floor((py - y0) / h + 0.5));
+  const int d1 = (px > x0 + i0 * h) ? 1 : -1;
+  const int d2 = (py > y0 + j0 * h) ? 1 : -1;
+  const int ri[6] = {0, 1, 0, 0, -1, d1}, rj[6] = {0, 0, 1, -1, 0, d2};
+  double A[6][6], Rv[6][6], At[6][6];
+  double chi[6];
+  for (int m = 0; m < 6; ++m) {
+    const int I = i0 + ri[m], J = j0 + rj[m];
+    const double dx = (x0 + I * h - px) / h, dy = (y0 + J * h - py) / h;
+    A[m][0] = 1.0;
+    A[m][1] = dx;
+    A[m][2] = dy;
+    A[m][3] = 0.5 * dx * dx;
+    A[m][4] = dx * dy;
+    A[m][5] = 0.5 * dy * dy;
+    const double Dx = dx * h, Dy = dy * h;
+    At[m][0] = 1.0;
+    At[m][1] = Dx;
+    At[m][2] = Dy;
+    At[m][3] = 0.5 * Dx * Dx;
+    At[m][4] = Dx * Dy;
+    At[m][5] = 0.5 * Dy * Dy;
+    chi[m] = lab[J * (N + 1) + I] ? 0.0 : 1.0;  // correction added for nodes in Omega-
+    need[J * (N + 1) + I] = 1;
+    stn[6 * k + m] = J * (N + 1) + I;
+  }
+  inv6(A, Rv);
+  MarkerExt me;
+  for (int m = 0; m < 6; ++m) {
+    me.W[m] = Rv[0][m];
+    me.W[6 + m] = Rv[1][m] / h;
+    me.W[12 + m] = Rv[2][m] / h;
+  }
+  // jumps at the marker as linear maps of (Phi, Phi_a, Phi_aa, Psi, Psi_a)
+  const double xa = geo[k], ya = geo[M + k], xaa = geo[2 * M + k], yaa = geo[3 * M + k];
+  double Cj[6][5];  // rows in Taylor order ([v],[v_x],[v_y],[v_xx],[v_xy],[v_yy])
+  for (int q = 0; q < 5; ++q) {
+    double u[5] = {0, 0, 0, 0, 0};
+    u[q] = 1.0;
+    double J[6];
+    jumps_closed(xa, ya, xaa, yaa, u[0], u[1], u[2], u[3], u[4], c2, J);
+    Cj[0][q] = J[0];
+    Cj[1][q] = J[1];
+    Cj[2][q] = J[2];
+    Cj[3][q] = J[3];
+    Cj[4][q] = J[5];
+    Cj[5][q] = J[4];
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 5; ++q) {
+      double e = 0.0;
+      for (int m = 0; m < 6; ++m) {
+        if (chi[m] == 0.0) continue;
+        double cm = 0.0;
+        for (int s = 0; s < 6; ++s) cm += At[m][s] * Cj[s][q];
+        e += me.W[6 * r + m] * cm;
+      }
+      me.E[5 * r + q] = e;
+      me.D[5 * r + q] = Cj[r][q];
+    }
+  const double sa = geo[4 * M + k];
+  me.nx = ya / sa;
+  me.ny = -xa / sa;
+  me.wq = sa * (2.0 * M_PI / M);
+  me.pad = 0.0;
+  ext[k] = me;
+}
+
+// Node numbering: per row count of needed nodes, then scan over rows (single block):
+// node offsets, compact list of needed rows, band [row_lo, row_hi].
+__global__ void k_need_rowcount(int N, const int* __restrict__ need, int* __restrict__ rowcnt) {
+  __shared__ double scratch[16];
+  const int j = blockIdx.x;
+  int s = 0;
+  for (int i = threadIdx.x; i <= N; i += blockDim.x) s += need[j * (N + 1) + i];
+  const double t = block_sum<double>(static_cast<double>(s), scratch);
+  if (threadIdx.x == 0) rowcnt[j] = static_cast<int>(t);
+}
+
+__global__ void k_rows_scan(int N, const int* __restrict__ rowcnt, int* __restrict__ nodeoff,
+                            int* __restrict__ rows, int* __restrict__ rowptr, GeoStatus* st) {
+  // single block: exclusive scans of counts and of (count > 0)
+  __shared__ int scratch[17];
+  const int n1 = N + 1;
+  const int T = blockDim.x;
+  const int per = (n1 + T - 1) / T;
+  const int b = threadIdx.x * per, e = min(n1, b + per);
+  int s = 0, f = 0;
+  for (int j = b; j < e; ++j) {
+    s += rowcnt[j];
+    f += rowcnt[j] > 0;
+  }
+  int tot_nodes, tot_rows;
+  int off = block_excl_scan(s, scratch, &tot_nodes);
+  int roff = block_excl_scan(f, scratch, &tot_rows);
+  for (int j = b; j < e; ++j) {
+    nodeoff[j] = off;
+    if (rowcnt[j] > 0) {
+      rows[roff] = j;
+      rowptr[roff] = off;
+      ++roff;
+    }
+    off += rowcnt[j];
+  }
+  if (threadIdx.x == 0) {
+    st->n_nodes = tot_nodes;
+    st->n_rows = tot_rows;
+    rowptr[tot_rows] = tot_nodes;
+  }
+  // band
+  int lo = 1 << 30, hi = -1;
+  for (int j = b; j < e; ++j)
+    if (rowcnt[j] > 0) {
+      lo = min(lo, j);
+      hi = max(hi, j);
+    }
+  if (hi >= 0) {
+    atomicMin(&st->row_lo, lo);
+    atomicMax(&st->row_hi, hi);
+  }
+}
+
+__global__ void k_node_assign(int N, const int* __restrict__ need, const int* __restrict__ nodeoff,
+                              int* __restrict__ nodeidx, int* __restrict__ nodei) {
+  __shared__ int scratch[17];
+  const int j = blockIdx.x;
+  const int n1 = N + 1;
+  const int T = blockDim.x;
+  const int per = (n1 + T - 1) / T;
+  const int b = threadIdx.x * per, e = min(n1, b + per);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += need[j * n1 + i];
+  int off = nodeoff[j] + block_excl_scan(s, scratch, nullptr);
+  for (int i = b; i < e; ++i) {
+    if (need[j * n1 + i]) {
+      nodeidx[j * n1 + i] = off;
+      nodei[off] = i;
+      ++off;
+    }
+  }
+}
+
+__global__ void k_marker_nodes(int M, const int* __restrict__ nodeidx, int* __restrict__ stn) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 6 * M) return;
+  stn[t] = nodeidx[stn[t]];
+}
+
+static inline int nblk(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
+
+int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
+  const int N = c->N;
+  const int n1 = N + 1;
+  const double h = c->h;
+  hipStream_t s = c->stream;
+  GeoStatus* st = c->gstat.as<GeoStatus>();
+  GeoStatus init{};
+  init.row_lo = 1 << 30;
+  init.row_hi = -1;
+
+  KFBI_TRY(c->X.ensure(sizeof(double) * 2 * M));
+  KFBI_TRY(c->geo.ensure(sizeof(double) * 6 * M));
+  KFBI_TRY(c->dvec.ensure(sizeof(double) * 2 * M));
+  KFBI_TRY(c->cnt.ensure(sizeof(int) * (2 * M + 2)));
+  KFBI_TRY(c->intptr.ensure(sizeof(int) * (2 * M + 2)));
+  KFBI_TRY(c->ext.ensure(sizeof(MarkerExt) * M));
+  KFBI_TRY(c->mknode.ensure(sizeof(int) * 6 * M));
+
+  KFBI_HIP(hipMemcpyAsync(c->X.p, xy, sizeof(double) * 2 * M, hipMemcpyDeviceToDevice, s));
+  KFBI_HIP(hipMemcpyAsync(st, &init, sizeof(GeoStatus), hipMemcpyHostToDevice, s));
+  double* d1 = c->dvec.as<double>();
+  double* d2 = d1 + M;
+  if (c->d_M != M) {
+    hipLaunchKernelGGL(k_diffvec, dim3(nblk(M, 256)), dim3(256), 0, s, M, d1, d2);
+    c->d_M = M;
+  }
+  const double mg = 3.0 * h;
+  hipLaunchKernelGGL(k_marker_geo, dim3(nblk(M, 256)), dim3(256), 0, s, M, c->X.as<double>(), d1,
+                     d2, c->geo.as<double>(), c->x0 + mg, c->x0 + c->side - mg, c->y0 + mg,
+                     c->y0 + c->side - mg, st);
+  int* cnt = c->cnt.as<int>();
+  hipLaunchKernelGGL(k_count_cross, dim3(nblk(M, 256)), dim3(256), 0, s, M, c->X.as<double>(),
+                     c->x0, c->y0, h, N, cnt);
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, M, cnt, &st->n_cross_h);
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, M, cnt + M, &st->n_cross_v);
+  GeoStatus* hs = static_cast<GeoStatus*>(c->hpin);
+  KFBI_HIP(hipMemcpyAsync(hs, st, sizeof(GeoStatus), hipMemcpyDeviceToHost, s));
+  KFBI_HIP(hipStreamSynchronize(s));
+  if (hs->err == 3) {
+    set_error("interface marker closer than 3h to the box boundary");
+    return KFBI_E_GEOMETRY;
+  }
+  const int nh = hs->n_cross_h, nv = hs->n_cross_v, nc = nh + nv;
+  KFBI_TRY(c->cross.ensure(sizeof(Crossing) * (nc + 1)));
+  const int narm_cap = 2 * nc + 1;
+  KFBI_TRY(c->armi.ensure(sizeof(int) * narm_cap));
+  KFBI_TRY(c->armcoef.ensure(sizeof(ArmCoef) * narm_cap));
+  KFBI_TRY(c->armint.ensure(sizeof(int) * narm_cap));
+  KFBI_TRY(c->armr.ensure(sizeof(double) * narm_cap));
+
+  Crossing* cr = c->cross.as<Crossing>();
+  hipLaunchKernelGGL(k_fill_cross, dim3(nblk(M, 128)), dim3(128), 0, s, M, c->X.as<double>(), c->x0,
+                     c->y0, h, N, cnt, nh, cr, nc, st);
+  int* hid = c->hid.as<int>();
+  int* vid = c->vid.as<int>();
+  KFBI_HIP(hipMemsetAsync(hid, 0xff, sizeof(int) * n1 * n1, s));
+  KFBI_HIP(hipMemsetAsync(vid, 0xff, sizeof(int) * n1 * n1, s));
+  if (nh > 0)
+    hipLaunchKernelGGL(k_mark_h, dim3(nblk(nh, 256)), dim3(256), 0, s, nh, cr, N, hid, st);
+  int8_t* lab = c->lab.as<int8_t>();
+  hipLaunchKernelGGL(k_label, dim3(n1), dim3(256), 0, s, N, hid, lab);
+  if (nv > 0)
+    hipLaunchKernelGGL(k_mark_v, dim3(nblk(nv, 256)), dim3(256), 0, s, nh, nv, cr, N, c->y0, h,
+                       lab, vid, st);
+  // arms
+  int* rowoff = c->armrow.as<int>();  // N+2 entries
+  KFBI_HIP(hipMemsetAsync(rowoff, 0, sizeof(int) * (N + 2), s));
+  hipLaunchKernelGGL(k_arm_rowcount, dim3(N - 1), dim3(256), 0, s, N, lab, hid, vid, rowoff, st);
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, rowoff, &st->n_arms);
+  int* intcnt = c->intptr.as<int>();  // M+1 counts -> offsets ; second half = fill counters
+  KFBI_HIP(hipMemsetAsync(intcnt, 0, sizeof(int) * (2 * M + 2), s));
+  hipLaunchKernelGGL(k_arm_fill, dim3(N - 1), dim3(256), 0, s, N, c->x0, c->y0, h, c->c2, M, lab,
+                     hid, vid, rowoff, cr, c->geo.as<double>(), c->armi.as<int>(),
+                     c->armcoef.as<ArmCoef>(), intcnt, st);
+  // row_ptr[N] = total (the scan wrote offsets for 0..N; total is in st->n_arms)
+  // interval CSR
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, M + 1, intcnt, nullptr);
+  // markers / nodes
+  int* need = c->need.as<int>();
+  KFBI_HIP(hipMemsetAsync(need, 0, sizeof(int) * n1 * n1, s));
+  hipLaunchKernelGGL(k_marker_ext, dim3(nblk(M, 128)), dim3(128), 0, s, M, c->X.as<double>(),
+                     c->geo.as<double>(), c->x0, c->y0, h, N, c->c2, lab, c->ext.as<MarkerExt>(),
+                     need, c->mknode.as<int>());
+  int* rowcnt = c->rowsum.as<int>();
+  hipLaunchKernelGGL(k_need_rowcount, dim3(n1), dim3(256), 0, s, N, need, rowcnt);
+  int* nodeoff = rowcnt + n1 + 1;
+  hipLaunchKernelGGL(k_rows_scan, dim3(1), dim3(1024), 0, s, N, rowcnt, nodeoff, c->rows.as<int>(),
+                     c->rowptr.as<int>(), st);
+  hipLaunchKernelGGL(k_node_assign, dim3(n1), dim3(256), 0, s, N, need, nodeoff,
+                     c->nodeidx.as<int>(), c->nodei.as<int>());
+  hipLaunchKernelGGL(k_marker_nodes, dim3(nblk(6 * M, 256)), dim3(256), 0, s, M,
+                     c->nodeidx.as<int>(), c->mknode.as<int>());
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipMemcpyAsync(hs, st, sizeof(GeoStatus), hipMemcpyDeviceToHost, s));
+  KFBI_HIP(hipStreamSynchronize(s));
+  if (hs->err != 0) {
+    static const char* msg[] = {"", "a grid segment is cut twice by the interface",
+                                "grid labels and interface crossings disagree",
+                                "interface marker closer than 3h to the box boundary",
+                                "crossing buffer overflow", "crossing outside the grid"};
+    set_error("geometry error: %s", msg[hs->err < 6 ? hs->err : 0]);
+    return KFBI_E_GEOMETRY;
+  }
+  // arms grouped by marker interval (for the per-apply correction kernel)
+  const int na = hs->n_arms;
+  if (na > 0)
+    hipLaunchKernelGGL(k_arm_by_interval, dim3(nblk(na, 256)), dim3(256), 0, s, na,
+                       c->armcoef.as<ArmCoef>(), intcnt, intcnt + M + 1, c->armint.as<int>());
+  KFBI_HIP(hipGetLastError());
+  c->st = *hs;
+  c->M = M;
+  return KFBI_OK;
+}
+
+}  // namespace kfbi

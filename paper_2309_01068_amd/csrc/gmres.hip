@@ -1,0 +1,435 @@
+// Matrix-free restarted GMRES on gfx950 (Sec. 4 opening: the discretised boundary
+// integral equations are solved by GMRES; each iteration applies the operator once).
+//
+// Device-resident FP64 Arnoldi with classical Gram-Schmidt applied twice (CGS2), inner
+// products as fixed-order block partials reduced by the last block to finish (no
+// floating-point atomics, so results are bitwise reproducible), Givens rotations in
+// that last block, convergence checked on the host from a 64-byte status word.  The
+// answer is accepted only on the true residual ||b - A x||_2 <= tol ||b||_2 computed
+// with the FP64 operator.  KFBI_FP32 selects iterative refinement: FP64 residual, inner
+// GMRES with the FP32 operator, x += d.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "device_util.h"
+
+namespace kfbi {
+
+constexpr int kMaxRestart = 64;
+constexpr int kRedBlock = 256;
+
+struct GmresStatus {
+  double resid;   // |g_{j+1}| (Givens estimate) or a reduced norm
+  double hnext;   // h_{j+1,j}
+  int breakdown;
+  int pad[11];
+};
+
+// Partial inner products <V_i, w> (i < nv) and optionally ||w||^2, after an optional
+// update w -= sum_i hprev_i V_i.  The last block to finish reduces the partials in block
+// order and writes out[0..nv) (and out[nv] = ||w||^2).
+__global__ void __launch_bounds__(kRedBlock)
+    k_cgs(int M, int ldv, const double* __restrict__ V, int nv, double* __restrict__ w,
+          const double* __restrict__ hprev, int want_norm, double* __restrict__ part,
+          unsigned int* __restrict__ counter, double* __restrict__ out) {
+  __shared__ double red[kMaxRestart + 2][4];
+  __shared__ int is_last;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double wk = 0.0;
+  if (k < M) {
+    wk = w[k];
+    if (hprev) {
+      for (int i = 0; i < nv; ++i) wk -= hprev[i] * V[static_cast<size_t>(i) * ldv + k];
+      w[k] = wk;
+    }
+  }
+  const int nout = nv + (want_norm ? 1 : 0);
+  for (int i = 0; i < nout; ++i) {
+    double p = 0.0;
+    if (k < M) p = (i < nv) ? V[static_cast<size_t>(i) * ldv + k] * wk : wk * wk;
+    p = wave_sum(p);
+    if (lane == 0) red[i][wv] = p;
+  }
+  __syncthreads();
+  const int nb = gridDim.x;
+  for (int i = threadIdx.x; i < nout; i += blockDim.x)
+    part[static_cast<size_t>(blockIdx.x) * nout + i] = ((red[i][0] + red[i][1]) + red[i][2]) + red[i][3];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int prev = atomicAdd(counter, 1u);
+    is_last = (prev == static_cast<unsigned int>(nb - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  for (int i = threadIdx.x; i < nout; i += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += __builtin_nontemporal_load(&part[static_cast<size_t>(b) * nout + i]);
+    out[i] = s;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+// w -= sum_i h_i V_i, then ||w||^2 partials; the last block finishes column j of the
+// Hessenberg matrix (h = h1 + h2, h_{j+1,j} = ||w||), applies the previous Givens
+// rotations, forms the new one and updates the residual vector g.
+__global__ void __launch_bounds__(kRedBlock)
+    k_finish(int M, int ldv, const double* __restrict__ V, int j, double* __restrict__ w,
+             const double* __restrict__ h1, const double* __restrict__ h2,
+             double* __restrict__ part, unsigned int* __restrict__ counter,
+             double* __restrict__ H /* (kMaxRestart+1) x kMaxRestart, column-major */,
+             double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+             GmresStatus* __restrict__ st) {
+  __shared__ double red[4];
+  __shared__ int is_last;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double wk = 0.0;
+  if (k < M) {
+    wk = w[k];
+    for (int i = 0; i <= j; ++i) wk -= h2[i] * V[static_cast<size_t>(i) * ldv + k];
+    w[k] = wk;
+  }
+  double p = wave_sum(wk * wk);
+  if (lane == 0) red[wv] = p;
+  __syncthreads();
+  const int nb = gridDim.x;
+  if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int prev = atomicAdd(counter, 1u);
+    is_last = (prev == static_cast<unsigned int>(nb - 1));
+  }
+  __syncthreads();
+  if (!is_last || threadIdx.x != 0) return;
+  __threadfence();
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += __builtin_nontemporal_load(&part[b]);
+  const double hn = sqrt(s);
+  const int ld = kMaxRestart + 1;
+  double* col = H + static_cast<size_t>(j) * ld;
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  const double c = col[j] / den, sv = col[j + 1] / den;
+  cs[j] = c;
+  sn[j] = sv;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sv * g[j];
+  g[j] = c * g[j];
+  st->resid = fabs(g[j + 1]);
+  st->hnext = hn;
+  st->breakdown = (hn == 0.0);
+  *counter = 0u;
+}
+
+__global__ void k_scale(int M, const double* __restrict__ w, const double* __restrict__ hn,
+                        double* __restrict__ v) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < M) v[k] = (*hn != 0.0) ? w[k] / *hn : 0.0;
+}
+
+// r = b - y, partial ||r||^2; last block writes status->resid = ||r||.
+__global__ void __launch_bounds__(kRedBlock)
+    k_residual(int M, const double* __restrict__ b, const double* __restrict__ y,
+               double* __restrict__ r, double* __restrict__ part, unsigned int* __restrict__ counter,
+               GmresStatus* __restrict__ st) {
+  __shared__ double red[4];
+  __shared__ int is_last;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double rk = 0.0;
+  if (k < M) {
+    rk = b[k] - (y ? y[k] : 0.0);
+    if (r) r[k] = rk;
+  }
+  double p = wave_sum(rk * rk);
+  if (lane == 0) red[wv] = p;
+  __syncthreads();
+  const int nb = gridDim.x;
+  if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int prev = atomicAdd(counter, 1u);
+    is_last = (prev == static_cast<unsigned int>(nb - 1));
+  }
+  __syncthreads();
+  if (!is_last || threadIdx.x != 0) return;
+  __threadfence();
+  double s = 0.0;
+  for (int bb = 0; bb < nb; ++bb) s += __builtin_nontemporal_load(&part[bb]);
+  st->resid = sqrt(s);
+  *counter = 0u;
+}
+
+// Start a cycle: V_0 = r / beta, g = (beta, 0, ...).
+__global__ void k_start(int M, const double* __restrict__ r, const GmresStatus* __restrict__ st,
+                        double* __restrict__ v0, double* __restrict__ g) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const double beta = st->resid;
+  if (k < M) v0[k] = r[k] / beta;
+  if (k <= kMaxRestart) g[k] = (k == 0) ? beta : 0.0;
+}
+
+// Back substitution H(0:m,0:m) y = g(0:m) and x += V y (y in LDS).
+__global__ void k_update_x(int M, int m, int ldv, const double* __restrict__ V,
+                           const double* __restrict__ H, const double* __restrict__ g,
+                           double* __restrict__ x) {
+  __shared__ double y[kMaxRestart];
+  if (threadIdx.x == 0) {
+    const int ld = kMaxRestart + 1;
+    for (int i = m - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int q = i + 1; q < m; ++q) s -= H[static_cast<size_t>(q) * ld + i] * y[q];
+      y[i] = s / H[static_cast<size_t>(i) * ld + i];
+    }
+  }
+  __syncthreads();
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  double s = x[k];
+  for (int i = 0; i < m; ++i) s += V[static_cast<size_t>(i) * ldv + k] * y[i];
+  x[k] = s;
+}
+
+__global__ void k_axpy(int M, double a, const double* __restrict__ d, double* __restrict__ x) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < M) x[k] += a * d[k];
+}
+
+struct GmresWork {
+  double* V;
+  int ldv;
+  double* H;
+  double* cs;
+  double* sn;
+  double* g;
+  double* h1;
+  double* h2;
+  double* w;
+  double* part;
+  unsigned int* counter;
+  GmresStatus* st;
+  GmresStatus* hst;  // pinned host copy
+  double* r;
+  double* d;
+  double* y;
+};
+
+static int ensure_work(kfbi_ctx* c, int restart, GmresWork* gw) {
+  const int M = c->M;
+  const int ldv = ((M + 63) / 64) * 64;
+  const int nblk = (M + kRedBlock - 1) / kRedBlock;
+  KFBI_TRY(c->gV.ensure(sizeof(double) * static_cast<size_t>(ldv) * (kMaxRestart + 1)));
+  KFBI_TRY(c->gH.ensure(sizeof(double) * (kMaxRestart + 1) * (kMaxRestart + 1)));
+  KFBI_TRY(c->gsc.ensure(sizeof(double) * 5 * (kMaxRestart + 2)));
+  KFBI_TRY(c->gpart.ensure(sizeof(double) * static_cast<size_t>(nblk) * (kMaxRestart + 2)));
+  KFBI_TRY(c->gcnt.ensure(sizeof(GmresStatus) + 64));
+  KFBI_TRY(c->gw.ensure(sizeof(double) * ldv * 4));
+  gw->V = c->gV.as<double>();
+  gw->ldv = ldv;
+  gw->H = c->gH.as<double>();
+  double* sc = c->gsc.as<double>();
+  gw->cs = sc;
+  gw->sn = sc + (kMaxRestart + 2);
+  gw->g = sc + 2 * (kMaxRestart + 2);
+  gw->h1 = sc + 3 * (kMaxRestart + 2);
+  gw->h2 = sc + 4 * (kMaxRestart + 2);
+  gw->part = c->gpart.as<double>();
+  gw->st = c->gcnt.as<GmresStatus>();
+  gw->counter = reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(c->gcnt.p) + sizeof(GmresStatus));
+  gw->hst = reinterpret_cast<GmresStatus*>(reinterpret_cast<char*>(c->hpin) + 1024);
+  double* wb = c->gw.as<double>();
+  gw->w = wb;
+  gw->r = wb + ldv;
+  gw->d = wb + 2 * ldv;
+  gw->y = wb + 3 * ldv;
+  return KFBI_OK;
+}
+
+static int read_status(kfbi_ctx* c, GmresWork* gw) {
+  KFBI_HIP(hipMemcpyAsync(gw->hst, gw->st, sizeof(GmresStatus), hipMemcpyDeviceToHost, c->stream));
+  KFBI_HIP(hipStreamSynchronize(c->stream));
+  return KFBI_OK;
+}
+
+// ||b - A x|| with the operator at `precision`; leaves r in gw->r.
+static int true_residual(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* b,
+                         const double* x, GmresWork* gw, double* out, int* applies) {
+  const int M = c->M;
+  const int nblk = (M + kRedBlock - 1) / kRedBlock;
+  KFBI_TRY(apply_impl(c, op->layer, precision, x, nullptr, nullptr, op, x, gw->y));
+  ++*applies;
+  hipLaunchKernelGGL(k_residual, dim3(nblk), dim3(kRedBlock), 0, c->stream, M, b, gw->y, gw->r,
+                     gw->part, gw->counter, gw->st);
+  KFBI_HIP(hipGetLastError());
+  KFBI_TRY(read_status(c, gw));
+  *out = gw->hst->resid;
+  return KFBI_OK;
+}
+
+// Restarted GMRES for A x = b with the operator at `precision`; stops when the true
+// residual (same precision) is <= tol * nb or after maxit Arnoldi steps.
+static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* b, double* x,
+                      double nb, double tol, int restart, int maxit, GmresWork* gw, int* iters,
+                      int* cycles, int* applies, double* relres) {
+  const int M = c->M;
+  const int nblk = (M + kRedBlock - 1) / kRedBlock;
+  const int mb = (M + 255) / 256;
+  hipStream_t s = c->stream;
+  double rn = 0.0;
+  for (;;) {
+    KFBI_TRY(true_residual(c, op, precision, b, x, gw, &rn, applies));
+    if (!std::isfinite(rn)) {
+      set_error("non-finite residual in GMRES");
+      return KFBI_E_NONFINITE;
+    }
+    *relres = rn / nb;
+    if (rn <= tol * nb) return KFBI_OK;
+    if (*iters >= maxit) return KFBI_E_NOCONV;
+    ++*cycles;
+    hipLaunchKernelGGL(k_start, dim3(mb), dim3(256), 0, s, M, gw->r, gw->st, gw->V, gw->g);
+    int m = 0;
+    for (int j = 0; j < restart; ++j) {
+      double* vj = gw->V + static_cast<size_t>(j) * gw->ldv;
+      double* vn = gw->V + static_cast<size_t>(j + 1) * gw->ldv;
+      KFBI_TRY(apply_impl(c, op->layer, precision, vj, nullptr, nullptr, op, vj, gw->w));
+      ++*applies;
+      hipLaunchKernelGGL(k_cgs, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j + 1, gw->w,
+                         nullptr, 0, gw->part, gw->counter, gw->h1);
+      hipLaunchKernelGGL(k_cgs, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j + 1, gw->w,
+                         gw->h1, 0, gw->part, gw->counter, gw->h2);
+      hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j, gw->w,
+                         gw->h1, gw->h2, gw->part, gw->counter, gw->H, gw->cs, gw->sn, gw->g,
+                         gw->st);
+      hipLaunchKernelGGL(k_scale, dim3(mb), dim3(256), 0, s, M, gw->w, &gw->st->hnext, vn);
+      KFBI_HIP(hipGetLastError());
+      ++*iters;
+      m = j + 1;
+      KFBI_TRY(read_status(c, gw));
+      if (!std::isfinite(gw->hst->resid)) {
+        set_error("non-finite Arnoldi residual");
+        return KFBI_E_NONFINITE;
+      }
+      if (gw->hst->resid <= tol * nb || gw->hst->breakdown || *iters >= maxit) break;
+    }
+    hipLaunchKernelGGL(k_update_x, dim3(mb), dim3(256), 0, s, M, m, gw->ldv, gw->V, gw->H, gw->g, x);
+    KFBI_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace kfbi
+
+using namespace kfbi;
+
+extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b, double* x,
+                                const kfbi_gmres_opts* o, kfbi_gmres_stats* stats) {
+  if (!c || !op || !b || !x || !o) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  if (!c->have_interface) {
+    set_error("no interface installed");
+    return KFBI_E_STATE;
+  }
+  if (c->box_bc == KFBI_BOX_USER) {
+    set_error("GMRES needs box data defined by the density (ZERO or FREESPACE)");
+    return KFBI_E_INVALID;
+  }
+  if (o->restart < 1 || o->restart > kMaxRestart || o->maxit < 1 || !(o->tol > 0.0) ||
+      (o->precision != KFBI_FP64 && o->precision != KFBI_FP32) ||
+      (op->layer != KFBI_SINGLE && op->layer != KFBI_DOUBLE) || op->side < KFBI_PLUS ||
+      op->side > KFBI_AVG) {
+    set_error("invalid GMRES options or operator");
+    return KFBI_E_INVALID;
+  }
+  GmresWork gw;
+  KFBI_TRY(ensure_work(c, o->restart, &gw));
+  const int M = c->M;
+  const int nblk = (M + kRedBlock - 1) / kRedBlock;
+  kfbi_gmres_stats loc{};
+  KFBI_HIP(hipMemsetAsync(gw.counter, 0, sizeof(unsigned int), c->stream));
+  // ||b||
+  hipLaunchKernelGGL(k_residual, dim3(nblk), dim3(kRedBlock), 0, c->stream, M, b, nullptr, nullptr,
+                     gw.part, gw.counter, gw.st);
+  KFBI_HIP(hipGetLastError());
+  KFBI_TRY(read_status(c, &gw));
+  const double nb = gw.hst->resid;
+  int status = KFBI_OK;
+  if (nb == 0.0) {
+    KFBI_HIP(hipMemsetAsync(x, 0, sizeof(double) * M, c->stream));
+    KFBI_HIP(hipStreamSynchronize(c->stream));
+    loc.converged = 1;
+  } else if (o->precision == KFBI_FP64) {
+    int applies = 0;
+    status = gmres_core(c, op, KFBI_FP64, b, x, nb, o->tol, o->restart, o->maxit, &gw, &loc.iters,
+                        &loc.outer_iters, &applies, &loc.relres);
+    loc.applies64 = applies;
+    loc.converged = (status == KFBI_OK);
+  } else {
+    // iterative refinement: r = b - A64 x ; A32 d = r ; x += d
+    const int mb = (M + 255) / 256;
+    double prev = INFINITY;
+    for (;;) {
+      double rn;
+      int a64 = 0;
+      status = true_residual(c, op, KFBI_FP64, b, x, &gw, &rn, &a64);
+      loc.applies64 += a64;
+      if (status != KFBI_OK) break;
+      loc.relres = rn / nb;
+      if (!std::isfinite(rn)) {
+        set_error("non-finite residual in refinement");
+        status = KFBI_E_NONFINITE;
+        break;
+      }
+      if (rn <= o->tol * nb) {
+        loc.converged = 1;
+        break;
+      }
+      if (loc.iters >= o->maxit || !(rn < prev)) {
+        set_error("iterative refinement stalled (relres %.3e)", rn / nb);
+        status = KFBI_E_NOCONV;
+        break;
+      }
+      prev = rn;
+      ++loc.outer_iters;
+      // rhs of the correction equation: keep r in gw.d, solve for the correction in gw.w+?
+      double* rr = gw.d;
+      KFBI_HIP(hipMemcpyAsync(rr, gw.r, sizeof(double) * M, hipMemcpyDeviceToDevice, c->stream));
+      double* dcorr = c->tmpM.as<double>();
+      KFBI_HIP(hipMemsetAsync(dcorr, 0, sizeof(double) * M, c->stream));
+      int it_in = 0, cyc = 0, a32 = 0;
+      double rel_in = 0.0;
+      const double itol = o->inner_tol > 0.0 ? o->inner_tol : 1e-5;
+      const int st_in = gmres_core(c, op, KFBI_FP32, rr, dcorr, rn, itol, o->restart,
+                                   o->maxit - loc.iters, &gw, &it_in, &cyc, &a32, &rel_in);
+      loc.iters += it_in;
+      loc.applies32 += a32;
+      if (st_in != KFBI_OK && st_in != KFBI_E_NOCONV) {
+        status = st_in;
+        break;
+      }
+      hipLaunchKernelGGL(k_axpy, dim3(mb), dim3(256), 0, c->stream, M, 1.0, dcorr, x);
+      KFBI_HIP(hipGetLastError());
+    }
+  }
+  KFBI_HIP(hipStreamSynchronize(c->stream));
+  if (stats) *stats = loc;
+  if (status == KFBI_E_NOCONV)
+    set_error("GMRES did not reach tol %.3e in %d iterations (relres %.3e)", o->tol, loc.iters,
+              loc.relres);
+  return status;
+}

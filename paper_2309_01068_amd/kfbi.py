@@ -1,0 +1,189 @@
+"""ctypes binding of libkfbi.so (the gfx950 KFBI library).  Argument marshalling only:
+every numerical step runs in the library's HIP kernels.  Tensors are torch CUDA (HIP)
+tensors; their data pointers are passed straight to the C ABI declared in include/kfbi.h.
+
+The library is built in-tree by ``paper_2309_01068_amd.build``; if it is missing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libkfbi.so")
+
+OK, E_INVALID, E_GEOMETRY, E_NOCONV, E_HIP, E_NOMEM, E_NONFINITE, E_STATE = range(8)
+SINGLE, DOUBLE = 0, 1
+PLUS, MINUS, AVG = 0, 1, 2
+BOX_ZERO, BOX_USER, BOX_FREESPACE = 0, 1, 2
+FP64, FP32 = 0, 1
+
+EXPORTS = [
+    "kfbi_last_error", "kfbi_create", "kfbi_destroy", "kfbi_set_interface", "kfbi_get_info",
+    "kfbi_apply", "kfbi_operator", "kfbi_gmres_solve", "kfbi_profile", "kfbi_profile_read",
+]
+
+
+class KfbiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"kfbi error {code}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("side", C.c_double), ("N", C.c_int),
+                ("c2", C.c_double), ("box_bc", C.c_int), ("max_markers", C.c_int),
+                ("stream", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("M", C.c_int), ("n_cross_h", C.c_int), ("n_cross_v", C.c_int),
+                ("n_arms", C.c_int), ("n_nodes", C.c_int), ("n_rows", C.c_int),
+                ("row_lo", C.c_int), ("row_hi", C.c_int)]
+
+
+class Out(C.Structure):
+    _fields_ = [("v_plus", C.c_void_p), ("v_minus", C.c_void_p), ("dn_plus", C.c_void_p),
+                ("dn_minus", C.c_void_p), ("grid", C.c_void_p)]
+
+
+class Bie(C.Structure):
+    _fields_ = [("layer", C.c_int), ("side", C.c_int), ("a", C.c_double), ("b", C.c_double),
+                ("q", C.c_double)]
+
+
+class GmresOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int),
+                ("precision", C.c_int), ("inner_tol", C.c_double)]
+
+
+class GmresStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("outer_iters", C.c_int), ("applies64", C.c_int),
+                ("applies32", C.c_int), ("relres", C.c_double), ("converged", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIBPATH):
+    """Load libkfbi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_2309_01068_amd.build`")
+    lib = C.CDLL(path)
+    lib.kfbi_last_error.restype = C.c_char_p
+    vp = C.c_void_p
+    lib.kfbi_create.argtypes = [C.POINTER(Grid), C.POINTER(vp)]
+    lib.kfbi_destroy.argtypes = [vp]
+    lib.kfbi_set_interface.argtypes = [vp, C.c_int, vp]
+    lib.kfbi_get_info.argtypes = [vp, C.POINTER(Info)]
+    lib.kfbi_apply.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.POINTER(Out)]
+    lib.kfbi_operator.argtypes = [vp, C.POINTER(Bie), C.c_int, vp, vp]
+    lib.kfbi_gmres_solve.argtypes = [vp, C.POINTER(Bie), vp, vp, C.POINTER(GmresOpts),
+                                     C.POINTER(GmresStats)]
+    lib.kfbi_profile.argtypes = [vp, C.c_int]
+    lib.kfbi_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise KfbiError(code, load().kfbi_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A KFBI context: box, grid, operator constant c2, box data mode."""
+
+    def __init__(self, x0, y0, side, N, c2=0.0, box_bc=BOX_ZERO, max_markers=4096, stream=None):
+        self.lib = load()
+        self.N = N
+        self.box_bc = box_bc
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.stream = s
+        g = Grid(x0, y0, side, N, c2, box_bc, max_markers, C.c_void_p(s.cuda_stream))
+        h = C.c_void_p()
+        _check(self.lib.kfbi_create(C.byref(g), C.byref(h)))
+        self.h = h
+        self.M = 0
+
+    def close(self):
+        if self.h:
+            self.lib.kfbi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_interface(self, xy: torch.Tensor):
+        """xy: (2, M) float64 device tensor (x row then y row)."""
+        xy = xy.contiguous()
+        self.M = xy.shape[1]
+        _check(self.lib.kfbi_set_interface(self.h, self.M, _ptr(xy)))
+
+    def info(self) -> dict:
+        i = Info()
+        _check(self.lib.kfbi_get_info(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    def apply(self, layer, density, precision=FP64, ring=None, want=("v_plus", "v_minus",
+                                                                       "dn_plus", "dn_minus"),
+              grid=False, out=None):
+        dev = density.device
+        res = {} if out is None else out
+        for k in want:
+            if k not in res:
+                res[k] = torch.empty(self.M, dtype=torch.float64, device=dev)
+        if grid and "grid" not in res:
+            res["grid"] = torch.empty((self.N + 1, self.N + 1), dtype=torch.float64, device=dev)
+        o = Out(*[(_ptr(res[k]) if k in res else None)
+                  for k in ("v_plus", "v_minus", "dn_plus", "dn_minus", "grid")])
+        _check(self.lib.kfbi_apply(self.h, layer, precision, _ptr(density), _ptr(ring), C.byref(o)))
+        return res
+
+    def operator(self, x, layer, side, a, b, q, precision=FP64, y=None):
+        y = torch.empty_like(x) if y is None else y
+        op = Bie(layer, side, a, b, q)
+        _check(self.lib.kfbi_operator(self.h, C.byref(op), precision, _ptr(x), _ptr(y)))
+        return y
+
+    def profile(self, on: bool):
+        _check(self.lib.kfbi_profile(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        """(ms summed per stage [4], number of profiled applies)."""
+        ms = (C.c_double * 4)()
+        n = C.c_long()
+        _check(self.lib.kfbi_profile_read(self.h, ms, C.byref(n)))
+        return list(ms), n.value
+
+    def gmres(self, rhs, x, layer, side, a, b, q, tol=1e-10, restart=50, maxit=1000,
+              precision=FP64, inner_tol=1e-5, raise_noconv=True):
+        op = Bie(layer, side, a, b, q)
+        opts = GmresOpts(tol, restart, maxit, precision, inner_tol)
+        st = GmresStats()
+        code = self.lib.kfbi_gmres_solve(self.h, C.byref(op), _ptr(rhs), _ptr(x), C.byref(opts),
+                                         C.byref(st))
+        if code == E_NOCONV and not raise_noconv:
+            return x, st.as_dict()
+        _check(code)
+        return x, st.as_dict()

@@ -1,0 +1,203 @@
+"""GPU parity of the HIP KFBI apply against the CPU oracle (element by element).
+
+FP64 bar: relative l2 difference <= 1e-10 on every trace (same discretisation, only
+rounding differs; typically ~1e-13).  FP32 bar (grid stages in FP32): relative l2
+<= 5e-5 against the FP64 oracle, derived from FP32 rounding amplified by the O(1/h^2)
+corrections and the Laplace low modes (the value measured is printed by -s).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry as G
+from oracle import kfbi as K
+from paper_2309_01068_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 5e-5
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def make_ctx(box, c2, box_bc, M):
+    from paper_2309_01068_amd import kfbi
+    return kfbi.Context(box.x0, box.y0, box.side, box.N, c2, box_bc, max_markers=max(M, 64))
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def run_pair(X, box, c2, box_bc, layer, dens, ring=None, precision=0, grid=False):
+    print(f"[case] N={box.N} M={X.shape[1]} c2={c2} box={box_bc} layer={layer} prec={precision}",
+          flush=True)
+    g = G.build_geometry(X, box)
+    ref = K.apply(g, layer, dens, c2, box_bc, ring)
+    ctx = make_ctx(box, c2, box_bc, X.shape[1])
+    ctx.set_interface(dev(X))
+    out = ctx.apply(layer, dev(dens), precision, None if ring is None else dev(ring), grid=grid)
+    torch.cuda.synchronize()
+    return g, ref, ctx, {k: host(v) for k, v in out.items()}
+
+
+CASES = [
+    # (name, curve, box, c2, box_bc)
+    ("star256_mh", W.star(512), W.box(-1, 1, 256), 1000.0, K.BOX_ZERO),
+    ("star256_lap", W.star(512), W.box(-1, 1, 256), 0.0, K.BOX_ZERO),
+    ("ellipse128", W.ellipse(256), W.box(-1, 1, 128), 0.0, K.BOX_ZERO),
+    ("hs3_free", W.hs3(256), W.box(-2, 2, 256), 0.0, K.BOX_FREESPACE),
+    ("pert_free", W.perturbed(384, 3), W.box(-2, 2, 128), 0.0, K.BOX_FREESPACE),
+]
+
+
+@pytest.mark.parametrize("name,X,box,c2,bc", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("layer", [K.SINGLE, K.DOUBLE])
+def test_apply_parity_fp64(name, X, box, c2, bc, layer):
+    dens = W.fourier_density(X.shape[1], seed=1)
+    g, ref, ctx, out = run_pair(X, box, c2, bc, layer, dens)
+    info = ctx.info()
+    assert info["n_arms"] == len(g.arms)
+    assert info["n_cross_h"] == g.hx.line.size and info["n_cross_v"] == g.vx.line.size
+    for k, r in (("v_plus", ref.v_plus), ("v_minus", ref.v_minus), ("dn_plus", ref.dn_plus),
+                 ("dn_minus", ref.dn_minus)):
+        e = rel(out[k], r)
+        print(f"  {k}: rel {e:.3e}")
+        assert e <= TOL64, (k, e)
+
+
+@pytest.mark.parametrize("layer", [K.SINGLE, K.DOUBLE])
+@pytest.mark.parametrize("c", [0.0, 5.0])
+def test_apply_parity_user_ring(layer, c):
+    box = W.box(-1, 1, 128)
+    X = W.circle(256, 0.6, (0.01, -0.02))
+    ring = W.random_ring(box.N, seed=4)
+    dens = W.fourier_density(256, seed=2)
+    g, ref, ctx, out = run_pair(X, box, c * c, K.BOX_USER, layer, dens, ring=ring, grid=True)
+    for k, r in (("v_plus", ref.v_plus), ("v_minus", ref.v_minus), ("dn_plus", ref.dn_plus),
+                 ("dn_minus", ref.dn_minus), ("grid", ref.grid)):
+        e = rel(out[k], r)
+        print(f"  {k}: rel {e:.3e}")
+        assert e <= TOL64, (k, e)
+
+
+def test_full_grid_parity():
+    box = W.box(-1, 1, 256)
+    X = W.star(512)
+    dens = W.fourier_density(512, seed=3)
+    g, ref, ctx, out = run_pair(X, box, 1000.0, K.BOX_ZERO, K.DOUBLE, dens, grid=True)
+    e = rel(out["grid"], ref.grid)
+    print(f"  grid: rel {e:.3e}")
+    assert e <= TOL64
+    assert rel(out["v_plus"], ref.v_plus) <= TOL64
+
+
+@pytest.mark.parametrize("N", [1024, 2048])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config2_full_size(N, precision):
+    """Star r = 0.5(1 + 0.2 cos 5a), 2048 markers, c^2 = 1000, grids 1024^2 and 2048^2:
+    every trace against the oracle."""
+    box = W.box(-1, 1, N)
+    X = W.star(2048)
+    dens = W.fourier_density(2048, seed=0)
+    for layer in (K.SINGLE, K.DOUBLE):
+        g, ref, ctx, out = run_pair(X, box, 1000.0, K.BOX_ZERO, layer, dens, precision=precision)
+        for k, r in (("v_plus", ref.v_plus), ("v_minus", ref.v_minus), ("dn_plus", ref.dn_plus),
+                     ("dn_minus", ref.dn_minus)):
+            e = rel(out[k], r)
+            print(f"  N={N} prec={precision} layer={layer} {k}: rel {e:.3e}")
+            assert e <= (TOL64 if precision == 0 else TOL32), (k, e)
+
+
+@pytest.mark.parametrize("name,X,box,c2,bc", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_apply_parity_fp32(name, X, box, c2, bc):
+    dens = W.fourier_density(X.shape[1], seed=5)
+    for layer in (K.SINGLE, K.DOUBLE):
+        g, ref, ctx, out = run_pair(X, box, c2, bc, layer, dens, precision=1)
+        for k, r in (("v_plus", ref.v_plus), ("v_minus", ref.v_minus)):
+            e = rel(out[k], r)
+            print(f"  fp32 {name} layer={layer} {k}: rel {e:.3e}")
+            assert e <= TOL32, (k, e)
+
+
+def test_operator_parity_hele_shaw_and_dirichlet():
+    from paper_2309_01068_amd import kfbi
+    X = W.hs3(256)
+    box = W.box(-2, 2, 256)
+    g = G.build_geometry(X, box)
+    x = W.fourier_density(256, seed=7) + 0.3
+    ref = K.operator(g, x, K.DOUBLE, K.MINUS, 0.0, 1.0, 1.0, 0.0, K.BOX_FREESPACE)
+    ctx = make_ctx(box, 0.0, K.BOX_FREESPACE, 256)
+    ctx.set_interface(dev(X))
+    y = host(ctx.operator(dev(x), kfbi.DOUBLE, kfbi.MINUS, 0.0, 1.0, 1.0))
+    assert rel(y, ref) <= TOL64
+    X = W.ellipse(256)
+    box = W.box(-1, 1, 128)
+    g = G.build_geometry(X, box)
+    ref = K.operator(g, x, K.DOUBLE, K.PLUS, 0.25, 1.0, 0.0, 0.0)
+    ctx = make_ctx(box, 0.0, K.BOX_ZERO, 256)
+    ctx.set_interface(dev(X))
+    y = host(ctx.operator(dev(x), kfbi.DOUBLE, kfbi.PLUS, 0.25, 1.0, 0.0))
+    assert rel(y, ref) <= TOL64
+
+
+def test_apply_is_bitwise_reproducible():
+    box = W.box(-1, 1, 256)
+    X = W.star(512)
+    ctx = make_ctx(box, 1000.0, K.BOX_ZERO, 512)
+    ctx.set_interface(dev(X))
+    d = dev(W.fourier_density(512, seed=9))
+    a = host(ctx.apply(K.SINGLE, d)["v_plus"])
+    b = host(ctx.apply(K.SINGLE, d)["v_plus"])
+    assert np.array_equal(a, b)
+
+
+def test_reinstalling_a_smaller_interface():
+    """set_interface twice in a row (second with fewer markers) gives oracle parity."""
+    box = W.box(-1, 1, 256)
+    ctx = make_ctx(box, 1000.0, K.BOX_ZERO, 1024)
+    for M in (1024, 300):
+        X = W.star(M)
+        d = W.fourier_density(M, seed=M)
+        ctx.set_interface(dev(X))
+        out = ctx.apply(K.DOUBLE, dev(d))
+        g = G.build_geometry(X, box)
+        ref = K.apply(g, K.DOUBLE, d, 1000.0)
+        assert rel(host(out["v_plus"]), ref.v_plus) <= TOL64
+
+
+def test_error_paths():
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-1, 1, 128)
+    ctx = make_ctx(box, 0.0, K.BOX_ZERO, 256)
+    with pytest.raises(kfbi.KfbiError) as e:
+        ctx.apply(K.DOUBLE, dev(np.zeros(256)))
+    assert e.value.code == kfbi.E_STATE
+    with pytest.raises(kfbi.KfbiError) as e:
+        ctx.set_interface(dev(W.circle(255, 0.5)))          # odd M
+    assert e.value.code == kfbi.E_INVALID
+    with pytest.raises(kfbi.KfbiError) as e:
+        ctx.set_interface(dev(W.circle(256, 0.97)))         # within 3h of the box
+    assert e.value.code == kfbi.E_GEOMETRY
+    a = 2 * np.pi * np.arange(128) / 128
+    with pytest.raises(kfbi.KfbiError) as e:                 # tangent to y = 0.5 at a marker
+        ctx.set_interface(dev(np.stack([0.5 * np.cos(a), 0.5 * np.sin(a)])))
+    assert e.value.code == kfbi.E_GEOMETRY
+    with pytest.raises(kfbi.KfbiError) as e:
+        kfbi.Context(-1, -1, 2, 100)                         # N not a power of two
+    assert e.value.code == kfbi.E_INVALID
+    # the context stays usable after errors
+    X = W.ellipse(256)
+    ctx.set_interface(dev(X))
+    d = W.fourier_density(256, seed=1)
+    ref = K.apply(G.build_geometry(X, box), K.DOUBLE, d, 0.0)
+    assert rel(host(ctx.apply(K.DOUBLE, dev(d))["v_plus"]), ref.v_plus) <= TOL64

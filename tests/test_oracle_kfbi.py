@@ -89,13 +89,15 @@ def _piecewise_quadratic():
     return up, um, gup, gum
 
 
-def test_corrected_scheme_exact_for_piecewise_harmonic_quadratics():
+@pytest.mark.parametrize("curve,N", [("ellipse", 64), ("star", 128)])
+def test_corrected_scheme_exact_for_piecewise_harmonic_quadratics(curve, N):
     """Harmonic quadratics have zero truncation error in the five-point scheme and the
     second-order correction is exact for them, so the grid solution equals u+- at every
-    node up to the interpolation of interface data between markers."""
-    N = 64
+    node up to the interpolation of interface data between markers.  The star passes
+    through the grid node (0, 0.5) up to rounding (column-crossing snapping)."""
     box = W.box(-1, 1, N)
-    g = G.build_geometry(W.ellipse(512), box)
+    X = W.ellipse(512) if curve == "ellipse" else W.star(256)
+    g = G.build_geometry(X, box)
     up, um, gup, gum = _piecewise_quadratic()
     x, y = g.mk.X
     nx, ny = g.mk.normal
@@ -107,12 +109,15 @@ def test_corrected_scheme_exact_for_piecewise_harmonic_quadratics():
     h = box.side / N
     X, Y = np.meshgrid(box.x0 + np.arange(N + 1) * h, box.y0 + np.arange(N + 1) * h)
     exact = np.where(g.inside, up(X, Y), um(X, Y))
-    assert np.max(np.abs(res.grid - exact)) < 1e-8
+    # tolerance = 6-point Lagrange error of the interface data (the 5-fold star has
+    # large high derivatives); a mis-assigned crossing would give errors ~h
+    tol = 1e-8 if curve == "ellipse" else 2e-6
+    assert np.max(np.abs(res.grid - exact)) < tol
     # and the extracted one-sided traces are exact too
-    assert np.max(np.abs(res.v_plus - up(x, y))) < 1e-8
-    assert np.max(np.abs(res.v_minus - um(x, y))) < 1e-8
-    assert np.max(np.abs(res.dn_plus - (nx * gp[0] + ny * gp[1]))) < 1e-7
-    assert np.max(np.abs(res.dn_minus - (nx * gm[0] + ny * gm[1]))) < 1e-7
+    assert np.max(np.abs(res.v_plus - up(x, y))) < tol
+    assert np.max(np.abs(res.v_minus - um(x, y))) < tol
+    assert np.max(np.abs(res.dn_plus - (nx * gp[0] + ny * gp[1]))) < 10 * tol
+    assert np.max(np.abs(res.dn_minus - (nx * gm[0] + ny * gm[1]))) < 10 * tol
 
 
 def test_extraction_exact_on_quadratics():
