@@ -60,7 +60,7 @@ extern "C" {
 typedef struct kfbi_ctx kfbi_ctx;
 
 /* The box [x0, x0+side] x [y0, y0+side] with N intervals per side, h = side/N,
- * nodes (i, j), i, j = 0..N (Sec. 4.2).  64 <= N <= 4096; the operator is
+ * nodes (i, j), i, j = 0..N (Sec. 4.2).  N a power of two, 64 <= N <= 2048; the operator is
  * Delta - c2 (c2 >= 0).  max_markers bounds M (even, 16 <= M <= 4096). */
 typedef struct {
   double x0, y0, side;

@@ -23,7 +23,7 @@ void set_error(const char* fmt, ...) {
 int DBuf::ensure(size_t need) {
   if (need <= bytes) return KFBI_OK;
   if (p) {
-    hipFree(p);
+    (void)hipFree(p);
     p = nullptr;
     bytes = 0;
   }
@@ -39,7 +39,7 @@ int DBuf::ensure(size_t need) {
 }
 
 void DBuf::release() {
-  if (p) hipFree(p);
+  if (p) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
 }
@@ -66,16 +66,18 @@ static int check_ctx(const kfbi_ctx* c, bool need_iface) {
 
 static void release_all(kfbi_ctx* c) {
   DBuf* bufs[] = {&c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
-                  &c->vid,    &c->lab,    &c->armcnt, &c->rowsum,  &c->armrow, &c->armi,
-                  &c->armcoef, &c->armint, &c->intptr, &c->need,    &c->nodeidx, &c->nodei,
+                  &c->vid,    &c->lab,    &c->armcnt, &c->rowsum,  &c->armrow, &c->armpk,
+                  &c->armc,   &c->armk,   &c->colc,   &c->lanef,   &c->cnode,  &c->ccount,
+                  &c->mkloc,  &c->tmat,   &c->pdesc,  &c->rowpart,
+                  &c->armcoef, &c->intptr, &c->need,    &c->nodeidx, &c->nodei,
                   &c->rowptr, &c->rows,   &c->mknode, &c->ext,     &c->gstat,  &c->mq,
                   &c->armr,   &c->qpart,  &c->ring,   &c->sinT,    &c->sinT32, &c->gband,
                   &c->nodeval, &c->tmpM,  &c->gV,     &c->gH,      &c->gsc,    &c->gpart,
                   &c->gcnt,   &c->gw,     &c->gx,     &c->gr,      &c->gd};
   for (DBuf* b : bufs) b->release();
   for (int i = 0; i < kfbi_ctx::kProfPool; ++i)
-    if (c->prof_ev[i]) hipEventDestroy(c->prof_ev[i]);
-  if (c->hpin) hipHostFree(c->hpin);
+    if (c->prof_ev[i]) (void)hipEventDestroy(c->prof_ev[i]);
+  if (c->hpin) (void)hipHostFree(c->hpin);
   c->hpin = nullptr;
 }
 
@@ -94,8 +96,8 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
   }
   *out = nullptr;
   const int N = g->N;
-  if (N < 64 || N > 4096 || (N & (N - 1)) != 0) {
-    set_error("N must be a power of two in [64, 4096] (got %d)", N);
+  if (N < 64 || N > 2048 || (N & (N - 1)) != 0) {
+    set_error("N must be a power of two in [64, 2048] (got %d)", N);
     return KFBI_E_INVALID;
   }
   if (!(g->side > 0.0) || !(g->c2 >= 0.0) || !std::isfinite(g->x0) || !std::isfinite(g->y0)) {
@@ -149,11 +151,12 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
       (st = c->armrow.ensure(sizeof(int) * (N + 2))) ||
       (st = c->rows.ensure(sizeof(int) * (N + 2))) ||
       (st = c->rowptr.ensure(sizeof(int) * (N + 2))) ||
+      (st = c->rowpart.ensure(sizeof(int) * (N + 2))) ||
       (st = c->nodei.ensure(sizeof(int) * 6 * Mx)) ||
       (st = c->nodeval.ensure(sizeof(double) * 6 * Mx)) ||
       (st = c->mq.ensure(sizeof(double) * 5 * Mx)) ||
       (st = c->qpart.ensure(sizeof(double) * (Mx + 64))) ||
-      (st = c->ring.ensure(sizeof(double) * 4 * (N + 1))) ||
+      (st = c->ring.ensure(sizeof(double) * 8 * (N + 1))) ||
       (st = c->sinT.ensure(sizeof(double) * 2 * N)) ||
       (st = c->sinT32.ensure(sizeof(float) * 2 * N)) ||
       (st = c->gband.ensure(sizeof(double) * n * N)) ||
@@ -165,6 +168,7 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
   }
   hipLaunchKernelGGL(k_sintab, dim3((2 * N + 255) / 256), dim3(256), 0, c->stream, N,
                      c->sinT.as<double>(), c->sinT32.as<float>());
+  if ((st = colconst_setup(c)) != KFBI_OK) return fail(st);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
     set_error("sine table kernel failed");
     return fail(KFBI_E_HIP);
@@ -175,7 +179,7 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
 
 int kfbi_destroy(kfbi_ctx* c) {
   if (!c) return KFBI_OK;
-  hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
   release_all(c);
   delete c;
   return KFBI_OK;
@@ -188,10 +192,10 @@ int kfbi_set_interface(kfbi_ctx* c, int M, const double* xy) {
     return KFBI_E_INVALID;
   }
   c->have_interface = 0;
+  c->mk_chunk = M >= 1024 ? M / 256 : 4;
+  c->n_mk_blocks = (M + c->mk_chunk - 1) / c->mk_chunk;
   const int st = geometry_setup(c, M, xy);
   if (st != KFBI_OK) return st;
-  c->mk_chunk = M >= 2048 ? M / 256 : 8;
-  c->n_mk_blocks = (M + c->mk_chunk - 1) / c->mk_chunk;
   c->have_interface = 1;
   return KFBI_OK;
 }

@@ -1,26 +1,30 @@
 // One KFBI operator apply on gfx950 (Sec. 4): four kernels per apply.
 //
-//  K1 k_prep     density -> Fourier derivatives at markers (circulant form, FP64), jump
-//                corrections of every irregular arm (Sec. 4.2.1 eq. modified-fdm with the
-//                App. A.1 jumps, coefficients precomputed per interface), trapezoid weight
-//                partial sums, and free-space box data (Sec. 4.1) when requested.
-//  K2 k_colsolve fast solve of (Delta_h - c^2) v = RHS.  The RHS is non-zero only at
-//                irregular nodes and next to the box, so the sine transform along x is
-//                formed directly from the arm list; along y each sine mode p leaves the
-//                constant tridiagonal system
-//                    G_{j+1} - (2 + delta_p) G_j + G_{j-1} = h^2 Rhat_{p,j},  G_0 = G_N = 0,
-//                    delta_p = 4 sin^2(p pi / 2N) + h^2 c^2,
-//                solved per wavefront by two first-order recurrences with root
-//                rho_p (rho + 1/rho = 2 + delta_p) and a rank-one boundary correction.
-//                One wavefront per mode, four modes per block; output rows of G.
-//  K3 k_nodes    inverse sine transform along x evaluated only at the interpolation
-//                nodes: v_ij = (2/N) sum_p G_{j,p} sin(p i pi / N).
-//  K4 k_extract  Sec. 4.3 corrected interpolation with precomputed weights -> v+-,
+//  K1 k_prep     density -> Fourier derivatives at the markers in circulant form
+//                (Phi_a, Phi_aa or Psi_a; FP64), trapezoid-weight partial sums, and the
+//                free-space box data of Sec. 4.1 when requested.
+//  K2 k_rowdst   per grid row: jump corrections of the row's irregular arms (Sec. 4.2.1
+//                eq. modified-fdm with App. A.1 jumps; 6-point interpolation of the
+//                marker quantities, coefficients precomputed per interface) and the sine
+//                transform along x of the row's sparse right-hand side,
+//                    T[j][p] = sum_{arms in row j} r_a sin(p i_a pi / N).
+//  K3 k_colsolve per sine mode p along y, the constant tridiagonal system
+//                    G_{j+1} - (2 + delta_p) G_j + G_{j-1} = h^2 T[j][p] (+ box terms),
+//                    delta_p = 4 sin^2(p pi / 2N) + h^2 c^2,  G_0 = G_N = 0,
+//                solved per wavefront by two first-order recurrences (root rho_p of
+//                rho + 1/rho = 2 + delta_p) and a rank-one boundary correction; four modes
+//                per block, output rows row_lo..row_hi of G.
+//  K4 k_nodes_extract  per chunk of markers: inverse transform along x at the chunk's
+//                interpolation nodes, v_ij = (2/N) sum_p G[j][p] sin(p i pi / N), then the
+//                Sec. 4.3 corrected interpolation with precomputed weights -> v+-,
 //                n.grad v+-, and the boundary operator a x + b trace + q int x ds.
-// The full-grid variant writes every row in K2 and evaluates the whole grid with a
-// tiled product against the sine matrix.
+// Together K2-K4 are the exact solution of the corrected five-point system (the 2-D
+// sine transform with the y-direction replaced by its tridiagonal equivalent).  The
+// full-grid variant writes every row in K3 and evaluates the whole grid with a tiled
+// product against the sine matrix.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -29,19 +33,62 @@
 namespace kfbi {
 
 constexpr int kColsPerBlock = 4;
+constexpr int kReg = 4;       // circulant outputs per thread in K1
+constexpr int kNodeBatch = 8; // nodes reduced together in K4
+
+// Two-level sine table in LDS: sin/cos(pi m / N) for m = 64 q + r from
+// hs/hc[q] = sin/cos(pi 64 q / N) and ls/lc[r] = sin/cos(pi r / N) by angle addition.
+template <class T>
+struct SinTab2 {
+  T* hs;
+  T* hc;
+  T* ls;
+  T* lc;
+  __device__ void stage(T* base, int N, const T* __restrict__ sinT) {
+    const int nh = (2 * N) / 64 > 0 ? (2 * N) / 64 : 1;
+    hs = base;
+    hc = base + nh;
+    ls = base + 2 * nh;
+    lc = base + 2 * nh + 64;
+    const int mask = 2 * N - 1, quarter = N / 2;
+    const int t = threadIdx.x;
+    if (t < nh) {
+      hs[t] = sinT[(64 * t) & mask];
+      hc[t] = sinT[(64 * t + quarter) & mask];
+    }
+    if (t < 64) {
+      ls[t] = sinT[t & mask];
+      lc[t] = sinT[(t + quarter) & mask];
+    }
+  }
+  __device__ __forceinline__ void get(int m, T& s, T& c) const {
+    const int q = m >> 6, r = m & 63;
+    const T sa = hs[q], ca = hc[q], sb = ls[r], cb = lc[r];
+    s = sa * cb + ca * sb;
+    c = ca * cb - sa * sb;
+  }
+};
+template <class T>
+__host__ __device__ constexpr int sintab2_size(int N) {
+  return 2 * ((2 * N) / 64 > 0 ? (2 * N) / 64 : 1) + 128;
+}
+
+// Column-group-major layouts: the four modes p = 4g+1..4g+4 of a row are adjacent and
+// the rows of one group are contiguous.
+__device__ __forceinline__ size_t grp_index(int p, int r, int nrows) {
+  return (static_cast<size_t>((p - 1) >> 2) * nrows + r) * 4 + ((p - 1) & 3);
+}
 
 // ---------------------------------------------------------------------------------- K1
-// Marker-chunk blocks: blocks [0, nmk).  Ring blocks (free-space box): [nmk, nmk+nring).
-template <class T>
+// Marker-chunk blocks [0, nmk): derivatives at markers k0..k1-1 with phi, d1, d2 staged
+// in LDS; every thread accumulates kReg consecutive outputs over a slice of m with a
+// sliding window on d.  Ring blocks [nmk, nmk+nring): free-space box data.
 __global__ void __launch_bounds__(256)
     k_prep(int M, int C, int nmk, int layer, const double* __restrict__ dens,
            const double* __restrict__ d1, const double* __restrict__ d2,
-           const ArmCoef* __restrict__ armc, const int* __restrict__ armint,
-           const int* __restrict__ intoff, T* __restrict__ armr, double* __restrict__ mq,
-           double* __restrict__ qpart, const MarkerExt* __restrict__ ext,
-           // free-space box data
-           int nring, int N, double x0, double y0, double h, const double* __restrict__ X,
-           const double* __restrict__ geo, T* __restrict__ ring) {
+           double* __restrict__ mq, double* __restrict__ qpart, const double* __restrict__ wq,
+           int N, double x0, double y0, double h, const double* __restrict__ X,
+           const double* __restrict__ geo, double* __restrict__ ring) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
   if (static_cast<int>(blockIdx.x) >= nmk) {
@@ -83,97 +130,215 @@ __global__ void __launch_bounds__(256)
           acc += dens[k] * sa[k] * 0.5 * log(r2);
       }
       acc = wave_sum(acc);
-      if (lane == 0) ring[node] = static_cast<T>(acc / M);
+      if (lane == 0) ring[node] = acc / M;
     }
     return;
   }
-  // ----- marker chunk
   const int b = blockIdx.x;
   const int k0 = b * C;
   const int k1 = min(M, k0 + C);
-  const int H = k1 - k0 + 5;  // markers k0-2 .. k1+2
+  const int H = k1 - k0;
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
-  const int nout = H * nd;
+  const int ngr = (H + kReg - 1) / kReg;
+  const int ng = ngr * nd;
+  const int S = 256 / ng;  // slices of m
   double* ph = lds;             // M
-  double* part = lds + M;       // 8 * nout
-  double* Qh = part + 8 * nout; // 5 * H
-  for (int m = tid; m < M; m += 256) ph[m] = dens[m];
-  __syncthreads();
-  // circulant dot products: output o = (hm, deriv), 8 slices of m
-  {
-    const int slices = 8;
-    const int per = (M + slices - 1) / slices;
-    for (int task = tid; task < nout * slices; task += 256) {
-      const int o = task % nout, sl = task / nout;
-      const int hm = o % H, dv = o / H;
-      int k = k0 - 2 + hm;
-      k = (k < 0) ? k + M : (k >= M ? k - M : k);
-      const double* dd = (dv == 0) ? d1 : d2;
-      const int mb = sl * per, me = min(M, mb + per);
-      double acc = 0.0;
-      for (int m = mb; m < me; ++m) {
-        int q = k - m;
-        q += (q < 0) ? M : 0;
-        acc += dd[q] * ph[m];
+  double* dl1 = ph + M;         // M
+  double* dl2 = dl1 + M;        // M (double layer only)
+  double* part = dl1 + nd * M;  // 256 * kReg
+  const double wmine = (k0 + tid < k1) ? wq[k0 + tid] : 0.0;
+  for (int m0 = tid; m0 < M; m0 += 256 * 8) {
+    double a[8], bb[8], cc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int m = m0 + 256 * u;
+      if (m < M) {
+        a[u] = dens[m];
+        bb[u] = d1[m];
+        cc[u] = (nd == 2) ? d2[m] : 0.0;
       }
-      part[sl * nout + o] = acc;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int m = m0 + 256 * u;
+      if (m < M) {
+        ph[m] = a[u];
+        dl1[m] = bb[u];
+        if (nd == 2) dl2[m] = cc[u];
+      }
     }
   }
   __syncthreads();
-  for (int hm = tid; hm < H; hm += 256) {
-    int k = k0 - 2 + hm;
-    k = (k < 0) ? k + M : (k >= M ? k - M : k);
-    double v1 = 0.0, v2 = 0.0;
-    for (int sl = 0; sl < 8; ++sl) {
-      v1 += part[sl * nout + hm];
-      if (nd == 2) v2 += part[sl * nout + H + hm];
+  if (tid < S * ng) {
+    const int g = tid % ng, sl = tid / ng;
+    const int dv = g / ngr, gr = g % ngr;
+    const double* dd = dv == 0 ? dl1 : dl2;
+    const int per = (M + S - 1) / S;
+    const int mb = sl * per, me = min(M, mb + per);
+    // outputs k_r = k0 + gr*kReg + r ; window w[r] = d[(k_r - m) mod M]
+    int kb = (k0 + gr * kReg - mb) % M;
+    kb += (kb < 0) ? M : 0;
+    double w[kReg], acc[kReg];
+#pragma unroll
+    for (int r = 0; r < kReg; ++r) {
+      int q = kb + r;
+      q -= (q >= M) ? M : 0;
+      w[r] = dd[q];
+      acc[r] = 0.0;
     }
-    double Q[5];
-    if (layer == KFBI_DOUBLE) {
-      Q[0] = ph[k];
-      Q[1] = v1;
-      Q[2] = v2;
-      Q[3] = 0.0;
-      Q[4] = 0.0;
-    } else {  // Psi = -psi
-      Q[0] = 0.0;
-      Q[1] = 0.0;
-      Q[2] = 0.0;
-      Q[3] = -ph[k];
-      Q[4] = -v1;
+    int q = kb;  // index of w[0]
+    int m = mb;
+    for (; m + 8 <= me; m += 8) {
+      double f[8], nw[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        f[u] = ph[m + u];
+        int qq = q - 1 - u;
+        qq += (qq < 0) ? M : 0;
+        nw[u] = dd[qq];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+#pragma unroll
+        for (int r = 0; r < kReg; ++r) acc[r] += w[r] * f[u];
+#pragma unroll
+        for (int r = kReg - 1; r > 0; --r) w[r] = w[r - 1];
+        w[0] = nw[u];
+      }
+      q -= 8;
+      q += (q < 0) ? M : 0;
+    }
+    for (; m < me; ++m) {
+      const double f = ph[m];
+#pragma unroll
+      for (int r = 0; r < kReg; ++r) acc[r] += w[r] * f;
+#pragma unroll
+      for (int r = kReg - 1; r > 0; --r) w[r] = w[r - 1];
+      q = (q == 0) ? M - 1 : q - 1;
+      w[0] = dd[q];
     }
 #pragma unroll
-    for (int q = 0; q < 5; ++q) Qh[q * H + hm] = Q[q];
-    if (hm >= 2 && hm < H - 3) {
-#pragma unroll
-      for (int q = 0; q < 5; ++q) mq[q * M + k] = Q[q];
-    }
+    for (int r = 0; r < kReg; ++r) part[(sl * ng + g) * kReg + r] = acc[r];
   }
   __syncthreads();
-  // arm corrections for crossings in intervals k0 .. k1-1
-  const int a0 = intoff[k0], a1 = intoff[k1];
-  for (int t = a0 + tid; t < a1; t += 256) {
-    const int a = armint[t];
-    const ArmCoef ac = armc[a];
-    const int base = ac.k - k0;  // Lagrange node m -> halo index base + m
-    double r = 0.0;
+  double v1 = 0.0, v2 = 0.0;
+  if (tid < H) {
+    const int gr = tid / kReg, r = tid % kReg;
+    int sl = 0;
+    for (; sl + 8 <= S; sl += 8) {
+      double a[8], bb[8];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      double s = 0.0;
+      for (int u = 0; u < 8; ++u) {
+        a[u] = part[((sl + u) * ng + gr) * kReg + r];
+        bb[u] = (nd == 2) ? part[((sl + u) * ng + ngr + gr) * kReg + r] : 0.0;
+      }
 #pragma unroll
-      for (int q = 0; q < 5; ++q) s += ac.coef[q] * Qh[q * H + base + m];
-      r += ac.l[m] * s;
+      for (int u = 0; u < 8; ++u) {
+        v1 += a[u];
+        v2 += bb[u];
+      }
     }
-    armr[a] = static_cast<T>(r);
+    for (; sl < S; ++sl) {
+      v1 += part[(sl * ng + gr) * kReg + r];
+      if (nd == 2) v2 += part[(sl * ng + ngr + gr) * kReg + r];
+    }
   }
   // trapezoid partial sum of the density
-  double qs = 0.0;
-  for (int k = k0 + tid; k < k1; k += 256) qs += ph[k] * ext[k].wq;
+  double qs = (k0 + tid < k1) ? ph[k0 + tid] * wmine : 0.0;
+  for (int k = k0 + 256 + tid; k < k1; k += 256) qs += ph[k] * wq[k];
+  __syncthreads();
   qs = block_sum<double>(qs, part);
+  // global stores last (no barrier waits on them)
+  if (tid < H) {
+    const int k = k0 + tid;
+    if (layer == KFBI_DOUBLE) {
+      mq[k] = ph[k];
+      mq[M + k] = v1;
+      mq[2 * M + k] = v2;
+      mq[3 * M + k] = 0.0;
+      mq[4 * M + k] = 0.0;
+    } else {  // Psi = -psi
+      mq[k] = 0.0;
+      mq[M + k] = 0.0;
+      mq[2 * M + k] = 0.0;
+      mq[3 * M + k] = -ph[k];
+      mq[4 * M + k] = -v1;
+    }
+  }
   if (tid == 0) qpart[b] = qs;
 }
 
 // ---------------------------------------------------------------------------------- K2
+// One block per row part (a row's arms in groups of at most kArmsPerPart).  The part's
+// arm corrections
+//   r_a = sum_m l_m sum_q coef_q Q_q(k_a - 2 + m)
+// (6-point interpolation of the marker quantities Q = (Phi, Phi_a, Phi_aa, Psi, Psi_a))
+// are formed one per thread; then every thread evaluates the partial transform
+// T_part[p] = sum_a r_a sin(p i_a pi / N) for PT consecutive modes p, starting from the
+// two-level table and rotating in steps of i_a pi / N.  Parts of one row are summed in
+// part order by the solve kernel.
+template <class T, int PT>
+__global__ void __launch_bounds__(256)
+    k_rowdst(int N, int M, int P, const int4* __restrict__ pdesc, const int* __restrict__ armpk,
+             const double* __restrict__ coefR, const int* __restrict__ kR, int cap,
+             const double* __restrict__ mq, const T* __restrict__ sinT, T* __restrict__ Tg) {
+  __shared__ T tab[sintab2_size<T>(4096)];
+  __shared__ T rr[kArmsPerPart];
+  __shared__ int ii[kArmsPerPart];
+  const int n = N - 1;
+  const int mask = 2 * N - 1;
+  const int tid = threadIdx.x;
+  const int q = blockIdx.x;
+  const int4 d = pdesc[q];
+  const int ab = d.y, na = d.z - d.y;
+  SinTab2<T> st2;
+  st2.stage(tab, N, sinT);
+  if (tid < na) {
+    const int a = ab + tid;
+    const int k = kR[a];
+    double l[6], cf[5];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) l[m] = coefR[m * cap + a];
+#pragma unroll
+    for (int qq = 0; qq < 5; ++qq) cf[qq] = coefR[(6 + qq) * cap + a];
+    double r = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      int km = k - 2 + m;
+      km = (km < 0) ? km + M : (km >= M ? km - M : km);
+      double sm = 0.0;
+#pragma unroll
+      for (int qq = 0; qq < 5; ++qq) sm += cf[qq] * mq[qq * M + km];
+      r += l[m] * sm;
+    }
+    rr[tid] = static_cast<T>(r);
+    ii[tid] = armpk[a] & 0xffff;
+  }
+  __syncthreads();
+  const int p0 = 1 + tid * PT;
+  T acc[PT];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) acc[k] = T(0);
+  for (int t = 0; t < na; ++t) {
+    const int i = ii[t];
+    const T r = rr[t];
+    T s, c, sb, cb;
+    st2.get((p0 * i) & mask, s, c);
+    st2.get(i & mask, sb, cb);
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      acc[k] += r * s;
+      const T t2 = s * cb + c * sb;
+      c = c * cb - s * sb;
+      s = t2;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PT; ++k)
+    if (p0 + k <= n) Tg[grp_index(p0 + k, q, P)] = acc[k];
+}
+
+// ---------------------------------------------------------------------------------- K3
 template <int E>
 __device__ __forceinline__ int slot(int j) {  // row j (1-based) -> LDS slot, padded
   const int e = j - 1;
@@ -182,58 +347,96 @@ __device__ __forceinline__ int slot(int j) {  // row j (1-based) -> LDS slot, pa
 
 template <class T, int E>
 __global__ void __launch_bounds__(256)
-    k_colsolve(int N, double h, double c2, const int* __restrict__ rowoff,
-               const int* __restrict__ armi, const T* __restrict__ armr,
-               const T* __restrict__ sinT, const T* __restrict__ ring, int jlo, int jhi,
-               int ldG, T* __restrict__ G, int nblk_x) {
+    k_colsolve(int N, double h, int P, const T* __restrict__ Tg, const int* __restrict__ rowpart,
+               const T* __restrict__ sinTg, const T* __restrict__ ring,
+               const double* __restrict__ colc, const double* __restrict__ lanef, int jlo,
+               int jhi, T* __restrict__ Gg, int nblk_x) {
   __shared__ T col[kColsPerBlock][64 * (E + 1)];
+  extern __shared__ double dynp[];  // the group's P part rows, 4 modes each
+  T* tp = reinterpret_cast<T*>(dynp);
   const int n = N - 1;
   const int mask = 2 * N - 1;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   // XCD-aware order: blocks resident on one XCD (ids congruent mod 8) take adjacent
-  // column groups, so partial cache lines of the row-major output meet in one L2.
+  // column groups.
   const int bid = blockIdx.x;
   const int per_xcd = (nblk_x + 7) / 8;
   const int grp = (bid % 8) * per_xcd + bid / 8;
   if (grp * kColsPerBlock + 1 > n) return;  // whole block beyond the last mode
   const int p0 = 1 + grp * kColsPerBlock;
-  int pc[kColsPerBlock];
+  const int p = p0 + w;
+  const bool live = (p <= n);
+  double rho = 0.0, eps = 0.0, inv_den = 0.0, abase = 0.0, r2j0 = 0.0;
+  if (live) {
+    rho = colc[3 * (p - 1)];
+    eps = colc[3 * (p - 1) + 1];
+    inv_den = colc[3 * (p - 1) + 2];
+    abase = lanef[(static_cast<size_t>(p - 1) * 64 + lane) * 2];
+    r2j0 = lanef[(static_cast<size_t>(p - 1) * 64 + lane) * 2 + 1];
+  }
+  constexpr int R = (64 * E + 255) / 256;  // rows per thread in the row sums
+  int rq0[R], rq1[R];
 #pragma unroll
-  for (int c = 0; c < kColsPerBlock; ++c) pc[c] = p0 + c;
-  const T ih2 = static_cast<T>(1.0 / (h * h));
-  // phase 1: sine transform along x of the sparse right-hand side, row by row
-  for (int idx = tid; idx < kColsPerBlock * 64 * (E + 1); idx += 256) (&col[0][0])[idx] = T(0);
-  __syncthreads();
-  for (int j = 1 + tid; j <= n; j += 256) {
-    T acc[kColsPerBlock];
+  for (int u = 0; u < R; ++u) {
+    const int j = 1 + tid + 256 * u;
+    rq0[u] = (j <= n) ? rowpart[j] : 0;
+    rq1[u] = (j <= n) ? rowpart[j + 1] : 0;
+  }
+  // the group's part rows are contiguous: P x 4 values
+  {
+    const T* src = Tg + static_cast<size_t>(grp) * P * 4;
+    constexpr int U = 8;
+    for (int e0 = tid; e0 < 4 * P; e0 += 256 * U) {
+      T v[U];
 #pragma unroll
-    for (int c = 0; c < kColsPerBlock; ++c) acc[c] = T(0);
-    const int ae = rowoff[j + 1];
-    for (int a = rowoff[j]; a < ae; ++a) {
-      const int i = armi[a];
-      const T r = armr[a];
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 256 * u;
+        v[u] = (e < 4 * P) ? src[e] : T(0);
+      }
 #pragma unroll
-      for (int c = 0; c < kColsPerBlock; ++c) acc[c] += r * sinT[(pc[c] * i) & mask];
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < 4 * P) tp[e] = v[u];
+      }
     }
-    if (ring) {  // left (i=0) and right (i=N) box nodes next to (1, j) and (N-1, j)
-      const int n1 = N + 1;
+  }
+  __syncthreads();
+  // rows: sum of their parts in part order (rows without arms are zero)
+  {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int j = 1 + tid + 256 * u;
+      if (j > 64 * E) continue;
+      T a4[kColsPerBlock] = {};
+      if (j <= n) {
+        for (int qq = rq0[u]; qq < rq1[u]; ++qq)
+#pragma unroll
+          for (int c = 0; c < kColsPerBlock; ++c) a4[c] += tp[4 * qq + c];
+      }
+#pragma unroll
+      for (int c = 0; c < kColsPerBlock; ++c) col[c][slot<E>(j)] = a4[c];
+    }
+  }
+  __syncthreads();
+  if (ring) {
+    const T ih2 = static_cast<T>(1.0 / (h * h));
+    // left (i=0) and right (i=N) box nodes next to (1, j) and (N-1, j)
+    const int n1 = N + 1;
+    for (int j = 1 + tid; j <= n; j += 256) {
       const T gl = ring[2 * n1 + j], gr = ring[3 * n1 + j];
 #pragma unroll
       for (int c = 0; c < kColsPerBlock; ++c)
-        acc[c] -= ih2 * (gl * sinT[pc[c] & mask] + gr * sinT[(pc[c] * n) & mask]);
+        col[c][slot<E>(j)] -=
+            ih2 * (gl * sinTg[(p0 + c) & mask] + gr * sinTg[((p0 + c) * n) & mask]);
     }
-#pragma unroll
-    for (int c = 0; c < kColsPerBlock; ++c) col[c][slot<E>(j)] = acc[c];
-  }
-  __syncthreads();
-  if (ring) {  // bottom (j=0) and top (j=N) box rows: a full sine sum each
-    const int p = pc[w];
+    __syncthreads();
+    // bottom (j=0) and top (j=N) box rows: a full sine sum each
     T sb = T(0), st = T(0);
     for (int i = 1 + lane; i <= n; i += 64) {
-      const T s = sinT[(p * i) & mask];
-      sb += ring[i] * s;
-      st += ring[(N + 1) + i] * s;
+      const T sv = sinTg[(p * i) & mask];
+      sb += ring[i] * sv;
+      st += ring[n1 + i] * sv;
     }
     sb = wave_sum(sb);
     st = wave_sum(st);
@@ -241,19 +444,13 @@ __global__ void __launch_bounds__(256)
       col[w][slot<E>(1)] -= ih2 * sb;
       col[w][slot<E>(n)] -= ih2 * st;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  // phase 2: tridiagonal solve along y for mode p = pc[w], one wavefront
-  const int p = pc[w];
-  if (p <= n) {
-    const double sp = sinpi(0.5 * p / N);
-    const double delta = 4.0 * sp * sp + h * h * c2;
-    const double sq = sqrt(delta * (4.0 + delta));
-    const double rho = 2.0 / (2.0 + delta + sq);
-    const double eps = (delta + sq) / (2.0 + delta + sq);  // 1 - rho without cancellation
+  // tridiagonal solve along y for mode p, one wavefront; recurrences in eps = 1 - rho
+  // form so FP32 keeps 1 - rho to full precision
+  if (live) {
     const T rhoT = static_cast<T>(rho), epsT = static_cast<T>(eps);
     const T h2 = static_cast<T>(h * h);
-    // powers rho^e, e = 0..E
     double pw[E + 1];
     pw[0] = 1.0;
 #pragma unroll
@@ -295,116 +492,194 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int e = 0; e < E; ++e) y[e] += static_cast<T>(pw[e + 1]) * carry;
     }
-    // z_n and the rank-one boundary correction
+    // G_j = -rho z_j + z_n rho^{n-j+3} (1 - rho^{2j}) / (1 - rho^{2n+2})
     const int ln = (n - 1) / E, en = (n - 1) % E;
     T sel = T(0);
 #pragma unroll
     for (int e = 0; e < E; ++e)
       if (e == en) sel = y[e];
     const T zn = __shfl(sel, ln, 64);
-    const double lr = log1p(-eps);
-    const double den = -expm1((2.0 * n + 2.0) * lr);
-    const int j0 = lane * E + 1;
-    // rho^{n - j + 3} for j = j0 + E - 1, then multiply up
-    const double abase = exp(static_cast<double>(n - (j0 + E - 1) + 3) * lr);
-    const double r2j0 = exp(2.0 * j0 * lr);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const double a = abase * pw[E - 1 - e];
       const double om = 1.0 - r2j0 * pw[e] * pw[e];
-      const double f = a * om / den;
-      y[e] = -rhoT * y[e] + static_cast<T>(f) * zn;
+      y[e] = -rhoT * y[e] + static_cast<T>(a * om * inv_den) * zn;
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) col[w][lane * (E + 1) + e] = y[e];
   }
   __syncthreads();
-  // phase 3: rows jlo..jhi of G (row-major, ldG; column p stored at p - 1)
+  // rows jlo..jhi of G, column-group-major: this block's rows are contiguous
   const int nb = jhi - jlo + 1;
-  for (int r = tid; r < nb; r += 256) {
-    const int j = jlo + r;
-    const int sj = slot<E>(j);
-    T* dst = G + static_cast<size_t>(r) * ldG + (p0 - 1);
-#pragma unroll
-    for (int c = 0; c < kColsPerBlock; ++c)
-      if (p0 + c <= n) dst[c] = col[c][sj];
+  T* dst = Gg + static_cast<size_t>(grp) * nb * 4;
+  for (int e = tid; e < 4 * nb; e += 256) {
+    const int r = e >> 2, c = e & 3;
+    dst[e] = (p0 + c <= n) ? col[c][slot<E>(jlo + r)] : T(0);
   }
 }
 
-// ---------------------------------------------------------------------------------- K3
-template <class T, int E>
-__global__ void __launch_bounds__(256)
-    k_nodes(int N, const int* __restrict__ rows, const int* __restrict__ rowptr,
-            const int* __restrict__ nodei, const T* __restrict__ sinT, int jlo, int ldG,
-            const T* __restrict__ G, T* __restrict__ nodeval) {
+// Per-mode constants of the column solve (depend on N, h, c^2 only):
+//   colc[3(p-1) + {0,1,2}] = rho_p, 1 - rho_p, 1 / (1 - rho_p^{2n+2})
+//   lanef[((p-1) 64 + l) 2 + {0,1}] = rho^{n - (j0+E-1) + 3}, rho^{2 j0}, j0 = l E + 1
+__global__ void k_colconst(int N, double hc2, int E, double* __restrict__ colc,
+                           double* __restrict__ lanef) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = N - 1;
-  const int mask = 2 * N - 1;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r = blockIdx.x;
-  const int j = rows[r];
-  const int nb = rowptr[r], ne = rowptr[r + 1];
-  const T* g = G + static_cast<size_t>(j - jlo) * ldG;
-  T gv[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int p = 1 + lane + 64 * e;
-    gv[e] = (p <= n) ? g[p - 1] : T(0);
+  if (t >= n * 64) return;
+  const int p = 1 + t / 64, l = t % 64;
+  const double sp = sinpi(0.5 * p / N);
+  const double delta = 4.0 * sp * sp + hc2;
+  const double sq = sqrt(delta * (4.0 + delta));
+  const double rho = 2.0 / (2.0 + delta + sq);
+  const double eps = (delta + sq) / (2.0 + delta + sq);
+  const double lr = log1p(-eps);
+  if (l == 0) {
+    colc[3 * (p - 1)] = rho;
+    colc[3 * (p - 1) + 1] = eps;
+    colc[3 * (p - 1) + 2] = 1.0 / (-expm1((2.0 * n + 2.0) * lr));
   }
-  const T scale = static_cast<T>(2.0 / N);
-  for (int idx = nb + w; idx < ne; idx += 4) {
-    const int i = nodei[idx];
-    T s = T(0);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int p = 1 + lane + 64 * e;
-      s += gv[e] * sinT[(p * i) & mask];
-    }
-    s = wave_sum(s);
-    if (lane == 0) nodeval[idx] = scale * s;
-  }
+  const int j0 = l * E + 1;
+  lanef[static_cast<size_t>(t) * 2] = exp(static_cast<double>(n - (j0 + E - 1) + 3) * lr);
+  lanef[static_cast<size_t>(t) * 2 + 1] = exp(2.0 * j0 * lr);
 }
 
 // ---------------------------------------------------------------------------------- K4
-template <class T>
+// One block per chunk of MC markers.  Its distinct stencil nodes (sorted by row) are
+// split over the four wavefronts; lane l of a wavefront keeps G[j][p] for
+// p = 1 + l + 64 e and advances sin(p i pi / N) over e by the angle-addition rotation
+// with step 64 i pi / N.  Eight nodes are reduced together by recursive halving.  Then
+// MC threads apply the Sec. 4.3 corrected interpolation.
+template <class T, int E>
 __global__ void __launch_bounds__(256)
-    k_extract(int M, const int* __restrict__ stn, const T* __restrict__ nodeval,
-              const double* __restrict__ mq, const MarkerExt* __restrict__ ext,
-              const double* __restrict__ qpart, int nq, double* __restrict__ vp_out,
-              double* __restrict__ vm_out, double* __restrict__ dnp_out,
-              double* __restrict__ dnm_out, int side, double oa, double ob, double oq,
-              const double* __restrict__ xop, double* __restrict__ yop) {
-  __shared__ double scratch[16];
+    k_nodes_extract(int N, int M, int MC, const int* __restrict__ cnode,
+                    const int* __restrict__ ccount, const int* __restrict__ mkloc,
+                    const T* __restrict__ sinT, int jlo, int nbr, const T* __restrict__ G,
+                    const double* __restrict__ mq, const double* __restrict__ ext,
+                    const double* __restrict__ qpart, int nq, double* __restrict__ vp_out,
+                    double* __restrict__ vm_out, double* __restrict__ dnp_out,
+                    double* __restrict__ dnm_out, int side, double oa, double ob, double oq,
+                    const double* __restrict__ xop, double* __restrict__ yop) {
+  extern __shared__ double nval[];  // 6 * MC node values
+  __shared__ double red[16];
+  __shared__ T tab[sintab2_size<T>(4096)];
+  SinTab2<T> st2;
+  st2.stage(tab, N, sinT);
+  __syncthreads();
+  const int n = N - 1;
+  const int mask = 2 * N - 1;
+  const int quarter = N / 2;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int ch = blockIdx.x;
+  const int nn = ccount[ch];
+  const int* keys = cnode + static_cast<size_t>(ch) * 6 * MC;
+  // prefetch the extraction data of this thread's marker (used after the node phase)
+  const int kx = ch * MC + tid;
+  const bool xmk = (tid < MC && kx < M);
+  int loc[6];
+  double Q[5], xw[kExtCount - 1];
+  if (xmk) {
+#pragma unroll
+    for (int m = 0; m < 6; ++m) loc[m] = mkloc[6 * kx + m];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Q[q] = mq[q * M + kx];
+#pragma unroll
+    for (int q = 0; q < kExtCount - 1; ++q) xw[q] = ext[q * M + kx];
+  }
   double qs = 0.0;
   if (yop && oq != 0.0) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < nq; i += blockDim.x) s += qpart[i];
-    qs = block_sum<double>(s, scratch);
+    for (int i = tid; i < nq; i += 256) s += qpart[i];
+    qs = block_sum<double>(s, red);
   }
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M) return;
-  const MarkerExt& me = ext[k];
-  double v[6], Q[5];
+  // this wavefront's nodes (contiguous in the sorted list, so rows repeat)
+  const int per = (nn + 3) / 4;
+  const int qb = w * per, qe = min(nn, qb + per);
+  int curj = -1;
+  T gv[E];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) v[m] = static_cast<double>(nodeval[stn[6 * k + m]]);
+  for (int e = 0; e < E; ++e) gv[e] = T(0);
+  for (int q0 = qb; q0 < qe; q0 += kNodeBatch) {
+    T part[kNodeBatch];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) Q[q] = mq[q * M + k];
+    for (int u = 0; u < kNodeBatch; ++u) {
+      const int q = q0 + u;
+      const int key = (q < qe) ? keys[q] : -1;
+      const int i = key & 0xffff, j = key >> 16;
+      if (key >= 0 && j != curj) {  // wave-uniform branch
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int pp = 1 + lane + 64 * e;
+          gv[e] = (pp <= n) ? G[grp_index(pp, j - jlo, nbr)] : T(0);
+        }
+        curj = j;
+      }
+      T sacc = T(0);
+      if (key >= 0) {
+        T a, c, sb, cb;
+        st2.get(((1 + lane) * i) & mask, a, c);
+        st2.get((64 * i) & mask, sb, cb);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          sacc += gv[e] * a;
+          const T t2 = a * cb + c * sb;
+          c = c * cb - a * sb;
+          a = t2;
+        }
+      }
+      part[u] = sacc;
+    }
+    // recursive-halving reduction of 8 values over 64 lanes; lane l ends with node
+    // (l >> 3) & 7 of the batch
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+    T h4[4], h2[2], h1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T keep = b5 ? part[q + 4] : part[q];
+      const T send = b5 ? part[q] : part[q + 4];
+      h4[q] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const T keep = b4 ? h4[q + 2] : h4[q];
+      const T send = b4 ? h4[q] : h4[q + 2];
+      h2[q] = keep + __shfl_xor(send, 16, 64);
+    }
+    {
+      const T keep = b3 ? h2[1] : h2[0];
+      const T send = b3 ? h2[0] : h2[1];
+      h1 = keep + __shfl_xor(send, 8, 64);
+    }
+    h1 += __shfl_xor(h1, 4, 64);
+    h1 += __shfl_xor(h1, 2, 64);
+    h1 += __shfl_xor(h1, 1, 64);
+    const int u = (lane >> 3) & 7;
+    if ((lane & 7) == 0 && q0 + u < qe) nval[q0 + u] = static_cast<double>(h1) * (2.0 / N);
+  }
+  __syncthreads();
+  if (!xmk) return;
+  const int k = kx;
+  double v[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) v[m] = nval[loc[m]];
   double out[3], jm[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     double s = 0.0, t = 0.0;
 #pragma unroll
-    for (int m = 0; m < 6; ++m) s += me.W[6 * r + m] * v[m];
+    for (int m = 0; m < 6; ++m) s += xw[kExtW + 6 * r + m] * v[m];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      s += me.E[5 * r + q] * Q[q];
-      t += me.D[5 * r + q] * Q[q];
+      s += xw[kExtE + 5 * r + q] * Q[q];
+      t += xw[kExtD + 5 * r + q] * Q[q];
     }
     out[r] = s;
     jm[r] = t;
   }
+  const double nx = xw[kExtN], ny = xw[kExtN + 1];
   const double vp = out[0], vm = out[0] - jm[0];
-  const double dnp = me.nx * out[1] + me.ny * out[2];
-  const double dnm = me.nx * (out[1] - jm[1]) + me.ny * (out[2] - jm[2]);
+  const double dnp = nx * out[1] + ny * out[2];
+  const double dnm = nx * (out[1] - jm[1]) + ny * (out[2] - jm[2]);
   if (vp_out) vp_out[k] = vp;
   if (vm_out) vm_out[k] = vm;
   if (dnp_out) dnp_out[k] = dnp;
@@ -432,7 +707,7 @@ __global__ void __launch_bounds__(256)
     for (int t = threadIdx.x; t < 16 * 64; t += 256) {
       const int kk = t & 15, rr = t >> 4;
       const int jr = j0 + rr, kp = k0 + kk;
-      As[kk][rr] = (jr < n && kp < n) ? G[static_cast<size_t>(jr) * ldG + kp] : T(0);
+      As[kk][rr] = (jr < n && kp < n) ? G[grp_index(kp + 1, jr, ldG)] : T(0);
       const int ic = i0 + rr;
       Bs[kk][rr] = (ic < n && kp < n) ? sinT[((kp + 1) * (ic + 1)) & mask] : T(0);
     }
@@ -459,7 +734,8 @@ __global__ void __launch_bounds__(256)
     for (int q = 0; q < 4; ++q) {
       const int jr = j0 + ty * 4 + r, ic = i0 + tx * 4 + q;
       if (jr < n && ic < n)
-        grid[static_cast<size_t>(jr + 1) * (N + 1) + (ic + 1)] = sc * static_cast<double>(acc[r][q]);
+        grid[static_cast<size_t>(jr + 1) * (N + 1) + (ic + 1)] =
+            sc * static_cast<double>(acc[r][q]);
     }
 }
 
@@ -488,26 +764,55 @@ __global__ void k_ring_cast(int n, const double* __restrict__ src, T* __restrict
 
 static inline int nblk(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
 
+// Allow a kernel more than the default dynamic LDS (done once per kernel and size class).
+template <class K>
+static void allow_dyn_lds(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return;
+  static size_t done = 0;
+  if (bytes <= done) return;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+  done = bytes;
+}
+
 template <class T, int E>
-static void launch_solve(kfbi_ctx* c, const T* armr, const T* sinT, const T* ring, int jlo,
-                         int jhi, T* G, bool full, double* grid, T* nodeval, hipEvent_t ev2) {
-  const int N = c->N, n = N - 1;
+static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jlo, int jhi,
+                               T* Tg, T* G, bool full, double* grid, hipEvent_t* ev,
+                               const kfbi_out* out, const kfbi_bie* op, const double* xop,
+                               double* yop) {
+  const int N = c->N, n = N - 1, M = c->M;
+  const int P = c->st.n_parts;
+  hipStream_t s = c->stream;
+  constexpr int PT = (64 * E + 255) / 256;
+  if (P > 0)
+    hipLaunchKernelGGL((k_rowdst<T, PT>), dim3(P), dim3(256), 0, s, N, M, P, c->pdesc.as<int4>(),
+                       c->armpk.as<int>(), c->armc.as<double>(), c->armk.as<int>(), c->arm_cap,
+                       c->mq.as<double>(), sinT, Tg);
+  if (ev) hipEventRecord(ev[2], s);
   const int ngrp = nblk(n, kColsPerBlock);
   const int nb = ((ngrp + 7) / 8) * 8;
-  hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb), dim3(256), 0, c->stream, N, c->h, c->c2,
-                     c->armrow.as<int>(), c->armi.as<int>(), armr, sinT, ring, jlo, jhi, N, G,
-                     nb);
-  if (ev2) hipEventRecord(ev2, c->stream);
-  if (c->st.n_rows > 0)
-    hipLaunchKernelGGL((k_nodes<T, E>), dim3(c->st.n_rows), dim3(256), 0, c->stream, N,
-                       c->rows.as<int>(), c->rowptr.as<int>(), c->nodei.as<int>(), sinT, jlo, N,
-                       G, nodeval);
+  const size_t lds_dyn = sizeof(T) * 4 * static_cast<size_t>(P > 0 ? P : 1);
+  allow_dyn_lds(k_colsolve<T, E>, lds_dyn);
+  hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb), dim3(256), lds_dyn, s, N, c->h, P, Tg,
+                     c->rowpart.as<int>(), sinT, ring, c->colc.as<double>(),
+                     c->lanef.as<double>(), jlo, jhi, G, nb);
+  if (ev) hipEventRecord(ev[3], s);
+  const int nbr = jhi - jlo + 1;
   if (full) {
-    hipLaunchKernelGGL((k_fullgrid<T>), dim3(nblk(n, 64), nblk(n, 64)), dim3(256), 0, c->stream,
-                       N, G, N, sinT, grid);
-    hipLaunchKernelGGL((k_grid_ring<T>), dim3(nblk(N + 1, 256)), dim3(256), 0, c->stream, N, ring,
-                       grid);
+    hipLaunchKernelGGL((k_fullgrid<T>), dim3(nblk(n, 64), nblk(n, 64)), dim3(256), 0, s, N, G,
+                       nbr, sinT, grid);
+    hipLaunchKernelGGL((k_grid_ring<T>), dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, ring, grid);
   }
+  const int MC = c->mk_chunk;
+  const int nch = nblk(M, MC);
+  const int side = op ? op->side : 0;
+  const double oa = op ? op->a : 0.0, ob = op ? op->b : 0.0, oq = op ? op->q : 0.0;
+  hipLaunchKernelGGL((k_nodes_extract<T, E>), dim3(nch), dim3(256), sizeof(double) * 6 * MC, s,
+                     N, M, MC, c->cnode.as<int>(), c->ccount.as<int>(), c->mkloc.as<int>(),
+                     sinT, jlo, nbr, G, c->mq.as<double>(), c->ext.as<double>(),
+                     c->qpart.as<double>(), c->n_mk_blocks, out ? out->v_plus : nullptr,
+                     out ? out->v_minus : nullptr, out ? out->dn_plus : nullptr,
+                     out ? out->dn_minus : nullptr, side, oa, ob, oq, xop, yop);
 }
 
 template <class T>
@@ -516,20 +821,12 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
   const int M = c->M, N = c->N;
   hipStream_t s = c->stream;
   const bool full = out && out->grid;
-  T* armr = reinterpret_cast<T*>(c->armr.p);
-  T* ring = nullptr;
   const T* sinT = reinterpret_cast<const T*>(sizeof(T) == 8 ? c->sinT.p : c->sinT32.p);
+  T* Tg = reinterpret_cast<T*>(c->tmat.p);
   T* G = reinterpret_cast<T*>(c->gband.p);
-  T* nodeval = reinterpret_cast<T*>(c->nodeval.p);
+  double* ring64 = c->ring.as<double>();
+  T* ringT = nullptr;  // box data in the working precision (after ring64 in the buffer)
   int nring = 0;
-  if (c->box_bc == KFBI_BOX_FREESPACE) {
-    ring = reinterpret_cast<T*>(c->ring.p);
-    nring = nblk(4 * (N + 1), 16);
-  } else if (c->box_bc == KFBI_BOX_USER) {
-    ring = reinterpret_cast<T*>(c->ring.p);
-    hipLaunchKernelGGL((k_ring_cast<T>), dim3(nblk(4 * (N + 1), 256)), dim3(256), 0, s,
-                       4 * (N + 1), ring_user, ring);
-  }
   hipEvent_t* ev = nullptr;
   if (c->prof_on) {
     if (c->prof_used + 5 > kfbi_ctx::kProfPool) KFBI_TRY(prof_flush(c));
@@ -537,36 +834,43 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
     c->prof_used += 5;
     hipEventRecord(ev[0], s);
   }
+  if (c->box_bc == KFBI_BOX_FREESPACE) nring = nblk(4 * (N + 1), 16);
   const int C = c->mk_chunk, nmk = c->n_mk_blocks;
-  const int H = C + 5;
-  const size_t lds = sizeof(double) * (M + 8 * 2 * H + 5 * H);
-  hipLaunchKernelGGL((k_prep<T>), dim3(nmk + nring), dim3(256), lds, s, M, C, nmk, layer, dens,
-                     c->dvec.as<double>(), c->dvec.as<double>() + M, c->armcoef.as<ArmCoef>(),
-                     c->armint.as<int>(), c->intptr.as<int>(), armr, c->mq.as<double>(),
-                     c->qpart.as<double>(), c->ext.as<MarkerExt>(), nring, N, c->x0, c->y0, c->h,
-                     c->X.as<double>(), c->geo.as<double>(), ring);
+  const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
+  const size_t lds = sizeof(double) * ((1 + nd) * M + 256 * kReg);
+  allow_dyn_lds(k_prep, lds);
+  hipLaunchKernelGGL(k_prep, dim3(nmk + nring), dim3(256), lds, s, M, C, nmk, layer, dens,
+                     c->dvec.as<double>(), c->dvec.as<double>() + M, c->mq.as<double>(),
+                     c->qpart.as<double>(), c->ext.as<double>() + kExtQ * M, N, c->x0, c->y0,
+                     c->h, c->X.as<double>(), c->geo.as<double>(), ring64);
+  if (c->box_bc != KFBI_BOX_ZERO) {
+    const double* src = (c->box_bc == KFBI_BOX_USER) ? ring_user : ring64;
+    ringT = reinterpret_cast<T*>(ring64 + 4 * (N + 1));
+    hipLaunchKernelGGL((k_ring_cast<T>), dim3(nblk(4 * (N + 1), 256)), dim3(256), 0, s,
+                       4 * (N + 1), src, ringT);
+  }
   if (ev) hipEventRecord(ev[1], s);
   const int jlo = full ? 1 : c->st.row_lo;
   const int jhi = full ? N - 1 : c->st.row_hi;
   double* grid = full ? out->grid : nullptr;
   const int E = (N - 1 + 63) / 64;
-  switch (E <= 1 ? 1 : E <= 2 ? 2 : E <= 4 ? 4 : E <= 8 ? 8 : E <= 16 ? 16 : E <= 32 ? 32 : 64) {
-    case 1: launch_solve<T, 1>(c, armr, sinT, ring, jlo, jhi, G, full, grid, nodeval, ev ? ev[2] : nullptr); break;
-    case 2: launch_solve<T, 2>(c, armr, sinT, ring, jlo, jhi, G, full, grid, nodeval, ev ? ev[2] : nullptr); break;
-    case 4: launch_solve<T, 4>(c, armr, sinT, ring, jlo, jhi, G, full, grid, nodeval, ev ? ev[2] : nullptr); break;
-    case 8: launch_solve<T, 8>(c, armr, sinT, ring, jlo, jhi, G, full, grid, nodeval, ev ? ev[2] : nullptr); break;
-    case 16: launch_solve<T, 16>(c, armr, sinT, ring, jlo, jhi, G, full, grid, nodeval, ev ? ev[2] : nullptr); break;
-    case 32: launch_solve<T, 32>(c, armr, sinT, ring, jlo, jhi, G, full, grid, nodeval, ev ? ev[2] : nullptr); break;
-    default: launch_solve<T, 64>(c, armr, sinT, ring, jlo, jhi, G, full, grid, nodeval, ev ? ev[2] : nullptr); break;
+  switch (E <= 1 ? 1 : E <= 2 ? 2 : E <= 4 ? 4 : E <= 8 ? 8 : E <= 16 ? 16 : 32) {
+#define KFBI_CASE(EE)                                                                         \
+  case EE:                                                                                    \
+    launch_grid_stages<T, EE>(c, sinT, ringT, jlo, jhi, Tg, G, full, grid, ev, out, op, xop, \
+                              yop);                                                           \
+    break;
+    KFBI_CASE(1)
+    KFBI_CASE(2)
+    KFBI_CASE(4)
+    KFBI_CASE(8)
+    KFBI_CASE(16)
+    default:
+      launch_grid_stages<T, 32>(c, sinT, ringT, jlo, jhi, Tg, G, full, grid, ev, out, op, xop,
+                                yop);
+      break;
+#undef KFBI_CASE
   }
-  if (ev) hipEventRecord(ev[3], s);
-  const int side = op ? op->side : 0;
-  const double oa = op ? op->a : 0.0, ob = op ? op->b : 0.0, oq = op ? op->q : 0.0;
-  hipLaunchKernelGGL((k_extract<T>), dim3(nblk(M, 256)), dim3(256), 0, s, M, c->mknode.as<int>(),
-                     nodeval, c->mq.as<double>(), c->ext.as<MarkerExt>(), c->qpart.as<double>(),
-                     nmk, out ? out->v_plus : nullptr, out ? out->v_minus : nullptr,
-                     out ? out->dn_plus : nullptr, out ? out->dn_minus : nullptr, side, oa, ob, oq,
-                     xop, yop);
   if (ev) hipEventRecord(ev[4], s);
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
@@ -584,6 +888,18 @@ int prof_flush(kfbi_ctx* c) {
     ++c->prof_count;
   }
   c->prof_used = 0;
+  return KFBI_OK;
+}
+
+int colconst_setup(kfbi_ctx* c) {
+  const int N = c->N, n = N - 1;
+  const int E0 = (n + 63) / 64;
+  const int E = E0 <= 1 ? 1 : E0 <= 2 ? 2 : E0 <= 4 ? 4 : E0 <= 8 ? 8 : E0 <= 16 ? 16 : 32;
+  KFBI_TRY(c->colc.ensure(sizeof(double) * 3 * n));
+  KFBI_TRY(c->lanef.ensure(sizeof(double) * 2 * 64 * n));
+  hipLaunchKernelGGL(k_colconst, dim3(nblk(64 * n, 256)), dim3(256), 0, c->stream, N,
+                     c->h * c->h * c->c2, E, c->colc.as<double>(), c->lanef.as<double>());
+  KFBI_HIP(hipGetLastError());
   return KFBI_OK;
 }
 

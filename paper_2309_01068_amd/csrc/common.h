@@ -51,18 +51,19 @@ struct Crossing {
   double pos;
 };
 
-// Per-marker extraction data (Sec. 4.3), all FP64:
-//   W[3][6]  rows of the inverse 6x6 Taylor system giving v+, v+_x, v+_y from grid values
-//   E[3][5]  jump-correction part: maps the marker quantities (Phi, Phi_a, Phi_aa, Psi,
-//            Psi_a) to the contribution of chi(q_m) C(q_m) to (v+, v+_x, v+_y)
-//   D[3][5]  maps the same quantities to the jumps ([v], [v_x], [v_y]) at the marker
-//   nx, ny   outward unit normal; wq = s_a 2 pi / M (trapezoid weight)
-struct MarkerExt {
-  double W[18];
-  double E[15];
-  double D[15];
-  double nx, ny, wq, pad;
-};
+// Per-marker extraction data (Sec. 4.3), FP64, structure of arrays: entry q of marker k
+// is ext[q * M + k] with
+//   q = kExtW + 6r + m   row r of the inverse 6x6 Taylor system (v+, v+_x, v+_y)
+//   q = kExtE + 5r + s   jump-correction part: maps the marker quantities (Phi, Phi_a,
+//                        Phi_aa, Psi, Psi_a) to the contribution of chi(q_m) C(q_m)
+//   q = kExtD + 5r + s   maps the same quantities to ([v], [v_x], [v_y]) at the marker
+//   q = kExtN, kExtN+1   outward unit normal;  q = kExtQ: s_a 2 pi / M (trapezoid weight)
+constexpr int kExtW = 0, kExtE = 18, kExtD = 33, kExtN = 48, kExtQ = 50, kExtCount = 51;
+// Per-arm coefficients in marker-interval order (for the correction kernel), SoA:
+// armc[q * cap + a], q = 0..5 Lagrange weights l_m, q = 6..10 coefficients of
+// (Phi, Phi_a, Phi_aa, Psi, Psi_a) in -+T/h^2.
+constexpr int kArmCoefCount = 11;
+constexpr int kArmsPerPart = 16;  // arms of one row handled by one block of the row transform
 
 // Per-arm data (Sec. 4.2.1): correction value r = sum_m l_m sum_q coef_q Q_q(k-2+m).
 struct ArmCoef {
@@ -81,6 +82,7 @@ struct GeoStatus {
   int n_nodes;
   int n_rows;
   int row_lo, row_hi;
+  int n_parts;
 };
 
 }  // namespace kfbi
@@ -102,8 +104,10 @@ struct kfbi_ctx {
   int d_M = 0;  // M for which the differentiation vectors are built
 
   // geometry buffers
-  kfbi::DBuf X, geo, dvec, cnt, cross, hid, vid, lab, armcnt, rowsum, armrow, armi, armcoef,
-      armint, intptr, need, nodeidx, nodei, rowptr, rows, mknode, ext, gstat;
+  kfbi::DBuf X, geo, dvec, cnt, cross, hid, vid, lab, armcnt, rowsum, armrow, armpk, armcoef,
+      intptr, need, nodeidx, nodei, rowptr, rows, mknode, ext, gstat, armc, armk,
+      colc, lanef, cnode, ccount, mkloc, tmat, pdesc, rowpart;
+  int arm_cap = 0;
   // per-apply buffers
   kfbi::DBuf mq, armr, qpart, ring, sinT, sinT32, gband, nodeval, tmpM;
   // gmres buffers
@@ -132,4 +136,5 @@ int apply_impl(kfbi_ctx* c, int layer, int precision, const double* dens, const 
                const kfbi_out* out, const kfbi_bie* op, const double* x_for_op, double* y_op);
 int ensure_apply_buffers(kfbi_ctx* c);
 int prof_flush(kfbi_ctx* c);
+int colconst_setup(kfbi_ctx* c);
 }  // namespace kfbi

@@ -318,8 +318,7 @@ __global__ void k_arm_fill(int N, double x0, double y0, double h, double c2, int
                            const int8_t* __restrict__ lab, const int* __restrict__ hid,
                            const int* __restrict__ vid, const int* __restrict__ rowoff,
                            const Crossing* __restrict__ cr, const double* __restrict__ geo,
-                           int* __restrict__ armi, ArmCoef* __restrict__ armc,
-                           int* __restrict__ intcnt, GeoStatus* st) {
+                           int* __restrict__ armpk, ArmCoef* __restrict__ armc, GeoStatus* st) {
   __shared__ int scratch[17];
   const int j = blockIdx.x + 1;
   const int n = N - 1;
@@ -368,22 +367,91 @@ __global__ void k_arm_fill(int N, double x0, double y0, double h, double c2, int
       }
       ac.k = x.k;
       ac.pad = 0;
-      armi[slot] = i;
+      armpk[slot] = i | (j << 16);
       armc[slot] = ac;
-      atomicAdd(&intcnt[x.k], 1);
       ++slot;
     }
   }
 }
 
-__global__ void k_arm_by_interval(int na, const ArmCoef* __restrict__ armc,
-                                  const int* __restrict__ intoff, int* __restrict__ fill,
-                                  int* __restrict__ armint) {
+// Row-ordered arm coefficients as structure of arrays (coefR[q * cap + a], kR[a]).
+__global__ void k_arm_soa(int na, int cap, const ArmCoef* __restrict__ armc,
+                          double* __restrict__ coefR, int* __restrict__ kR) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= na) return;
-  const int k = armc[a].k;
-  const int s = atomicAdd(&fill[k], 1);
-  armint[intoff[k] + s] = a;
+  const ArmCoef ac = armc[a];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) coefR[m * cap + a] = ac.l[m];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) coefR[(6 + q) * cap + a] = ac.coef[q];
+  kR[a] = ac.k;
+}
+
+// Rows split into parts of at most kArmsPerPart arms: parts per row, then descriptors
+// (row, first arm, end arm) in row order after an exclusive scan.
+__global__ void k_part_count(int N, const int* __restrict__ rowoff, int* __restrict__ rowpart) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > N) return;
+  int c = 0;
+  if (j >= 1 && j <= N - 1) {
+    const int na = rowoff[j + 1] - rowoff[j];
+    c = (na + kArmsPerPart - 1) / kArmsPerPart;
+  }
+  rowpart[j] = c;
+}
+
+__global__ void k_part_fill(int N, const int* __restrict__ rowoff,
+                            const int* __restrict__ rowpart, int4* __restrict__ pdesc) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < 1 || j > N - 1) return;
+  const int a0 = rowoff[j], a1 = rowoff[j + 1];
+  int q = rowpart[j];
+  for (int a = a0; a < a1; a += kArmsPerPart, ++q) pdesc[q] = make_int4(j, a, min(a1, a + kArmsPerPart), 0);
+}
+
+// Distinct interpolation nodes of each chunk of MC consecutive markers, sorted by (row,
+// column), and each marker's six stencil slots as indices into its chunk's list.
+__global__ void k_chunk_nodes(int M, int MC, const int* __restrict__ mkkey,
+                              int* __restrict__ cnode, int* __restrict__ ccount,
+                              int* __restrict__ mkloc) {
+  extern __shared__ int keys[];  // 6 * MC
+  __shared__ int nuniq;
+  const int ch = blockIdx.x;
+  const int k0 = ch * MC, k1 = min(M, k0 + MC);
+  const int ns = 6 * (k1 - k0);
+  for (int t = threadIdx.x; t < ns; t += blockDim.x) keys[t] = mkkey[6 * k0 + t];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int a = 1; a < ns; ++a) {  // insertion sort (ns <= 96)
+      const int v = keys[a];
+      int b = a - 1;
+      while (b >= 0 && keys[b] > v) {
+        keys[b + 1] = keys[b];
+        --b;
+      }
+      keys[b + 1] = v;
+    }
+    int u = 0;
+    for (int a = 0; a < ns; ++a)
+      if (a == 0 || keys[a] != keys[a - 1]) keys[u++] = keys[a];
+    nuniq = u;
+    ccount[ch] = u;
+  }
+  __syncthreads();
+  const int u = nuniq;
+  for (int t = threadIdx.x; t < u; t += blockDim.x) cnode[ch * 6 * MC + t] = keys[t];
+  for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+    const int key = mkkey[6 * k0 + t];
+    int lo = 0, hi = u - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      if (keys[mid] < key)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    mkloc[6 * k0 + t] = lo;
+  }
 }
 
 // Gauss-Jordan inverse of a 6x6 matrix with partial pivoting (in registers).
@@ -427,7 +495,7 @@ __device__ inline void inv6(double A[6][6], double R[6][6]) {
 // Sec. 4.3 extraction weights for every marker; marks the needed stencil nodes.
 __global__ void k_marker_ext(int M, const double* __restrict__ X, const double* __restrict__ geo,
                              double x0, double y0, double h, int N, double c2,
-                             const int8_t* __restrict__ lab, MarkerExt* __restrict__ ext,
+                             const int8_t* __restrict__ lab, double* __restrict__ ext,
                              int* __restrict__ need, int* __restrict__ stn) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
@@ -457,15 +525,16 @@ __global__ void k_marker_ext(int M, const double* __restrict__ X, const double* 
     At[m][5] = 0.5 * Dy * Dy;
     chi[m] = lab[J * (N + 1) + I] ? 0.0 : 1.0;  // correction added for nodes in Omega-
     need[J * (N + 1) + I] = 1;
-    stn[6 * k + m] = J * (N + 1) + I;
+    stn[6 * k + m] = (J << 16) | I;
   }
   inv6(A, Rv);
-  MarkerExt me;
+  double Wr[18];
   for (int m = 0; m < 6; ++m) {
-    me.W[m] = Rv[0][m];
-    me.W[6 + m] = Rv[1][m] / h;
-    me.W[12 + m] = Rv[2][m] / h;
+    Wr[m] = Rv[0][m];
+    Wr[6 + m] = Rv[1][m] / h;
+    Wr[12 + m] = Rv[2][m] / h;
   }
+  for (int q = 0; q < 18; ++q) ext[(kExtW + q) * M + k] = Wr[q];
   // jumps at the marker as linear maps of (Phi, Phi_a, Phi_aa, Psi, Psi_a)
   const double xa = geo[k], ya = geo[M + k], xaa = geo[2 * M + k], yaa = geo[3 * M + k];
   double Cj[6][5];  // rows in Taylor order ([v],[v_x],[v_y],[v_xx],[v_xy],[v_yy])
@@ -488,17 +557,15 @@ __global__ void k_marker_ext(int M, const double* __restrict__ X, const double* 
         if (chi[m] == 0.0) continue;
         double cm = 0.0;
         for (int s = 0; s < 6; ++s) cm += At[m][s] * Cj[s][q];
-        e += me.W[6 * r + m] * cm;
+        e += Wr[6 * r + m] * cm;
       }
-      me.E[5 * r + q] = e;
-      me.D[5 * r + q] = Cj[r][q];
+      ext[(kExtE + 5 * r + q) * M + k] = e;
+      ext[(kExtD + 5 * r + q) * M + k] = Cj[r][q];
     }
   const double sa = geo[4 * M + k];
-  me.nx = ya / sa;
-  me.ny = -xa / sa;
-  me.wq = sa * (2.0 * M_PI / M);
-  me.pad = 0.0;
-  ext[k] = me;
+  ext[kExtN * M + k] = ya / sa;
+  ext[(kExtN + 1) * M + k] = -xa / sa;
+  ext[kExtQ * M + k] = sa * (2.0 * M_PI / M);
 }
 
 // Node numbering: per row count of needed nodes, then scan over rows (single block):
@@ -555,32 +622,6 @@ __global__ void k_rows_scan(int N, const int* __restrict__ rowcnt, int* __restri
   }
 }
 
-__global__ void k_node_assign(int N, const int* __restrict__ need, const int* __restrict__ nodeoff,
-                              int* __restrict__ nodeidx, int* __restrict__ nodei) {
-  __shared__ int scratch[17];
-  const int j = blockIdx.x;
-  const int n1 = N + 1;
-  const int T = blockDim.x;
-  const int per = (n1 + T - 1) / T;
-  const int b = threadIdx.x * per, e = min(n1, b + per);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += need[j * n1 + i];
-  int off = nodeoff[j] + block_excl_scan(s, scratch, nullptr);
-  for (int i = b; i < e; ++i) {
-    if (need[j * n1 + i]) {
-      nodeidx[j * n1 + i] = off;
-      nodei[off] = i;
-      ++off;
-    }
-  }
-}
-
-__global__ void k_marker_nodes(int M, const int* __restrict__ nodeidx, int* __restrict__ stn) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 6 * M) return;
-  stn[t] = nodeidx[stn[t]];
-}
-
 static inline int nblk(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
 
 int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
@@ -598,7 +639,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   KFBI_TRY(c->dvec.ensure(sizeof(double) * 2 * M));
   KFBI_TRY(c->cnt.ensure(sizeof(int) * (2 * M + 2)));
   KFBI_TRY(c->intptr.ensure(sizeof(int) * (2 * M + 2)));
-  KFBI_TRY(c->ext.ensure(sizeof(MarkerExt) * M));
+  KFBI_TRY(c->ext.ensure(sizeof(double) * kExtCount * M));
   KFBI_TRY(c->mknode.ensure(sizeof(int) * 6 * M));
 
   KFBI_HIP(hipMemcpyAsync(c->X.p, xy, sizeof(double) * 2 * M, hipMemcpyDeviceToDevice, s));
@@ -628,10 +669,12 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   const int nh = hs->n_cross_h, nv = hs->n_cross_v, nc = nh + nv;
   KFBI_TRY(c->cross.ensure(sizeof(Crossing) * (nc + 1)));
   const int narm_cap = 2 * nc + 1;
-  KFBI_TRY(c->armi.ensure(sizeof(int) * narm_cap));
+  KFBI_TRY(c->armpk.ensure(sizeof(int) * narm_cap));
   KFBI_TRY(c->armcoef.ensure(sizeof(ArmCoef) * narm_cap));
-  KFBI_TRY(c->armint.ensure(sizeof(int) * narm_cap));
   KFBI_TRY(c->armr.ensure(sizeof(double) * narm_cap));
+  KFBI_TRY(c->armc.ensure(sizeof(double) * kArmCoefCount * narm_cap));
+  KFBI_TRY(c->armk.ensure(sizeof(int) * narm_cap));
+  c->arm_cap = narm_cap;
 
   Crossing* cr = c->cross.as<Crossing>();
   hipLaunchKernelGGL(k_fill_cross, dim3(nblk(M, 128)), dim3(128), 0, s, M, c->X.as<double>(), c->x0,
@@ -652,29 +695,29 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   KFBI_HIP(hipMemsetAsync(rowoff, 0, sizeof(int) * (N + 2), s));
   hipLaunchKernelGGL(k_arm_rowcount, dim3(N - 1), dim3(256), 0, s, N, lab, hid, vid, rowoff, st);
   hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, rowoff, &st->n_arms);
-  int* intcnt = c->intptr.as<int>();  // M+1 counts -> offsets ; second half = fill counters
-  KFBI_HIP(hipMemsetAsync(intcnt, 0, sizeof(int) * (2 * M + 2), s));
   hipLaunchKernelGGL(k_arm_fill, dim3(N - 1), dim3(256), 0, s, N, c->x0, c->y0, h, c->c2, M, lab,
-                     hid, vid, rowoff, cr, c->geo.as<double>(), c->armi.as<int>(),
-                     c->armcoef.as<ArmCoef>(), intcnt, st);
-  // row_ptr[N] = total (the scan wrote offsets for 0..N; total is in st->n_arms)
-  // interval CSR
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, M + 1, intcnt, nullptr);
+                     hid, vid, rowoff, cr, c->geo.as<double>(), c->armpk.as<int>(),
+                     c->armcoef.as<ArmCoef>(), st);
   // markers / nodes
   int* need = c->need.as<int>();
   KFBI_HIP(hipMemsetAsync(need, 0, sizeof(int) * n1 * n1, s));
   hipLaunchKernelGGL(k_marker_ext, dim3(nblk(M, 128)), dim3(128), 0, s, M, c->X.as<double>(),
-                     c->geo.as<double>(), c->x0, c->y0, h, N, c->c2, lab, c->ext.as<MarkerExt>(),
+                     c->geo.as<double>(), c->x0, c->y0, h, N, c->c2, lab, c->ext.as<double>(),
                      need, c->mknode.as<int>());
   int* rowcnt = c->rowsum.as<int>();
   hipLaunchKernelGGL(k_need_rowcount, dim3(n1), dim3(256), 0, s, N, need, rowcnt);
   int* nodeoff = rowcnt + n1 + 1;
   hipLaunchKernelGGL(k_rows_scan, dim3(1), dim3(1024), 0, s, N, rowcnt, nodeoff, c->rows.as<int>(),
                      c->rowptr.as<int>(), st);
-  hipLaunchKernelGGL(k_node_assign, dim3(n1), dim3(256), 0, s, N, need, nodeoff,
-                     c->nodeidx.as<int>(), c->nodei.as<int>());
-  hipLaunchKernelGGL(k_marker_nodes, dim3(nblk(6 * M, 256)), dim3(256), 0, s, M,
-                     c->nodeidx.as<int>(), c->mknode.as<int>());
+  // per-chunk node lists for the node-transform + extraction kernel
+  const int MC = c->mk_chunk;
+  const int nch = (M + MC - 1) / MC;
+  KFBI_TRY(c->cnode.ensure(sizeof(int) * nch * 6 * MC));
+  KFBI_TRY(c->ccount.ensure(sizeof(int) * nch));
+  KFBI_TRY(c->mkloc.ensure(sizeof(int) * 6 * M));
+  hipLaunchKernelGGL(k_chunk_nodes, dim3(nch), dim3(64), sizeof(int) * 6 * MC, s, M, MC,
+                     c->mknode.as<int>(), c->cnode.as<int>(), c->ccount.as<int>(),
+                     c->mkloc.as<int>());
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(hs, st, sizeof(GeoStatus), hipMemcpyDeviceToHost, s));
   KFBI_HIP(hipStreamSynchronize(s));
@@ -686,11 +729,26 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
     set_error("geometry error: %s", msg[hs->err < 6 ? hs->err : 0]);
     return KFBI_E_GEOMETRY;
   }
-  // arms grouped by marker interval (for the per-apply correction kernel)
+  // row parts for the row transform kernel
+  {
+    int* rowpart = c->rowpart.as<int>();
+    const int* rowoff = c->armrow.as<int>();
+    hipLaunchKernelGGL(k_part_count, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart);
+    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, rowpart, &st->n_parts);
+    KFBI_HIP(hipMemcpyAsync(hs, st, sizeof(GeoStatus), hipMemcpyDeviceToHost, s));
+    KFBI_HIP(hipStreamSynchronize(s));
+    const int P = hs->n_parts;
+    KFBI_TRY(c->pdesc.ensure(sizeof(int4) * (P + 1)));
+    const int ng = (N - 1 + 3) / 4;
+    KFBI_TRY(c->tmat.ensure(sizeof(double) * 4 * static_cast<size_t>(ng) * (P + 1)));
+    hipLaunchKernelGGL(k_part_fill, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart,
+                       c->pdesc.as<int4>());
+  }
+  // row-ordered arm coefficients (structure of arrays) for the row transform kernel
   const int na = hs->n_arms;
   if (na > 0)
-    hipLaunchKernelGGL(k_arm_by_interval, dim3(nblk(na, 256)), dim3(256), 0, s, na,
-                       c->armcoef.as<ArmCoef>(), intcnt, intcnt + M + 1, c->armint.as<int>());
+    hipLaunchKernelGGL(k_arm_soa, dim3(nblk(na, 256)), dim3(256), 0, s, na, c->arm_cap,
+                       c->armcoef.as<ArmCoef>(), c->armc.as<double>(), c->armk.as<int>());
   KFBI_HIP(hipGetLastError());
   c->st = *hs;
   c->M = M;
