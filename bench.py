@@ -7,7 +7,9 @@ grid arithmetic, densities = seeded random Fourier series (modes 1..32, amplitud
 N(0,1)/k^2), eight densities cycled.  Inputs are resident in HBM before timing.
 
 Prints one JSON line with the headline value plus:
-  roofline      dominant kernel (k_colsolve) measured with HIP events around each launch
+  roofline      the slowest of the four kernels of an apply: algorithmic bytes over its
+                average duration (back-to-back replays between two HIP events), with the
+                per-kernel table and the in-apply stage times
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
   extra         2048^2 and FP32 rates, GMRES time to 1e-10 for plain FP64, FP32-inner
                 refinement (same true FP64 residual)
@@ -36,16 +38,42 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--reps", type=int, default=400,
+                    help="back-to-back replays per kernel for the per-kernel durations")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy 10 times (the reference "
+                         "kernel for scaling hardware byte counters) and exit")
     return ap.parse_args()
 
 
-def algorithmic_bytes_colsolve(info, N, wbytes):
-    """k_colsolve moves: the band of G it writes (rows row_lo..row_hi, N-1 modes) plus
-    one read of the arm list (column index int32 + correction value) and the row
-    offsets.  Per launch."""
+def algorithmic_bytes(info, N, M, wbytes, layer_double=False):
+    """Bytes each kernel of one apply must move at least (per launch), from its inputs and
+    outputs: n = N-1 sine modes, P row parts, nb = row_hi-row_lo+1 rows of G written by the
+    column solve, R = rows holding interpolation nodes, w = 8 (FP64) or 4 (FP32).
+      k_prep           density, two differentiation vectors, trapezoid weights (8 B each per
+                       marker) in; five marker quantities and the weighted sum out
+      k_rowdst         per arm 11 coefficients (8 B), marker index and packed node (4 B each),
+                       per part one row of n transformed values out (P n w)
+      k_colsolve       the P n w part rows in, the nb n w rows of G out, per-mode constants
+                       (3 + 128 doubles per mode) and the row-to-part offsets
+      k_nodes_extract  each of the R node rows of G once (R n w), per marker the 51
+                       extraction values and 5 marker quantities (8 B), 6 stencil slots (4 B),
+                       four traces out (8 B each)
+    """
     n = N - 1
-    band = info["row_hi"] - info["row_lo"] + 1
-    return band * n * wbytes + info["n_arms"] * (4 + wbytes) + (N + 1) * 4
+    P = info["n_parts"]
+    nb = info["row_hi"] - info["row_lo"] + 1
+    R = info["n_rows"]
+    A = info["n_arms"]
+    return {
+        "k_prep": M * 8 * (1 + 2 + 1) + M * 8 * 5 + 8 * (M // 8 + 1),
+        "k_rowdst": A * (11 * 8 + 4 + 4) + P * 16 + P * n * wbytes,
+        "k_colsolve": P * n * wbytes + nb * n * wbytes + n * 8 * (3 + 128) + (N + 2) * 4,
+        "k_nodes_extract": R * n * wbytes + M * (51 * 8 + 5 * 8 + 6 * 4 + 4 * 8),
+    }
+
+
+STAGES = ["k_prep", "k_rowdst", "k_colsolve", "k_nodes_extract"]
 
 
 def time_applies(ctx, kf, dens, outs, steps, warmup, layer, precision):
@@ -74,6 +102,16 @@ def main():
     import numpy as np
     import torch
 
+    if a.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": src.numel() * 8,
+                          "copy_calibration_bytes_written": dst.numel() * 8, "launches": 10}))
+        return
+
     from paper_2309_01068_amd import kfbi as kf
     from paper_2309_01068_amd import workloads as W
 
@@ -95,22 +133,36 @@ def main():
     value = a.steps / secs
     ms_per_step = 1e3 * secs / a.steps
 
-    # dominant kernel: HIP events around each stage of the same applies
+    # per-kernel durations: each kernel of the last apply replayed back to back on the
+    # context stream between two HIP events (no events between the launches)
+    kern_us = [ctx.profile_kernel(q, reps=a.reps) for q in range(4)]
+    # in-apply stage times: HIP events around every kernel of the same applies
     ctx.profile(True)
     for i in range(min(a.steps, 1024)):
         ctx.apply(layer, dens[i % 8], a.precision, out=outs)
     ms, napp = ctx.profile_read()
     ctx.profile(False)
     stage_us = [1e3 * m / max(napp, 1) for m in ms]
+    # host cost of issuing one apply (Python binding + four launches), no synchronisation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(200):
+        ctx.apply(layer, dens[i % 8], a.precision, out=outs)
+    issue_us = 1e6 * (time.perf_counter() - t0) / 200
+    torch.cuda.synchronize()
     wb = 8 if a.precision == 0 else 4
-    bytes_k2 = algorithmic_bytes_colsolve(info, a.N, wb)
-    k2_s = stage_us[1] * 1e-6
-    achieved = bytes_k2 / k2_s / 1e9
-    roof = {"kernel": "k_colsolve", "bound": "hbm", "achieved": round(achieved, 1),
+    byts = algorithmic_bytes(info, a.N, M, wb)
+    dom = max(range(4), key=lambda q: kern_us[q])
+    kname = STAGES[dom]
+    achieved = byts[kname] / (kern_us[dom] * 1e-6) / 1e9
+    roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "algorithmic_bytes": bytes_k2, "avg_us": round(stage_us[1], 3),
-            "stage_us": {"prep": round(stage_us[0], 3), "colsolve": round(stage_us[1], 3),
-                         "nodes": round(stage_us[2], 3), "extract": round(stage_us[3], 3)}}
+            "traffic": None, "algorithmic_bytes": byts[kname], "avg_us": round(kern_us[dom], 3),
+            "kernels": {STAGES[q]: {"avg_us": round(kern_us[q], 3), "bytes": byts[STAGES[q]],
+                                    "GB_s": round(byts[STAGES[q]] / kern_us[q] / 1e3, 1)}
+                        for q in range(4)},
+            "in_apply_stage_us": {STAGES[q]: round(stage_us[q], 3) for q in range(4)},
+            "host_issue_us_per_apply": round(issue_us, 2)}
     result = {
         "metric": "KFBI applies/s at 1024^2 (single layer, modified Helmholtz, star, 2048 markers)"
         if a.N == 1024 else f"KFBI applies/s at {a.N}^2",
@@ -122,6 +174,7 @@ def main():
         "config": {"workload": f"kfbi_apply star M={M} grid {a.N}^2 c2={c2} S-layer",
                    "grid": a.N, "markers": M, "c2": c2, "layer": "single",
                    "arms": info["n_arms"], "stencil_nodes": info["n_nodes"],
+                   "row_parts": info["n_parts"], "node_rows": info["n_rows"],
                    "band_rows": info["row_hi"] - info["row_lo"] + 1},
         "wall_s": round(wall, 4),
         "roofline": roof,

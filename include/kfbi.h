@@ -80,6 +80,8 @@ typedef struct {
   int n_nodes;      /* distinct interpolation-stencil nodes (Sec. 4.3)    */
   int n_rows;       /* grid rows holding stencil nodes                    */
   int row_lo, row_hi; /* band of grid rows written by the fast solve      */
+  int n_parts;      /* row parts (at most 16 arms of one row each) of the
+                       row sine transform                                */
 } kfbi_info;
 
 /* Outputs of one apply.  Each pointer is a device array or NULL (not computed).
@@ -163,14 +165,23 @@ typedef struct {
 int kfbi_gmres_solve(kfbi_ctx* ctx, const kfbi_bie* op, const double* rhs_dev,
                      double* x_dev, const kfbi_gmres_opts* opts, kfbi_gmres_stats* stats);
 
-/* Measurement hook: while on, every apply brackets its four stages with HIP events on
- * the context stream (stage 0: density derivatives and jump corrections; 1: the fast
- * solve kernel k_colsolve; 2: inverse transform at the stencil nodes (and the full grid
- * when requested); 3: corrected interpolation).  kfbi_profile_read synchronises and
+/* Measurement hook: while on, every apply brackets its four kernels with HIP events on
+ * the context stream (stage 0: density derivatives and marker jump quantities, k_prep;
+ * 1: corrected right-hand sides and their row sine transform, k_rowdst; 2: column
+ * tridiagonal solves, k_colsolve; 3: inverse transform at the stencil nodes and the
+ * corrected interpolation, k_nodes_extract, plus the full grid when requested).  kfbi_profile_read synchronises and
  * returns the summed milliseconds per stage (ms_total[4], host) and the number of
  * recorded applies.  Turning profiling on resets the sums. */
 int kfbi_profile(kfbi_ctx* ctx, int on);
 int kfbi_profile_read(kfbi_ctx* ctx, double* ms_total, long* napplies);
+
+/* Measurement hook: replays kernel `stage` (0..3, numbered as above) of the last
+ * kfbi_apply/kfbi_operator call reps times back to back on the context stream, on the
+ * library's own buffers, and returns the average launch duration in microseconds
+ * (HIP events around the replays; one untimed launch first).  Stage 0 reads a library
+ * workspace as its density and stage 3 writes no caller output, so no caller array is
+ * touched.  Synchronises.  KFBI_E_STATE if no apply ran since kfbi_set_interface. */
+int kfbi_profile_kernel(kfbi_ctx* ctx, int stage, int reps, double* us_avg);
 
 #ifdef __cplusplus
 }

@@ -166,6 +166,10 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
     set_error("hipHostMalloc failed");
     return fail(KFBI_E_NOMEM);
   }
+  if (hipMemsetAsync(c->tmpM.p, 0, c->tmpM.bytes, c->stream) != hipSuccess) {
+    set_error("hipMemsetAsync failed");
+    return fail(KFBI_E_HIP);
+  }
   hipLaunchKernelGGL(k_sintab, dim3((2 * N + 255) / 256), dim3(256), 0, c->stream, N,
                      c->sinT.as<double>(), c->sinT32.as<float>());
   if ((st = colconst_setup(c)) != KFBI_OK) return fail(st);
@@ -192,6 +196,7 @@ int kfbi_set_interface(kfbi_ctx* c, int M, const double* xy) {
     return KFBI_E_INVALID;
   }
   c->have_interface = 0;
+  c->last_layer = -1;
   c->mk_chunk = M >= 1024 ? M / 256 : 4;
   c->n_mk_blocks = (M + c->mk_chunk - 1) / c->mk_chunk;
   const int st = geometry_setup(c, M, xy);
@@ -214,6 +219,7 @@ int kfbi_get_info(const kfbi_ctx* c, kfbi_info* info) {
   info->n_rows = c->st.n_rows;
   info->row_lo = c->st.row_lo;
   info->row_hi = c->st.row_hi;
+  info->n_parts = c->st.n_parts;
   return KFBI_OK;
 }
 
@@ -287,3 +293,12 @@ int kfbi_profile_read(kfbi_ctx* c, double* ms_total, long* napplies) {
 }
 
 }  // extern "C"
+
+int kfbi_profile_kernel(kfbi_ctx* c, int stage, int reps, double* us_avg) {
+  KFBI_TRY(check_ctx(c, true));
+  if (!us_avg) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  return kfbi::replay_stage(c, stage, reps, us_avg);
+}

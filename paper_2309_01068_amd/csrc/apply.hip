@@ -779,12 +779,12 @@ template <class T, int E>
 static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jlo, int jhi,
                                T* Tg, T* G, bool full, double* grid, hipEvent_t* ev,
                                const kfbi_out* out, const kfbi_bie* op, const double* xop,
-                               double* yop) {
+                               double* yop, int stages) {
   const int N = c->N, n = N - 1, M = c->M;
   const int P = c->st.n_parts;
   hipStream_t s = c->stream;
   constexpr int PT = (64 * E + 255) / 256;
-  if (P > 0)
+  if (P > 0 && (stages & 2))
     hipLaunchKernelGGL((k_rowdst<T, PT>), dim3(P), dim3(256), 0, s, N, M, P, c->pdesc.as<int4>(),
                        c->armpk.as<int>(), c->armc.as<double>(), c->armk.as<int>(), c->arm_cap,
                        c->mq.as<double>(), sinT, Tg);
@@ -793,9 +793,10 @@ static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jl
   const int nb = ((ngrp + 7) / 8) * 8;
   const size_t lds_dyn = sizeof(T) * 4 * static_cast<size_t>(P > 0 ? P : 1);
   allow_dyn_lds(k_colsolve<T, E>, lds_dyn);
-  hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb), dim3(256), lds_dyn, s, N, c->h, P, Tg,
-                     c->rowpart.as<int>(), sinT, ring, c->colc.as<double>(),
-                     c->lanef.as<double>(), jlo, jhi, G, nb);
+  if (stages & 4)
+    hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb), dim3(256), lds_dyn, s, N, c->h, P, Tg,
+                       c->rowpart.as<int>(), sinT, ring, c->colc.as<double>(),
+                       c->lanef.as<double>(), jlo, jhi, G, nb);
   if (ev) hipEventRecord(ev[3], s);
   const int nbr = jhi - jlo + 1;
   if (full) {
@@ -807,7 +808,8 @@ static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jl
   const int nch = nblk(M, MC);
   const int side = op ? op->side : 0;
   const double oa = op ? op->a : 0.0, ob = op ? op->b : 0.0, oq = op ? op->q : 0.0;
-  hipLaunchKernelGGL((k_nodes_extract<T, E>), dim3(nch), dim3(256), sizeof(double) * 6 * MC, s,
+  if (stages & 8)
+    hipLaunchKernelGGL((k_nodes_extract<T, E>), dim3(nch), dim3(256), sizeof(double) * 6 * MC, s,
                      N, M, MC, c->cnode.as<int>(), c->ccount.as<int>(), c->mkloc.as<int>(),
                      sinT, jlo, nbr, G, c->mq.as<double>(), c->ext.as<double>(),
                      c->qpart.as<double>(), c->n_mk_blocks, out ? out->v_plus : nullptr,
@@ -815,9 +817,11 @@ static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jl
                      out ? out->dn_minus : nullptr, side, oa, ob, oq, xop, yop);
 }
 
+// Launches the selected kernels (bit s = stage s) of one apply.
 template <class T>
 static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* ring_user,
-                   const kfbi_out* out, const kfbi_bie* op, const double* xop, double* yop) {
+                   const kfbi_out* out, const kfbi_bie* op, const double* xop, double* yop,
+                   int stages = 15) {
   const int M = c->M, N = c->N;
   hipStream_t s = c->stream;
   const bool full = out && out->grid;
@@ -828,7 +832,7 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
   T* ringT = nullptr;  // box data in the working precision (after ring64 in the buffer)
   int nring = 0;
   hipEvent_t* ev = nullptr;
-  if (c->prof_on) {
+  if (c->prof_on && stages == 15) {
     if (c->prof_used + 5 > kfbi_ctx::kProfPool) KFBI_TRY(prof_flush(c));
     ev = c->prof_ev + c->prof_used;
     c->prof_used += 5;
@@ -839,14 +843,16 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
   const size_t lds = sizeof(double) * ((1 + nd) * M + 256 * kReg);
   allow_dyn_lds(k_prep, lds);
-  hipLaunchKernelGGL(k_prep, dim3(nmk + nring), dim3(256), lds, s, M, C, nmk, layer, dens,
+  if (stages & 1)
+    hipLaunchKernelGGL(k_prep, dim3(nmk + nring), dim3(256), lds, s, M, C, nmk, layer, dens,
                      c->dvec.as<double>(), c->dvec.as<double>() + M, c->mq.as<double>(),
                      c->qpart.as<double>(), c->ext.as<double>() + kExtQ * M, N, c->x0, c->y0,
                      c->h, c->X.as<double>(), c->geo.as<double>(), ring64);
   if (c->box_bc != KFBI_BOX_ZERO) {
     const double* src = (c->box_bc == KFBI_BOX_USER) ? ring_user : ring64;
     ringT = reinterpret_cast<T*>(ring64 + 4 * (N + 1));
-    hipLaunchKernelGGL((k_ring_cast<T>), dim3(nblk(4 * (N + 1), 256)), dim3(256), 0, s,
+    if ((stages & 1) && src)
+      hipLaunchKernelGGL((k_ring_cast<T>), dim3(nblk(4 * (N + 1), 256)), dim3(256), 0, s,
                        4 * (N + 1), src, ringT);
   }
   if (ev) hipEventRecord(ev[1], s);
@@ -858,7 +864,7 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
 #define KFBI_CASE(EE)                                                                         \
   case EE:                                                                                    \
     launch_grid_stages<T, EE>(c, sinT, ringT, jlo, jhi, Tg, G, full, grid, ev, out, op, xop, \
-                              yop);                                                           \
+                              yop, stages);                                                   \
     break;
     KFBI_CASE(1)
     KFBI_CASE(2)
@@ -867,12 +873,14 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
     KFBI_CASE(16)
     default:
       launch_grid_stages<T, 32>(c, sinT, ringT, jlo, jhi, Tg, G, full, grid, ev, out, op, xop,
-                                yop);
+                                yop, stages);
       break;
 #undef KFBI_CASE
   }
   if (ev) hipEventRecord(ev[4], s);
   KFBI_HIP(hipGetLastError());
+  c->last_layer = layer;
+  c->last_precision = sizeof(T) == 8 ? KFBI_FP64 : KFBI_FP32;
   return KFBI_OK;
 }
 
@@ -900,6 +908,45 @@ int colconst_setup(kfbi_ctx* c) {
   hipLaunchKernelGGL(k_colconst, dim3(nblk(64 * n, 256)), dim3(256), 0, c->stream, N,
                      c->h * c->h * c->c2, E, c->colc.as<double>(), c->lanef.as<double>());
   KFBI_HIP(hipGetLastError());
+  return KFBI_OK;
+}
+
+// Back-to-back replay of one kernel of the last apply on its own buffers (the outputs of
+// the last stage are not written; the first stage reads a workspace as its density).
+int replay_stage(kfbi_ctx* c, int stage, int reps, double* us_avg) {
+  if (c->last_layer < 0) {
+    set_error("kfbi_profile_kernel: no apply since the interface was installed");
+    return KFBI_E_STATE;
+  }
+  if (stage < 0 || stage > 3 || reps < 1) {
+    set_error("kfbi_profile_kernel: stage must be 0..3 and reps >= 1");
+    return KFBI_E_INVALID;
+  }
+  hipEvent_t e0, e1;
+  KFBI_HIP(hipEventCreate(&e0));
+  KFBI_HIP(hipEventCreate(&e1));
+  const double* dens = c->tmpM.as<double>();
+  const int layer = c->last_layer, mask = 1 << stage;
+  // one untimed launch, then the timed ones
+  int st = KFBI_OK;
+  for (int r = 0; r <= reps && st == KFBI_OK; ++r) {
+    if (r == 1) hipEventRecord(e0, c->stream);
+    st = (c->last_precision == KFBI_FP32)
+             ? apply_t<float>(c, layer, dens, nullptr, nullptr, nullptr, nullptr, nullptr, mask)
+             : apply_t<double>(c, layer, dens, nullptr, nullptr, nullptr, nullptr, nullptr, mask);
+  }
+  hipEventRecord(e1, c->stream);
+  float ms = 0.f;
+  hipError_t e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != KFBI_OK) return st;
+  if (e != hipSuccess) {
+    set_error("kfbi_profile_kernel: %s", hipGetErrorString(e));
+    return KFBI_E_HIP;
+  }
+  *us_avg = 1e3 * static_cast<double>(ms) / reps;
   return KFBI_OK;
 }
 

@@ -123,6 +123,10 @@ struct kfbi_ctx {
   double prof_ms[4] = {0, 0, 0, 0};
   long prof_count = 0;
 
+  // kernel replay (kfbi_profile_kernel): layer and precision of the last apply, -1 = none
+  int last_layer = -1;
+  int last_precision = 0;
+
   // apply launch geometry (set by set_interface)
   int mk_chunk = 8;   // markers per K1 block
   int n_mk_blocks = 0;
@@ -136,5 +140,6 @@ int apply_impl(kfbi_ctx* c, int layer, int precision, const double* dens, const 
                const kfbi_out* out, const kfbi_bie* op, const double* x_for_op, double* y_op);
 int ensure_apply_buffers(kfbi_ctx* c);
 int prof_flush(kfbi_ctx* c);
+int replay_stage(kfbi_ctx* c, int stage, int reps, double* us_avg);
 int colconst_setup(kfbi_ctx* c);
 }  // namespace kfbi

@@ -24,6 +24,7 @@ FP64, FP32 = 0, 1
 EXPORTS = [
     "kfbi_last_error", "kfbi_create", "kfbi_destroy", "kfbi_set_interface", "kfbi_get_info",
     "kfbi_apply", "kfbi_operator", "kfbi_gmres_solve", "kfbi_profile", "kfbi_profile_read",
+    "kfbi_profile_kernel",
 ]
 
 
@@ -42,7 +43,7 @@ class Grid(C.Structure):
 class Info(C.Structure):
     _fields_ = [("M", C.c_int), ("n_cross_h", C.c_int), ("n_cross_v", C.c_int),
                 ("n_arms", C.c_int), ("n_nodes", C.c_int), ("n_rows", C.c_int),
-                ("row_lo", C.c_int), ("row_hi", C.c_int)]
+                ("row_lo", C.c_int), ("row_hi", C.c_int), ("n_parts", C.c_int)]
 
 
 class Out(C.Structure):
@@ -91,6 +92,7 @@ def load(path: str = LIBPATH):
                                      C.POINTER(GmresStats)]
     lib.kfbi_profile.argtypes = [vp, C.c_int]
     lib.kfbi_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+    lib.kfbi_profile_kernel.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
     _lib = lib
     return lib
 
@@ -175,6 +177,12 @@ class Context:
         n = C.c_long()
         _check(self.lib.kfbi_profile_read(self.h, ms, C.byref(n)))
         return list(ms), n.value
+
+    def profile_kernel(self, stage, reps=200):
+        """Average duration (us) of kernel `stage` of the last apply, replayed back to back."""
+        us = C.c_double()
+        _check(self.lib.kfbi_profile_kernel(self.h, stage, reps, C.byref(us)))
+        return us.value
 
     def gmres(self, rhs, x, layer, side, a, b, q, tol=1e-10, restart=50, maxit=1000,
               precision=FP64, inner_tol=1e-5, raise_noconv=True):

@@ -201,3 +201,28 @@ def test_error_paths():
     d = W.fourier_density(256, seed=1)
     ref = K.apply(G.build_geometry(X, box), K.DOUBLE, d, 0.0)
     assert rel(host(ctx.apply(K.DOUBLE, dev(d))["v_plus"]), ref.v_plus) <= TOL64
+
+
+def test_profile_kernel_replay_leaves_results_intact():
+    """Replaying the kernels of the last apply times them without touching caller arrays,
+    and the next apply still matches the oracle."""
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-1, 1, 256)
+    X = W.star(512)
+    ctx = make_ctx(box, 1000.0, K.BOX_ZERO, 512)
+    ctx.set_interface(dev(X))
+    with pytest.raises(kfbi.KfbiError) as e:
+        ctx.profile_kernel(0, 4)
+    assert e.value.code == kfbi.E_STATE
+    d = W.fourier_density(512, seed=4)
+    out = ctx.apply(K.SINGLE, dev(d))
+    keep = host(out["v_plus"]).copy()
+    for q in range(4):
+        us = ctx.profile_kernel(q, 8)
+        assert 0.0 < us < 1e4
+    assert np.array_equal(host(out["v_plus"]), keep)
+    with pytest.raises(kfbi.KfbiError) as e:
+        ctx.profile_kernel(4, 8)
+    assert e.value.code == kfbi.E_INVALID
+    ref = K.apply(G.build_geometry(X, box), K.SINGLE, d, 1000.0)
+    assert rel(host(ctx.apply(K.SINGLE, dev(d))["v_plus"]), ref.v_plus) <= TOL64
