@@ -141,11 +141,13 @@ __global__ void __launch_bounds__(256)
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
   const int ngr = (H + kReg - 1) / kReg;
   const int ng = ngr * nd;
-  const int S = 256 / ng;  // slices of m
+  int ngp = 1;  // groups rounded up to a power of two (at most 8)
+  while (ngp < ng) ngp <<= 1;
+  const int S = 256 / ngp;  // slices of m
   double* ph = lds;             // M
   double* dl1 = ph + M;         // M
   double* dl2 = dl1 + M;        // M (double layer only)
-  double* part = dl1 + nd * M;  // 256 * kReg
+  double* part = dl1 + nd * M;  // 4 waves x ngp x kReg
   const double wmine = (k0 + tid < k1) ? wq[k0 + tid] : 0.0;
   for (int m0 = tid; m0 < M; m0 += 256 * 8) {
     double a[8], bb[8], cc[8];
@@ -169,8 +171,13 @@ __global__ void __launch_bounds__(256)
     }
   }
   __syncthreads();
-  if (tid < S * ng) {
-    const int g = tid % ng, sl = tid / ng;
+  // thread = (slice sl, group g): g = tid mod ngp, so the slices of one group sit in
+  // lanes ngp apart and are summed by shuffles, then over the four wavefronts
+  const int g = tid & (ngp - 1), sl = tid / ngp;
+  double acc[kReg];
+#pragma unroll
+  for (int r = 0; r < kReg; ++r) acc[r] = 0.0;
+  if (g < ng) {
     const int dv = g / ngr, gr = g % ngr;
     const double* dd = dv == 0 ? dl1 : dl2;
     const int per = (M + S - 1) / S;
@@ -178,13 +185,12 @@ __global__ void __launch_bounds__(256)
     // outputs k_r = k0 + gr*kReg + r ; window w[r] = d[(k_r - m) mod M]
     int kb = (k0 + gr * kReg - mb) % M;
     kb += (kb < 0) ? M : 0;
-    double w[kReg], acc[kReg];
+    double w[kReg];
 #pragma unroll
     for (int r = 0; r < kReg; ++r) {
       int q = kb + r;
       q -= (q >= M) ? M : 0;
       w[r] = dd[q];
-      acc[r] = 0.0;
     }
     int q = kb;  // index of w[0]
     int m = mb;
@@ -217,30 +223,24 @@ __global__ void __launch_bounds__(256)
       q = (q == 0) ? M - 1 : q - 1;
       w[0] = dd[q];
     }
+  }
+  for (int off = ngp; off < 64; off <<= 1) {
 #pragma unroll
-    for (int r = 0; r < kReg; ++r) part[(sl * ng + g) * kReg + r] = acc[r];
+    for (int r = 0; r < kReg; ++r) acc[r] += __shfl_xor(acc[r], off, 64);
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane < ngp) {
+#pragma unroll
+    for (int r = 0; r < kReg; ++r) part[(wv * ngp + lane) * kReg + r] = acc[r];
   }
   __syncthreads();
   double v1 = 0.0, v2 = 0.0;
   if (tid < H) {
     const int gr = tid / kReg, r = tid % kReg;
-    int sl = 0;
-    for (; sl + 8 <= S; sl += 8) {
-      double a[8], bb[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        a[u] = part[((sl + u) * ng + gr) * kReg + r];
-        bb[u] = (nd == 2) ? part[((sl + u) * ng + ngr + gr) * kReg + r] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        v1 += a[u];
-        v2 += bb[u];
-      }
-    }
-    for (; sl < S; ++sl) {
-      v1 += part[(sl * ng + gr) * kReg + r];
-      if (nd == 2) v2 += part[(sl * ng + ngr + gr) * kReg + r];
+    for (int u = 0; u < 4; ++u) {
+      v1 += part[(u * ngp + gr) * kReg + r];
+      if (nd == 2) v2 += part[(u * ngp + ngr + gr) * kReg + r];
     }
   }
   // trapezoid partial sum of the density
@@ -279,9 +279,9 @@ __global__ void __launch_bounds__(256)
 // part order by the solve kernel.
 template <class T, int PT>
 __global__ void __launch_bounds__(256)
-    k_rowdst(int N, int M, int P, const int4* __restrict__ pdesc, const int* __restrict__ armpk,
-             const double* __restrict__ coefR, const int* __restrict__ kR, int cap,
-             const double* __restrict__ mq, const T* __restrict__ sinT, T* __restrict__ Tg) {
+    k_rowdst(int N, int M, int P, const int4* __restrict__ pdesc, const double* __restrict__ coefR,
+             const int* __restrict__ kR, const double* __restrict__ mq,
+             const T* __restrict__ sinT, T* __restrict__ Tg) {
   __shared__ T tab[sintab2_size<T>(4096)];
   __shared__ T rr[kArmsPerPart];
   __shared__ int ii[kArmsPerPart];
@@ -289,13 +289,14 @@ __global__ void __launch_bounds__(256)
   const int mask = 2 * N - 1;
   const int tid = threadIdx.x;
   const int q = blockIdx.x;
+  const int cap = kArmsPerPart * P;
   const int4 d = pdesc[q];
-  const int ab = d.y, na = d.z - d.y;
   SinTab2<T> st2;
   st2.stage(tab, N, sinT);
-  if (tid < na) {
-    const int a = ab + tid;
+  if (tid < kArmsPerPart) {  // slot tid of the part (empty slots have zero coefficients)
+    const int a = q * kArmsPerPart + tid;
     const int k = kR[a];
+    const int i = kR[cap + a];
     double l[6], cf[5];
 #pragma unroll
     for (int m = 0; m < 6; ++m) l[m] = coefR[m * cap + a];
@@ -312,8 +313,9 @@ __global__ void __launch_bounds__(256)
       r += l[m] * sm;
     }
     rr[tid] = static_cast<T>(r);
-    ii[tid] = armpk[a] & 0xffff;
+    ii[tid] = i;
   }
+  const int na = d.z - d.y;
   __syncthreads();
   const int p0 = 1 + tid * PT;
   T acc[PT];
@@ -551,7 +553,7 @@ __global__ void k_colconst(int N, double hc2, int E, double* __restrict__ colc,
 // MC threads apply the Sec. 4.3 corrected interpolation.
 template <class T, int E>
 __global__ void __launch_bounds__(256)
-    k_nodes_extract(int N, int M, int MC, const int* __restrict__ cnode,
+    k_nodes_extract(int N, int M, int MC, int nch, const int* __restrict__ cnode,
                     const int* __restrict__ ccount, const int* __restrict__ mkloc,
                     const T* __restrict__ sinT, int jlo, int nbr, const T* __restrict__ G,
                     const double* __restrict__ mq, const double* __restrict__ ext,
@@ -570,7 +572,12 @@ __global__ void __launch_bounds__(256)
   const int quarter = N / 2;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  const int ch = blockIdx.x;
+  // XCD-aware order: blocks resident on one XCD (ids congruent mod 8) take consecutive
+  // marker chunks, whose stencils share grid rows, so those rows are fetched into one L2
+  const int per_xcd = gridDim.x / 8;  // the grid is 8 per_xcd blocks
+  const int bx = blockIdx.x;
+  const int ch = (bx % 8) * per_xcd + bx / 8;
+  if (ch >= nch) return;
   const int nn = ccount[ch];
   const int* keys = cnode + static_cast<size_t>(ch) * 6 * MC;
   // prefetch the extraction data of this thread's marker (used after the node phase)
@@ -786,8 +793,7 @@ static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jl
   constexpr int PT = (64 * E + 255) / 256;
   if (P > 0 && (stages & 2))
     hipLaunchKernelGGL((k_rowdst<T, PT>), dim3(P), dim3(256), 0, s, N, M, P, c->pdesc.as<int4>(),
-                       c->armpk.as<int>(), c->armc.as<double>(), c->armk.as<int>(), c->arm_cap,
-                       c->mq.as<double>(), sinT, Tg);
+                       c->armc.as<double>(), c->armk.as<int>(), c->mq.as<double>(), sinT, Tg);
   if (ev) hipEventRecord(ev[2], s);
   const int ngrp = nblk(n, kColsPerBlock);
   const int nb = ((ngrp + 7) / 8) * 8;
@@ -809,8 +815,8 @@ static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jl
   const int side = op ? op->side : 0;
   const double oa = op ? op->a : 0.0, ob = op ? op->b : 0.0, oq = op ? op->q : 0.0;
   if (stages & 8)
-    hipLaunchKernelGGL((k_nodes_extract<T, E>), dim3(nch), dim3(256), sizeof(double) * 6 * MC, s,
-                     N, M, MC, c->cnode.as<int>(), c->ccount.as<int>(), c->mkloc.as<int>(),
+    hipLaunchKernelGGL((k_nodes_extract<T, E>), dim3(8 * nblk(nch, 8)), dim3(256),
+                       sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(), c->ccount.as<int>(), c->mkloc.as<int>(),
                      sinT, jlo, nbr, G, c->mq.as<double>(), c->ext.as<double>(),
                      c->qpart.as<double>(), c->n_mk_blocks, out ? out->v_plus : nullptr,
                      out ? out->v_minus : nullptr, out ? out->dn_plus : nullptr,
@@ -841,7 +847,7 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
   if (c->box_bc == KFBI_BOX_FREESPACE) nring = nblk(4 * (N + 1), 16);
   const int C = c->mk_chunk, nmk = c->n_mk_blocks;
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
-  const size_t lds = sizeof(double) * ((1 + nd) * M + 256 * kReg);
+  const size_t lds = sizeof(double) * ((1 + nd) * M + 256 * kReg);  // covers block_sum too
   allow_dyn_lds(k_prep, lds);
   if (stages & 1)
     hipLaunchKernelGGL(k_prep, dim3(nmk + nring), dim3(256), lds, s, M, C, nmk, layer, dens,

@@ -375,16 +375,33 @@ __global__ void k_arm_fill(int N, double x0, double y0, double h, double c2, int
 }
 
 // Row-ordered arm coefficients as structure of arrays (coefR[q * cap + a], kR[a]).
-__global__ void k_arm_soa(int na, int cap, const ArmCoef* __restrict__ armc,
-                          double* __restrict__ coefR, int* __restrict__ kR) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= na) return;
-  const ArmCoef ac = armc[a];
+// Arm coefficients in part-slot order for the row transform kernel: slot t of part q
+// is arm pdesc[q].a0 + t, or an empty slot (zero coefficients) past the part's end.
+// Structure of arrays: coefR[c * cap + 16 q + t] (c = 0..10), kR[16 q + t] (first
+// stencil marker), iR = kR + cap (grid column of the arm's node), cap = 16 P.
+__global__ void k_part_soa(int P, const int4* __restrict__ pdesc, const ArmCoef* __restrict__ armc,
+                           const int* __restrict__ armpk, double* __restrict__ coefR,
+                           int* __restrict__ kR) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cap = kArmsPerPart * P;
+  if (s >= cap) return;
+  const int q = s / kArmsPerPart, t = s % kArmsPerPart;
+  const int4 d = pdesc[q];
+  const int a = d.y + t;
+  if (a < d.z) {
+    const ArmCoef ac = armc[a];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) coefR[m * cap + a] = ac.l[m];
+    for (int m = 0; m < 6; ++m) coefR[m * cap + s] = ac.l[m];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) coefR[(6 + q) * cap + a] = ac.coef[q];
-  kR[a] = ac.k;
+    for (int c = 0; c < 5; ++c) coefR[(6 + c) * cap + s] = ac.coef[c];
+    kR[s] = ac.k;
+    kR[cap + s] = armpk[a] & 0xffff;
+  } else {
+#pragma unroll
+    for (int c = 0; c < kArmCoefCount; ++c) coefR[c * cap + s] = 0.0;
+    kR[s] = 0;
+    kR[cap + s] = 0;
+  }
 }
 
 // Rows split into parts of at most kArmsPerPart arms: parts per row, then descriptors
@@ -672,9 +689,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   KFBI_TRY(c->armpk.ensure(sizeof(int) * narm_cap));
   KFBI_TRY(c->armcoef.ensure(sizeof(ArmCoef) * narm_cap));
   KFBI_TRY(c->armr.ensure(sizeof(double) * narm_cap));
-  KFBI_TRY(c->armc.ensure(sizeof(double) * kArmCoefCount * narm_cap));
-  KFBI_TRY(c->armk.ensure(sizeof(int) * narm_cap));
-  c->arm_cap = narm_cap;
+
 
   Crossing* cr = c->cross.as<Crossing>();
   hipLaunchKernelGGL(k_fill_cross, dim3(nblk(M, 128)), dim3(128), 0, s, M, c->X.as<double>(), c->x0,
@@ -743,12 +758,16 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
     KFBI_TRY(c->tmat.ensure(sizeof(double) * 4 * static_cast<size_t>(ng) * (P + 1)));
     hipLaunchKernelGGL(k_part_fill, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart,
                        c->pdesc.as<int4>());
+    // part-slot arm coefficients for the row transform kernel
+    const int cap = kArmsPerPart * (P > 0 ? P : 1);
+    KFBI_TRY(c->armc.ensure(sizeof(double) * kArmCoefCount * cap));
+    KFBI_TRY(c->armk.ensure(sizeof(int) * 2 * cap));
+    c->arm_cap = cap;
+    if (P > 0)
+      hipLaunchKernelGGL(k_part_soa, dim3(nblk(cap, 256)), dim3(256), 0, s, P,
+                         c->pdesc.as<int4>(), c->armcoef.as<ArmCoef>(), c->armpk.as<int>(),
+                         c->armc.as<double>(), c->armk.as<int>());
   }
-  // row-ordered arm coefficients (structure of arrays) for the row transform kernel
-  const int na = hs->n_arms;
-  if (na > 0)
-    hipLaunchKernelGGL(k_arm_soa, dim3(nblk(na, 256)), dim3(256), 0, s, na, c->arm_cap,
-                       c->armcoef.as<ArmCoef>(), c->armc.as<double>(), c->armk.as<int>());
   KFBI_HIP(hipGetLastError());
   c->st = *hs;
   c->M = M;
