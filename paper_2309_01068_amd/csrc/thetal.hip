@@ -1,0 +1,830 @@
+// theta-L / small-scale-decomposition Hele-Shaw evolution on gfx950 (Sec. 5), driving the
+// KFBI pressure solve of eq. bie-HS through the kfbi C ABI.
+//
+// Per step: k_tl_pre (one workgroup) reconstructs the markers from (eta, L, Xbar) and
+// forms the right-hand side -sigma kappa - v; kfbi_set_interface rebuilds the grid
+// geometry; kfbi_gmres_solve finds the density; one more apply gives d_n(D phi);
+// k_tl_post (one workgroup) forms U, V, the explicit term, and advances eta (integrating
+// factor AB2 in Fourier space), L and Xbar (AB2).  All spectral operations are radix-2
+// Stockham FFTs of length M held in LDS, FP64.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <new>
+
+#include "../../include/thetal.h"
+#include "common.h"
+#include "device_util.h"
+
+namespace kfbi {
+namespace {
+
+constexpr int kTLThreads = 1024;
+constexpr int kTLMaxM = 2048;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// scal[] slots (device)
+enum { S_L = 0, S_XBX, S_XBY, S_T, S_LPREV, S_MPREV, S_QPX, S_QPY, S_AREA, S_LEN, S_BAD, S_COUNT };
+// aux[] planes of M doubles (device)
+enum { A_THA = 0, A_HETA, A_NX, A_NY, A_R2, A_U, A_COUNT };
+
+__device__ __forceinline__ int wavenum(int q, int M) {  // signed wavenumber, Nyquist -> 0
+  const int h = M >> 1;
+  return q < h ? q : (q == h ? 0 : q - M);
+}
+
+// Radix-2 Stockham FFT of length M (power of two) on LDS arrays; (xr, xi) holds the input
+// and, on return, the output (the pointers are swapped as the passes ping-pong).  The
+// inverse is unscaled.  Twiddles tw[k] = exp(-2 pi i k / M), k < M/2, in LDS.
+__device__ void fft_lds(double*& xr, double*& xi, double*& yr, double*& yi,
+                        const double* __restrict__ twr, const double* __restrict__ twi, int M,
+                        bool inverse) {
+  const int h = M >> 1;
+  for (int ns = 1; ns < M; ns <<= 1) {
+    const int stride = M / (2 * ns);
+    for (int j = threadIdx.x; j < h; j += blockDim.x) {
+      const int k = j & (ns - 1);
+      const double ar = xr[j], ai = xi[j], br = xr[j + h], bi = xi[j + h];
+      const double wr = twr[k * stride];
+      const double wi = inverse ? -twi[k * stride] : twi[k * stride];
+      const double tr = br * wr - bi * wi, ti = br * wi + bi * wr;
+      const int d = ((j - k) << 1) + k;
+      yr[d] = ar + tr;
+      yi[d] = ai + ti;
+      yr[d + ns] = ar - tr;
+      yi[d + ns] = ai - ti;
+    }
+    __syncthreads();
+    double* t = xr;
+    xr = yr;
+    yr = t;
+    t = xi;
+    xi = yi;
+    yi = t;
+  }
+}
+
+struct TLShared {
+  double *xr, *xi, *yr, *yi, *twr, *twi, *red;
+  __device__ void setup(double* lds, int M, const double* __restrict__ tw) {
+    xr = lds;
+    xi = xr + M;
+    yr = xi + M;
+    yi = yr + M;
+    twr = yi + M;
+    twi = twr + M / 2;
+    red = twi + M / 2;
+    for (int k = threadIdx.x; k < M / 2; k += blockDim.x) {
+      twr[k] = tw[2 * k];
+      twi[k] = tw[2 * k + 1];
+    }
+    __syncthreads();
+  }
+};
+inline size_t tl_lds_bytes(int M) { return sizeof(double) * (5 * static_cast<size_t>(M) + 32); }
+
+// ---------------------------------------------------------------------------- pre-step
+// Reconstruction (Sec. 5.1): theta = alpha + eta, X = Xbar + (L/2pi) A[exp(i theta)] with
+// the mean-free antiderivative A; eta_a and H[eta_aaa] (Sec. 5.2.1); curvature
+// kappa = (2pi/L) theta_a; right-hand side -sigma kappa + J ln|x| (eq. bie-HS with
+// v = -J ln|x|); area (1/2) int (x y_a - y x_a) da.
+__global__ void __launch_bounds__(kTLThreads)
+    k_tl_pre(int M, double sigma, double J, const double* __restrict__ tw,
+             const double* __restrict__ eta, double* __restrict__ scal, double* __restrict__ X,
+             double* __restrict__ rhs, double* __restrict__ aux, double* __restrict__ etahat) {
+  extern __shared__ double lds[];
+  TLShared sh;
+  sh.setup(lds, M, tw);
+  const int tid = threadIdx.x;
+  const double L = scal[S_L], xbx = scal[S_XBX], xby = scal[S_XBY];
+  const double invM = 1.0 / M;
+  // exp(i theta)
+  for (int j = tid; j < M; j += blockDim.x) {
+    double s, c;
+    sincos(kTwoPi * j * invM + eta[j], &s, &c);
+    sh.xr[j] = c;
+    sh.xi[j] = s;
+  }
+  __syncthreads();
+  fft_lds(sh.xr, sh.xi, sh.yr, sh.yi, sh.twr, sh.twi, M, false);
+  // keep zhat (k = 0 and Nyquist removed) in registers for the tangent; antiderivative
+  constexpr int U = kTLMaxM / kTLThreads;
+  double zr[U], zi[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * kTLThreads;
+    zr[u] = zi[u] = 0.0;
+    if (q < M) {
+      const int k = wavenum(q, M);
+      const double a = sh.xr[q], b = sh.xi[q];
+      if (k != 0) {
+        zr[u] = a;
+        zi[u] = b;
+      }
+      sh.yr[q] = (k != 0) ? b / k : 0.0;
+      sh.yi[q] = (k != 0) ? -a / k : 0.0;
+    }
+  }
+  __syncthreads();
+  fft_lds(sh.yr, sh.yi, sh.xr, sh.xi, sh.twr, sh.twi, M, true);
+  const double sc = L / kTwoPi * invM;
+  double xs[U], ys[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = tid + u * kTLThreads;
+    if (j < M) {
+      xs[u] = xbx + sc * sh.yr[j];
+      ys[u] = xby + sc * sh.yi[j];
+    }
+  }
+  __syncthreads();
+  // tangent X_a + i Y_a = (L/2pi) IFFT(zhat without k = 0, Nyquist)
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * kTLThreads;
+    if (q < M) {
+      sh.xr[q] = zr[u];
+      sh.xi[q] = zi[u];
+    }
+  }
+  __syncthreads();
+  fft_lds(sh.xr, sh.xi, sh.yr, sh.yi, sh.twr, sh.twi, M, true);
+  double ar = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = tid + u * kTLThreads;
+    if (j < M) ar += xs[u] * (sc * sh.xi[j]) - ys[u] * (sc * sh.xr[j]);
+  }
+  ar = block_sum<double>(ar, sh.red);
+  // eta_hat, then eta_a + i H[eta_aaa] (multipliers ik and -|k|^3)
+  for (int j = tid; j < M; j += blockDim.x) {
+    sh.xr[j] = eta[j];
+    sh.xi[j] = 0.0;
+  }
+  __syncthreads();
+  fft_lds(sh.xr, sh.xi, sh.yr, sh.yi, sh.twr, sh.twi, M, false);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * kTLThreads;
+    if (q < M) {
+      const double er = sh.xr[q], ei = sh.xi[q];
+      etahat[2 * q] = er;
+      etahat[2 * q + 1] = ei;
+      const double k = wavenum(q, M);
+      const double k3 = fabs(k) * k * k;
+      sh.yr[q] = -k * ei + k3 * ei;
+      sh.yi[q] = k * er - k3 * er;
+    }
+  }
+  __syncthreads();
+  fft_lds(sh.yr, sh.yi, sh.xr, sh.xi, sh.twr, sh.twi, M, true);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = tid + u * kTLThreads;
+    if (j < M) {
+      const double eta_a = sh.yr[j] * invM, heta = sh.yi[j] * invM;
+      const double tha = 1.0 + eta_a;
+      const double kappa = kTwoPi / L * tha;
+      const double r2 = xs[u] * xs[u] + ys[u] * ys[u];
+      double s, c;
+      sincos(kTwoPi * j * invM + eta[j], &s, &c);
+      X[j] = xs[u];
+      X[M + j] = ys[u];
+      rhs[j] = -sigma * kappa + J * 0.5 * log(r2);
+      aux[A_THA * M + j] = tha;
+      aux[A_HETA * M + j] = heta;
+      aux[A_NX * M + j] = s;
+      aux[A_NY * M + j] = -c;
+      aux[A_R2 * M + j] = r2;
+    }
+  }
+  if (tid == 0) {
+    scal[S_AREA] = 0.5 * ar * kTwoPi * invM;
+    scal[S_LEN] = L;
+  }
+}
+
+// --------------------------------------------------------------------------- post-step
+// U = J (x.n)/|x|^2 - (d_n+ + d_n-)/2 of D phi; M_dot = int theta_a U da;
+// V = -(int_0^a theta_a U - mean part) (eq. L-evo/the-evo); Qbar = mean(U n + V s);
+// explicit term N = (2pi/L)(theta_a V - U_a) - lambda2 (2pi/L)^3 H[eta_aaa]; then the
+// integrating-factor step for eta_hat (eq. Fourier-theta2), AB2 (or Euler at n = 0) for
+// L and Xbar.
+__global__ void __launch_bounds__(kTLThreads)
+    k_tl_post(int M, double J, double tau, double lam2, int first,
+              const double* __restrict__ tw, const double* __restrict__ X,
+              double* __restrict__ aux, const double* __restrict__ dnp,
+              const double* __restrict__ dnm, const double* __restrict__ etahat,
+              double* __restrict__ nhat_prev, double* __restrict__ scal,
+              double* __restrict__ eta) {
+  extern __shared__ double lds[];
+  TLShared sh;
+  sh.setup(lds, M, tw);
+  const int tid = threadIdx.x;
+  const double invM = 1.0 / M;
+  const double L = scal[S_L];
+  constexpr int U = kTLMaxM / kTLThreads;
+  double uu[U], tha[U], nx[U], ny[U], he[U];
+  double gs = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = tid + u * kTLThreads;
+    if (j < M) {
+      tha[u] = aux[A_THA * M + j];
+      he[u] = aux[A_HETA * M + j];
+      nx[u] = aux[A_NX * M + j];
+      ny[u] = aux[A_NY * M + j];
+      const double r2 = aux[A_R2 * M + j];
+      const double x = X[j], y = X[M + j];
+      uu[u] = J * (x * nx[u] + y * ny[u]) / r2 - 0.5 * (dnp[j] + dnm[j]);
+      aux[A_U * M + j] = uu[u];
+      const double g = tha[u] * uu[u];
+      sh.xr[j] = g;
+      sh.xi[j] = uu[u];
+      gs += g;
+    }
+  }
+  gs = block_sum<double>(gs, sh.red);  // (synchronises: the FFT input is complete)
+  const double Mdot = kTwoPi * gs * invM;
+  fft_lds(sh.xr, sh.xi, sh.yr, sh.yi, sh.twr, sh.twi, M, false);
+  // split F = FFT(g + iU) into G_hat and U_hat; spectrum of A[g] + i U_a
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * kTLThreads;
+    if (q < M) {
+      const int qm = (M - q) & (M - 1);
+      const double fr = sh.xr[q], fi = sh.xi[q], cr = sh.xr[qm], ci = -sh.xi[qm];
+      const double gr = 0.5 * (fr + cr), gi = 0.5 * (fi + ci);
+      const double ur = 0.5 * (fi - ci), ui = -0.5 * (fr - cr);
+      const int k = wavenum(q, M);
+      sh.yr[q] = (k != 0) ? gi / k - k * ur : 0.0;
+      sh.yi[q] = (k != 0) ? -gr / k - k * ui : 0.0;
+    }
+  }
+  __syncthreads();
+  fft_lds(sh.yr, sh.yi, sh.xr, sh.xi, sh.twr, sh.twi, M, true);
+  const double A0 = sh.yr[0] * invM;
+  const double w = kTwoPi / L;
+  double qx = 0.0, qy = 0.0;
+  double nv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = tid + u * kTLThreads;
+    if (j < M) {
+      const double A = sh.yr[j] * invM, Ua = sh.yi[j] * invM;
+      const double V = -(A - A0);
+      const double sx = -ny[u], sy = nx[u];
+      qx += uu[u] * nx[u] + V * sx;
+      qy += uu[u] * ny[u] + V * sy;
+      nv[u] = w * (tha[u] * V - Ua) - lam2 * w * w * w * he[u];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = tid + u * kTLThreads;
+    if (j < M) {
+      sh.xr[j] = nv[u];
+      sh.xi[j] = 0.0;
+    }
+  }
+  qx = block_sum<double>(qx, sh.red);
+  qy = block_sum<double>(qy, sh.red);
+  qx *= invM;
+  qy *= invM;
+  fft_lds(sh.xr, sh.xi, sh.yr, sh.yi, sh.twr, sh.twi, M, false);
+  // scalars (every thread computes the same values)
+  const double xbx = scal[S_XBX], xby = scal[S_XBY];
+  double Ln, xn, yn;
+  if (first) {
+    Ln = L + tau * Mdot;
+    xn = xbx + tau * qx;
+    yn = xby + tau * qy;
+  } else {
+    Ln = L + 0.5 * tau * (3.0 * Mdot - scal[S_MPREV]);
+    xn = xbx + 0.5 * tau * (3.0 * qx - scal[S_QPX]);
+    yn = xby + 0.5 * tau * (3.0 * qy - scal[S_QPY]);
+  }
+  const double Lp = scal[S_LPREV];
+  const double c1 = 0.5 * lam2 * tau * (1.0 / (L * L * L) + 1.0 / (Ln * Ln * Ln));
+  const double c2 = first ? 0.0
+                          : lam2 * tau * (0.5 / (Lp * Lp * Lp) + 1.0 / (L * L * L) +
+                                          0.5 / (Ln * Ln * Ln));
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * kTLThreads;
+    if (q < M) {
+      const double k = fabs(static_cast<double>(wavenum(q, M)));
+      const double tk3 = (kTwoPi * k) * (kTwoPi * k) * (kTwoPi * k);
+      const double e1 = exp(-c1 * tk3);
+      const double nr = sh.xr[q], ni = sh.xi[q];
+      const double er = etahat[2 * q], ei = etahat[2 * q + 1];
+      double hr, hi;
+      if (first) {
+        hr = e1 * (er + tau * nr);
+        hi = e1 * (ei + tau * ni);
+      } else {
+        const double e2 = exp(-c2 * tk3);
+        const double pr = nhat_prev[2 * q], pi = nhat_prev[2 * q + 1];
+        hr = e1 * er + 0.5 * tau * (3.0 * e1 * nr - e2 * pr);
+        hi = e1 * ei + 0.5 * tau * (3.0 * e1 * ni - e2 * pi);
+      }
+      if (q == (M >> 1)) hr = hi = 0.0;
+      nhat_prev[2 * q] = nr;
+      nhat_prev[2 * q + 1] = ni;
+      sh.yr[q] = hr;
+      sh.yi[q] = hi;
+    }
+  }
+  __syncthreads();
+  fft_lds(sh.yr, sh.yi, sh.xr, sh.xi, sh.twr, sh.twi, M, true);
+  int bad = 0;
+  for (int j = tid; j < M; j += blockDim.x) {
+    const double v = sh.yr[j] * invM;
+    eta[j] = v;
+    bad |= !isfinite(v);
+  }
+  bad = __syncthreads_or(bad);
+  if (tid == 0) {
+    scal[S_LPREV] = L;
+    scal[S_MPREV] = Mdot;
+    scal[S_QPX] = qx;
+    scal[S_QPY] = qy;
+    scal[S_L] = Ln;
+    scal[S_XBX] = xn;
+    scal[S_XBY] = yn;
+    scal[S_T] += tau;
+    scal[S_BAD] = (bad || !isfinite(Ln) || !(Ln > 0.0) || !isfinite(xn) || !isfinite(yn)) ? 1.0 : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- equal-arclength start
+// Trigonometric interpolation coefficients c_q = (1/Mi) sum_j f_j e^{-2 pi i q j / Mi}
+// (Nyquist set to zero) of nf arrays, one block per (q, array).
+__global__ void k_dft_coef(int Mi, const double* __restrict__ f, double* __restrict__ c) {
+  __shared__ double red[32];
+  const int q = blockIdx.x, a = blockIdx.y;
+  const double* fa = f + static_cast<size_t>(a) * Mi;
+  double sr = 0.0, si = 0.0;
+  for (int j = threadIdx.x; j < Mi; j += blockDim.x) {
+    const long long m = (static_cast<long long>(q) * j) % Mi;
+    double s, co;
+    sincospi(2.0 * static_cast<double>(m) / Mi, &s, &co);
+    sr += fa[j] * co;
+    si -= fa[j] * s;
+  }
+  sr = block_sum<double>(sr, red);
+  si = block_sum<double>(si, red);
+  if (threadIdx.x == 0) {
+    const bool nyq = (q == Mi / 2);
+    c[(static_cast<size_t>(a) * Mi + q) * 2] = nyq ? 0.0 : sr / Mi;
+    c[(static_cast<size_t>(a) * Mi + q) * 2 + 1] = nyq ? 0.0 : si / Mi;
+  }
+}
+
+// Real part of sum_q c_q (i k_q)^d e^{i k_q beta} for one coefficient set.
+__device__ double trig_eval(const double* __restrict__ c, int Mi, double beta, int d,
+                            double* red) {
+  double s = 0.0;
+  for (int q = threadIdx.x; q < Mi; q += blockDim.x) {
+    const int k = wavenum(q, Mi);
+    double sn, cs;
+    sincos(k * beta, &sn, &cs);
+    double cr = c[2 * q], ci = c[2 * q + 1];
+    for (int t = 0; t < d; ++t) {  // multiply by ik
+      const double nr = -k * ci, ni = k * cr;
+      cr = nr;
+      ci = ni;
+    }
+    s += cr * cs - ci * sn;
+  }
+  return block_sum<double>(s, red);
+}
+
+// |X_beta| at the input samples, one block per sample.
+__global__ void k_speed(int Mi, const double* __restrict__ cxy, double* __restrict__ sb) {
+  __shared__ double red[32];
+  const int j = blockIdx.x;
+  const double beta = kTwoPi * j / Mi;
+  const double xd = trig_eval(cxy, Mi, beta, 1, red);
+  const double yd = trig_eval(cxy + 2 * static_cast<size_t>(Mi), Mi, beta, 1, red);
+  if (threadIdx.x == 0) sb[j] = hypot(xd, yd);
+}
+
+// Newton for beta_j with s(beta_j) = L j / M, s(beta) = (L/2pi) beta + A(beta) - A(0), A the
+// mean-free antiderivative of |X_beta|; then X(beta_j), the raw tangent angle.  One block
+// per output point; each point iterates until its own step is below 1e-14 (50 at most).
+__global__ void k_newton(int Mi, int M, const double* __restrict__ cxy,
+                         const double* __restrict__ cs, double* __restrict__ anti,
+                         double* __restrict__ out) {
+  __shared__ double red[32];
+  const int j = blockIdx.x;
+  const double L = kTwoPi * cs[0];
+  // A(0) = Re sum anti_q
+  const double a0 = trig_eval(anti, Mi, 0.0, 0, red);
+  const double target = L * j / M;
+  double beta = kTwoPi * j / M;
+  for (int it = 0; it < 50; ++it) {
+    const double f = L / kTwoPi * beta + trig_eval(anti, Mi, beta, 0, red) - a0 - target;
+    const double d = trig_eval(cs, Mi, beta, 0, red);
+    const double step = f / d;
+    beta -= step;
+    if (fabs(step) < 1e-14) break;  // block-uniform
+  }
+  const double xb = trig_eval(cxy, Mi, beta, 0, red);
+  const double yb = trig_eval(cxy + 2 * static_cast<size_t>(Mi), Mi, beta, 0, red);
+  const double xd = trig_eval(cxy, Mi, beta, 1, red);
+  const double yd = trig_eval(cxy + 2 * static_cast<size_t>(Mi), Mi, beta, 1, red);
+  if (threadIdx.x == 0) {
+    out[j] = atan2(yd, xd);
+    out[M + j] = xb;
+    out[2 * M + j] = yb;
+  }
+}
+
+// anti_q = cs_q / (i k_q) for k_q != 0.
+__global__ void k_anti(int Mi, const double* __restrict__ cs, double* __restrict__ anti) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Mi) return;
+  const int k = wavenum(q, Mi);
+  const double a = cs[2 * q], b = cs[2 * q + 1];
+  anti[2 * q] = (k != 0) ? b / k : 0.0;
+  anti[2 * q + 1] = (k != 0) ? -a / k : 0.0;
+}
+
+// Unwrap the raw angles (add the multiple of 2 pi that keeps consecutive jumps within pi),
+// eta = theta - alpha, Xbar = mean of the resampled points, L; reset the scalars.
+__global__ void __launch_bounds__(kTLThreads)
+    k_unwrap(int M, const double* __restrict__ raw, const double* __restrict__ cs,
+             double* __restrict__ eta, double* __restrict__ scal) {
+  __shared__ int sc[kTLMaxM];
+  __shared__ double red[32];
+  const int tid = threadIdx.x;
+  // per-sample correction count (numpy's unwrap rule)
+  for (int j = tid; j < M; j += blockDim.x) {
+    int c = 0;
+    if (j > 0) {
+      const double dd = raw[j] - raw[j - 1];
+      double dm = fmod(dd + M_PI, kTwoPi);
+      if (dm < 0) dm += kTwoPi;
+      dm -= M_PI;
+      if (dm == -M_PI && dd > 0) dm = M_PI;
+      const double corr = dm - dd;
+      c = (fabs(dd) < M_PI) ? 0 : static_cast<int>(rint(corr / kTwoPi));
+    }
+    sc[j] = c;
+  }
+  __syncthreads();
+  // inclusive prefix sum (Hillis-Steele over LDS, M <= 2048)
+  for (int off = 1; off < M; off <<= 1) {
+    int v[2];
+    for (int u = 0; u < 2; ++u) {
+      const int j = tid + u * kTLThreads;
+      v[u] = (j < M && j >= off) ? sc[j - off] : 0;
+    }
+    __syncthreads();
+    for (int u = 0; u < 2; ++u) {
+      const int j = tid + u * kTLThreads;
+      if (j < M) sc[j] += v[u];
+    }
+    __syncthreads();
+  }
+  double sx = 0.0, sy = 0.0;
+  for (int j = tid; j < M; j += blockDim.x) {
+    eta[j] = raw[j] + kTwoPi * sc[j] - kTwoPi * j / M;
+    sx += raw[M + j];
+    sy += raw[2 * M + j];
+  }
+  sx = block_sum<double>(sx, red);
+  sy = block_sum<double>(sy, red);
+  if (tid == 0) {
+    for (int s = 0; s < S_COUNT; ++s) scal[s] = 0.0;
+    scal[S_L] = kTwoPi * cs[0];
+    scal[S_XBX] = sx / M;
+    scal[S_XBY] = sy / M;
+  }
+}
+
+__global__ void k_twiddles(int M, double* __restrict__ tw) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M / 2) return;
+  double s, c;
+  sincospi(2.0 * k / M, &s, &c);
+  tw[2 * k] = c;
+  tw[2 * k + 1] = -s;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+}  // namespace kfbi
+
+struct thetaL {
+  thetaL_params prm{};
+  kfbi_ctx* kc = nullptr;
+  hipStream_t stream = nullptr;
+  int M = 0;
+  int n = 0;           // steps taken
+  int ready = 0;       // thetaL_init or set_state done
+  int have_phi = 0;    // phi_prev holds a density
+  kfbi::DBuf tw, eta, scal, X, rhs, aux, etahat, nhat, phi, phiw, dnp, dnm, init;
+  double* hscal = nullptr;  // pinned copy of scal
+};
+
+using namespace kfbi;
+
+static int tl_check(const thetaL* th, bool need_ready) {
+  if (!th) {
+    set_error("null thetaL object");
+    return KFBI_E_INVALID;
+  }
+  if (need_ready && !th->ready) {
+    set_error("thetaL_init (or thetaL_set_state) has not been called");
+    return KFBI_E_STATE;
+  }
+  return KFBI_OK;
+}
+
+static void tl_free(thetaL* th) {
+  for (DBuf* b : {&th->tw, &th->eta, &th->scal, &th->X, &th->rhs, &th->aux, &th->etahat, &th->nhat,
+                  &th->phi, &th->phiw, &th->dnp, &th->dnm, &th->init})
+    b->release();
+  if (th->hscal) (void)hipHostFree(th->hscal);
+  th->hscal = nullptr;
+  if (th->kc) kfbi_destroy(th->kc);
+  th->kc = nullptr;
+}
+
+extern "C" {
+
+int thetaL_create(const thetaL_params* p, thetaL** out) {
+  if (!p || !out) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  *out = nullptr;
+  const int M = p->M;
+  if (M < 16 || M > kTLMaxM || (M & (M - 1))) {
+    set_error("thetaL: M must be a power of two in [16, %d] (M=%d)", kTLMaxM, M);
+    return KFBI_E_INVALID;
+  }
+  if (p->grid.box_bc != KFBI_BOX_FREESPACE || p->grid.c2 != 0.0) {
+    set_error("thetaL: the Hele-Shaw pressure solve needs box_bc = KFBI_BOX_FREESPACE, c2 = 0");
+    return KFBI_E_INVALID;
+  }
+  if (!(p->tau > 0.0) || !(p->sigma >= 0.0) || !std::isfinite(p->J)) {
+    set_error("thetaL: need tau > 0, sigma >= 0, finite J");
+    return KFBI_E_INVALID;
+  }
+  thetaL* th = new (std::nothrow) thetaL();
+  if (!th) {
+    set_error("out of host memory");
+    return KFBI_E_NOMEM;
+  }
+  th->prm = *p;
+  th->M = M;
+  kfbi_grid g = p->grid;
+  g.max_markers = M;
+  int st = kfbi_create(&g, &th->kc);
+  if (st != KFBI_OK) {
+    delete th;
+    return st;
+  }
+  th->stream = static_cast<hipStream_t>(g.stream);
+  const int Mi = 4096;  // largest accepted input sampling of thetaL_init
+  if ((st = th->tw.ensure(sizeof(double) * M)) || (st = th->eta.ensure(sizeof(double) * M)) ||
+      (st = th->scal.ensure(sizeof(double) * S_COUNT)) ||
+      (st = th->X.ensure(sizeof(double) * 2 * M)) || (st = th->rhs.ensure(sizeof(double) * M)) ||
+      (st = th->aux.ensure(sizeof(double) * A_COUNT * M)) ||
+      (st = th->etahat.ensure(sizeof(double) * 2 * M)) ||
+      (st = th->nhat.ensure(sizeof(double) * 2 * M)) ||
+      (st = th->phi.ensure(sizeof(double) * M)) || (st = th->phiw.ensure(sizeof(double) * M)) ||
+      (st = th->dnp.ensure(sizeof(double) * M)) || (st = th->dnm.ensure(sizeof(double) * M)) ||
+      (st = th->init.ensure(sizeof(double) * (2 * Mi + 4 * Mi + 2 * Mi + 2 * Mi + Mi + 3 * M)))) {
+    tl_free(th);
+    delete th;
+    return st;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&th->hscal), sizeof(double) * S_COUNT,
+                    hipHostMallocDefault) != hipSuccess) {
+    th->hscal = nullptr;
+    tl_free(th);
+    delete th;
+    set_error("hipHostMalloc failed");
+    return KFBI_E_NOMEM;
+  }
+  hipLaunchKernelGGL(k_twiddles, dim3((M / 2 + 255) / 256), dim3(256), 0, th->stream, M,
+                     th->tw.as<double>());
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(th->stream) != hipSuccess) {
+    tl_free(th);
+    delete th;
+    set_error("thetaL: twiddle kernel failed");
+    return KFBI_E_HIP;
+  }
+  const size_t lds = tl_lds_bytes(M);
+  if (lds > 64 * 1024) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_pre),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_post),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  }
+  *out = th;
+  return KFBI_OK;
+}
+
+int thetaL_destroy(thetaL* th) {
+  if (!th) return KFBI_OK;
+  (void)hipStreamSynchronize(th->stream);
+  tl_free(th);
+  delete th;
+  return KFBI_OK;
+}
+
+kfbi_ctx* thetaL_kfbi(thetaL* th) { return th ? th->kc : nullptr; }
+
+int thetaL_init(thetaL* th, int Mi, const double* xy) {
+  KFBI_TRY(tl_check(th, false));
+  if (!xy || Mi < 16 || Mi > 4096 || (Mi & 1)) {
+    set_error("thetaL_init: Mi must be even in [16, 4096] with a non-null xy (Mi=%d)", Mi);
+    return KFBI_E_INVALID;
+  }
+  const int M = th->M;
+  hipStream_t s = th->stream;
+  double* w = th->init.as<double>();
+  double* cxy = w;                 // 2 x Mi complex
+  double* cs = cxy + 4 * Mi;       // Mi complex
+  double* anti = cs + 2 * Mi;      // Mi complex
+  double* sb = anti + 2 * Mi;      // Mi
+  double* raw = sb + Mi;           // 3 M: raw angle, x, y
+  hipLaunchKernelGGL(k_dft_coef, dim3(Mi, 2), dim3(256), 0, s, Mi, xy, cxy);
+  hipLaunchKernelGGL(k_speed, dim3(Mi), dim3(256), 0, s, Mi, cxy, sb);
+  hipLaunchKernelGGL(k_dft_coef, dim3(Mi, 1), dim3(256), 0, s, Mi, sb, cs);
+  hipLaunchKernelGGL(k_anti, dim3((Mi + 255) / 256), dim3(256), 0, s, Mi, cs, anti);
+  hipLaunchKernelGGL(k_newton, dim3(M), dim3(256), 0, s, Mi, M, cxy, cs, anti, raw);
+  hipLaunchKernelGGL(k_unwrap, dim3(1), dim3(kTLThreads), 0, s, M, raw, cs, th->eta.as<double>(),
+                     th->scal.as<double>());
+  KFBI_HIP(hipMemsetAsync(th->phi.p, 0, sizeof(double) * M, s));
+  KFBI_HIP(hipMemsetAsync(th->nhat.p, 0, sizeof(double) * 2 * M, s));
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, s));
+  KFBI_HIP(hipStreamSynchronize(s));
+  if (!std::isfinite(th->hscal[S_L]) || !(th->hscal[S_L] > 0.0)) {
+    set_error("thetaL_init: the curve has no finite positive length");
+    return KFBI_E_NONFINITE;
+  }
+  th->n = 0;
+  th->have_phi = 0;
+  th->ready = 1;
+  return KFBI_OK;
+}
+
+int thetaL_markers(thetaL* th, double* xy) {
+  KFBI_TRY(tl_check(th, true));
+  if (!xy) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  const int M = th->M;
+  // the reconstruction kernel writes X straight into the caller's array
+  hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), th->stream, M,
+                     th->prm.sigma, th->prm.J, th->tw.as<double>(), th->eta.as<double>(),
+                     th->scal.as<double>(), xy, th->rhs.as<double>(), th->aux.as<double>(),
+                     th->etahat.as<double>());
+  KFBI_HIP(hipGetLastError());
+  return KFBI_OK;
+}
+
+int thetaL_density(const thetaL* th, double* phi) {
+  KFBI_TRY(tl_check(th, true));
+  if (!phi) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  KFBI_HIP(hipMemcpyAsync(phi, th->phi.p, sizeof(double) * th->M, hipMemcpyDeviceToDevice,
+                          th->stream));
+  return KFBI_OK;
+}
+
+int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
+  KFBI_TRY(tl_check(th, true));
+  const int M = th->M;
+  hipStream_t s = th->stream;
+  const thetaL_params& p = th->prm;
+  auto t0 = std::chrono::steady_clock::now();
+  hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), s, M, p.sigma, p.J,
+                     th->tw.as<double>(), th->eta.as<double>(), th->scal.as<double>(),
+                     th->X.as<double>(), th->rhs.as<double>(), th->aux.as<double>(),
+                     th->etahat.as<double>());
+  KFBI_HIP(hipGetLastError());
+  int st = kfbi_set_interface(th->kc, M, th->X.as<double>());
+  if (st != KFBI_OK) return st;
+  const double ms_geo = ms_since(t0);
+  // GMRES: initial guess = x0, else the previous density (zero before the first solve)
+  auto t1 = std::chrono::steady_clock::now();
+  const double* guess = x0 ? x0 : th->phi.as<double>();
+  KFBI_HIP(hipMemcpyAsync(th->phiw.p, guess, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+  const kfbi_bie op{KFBI_DOUBLE, KFBI_MINUS, 0.0, 1.0, 1.0};
+  kfbi_gmres_stats gs{};
+  st = kfbi_gmres_solve(th->kc, &op, th->rhs.as<double>(), th->phiw.as<double>(), &p.gmres, &gs);
+  if (st != KFBI_OK) return st;
+  const double ms_gm = ms_since(t1);
+  auto t2 = std::chrono::steady_clock::now();
+  kfbi_out o{nullptr, nullptr, th->dnp.as<double>(), th->dnm.as<double>(), nullptr};
+  st = kfbi_apply(th->kc, KFBI_DOUBLE, KFBI_FP64, th->phiw.as<double>(), nullptr, &o);
+  if (st != KFBI_OK) return st;
+  KFBI_HIP(hipStreamSynchronize(s));
+  const double ms_ap = ms_since(t2);
+  auto t3 = std::chrono::steady_clock::now();
+  const double lam2 = p.lambda2 < 0.0 ? p.sigma : p.lambda2;
+  hipLaunchKernelGGL(k_tl_post, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), s, M, p.J, p.tau,
+                     lam2, th->n == 0 ? 1 : 0, th->tw.as<double>(), th->X.as<double>(),
+                     th->aux.as<double>(), th->dnp.as<double>(), th->dnm.as<double>(),
+                     th->etahat.as<double>(), th->nhat.as<double>(), th->scal.as<double>(),
+                     th->eta.as<double>());
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipMemcpyAsync(th->phi.p, th->phiw.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+  KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, s));
+  KFBI_HIP(hipStreamSynchronize(s));
+  const double ms_up = ms_since(t3);
+  const int step = th->n;
+  th->n += 1;
+  th->have_phi = 1;
+  if (stats) {
+    stats->step = step;
+    stats->t = th->hscal[S_T];
+    stats->iters = gs.iters;
+    stats->applies64 = gs.applies64;
+    stats->applies32 = gs.applies32;
+    stats->relres = gs.relres;
+    stats->area = th->hscal[S_AREA];
+    stats->length = th->hscal[S_LEN];
+    stats->ms_geometry = ms_geo;
+    stats->ms_gmres = ms_gm;
+    stats->ms_apply = ms_ap;
+    stats->ms_update = ms_up;
+  }
+  if (th->hscal[S_BAD] != 0.0) {
+    set_error("thetaL_step: the new state is not finite (step %d)", step);
+    return KFBI_E_NONFINITE;
+  }
+  return KFBI_OK;
+}
+
+int thetaL_run(thetaL* th, int nsteps, thetaL_stats* stats) {
+  KFBI_TRY(tl_check(th, true));
+  if (nsteps < 0) {
+    set_error("nsteps < 0");
+    return KFBI_E_INVALID;
+  }
+  for (int i = 0; i < nsteps; ++i) KFBI_TRY(thetaL_step(th, nullptr, stats ? stats + i : nullptr));
+  return KFBI_OK;
+}
+
+int thetaL_get_state(const thetaL* th, thetaL_state* st) {
+  KFBI_TRY(tl_check(th, true));
+  if (!st || !st->eta_dev || !st->phi_prev_dev || !st->nhat_prev_dev) {
+    set_error("thetaL_get_state: null state array");
+    return KFBI_E_INVALID;
+  }
+  const int M = th->M;
+  hipStream_t s = th->stream;
+  KFBI_HIP(hipMemcpyAsync(st->eta_dev, th->eta.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+  KFBI_HIP(hipMemcpyAsync(st->phi_prev_dev, th->phi.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+  KFBI_HIP(hipMemcpyAsync(st->nhat_prev_dev, th->nhat.p, sizeof(double) * 2 * M,
+                          hipMemcpyDeviceToDevice, s));
+  KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, s));
+  KFBI_HIP(hipStreamSynchronize(s));
+  for (int q = 0; q < 8; ++q) st->scal[q] = th->hscal[q];
+  st->n = th->n;
+  return KFBI_OK;
+}
+
+int thetaL_set_state(thetaL* th, const thetaL_state* st) {
+  KFBI_TRY(tl_check(th, false));
+  if (!st || !st->eta_dev || !st->phi_prev_dev || !st->nhat_prev_dev || st->n < 0) {
+    set_error("thetaL_set_state: null state array or negative step count");
+    return KFBI_E_INVALID;
+  }
+  if (!(st->scal[S_L] > 0.0)) {
+    set_error("thetaL_set_state: L must be positive");
+    return KFBI_E_INVALID;
+  }
+  const int M = th->M;
+  hipStream_t s = th->stream;
+  KFBI_HIP(hipMemcpyAsync(th->eta.p, st->eta_dev, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+  KFBI_HIP(hipMemcpyAsync(th->phi.p, st->phi_prev_dev, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+  KFBI_HIP(hipMemcpyAsync(th->nhat.p, st->nhat_prev_dev, sizeof(double) * 2 * M,
+                          hipMemcpyDeviceToDevice, s));
+  for (int q = 0; q < S_COUNT; ++q) th->hscal[q] = (q < 8) ? st->scal[q] : 0.0;
+  KFBI_HIP(hipMemcpyAsync(th->scal.p, th->hscal, sizeof(double) * S_COUNT, hipMemcpyHostToDevice, s));
+  KFBI_HIP(hipStreamSynchronize(s));
+  th->n = st->n;
+  th->have_phi = 1;
+  th->ready = 1;
+  return KFBI_OK;
+}
+
+}  // extern "C"

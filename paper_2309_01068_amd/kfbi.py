@@ -25,6 +25,8 @@ EXPORTS = [
     "kfbi_last_error", "kfbi_create", "kfbi_destroy", "kfbi_set_interface", "kfbi_get_info",
     "kfbi_apply", "kfbi_operator", "kfbi_gmres_solve", "kfbi_profile", "kfbi_profile_read",
     "kfbi_profile_kernel",
+    "thetaL_create", "thetaL_destroy", "thetaL_init", "thetaL_step", "thetaL_run",
+    "thetaL_markers", "thetaL_density", "thetaL_kfbi", "thetaL_get_state", "thetaL_set_state",
 ]
 
 
@@ -69,6 +71,26 @@ class GmresStats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ThetaLParams(C.Structure):
+    _fields_ = [("grid", Grid), ("M", C.c_int), ("sigma", C.c_double), ("J", C.c_double),
+                ("tau", C.c_double), ("lambda2", C.c_double), ("gmres", GmresOpts)]
+
+
+class ThetaLStats(C.Structure):
+    _fields_ = [("step", C.c_int), ("t", C.c_double), ("iters", C.c_int), ("applies64", C.c_int),
+                ("applies32", C.c_int), ("relres", C.c_double), ("area", C.c_double),
+                ("length", C.c_double), ("ms_geometry", C.c_double), ("ms_gmres", C.c_double),
+                ("ms_apply", C.c_double), ("ms_update", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ThetaLState(C.Structure):
+    _fields_ = [("eta_dev", C.c_void_p), ("phi_prev_dev", C.c_void_p),
+                ("nhat_prev_dev", C.c_void_p), ("scal", C.c_double * 8), ("n", C.c_int)]
+
+
 _lib = None
 
 
@@ -93,6 +115,17 @@ def load(path: str = LIBPATH):
     lib.kfbi_profile.argtypes = [vp, C.c_int]
     lib.kfbi_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_long)]
     lib.kfbi_profile_kernel.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    lib.thetaL_create.argtypes = [C.POINTER(ThetaLParams), C.POINTER(vp)]
+    lib.thetaL_destroy.argtypes = [vp]
+    lib.thetaL_init.argtypes = [vp, C.c_int, vp]
+    lib.thetaL_step.argtypes = [vp, vp, C.POINTER(ThetaLStats)]
+    lib.thetaL_run.argtypes = [vp, C.c_int, C.POINTER(ThetaLStats)]
+    lib.thetaL_markers.argtypes = [vp, vp]
+    lib.thetaL_density.argtypes = [vp, vp]
+    lib.thetaL_kfbi.argtypes = [vp]
+    lib.thetaL_kfbi.restype = vp
+    lib.thetaL_get_state.argtypes = [vp, C.POINTER(ThetaLState)]
+    lib.thetaL_set_state.argtypes = [vp, C.POINTER(ThetaLState)]
     _lib = lib
     return lib
 
@@ -195,3 +228,71 @@ class Context:
             return x, st.as_dict()
         _check(code)
         return x, st.as_dict()
+
+
+class ThetaL:
+    """theta-L / SSD Hele-Shaw evolution (include/thetal.h) on the current torch stream."""
+
+    def __init__(self, x0, y0, side, N, M, sigma, J, tau, lambda2=-1.0, tol=1e-10, restart=50,
+                 maxit=1000, precision=FP64, inner_tol=1e-5, stream=None):
+        self.lib = load()
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.stream = s
+        g = Grid(x0, y0, side, N, 0.0, BOX_FREESPACE, M, C.c_void_p(s.cuda_stream))
+        p = ThetaLParams(g, M, sigma, J, tau, lambda2,
+                         GmresOpts(tol, restart, maxit, precision, inner_tol))
+        h = C.c_void_p()
+        _check(self.lib.thetaL_create(C.byref(p), C.byref(h)))
+        self.h = h
+        self.M = M
+
+    def close(self):
+        if self.h:
+            self.lib.thetaL_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, xy: torch.Tensor):
+        xy = xy.contiguous()
+        _check(self.lib.thetaL_init(self.h, xy.shape[1], _ptr(xy)))
+
+    def step(self, x0=None) -> dict:
+        st = ThetaLStats()
+        _check(self.lib.thetaL_step(self.h, _ptr(x0), C.byref(st)))
+        return st.as_dict()
+
+    def run(self, nsteps: int) -> list:
+        arr = (ThetaLStats * max(nsteps, 1))()
+        _check(self.lib.thetaL_run(self.h, nsteps, arr))
+        return [arr[i].as_dict() for i in range(nsteps)]
+
+    def markers(self) -> torch.Tensor:
+        xy = torch.empty((2, self.M), dtype=torch.float64, device="cuda")
+        _check(self.lib.thetaL_markers(self.h, _ptr(xy)))
+        return xy
+
+    def density(self) -> torch.Tensor:
+        phi = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        _check(self.lib.thetaL_density(self.h, _ptr(phi)))
+        return phi
+
+    def get_state(self) -> dict:
+        eta = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        phi = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        nh = torch.empty(2 * self.M, dtype=torch.float64, device="cuda")
+        st = ThetaLState(C.c_void_p(eta.data_ptr()), C.c_void_p(phi.data_ptr()),
+                         C.c_void_p(nh.data_ptr()))
+        _check(self.lib.thetaL_get_state(self.h, C.byref(st)))
+        return {"eta": eta, "phi_prev": phi, "nhat_prev": nh, "scal": list(st.scal), "n": st.n}
+
+    def set_state(self, d: dict):
+        st = ThetaLState(_ptr(d["eta"]), _ptr(d["phi_prev"]), _ptr(d["nhat_prev"]))
+        for i in range(8):
+            st.scal[i] = d["scal"][i]
+        st.n = d["n"]
+        _check(self.lib.thetaL_set_state(self.h, C.byref(st)))

@@ -1,0 +1,157 @@
+"""GPU theta-L / SSD Hele-Shaw evolution (include/thetal.h) against the CPU oracle.
+
+Tolerances: every spectral step is FP64 on both sides (1e-13 level); the pressure
+density comes from GMRES run to a 1e-10 relative residual on each side from the same
+initial guess, so the densities agree to about the conditioning of the second-kind
+equation times 1e-10 (tested at 1e-8 relative); the state moves by tau times quantities
+built from that density, so eta, L and Xbar agree to well below 1e-9.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import thetal as T
+from paper_2309_01068_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make(box, M, sigma, J, tau, precision=0):
+    from paper_2309_01068_amd import kfbi
+    return kfbi.ThetaL(box.x0, box.y0, box.side, box.N, M, sigma, J, tau, precision=precision)
+
+
+def oracle_state(X, M, box, sigma, J, tau):
+    eta, L, Xb = T.equal_arclength_init(X, M)
+    return T.HSState(eta, L, Xb), T.HSParams(sigma=sigma, J=J, tau=tau, box=box)
+
+
+@pytest.mark.parametrize("name,X,M", [("hs3_1024", W.hs3(1024), 1024),
+                                      ("pert_from_300", W.perturbed(300, 5), 256),
+                                      ("ellipse_up", W.ellipse(128), 512)])
+def test_equal_arclength_init_parity(name, X, M):
+    print(f"[case] init {name} M={M}", flush=True)
+    box = W.box(-2, 2, 128)
+    eta, L, Xb = T.equal_arclength_init(X, M)
+    th = make(box, M, 1e-3, 1.0, 1e-3)
+    th.init(dev(X))
+    st = th.get_state()
+    assert abs(st["scal"][0] - L) <= 1e-12 * L
+    assert np.max(np.abs(np.array(st["scal"][1:3]) - Xb)) <= 1e-12
+    assert np.max(np.abs(host(st["eta"]) - eta)) <= 1e-11
+    assert st["n"] == 0
+    # the reconstructed markers reproduce the oracle's reconstruction
+    Xr, *_ = T.reconstruct(eta, L, Xb)
+    assert np.max(np.abs(host(th.markers()) - Xr)) <= 1e-11
+
+
+def run_both(X, M, box, sigma, J, tau, nsteps, precision=0):
+    st, prm = oracle_state(X, M, box, sigma, J, tau)
+    th = make(box, M, sigma, J, tau, precision)
+    th.init(dev(X))
+    recs = []
+    for k in range(nsteps):
+        print(f"[case] step {k} N={box.N} M={M} prec={precision}", flush=True)
+        st, info = T.hs_step(st, prm)
+        g = th.step()
+        recs.append((info, g, host(th.density()), th.get_state()))
+    return st, th, recs
+
+
+def test_steps_parity_small():
+    box = W.box(-2, 2, 256)
+    st, th, recs = run_both(W.hs3(256), 256, box, 1e-3, 1.0, 1e-3, 5)
+    for info, g, phi, s in recs:
+        assert abs(g["area"] - info.area) <= 1e-12 * info.area
+        assert abs(g["length"] - info.length) <= 1e-13 * info.length
+        assert g["relres"] <= 1e-10
+        assert np.linalg.norm(phi - info.phi) <= 1e-8 * np.linalg.norm(info.phi)
+    s = recs[-1][3]
+    assert abs(s["scal"][0] - st.L) <= 1e-12 * st.L
+    assert np.max(np.abs(np.array(s["scal"][1:3]) - st.Xbar)) <= 1e-11
+    assert np.max(np.abs(host(s["eta"]) - st.eta)) <= 1e-10
+    assert abs(s["scal"][3] - st.t) <= 1e-15
+    assert s["n"] == 5
+
+
+def test_steps_parity_hele_shaw_full_size():
+    """The Hele-Shaw workload at full size: r = 1 + 0.1 cos 3a + 0.05 sin 5a, 1024 markers,
+    [-2,2]^2 with 1024^2 intervals, sigma = 1e-3, J = 1, tau = 1e-3; the Euler start and
+    one Adams-Bashforth step."""
+    box = W.box(-2, 2, 1024)
+    st, th, recs = run_both(W.hs3(1024), 1024, box, 1e-3, 1.0, 1e-3, 2)
+    for info, g, phi, s in recs:
+        assert abs(g["area"] - info.area) <= 1e-12 * info.area
+        assert np.linalg.norm(phi - info.phi) <= 1e-8 * np.linalg.norm(info.phi)
+    s = recs[-1][3]
+    assert abs(s["scal"][0] - st.L) <= 1e-12 * st.L
+    assert np.max(np.abs(host(s["eta"]) - st.eta)) <= 1e-10
+
+
+def test_fp32_inner_solve_gives_the_same_evolution():
+    box = W.box(-2, 2, 256)
+    X = W.hs3(256)
+    a = make(box, 256, 1e-3, 1.0, 1e-3, precision=0)
+    b = make(box, 256, 1e-3, 1.0, 1e-3, precision=1)
+    a.init(dev(X))
+    b.init(dev(X))
+    for _ in range(3):
+        ga, gb = a.step(), b.step()
+        assert gb["relres"] <= 1e-10 and gb["applies32"] > 0
+    sa, sb = a.get_state(), b.get_state()
+    assert np.max(np.abs(host(sa["eta"]) - host(sb["eta"]))) <= 1e-10
+    assert abs(sa["scal"][0] - sb["scal"][0]) <= 1e-12 * sa["scal"][0]
+
+
+def test_circle_grows_by_the_injection_law():
+    """With injection J a circle stays a circle of radius sqrt(R0^2 + 2 J t)."""
+    R0 = 0.5
+    box = W.box(-1.5, 1.5, 128)
+    th = make(box, 64, 1e-3, 1.0, 2e-3)
+    th.init(dev(W.circle(64, R0)))
+    recs = th.run(10)
+    s = th.get_state()
+    R = s["scal"][0] / (2 * np.pi)
+    assert abs(R - np.sqrt(R0 ** 2 + 2 * s["scal"][3])) < 2e-5
+    assert np.max(np.abs(s["scal"][1:3])) < 1e-8
+    assert np.std(host(s["eta"])) < 1e-8
+    assert [r["step"] for r in recs] == list(range(10))
+
+
+def test_checkpoint_restart_is_bitwise():
+    box = W.box(-2, 2, 128)
+    th = make(box, 128, 1e-3, 1.0, 1e-3)
+    th.init(dev(W.hs3(128)))
+    th.run(3)
+    ck = th.get_state()
+    ck = {k: (v.clone() if torch.is_tensor(v) else v) for k, v in ck.items()}
+    th.run(2)
+    a = th.get_state()
+    th.set_state(ck)
+    th.run(2)
+    b = th.get_state()
+    assert torch.equal(a["eta"], b["eta"]) and a["scal"] == b["scal"] and a["n"] == b["n"] == 5
+
+
+def test_errors():
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-2, 2, 128)
+    with pytest.raises(kfbi.KfbiError) as e:
+        make(box, 100, 1e-3, 1.0, 1e-3)                      # M not a power of two
+    assert e.value.code == kfbi.E_INVALID
+    th = make(box, 64, 1e-3, 1.0, 1e-3)
+    with pytest.raises(kfbi.KfbiError) as e:
+        th.step()                                            # before init
+    assert e.value.code == kfbi.E_STATE
+    with pytest.raises(kfbi.KfbiError) as e:
+        th.init(dev(W.circle(64, 1.95)))                     # init fine, but too close to the box
+        th.step()
+    assert e.value.code == kfbi.E_GEOMETRY
