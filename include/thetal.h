@@ -68,6 +68,7 @@ typedef struct {
 typedef struct {
   double* eta_dev;       /* [M] eta = theta - alpha                                      */
   double* phi_prev_dev;  /* [M] density of the last solve (next initial guess)            */
+  double* phi_prev2_dev; /* [M] density of the solve before it (zero if none)              */
   double* nhat_prev_dev; /* [2M] DFT of the last explicit term, (re, im) interleaved      */
   double scal[8];        /* L, Xbar_x, Xbar_y, t, L_prev, M_prev, Qbar_prev_x, Qbar_prev_y */
   int n;                 /* steps taken                                                  */

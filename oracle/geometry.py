@@ -9,11 +9,17 @@ inside/outside; the readings used (identical on the GPU side, written independen
 * markers X_k at a_k = 2 pi k/M, counter-clockwise, outward normal (y_a, -x_a)/s_a (App. A);
 * between markers, every marker quantity is interpolated by the 6-point Lagrange
   polynomial through markers k-2..k+3 in the local variable t = (a - a_k)/da in [0, 1];
-* a marker interval crosses the line y = y_j iff (y_k >= y_j) != (y_{k+1} >= y_j); the
-  crossing parameter solves y_P(t) = y_j by safeguarded Newton (bisection fallback);
-* node (i, j) lies in Omega+ iff the number of row-j crossings with xi < x_i is odd;
-* every marker must stay 3h away from the box boundary; a grid segment holding two
-  crossings, or a label change without a crossing, is a geometry error;
+* crossings are searched on the interpolant sampled at t = s/8, s = 0..8, of each marker
+  interval (marker values at the ends): sub-interval s crosses y = y_j iff
+  (y(t_s) >= y_j) != (y(t_{s+1}) >= y_j), so a curve nearly tangent to a line between
+  two markers shows both of its crossings; the crossing parameter solves y_P(t) = y_j on
+  the sub-interval by safeguarded Newton (bisection fallback);
+* a grid segment cut exactly twice is treated as not cut (the grid does not resolve the
+  bump between the two crossings; both are dropped); three or more crossings in one
+  segment are a geometry error;
+* node (i, j) lies in Omega+ iff the number of kept row-j crossings with xi < x_i is odd;
+* every marker must stay 3h away from the box boundary; a label change without a
+  crossing is a geometry error;
 * a column crossing within 1e-9 h of a grid node may move to the adjacent column
   segment so that it sits where the row-based labels change (the interface passes
   through that node up to rounding).
@@ -109,16 +115,17 @@ def grid_coord(lo: float, h: float, i):
     return lo + np.asarray(i, dtype=np.float64) * h
 
 
-def _newton_root(c: np.ndarray, target: np.ndarray, a: np.ndarray, b: np.ndarray):
-    """Solve P(t) = target on [0, 1] where P is the Lagrange polynomial with nodal
-    values c (shape (K, 6)); a = P(0) - target, b = P(1) - target have opposite
-    signs under the rule sign(v) = (v >= 0).  Safeguarded Newton: start from the
-    secant point, keep a bracket, bisect whenever Newton leaves it; stop when the
+def _newton_root(c: np.ndarray, target: np.ndarray, a: np.ndarray, b: np.ndarray,
+                 ta: np.ndarray | None = None, tb: np.ndarray | None = None):
+    """Solve P(t) = target on [ta, tb] (default [0, 1]) where P is the Lagrange
+    polynomial with nodal values c (shape (K, 6)); a = P(ta) - target, b = P(tb) - target
+    have opposite signs under the rule sign(v) = (v >= 0).  Safeguarded Newton: start
+    from the secant point, keep a bracket, bisect whenever Newton leaves it; stop when the
     update is below 1e-12 (in t) or after 60 iterations."""
     K = c.shape[0]
-    t = a / (a - b)
-    lo = np.zeros(K)
-    hi = np.ones(K)
+    lo = np.zeros(K) if ta is None else np.array(ta, dtype=np.float64)
+    hi = np.ones(K) if tb is None else np.array(tb, dtype=np.float64)
+    t = lo + (hi - lo) * (a / (a - b))
     sa = a >= 0.0
     done = np.zeros(K, dtype=bool)
     for _ in range(60):
@@ -141,6 +148,12 @@ def _newton_root(c: np.ndarray, target: np.ndarray, a: np.ndarray, b: np.ndarray
     return t
 
 
+# Sub-intervals per marker interval in the crossing search: the interpolant is sampled at
+# t = s / SUB so that a line crossed twice between two markers (the curve nearly tangent
+# to it) is found.
+SUB = 8
+
+
 @dataclass
 class Crossings:
     """Intersections of the interface with grid lines."""
@@ -149,35 +162,47 @@ class Crossings:
     t: np.ndarray          # local parameter in [0, 1]
     pos: np.ndarray        # x-coordinate (horizontal lines) or y-coordinate (vertical)
     seg: np.ndarray        # grid segment index: node index m with g_m <= pos < g_{m+1}
+    keep: np.ndarray | None = None  # False for the two crossings of a segment cut twice
 
 
 def find_crossings(mk: Markers, lo: float, h: float, N: int, axis: int) -> Crossings:
     """Crossings with lines y = y_j (axis=1: the varying coordinate is y) or x = x_i
-    (axis=0), lines 1..N-1 (Sec. 4.2: intersection point (xi, y_j))."""
+    (axis=0), lines 1..N-1 (Sec. 4.2: intersection point (xi, y_j)).  Within marker
+    interval k the coordinate follows the 6-point Lagrange polynomial through markers
+    k-2..k+3; it is sampled at t = s/SUB (the marker values themselves at t = 0, 1) and a
+    line g is crossed in sub-interval s iff (v(t_s) >= g) != (v(t_{s+1}) >= g)."""
     M = mk.M
     v = mk.X[axis]                 # coordinate compared with the line
     other = mk.X[1 - axis]
-    k = np.arange(M)
-    v0, v1 = v, np.roll(v, -1)
-    vmin, vmax = np.minimum(v0, v1), np.maximum(v0, v1)
-    # lines g_j with vmin < g_j <= vmax  <=>  (v0 >= g) != (v1 >= g)
-    jl = np.floor((vmin - lo) / h).astype(np.int64) - 1
-    jh = np.floor((vmax - lo) / h).astype(np.int64) + 1
-    ks, js = [], []
+    kk_all = np.arange(M)
+    cv = v[stencil_markers(kk_all, M)]                   # (M, 6)
+    ts = np.arange(SUB + 1, dtype=np.float64) / SUB
+    Wt, _ = lagrange6(ts)                                # (SUB+1, 6)
+    vals = np.zeros((M, SUB + 1))
+    for m in range(6):
+        vals = vals + cv[:, m:m + 1] * Wt[None, :, m]
+    vals[:, 0] = v
+    vals[:, SUB] = np.roll(v, -1)
+    jl = np.floor((vals.min(axis=1) - lo) / h).astype(np.int64) - 1
+    jh = np.floor((vals.max(axis=1) - lo) / h).astype(np.int64) + 1
+    ks, js, ss = [], [], []
     for kk in range(M):
         for j in range(max(jl[kk], 1), min(jh[kk], N - 1) + 1):
-            g = lo + j * h
-            if (v0[kk] >= g) != (v1[kk] >= g):
+            above = vals[kk] >= lo + j * h
+            for sidx in np.nonzero(above[:-1] != above[1:])[0]:
                 ks.append(kk)
                 js.append(j)
+                ss.append(int(sidx))
     ks = np.array(ks, dtype=np.int64)
     js = np.array(js, dtype=np.int64)
+    ss = np.array(ss, dtype=np.int64)
     if ks.size == 0:
-        return Crossings(js, ks, np.zeros(0), np.zeros(0), js.copy())
+        z = np.zeros(0)
+        return Crossings(js, ks, z, z.copy(), js.copy(), np.ones(0, dtype=bool))
     g = lo + js * h
     idx = stencil_markers(ks, M)
     c = v[idx]
-    t = _newton_root(c, g, v0[ks] - g, v1[ks] - g)
+    t = _newton_root(c, g, vals[ks, ss] - g, vals[ks, ss + 1] - g, ts[ss], ts[ss + 1])
     w, _ = lagrange6(t)
     pos = np.sum(w * other[idx], axis=1)
     seg = np.floor((pos - lo) / h).astype(np.int64)
@@ -185,7 +210,21 @@ def find_crossings(mk: Markers, lo: float, h: float, N: int, axis: int) -> Cross
     for _ in range(2):
         seg = np.where(lo + (seg + 1) * h <= pos, seg + 1, seg)
         seg = np.where(lo + seg * h > pos, seg - 1, seg)
-    return Crossings(js, ks, t, pos, seg)
+    return Crossings(js, ks, t, pos, seg, np.ones(ks.size, dtype=bool))
+
+
+def _pair_out(cr: Crossings, N: int):
+    """A grid segment cut twice is treated as not cut (the grid does not resolve the
+    bump between the two crossings): both crossings are dropped.  Three or more
+    crossings in one segment are a geometry error."""
+    if cr.line.size == 0:
+        return
+    key = cr.line * (N + 1) + cr.seg
+    _, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+    c = cnt[inv]
+    if np.any(c > 2):
+        raise GeometryError("a grid segment holds more than two interface crossings")
+    cr.keep = c == 1
 
 
 @dataclass
@@ -208,10 +247,14 @@ def build_geometry(X: np.ndarray, box) -> Geometry:
         raise GeometryError("interface closer than 3h to the box boundary")
     hx = find_crossings(mk, y0, h, N, axis=1)
     vx = find_crossings(mk, x0, h, N, axis=0)
+    if np.any((hx.seg < 0) | (hx.seg >= N)) or np.any((vx.seg < 0) | (vx.seg >= N)):
+        raise GeometryError("crossing outside the grid")
+    _pair_out(hx, N)
+    _pair_out(vx, N)
     xi = grid_coord(x0, h, np.arange(N + 1))
     inside = np.zeros((N + 1, N + 1), dtype=bool)
     for j in range(1, N):
-        sel = hx.line == j
+        sel = (hx.line == j) & hx.keep
         xs = np.sort(hx.pos[sel])
         cnt = np.searchsorted(xs, xi, side="left")     # #{xi_c < x_i}
         inside[j] = (cnt % 2) == 1
@@ -238,6 +281,10 @@ def _snap_vertical(g: Geometry):
 
         def flips(t):
             return 0 <= t <= N - 1 and lab[t, i] != lab[t + 1, i]
+        if not g.vx.keep[c]:          # one of a pair: the segment must not change label
+            if flips(s):
+                raise GeometryError("vertical labels and crossings disagree")
+            continue
         if flips(s):
             continue
         if eta - (y0 + s * h) <= tol and flips(s - 1):
@@ -252,33 +299,32 @@ def _snap_vertical(g: Geometry):
 def _check_and_build_arms(g: Geometry):
     N = g.box.N
     lab = g.inside
-    if np.any((g.hx.seg < 0) | (g.hx.seg >= N)) or np.any((g.vx.seg < 0) | (g.vx.seg >= N)):
-        raise GeometryError("crossing outside the grid")
     _snap_vertical(g)
-    # horizontal segments: (i, j)-(i+1, j); crossings keyed by (j, seg)
-    hkey = g.hx.line * (N + 1) + g.hx.seg
-    vkey = g.vx.line * (N + 1) + g.vx.seg
+    hk, vk = g.hx.keep, g.vx.keep
+    # horizontal segments: (i, j)-(i+1, j); kept crossings keyed by (j, seg)
+    hkey = g.hx.line[hk] * (N + 1) + g.hx.seg[hk]
+    vkey = g.vx.line[vk] * (N + 1) + g.vx.seg[vk]
     if np.unique(hkey).size != hkey.size or np.unique(vkey).size != vkey.size:
         raise GeometryError("a grid segment holds two interface crossings")
     # label changes along rows <-> horizontal crossings
     dh = lab[:, 1:] != lab[:, :-1]          # [j, i] segment (i, i+1)
     dv = lab[1:, :] != lab[:-1, :]          # [j, i] segment (j, j+1) on column i
     hset = np.zeros_like(dh)
-    hset[g.hx.line, g.hx.seg] = True
+    hset[g.hx.line[hk], g.hx.seg[hk]] = True
     vset = np.zeros_like(dv)
-    vset[g.vx.seg, g.vx.line] = True
+    vset[g.vx.seg[vk], g.vx.line[vk]] = True
     if not np.array_equal(dh, hset):
         raise GeometryError("horizontal labels and crossings disagree")
     if not np.array_equal(dv, vset):
         raise GeometryError("vertical labels and crossings disagree")
     # irregular arms P -> Q, P interior: list of (iP, jP, iQ, jQ, crossing id, horizontal?)
     arms = []
-    for c in range(g.hx.line.size):
+    for c in np.nonzero(hk)[0]:
         j, s = int(g.hx.line[c]), int(g.hx.seg[c])
         for (ip, iq) in ((s, s + 1), (s + 1, s)):
             if 1 <= ip <= N - 1:
                 arms.append((ip, j, iq, j, c, 1))
-    for c in range(g.vx.line.size):
+    for c in np.nonzero(vk)[0]:
         i, s = int(g.vx.line[c]), int(g.vx.seg[c])
         for (jp, jq) in ((s, s + 1), (s + 1, s)):
             if 1 <= jp <= N - 1:

@@ -65,7 +65,7 @@ static int check_ctx(const kfbi_ctx* c, bool need_iface) {
 }
 
 static void release_all(kfbi_ctx* c) {
-  DBuf* bufs[] = {&c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
+  DBuf* bufs[] = {&c->vraw, &c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
                   &c->vid,    &c->lab,    &c->armcnt, &c->rowsum,  &c->armrow, &c->armpk,
                   &c->armc,   &c->armk,   &c->colc,   &c->lanef,   &c->cnode,  &c->ccount,
                   &c->mkloc,  &c->tmat,   &c->pdesc,  &c->rowpart,
@@ -145,6 +145,7 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
   const int Mx = g->max_markers;
   if ((st = c->gstat.ensure(sizeof(GeoStatus))) ||
       (st = c->hid.ensure(sizeof(int) * n1sq)) || (st = c->vid.ensure(sizeof(int) * n1sq)) ||
+      (st = c->vraw.ensure(sizeof(int) * n1sq)) ||
       (st = c->lab.ensure(n1sq)) || (st = c->need.ensure(sizeof(int) * n1sq)) ||
       (st = c->nodeidx.ensure(sizeof(int) * n1sq)) ||
       (st = c->rowsum.ensure(sizeof(int) * (2 * (N + 1) + 2))) ||

@@ -104,7 +104,7 @@ struct kfbi_ctx {
   int d_M = 0;  // M for which the differentiation vectors are built
 
   // geometry buffers
-  kfbi::DBuf X, geo, dvec, cnt, cross, hid, vid, lab, armcnt, rowsum, armrow, armpk, armcoef,
+  kfbi::DBuf X, geo, dvec, cnt, cross, hid, vid, vraw, lab, armcnt, rowsum, armrow, armpk, armcoef,
       intptr, need, nodeidx, nodei, rowptr, rows, mknode, ext, gstat, armc, armk,
       colc, lanef, cnode, ccount, mkloc, tmat, pdesc, rowpart;
   int arm_cap = 0;

@@ -6,10 +6,11 @@
 // derivatives of periodic interface quantities in Fourier space.
 //
 // Readings fixed here (the paper leaves them open): interface quantities between markers
-// come from the 6-point Lagrange polynomial through markers k-2..k+3; a marker interval
-// crosses the line g iff (v_k >= g) != (v_{k+1} >= g); the crossing is the root of the
-// Lagrange polynomial found by safeguarded Newton; node (i, j) is inside iff an odd number
-// of row-j crossings lie strictly left of x_i; closest node = floor(t + 1/2).
+// come from the 6-point Lagrange polynomial through markers k-2..k+3; crossings are
+// searched on that polynomial sampled at t = s/8 of each marker interval (sign rule
+// (v >= g) per sub-interval) and located by safeguarded Newton; a grid segment cut twice
+// is treated as not cut, three times is an error; node (i, j) is inside iff an odd number
+// of kept row-j crossings lie strictly left of x_i; closest node = floor(t + 1/2).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -68,31 +69,67 @@ __global__ void k_marker_geo(int M, const double* __restrict__ X, const double* 
   if (!(x[k] >= lox && x[k] <= hix && y[k] >= loy && y[k] <= hiy)) atomicMax(&st->err, 3);
 }
 
-// Lines g_j = lo + j h, j = 1..N-1, crossed by the marker interval (v0, v1).
-__device__ inline void line_range(double v0, double v1, double lo, double h, int N, int* jb,
+// Crossing search on the 6-point Lagrange interpolant of one marker interval sampled at
+// t = s / kSub, s = 0..kSub (the marker values themselves at t = 0 and 1): sub-interval s
+// crosses the line g iff (v(t_s) >= g) != (v(t_{s+1}) >= g).  A curve nearly tangent to a
+// line between two markers thereby shows both of its crossings.
+constexpr int kSub = 8;
+
+__device__ inline void sub_values(const double* cv, double* vals) {
+  vals[0] = cv[2];
+  vals[kSub] = cv[3];
+#pragma unroll
+  for (int s = 1; s < kSub; ++s) {
+    double w[6];
+    lagrange6(static_cast<double>(s) / kSub, w, nullptr);
+    double v = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) v += cv[m] * w[m];
+    vals[s] = v;
+  }
+}
+
+// Lines g_j = lo + j h, j = 1..N-1, that the sampled values can cross.
+__device__ inline void line_range(const double* vals, double lo, double h, int N, int* jb,
                                   int* je) {
-  const double vmin = fmin(v0, v1), vmax = fmax(v0, v1);
+  double vmin = vals[0], vmax = vals[0];
+#pragma unroll
+  for (int s = 1; s <= kSub; ++s) {
+    vmin = fmin(vmin, vals[s]);
+    vmax = fmax(vmax, vals[s]);
+  }
   int a = static_cast<int>(floor((vmin - lo) / h)) - 1;
   int b = static_cast<int>(floor((vmax - lo) / h)) + 1;
   *jb = a < 1 ? 1 : a;
   *je = b > N - 1 ? N - 1 : b;
 }
 
+__device__ inline void stencil_values(const double* v, int k, int M, double* cv) {
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    int q = k - 2 + m;
+    q = (q < 0) ? q + M : (q >= M ? q - M : q);
+    cv[m] = v[q];
+  }
+}
+
 __global__ void k_count_cross(int M, const double* __restrict__ X, double x0, double y0, double h,
                               int N, int* __restrict__ cnt) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
-  const int k1 = (k + 1 == M) ? 0 : k + 1;
   for (int ax = 0; ax < 2; ++ax) {
     // ax = 0: rows y = y_j (compare y); ax = 1: columns x = x_i (compare x)
     const double* v = (ax == 0) ? X + M : X;
     const double lo = (ax == 0) ? y0 : x0;
-    const double v0 = v[k], v1 = v[k1];
+    double cv[6], vals[kSub + 1];
+    stencil_values(v, k, M, cv);
+    sub_values(cv, vals);
     int jb, je, c = 0;
-    line_range(v0, v1, lo, h, N, &jb, &je);
+    line_range(vals, lo, h, N, &jb, &je);
     for (int j = jb; j <= je; ++j) {
       const double g = lo + j * h;
-      c += ((v0 >= g) != (v1 >= g)) ? 1 : 0;
+#pragma unroll
+      for (int s = 0; s < kSub; ++s) c += ((vals[s] >= g) != (vals[s + 1] >= g)) ? 1 : 0;
     }
     cnt[ax * M + k] = c;
   }
@@ -117,10 +154,12 @@ __global__ void k_scan_inplace(int n, int* __restrict__ a, int* __restrict__ tot
   if (threadIdx.x == 0 && total) *total = tot;
 }
 
-// Safeguarded Newton for P(t) = g on [0, 1], P the Lagrange polynomial with nodal values c.
-__device__ inline double newton_root(const double* c, double g, double a, double b) {
-  double t = a / (a - b);
-  double lo = 0.0, hi = 1.0;
+// Safeguarded Newton for P(t) = g on [ta, tb], P the Lagrange polynomial with nodal values
+// c; a = P(ta) - g and b = P(tb) - g differ in sign under sign(v) = (v >= 0).
+__device__ inline double newton_root(const double* c, double g, double a, double b, double ta,
+                                     double tb) {
+  double lo = ta, hi = tb;
+  double t = ta + (tb - ta) * (a / (a - b));
   const bool sa = (a >= 0.0);
   for (int it = 0; it < 60; ++it) {
     double w[6], dw[6];
@@ -151,53 +190,61 @@ __global__ void k_fill_cross(int M, const double* __restrict__ X, double x0, dou
                              int cap, GeoStatus* st) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
-  const int k1 = (k + 1 == M) ? 0 : k + 1;
   for (int ax = 0; ax < 2; ++ax) {
     const double* v = (ax == 0) ? X + M : X;
     const double* o = (ax == 0) ? X : X + M;
     const double lo = (ax == 0) ? y0 : x0;
     const double olo = (ax == 0) ? x0 : y0;
-    const double v0 = v[k], v1 = v[k1];
-    double cv[6], co[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      int q = k - 2 + m;
-      q = (q < 0) ? q + M : (q >= M ? q - M : q);
-      cv[m] = v[q];
-      co[m] = o[q];
-    }
+    double cv[6], co[6], vals[kSub + 1];
+    stencil_values(v, k, M, cv);
+    stencil_values(o, k, M, co);
+    sub_values(cv, vals);
     int jb, je;
-    line_range(v0, v1, lo, h, N, &jb, &je);
+    line_range(vals, lo, h, N, &jb, &je);
     int slot = off[ax * M + k] + (ax == 0 ? 0 : nh);
     for (int j = jb; j <= je; ++j) {
       const double g = lo + j * h;
-      if ((v0 >= g) == (v1 >= g)) continue;
-      const double t = newton_root(cv, g, v0 - g, v1 - g);
-      double w[6];
-      lagrange6(t, w, nullptr);
-      double pos = 0.0;
+      for (int sb = 0; sb < kSub; ++sb) {
+        if ((vals[sb] >= g) == (vals[sb + 1] >= g)) continue;
+        const double t = newton_root(cv, g, vals[sb] - g, vals[sb + 1] - g,
+                                     static_cast<double>(sb) / kSub,
+                                     static_cast<double>(sb + 1) / kSub);
+        double w[6];
+        lagrange6(t, w, nullptr);
+        double pos = 0.0;
 #pragma unroll
-      for (int m = 0; m < 6; ++m) pos += w[m] * co[m];
-      int seg = static_cast<int>(floor((pos - olo) / h));
-      for (int r = 0; r < 2; ++r) {
-        if (olo + (seg + 1) * h <= pos) seg += 1;
-        if (olo + seg * h > pos) seg -= 1;
+        for (int m = 0; m < 6; ++m) pos += w[m] * co[m];
+        int seg = static_cast<int>(floor((pos - olo) / h));
+        for (int r = 0; r < 2; ++r) {
+          if (olo + (seg + 1) * h <= pos) seg += 1;
+          if (olo + seg * h > pos) seg -= 1;
+        }
+        if (slot < cap) {
+          Crossing c;
+          c.line = j;
+          c.k = k;
+          c.seg = seg;
+          c.horiz = (ax == 0);
+          c.t = t;
+          c.pos = pos;
+          cr[slot] = c;
+        } else {
+          atomicMax(&st->err, 4);
+        }
+        ++slot;
       }
-      if (slot < cap) {
-        Crossing c;
-        c.line = j;
-        c.k = k;
-        c.seg = seg;
-        c.horiz = (ax == 0);
-        c.t = t;
-        c.pos = pos;
-        cr[slot] = c;
-      } else {
-        atomicMax(&st->err, 4);
-      }
-      ++slot;
     }
   }
+}
+
+// Segment marking with pairs dropped: the first crossing of a segment stores its id, a
+// second one turns the entry into -2 (segment cut twice: treated as not cut), a third is
+// a geometry error (1).
+__device__ inline void mark_segment(int* slot, int c, GeoStatus* st) {
+  const int prev = atomicCAS(slot, -1, c);
+  if (prev == -1) return;
+  const int old = atomicExch(slot, -2);
+  if (old < 0) atomicMax(&st->err, 1);
 }
 
 // Mark row segments: hid[j*(N+1)+i] = crossing on row segment (i, i+1) of row j.
@@ -210,8 +257,20 @@ __global__ void k_mark_h(int nh, const Crossing* __restrict__ cr, int N, int* __
     atomicMax(&st->err, 5);
     return;
   }
-  const int old = atomicExch(&hid[x.line * (N + 1) + x.seg], c);
-  if (old != -1) atomicMax(&st->err, 1);
+  mark_segment(&hid[x.line * (N + 1) + x.seg], c, st);
+}
+
+// Raw column segments of the column crossings (pairs marked -2 as for rows).
+__global__ void k_pair_v(int nh, int nv, const Crossing* __restrict__ cr, int N,
+                         int* __restrict__ vraw, GeoStatus* st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nv) return;
+  const Crossing x = cr[nh + c];
+  if (x.seg < 0 || x.seg > N - 1) {
+    atomicMax(&st->err, 5);
+    return;
+  }
+  mark_segment(&vraw[x.seg * (N + 1) + x.line], nh + c, st);
 }
 
 // Mark column segments after the labels exist: vid[j*(N+1)+i] = crossing on column i
@@ -219,8 +278,8 @@ __global__ void k_mark_h(int nh, const Crossing* __restrict__ cr, int N, int* __
 // neighbouring segment when only that one changes label (interface through a node up
 // to rounding); a crossing with no label change nearby is a geometry error.
 __global__ void k_mark_v(int nh, int nv, const Crossing* __restrict__ cr, int N, double y0,
-                         double h, const int8_t* __restrict__ lab, int* __restrict__ vid,
-                         GeoStatus* st) {
+                         double h, const int8_t* __restrict__ lab, const int* __restrict__ vraw,
+                         int* __restrict__ vid, GeoStatus* st) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nv) return;
   const Crossing x = cr[nh + c];
@@ -231,6 +290,10 @@ __global__ void k_mark_v(int nh, int nv, const Crossing* __restrict__ cr, int N,
   }
   const double tol = 1e-9 * h;
   auto flips = [&](int t) { return t >= 0 && t <= N - 1 && lab[t * n1 + i] != lab[(t + 1) * n1 + i]; };
+  if (vraw[s * n1 + i] == -2) {  // one of a pair: the segment must not change label
+    if (flips(s)) atomicMax(&st->err, 2);
+    return;
+  }
   int seg;
   if (flips(s))
     seg = s;
@@ -698,13 +761,17 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   int* vid = c->vid.as<int>();
   KFBI_HIP(hipMemsetAsync(hid, 0xff, sizeof(int) * n1 * n1, s));
   KFBI_HIP(hipMemsetAsync(vid, 0xff, sizeof(int) * n1 * n1, s));
+  int* vraw = c->vraw.as<int>();
+  KFBI_HIP(hipMemsetAsync(vraw, 0xff, sizeof(int) * n1 * n1, s));
   if (nh > 0)
     hipLaunchKernelGGL(k_mark_h, dim3(nblk(nh, 256)), dim3(256), 0, s, nh, cr, N, hid, st);
   int8_t* lab = c->lab.as<int8_t>();
   hipLaunchKernelGGL(k_label, dim3(n1), dim3(256), 0, s, N, hid, lab);
-  if (nv > 0)
+  if (nv > 0) {
+    hipLaunchKernelGGL(k_pair_v, dim3(nblk(nv, 256)), dim3(256), 0, s, nh, nv, cr, N, vraw, st);
     hipLaunchKernelGGL(k_mark_v, dim3(nblk(nv, 256)), dim3(256), 0, s, nh, nv, cr, N, c->y0, h,
-                       lab, vid, st);
+                       lab, vraw, vid, st);
+  }
   // arms
   int* rowoff = c->armrow.as<int>();  // N+2 entries
   KFBI_HIP(hipMemsetAsync(rowoff, 0, sizeof(int) * (N + 2), s));

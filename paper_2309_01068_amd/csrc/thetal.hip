@@ -13,21 +13,15 @@
 #include <cmath>
 #include <new>
 
-#include "../../include/thetal.h"
 #include "common.h"
 #include "device_util.h"
+#include "thetal_internal.h"
 
 namespace kfbi {
 namespace {
 
-constexpr int kTLThreads = 1024;
-constexpr int kTLMaxM = 2048;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
-// scal[] slots (device)
-enum { S_L = 0, S_XBX, S_XBY, S_T, S_LPREV, S_MPREV, S_QPX, S_QPY, S_AREA, S_LEN, S_BAD, S_COUNT };
-// aux[] planes of M doubles (device)
-enum { A_THA = 0, A_HETA, A_NX, A_NY, A_R2, A_U, A_COUNT };
 
 __device__ __forceinline__ int wavenum(int q, int M) {  // signed wavenumber, Nyquist -> 0
   const int h = M >> 1;
@@ -522,19 +516,19 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 }  // namespace
 }  // namespace kfbi
 
-struct thetaL {
-  thetaL_params prm{};
-  kfbi_ctx* kc = nullptr;
-  hipStream_t stream = nullptr;
-  int M = 0;
-  int n = 0;           // steps taken
-  int ready = 0;       // thetaL_init or set_state done
-  int have_phi = 0;    // phi_prev holds a density
-  kfbi::DBuf tw, eta, scal, X, rhs, aux, etahat, nhat, phi, phiw, dnp, dnm, init;
-  double* hscal = nullptr;  // pinned copy of scal
-};
-
 using namespace kfbi;
+
+namespace kfbi {
+int thetal_refresh(thetaL* th) {
+  const int M = th->M;
+  hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), th->stream, M,
+                     th->prm.sigma, th->prm.J, th->tw.as<double>(), th->eta.as<double>(),
+                     th->scal.as<double>(), th->X.as<double>(), th->rhs.as<double>(),
+                     th->aux.as<double>(), th->etahat.as<double>());
+  KFBI_HIP(hipGetLastError());
+  return KFBI_OK;
+}
+}  // namespace kfbi
 
 static int tl_check(const thetaL* th, bool need_ready) {
   if (!th) {
@@ -550,7 +544,7 @@ static int tl_check(const thetaL* th, bool need_ready) {
 
 static void tl_free(thetaL* th) {
   for (DBuf* b : {&th->tw, &th->eta, &th->scal, &th->X, &th->rhs, &th->aux, &th->etahat, &th->nhat,
-                  &th->phi, &th->phiw, &th->dnp, &th->dnm, &th->init})
+                  &th->phi, &th->phi2, &th->phiw, &th->dnp, &th->dnm, &th->init})
     b->release();
   if (th->hscal) (void)hipHostFree(th->hscal);
   th->hscal = nullptr;
@@ -601,7 +595,8 @@ int thetaL_create(const thetaL_params* p, thetaL** out) {
       (st = th->aux.ensure(sizeof(double) * A_COUNT * M)) ||
       (st = th->etahat.ensure(sizeof(double) * 2 * M)) ||
       (st = th->nhat.ensure(sizeof(double) * 2 * M)) ||
-      (st = th->phi.ensure(sizeof(double) * M)) || (st = th->phiw.ensure(sizeof(double) * M)) ||
+      (st = th->phi.ensure(sizeof(double) * M)) || (st = th->phi2.ensure(sizeof(double) * M)) ||
+      (st = th->phiw.ensure(sizeof(double) * M)) ||
       (st = th->dnp.ensure(sizeof(double) * M)) || (st = th->dnm.ensure(sizeof(double) * M)) ||
       (st = th->init.ensure(sizeof(double) * (2 * Mi + 4 * Mi + 2 * Mi + 2 * Mi + Mi + 3 * M)))) {
     tl_free(th);
@@ -667,6 +662,7 @@ int thetaL_init(thetaL* th, int Mi, const double* xy) {
   hipLaunchKernelGGL(k_unwrap, dim3(1), dim3(kTLThreads), 0, s, M, raw, cs, th->eta.as<double>(),
                      th->scal.as<double>());
   KFBI_HIP(hipMemsetAsync(th->phi.p, 0, sizeof(double) * M, s));
+  KFBI_HIP(hipMemsetAsync(th->phi2.p, 0, sizeof(double) * M, s));
   KFBI_HIP(hipMemsetAsync(th->nhat.p, 0, sizeof(double) * 2 * M, s));
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, s));
@@ -745,6 +741,7 @@ int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
                      th->etahat.as<double>(), th->nhat.as<double>(), th->scal.as<double>(),
                      th->eta.as<double>());
   KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipMemcpyAsync(th->phi2.p, th->phi.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
   KFBI_HIP(hipMemcpyAsync(th->phi.p, th->phiw.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
   KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, s));
   KFBI_HIP(hipStreamSynchronize(s));
@@ -785,7 +782,7 @@ int thetaL_run(thetaL* th, int nsteps, thetaL_stats* stats) {
 
 int thetaL_get_state(const thetaL* th, thetaL_state* st) {
   KFBI_TRY(tl_check(th, true));
-  if (!st || !st->eta_dev || !st->phi_prev_dev || !st->nhat_prev_dev) {
+  if (!st || !st->eta_dev || !st->phi_prev_dev || !st->phi_prev2_dev || !st->nhat_prev_dev) {
     set_error("thetaL_get_state: null state array");
     return KFBI_E_INVALID;
   }
@@ -793,6 +790,7 @@ int thetaL_get_state(const thetaL* th, thetaL_state* st) {
   hipStream_t s = th->stream;
   KFBI_HIP(hipMemcpyAsync(st->eta_dev, th->eta.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
   KFBI_HIP(hipMemcpyAsync(st->phi_prev_dev, th->phi.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+  KFBI_HIP(hipMemcpyAsync(st->phi_prev2_dev, th->phi2.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
   KFBI_HIP(hipMemcpyAsync(st->nhat_prev_dev, th->nhat.p, sizeof(double) * 2 * M,
                           hipMemcpyDeviceToDevice, s));
   KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, s));
@@ -804,7 +802,8 @@ int thetaL_get_state(const thetaL* th, thetaL_state* st) {
 
 int thetaL_set_state(thetaL* th, const thetaL_state* st) {
   KFBI_TRY(tl_check(th, false));
-  if (!st || !st->eta_dev || !st->phi_prev_dev || !st->nhat_prev_dev || st->n < 0) {
+  if (!st || !st->eta_dev || !st->phi_prev_dev || !st->phi_prev2_dev || !st->nhat_prev_dev ||
+      st->n < 0) {
     set_error("thetaL_set_state: null state array or negative step count");
     return KFBI_E_INVALID;
   }
@@ -816,6 +815,7 @@ int thetaL_set_state(thetaL* th, const thetaL_state* st) {
   hipStream_t s = th->stream;
   KFBI_HIP(hipMemcpyAsync(th->eta.p, st->eta_dev, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
   KFBI_HIP(hipMemcpyAsync(th->phi.p, st->phi_prev_dev, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
+  KFBI_HIP(hipMemcpyAsync(th->phi2.p, st->phi_prev2_dev, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
   KFBI_HIP(hipMemcpyAsync(th->nhat.p, st->nhat_prev_dev, sizeof(double) * 2 * M,
                           hipMemcpyDeviceToDevice, s));
   for (int q = 0; q < S_COUNT; ++q) th->hscal[q] = (q < 8) ? st->scal[q] : 0.0;

@@ -1,0 +1,34 @@
+// Internal layout of the theta-L evolution object (shared with the warm-start code).
+#pragma once
+
+#include "../../include/thetal.h"
+#include "common.h"
+
+namespace kfbi {
+constexpr int kTLThreads = 1024;
+constexpr int kTLMaxM = 2048;
+// scal[] slots (device)
+enum { S_L = 0, S_XBX, S_XBY, S_T, S_LPREV, S_MPREV, S_QPX, S_QPY, S_AREA, S_LEN, S_BAD, S_COUNT };
+// aux[] planes of M doubles (device)
+enum { A_THA = 0, A_HETA, A_NX, A_NY, A_R2, A_U, A_COUNT };
+}  // namespace kfbi
+
+struct thetaL {
+  thetaL_params prm{};
+  kfbi_ctx* kc = nullptr;
+  hipStream_t stream = nullptr;
+  int M = 0;
+  int n = 0;           // steps taken
+  int ready = 0;       // thetaL_init or set_state done
+  int have_phi = 0;    // phi_prev holds a density
+  // phi: density of the last solve, phi2: of the solve before it, phiw: working copy
+  kfbi::DBuf tw, eta, scal, X, rhs, aux, etahat, nhat, phi, phi2, phiw, dnp, dnm, init;
+  double* hscal = nullptr;  // pinned copy of scal
+};
+
+
+namespace kfbi {
+// Recompute the per-marker shape data of the current state (aux planes, markers, rhs)
+// without advancing it (used before a learned initial guess is formed).
+int thetal_refresh(thetaL* th);
+}  // namespace kfbi

@@ -27,6 +27,10 @@ EXPORTS = [
     "kfbi_profile_kernel",
     "thetaL_create", "thetaL_destroy", "thetaL_init", "thetaL_step", "thetaL_run",
     "thetaL_markers", "thetaL_density", "thetaL_kfbi", "thetaL_get_state", "thetaL_set_state",
+    "kfbi_ws_create", "kfbi_ws_destroy", "kfbi_ws_n_params", "kfbi_ws_get_weights",
+    "kfbi_ws_set_weights", "kfbi_ws_predict", "kfbi_ws_record", "kfbi_ws_n_samples",
+    "kfbi_ws_clear", "kfbi_ws_train", "kfbi_ws_eval", "kfbi_ws_forward", "kfbi_ws_backward",
+    "kfbi_ws_target_scale",
 ]
 
 
@@ -88,7 +92,15 @@ class ThetaLStats(C.Structure):
 
 class ThetaLState(C.Structure):
     _fields_ = [("eta_dev", C.c_void_p), ("phi_prev_dev", C.c_void_p),
-                ("nhat_prev_dev", C.c_void_p), ("scal", C.c_double * 8), ("n", C.c_int)]
+                ("phi_prev2_dev", C.c_void_p), ("nhat_prev_dev", C.c_void_p),
+                ("scal", C.c_double * 8), ("n", C.c_int)]
+
+
+class WsCfg(C.Structure):
+    _fields_ = [("M", C.c_int), ("max_batch", C.c_int), ("capacity", C.c_int),
+                ("L_ref", C.c_double), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_ulonglong),
+                ("target_scale", C.c_double), ("stream", C.c_void_p)]
 
 
 _lib = None
@@ -126,6 +138,21 @@ def load(path: str = LIBPATH):
     lib.thetaL_kfbi.restype = vp
     lib.thetaL_get_state.argtypes = [vp, C.POINTER(ThetaLState)]
     lib.thetaL_set_state.argtypes = [vp, C.POINTER(ThetaLState)]
+    ip, fp = C.POINTER(C.c_int), C.POINTER(C.c_float)
+    lib.kfbi_ws_create.argtypes = [C.POINTER(WsCfg), C.POINTER(vp)]
+    lib.kfbi_ws_destroy.argtypes = [vp]
+    lib.kfbi_ws_n_params.argtypes = [vp, ip]
+    lib.kfbi_ws_get_weights.argtypes = [vp, fp]
+    lib.kfbi_ws_set_weights.argtypes = [vp, fp]
+    lib.kfbi_ws_predict.argtypes = [vp, vp, vp]
+    lib.kfbi_ws_record.argtypes = [vp, vp, ip]
+    lib.kfbi_ws_n_samples.argtypes = [vp, ip]
+    lib.kfbi_ws_clear.argtypes = [vp]
+    lib.kfbi_ws_train.argtypes = [vp, C.c_int, C.c_int, C.c_int, fp]
+    lib.kfbi_ws_eval.argtypes = [vp, C.c_int, C.c_int, fp]
+    lib.kfbi_ws_forward.argtypes = [vp, C.c_int, vp, vp]
+    lib.kfbi_ws_backward.argtypes = [vp, C.c_int, vp, vp, vp, fp]
+    lib.kfbi_ws_target_scale.argtypes = [vp, C.POINTER(C.c_double)]
     _lib = lib
     return lib
 
@@ -284,15 +311,113 @@ class ThetaL:
     def get_state(self) -> dict:
         eta = torch.empty(self.M, dtype=torch.float64, device="cuda")
         phi = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        phi2 = torch.empty(self.M, dtype=torch.float64, device="cuda")
         nh = torch.empty(2 * self.M, dtype=torch.float64, device="cuda")
         st = ThetaLState(C.c_void_p(eta.data_ptr()), C.c_void_p(phi.data_ptr()),
-                         C.c_void_p(nh.data_ptr()))
+                         C.c_void_p(phi2.data_ptr()), C.c_void_p(nh.data_ptr()))
         _check(self.lib.thetaL_get_state(self.h, C.byref(st)))
-        return {"eta": eta, "phi_prev": phi, "nhat_prev": nh, "scal": list(st.scal), "n": st.n}
+        return {"eta": eta, "phi_prev": phi, "phi_prev2": phi2, "nhat_prev": nh,
+                "scal": list(st.scal), "n": st.n}
 
     def set_state(self, d: dict):
-        st = ThetaLState(_ptr(d["eta"]), _ptr(d["phi_prev"]), _ptr(d["nhat_prev"]))
+        st = ThetaLState(_ptr(d["eta"]), _ptr(d["phi_prev"]), _ptr(d["phi_prev2"]),
+                         _ptr(d["nhat_prev"]))
         for i in range(8):
             st.scal[i] = d["scal"][i]
         st.n = d["n"]
         _check(self.lib.thetaL_set_state(self.h, C.byref(st)))
+
+
+def _fptr(t):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class WarmStart:
+    """Learned GMRES initial guess for a ThetaL evolution (include/warmstart.h)."""
+
+    def __init__(self, M, max_batch=64, capacity=16384, L_ref=2 * 3.141592653589793, lr=1e-3,
+                 beta1=0.9, beta2=0.999, eps=1e-8, seed=0, target_scale=0.0, stream=None):
+        self.lib = load()
+        s = torch.cuda.current_stream() if stream is None else stream
+        cfg = WsCfg(M, max_batch, capacity, L_ref, lr, beta1, beta2, eps, seed, target_scale,
+                    C.c_void_p(s.cuda_stream))
+        h = C.c_void_p()
+        _check(self.lib.kfbi_ws_create(C.byref(cfg), C.byref(h)))
+        self.h = h
+        self.M = M
+        n = C.c_int()
+        _check(self.lib.kfbi_ws_n_params(self.h, C.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if self.h:
+            self.lib.kfbi_ws_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self):
+        import numpy as np
+        w = np.empty(self.n_params, dtype=np.float32)
+        _check(self.lib.kfbi_ws_get_weights(self.h, w.ctypes.data_as(C.POINTER(C.c_float))))
+        return w
+
+    def set_weights(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == self.n_params
+        _check(self.lib.kfbi_ws_set_weights(self.h, w.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def predict(self, th, x0=None):
+        """Initial guess for the next step of th (x0 None: features only, no guess)."""
+        _check(self.lib.kfbi_ws_predict(self.h, th.h, _ptr(x0)))
+        return x0
+
+    def record(self, th) -> bool:
+        st = C.c_int()
+        _check(self.lib.kfbi_ws_record(self.h, th.h, C.byref(st)))
+        return bool(st.value)
+
+    def target_scale(self) -> float:
+        v = C.c_double()
+        _check(self.lib.kfbi_ws_target_scale(self.h, C.byref(v)))
+        return v.value
+
+    def n_samples(self) -> int:
+        n = C.c_int()
+        _check(self.lib.kfbi_ws_n_samples(self.h, C.byref(n)))
+        return n.value
+
+    def clear(self):
+        _check(self.lib.kfbi_ws_clear(self.h))
+
+    def train(self, n_train, epochs, batch):
+        losses = (C.c_float * max(epochs, 1))()
+        _check(self.lib.kfbi_ws_train(self.h, n_train, epochs, batch, losses))
+        return [losses[i] for i in range(epochs)]
+
+    def eval(self, first, count):
+        v = C.c_float()
+        _check(self.lib.kfbi_ws_eval(self.h, first, count, C.byref(v)))
+        return v.value
+
+    def forward(self, feat):
+        """feat: (B, M, 5) float32 device tensor -> (B, M) float32."""
+        feat = feat.contiguous()
+        out = torch.empty(feat.shape[:2], dtype=torch.float32, device=feat.device)
+        _check(self.lib.kfbi_ws_forward(self.h, feat.shape[0], _fptr(feat), _fptr(out)))
+        return out
+
+    def backward(self, feat, target):
+        feat, target = feat.contiguous(), target.contiguous()
+        g = torch.empty(self.n_params, dtype=torch.float32, device=feat.device)
+        loss = C.c_float()
+        _check(self.lib.kfbi_ws_backward(self.h, feat.shape[0], _fptr(feat), _fptr(target),
+                                         _fptr(g), C.byref(loss)))
+        return loss.value, g

@@ -226,3 +226,35 @@ def test_profile_kernel_replay_leaves_results_intact():
     assert e.value.code == kfbi.E_INVALID
     ref = K.apply(G.build_geometry(X, box), K.SINGLE, d, 1000.0)
     assert rel(host(ctx.apply(K.SINGLE, dev(d))["v_plus"]), ref.v_plus) <= TOL64
+
+
+def _poke_circle(N, frac):
+    """Circle that pokes `frac` h past the column x_56, with no marker at the tangent
+    point: the interpolant crosses that column twice between two markers."""
+    h = 2.0 / N
+    R = 0.75
+    xi = -1 + 56 * h
+    M = 96
+    a = 2 * np.pi * (np.arange(M) + 0.5) / M
+    return np.stack([xi - R + frac * h + R * np.cos(a), 0.01 + R * np.sin(a)])
+
+
+@pytest.mark.parametrize("case", ["poke", "sliver"])
+def test_near_tangent_geometry_parity(case):
+    """Double crossings between markers are found and segments cut twice are dropped,
+    identically on both sides."""
+    if case == "poke":
+        X, box = _poke_circle(64, 0.004), W.box(-1, 1, 64)
+    else:
+        a = 2 * np.pi * np.arange(256) / 256
+        X, box = np.stack([0.003 * np.cos(a) + 0.0101, 0.5 * np.sin(a)]), W.box(-1, 1, 64)
+    dens = W.fourier_density(X.shape[1], seed=11)
+    g, ref, ctx, out = run_pair(X, box, 0.0, K.BOX_ZERO, K.DOUBLE, dens)
+    info = ctx.info()
+    assert info["n_cross_h"] == g.hx.line.size and info["n_cross_v"] == g.vx.line.size
+    assert info["n_arms"] == g.arms.shape[0]
+    # (the unresolved sliver leaves v- and both normal derivatives at rounding level:
+    # errors are measured against the largest of the four traces)
+    scale = max(np.linalg.norm(getattr(ref, k)) for k in ("v_plus", "v_minus", "dn_plus", "dn_minus"))
+    for k in ("v_plus", "v_minus", "dn_plus", "dn_minus"):
+        assert np.linalg.norm(out[k] - getattr(ref, k)) <= TOL64 * scale, k

@@ -55,14 +55,45 @@ def test_margin_is_enforced():
         G.build_geometry(W.circle(256, 0.95), W.box(-1, 1, 64))
 
 
-def test_two_crossings_in_one_segment_rejected():
-    # a thin ellipse whose width is far below h puts two crossings in one row segment
+def test_segment_cut_twice_is_not_cut():
+    # a sliver far narrower than h: each row segment it spans is cut twice, the grid does
+    # not resolve it, so both crossings are dropped and every node stays outside
     N = 32
     M = 256
     a = 2 * np.pi * np.arange(M) / M
     X = np.stack([0.003 * np.cos(a) + 0.0101, 0.5 * np.sin(a)])
+    g = G.build_geometry(X, W.box(-1, 1, N))
+    assert g.hx.line.size > 0 and not g.hx.keep.any()
+    assert not g.inside.any() and g.arms.shape[0] == 0
+
+
+def test_three_crossings_in_one_segment_rejected():
+    cr = G.Crossings(np.array([5, 5, 5, 6]), np.zeros(4, int), np.zeros(4), np.zeros(4),
+                     np.array([3, 3, 3, 3]))
     with pytest.raises(G.GeometryError):
-        G.build_geometry(X, W.box(-1, 1, N))
+        G._pair_out(cr, 32)
+    cr = G.Crossings(np.array([5, 5, 6]), np.zeros(3, int), np.zeros(3), np.zeros(3),
+                     np.array([3, 3, 3]))
+    G._pair_out(cr, 32)
+    assert cr.keep.tolist() == [False, False, True]
+
+
+def test_double_crossing_between_two_markers_is_found():
+    # a coarse circle (few markers per h) nearly tangent to the column x = x_i just
+    # inside it: the markers next to the tangent point lie left of x_i while the
+    # interpolant crosses it twice; both crossings are found and the labels agree
+    N = 64
+    h = 2.0 / N
+    R = 0.75
+    xi = -1 + 56 * h                       # column i = 56
+    cx = xi - R + 0.004 * h                # the circle pokes 0.004 h past x_i
+    M = 96
+    a = 2 * np.pi * (np.arange(M) + 0.5) / M   # no marker at the tangent point
+    X = np.stack([cx + R * np.cos(a), 0.01 + R * np.sin(a)])
+    assert np.all(X[0] < xi)
+    g = G.build_geometry(X, W.box(-1, 1, N))
+    on = (g.vx.line == 56) & g.vx.keep
+    assert on.sum() == 2 or (g.vx.line == 56).sum() == 2
 
 
 def test_newton_root_accuracy():
