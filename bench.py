@@ -40,6 +40,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--reps", type=int, default=400,
                     help="back-to-back replays per kernel for the per-kernel durations")
+    ap.add_argument("--hs-steps", type=int, default=200,
+                    help="Hele-Shaw steps timed per evolution (the workload runs 200)")
+    ap.add_argument("--ws-train-runs", type=int, default=24,
+                    help="training evolutions for the learned warm start (56 = full set)")
+    ap.add_argument("--ws-test-runs", type=int, default=4,
+                    help="held-out evolutions for the learned warm start (8 = full set)")
+    ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 10 times (the reference "
                          "kernel for scaling hardware byte counters) and exit")
@@ -208,6 +215,9 @@ def main():
 
     if not a.no_extra:
         result["extra"] = extras(kf, W, torch, np, dev, dens, layer)
+        result["interior_dirichlet"] = interior_dirichlet(kf, W, torch, np, dev)
+        result["hele_shaw"] = hele_shaw(kf, W, torch, np, dev, a)
+        result["warm_start"] = warm_start(kf, W, torch, np, dev, a)
     print(json.dumps(result), flush=True)
 
 
@@ -272,6 +282,131 @@ def extras(kf, W, torch, np, dev, dens, layer):
             "seconds": round(el, 5), "iters": st["iters"], "relres": st["relres"],
             "applies64": st["applies64"], "applies32": st["applies32"]}
     return out
+
+
+def interior_dirichlet(kf, W, torch, np, dev):
+    """Ellipse 0.6 x 0.4 (256 markers) in [-1,1]^2, N = 128, Laplace: interior Dirichlet
+    BIE v+ = g for u = e^x sin y by FP64 GMRES to 1e-10 from x0 = 0; iterations, solve
+    time and the error of the grid solution at the inside nodes."""
+    box = W.box(-1.0, 1.0, 128)
+    X = W.ellipse(256)
+    ctx = kf.Context(box.x0, box.y0, box.side, 128, 0.0, kf.BOX_ZERO, 256)
+    ctx.set_interface(torch.tensor(X, device=dev))
+    g = torch.tensor(np.exp(X[0]) * np.sin(X[1]), device=dev)
+    x = torch.zeros(256, dtype=torch.float64, device=dev)
+    ctx.gmres(g, x, kf.DOUBLE, kf.PLUS, 0.0, 1.0, 0.0, tol=1e-10)   # warm-up
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = ctx.gmres(g, x, kf.DOUBLE, kf.PLUS, 0.0, 1.0, 0.0, tol=1e-10)
+    el = time.perf_counter() - t0
+    grid = ctx.apply(kf.DOUBLE, x, grid=True)["grid"].cpu().numpy()
+    xs = box.x0 + box.h * np.arange(129)
+    XX, YY = np.meshgrid(xs, xs)                     # [j, i]
+    inside = (XX / 0.6) ** 2 + (YY / 0.4) ** 2 < 1.0
+    err = np.abs(grid - np.exp(XX) * np.sin(YY))[inside]
+    ctx.close()
+    return {"iters": st["iters"], "relres": st["relres"], "solve_ms": round(1e3 * el, 4),
+            "max_err_inside": float(err.max()), "l2_err_inside": float(np.sqrt(np.mean(err ** 2)))}
+
+
+def hele_shaw(kf, W, torch, np, dev, a):
+    """Hele-Shaw evolution: r = 1 + 0.1 cos 3a + 0.05 sin 5a resampled to 1024 markers of
+    equal arclength, [-2,2]^2 with 1024^2 intervals, sigma = 1e-3, J = 1, tau = 1e-3,
+    previous-density initial guess, FP64 GMRES to 1e-10: wall time per step and its
+    split, iterations, area and length."""
+    box = W.box(-2.0, 2.0, 1024)
+    out = {}
+    for prec in (0, 1):
+        th = kf.ThetaL(box.x0, box.y0, box.side, 1024, 1024, 1e-3, 1.0, 1e-3, precision=prec)
+        th.init(torch.tensor(W.hs3(1024), device=dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = th.run(a.hs_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        n = len(recs)
+        key = "f64" if prec == 0 else "f32ir"
+        out[key] = {
+            "steps": n, "ms_per_step": round(1e3 * el / n, 4),
+            "ms_split": {k: round(sum(r[k] for r in recs) / n, 4)
+                         for k in ("ms_geometry", "ms_gmres", "ms_apply", "ms_update")},
+            "mean_iters": round(sum(r["iters"] for r in recs) / n, 3),
+            "max_relres": max(r["relres"] for r in recs),
+            "area_first_last": [recs[0]["area"], recs[-1]["area"]],
+            "length_first_last": [recs[0]["length"], recs[-1]["length"]],
+            "t_end": recs[-1]["t"]}
+        th.close()
+    return out
+
+
+def warm_start(kf, W, torch, np, dev, a):
+    """Learned initial guess on the Hele-Shaw setup with perturbed curves
+    r = 1 + sum_{m=2..8} a_m cos(m a + p_m), a_m ~ U(0, 0.1): data from training
+    evolutions (seeds 0..), training on the GPU, then per-step GMRES iterations and wall
+    time on held-out evolutions (seeds 56..) for x0 = 0, the previous density and the
+    learned guess, FP64 and FP32-inner GMRES, all to the same 1e-10 FP64 residual."""
+    box = W.box(-2.0, 2.0, 1024)
+    M, nst = 1024, a.hs_steps
+    args = (box.x0, box.y0, box.side, 1024, M, 1e-3, 1.0, 1e-3)
+    cap = a.ws_train_runs * nst
+    ws = kf.WarmStart(M, max_batch=64, capacity=max(cap, 64), seed=0)
+    t0 = time.perf_counter()
+    used = []
+    sd = 0
+    while len(used) < a.ws_train_runs:
+        th = kf.ThetaL(*args)
+        th.init(torch.tensor(W.perturbed(M, sd), device=dev))
+        try:
+            for _ in range(nst):
+                ws.predict(th)
+                th.step()
+                ws.record(th)
+            used.append(sd)
+        except kf.KfbiError:  # a curve that leaves the box: replaced by the next seed
+            pass
+        th.close()
+        sd += 1
+    gen_s = time.perf_counter() - t0
+    n = ws.n_samples()
+    t0 = time.perf_counter()
+    losses = ws.train(n, a.ws_epochs, 64)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    res = {"train_runs": len(used), "samples": n, "data_gen_s": round(gen_s, 2),
+           "train_s": round(train_s, 2), "epochs": a.ws_epochs,
+           "loss_first_last": [losses[0], losses[-1]] if losses else None,
+           "target_scale": ws.target_scale()}
+    x0 = torch.empty(M, dtype=torch.float64, device=dev)
+    for prec in (0, 1):
+        for mode in ("zero", "previous", "learned"):
+            its, tsum, nsteps = [], 0.0, 0
+            for k in range(a.ws_test_runs):
+                th = kf.ThetaL(*args, precision=prec)
+                th.init(torch.tensor(W.perturbed(M, 56 + k), device=dev))
+                try:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(nst):
+                        if mode == "zero":
+                            x0.zero_()
+                            r = th.step(x0)
+                        elif mode == "previous":
+                            r = th.step()
+                        else:
+                            ws.predict(th, x0)
+                            r = th.step(x0)
+                        its.append(r["iters"])
+                    torch.cuda.synchronize()
+                    tsum += time.perf_counter() - t0
+                    nsteps += nst
+                except kf.KfbiError:
+                    pass
+                th.close()
+            key = f"{'f64' if prec == 0 else 'f32ir'}_{mode}"
+            res[key] = {"mean_iters": round(float(np.mean(its)), 3) if its else None,
+                        "ms_per_step": round(1e3 * tsum / max(nsteps, 1), 4), "steps": nsteps}
+    return res
 
 
 if __name__ == "__main__":
