@@ -77,6 +77,8 @@ static void release_all(kfbi_ctx* c) {
   for (DBuf* b : bufs) b->release();
   for (int i = 0; i < kfbi_ctx::kProfPool; ++i)
     if (c->prof_ev[i]) (void)hipEventDestroy(c->prof_ev[i]);
+  for (int i = 0; i < kfbi_ctx::kGmresRing; ++i)
+    if (c->gev[i]) (void)hipEventDestroy(c->gev[i]);
   if (c->hpin) (void)hipHostFree(c->hpin);
   c->hpin = nullptr;
 }

@@ -35,6 +35,7 @@ namespace kfbi {
 constexpr int kColsPerBlock = 4;
 constexpr int kReg = 4;       // circulant outputs per thread in K1
 constexpr int kNodeBatch = 8; // nodes reduced together in K4
+constexpr int kRingNodes = 16; // free-space box nodes per K1 block
 
 // Two-level sine table in LDS: sin/cos(pi m / N) for m = 64 q + r from
 // hs/hc[q] = sin/cos(pi 64 q / N) and ls/lc[r] = sin/cos(pi r / N) by angle addition.
@@ -88,49 +89,70 @@ __global__ void __launch_bounds__(256)
            const double* __restrict__ d1, const double* __restrict__ d2,
            double* __restrict__ mq, double* __restrict__ qpart, const double* __restrict__ wq,
            int N, double x0, double y0, double h, const double* __restrict__ X,
-           const double* __restrict__ geo, double* __restrict__ ring) {
+           const double* __restrict__ geo, double* __restrict__ ring, float* __restrict__ ringT) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
   if (static_cast<int>(blockIdx.x) >= nmk) {
-    // ----- box data: one wavefront per box node, lanes split the markers
+    // ----- box data: kRingNodes box nodes per block; thread (node, slice) sums the
+    // trapezoid terms of one slice of the markers, slices are then added in order
     const int rb = blockIdx.x - nmk;
-    const int lane = tid & 63, w = tid >> 6;
+    const int nd = tid % kRingNodes, sl = tid / kRingNodes;
+    constexpr int S = 256 / kRingNodes;
     const int n1 = N + 1;
-    const int total = 4 * n1;
-    const double* xs = X;
-    const double* ys = X + M;
-    const double* xa = geo;
-    const double* ya = geo + M;
-    const double* sa = geo + 4 * M;
-    for (int q = 0; q < 4; ++q) {
-      const int node = rb * 16 + w * 4 + q;
-      if (node >= total) break;
+    const int node = rb * kRingNodes + nd;
+    const bool live = node < 4 * n1;
+    double zx = 0.0, zy = 0.0;
+    if (live) {
       const int side = node / n1, r = node % n1;
-      double zx, zy;
-      if (side == 0) {
-        zx = x0 + r * h;
-        zy = y0;
-      } else if (side == 1) {
-        zx = x0 + r * h;
-        zy = y0 + N * h;
-      } else if (side == 2) {
-        zx = x0;
-        zy = y0 + r * h;
+      zx = (side == 2) ? x0 : (side == 3 ? x0 + N * h : x0 + r * h);
+      zy = (side == 0) ? y0 : (side == 1 ? y0 + N * h : y0 + r * h);
+    }
+    // markers staged in LDS in chunks of 256: (x, y, phi y_a, phi x_a) for the double
+    // layer, (x, y, psi s_a / 2) for the single layer; slice sl takes 16 of each chunk
+    double* cx = lds;
+    double* cy = cx + 256;
+    double* ca = cy + 256;
+    double* cb = ca + 256;
+    double acc = 0.0;
+    for (int c0 = 0; c0 < M; c0 += 256) {
+      const int k = c0 + tid;
+      __syncthreads();
+      if (k < M) {
+        cx[tid] = X[k];
+        cy[tid] = X[M + k];
+        if (layer == KFBI_DOUBLE) {
+          ca[tid] = dens[k] * geo[M + k];
+          cb[tid] = dens[k] * geo[k];
+        } else {
+          ca[tid] = 0.5 * dens[k] * geo[4 * M + k];
+        }
+      }
+      __syncthreads();
+      const int nk = min(256, M - c0);
+      const int q0 = sl * 16, q1 = min(nk, q0 + 16);
+      if (layer == KFBI_DOUBLE) {
+#pragma unroll 4
+        for (int q = q0; q < q1; ++q) {
+          const double dx = cx[q] - zx, dy = cy[q] - zy;
+          acc += (dx * ca[q] - dy * cb[q]) / (dx * dx + dy * dy);
+        }
       } else {
-        zx = x0 + N * h;
-        zy = y0 + r * h;
+#pragma unroll 4
+        for (int q = q0; q < q1; ++q) {
+          const double dx = cx[q] - zx, dy = cy[q] - zy;
+          acc += ca[q] * log(dx * dx + dy * dy);
+        }
       }
-      double acc = 0.0;
-      for (int k = lane; k < M; k += 64) {
-        const double dx = xs[k] - zx, dy = ys[k] - zy;
-        const double r2 = dx * dx + dy * dy;
-        if (layer == KFBI_DOUBLE)
-          acc += dens[k] * (dx * ya[k] - dy * xa[k]) / r2;
-        else
-          acc += dens[k] * sa[k] * 0.5 * log(r2);
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) ring[node] = acc / M;
+    }
+    __syncthreads();
+    double* part = lds;  // S x kRingNodes
+    part[sl * kRingNodes + nd] = acc;
+    __syncthreads();
+    if (tid < kRingNodes && live) {
+      double v = 0.0;
+      for (int q = 0; q < S; ++q) v += part[q * kRingNodes + tid];
+      ring[node] = v / M;
+      if (ringT) ringT[node] = static_cast<float>(v / M);
     }
     return;
   }
@@ -844,7 +866,10 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
     c->prof_used += 5;
     hipEventRecord(ev[0], s);
   }
-  if (c->box_bc == KFBI_BOX_FREESPACE) nring = nblk(4 * (N + 1), 16);
+  if (c->box_bc == KFBI_BOX_FREESPACE) nring = nblk(4 * (N + 1), kRingNodes);
+  // box data in the working precision: FP64 uses the FP64 values in place; FP32 keeps a
+  // float copy after the FP64 ring (written by k_prep for the free-space data)
+  float* ring32 = reinterpret_cast<float*>(ring64 + 4 * (N + 1));
   const int C = c->mk_chunk, nmk = c->n_mk_blocks;
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
   const size_t lds = sizeof(double) * ((1 + nd) * M + 256 * kReg);  // covers block_sum too
@@ -853,13 +878,19 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
     hipLaunchKernelGGL(k_prep, dim3(nmk + nring), dim3(256), lds, s, M, C, nmk, layer, dens,
                      c->dvec.as<double>(), c->dvec.as<double>() + M, c->mq.as<double>(),
                      c->qpart.as<double>(), c->ext.as<double>() + kExtQ * M, N, c->x0, c->y0,
-                     c->h, c->X.as<double>(), c->geo.as<double>(), ring64);
-  if (c->box_bc != KFBI_BOX_ZERO) {
-    const double* src = (c->box_bc == KFBI_BOX_USER) ? ring_user : ring64;
-    ringT = reinterpret_cast<T*>(ring64 + 4 * (N + 1));
-    if ((stages & 1) && src)
-      hipLaunchKernelGGL((k_ring_cast<T>), dim3(nblk(4 * (N + 1), 256)), dim3(256), 0, s,
-                       4 * (N + 1), src, ringT);
+                     c->h, c->X.as<double>(), c->geo.as<double>(), ring64,
+                     sizeof(T) == 4 ? ring32 : nullptr);
+  if (c->box_bc == KFBI_BOX_FREESPACE) {
+    ringT = sizeof(T) == 8 ? reinterpret_cast<T*>(ring64) : reinterpret_cast<T*>(ring32);
+  } else if (c->box_bc == KFBI_BOX_USER) {
+    if (sizeof(T) == 8) {
+      ringT = const_cast<T*>(reinterpret_cast<const T*>(ring_user));
+    } else {
+      ringT = reinterpret_cast<T*>(ring32);
+      if ((stages & 1) && ring_user)
+        hipLaunchKernelGGL((k_ring_cast<T>), dim3(nblk(4 * (N + 1), 256)), dim3(256), 0, s,
+                           4 * (N + 1), ring_user, ringT);
+    }
   }
   if (ev) hipEventRecord(ev[1], s);
   const int jlo = full ? 1 : c->st.row_lo;

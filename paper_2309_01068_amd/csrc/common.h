@@ -112,6 +112,8 @@ struct kfbi_ctx {
   kfbi::DBuf mq, armr, qpart, ring, sinT, sinT32, gband, nodeval, tmpM;
   // gmres buffers
   kfbi::DBuf gV, gH, gsc, gpart, gcnt, gw, gx, gr, gd;
+  static constexpr int kGmresRing = 4;
+  hipEvent_t gev[kGmresRing] = {};
   // pinned host status
   void* hpin = nullptr;
 

@@ -41,16 +41,18 @@ __global__ void k_diffvec(int M, double* __restrict__ d1, double* __restrict__ d
 }
 
 // Marker geometry: x_a, y_a, x_aa, y_aa, s_a, s_aa (App. A: n = (y_a, -x_a)/s_a) and the
-// 3h margin test against the box.
-__global__ void k_marker_geo(int M, const double* __restrict__ X, const double* __restrict__ d1,
-                             const double* __restrict__ d2, double* __restrict__ geo, double lox,
-                             double hix, double loy, double hiy, GeoStatus* st) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M) return;
+// 3h margin test against the box.  One block per marker: the four circulant sums are split
+// over the threads and reduced in a fixed order.
+__global__ void __launch_bounds__(256)
+    k_marker_geo(int M, const double* __restrict__ X, const double* __restrict__ d1,
+                 const double* __restrict__ d2, double* __restrict__ geo, double lox,
+                 double hix, double loy, double hiy, GeoStatus* st) {
+  __shared__ double red[4][4];
+  const int k = blockIdx.x;
   const double* x = X;
   const double* y = X + M;
   double xa = 0, ya = 0, xaa = 0, yaa = 0;
-  for (int m = 0; m < M; ++m) {
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
     int q = k - m;
     q += (q < 0) ? M : 0;
     const double a1 = d1[q], a2 = d2[q], xm = x[m], ym = y[m];
@@ -59,6 +61,23 @@ __global__ void k_marker_geo(int M, const double* __restrict__ X, const double* 
     xaa += a2 * xm;
     yaa += a2 * ym;
   }
+  xa = wave_sum(xa);
+  ya = wave_sum(ya);
+  xaa = wave_sum(xaa);
+  yaa = wave_sum(yaa);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = xa;
+    red[1][w] = ya;
+    red[2][w] = xaa;
+    red[3][w] = yaa;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  xa = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+  ya = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  xaa = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
+  yaa = ((red[3][0] + red[3][1]) + red[3][2]) + red[3][3];
   const double sa = sqrt(xa * xa + ya * ya);
   geo[k] = xa;
   geo[M + k] = ya;
@@ -185,7 +204,7 @@ __device__ inline double newton_root(const double* c, double g, double a, double
   return t;
 }
 
-__global__ void k_fill_cross(int M, const double* __restrict__ X, double x0, double y0, double h,
+__global__ void __launch_bounds__(64) k_fill_cross(int M, const double* __restrict__ X, double x0, double y0, double h,
                              int N, const int* __restrict__ off, int nh, Crossing* __restrict__ cr,
                              int cap, GeoStatus* st) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -494,76 +513,74 @@ __global__ void k_part_fill(int N, const int* __restrict__ rowoff,
 __global__ void k_chunk_nodes(int M, int MC, const int* __restrict__ mkkey,
                               int* __restrict__ cnode, int* __restrict__ ccount,
                               int* __restrict__ mkloc) {
-  extern __shared__ int keys[];  // 6 * MC
-  __shared__ int nuniq;
+  extern __shared__ int keys[];  // 2 * 6 * MC: keys, first-occurrence flags
+  int* first = keys + 6 * MC;
   const int ch = blockIdx.x;
   const int k0 = ch * MC, k1 = min(M, k0 + MC);
   const int ns = 6 * (k1 - k0);
   for (int t = threadIdx.x; t < ns; t += blockDim.x) keys[t] = mkkey[6 * k0 + t];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int a = 1; a < ns; ++a) {  // insertion sort (ns <= 96)
-      const int v = keys[a];
-      int b = a - 1;
-      while (b >= 0 && keys[b] > v) {
-        keys[b + 1] = keys[b];
-        --b;
-      }
-      keys[b + 1] = v;
-    }
-    int u = 0;
-    for (int a = 0; a < ns; ++a)
-      if (a == 0 || keys[a] != keys[a - 1]) keys[u++] = keys[a];
-    nuniq = u;
-    ccount[ch] = u;
+  // rank-based sort with duplicates removed: a key's slot is the number of distinct keys
+  // below it (ns <= 96, one thread per stencil slot)
+  for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+    const int v = keys[t];
+    int f = 1;
+    for (int a = 0; a < t; ++a) f &= (keys[a] != v);
+    first[t] = f;
   }
   __syncthreads();
-  const int u = nuniq;
-  for (int t = threadIdx.x; t < u; t += blockDim.x) cnode[ch * 6 * MC + t] = keys[t];
+  int nu = 0;
+  for (int a = 0; a < ns; ++a) nu += first[a];
   for (int t = threadIdx.x; t < ns; t += blockDim.x) {
-    const int key = mkkey[6 * k0 + t];
-    int lo = 0, hi = u - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) / 2;
-      if (keys[mid] < key)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    mkloc[6 * k0 + t] = lo;
+    const int v = keys[t];
+    int r = 0;
+    for (int a = 0; a < ns; ++a) r += (first[a] && keys[a] < v) ? 1 : 0;
+    mkloc[6 * k0 + t] = r;
+    if (first[t]) cnode[ch * 6 * MC + r] = v;
   }
+  if (threadIdx.x == 0) ccount[ch] = nu;
 }
 
-// Gauss-Jordan inverse of a 6x6 matrix with partial pivoting (in registers).
+// Gauss-Jordan inverse of a 6x6 matrix with partial pivoting.  Every loop is unrolled and
+// the row exchange is done with selects, so both matrices stay in registers.
 __device__ inline void inv6(double A[6][6], double R[6][6]) {
+#pragma unroll
   for (int r = 0; r < 6; ++r)
+#pragma unroll
     for (int c = 0; c < 6; ++c) R[r][c] = (r == c) ? 1.0 : 0.0;
+#pragma unroll
   for (int c = 0; c < 6; ++c) {
     int p = c;
     double best = fabs(A[c][c]);
+#pragma unroll
     for (int r = c + 1; r < 6; ++r)
       if (fabs(A[r][c]) > best) {
         best = fabs(A[r][c]);
         p = r;
       }
-    if (p != c)
+#pragma unroll
+    for (int r = c + 1; r < 6; ++r) {
+      const bool sw = (r == p);
+#pragma unroll
       for (int q = 0; q < 6; ++q) {
-        double t = A[c][q];
-        A[c][q] = A[p][q];
-        A[p][q] = t;
-        t = R[c][q];
-        R[c][q] = R[p][q];
-        R[p][q] = t;
+        const double ac = A[c][q], ar = A[r][q], rc = R[c][q], rr = R[r][q];
+        A[c][q] = sw ? ar : ac;
+        A[r][q] = sw ? ac : ar;
+        R[c][q] = sw ? rr : rc;
+        R[r][q] = sw ? rc : rr;
       }
+    }
     const double piv = 1.0 / A[c][c];
+#pragma unroll
     for (int q = 0; q < 6; ++q) {
       A[c][q] *= piv;
       R[c][q] *= piv;
     }
+#pragma unroll
     for (int r = 0; r < 6; ++r) {
       if (r == c) continue;
       const double f = A[r][c];
-      if (f == 0.0) continue;
+#pragma unroll
       for (int q = 0; q < 6; ++q) {
         A[r][q] -= f * A[c][q];
         R[r][q] -= f * R[c][q];
@@ -573,7 +590,7 @@ __device__ inline void inv6(double A[6][6], double R[6][6]) {
 }
 
 // Sec. 4.3 extraction weights for every marker; marks the needed stencil nodes.
-__global__ void k_marker_ext(int M, const double* __restrict__ X, const double* __restrict__ geo,
+__global__ void __launch_bounds__(64) k_marker_ext(int M, const double* __restrict__ X, const double* __restrict__ geo,
                              double x0, double y0, double h, int N, double c2,
                              const int8_t* __restrict__ lab, double* __restrict__ ext,
                              int* __restrict__ need, int* __restrict__ stn) {
@@ -587,6 +604,7 @@ __global__ void k_marker_ext(int M, const double* __restrict__ X, const double* 
   const int ri[6] = {0, 1, 0, 0, -1, d1}, rj[6] = {0, 0, 1, -1, 0, d2};
   double A[6][6], Rv[6][6], At[6][6];
   double chi[6];
+#pragma unroll
   for (int m = 0; m < 6; ++m) {
     const int I = i0 + ri[m], J = j0 + rj[m];
     const double dx = (x0 + I * h - px) / h, dy = (y0 + J * h - py) / h;
@@ -609,6 +627,7 @@ __global__ void k_marker_ext(int M, const double* __restrict__ X, const double* 
   }
   inv6(A, Rv);
   double Wr[18];
+#pragma unroll
   for (int m = 0; m < 6; ++m) {
     Wr[m] = Rv[0][m];
     Wr[6 + m] = Rv[1][m] / h;
@@ -618,6 +637,7 @@ __global__ void k_marker_ext(int M, const double* __restrict__ X, const double* 
   // jumps at the marker as linear maps of (Phi, Phi_a, Phi_aa, Psi, Psi_a)
   const double xa = geo[k], ya = geo[M + k], xaa = geo[2 * M + k], yaa = geo[3 * M + k];
   double Cj[6][5];  // rows in Taylor order ([v],[v_x],[v_y],[v_xx],[v_xy],[v_yy])
+#pragma unroll
   for (int q = 0; q < 5; ++q) {
     double u[5] = {0, 0, 0, 0, 0};
     u[q] = 1.0;
@@ -630,14 +650,17 @@ __global__ void k_marker_ext(int M, const double* __restrict__ X, const double* 
     Cj[4][q] = J[5];
     Cj[5][q] = J[4];
   }
+#pragma unroll
   for (int r = 0; r < 3; ++r)
+#pragma unroll
     for (int q = 0; q < 5; ++q) {
       double e = 0.0;
+#pragma unroll
       for (int m = 0; m < 6; ++m) {
-        if (chi[m] == 0.0) continue;
         double cm = 0.0;
+#pragma unroll
         for (int s = 0; s < 6; ++s) cm += At[m][s] * Cj[s][q];
-        e += Wr[6 * r + m] * cm;
+        e += chi[m] * (Wr[6 * r + m] * cm);
       }
       ext[(kExtE + 5 * r + q) * M + k] = e;
       ext[(kExtD + 5 * r + q) * M + k] = Cj[r][q];
@@ -731,7 +754,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
     c->d_M = M;
   }
   const double mg = 3.0 * h;
-  hipLaunchKernelGGL(k_marker_geo, dim3(nblk(M, 256)), dim3(256), 0, s, M, c->X.as<double>(), d1,
+  hipLaunchKernelGGL(k_marker_geo, dim3(M), dim3(256), 0, s, M, c->X.as<double>(), d1,
                      d2, c->geo.as<double>(), c->x0 + mg, c->x0 + c->side - mg, c->y0 + mg,
                      c->y0 + c->side - mg, st);
   int* cnt = c->cnt.as<int>();
@@ -755,7 +778,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
 
 
   Crossing* cr = c->cross.as<Crossing>();
-  hipLaunchKernelGGL(k_fill_cross, dim3(nblk(M, 128)), dim3(128), 0, s, M, c->X.as<double>(), c->x0,
+  hipLaunchKernelGGL(k_fill_cross, dim3(nblk(M, 64)), dim3(64), 0, s, M, c->X.as<double>(), c->x0,
                      c->y0, h, N, cnt, nh, cr, nc, st);
   int* hid = c->hid.as<int>();
   int* vid = c->vid.as<int>();
@@ -783,7 +806,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   // markers / nodes
   int* need = c->need.as<int>();
   KFBI_HIP(hipMemsetAsync(need, 0, sizeof(int) * n1 * n1, s));
-  hipLaunchKernelGGL(k_marker_ext, dim3(nblk(M, 128)), dim3(128), 0, s, M, c->X.as<double>(),
+  hipLaunchKernelGGL(k_marker_ext, dim3(nblk(M, 64)), dim3(64), 0, s, M, c->X.as<double>(),
                      c->geo.as<double>(), c->x0, c->y0, h, N, c->c2, lab, c->ext.as<double>(),
                      need, c->mknode.as<int>());
   int* rowcnt = c->rowsum.as<int>();
@@ -797,7 +820,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   KFBI_TRY(c->cnode.ensure(sizeof(int) * nch * 6 * MC));
   KFBI_TRY(c->ccount.ensure(sizeof(int) * nch));
   KFBI_TRY(c->mkloc.ensure(sizeof(int) * 6 * M));
-  hipLaunchKernelGGL(k_chunk_nodes, dim3(nch), dim3(64), sizeof(int) * 6 * MC, s, M, MC,
+  hipLaunchKernelGGL(k_chunk_nodes, dim3(nch), dim3(128), sizeof(int) * 12 * MC, s, M, MC,
                      c->mknode.as<int>(), c->cnode.as<int>(), c->ccount.as<int>(),
                      c->mkloc.as<int>());
   KFBI_HIP(hipGetLastError());

@@ -20,6 +20,7 @@ namespace kfbi {
 
 constexpr int kMaxRestart = 64;
 constexpr int kRedBlock = 256;
+constexpr int kRing = kfbi_ctx::kGmresRing;  // Arnoldi status slots in flight
 
 struct GmresStatus {
   double resid;   // |g_{j+1}| (Givens estimate) or a reduced norm
@@ -135,6 +136,98 @@ __global__ void __launch_bounds__(kRedBlock)
   *counter = 0u;
 }
 
+// One Arnoldi step in a single workgroup (used while M (j+1) is small): CGS2 against
+// V_0..V_j, h_{j+1,j} = ||w||, the Hessenberg column with the previous Givens rotations,
+// the new rotation, g, the status word, and V_{j+1} = w / h_{j+1,j}.  All reductions are
+// fixed-order within the workgroup.
+constexpr int kArnThreads = 1024;
+constexpr int kArnPer = 4;  // elements per thread: M <= 4096
+__global__ void __launch_bounds__(kArnThreads)
+    k_arnoldi(int M, int ldv, double* __restrict__ V, int j, const double* __restrict__ w,
+              double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+              double* __restrict__ g, GmresStatus* __restrict__ st) {
+  __shared__ double red[kMaxRestart + 1][kArnThreads / 64];
+  __shared__ double hv[2][kMaxRestart + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = kArnThreads / 64;
+  double wk[kArnPer];
+#pragma unroll
+  for (int u = 0; u < kArnPer; ++u) {
+    const int k = tid + u * kArnThreads;
+    wk[u] = (k < M) ? w[k] : 0.0;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i <= j; ++i) {
+      const double* vi = V + static_cast<size_t>(i) * ldv;
+      double p = 0.0;
+#pragma unroll
+      for (int u = 0; u < kArnPer; ++u) {
+        const int k = tid + u * kArnThreads;
+        if (k < M) p += vi[k] * wk[u];
+      }
+      p = wave_sum(p);
+      if (lane == 0) red[i][wv] = p;
+    }
+    __syncthreads();
+    if (tid <= j) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) s += red[tid][q];
+      hv[pass][tid] = s;
+    }
+    __syncthreads();
+    for (int i = 0; i <= j; ++i) {
+      const double hi = hv[pass][i];
+      const double* vi = V + static_cast<size_t>(i) * ldv;
+#pragma unroll
+      for (int u = 0; u < kArnPer; ++u) {
+        const int k = tid + u * kArnThreads;
+        if (k < M) wk[u] -= hi * vi[k];
+      }
+    }
+  }
+  double p = 0.0;
+#pragma unroll
+  for (int u = 0; u < kArnPer; ++u) p += wk[u] * wk[u];
+  p = wave_sum(p);
+  if (lane == 0) red[0][wv] = p;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int q = 0; q < NW; ++q) s += red[0][q];
+    const double hn = sqrt(s);
+    const int ld = kMaxRestart + 1;
+    double* col = H + static_cast<size_t>(j) * ld;
+    for (int i = 0; i <= j; ++i) col[i] = hv[0][i] + hv[1][i];
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double den = hypot(col[j], col[j + 1]);
+    const double c = col[j] / den, sv = col[j + 1] / den;
+    cs[j] = c;
+    sn[j] = sv;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sv * g[j];
+    g[j] = c * g[j];
+    st->resid = fabs(g[j + 1]);
+    st->hnext = hn;
+    st->breakdown = (hn == 0.0);
+    red[1][0] = hn;
+  }
+  __syncthreads();
+  const double hn = red[1][0];
+  double* vn = V + static_cast<size_t>(j + 1) * ldv;
+#pragma unroll
+  for (int u = 0; u < kArnPer; ++u) {
+    const int k = tid + u * kArnThreads;
+    if (k < M) vn[k] = (hn != 0.0) ? wk[u] / hn : 0.0;
+  }
+}
+
 __global__ void k_scale(int M, const double* __restrict__ w, const double* __restrict__ hn,
                         double* __restrict__ v) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,8 +315,11 @@ struct GmresWork {
   double* w;
   double* part;
   unsigned int* counter;
-  GmresStatus* st;
+  GmresStatus* st;   // status of the last reduction (residual norms)
   GmresStatus* hst;  // pinned host copy
+  GmresStatus* ring;   // per-iteration Arnoldi status, slot j % kRing (device)
+  GmresStatus* hring;  // pinned host copies
+  hipEvent_t* ev;      // one event per ring slot, recorded after its copy
   double* r;
   double* d;
   double* y;
@@ -237,7 +333,9 @@ static int ensure_work(kfbi_ctx* c, int restart, GmresWork* gw) {
   KFBI_TRY(c->gH.ensure(sizeof(double) * (kMaxRestart + 1) * (kMaxRestart + 1)));
   KFBI_TRY(c->gsc.ensure(sizeof(double) * 5 * (kMaxRestart + 2)));
   KFBI_TRY(c->gpart.ensure(sizeof(double) * static_cast<size_t>(nblk) * (kMaxRestart + 2)));
-  KFBI_TRY(c->gcnt.ensure(sizeof(GmresStatus) + 64));
+  KFBI_TRY(c->gcnt.ensure(sizeof(GmresStatus) * (1 + kRing) + 64));
+  for (int q = 0; q < kRing; ++q)
+    if (!c->gev[q]) KFBI_HIP(hipEventCreateWithFlags(&c->gev[q], hipEventDisableTiming));
   KFBI_TRY(c->gw.ensure(sizeof(double) * ldv * 4));
   gw->V = c->gV.as<double>();
   gw->ldv = ldv;
@@ -250,8 +348,11 @@ static int ensure_work(kfbi_ctx* c, int restart, GmresWork* gw) {
   gw->h2 = sc + 4 * (kMaxRestart + 2);
   gw->part = c->gpart.as<double>();
   gw->st = c->gcnt.as<GmresStatus>();
-  gw->counter = reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(c->gcnt.p) + sizeof(GmresStatus));
+  gw->ring = gw->st + 1;
+  gw->counter = reinterpret_cast<unsigned int*>(gw->st + 1 + kRing);
   gw->hst = reinterpret_cast<GmresStatus*>(reinterpret_cast<char*>(c->hpin) + 1024);
+  gw->hring = gw->hst + 1;
+  gw->ev = c->gev;
   double* wb = c->gw.as<double>();
   gw->w = wb;
   gw->r = wb + ldv;
@@ -302,29 +403,55 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
     if (*iters >= maxit) return KFBI_E_NOCONV;
     ++*cycles;
     hipLaunchKernelGGL(k_start, dim3(mb), dim3(256), 0, s, M, gw->r, gw->st, gw->V, gw->g);
+    // Iteration j is enqueued before the status of iteration j-1 is examined, so the GPU
+    // always has work queued while the host waits; when j-1 turns out to be the last one,
+    // iteration j was computed in vain (its Hessenberg column and g entries beyond j-1 are
+    // never used).
+    const bool one_block = (M <= kArnThreads * kArnPer) &&
+                           (static_cast<long long>(M) * restart <= (1 << 17));
     int m = 0;
-    for (int j = 0; j < restart; ++j) {
-      double* vj = gw->V + static_cast<size_t>(j) * gw->ldv;
-      double* vn = gw->V + static_cast<size_t>(j + 1) * gw->ldv;
-      KFBI_TRY(apply_impl(c, op->layer, precision, vj, nullptr, nullptr, op, vj, gw->w));
-      ++*applies;
-      hipLaunchKernelGGL(k_cgs, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j + 1, gw->w,
-                         nullptr, 0, gw->part, gw->counter, gw->h1);
-      hipLaunchKernelGGL(k_cgs, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j + 1, gw->w,
-                         gw->h1, 0, gw->part, gw->counter, gw->h2);
-      hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j, gw->w,
-                         gw->h1, gw->h2, gw->part, gw->counter, gw->H, gw->cs, gw->sn, gw->g,
-                         gw->st);
-      hipLaunchKernelGGL(k_scale, dim3(mb), dim3(256), 0, s, M, gw->w, &gw->st->hnext, vn);
-      KFBI_HIP(hipGetLastError());
+    int launched = 0;
+    const int base = *iters;  // iterations of earlier cycles (< maxit here)
+    bool stop = false;
+    for (int j = 0; j <= restart && !stop; ++j) {
+      if (j < restart && base + launched < maxit) {
+        double* vj = gw->V + static_cast<size_t>(j) * gw->ldv;
+        double* vn = gw->V + static_cast<size_t>(j + 1) * gw->ldv;
+        KFBI_TRY(apply_impl(c, op->layer, precision, vj, nullptr, nullptr, op, vj, gw->w));
+        ++*applies;
+        GmresStatus* sj = gw->ring + (j % kRing);
+        if (one_block) {
+          hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(kArnThreads), 0, s, M, gw->ldv, gw->V, j,
+                             gw->w, gw->H, gw->cs, gw->sn, gw->g, sj);
+        } else {
+          hipLaunchKernelGGL(k_cgs, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j + 1,
+                             gw->w, nullptr, 0, gw->part, gw->counter, gw->h1);
+          hipLaunchKernelGGL(k_cgs, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j + 1,
+                             gw->w, gw->h1, 0, gw->part, gw->counter, gw->h2);
+          hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j,
+                             gw->w, gw->h1, gw->h2, gw->part, gw->counter, gw->H, gw->cs, gw->sn,
+                             gw->g, sj);
+          hipLaunchKernelGGL(k_scale, dim3(mb), dim3(256), 0, s, M, gw->w, &sj->hnext, vn);
+        }
+        KFBI_HIP(hipGetLastError());
+        KFBI_HIP(hipMemcpyAsync(gw->hring + (j % kRing), sj, sizeof(GmresStatus),
+                                hipMemcpyDeviceToHost, s));
+        KFBI_HIP(hipEventRecord(gw->ev[j % kRing], s));
+        ++launched;
+      }
+      if (j == 0) continue;
+      // examine iteration j-1
+      const int q = j - 1;
+      KFBI_HIP(hipEventSynchronize(gw->ev[q % kRing]));
+      const GmresStatus& hs = gw->hring[q % kRing];
       ++*iters;
-      m = j + 1;
-      KFBI_TRY(read_status(c, gw));
-      if (!std::isfinite(gw->hst->resid)) {
+      m = q + 1;
+      if (!std::isfinite(hs.resid)) {
+        KFBI_HIP(hipStreamSynchronize(s));
         set_error("non-finite Arnoldi residual");
         return KFBI_E_NONFINITE;
       }
-      if (gw->hst->resid <= tol * nb || gw->hst->breakdown || *iters >= maxit) break;
+      if (hs.resid <= tol * nb || hs.breakdown || *iters >= maxit || m == restart) stop = true;
     }
     hipLaunchKernelGGL(k_update_x, dim3(mb), dim3(256), 0, s, M, m, gw->ldv, gw->V, gw->H, gw->g, x);
     KFBI_HIP(hipGetLastError());
