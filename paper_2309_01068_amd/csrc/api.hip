@@ -68,7 +68,7 @@ static void release_all(kfbi_ctx* c) {
   DBuf* bufs[] = {&c->vraw, &c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
                   &c->vid,    &c->lab,    &c->armcnt, &c->rowsum,  &c->armrow, &c->armpk,
                   &c->armc,   &c->armk,   &c->colc,   &c->lanef,   &c->cnode,  &c->ccount,
-                  &c->mkloc,  &c->tmat,   &c->pdesc,  &c->rowpart,
+                  &c->mkloc,  &c->tmat,   &c->pdesc,  &c->rowpart, &c->ckoff, &c->cklist,
                   &c->armcoef, &c->intptr, &c->need,    &c->nodeidx, &c->nodei,
                   &c->rowptr, &c->rows,   &c->mknode, &c->ext,     &c->gstat,  &c->mq,
                   &c->armr,   &c->qpart,  &c->ring,   &c->sinT,    &c->sinT32, &c->gband,

@@ -36,6 +36,7 @@ constexpr int kColsPerBlock = 4;
 constexpr int kReg = 4;       // circulant outputs per thread in K1
 constexpr int kNodeBatch = 8; // nodes reduced together in K4
 constexpr int kRingNodes = 16; // free-space box nodes per K1 block
+constexpr int kWinMax = 24;    // derivative window per K1 chunk: at most 16 + 5 markers
 
 // Two-level sine table in LDS: sin/cos(pi m / N) for m = 64 q + r from
 // hs/hc[q] = sin/cos(pi 64 q / N) and ls/lc[r] = sin/cos(pi r / N) by angle addition.
@@ -89,7 +90,10 @@ __global__ void __launch_bounds__(256)
            const double* __restrict__ d1, const double* __restrict__ d2,
            double* __restrict__ mq, double* __restrict__ qpart, const double* __restrict__ wq,
            int N, double x0, double y0, double h, const double* __restrict__ X,
-           const double* __restrict__ geo, double* __restrict__ ring, float* __restrict__ ringT) {
+           const double* __restrict__ geo, double* __restrict__ ring, float* __restrict__ ringT,
+           const int* __restrict__ ckoff, const int* __restrict__ cklist,
+           const double* __restrict__ coefR, const int* __restrict__ kR, int cap,
+           double* __restrict__ rarm) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
   if (static_cast<int>(blockIdx.x) >= nmk) {
@@ -156,20 +160,26 @@ __global__ void __launch_bounds__(256)
     }
     return;
   }
+  // ----- marker chunk [k0, k1): derivatives on the window k0-2 .. k1+2 (the markers the
+  // 6-point interpolation of this chunk's arms reads), marker quantities of the chunk,
+  // and the arm corrections r_a of the arms whose interval starts in the chunk
   const int b = blockIdx.x;
   const int k0 = b * C;
   const int k1 = min(M, k0 + C);
   const int H = k1 - k0;
+  const int HW = H + 5;
+  const int w0 = k0 - 2;
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
-  const int ngr = (H + kReg - 1) / kReg;
+  const int ngr = (HW + kReg - 1) / kReg;
   const int ng = ngr * nd;
-  int ngp = 1;  // groups rounded up to a power of two (at most 8)
+  int ngp = 1;  // groups rounded up to a power of two (at most 16)
   while (ngp < ng) ngp <<= 1;
   const int S = 256 / ngp;  // slices of m
   double* ph = lds;             // M
   double* dl1 = ph + M;         // M
   double* dl2 = dl1 + M;        // M (double layer only)
-  double* part = dl1 + nd * M;  // 4 waves x ngp x kReg
+  double* part = dl1 + nd * M;  // 4 waves x ngp x kReg, then the window quantities
+  double* qw = part + 4 * 16 * kReg;  // 5 x kWinMax
   const double wmine = (k0 + tid < k1) ? wq[k0 + tid] : 0.0;
   for (int m0 = tid; m0 < M; m0 += 256 * 8) {
     double a[8], bb[8], cc[8];
@@ -204,8 +214,8 @@ __global__ void __launch_bounds__(256)
     const double* dd = dv == 0 ? dl1 : dl2;
     const int per = (M + S - 1) / S;
     const int mb = sl * per, me = min(M, mb + per);
-    // outputs k_r = k0 + gr*kReg + r ; window w[r] = d[(k_r - m) mod M]
-    int kb = (k0 + gr * kReg - mb) % M;
+    // outputs k_r = w0 + gr*kReg + r ; window w[r] = d[(k_r - m) mod M]
+    int kb = (w0 + gr * kReg - mb) % M;
     kb += (kb < 0) ? M : 0;
     double w[kReg];
 #pragma unroll
@@ -256,54 +266,68 @@ __global__ void __launch_bounds__(256)
     for (int r = 0; r < kReg; ++r) part[(wv * ngp + lane) * kReg + r] = acc[r];
   }
   __syncthreads();
-  double v1 = 0.0, v2 = 0.0;
-  if (tid < H) {
+  // window quantities Q = (Phi, Phi_a, Phi_aa, Psi, Psi_a) at markers w0 + t
+  double v1 = 0.0, v2 = 0.0, vph = 0.0;
+  if (tid < HW) {
     const int gr = tid / kReg, r = tid % kReg;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       v1 += part[(u * ngp + gr) * kReg + r];
       if (nd == 2) v2 += part[(u * ngp + ngr + gr) * kReg + r];
     }
+    int km = w0 + tid;
+    km += (km < 0) ? M : 0;
+    km -= (km >= M) ? M : 0;
+    vph = ph[km];
+    const bool dl = (layer == KFBI_DOUBLE);
+    qw[0 * kWinMax + tid] = dl ? vph : 0.0;
+    qw[1 * kWinMax + tid] = dl ? v1 : 0.0;
+    qw[2 * kWinMax + tid] = dl ? v2 : 0.0;
+    qw[3 * kWinMax + tid] = dl ? 0.0 : -vph;  // Psi = -psi for the single layer
+    qw[4 * kWinMax + tid] = dl ? 0.0 : -v1;
   }
   // trapezoid partial sum of the density
   double qs = (k0 + tid < k1) ? ph[k0 + tid] * wmine : 0.0;
   for (int k = k0 + 256 + tid; k < k1; k += 256) qs += ph[k] * wq[k];
   __syncthreads();
+  // arm corrections r_a = sum_m l_m sum_q coef_q Q_q(k_a - 2 + m) (Sec. 4.2.1 with the
+  // App. A.1 jumps; coefficients per arm from the interface setup)
+  {
+    const int a0 = ckoff[b], a1 = ckoff[b + 1];
+    for (int e = a0 + tid; e < a1; e += 256) {
+      const int a = cklist[e];
+      const int t0 = kR[a] - k0;  // window offset of marker k_a - 2
+      double r = 0.0;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        double sm = 0.0;
+#pragma unroll
+        for (int qq = 0; qq < 5; ++qq) sm += coefR[(6 + qq) * cap + a] * qw[qq * kWinMax + t0 + m];
+        r += coefR[m * cap + a] * sm;
+      }
+      rarm[a] = r;
+    }
+  }
   qs = block_sum<double>(qs, part);
   // global stores last (no barrier waits on them)
-  if (tid < H) {
-    const int k = k0 + tid;
-    if (layer == KFBI_DOUBLE) {
-      mq[k] = ph[k];
-      mq[M + k] = v1;
-      mq[2 * M + k] = v2;
-      mq[3 * M + k] = 0.0;
-      mq[4 * M + k] = 0.0;
-    } else {  // Psi = -psi
-      mq[k] = 0.0;
-      mq[M + k] = 0.0;
-      mq[2 * M + k] = 0.0;
-      mq[3 * M + k] = -ph[k];
-      mq[4 * M + k] = -v1;
-    }
+  if (tid >= 2 && tid < 2 + H) {
+    const int k = w0 + tid;
+#pragma unroll
+    for (int qq = 0; qq < 5; ++qq) mq[qq * M + k] = qw[qq * kWinMax + tid];
   }
   if (tid == 0) qpart[b] = qs;
 }
 
 // ---------------------------------------------------------------------------------- K2
-// One block per row part (a row's arms in groups of at most kArmsPerPart).  The part's
-// arm corrections
-//   r_a = sum_m l_m sum_q coef_q Q_q(k_a - 2 + m)
-// (6-point interpolation of the marker quantities Q = (Phi, Phi_a, Phi_aa, Psi, Psi_a))
-// are formed one per thread; then every thread evaluates the partial transform
+// One block per row part (a row's arms in groups of at most kArmsPerPart, corrections r_a
+// from K1 in part-slot order); every thread evaluates the partial transform
 // T_part[p] = sum_a r_a sin(p i_a pi / N) for PT consecutive modes p, starting from the
 // two-level table and rotating in steps of i_a pi / N.  Parts of one row are summed in
 // part order by the solve kernel.
 template <class T, int PT>
 __global__ void __launch_bounds__(256)
-    k_rowdst(int N, int M, int P, const int4* __restrict__ pdesc, const double* __restrict__ coefR,
-             const int* __restrict__ kR, const double* __restrict__ mq,
-             const T* __restrict__ sinT, T* __restrict__ Tg) {
+    k_rowdst(int N, int P, const int4* __restrict__ pdesc, const double* __restrict__ rslot,
+             const int* __restrict__ iR, const T* __restrict__ sinT, T* __restrict__ Tg) {
   __shared__ T tab[sintab2_size<T>(4096)];
   __shared__ T rr[kArmsPerPart];
   __shared__ int ii[kArmsPerPart];
@@ -311,31 +335,13 @@ __global__ void __launch_bounds__(256)
   const int mask = 2 * N - 1;
   const int tid = threadIdx.x;
   const int q = blockIdx.x;
-  const int cap = kArmsPerPart * P;
   const int4 d = pdesc[q];
   SinTab2<T> st2;
   st2.stage(tab, N, sinT);
-  if (tid < kArmsPerPart) {  // slot tid of the part (empty slots have zero coefficients)
+  if (tid < kArmsPerPart) {  // slot tid of the part (empty slots have r = 0, i = 0)
     const int a = q * kArmsPerPart + tid;
-    const int k = kR[a];
-    const int i = kR[cap + a];
-    double l[6], cf[5];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) l[m] = coefR[m * cap + a];
-#pragma unroll
-    for (int qq = 0; qq < 5; ++qq) cf[qq] = coefR[(6 + qq) * cap + a];
-    double r = 0.0;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      int km = k - 2 + m;
-      km = (km < 0) ? km + M : (km >= M ? km - M : km);
-      double sm = 0.0;
-#pragma unroll
-      for (int qq = 0; qq < 5; ++qq) sm += cf[qq] * mq[qq * M + km];
-      r += l[m] * sm;
-    }
-    rr[tid] = static_cast<T>(r);
-    ii[tid] = i;
+    rr[tid] = static_cast<T>(rslot[a]);
+    ii[tid] = iR[a];
   }
   const int na = d.z - d.y;
   __syncthreads();
@@ -357,9 +363,24 @@ __global__ void __launch_bounds__(256)
       s = t2;
     }
   }
+  if constexpr (PT % 4 == 0) {
+    // whole groups of four modes: one 32-byte (FP64) or 16-byte (FP32) piece each; modes
+    // beyond n land in the padding of the last group
 #pragma unroll
-  for (int k = 0; k < PT; ++k)
-    if (p0 + k <= n) Tg[grp_index(p0 + k, q, P)] = acc[k];
+    for (int k = 0; k < PT; k += 4) {
+      T* dst = Tg + grp_index(p0 + k, q, P);
+      if constexpr (sizeof(T) == 8) {
+        reinterpret_cast<double2*>(dst)[0] = make_double2(acc[k], acc[k + 1]);
+        reinterpret_cast<double2*>(dst)[1] = make_double2(acc[k + 2], acc[k + 3]);
+      } else {
+        reinterpret_cast<float4*>(dst)[0] = make_float4(acc[k], acc[k + 1], acc[k + 2], acc[k + 3]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PT; ++k)
+      if (p0 + k <= n) Tg[grp_index(p0 + k, q, P)] = acc[k];
+  }
 }
 
 // ---------------------------------------------------------------------------------- K3
@@ -814,8 +835,8 @@ static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jl
   hipStream_t s = c->stream;
   constexpr int PT = (64 * E + 255) / 256;
   if (P > 0 && (stages & 2))
-    hipLaunchKernelGGL((k_rowdst<T, PT>), dim3(P), dim3(256), 0, s, N, M, P, c->pdesc.as<int4>(),
-                       c->armc.as<double>(), c->armk.as<int>(), c->mq.as<double>(), sinT, Tg);
+    hipLaunchKernelGGL((k_rowdst<T, PT>), dim3(P), dim3(256), 0, s, N, P, c->pdesc.as<int4>(),
+                       c->armr.as<double>(), c->armk.as<int>() + c->arm_cap, sinT, Tg);
   if (ev) hipEventRecord(ev[2], s);
   const int ngrp = nblk(n, kColsPerBlock);
   const int nb = ((ngrp + 7) / 8) * 8;
@@ -879,7 +900,8 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
                      c->dvec.as<double>(), c->dvec.as<double>() + M, c->mq.as<double>(),
                      c->qpart.as<double>(), c->ext.as<double>() + kExtQ * M, N, c->x0, c->y0,
                      c->h, c->X.as<double>(), c->geo.as<double>(), ring64,
-                     sizeof(T) == 4 ? ring32 : nullptr);
+                     sizeof(T) == 4 ? ring32 : nullptr, c->ckoff.as<int>(), c->cklist.as<int>(),
+                     c->armc.as<double>(), c->armk.as<int>(), c->arm_cap, c->armr.as<double>());
   if (c->box_bc == KFBI_BOX_FREESPACE) {
     ringT = sizeof(T) == 8 ? reinterpret_cast<T*>(ring64) : reinterpret_cast<T*>(ring32);
   } else if (c->box_bc == KFBI_BOX_USER) {

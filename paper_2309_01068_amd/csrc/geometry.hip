@@ -204,19 +204,20 @@ __device__ inline double newton_root(const double* c, double g, double a, double
   return t;
 }
 
-__global__ void __launch_bounds__(64) k_fill_cross(int M, const double* __restrict__ X, double x0, double y0, double h,
-                             int N, const int* __restrict__ off, int nh, Crossing* __restrict__ cr,
-                             int cap, GeoStatus* st) {
+// Crossing records in marker order: (line, marker interval, sub-interval in t) per
+// crossing; the root itself is found by k_cross_newton, one thread per crossing.
+__global__ void __launch_bounds__(64) k_fill_cross(int M, const double* __restrict__ X, double x0,
+                                                   double y0, double h, int N,
+                                                   const int* __restrict__ off, int nh,
+                                                   Crossing* __restrict__ cr, int cap,
+                                                   GeoStatus* st) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
   for (int ax = 0; ax < 2; ++ax) {
     const double* v = (ax == 0) ? X + M : X;
-    const double* o = (ax == 0) ? X : X + M;
     const double lo = (ax == 0) ? y0 : x0;
-    const double olo = (ax == 0) ? x0 : y0;
-    double cv[6], co[6], vals[kSub + 1];
+    double cv[6], vals[kSub + 1];
     stencil_values(v, k, M, cv);
-    stencil_values(o, k, M, co);
     sub_values(cv, vals);
     int jb, je;
     line_range(vals, lo, h, N, &jb, &je);
@@ -225,27 +226,14 @@ __global__ void __launch_bounds__(64) k_fill_cross(int M, const double* __restri
       const double g = lo + j * h;
       for (int sb = 0; sb < kSub; ++sb) {
         if ((vals[sb] >= g) == (vals[sb + 1] >= g)) continue;
-        const double t = newton_root(cv, g, vals[sb] - g, vals[sb + 1] - g,
-                                     static_cast<double>(sb) / kSub,
-                                     static_cast<double>(sb + 1) / kSub);
-        double w[6];
-        lagrange6(t, w, nullptr);
-        double pos = 0.0;
-#pragma unroll
-        for (int m = 0; m < 6; ++m) pos += w[m] * co[m];
-        int seg = static_cast<int>(floor((pos - olo) / h));
-        for (int r = 0; r < 2; ++r) {
-          if (olo + (seg + 1) * h <= pos) seg += 1;
-          if (olo + seg * h > pos) seg -= 1;
-        }
         if (slot < cap) {
           Crossing c;
           c.line = j;
           c.k = k;
-          c.seg = seg;
+          c.seg = sb;  // sub-interval until k_cross_newton
           c.horiz = (ax == 0);
-          c.t = t;
-          c.pos = pos;
+          c.t = 0.0;
+          c.pos = 0.0;
           cr[slot] = c;
         } else {
           atomicMax(&st->err, 4);
@@ -254,6 +242,43 @@ __global__ void __launch_bounds__(64) k_fill_cross(int M, const double* __restri
       }
     }
   }
+}
+
+// Root of the crossing in its sub-interval (safeguarded Newton), the other coordinate and
+// the grid segment lo + seg h <= pos < lo + (seg + 1) h.
+__global__ void __launch_bounds__(64) k_cross_newton(int nc, int M, const double* __restrict__ X,
+                                                     double x0, double y0, double h,
+                                                     Crossing* __restrict__ cr) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  Crossing x = cr[c];
+  const int ax = x.horiz ? 0 : 1;
+  const double* v = (ax == 0) ? X + M : X;
+  const double* o = (ax == 0) ? X : X + M;
+  const double lo = (ax == 0) ? y0 : x0;
+  const double olo = (ax == 0) ? x0 : y0;
+  double cv[6], co[6], vals[kSub + 1];
+  stencil_values(v, x.k, M, cv);
+  stencil_values(o, x.k, M, co);
+  sub_values(cv, vals);
+  const int sb = x.seg;
+  const double g = lo + x.line * h;
+  const double t = newton_root(cv, g, vals[sb] - g, vals[sb + 1] - g,
+                               static_cast<double>(sb) / kSub, static_cast<double>(sb + 1) / kSub);
+  double w[6];
+  lagrange6(t, w, nullptr);
+  double pos = 0.0;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) pos += w[m] * co[m];
+  int seg = static_cast<int>(floor((pos - olo) / h));
+  for (int r = 0; r < 2; ++r) {
+    if (olo + (seg + 1) * h <= pos) seg += 1;
+    if (olo + seg * h > pos) seg -= 1;
+  }
+  x.t = t;
+  x.pos = pos;
+  x.seg = seg;
+  cr[c] = x;
 }
 
 // Segment marking with pairs dropped: the first crossing of a segment stores its id, a
@@ -484,6 +509,20 @@ __global__ void k_part_soa(int P, const int4* __restrict__ pdesc, const ArmCoef*
     kR[s] = 0;
     kR[cap + s] = 0;
   }
+}
+
+// Arm slots grouped by the marker chunk of their interval (the chunks of the derivative
+// kernel, which forms their corrections): counts, then slots from a cursor per chunk
+// (order within a chunk is free).  Empty slots (column 0) are skipped.
+__global__ void k_chunk_arm_count(int cap, int MC, const int* __restrict__ kR,
+                                  int* __restrict__ cnt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < cap && kR[cap + s] != 0) atomicAdd(&cnt[kR[s] / MC], 1);
+}
+__global__ void k_chunk_arm_fill(int cap, int MC, const int* __restrict__ kR,
+                                 int* __restrict__ cur, int* __restrict__ list) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < cap && kR[cap + s] != 0) list[atomicAdd(&cur[kR[s] / MC], 1)] = s;
 }
 
 // Rows split into parts of at most kArmsPerPart arms: parts per row, then descriptors
@@ -780,6 +819,9 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   Crossing* cr = c->cross.as<Crossing>();
   hipLaunchKernelGGL(k_fill_cross, dim3(nblk(M, 64)), dim3(64), 0, s, M, c->X.as<double>(), c->x0,
                      c->y0, h, N, cnt, nh, cr, nc, st);
+  if (nc > 0)
+    hipLaunchKernelGGL(k_cross_newton, dim3(nblk(nc, 64)), dim3(64), 0, s, nc, M,
+                       c->X.as<double>(), c->x0, c->y0, h, cr);
   int* hid = c->hid.as<int>();
   int* vid = c->vid.as<int>();
   KFBI_HIP(hipMemsetAsync(hid, 0xff, sizeof(int) * n1 * n1, s));
@@ -857,6 +899,23 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
       hipLaunchKernelGGL(k_part_soa, dim3(nblk(cap, 256)), dim3(256), 0, s, P,
                          c->pdesc.as<int4>(), c->armcoef.as<ArmCoef>(), c->armpk.as<int>(),
                          c->armc.as<double>(), c->armk.as<int>());
+    // per-apply corrections r (zero in empty slots) and the marker-chunk lists of slots
+    KFBI_TRY(c->armr.ensure(sizeof(double) * cap));
+    KFBI_HIP(hipMemsetAsync(c->armr.p, 0, sizeof(double) * cap, s));
+    const int nmk = c->n_mk_blocks;
+    KFBI_TRY(c->ckoff.ensure(sizeof(int) * (2 * nmk + 2)));
+    KFBI_TRY(c->cklist.ensure(sizeof(int) * cap));
+    int* ckoff = c->ckoff.as<int>();
+    int* ckcur = ckoff + nmk + 1;
+    KFBI_HIP(hipMemsetAsync(ckoff, 0, sizeof(int) * (nmk + 1), s));
+    if (P > 0)
+      hipLaunchKernelGGL(k_chunk_arm_count, dim3(nblk(cap, 256)), dim3(256), 0, s, cap,
+                         c->mk_chunk, c->armk.as<int>(), ckoff);
+    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, nmk + 1, ckoff, nullptr);
+    KFBI_HIP(hipMemcpyAsync(ckcur, ckoff, sizeof(int) * nmk, hipMemcpyDeviceToDevice, s));
+    if (P > 0)
+      hipLaunchKernelGGL(k_chunk_arm_fill, dim3(nblk(cap, 256)), dim3(256), 0, s, cap,
+                         c->mk_chunk, c->armk.as<int>(), ckcur, c->cklist.as<int>());
   }
   KFBI_HIP(hipGetLastError());
   c->st = *hs;

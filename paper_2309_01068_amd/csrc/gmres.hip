@@ -148,6 +148,7 @@ __global__ void __launch_bounds__(kArnThreads)
               double* __restrict__ g, GmresStatus* __restrict__ st) {
   __shared__ double red[kMaxRestart + 1][kArnThreads / 64];
   __shared__ double hv[2][kMaxRestart + 1];
+  __shared__ double wsh[kArnThreads * kArnPer];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = kArnThreads / 64;
   double wk[kArnPer];
@@ -157,25 +158,23 @@ __global__ void __launch_bounds__(kArnThreads)
     wk[u] = (k < M) ? w[k] : 0.0;
   }
   for (int pass = 0; pass < 2; ++pass) {
-    for (int i = 0; i <= j; ++i) {
+    // stage w, then wavefront q takes the inner products <V_i, w> for i = q, q + 16, ...
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kArnPer; ++u) {
+      const int k = tid + u * kArnThreads;
+      if (k < M) wsh[k] = wk[u];
+    }
+    __syncthreads();
+    for (int i = wv; i <= j; i += NW) {
       const double* vi = V + static_cast<size_t>(i) * ldv;
       double p = 0.0;
-#pragma unroll
-      for (int u = 0; u < kArnPer; ++u) {
-        const int k = tid + u * kArnThreads;
-        if (k < M) p += vi[k] * wk[u];
-      }
+      for (int k = lane; k < M; k += 64) p += vi[k] * wsh[k];
       p = wave_sum(p);
-      if (lane == 0) red[i][wv] = p;
+      if (lane == 0) hv[pass][i] = p;
     }
     __syncthreads();
-    if (tid <= j) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < NW; ++q) s += red[tid][q];
-      hv[pass][tid] = s;
-    }
-    __syncthreads();
+    // w -= sum_i h_i V_i
     for (int i = 0; i <= j; ++i) {
       const double hi = hv[pass][i];
       const double* vi = V + static_cast<size_t>(i) * ldv;
