@@ -468,20 +468,38 @@ __global__ void __launch_bounds__(256)
     const T ih2 = static_cast<T>(1.0 / (h * h));
     // left (i=0) and right (i=N) box nodes next to (1, j) and (N-1, j)
     const int n1 = N + 1;
-    for (int j = 1 + tid; j <= n; j += 256) {
-      const T gl = ring[2 * n1 + j], gr = ring[3 * n1 + j];
+    T s1[kColsPerBlock], sn[kColsPerBlock];
 #pragma unroll
-      for (int c = 0; c < kColsPerBlock; ++c)
-        col[c][slot<E>(j)] -=
-            ih2 * (gl * sinTg[(p0 + c) & mask] + gr * sinTg[((p0 + c) * n) & mask]);
+    for (int c = 0; c < kColsPerBlock; ++c) {
+      s1[c] = sinTg[(p0 + c) & mask];
+      sn[c] = sinTg[((p0 + c) * n) & mask];
+    }
+    constexpr int RJ = (64 * E + 255) / 256;
+    T gl[RJ], gr[RJ];
+#pragma unroll
+    for (int u = 0; u < RJ; ++u) {
+      const int j = 1 + tid + 256 * u;
+      gl[u] = (j <= n) ? ring[2 * n1 + j] : T(0);
+      gr[u] = (j <= n) ? ring[3 * n1 + j] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < RJ; ++u) {
+      const int j = 1 + tid + 256 * u;
+      if (j <= n)
+#pragma unroll
+        for (int c = 0; c < kColsPerBlock; ++c)
+          col[c][slot<E>(j)] -= ih2 * (gl[u] * s1[c] + gr[u] * sn[c]);
     }
     __syncthreads();
-    // bottom (j=0) and top (j=N) box rows: a full sine sum each
+    // bottom (j=0) and top (j=N) box rows: a full sine sum each, loads issued together
     T sb = T(0), st = T(0);
-    for (int i = 1 + lane; i <= n; i += 64) {
-      const T sv = sinTg[(p * i) & mask];
-      sb += ring[i] * sv;
-      st += ring[n1 + i] * sv;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int i = 1 + lane + 64 * u;
+      const bool in = (i <= n);
+      const T sv = in ? sinTg[(p * i) & mask] : T(0);
+      sb += (in ? ring[i] : T(0)) * sv;
+      st += (in ? ring[n1 + i] : T(0)) * sv;
     }
     sb = wave_sum(sb);
     st = wave_sum(st);
