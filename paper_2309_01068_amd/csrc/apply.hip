@@ -35,7 +35,7 @@ namespace kfbi {
 constexpr int kColsPerBlock = 4;
 constexpr int kReg = 4;       // circulant outputs per thread in K1
 constexpr int kNodeBatch = 8; // nodes reduced together in K4
-constexpr int kRingNodes = 16; // free-space box nodes per K1 block
+constexpr int kRingNodes = 8;  // free-space box nodes per K1 block
 constexpr int kWinMax = 24;    // derivative window per K1 chunk: at most 16 + 5 markers
 
 // Two-level sine table in LDS: sin/cos(pi m / N) for m = 64 q + r from
@@ -112,28 +112,39 @@ __global__ void __launch_bounds__(256)
       zy = (side == 0) ? y0 : (side == 1 ? y0 + N * h : y0 + r * h);
     }
     // markers staged in LDS in chunks of 256: (x, y, phi y_a, phi x_a) for the double
-    // layer, (x, y, psi s_a / 2) for the single layer; slice sl takes 16 of each chunk
+    // layer, (x, y, psi s_a / 2) for the single layer; slice sl takes 256/S of each chunk
     double* cx = lds;
     double* cy = cx + 256;
     double* ca = cy + 256;
     double* cb = ca + 256;
     double acc = 0.0;
-    for (int c0 = 0; c0 < M; c0 += 256) {
+    // software pipeline: the next chunk's markers are loaded while this one is summed
+    double px = 0.0, py = 0.0, pa = 0.0, pb = 0.0;
+    auto fetch = [&](int c0) {
       const int k = c0 + tid;
-      __syncthreads();
       if (k < M) {
-        cx[tid] = X[k];
-        cy[tid] = X[M + k];
+        px = X[k];
+        py = X[M + k];
         if (layer == KFBI_DOUBLE) {
-          ca[tid] = dens[k] * geo[M + k];
-          cb[tid] = dens[k] * geo[k];
+          const double f = dens[k];
+          pa = f * geo[M + k];
+          pb = f * geo[k];
         } else {
-          ca[tid] = 0.5 * dens[k] * geo[4 * M + k];
+          pa = 0.5 * dens[k] * geo[4 * M + k];
         }
       }
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < M; c0 += 256) {
       __syncthreads();
+      cx[tid] = px;
+      cy[tid] = py;
+      ca[tid] = pa;
+      cb[tid] = pb;
+      __syncthreads();
+      if (c0 + 256 < M) fetch(c0 + 256);
       const int nk = min(256, M - c0);
-      const int q0 = sl * 16, q1 = min(nk, q0 + 16);
+      const int q0 = sl * (256 / S), q1 = min(nk, q0 + 256 / S);
       if (layer == KFBI_DOUBLE) {
 #pragma unroll 4
         for (int q = q0; q < q1; ++q) {
