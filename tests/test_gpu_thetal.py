@@ -155,3 +155,36 @@ def test_errors():
         th.init(dev(W.circle(64, 1.95)))                     # init fine, but too close to the box
         th.step()
     assert e.value.code == kfbi.E_GEOMETRY
+
+
+def test_evolution_parity_over_50_steps():
+    """The GPU evolution follows the oracle over 50 steps (256 markers, 256^2 grid):
+    eta, L and Xbar compared at steps 1, 10 and 50."""
+    box = W.box(-2, 2, 256)
+    X = W.hs3(256)
+    st, prm = oracle_state(X, 256, box, 1e-3, 1.0, 1e-3)
+    th = make(box, 256, 1e-3, 1.0, 1e-3)
+    th.init(dev(X))
+    for k in range(1, 51):
+        st, _ = T.hs_step(st, prm)
+        th.step()
+        if k in (1, 10, 50):
+            print(f"[case] compare at step {k}", flush=True)
+            s = th.get_state()
+            assert np.max(np.abs(host(s["eta"]) - st.eta)) <= 1e-8, k
+            assert abs(s["scal"][0] - st.L) <= 1e-10 * st.L, k
+            assert np.max(np.abs(np.array(s["scal"][1:3]) - st.Xbar)) <= 1e-9, k
+
+
+def test_area_conserved_without_injection():
+    """With J = 0 the enclosed area is conserved (to the discretisation error) and the
+    length decreases (surface tension relaxes the curve)."""
+    box = W.box(-1.5, 1.5, 256)
+    X = W.polar_curve(lambda a: 0.8 + 0.2 * np.cos(4 * a), 256)
+    th = make(box, 256, 1e-2, 0.0, 2e-3)
+    th.init(dev(X))
+    recs = th.run(40)
+    areas = np.array([r["area"] for r in recs])
+    lengths = np.array([r["length"] for r in recs])
+    assert np.max(np.abs(areas - areas[0])) <= 1e-3 * areas[0]
+    assert np.all(np.diff(lengths) < 0)
