@@ -55,12 +55,14 @@ def parse():
 
 def algorithmic_bytes(info, N, M, wbytes, layer_double=False):
     """Bytes each kernel of one apply must move at least (per launch), from its inputs and
-    outputs: n = N-1 sine modes, P row parts, nb = row_hi-row_lo+1 rows of G written by the
-    column solve, R = rows holding interpolation nodes, w = 8 (FP64) or 4 (FP32).
+    outputs: n = N-1 sine modes, A arms, P row parts, nb = row_hi-row_lo+1 rows of G written
+    by the column solve, R = rows holding interpolation nodes, w = 8 (FP64) or 4 (FP32).
       k_prep           density, two differentiation vectors, trapezoid weights (8 B each per
-                       marker) in; five marker quantities and the weighted sum out
-      k_rowdst         per arm 11 coefficients (8 B), marker index and packed node (4 B each),
-                       per part one row of n transformed values out (P n w)
+                       marker) in; five marker quantities and the weighted sum out; per arm
+                       11 coefficients, its marker and its list entry (8 + 4 + 4 B) in and
+                       its correction (8 B) out
+      k_rowdst         per arm the correction and its column (8 + 4 B), per part its
+                       descriptor (16 B) in; per part one row of n transformed values out
       k_colsolve       the P n w part rows in, the nb n w rows of G out, per-mode constants
                        (3 + 128 doubles per mode) and the row-to-part offsets
       k_nodes_extract  each of the R node rows of G once (R n w), per marker the 51
@@ -73,8 +75,8 @@ def algorithmic_bytes(info, N, M, wbytes, layer_double=False):
     R = info["n_rows"]
     A = info["n_arms"]
     return {
-        "k_prep": M * 8 * (1 + 2 + 1) + M * 8 * 5 + 8 * (M // 8 + 1),
-        "k_rowdst": A * (11 * 8 + 4 + 4) + P * 16 + P * n * wbytes,
+        "k_prep": M * 8 * (1 + 2 + 1) + M * 8 * 5 + 8 * (M // 8 + 1) + A * (11 * 8 + 4 + 4 + 8),
+        "k_rowdst": A * (8 + 4) + P * 16 + P * n * wbytes,
         "k_colsolve": P * n * wbytes + nb * n * wbytes + n * 8 * (3 + 128) + (N + 2) * 4,
         "k_nodes_extract": R * n * wbytes + M * (51 * 8 + 5 * 8 + 6 * 4 + 4 * 8),
     }
