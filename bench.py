@@ -53,7 +53,7 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(info, N, M, wbytes, layer_double=False):
+def algorithmic_bytes(info, N, M, wbytes, layer_double=False, batch=1):
     """Bytes each kernel of one apply must move at least (per launch), from its inputs and
     outputs: n = N-1 sine modes, A arms, P row parts, nb = row_hi-row_lo+1 rows of G written
     by the column solve, R = rows holding interpolation nodes, w = 8 (FP64) or 4 (FP32).
@@ -68,17 +68,22 @@ def algorithmic_bytes(info, N, M, wbytes, layer_double=False):
       k_nodes_extract  each of the R node rows of G once (R n w), per marker the 51
                        extraction values and 5 marker quantities (8 B), 6 stencil slots (4 B),
                        four traces out (8 B each)
+    For a batch of B densities the per-density terms count B times and the geometry terms
+    (differentiation vectors, weights, arm coefficients and columns, part descriptors,
+    per-mode constants, extraction values, stencil slots) once.
     """
     n = N - 1
     P = info["n_parts"]
     nb = info["row_hi"] - info["row_lo"] + 1
     R = info["n_rows"]
     A = info["n_arms"]
+    B = batch
     return {
-        "k_prep": M * 8 * (1 + 2 + 1) + M * 8 * 5 + 8 * (M // 8 + 1) + A * (11 * 8 + 4 + 4 + 8),
-        "k_rowdst": A * (8 + 4) + P * 16 + P * n * wbytes,
-        "k_colsolve": P * n * wbytes + nb * n * wbytes + n * 8 * (3 + 128) + (N + 2) * 4,
-        "k_nodes_extract": R * n * wbytes + M * (51 * 8 + 5 * 8 + 6 * 4 + 4 * 8),
+        "k_prep": B * (M * 8 * (1 + 5) + 8 * (M // 8 + 1) + A * 8)
+        + M * 8 * (2 + 1) + A * (11 * 8 + 4 + 4),
+        "k_rowdst": B * (A * 8 + P * n * wbytes) + A * 4 + P * 16,
+        "k_colsolve": B * (P * n * wbytes + nb * n * wbytes) + n * 8 * (3 + 128) + (N + 2) * 4,
+        "k_nodes_extract": B * (R * n * wbytes + M * (5 * 8 + 4 * 8)) + M * (51 * 8 + 6 * 4),
     }
 
 
@@ -217,6 +222,7 @@ def main():
 
     if not a.no_extra:
         result["extra"] = extras(kf, W, torch, np, dev, dens, layer)
+        result["batched"] = batched(kf, W, torch, np, dev, a)
         result["interior_dirichlet"] = interior_dirichlet(kf, W, torch, np, dev)
         result["hele_shaw"] = hele_shaw(kf, W, torch, np, dev, a)
         result["warm_start"] = warm_start(kf, W, torch, np, dev, a)
@@ -283,6 +289,41 @@ def extras(kf, W, torch, np, dev, dens, layer):
         out[f"gmres_hs_{'f64' if prec == 0 else 'f32ir'}"] = {
             "seconds": round(el, 5), "iters": st["iters"], "relres": st["relres"],
             "applies64": st["applies64"], "applies32": st["applies32"]}
+    return out
+
+
+def batched(kf, W, torch, np, dev, a):
+    """Batched apply (one launch per kernel for B densities) on the headline workload:
+    densities/s for several B, and per-kernel replay durations with the algorithmic bytes
+    of B densities (the geometry-only terms counted once)."""
+    M, N, c2 = 2048, a.N, 1000.0
+    box = W.box(-1.0, 1.0, N)
+    ctx = kf.Context(box.x0, box.y0, box.side, N, c2, kf.BOX_ZERO, M, max_batch=64)
+    ctx.set_interface(torch.tensor(W.star(M), device=dev))
+    info = ctx.info()
+    D = torch.tensor(np.stack([W.fourier_density(M, seed=s) for s in range(64)]), device=dev)
+    out = {}
+    for B in (1, 4, 16, 64):
+        d = D[:B].contiguous()
+        res = ctx.apply_batch(kf.SINGLE, d, a.precision)
+        reps = max(20, 2000 // B)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.apply_batch(kf.SINGLE, d, a.precision, out=res)
+        e1.record()
+        torch.cuda.synchronize()
+        secs = e0.elapsed_time(e1) / 1e3
+        kern = [ctx.profile_kernel(q, reps=max(10, a.reps // B)) for q in range(4)]
+        byts = algorithmic_bytes(info, N, M, 8 if a.precision == 0 else 4, batch=B)
+        out[f"B{B}"] = {
+            "densities_per_s": round(B * reps / secs, 1), "us_per_batch": round(1e6 * secs / reps, 2),
+            "kernels": {STAGES[q]: {"avg_us": round(kern[q], 3), "bytes": byts[STAGES[q]],
+                                    "GB_s": round(byts[STAGES[q]] / kern[q] / 1e3, 1)}
+                        for q in range(4)}}
+    ctx.close()
     return out
 
 

@@ -61,7 +61,9 @@ typedef struct kfbi_ctx kfbi_ctx;
 
 /* The box [x0, x0+side] x [y0, y0+side] with N intervals per side, h = side/N,
  * nodes (i, j), i, j = 0..N (Sec. 4.2).  N a power of two, 64 <= N <= 2048; the operator is
- * Delta - c2 (c2 >= 0).  max_markers bounds M (even, 16 <= M <= 4096). */
+ * Delta - c2 (c2 >= 0).  max_markers bounds M (even, 16 <= M <= 4096).  max_batch bounds
+ * the densities of one kfbi_apply_batch call (0 is taken as 1; at most 64); the grid
+ * workspaces are allocated max_batch times. */
 typedef struct {
   double x0, y0, side;
   int N;
@@ -69,6 +71,7 @@ typedef struct {
   int box_bc;
   int max_markers;
   void* stream; /* hipStream_t */
+  int max_batch;
 } kfbi_grid;
 
 /* Sizes of the current interface discretisation (host struct, filled on request). */
@@ -127,6 +130,15 @@ int kfbi_get_info(const kfbi_ctx* ctx, kfbi_info* info);
 int kfbi_apply(kfbi_ctx* ctx, int layer, int precision, const double* density_dev,
                const double* ring_dev, const kfbi_out* out);
 
+/* B independent applies of the same layer on the installed interface, in one launch per
+ * stage (the densities share the geometry; Sec. 4 for each of them).  density_dev
+ * [B][M] (row b = density b); ring_dev [B][4(N+1)] (KFBI_BOX_USER) or NULL; the outputs
+ * v_plus, v_minus, dn_plus, dn_minus are [B][M] device arrays or NULL, and out->grid must
+ * be NULL.  Each result equals, bit for bit, kfbi_apply on that density alone.
+ * 1 <= B <= max_batch of the context (else KFBI_E_INVALID).  Asynchronous. */
+int kfbi_apply_batch(kfbi_ctx* ctx, int layer, int precision, int B, const double* density_dev,
+                     const double* ring_dev, const kfbi_out* out);
+
 /* Discrete boundary integral operator A x = a x + b * trace_side(layer[x])
  *                                          + q * sum_k x_k s_a,k (2 pi / M).
  * Hele-Shaw (Sec. 3.1, eq. bie-HS): {DOUBLE, MINUS, a=0, b=1, q=1} with the free-space
@@ -176,8 +188,8 @@ int kfbi_profile(kfbi_ctx* ctx, int on);
 int kfbi_profile_read(kfbi_ctx* ctx, double* ms_total, long* napplies);
 
 /* Measurement hook: replays kernel `stage` (0..3, numbered as above) of the last
- * kfbi_apply/kfbi_operator call reps times back to back on the context stream, on the
- * library's own buffers, and returns the average launch duration in microseconds
+ * kfbi_apply/kfbi_apply_batch/kfbi_operator call (with the batch size of that call) reps
+ * times back to back on the context stream, on the library's own buffers, and returns the average launch duration in microseconds
  * (HIP events around the replays; one untimed launch first).  Stage 0 reads a library
  * workspace as its density and stage 3 writes no caller output, so no caller array is
  * touched.  Synchronises.  KFBI_E_STATE if no apply ran since kfbi_set_interface. */

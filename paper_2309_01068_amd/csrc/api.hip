@@ -118,6 +118,10 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
     set_error("max_markers must be in [16, 4096]");
     return KFBI_E_INVALID;
   }
+  if (g->max_batch < 0 || g->max_batch > 64) {
+    set_error("max_batch must be in [0, 64] (got %d)", g->max_batch);
+    return KFBI_E_INVALID;
+  }
   kfbi_ctx* c = new (std::nothrow) kfbi_ctx();
   if (!c) {
     set_error("out of host memory");
@@ -131,6 +135,7 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
   c->c2 = g->c2;
   c->box_bc = g->box_bc;
   c->max_markers = g->max_markers;
+  c->max_batch = g->max_batch > 0 ? g->max_batch : 1;
   c->stream = static_cast<hipStream_t>(g->stream);
   int st = KFBI_OK;
   auto fail = [&](int code) {
@@ -145,6 +150,7 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
   const size_t n1sq = static_cast<size_t>(N + 1) * (N + 1);
   const size_t n = N - 1;
   const int Mx = g->max_markers;
+  const size_t Bx = c->max_batch;
   if ((st = c->gstat.ensure(sizeof(GeoStatus))) ||
       (st = c->hid.ensure(sizeof(int) * n1sq)) || (st = c->vid.ensure(sizeof(int) * n1sq)) ||
       (st = c->vraw.ensure(sizeof(int) * n1sq)) ||
@@ -157,13 +163,13 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
       (st = c->rowpart.ensure(sizeof(int) * (N + 2))) ||
       (st = c->nodei.ensure(sizeof(int) * 6 * Mx)) ||
       (st = c->nodeval.ensure(sizeof(double) * 6 * Mx)) ||
-      (st = c->mq.ensure(sizeof(double) * 5 * Mx)) ||
-      (st = c->qpart.ensure(sizeof(double) * (Mx + 64))) ||
-      (st = c->ring.ensure(sizeof(double) * 8 * (N + 1))) ||
+      (st = c->mq.ensure(sizeof(double) * 5 * Mx * Bx)) ||
+      (st = c->qpart.ensure(sizeof(double) * (Mx + 64) * Bx)) ||
+      (st = c->ring.ensure(sizeof(double) * 8 * (N + 1) * Bx)) ||
       (st = c->sinT.ensure(sizeof(double) * 2 * N)) ||
       (st = c->sinT32.ensure(sizeof(float) * 2 * N)) ||
-      (st = c->gband.ensure(sizeof(double) * n * N)) ||
-      (st = c->tmpM.ensure(sizeof(double) * 4 * Mx)))
+      (st = c->gband.ensure(sizeof(double) * n * N * Bx)) ||
+      (st = c->tmpM.ensure(sizeof(double) * (Bx > 4 ? Bx : 4) * Mx)))
     return fail(st);
   if (hipHostMalloc(&c->hpin, 4096, hipHostMallocDefault) != hipSuccess) {
     set_error("hipHostMalloc failed");
@@ -246,6 +252,36 @@ int kfbi_apply(kfbi_ctx* c, int layer, int precision, const double* dens, const 
     return KFBI_E_INVALID;
   }
   return apply_impl(c, layer, precision, dens, ring, out, nullptr, nullptr, nullptr);
+}
+
+int kfbi_apply_batch(kfbi_ctx* c, int layer, int precision, int B, const double* dens,
+                     const double* ring, const kfbi_out* out) {
+  KFBI_TRY(check_ctx(c, true));
+  if (!dens || !out) {
+    set_error("null density or output struct");
+    return KFBI_E_INVALID;
+  }
+  if (B < 1 || B > c->max_batch) {
+    set_error("batch %d outside [1, max_batch = %d]", B, c->max_batch);
+    return KFBI_E_INVALID;
+  }
+  if (out->grid) {
+    set_error("the grid output is not available for a batch");
+    return KFBI_E_INVALID;
+  }
+  if (layer != KFBI_SINGLE && layer != KFBI_DOUBLE) {
+    set_error("invalid layer %d", layer);
+    return KFBI_E_INVALID;
+  }
+  if (precision != KFBI_FP64 && precision != KFBI_FP32) {
+    set_error("invalid precision %d", precision);
+    return KFBI_E_INVALID;
+  }
+  if ((c->box_bc == KFBI_BOX_USER) != (ring != nullptr)) {
+    set_error("ring values must be given exactly when box_bc == KFBI_BOX_USER");
+    return KFBI_E_INVALID;
+  }
+  return apply_impl(c, layer, precision, dens, ring, out, nullptr, nullptr, nullptr, B);
 }
 
 int kfbi_operator(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* x, double* y) {

@@ -96,6 +96,15 @@ __global__ void __launch_bounds__(256)
            double* __restrict__ rarm) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
+  {  // density blockIdx.y of a batch: its own slices of every per-density array
+    const int bd = blockIdx.y;
+    dens += static_cast<size_t>(bd) * M;
+    mq += static_cast<size_t>(bd) * 5 * M;
+    qpart += static_cast<size_t>(bd) * nmk;
+    rarm += static_cast<size_t>(bd) * cap;
+    ring += static_cast<size_t>(bd) * 8 * (N + 1);
+    if (ringT) ringT += static_cast<size_t>(bd) * 16 * (N + 1);
+  }
   if (static_cast<int>(blockIdx.x) >= nmk) {
     // ----- box data: kRingNodes box nodes per block; thread (node, slice) sums the
     // trapezoid terms of one slice of the markers, slices are then added in order
@@ -338,7 +347,8 @@ __global__ void __launch_bounds__(256)
 template <class T, int PT>
 __global__ void __launch_bounds__(256)
     k_rowdst(int N, int P, const int4* __restrict__ pdesc, const double* __restrict__ rslot,
-             const int* __restrict__ iR, const T* __restrict__ sinT, T* __restrict__ Tg) {
+             const int* __restrict__ iR, const T* __restrict__ sinT, T* __restrict__ Tg,
+             size_t tstride) {
   __shared__ T tab[sintab2_size<T>(4096)];
   __shared__ T rr[kArmsPerPart];
   __shared__ int ii[kArmsPerPart];
@@ -346,6 +356,9 @@ __global__ void __launch_bounds__(256)
   const int mask = 2 * N - 1;
   const int tid = threadIdx.x;
   const int q = blockIdx.x;
+  const int cap = kArmsPerPart * P;
+  rslot += static_cast<size_t>(blockIdx.y) * cap;
+  Tg += static_cast<size_t>(blockIdx.y) * tstride;
   const int4 d = pdesc[q];
   SinTab2<T> st2;
   st2.stage(tab, N, sinT);
@@ -406,7 +419,8 @@ __global__ void __launch_bounds__(256)
     k_colsolve(int N, double h, int P, const T* __restrict__ Tg, const int* __restrict__ rowpart,
                const T* __restrict__ sinTg, const T* __restrict__ ring,
                const double* __restrict__ colc, const double* __restrict__ lanef, int jlo,
-               int jhi, T* __restrict__ Gg, int nblk_x) {
+               int jhi, T* __restrict__ Gg, int nblk_x, size_t tstride, size_t rstride,
+               size_t gstride) {
   __shared__ T col[kColsPerBlock][64 * (E + 1)];
   extern __shared__ double dynp[];  // the group's P part rows, 4 modes each
   T* tp = reinterpret_cast<T*>(dynp);
@@ -420,6 +434,9 @@ __global__ void __launch_bounds__(256)
   const int per_xcd = (nblk_x + 7) / 8;
   const int grp = (bid % 8) * per_xcd + bid / 8;
   if (grp * kColsPerBlock + 1 > n) return;  // whole block beyond the last mode
+  Tg += static_cast<size_t>(blockIdx.y) * tstride;
+  if (ring) ring += static_cast<size_t>(blockIdx.y) * rstride;
+  Gg += static_cast<size_t>(blockIdx.y) * gstride;
   const int p0 = 1 + grp * kColsPerBlock;
   const int p = p0 + w;
   const bool live = (p <= n);
@@ -632,8 +649,18 @@ __global__ void __launch_bounds__(256)
                     const double* __restrict__ qpart, int nq, double* __restrict__ vp_out,
                     double* __restrict__ vm_out, double* __restrict__ dnp_out,
                     double* __restrict__ dnm_out, int side, double oa, double ob, double oq,
-                    const double* __restrict__ xop, double* __restrict__ yop) {
+                    const double* __restrict__ xop, double* __restrict__ yop, size_t gstride) {
   extern __shared__ double nval[];  // 6 * MC node values
+  {  // density blockIdx.y of a batch
+    const size_t bd = blockIdx.y;
+    G += bd * gstride;
+    mq += bd * 5 * M;
+    qpart += bd * nq;
+    if (vp_out) vp_out += bd * M;
+    if (vm_out) vm_out += bd * M;
+    if (dnp_out) dnp_out += bd * M;
+    if (dnm_out) dnm_out += bd * M;
+  }
   __shared__ double red[16];
   __shared__ T tab[sintab2_size<T>(4096)];
   SinTab2<T> st2;
@@ -835,12 +862,6 @@ __global__ void k_grid_ring(int N, const T* __restrict__ ring, double* __restric
   grid[static_cast<size_t>(t) * n1 + N] = r;
 }
 
-template <class T>
-__global__ void k_ring_cast(int n, const double* __restrict__ src, T* __restrict__ dst) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) dst[t] = static_cast<T>(src[t]);
-}
-
 static inline int nblk(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
 
 // Allow a kernel more than the default dynamic LDS (done once per kernel and size class).
@@ -855,29 +876,31 @@ static void allow_dyn_lds(K kernel, size_t bytes) {
 }
 
 template <class T, int E>
-static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jlo, int jhi,
-                               T* Tg, T* G, bool full, double* grid, hipEvent_t* ev,
-                               const kfbi_out* out, const kfbi_bie* op, const double* xop,
-                               double* yop, int stages) {
+static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring, size_t rstride,
+                               int jlo, int jhi, T* Tg, T* G, bool full, double* grid,
+                               hipEvent_t* ev, const kfbi_out* out, const kfbi_bie* op,
+                               const double* xop, double* yop, int stages) {
   const int N = c->N, n = N - 1, M = c->M;
   const int P = c->st.n_parts;
   hipStream_t s = c->stream;
   constexpr int PT = (64 * E + 255) / 256;
+  const size_t tstride = 4 * static_cast<size_t>((n + 3) / 4) * (P + 1);
+  const size_t gstride = static_cast<size_t>(n) * N;
   if (P > 0 && (stages & 2))
-    hipLaunchKernelGGL((k_rowdst<T, PT>), dim3(P), dim3(256), 0, s, N, P, c->pdesc.as<int4>(),
-                       c->armr.as<double>(), c->armk.as<int>() + c->arm_cap, sinT, Tg);
+    hipLaunchKernelGGL((k_rowdst<T, PT>), dim3(P, B), dim3(256), 0, s, N, P, c->pdesc.as<int4>(),
+                       c->armr.as<double>(), c->armk.as<int>() + c->arm_cap, sinT, Tg, tstride);
   if (ev) hipEventRecord(ev[2], s);
   const int ngrp = nblk(n, kColsPerBlock);
   const int nb = ((ngrp + 7) / 8) * 8;
   const size_t lds_dyn = sizeof(T) * 4 * static_cast<size_t>(P > 0 ? P : 1);
   allow_dyn_lds(k_colsolve<T, E>, lds_dyn);
   if (stages & 4)
-    hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb), dim3(256), lds_dyn, s, N, c->h, P, Tg,
+    hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P, Tg,
                        c->rowpart.as<int>(), sinT, ring, c->colc.as<double>(),
-                       c->lanef.as<double>(), jlo, jhi, G, nb);
+                       c->lanef.as<double>(), jlo, jhi, G, nb, tstride, rstride, gstride);
   if (ev) hipEventRecord(ev[3], s);
   const int nbr = jhi - jlo + 1;
-  if (full) {
+  if (full) {  // single density only
     hipLaunchKernelGGL((k_fullgrid<T>), dim3(nblk(n, 64), nblk(n, 64)), dim3(256), 0, s, N, G,
                        nbr, sinT, grid);
     hipLaunchKernelGGL((k_grid_ring<T>), dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, ring, grid);
@@ -887,17 +910,28 @@ static void launch_grid_stages(kfbi_ctx* c, const T* sinT, const T* ring, int jl
   const int side = op ? op->side : 0;
   const double oa = op ? op->a : 0.0, ob = op ? op->b : 0.0, oq = op ? op->q : 0.0;
   if (stages & 8)
-    hipLaunchKernelGGL((k_nodes_extract<T, E>), dim3(8 * nblk(nch, 8)), dim3(256),
-                       sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(), c->ccount.as<int>(), c->mkloc.as<int>(),
-                     sinT, jlo, nbr, G, c->mq.as<double>(), c->ext.as<double>(),
-                     c->qpart.as<double>(), c->n_mk_blocks, out ? out->v_plus : nullptr,
-                     out ? out->v_minus : nullptr, out ? out->dn_plus : nullptr,
-                     out ? out->dn_minus : nullptr, side, oa, ob, oq, xop, yop);
+    hipLaunchKernelGGL((k_nodes_extract<T, E>), dim3(8 * nblk(nch, 8), B), dim3(256),
+                       sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(),
+                       c->ccount.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G,
+                       c->mq.as<double>(), c->ext.as<double>(), c->qpart.as<double>(),
+                       c->n_mk_blocks, out ? out->v_plus : nullptr,
+                       out ? out->v_minus : nullptr, out ? out->dn_plus : nullptr,
+                       out ? out->dn_minus : nullptr, side, oa, ob, oq, xop, yop, gstride);
 }
 
-// Launches the selected kernels (bit s = stage s) of one apply.
+// FP32 copies of user box values for a batch: src [B][4(N+1)] -> dst with stride dstride.
+__global__ void k_ring_cast_b(int n4, int B, const double* __restrict__ src, float* __restrict__ dst,
+                              size_t dstride) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n4 * B) return;
+  const int b = t / n4, r = t % n4;
+  dst[b * dstride + r] = static_cast<float>(src[t]);
+}
+
+// Launches the selected kernels (bit s = stage s) of one apply of B densities (B = 1 for
+// the single apply and the operator).
 template <class T>
-static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* ring_user,
+static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const double* ring_user,
                    const kfbi_out* out, const kfbi_bie* op, const double* xop, double* yop,
                    int stages = 15) {
   const int M = c->M, N = c->N;
@@ -907,7 +941,8 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
   T* Tg = reinterpret_cast<T*>(c->tmat.p);
   T* G = reinterpret_cast<T*>(c->gband.p);
   double* ring64 = c->ring.as<double>();
-  T* ringT = nullptr;  // box data in the working precision (after ring64 in the buffer)
+  T* ringT = nullptr;  // box data in the working precision
+  size_t rstride = 0;  // its stride between densities, in T elements
   int nring = 0;
   hipEvent_t* ev = nullptr;
   if (c->prof_on && stages == 15) {
@@ -917,30 +952,33 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
     hipEventRecord(ev[0], s);
   }
   if (c->box_bc == KFBI_BOX_FREESPACE) nring = nblk(4 * (N + 1), kRingNodes);
-  // box data in the working precision: FP64 uses the FP64 values in place; FP32 keeps a
-  // float copy after the FP64 ring (written by k_prep for the free-space data)
+  // box data per density: 8(N+1) doubles, the FP64 values then (FP32 applies) a float copy
   float* ring32 = reinterpret_cast<float*>(ring64 + 4 * (N + 1));
   const int C = c->mk_chunk, nmk = c->n_mk_blocks;
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
   const size_t lds = sizeof(double) * ((1 + nd) * M + 256 * kReg);  // covers block_sum too
   allow_dyn_lds(k_prep, lds);
   if (stages & 1)
-    hipLaunchKernelGGL(k_prep, dim3(nmk + nring), dim3(256), lds, s, M, C, nmk, layer, dens,
-                     c->dvec.as<double>(), c->dvec.as<double>() + M, c->mq.as<double>(),
-                     c->qpart.as<double>(), c->ext.as<double>() + kExtQ * M, N, c->x0, c->y0,
-                     c->h, c->X.as<double>(), c->geo.as<double>(), ring64,
-                     sizeof(T) == 4 ? ring32 : nullptr, c->ckoff.as<int>(), c->cklist.as<int>(),
-                     c->armc.as<double>(), c->armk.as<int>(), c->arm_cap, c->armr.as<double>());
+    hipLaunchKernelGGL(k_prep, dim3(nmk + nring, B), dim3(256), lds, s, M, C, nmk, layer, dens,
+                       c->dvec.as<double>(), c->dvec.as<double>() + M, c->mq.as<double>(),
+                       c->qpart.as<double>(), c->ext.as<double>() + kExtQ * M, N, c->x0, c->y0,
+                       c->h, c->X.as<double>(), c->geo.as<double>(), ring64,
+                       sizeof(T) == 4 ? ring32 : nullptr, c->ckoff.as<int>(),
+                       c->cklist.as<int>(), c->armc.as<double>(), c->armk.as<int>(),
+                       c->arm_cap, c->armr.as<double>());
   if (c->box_bc == KFBI_BOX_FREESPACE) {
     ringT = sizeof(T) == 8 ? reinterpret_cast<T*>(ring64) : reinterpret_cast<T*>(ring32);
+    rstride = sizeof(T) == 8 ? 8 * static_cast<size_t>(N + 1) : 16 * static_cast<size_t>(N + 1);
   } else if (c->box_bc == KFBI_BOX_USER) {
     if (sizeof(T) == 8) {
       ringT = const_cast<T*>(reinterpret_cast<const T*>(ring_user));
+      rstride = 4 * static_cast<size_t>(N + 1);
     } else {
       ringT = reinterpret_cast<T*>(ring32);
+      rstride = 16 * static_cast<size_t>(N + 1);
       if ((stages & 1) && ring_user)
-        hipLaunchKernelGGL((k_ring_cast<T>), dim3(nblk(4 * (N + 1), 256)), dim3(256), 0, s,
-                           4 * (N + 1), ring_user, ringT);
+        hipLaunchKernelGGL(k_ring_cast_b, dim3(nblk(4LL * (N + 1) * B, 256)), dim3(256), 0, s,
+                           4 * (N + 1), B, ring_user, ring32, rstride);
     }
   }
   if (ev) hipEventRecord(ev[1], s);
@@ -951,8 +989,8 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
   switch (E <= 1 ? 1 : E <= 2 ? 2 : E <= 4 ? 4 : E <= 8 ? 8 : E <= 16 ? 16 : 32) {
 #define KFBI_CASE(EE)                                                                         \
   case EE:                                                                                    \
-    launch_grid_stages<T, EE>(c, sinT, ringT, jlo, jhi, Tg, G, full, grid, ev, out, op, xop, \
-                              yop, stages);                                                   \
+    launch_grid_stages<T, EE>(c, B, sinT, ringT, rstride, jlo, jhi, Tg, G, full, grid, ev, out, \
+                              op, xop, yop, stages);                                          \
     break;
     KFBI_CASE(1)
     KFBI_CASE(2)
@@ -960,8 +998,8 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
     KFBI_CASE(8)
     KFBI_CASE(16)
     default:
-      launch_grid_stages<T, 32>(c, sinT, ringT, jlo, jhi, Tg, G, full, grid, ev, out, op, xop,
-                                yop, stages);
+      launch_grid_stages<T, 32>(c, B, sinT, ringT, rstride, jlo, jhi, Tg, G, full, grid, ev, out,
+                                op, xop, yop, stages);
       break;
 #undef KFBI_CASE
   }
@@ -969,6 +1007,7 @@ static int apply_t(kfbi_ctx* c, int layer, const double* dens, const double* rin
   KFBI_HIP(hipGetLastError());
   c->last_layer = layer;
   c->last_precision = sizeof(T) == 8 ? KFBI_FP64 : KFBI_FP32;
+  c->last_batch = B;
   return KFBI_OK;
 }
 
@@ -1013,15 +1052,15 @@ int replay_stage(kfbi_ctx* c, int stage, int reps, double* us_avg) {
   hipEvent_t e0, e1;
   KFBI_HIP(hipEventCreate(&e0));
   KFBI_HIP(hipEventCreate(&e1));
-  const double* dens = c->tmpM.as<double>();
-  const int layer = c->last_layer, mask = 1 << stage;
+  const double* dens = c->tmpM.as<double>();  // max(4, max_batch) * max_markers doubles
+  const int layer = c->last_layer, B = c->last_batch, mask = 1 << stage;
   // one untimed launch, then the timed ones
   int st = KFBI_OK;
   for (int r = 0; r <= reps && st == KFBI_OK; ++r) {
     if (r == 1) hipEventRecord(e0, c->stream);
     st = (c->last_precision == KFBI_FP32)
-             ? apply_t<float>(c, layer, dens, nullptr, nullptr, nullptr, nullptr, nullptr, mask)
-             : apply_t<double>(c, layer, dens, nullptr, nullptr, nullptr, nullptr, nullptr, mask);
+             ? apply_t<float>(c, B, layer, dens, nullptr, nullptr, nullptr, nullptr, nullptr, mask)
+             : apply_t<double>(c, B, layer, dens, nullptr, nullptr, nullptr, nullptr, nullptr, mask);
   }
   hipEventRecord(e1, c->stream);
   float ms = 0.f;
@@ -1039,9 +1078,10 @@ int replay_stage(kfbi_ctx* c, int stage, int reps, double* us_avg) {
 }
 
 int apply_impl(kfbi_ctx* c, int layer, int precision, const double* dens, const double* ring_user,
-               const kfbi_out* out, const kfbi_bie* op, const double* xop, double* yop) {
-  if (precision == KFBI_FP32) return apply_t<float>(c, layer, dens, ring_user, out, op, xop, yop);
-  return apply_t<double>(c, layer, dens, ring_user, out, op, xop, yop);
+               const kfbi_out* out, const kfbi_bie* op, const double* xop, double* yop, int B) {
+  if (precision == KFBI_FP32)
+    return apply_t<float>(c, B, layer, dens, ring_user, out, op, xop, yop);
+  return apply_t<double>(c, B, layer, dens, ring_user, out, op, xop, yop);
 }
 
 }  // namespace kfbi

@@ -94,6 +94,7 @@ struct kfbi_ctx {
   double c2;
   int box_bc;
   int max_markers;
+  int max_batch = 1;  // densities per kfbi_apply_batch call the workspaces hold
   hipStream_t stream;
   int device;
 
@@ -128,6 +129,7 @@ struct kfbi_ctx {
   // kernel replay (kfbi_profile_kernel): layer and precision of the last apply, -1 = none
   int last_layer = -1;
   int last_precision = 0;
+  int last_batch = 1;
 
   // apply launch geometry (set by set_interface)
   int mk_chunk = 8;   // markers per K1 block
@@ -139,7 +141,8 @@ namespace kfbi {
 // stage entry points (implemented in the .hip files)
 int geometry_setup(kfbi_ctx* c, int M, const double* xy);
 int apply_impl(kfbi_ctx* c, int layer, int precision, const double* dens, const double* ring_user,
-               const kfbi_out* out, const kfbi_bie* op, const double* x_for_op, double* y_op);
+               const kfbi_out* out, const kfbi_bie* op, const double* x_for_op, double* y_op,
+               int batch = 1);
 int ensure_apply_buffers(kfbi_ctx* c);
 int prof_flush(kfbi_ctx* c);
 int replay_stage(kfbi_ctx* c, int stage, int reps, double* us_avg);

@@ -887,7 +887,8 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
     const int P = hs->n_parts;
     KFBI_TRY(c->pdesc.ensure(sizeof(int4) * (P + 1)));
     const int ng = (N - 1 + 3) / 4;
-    KFBI_TRY(c->tmat.ensure(sizeof(double) * 4 * static_cast<size_t>(ng) * (P + 1)));
+    KFBI_TRY(c->tmat.ensure(sizeof(double) * 4 * static_cast<size_t>(ng) * (P + 1) *
+                            c->max_batch));
     hipLaunchKernelGGL(k_part_fill, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart,
                        c->pdesc.as<int4>());
     // part-slot arm coefficients for the row transform kernel
@@ -900,8 +901,9 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
                          c->pdesc.as<int4>(), c->armcoef.as<ArmCoef>(), c->armpk.as<int>(),
                          c->armc.as<double>(), c->armk.as<int>());
     // per-apply corrections r (zero in empty slots) and the marker-chunk lists of slots
-    KFBI_TRY(c->armr.ensure(sizeof(double) * cap));
-    KFBI_HIP(hipMemsetAsync(c->armr.p, 0, sizeof(double) * cap, s));
+    // (one copy per density of a batch)
+    KFBI_TRY(c->armr.ensure(sizeof(double) * cap * c->max_batch));
+    KFBI_HIP(hipMemsetAsync(c->armr.p, 0, sizeof(double) * cap * c->max_batch, s));
     const int nmk = c->n_mk_blocks;
     KFBI_TRY(c->ckoff.ensure(sizeof(int) * (2 * nmk + 2)));
     KFBI_TRY(c->cklist.ensure(sizeof(int) * cap));

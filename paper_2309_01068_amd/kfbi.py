@@ -23,7 +23,7 @@ FP64, FP32 = 0, 1
 
 EXPORTS = [
     "kfbi_last_error", "kfbi_create", "kfbi_destroy", "kfbi_set_interface", "kfbi_get_info",
-    "kfbi_apply", "kfbi_operator", "kfbi_gmres_solve", "kfbi_profile", "kfbi_profile_read",
+    "kfbi_apply", "kfbi_apply_batch", "kfbi_operator", "kfbi_gmres_solve", "kfbi_profile", "kfbi_profile_read",
     "kfbi_profile_kernel",
     "thetaL_create", "thetaL_destroy", "thetaL_init", "thetaL_step", "thetaL_run",
     "thetaL_markers", "thetaL_density", "thetaL_kfbi", "thetaL_get_state", "thetaL_set_state",
@@ -43,7 +43,7 @@ class KfbiError(RuntimeError):
 class Grid(C.Structure):
     _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("side", C.c_double), ("N", C.c_int),
                 ("c2", C.c_double), ("box_bc", C.c_int), ("max_markers", C.c_int),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("max_batch", C.c_int)]
 
 
 class Info(C.Structure):
@@ -121,6 +121,7 @@ def load(path: str = LIBPATH):
     lib.kfbi_set_interface.argtypes = [vp, C.c_int, vp]
     lib.kfbi_get_info.argtypes = [vp, C.POINTER(Info)]
     lib.kfbi_apply.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.POINTER(Out)]
+    lib.kfbi_apply_batch.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(Out)]
     lib.kfbi_operator.argtypes = [vp, C.POINTER(Bie), C.c_int, vp, vp]
     lib.kfbi_gmres_solve.argtypes = [vp, C.POINTER(Bie), vp, vp, C.POINTER(GmresOpts),
                                      C.POINTER(GmresStats)]
@@ -173,13 +174,14 @@ def _ptr(t):
 class Context:
     """A KFBI context: box, grid, operator constant c2, box data mode."""
 
-    def __init__(self, x0, y0, side, N, c2=0.0, box_bc=BOX_ZERO, max_markers=4096, stream=None):
+    def __init__(self, x0, y0, side, N, c2=0.0, box_bc=BOX_ZERO, max_markers=4096, stream=None,
+                 max_batch=1):
         self.lib = load()
         self.N = N
         self.box_bc = box_bc
         s = torch.cuda.current_stream() if stream is None else stream
         self.stream = s
-        g = Grid(x0, y0, side, N, c2, box_bc, max_markers, C.c_void_p(s.cuda_stream))
+        g = Grid(x0, y0, side, N, c2, box_bc, max_markers, C.c_void_p(s.cuda_stream), max_batch)
         h = C.c_void_p()
         _check(self.lib.kfbi_create(C.byref(g), C.byref(h)))
         self.h = h
@@ -220,6 +222,20 @@ class Context:
         o = Out(*[(_ptr(res[k]) if k in res else None)
                   for k in ("v_plus", "v_minus", "dn_plus", "dn_minus", "grid")])
         _check(self.lib.kfbi_apply(self.h, layer, precision, _ptr(density), _ptr(ring), C.byref(o)))
+        return res
+
+    def apply_batch(self, layer, density, precision=FP64, ring=None,
+                    want=("v_plus", "v_minus", "dn_plus", "dn_minus"), out=None):
+        """density: (B, M) float64 device tensor; outputs (B, M); ring (B, 4(N+1)) or None."""
+        B = density.shape[0]
+        res = {} if out is None else out
+        for k in want:
+            if k not in res:
+                res[k] = torch.empty((B, self.M), dtype=torch.float64, device=density.device)
+        o = Out(*[(_ptr(res[k]) if k in res else None)
+                  for k in ("v_plus", "v_minus", "dn_plus", "dn_minus")], None)
+        _check(self.lib.kfbi_apply_batch(self.h, layer, precision, B, _ptr(density), _ptr(ring),
+                                         C.byref(o)))
         return res
 
     def operator(self, x, layer, side, a, b, q, precision=FP64, y=None):
