@@ -68,7 +68,7 @@ static void release_all(kfbi_ctx* c) {
   DBuf* bufs[] = {&c->vraw, &c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
                   &c->vid,    &c->lab,    &c->armcnt, &c->rowsum,  &c->armrow, &c->armpk,
                   &c->armc,   &c->armk,   &c->colc,   &c->lanef,   &c->cnode,  &c->ccount,
-                  &c->mkloc,  &c->tmat,   &c->pdesc,  &c->rowpart, &c->ckoff, &c->cklist,
+                  &c->mkloc,  &c->tmat,   &c->pdesc,  &c->rowpart, &c->ckoff, &c->cklist, &c->ckcoef, &c->ckmk,
                   &c->armcoef, &c->intptr, &c->need,    &c->nodeidx, &c->nodei,
                   &c->rowptr, &c->rows,   &c->mknode, &c->ext,     &c->gstat,  &c->mq,
                   &c->armr,   &c->qpart,  &c->ring,   &c->sinT,    &c->sinT32, &c->gband,
@@ -206,6 +206,8 @@ int kfbi_set_interface(kfbi_ctx* c, int M, const double* xy) {
   }
   c->have_interface = 0;
   c->last_layer = -1;
+  // markers per derivative / interpolation chunk; at most 16 (M <= 4096), so a chunk has
+  // at most 96 stencil nodes, which the interpolation kernel keeps two per lane
   c->mk_chunk = M >= 1024 ? M / 256 : 4;
   c->n_mk_blocks = (M + c->mk_chunk - 1) / c->mk_chunk;
   const int st = geometry_setup(c, M, xy);

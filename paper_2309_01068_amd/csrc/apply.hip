@@ -1,13 +1,14 @@
 // One KFBI operator apply on gfx950 (Sec. 4): four kernels per apply.
 //
-//  K1 k_prep     density -> Fourier derivatives at the markers in circulant form
-//                (Phi_a, Phi_aa or Psi_a; FP64), trapezoid-weight partial sums, and the
-//                free-space box data of Sec. 4.1 when requested.
-//  K2 k_rowdst   per grid row: jump corrections of the row's irregular arms (Sec. 4.2.1
-//                eq. modified-fdm with App. A.1 jumps; 6-point interpolation of the
-//                marker quantities, coefficients precomputed per interface) and the sine
-//                transform along x of the row's sparse right-hand side,
-//                    T[j][p] = sum_{arms in row j} r_a sin(p i_a pi / N).
+//  K1 k_prep     per chunk of markers: Fourier derivatives at the markers in circulant
+//                form (Phi_a, Phi_aa or Psi_a; FP64), the marker jump quantities, the
+//                jump corrections r_a of the irregular arms whose interval starts in the
+//                chunk (Sec. 4.2.1 eq. modified-fdm with App. A.1 jumps; 6-point
+//                interpolation of the marker quantities, coefficients precomputed per
+//                interface), trapezoid-weight partial sums, and the free-space box data of
+//                Sec. 4.1 when requested.
+//  K2 k_rowdst   per row part: the sine transform along x of the row's sparse right-hand
+//                side, T[j][p] = sum_{arms in row j} r_a sin(p i_a pi / N).
 //  K3 k_colsolve per sine mode p along y, the constant tridiagonal system
 //                    G_{j+1} - (2 + delta_p) G_j + G_{j-1} = h^2 T[j][p] (+ box terms),
 //                    delta_p = 4 sin^2(p pi / 2N) + h^2 c^2,  G_0 = G_N = 0,
@@ -75,6 +76,9 @@ __host__ __device__ constexpr int sintab2_size(int N) {
   return 2 * ((2 * N) / 64 > 0 ? (2 * N) / 64 : 1) + 128;
 }
 
+// Padded LDS position of entry m of a marker array in K1.
+__host__ __device__ __forceinline__ int lpad(int m) { return m + (m >> 5); }
+
 // Column-group-major layouts: the four modes p = 4g+1..4g+4 of a row are adjacent and
 // the rows of one group are contiguous.
 __device__ __forceinline__ size_t grp_index(int p, int r, int nrows) {
@@ -92,7 +96,7 @@ __global__ void __launch_bounds__(256)
            int N, double x0, double y0, double h, const double* __restrict__ X,
            const double* __restrict__ geo, double* __restrict__ ring, float* __restrict__ ringT,
            const int* __restrict__ ckoff, const int* __restrict__ cklist,
-           const double* __restrict__ coefR, const int* __restrict__ kR, int cap,
+           const double* __restrict__ ckc, const int* __restrict__ ckk, int cap,
            double* __restrict__ rarm) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
@@ -195,11 +199,19 @@ __global__ void __launch_bounds__(256)
   int ngp = 1;  // groups rounded up to a power of two (at most 16)
   while (ngp < ng) ngp <<= 1;
   const int S = 256 / ngp;  // slices of m
-  double* ph = lds;             // M
-  double* dl1 = ph + M;         // M
-  double* dl2 = dl1 + M;        // M (double layer only)
-  double* part = dl1 + nd * M;  // 4 waves x ngp x kReg, then the window quantities
+  // ph, dl1, dl2 hold M values each at padded positions lpad(m) = m + m / 32: the slices
+  // of m summed by the lanes of a wavefront start 32 apart, and the padding puts their
+  // reads in different LDS banks
+  const int Mp = lpad(M - 1) + 1;
+  double* ph = lds;              // Mp
+  double* dl1 = ph + Mp;         // Mp
+  double* dl2 = dl1 + Mp;        // Mp (double layer only)
+  double* part = dl1 + nd * Mp;  // 4 waves x ngp x kReg, then the window quantities
   double* qw = part + 4 * 16 * kReg;  // 5 x kWinMax
+  // this chunk's arm records, in list order (issued first: the record loads below depend
+  // on them and then overlap the circulant sums); ckk holds the window offset k_a - k0
+  // of marker k_a - 2
+  const int a0 = ckoff[b], a1 = ckoff[b + 1];
   const double wmine = (k0 + tid < k1) ? wq[k0 + tid] : 0.0;
   for (int m0 = tid; m0 < M; m0 += 256 * 8) {
     double a[8], bb[8], cc[8];
@@ -216,11 +228,22 @@ __global__ void __launch_bounds__(256)
     for (int u = 0; u < 8; ++u) {
       const int m = m0 + 256 * u;
       if (m < M) {
-        ph[m] = a[u];
-        dl1[m] = bb[u];
-        if (nd == 2) dl2[m] = cc[u];
+        ph[lpad(m)] = a[u];
+        dl1[lpad(m)] = bb[u];
+        if (nd == 2) dl2[lpad(m)] = cc[u];
       }
     }
+  }
+  // first arm of this thread: slot, window offset of marker k_a - 2, coefficients
+  const int e0 = a0 + tid;
+  const bool arm0 = e0 < a1;
+  unsigned slot0 = 0, t00 = 0;  // unsigned: nothing needs the values before the barrier
+  double cf[kArmCoefCount];
+  if (arm0) {
+    slot0 = static_cast<unsigned>(cklist[e0]);
+    t00 = static_cast<unsigned>(ckk[e0]);
+#pragma unroll
+    for (int qq = 0; qq < kArmCoefCount; ++qq) cf[qq] = ckc[qq * cap + e0];
   }
   __syncthreads();
   // thread = (slice sl, group g): g = tid mod ngp, so the slices of one group sit in
@@ -242,7 +265,7 @@ __global__ void __launch_bounds__(256)
     for (int r = 0; r < kReg; ++r) {
       int q = kb + r;
       q -= (q >= M) ? M : 0;
-      w[r] = dd[q];
+      w[r] = dd[lpad(q)];
     }
     int q = kb;  // index of w[0]
     int m = mb;
@@ -250,10 +273,10 @@ __global__ void __launch_bounds__(256)
       double f[8], nw[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        f[u] = ph[m + u];
+        f[u] = ph[lpad(m + u)];
         int qq = q - 1 - u;
         qq += (qq < 0) ? M : 0;
-        nw[u] = dd[qq];
+        nw[u] = dd[lpad(qq)];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -267,13 +290,13 @@ __global__ void __launch_bounds__(256)
       q += (q < 0) ? M : 0;
     }
     for (; m < me; ++m) {
-      const double f = ph[m];
+      const double f = ph[lpad(m)];
 #pragma unroll
       for (int r = 0; r < kReg; ++r) acc[r] += w[r] * f;
 #pragma unroll
       for (int r = kReg - 1; r > 0; --r) w[r] = w[r - 1];
       q = (q == 0) ? M - 1 : q - 1;
-      w[0] = dd[q];
+      w[0] = dd[lpad(q)];
     }
   }
   for (int off = ngp; off < 64; off <<= 1) {
@@ -298,7 +321,7 @@ __global__ void __launch_bounds__(256)
     int km = w0 + tid;
     km += (km < 0) ? M : 0;
     km -= (km >= M) ? M : 0;
-    vph = ph[km];
+    vph = ph[lpad(km)];
     const bool dl = (layer == KFBI_DOUBLE);
     qw[0 * kWinMax + tid] = dl ? vph : 0.0;
     qw[1 * kWinMax + tid] = dl ? v1 : 0.0;
@@ -307,26 +330,33 @@ __global__ void __launch_bounds__(256)
     qw[4 * kWinMax + tid] = dl ? 0.0 : -v1;
   }
   // trapezoid partial sum of the density
-  double qs = (k0 + tid < k1) ? ph[k0 + tid] * wmine : 0.0;
-  for (int k = k0 + 256 + tid; k < k1; k += 256) qs += ph[k] * wq[k];
+  double qs = (k0 + tid < k1) ? ph[lpad(k0 + tid)] * wmine : 0.0;
+  for (int k = k0 + 256 + tid; k < k1; k += 256) qs += ph[lpad(k)] * wq[k];
   __syncthreads();
   // arm corrections r_a = sum_m l_m sum_q coef_q Q_q(k_a - 2 + m) (Sec. 4.2.1 with the
   // App. A.1 jumps; coefficients per arm from the interface setup)
-  {
-    const int a0 = ckoff[b], a1 = ckoff[b + 1];
-    for (int e = a0 + tid; e < a1; e += 256) {
-      const int a = cklist[e];
-      const int t0 = kR[a] - k0;  // window offset of marker k_a - 2
-      double r = 0.0;
+  if (arm0) {
+    double r = 0.0;
 #pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        double sm = 0.0;
+    for (int m = 0; m < 6; ++m) {
+      double sm = 0.0;
 #pragma unroll
-        for (int qq = 0; qq < 5; ++qq) sm += coefR[(6 + qq) * cap + a] * qw[qq * kWinMax + t0 + m];
-        r += coefR[m * cap + a] * sm;
-      }
-      rarm[a] = r;
+      for (int qq = 0; qq < 5; ++qq) sm += cf[6 + qq] * qw[qq * kWinMax + t00 + m];
+      r += cf[m] * sm;
     }
+    rarm[slot0] = r;
+  }
+  for (int e = e0 + 256; e < a1; e += 256) {  // chunks with more than 256 arms
+    const int t0 = ckk[e];
+    double r = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      double sm = 0.0;
+#pragma unroll
+      for (int qq = 0; qq < 5; ++qq) sm += ckc[(6 + qq) * cap + e] * qw[qq * kWinMax + t0 + m];
+      r += ckc[m * cap + e] * sm;
+    }
+    rarm[cklist[e]] = r;
   }
   qs = block_sum<double>(qs, part);
   // global stores last (no barrier waits on them)
@@ -342,7 +372,8 @@ __global__ void __launch_bounds__(256)
 // One block per row part (a row's arms in groups of at most kArmsPerPart, corrections r_a
 // from K1 in part-slot order); every thread evaluates the partial transform
 // T_part[p] = sum_a r_a sin(p i_a pi / N) for PT consecutive modes p, starting from the
-// two-level table and rotating in steps of i_a pi / N.  Parts of one row are summed in
+// two-level table and advancing by the three-term sine recurrence in steps of i_a pi / N.
+// Parts of one row are summed in
 // part order by the solve kernel.
 template <class T, int PT>
 __global__ void __launch_bounds__(256)
@@ -379,12 +410,17 @@ __global__ void __launch_bounds__(256)
     T s, c, sb, cb;
     st2.get((p0 * i) & mask, s, c);
     st2.get(i & mask, sb, cb);
+    // sin((p + 1) x) = 2 cos(x) sin(p x) - sin((p - 1) x), started from sin(p0 x) and
+    // sin((p0 - 1) x); over PT steps the rounding grows by at most a factor PT
+    const T c2 = cb + cb;
+    T sm = s * cb - c * sb;
+    acc[0] += r * s;
 #pragma unroll
-    for (int k = 0; k < PT; ++k) {
+    for (int k = 1; k < PT; ++k) {
+      const T sn = c2 * s - sm;
+      sm = s;
+      s = sn;
       acc[k] += r * s;
-      const T t2 = s * cb + c * sb;
-      c = c * cb - s * sb;
-      s = t2;
     }
   }
   if constexpr (PT % 4 == 0) {
@@ -637,7 +673,7 @@ __global__ void k_colconst(int N, double hc2, int E, double* __restrict__ colc,
 // ---------------------------------------------------------------------------------- K4
 // One block per chunk of MC markers.  Its distinct stencil nodes (sorted by row) are
 // split over the four wavefronts; lane l of a wavefront keeps G[j][p] for
-// p = 1 + l + 64 e and advances sin(p i pi / N) over e by the angle-addition rotation
+// p = 1 + l + 64 e and advances sin(p i pi / N) over e by the three-term sine recurrence
 // with step 64 i pi / N.  Eight nodes are reduced together by recursive halving.  Then
 // MC threads apply the Sec. 4.3 corrected interpolation.
 template <class T, int E>
@@ -663,9 +699,6 @@ __global__ void __launch_bounds__(256)
   }
   __shared__ double red[16];
   __shared__ T tab[sintab2_size<T>(4096)];
-  SinTab2<T> st2;
-  st2.stage(tab, N, sinT);
-  __syncthreads();
   const int n = N - 1;
   const int mask = 2 * N - 1;
   const int quarter = N / 2;
@@ -679,6 +712,12 @@ __global__ void __launch_bounds__(256)
   if (ch >= nch) return;
   const int nn = ccount[ch];
   const int* keys = cnode + static_cast<size_t>(ch) * 6 * MC;
+  // the chunk's node keys (at most 6 MC <= 128), two per lane, loaded with the table
+  const int key_lo = (lane < 6 * MC) ? keys[lane] : -1;
+  const int key_hi = (64 + lane < 6 * MC) ? keys[64 + lane] : -1;
+  SinTab2<T> st2;
+  st2.stage(tab, N, sinT);
+  __syncthreads();
   // prefetch the extraction data of this thread's marker (used after the node phase)
   const int kx = ch * MC + tid;
   const bool xmk = (tid < MC && kx < M);
@@ -710,7 +749,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int u = 0; u < kNodeBatch; ++u) {
       const int q = q0 + u;
-      const int key = (q < qe) ? keys[q] : -1;
+      const int kq = __shfl(q < 64 ? key_lo : key_hi, q & 63, 64);
+      const int key = (q < qe) ? kq : -1;
       const int i = key & 0xffff, j = key >> 16;
       if (key >= 0 && j != curj) {  // wave-uniform branch
 #pragma unroll
@@ -725,12 +765,16 @@ __global__ void __launch_bounds__(256)
         T a, c, sb, cb;
         st2.get(((1 + lane) * i) & mask, a, c);
         st2.get((64 * i) & mask, sb, cb);
+        // three-term recurrence in steps of 64 i pi / N (rounding grows at most E-fold)
+        const T c2 = cb + cb;
+        T am = a * cb - c * sb;
+        sacc += gv[0] * a;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
+        for (int e = 1; e < E; ++e) {
+          const T an = c2 * a - am;
+          am = a;
+          a = an;
           sacc += gv[e] * a;
-          const T t2 = a * cb + c * sb;
-          c = c * cb - a * sb;
-          a = t2;
         }
       }
       part[u] = sacc;
@@ -956,7 +1000,7 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
   float* ring32 = reinterpret_cast<float*>(ring64 + 4 * (N + 1));
   const int C = c->mk_chunk, nmk = c->n_mk_blocks;
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
-  const size_t lds = sizeof(double) * ((1 + nd) * M + 256 * kReg);  // covers block_sum too
+  const size_t lds = sizeof(double) * ((1 + nd) * (lpad(M - 1) + 1) + 256 * kReg);  // covers block_sum too
   allow_dyn_lds(k_prep, lds);
   if (stages & 1)
     hipLaunchKernelGGL(k_prep, dim3(nmk + nring, B), dim3(256), lds, s, M, C, nmk, layer, dens,
@@ -964,7 +1008,7 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
                        c->qpart.as<double>(), c->ext.as<double>() + kExtQ * M, N, c->x0, c->y0,
                        c->h, c->X.as<double>(), c->geo.as<double>(), ring64,
                        sizeof(T) == 4 ? ring32 : nullptr, c->ckoff.as<int>(),
-                       c->cklist.as<int>(), c->armc.as<double>(), c->armk.as<int>(),
+                       c->cklist.as<int>(), c->ckcoef.as<double>(), c->ckmk.as<int>(),
                        c->arm_cap, c->armr.as<double>());
   if (c->box_bc == KFBI_BOX_FREESPACE) {
     ringT = sizeof(T) == 8 ? reinterpret_cast<T*>(ring64) : reinterpret_cast<T*>(ring32);

@@ -525,6 +525,21 @@ __global__ void k_chunk_arm_fill(int cap, int MC, const int* __restrict__ kR,
   if (s < cap && kR[cap + s] != 0) list[atomicAdd(&cur[kR[s] / MC], 1)] = s;
 }
 
+// The chunk lists' arm data in list order (coefficients [kArmCoefCount][cap], and the
+// offset k_a - k0 of the arm's interval in its chunk, which is the window position of
+// marker k_a - 2), so that the derivative kernel reads a chunk's arms with contiguous loads.
+__global__ void k_chunk_arm_pack(int cap, int MC, const int* __restrict__ total,
+                                 const int* __restrict__ list, const double* __restrict__ coefR,
+                                 const int* __restrict__ kR, double* __restrict__ cc,
+                                 int* __restrict__ ck) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cap || e >= *total) return;
+  const int s = list[e];
+#pragma unroll
+  for (int q = 0; q < kArmCoefCount; ++q) cc[q * cap + e] = coefR[q * cap + s];
+  ck[e] = kR[s] % MC;
+}
+
 // Rows split into parts of at most kArmsPerPart arms: parts per row, then descriptors
 // (row, first arm, end arm) in row order after an exclusive scan.
 __global__ void k_part_count(int N, const int* __restrict__ rowoff, int* __restrict__ rowpart) {
@@ -918,6 +933,12 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
     if (P > 0)
       hipLaunchKernelGGL(k_chunk_arm_fill, dim3(nblk(cap, 256)), dim3(256), 0, s, cap,
                          c->mk_chunk, c->armk.as<int>(), ckcur, c->cklist.as<int>());
+    KFBI_TRY(c->ckcoef.ensure(sizeof(double) * kArmCoefCount * cap));
+    KFBI_TRY(c->ckmk.ensure(sizeof(int) * cap));
+    if (P > 0)
+      hipLaunchKernelGGL(k_chunk_arm_pack, dim3(nblk(cap, 256)), dim3(256), 0, s, cap,
+                         c->mk_chunk, ckoff + nmk, c->cklist.as<int>(), c->armc.as<double>(),
+                         c->armk.as<int>(), c->ckcoef.as<double>(), c->ckmk.as<int>());
   }
   KFBI_HIP(hipGetLastError());
   c->st = *hs;
