@@ -7,7 +7,9 @@ interpolant with modes |k| < M/2; the Nyquist mode k = M/2 is set to zero for ev
 derivative, antiderivative and Hilbert transform.
 
 Pinned by: exact derivatives / antiderivatives / Hilbert transforms of trigonometric
-polynomials (tests/test_oracle_spectral.py), H[H f] = -f for mean-free f.
+polynomials (tests/test_oracle_spectral.py), H[H f] = -f for mean-free f; upsample2
+reproduces a trigonometric polynomial at the doubled samples exactly
+(tests/test_oracle_refine.py).
 """
 from __future__ import annotations
 
@@ -62,3 +64,15 @@ def hilbert(f: np.ndarray) -> np.ndarray:
     k = wavenumbers(M)
     fh = np.fft.fft(f, axis=-1) * (-1j * np.sign(k))
     return np.real(np.fft.ifft(fh, axis=-1))
+
+
+def upsample2(f: np.ndarray) -> np.ndarray:
+    """Values of the trigonometric interpolant (Nyquist mode dropped) at 2M equispaced
+    samples a'_j = pi j / M; the even samples reproduce f when f has no Nyquist part."""
+    M = f.shape[-1]
+    fh = np.fft.fft(f, axis=-1) * _nyq_mask(M)
+    g = np.zeros(f.shape[:-1] + (2 * M,), dtype=complex)
+    h = M // 2
+    g[..., :h] = fh[..., :h]
+    g[..., 2 * M - h + 1:] = fh[..., h + 1:]
+    return np.real(np.fft.ifft(g, axis=-1)) * 2.0

@@ -21,9 +21,16 @@ Readings where the paper is inconsistent or silent:
 * initialisation: equal-arclength resampling of a sampled curve by Newton on the
   trigonometric interpolant of the arclength function.
 
+Adaptive marker refinement (Sec. 6.1, long-time computation): when the marker spacing
+L/M exceeds ratio * h after a step, M is doubled; eta, the last density and the history of
+the explicit term are carried to the doubled parameter grid by trigonometric
+interpolation (zero padding in Fourier space; the unnormalised DFT doubles).  The paper
+gives only the criterion; the interpolation is this reading.
+
 Pinned by: a circle grows as R(t) = sqrt(R0^2 + 2 J t); J = 0 conserves area and
 shortens the curve; equal-arclength resampling of a circle/ellipse
-(tests/test_oracle_thetal.py).
+(tests/test_oracle_thetal.py); refinement keeps the curve, L, Xbar and the explicit-term
+history (tests/test_oracle_refine.py).
 """
 from __future__ import annotations
 
@@ -202,3 +209,24 @@ def hs_step(st: HSState, prm: HSParams) -> tuple[HSState, StepInfo]:
     new = HSState(eta_new, Lnew, Xnew, st.n + 1, st.t + tau, Nhat, Mdot, Q, L, phi)
     info = StepInfo(gs.iters, gs.relres, area(X), L, phi, U)
     return new, info
+
+
+def refine(st: HSState) -> HSState:
+    """Double the markers of the state by trigonometric interpolation in alpha."""
+    M = st.eta.size
+    eta2 = spectral.upsample2(st.eta)
+    nh = None
+    if st.Nhat_prev is not None:
+        nh = np.zeros(2 * M, dtype=complex)
+        h = M // 2
+        nh[:h] = 2.0 * st.Nhat_prev[:h]
+        nh[2 * M - h + 1:] = 2.0 * st.Nhat_prev[h + 1:]
+    phi = None if st.phi_prev is None else spectral.upsample2(st.phi_prev)
+    return HSState(eta2, st.L, st.Xbar.copy(), st.n, st.t, nh, st.Mdot_prev, st.Q_prev.copy(),
+                   st.L_prev, phi)
+
+
+def refine_due(st: HSState, h: float, ratio: float, max_M: int) -> bool:
+    """The refinement criterion: marker spacing L/M above ratio * h, room to double."""
+    M = st.eta.size
+    return ratio > 0.0 and st.L / M > ratio * h and 2 * M <= max_M
