@@ -23,6 +23,12 @@
  *  - the reconstruction X = Xbar + (L/2pi) * mean-free antiderivative of
  *    (cos theta, sin theta); Nyquist modes are zeroed in every spectral operation.
  *
+ * Adaptive marker refinement (Sec. 6.1, long-time computation): with refine > 0, after
+ * a step whose new length gives a marker spacing L/M above refine * h, M is doubled (up
+ * to max_M); eta, the last two densities and the history of the explicit term are
+ * carried to the doubled parameter grid by trigonometric interpolation (zero padding in
+ * Fourier space).  The paper fixes only the criterion (refine = 1.5 there).
+ *
  * Every spectral operation runs in FP64 on the GPU (single-workgroup LDS FFTs); the
  * pressure solve uses kfbi_gmres_solve with the options given at creation (its FP32
  * inner mode keeps the FP64 residual tolerance).  Conventions as in kfbi.h: *_dev are
@@ -49,6 +55,10 @@ typedef struct {
   double tau;            /* time step                                                    */
   double lambda2;        /* SSD constant of the stiff term; a negative value selects sigma */
   kfbi_gmres_opts gmres; /* options of the per-step GMRES solve                          */
+  double refine;         /* marker refinement ratio (0 = off; > 0: double M when
+                            L/M > refine * h)                                           */
+  int max_M;             /* largest M refinement may reach (a power of two, M <= max_M
+                            <= 2048; 0 = M)                                             */
 } thetaL_params;
 
 /* Per-step record (host).  area and length describe the curve at the start of the step
@@ -62,9 +72,12 @@ typedef struct {
   double relres;         /* final true FP64 relative residual                            */
   double area, length;
   double ms_geometry, ms_gmres, ms_apply, ms_update;
+  int M;                 /* markers of this step                                         */
+  int M_next;            /* markers after it (2M when the step ended with a refinement)  */
 } thetaL_stats;
 
-/* Checkpoint of the evolution.  Arrays are caller-owned device arrays; scal is host. */
+/* Checkpoint of the evolution.  Arrays are caller-owned device arrays sized for the
+ * current M (thetaL_size); scal is host. */
 typedef struct {
   double* eta_dev;       /* [M] eta = theta - alpha                                      */
   double* phi_prev_dev;  /* [M] density of the last solve (next initial guess)            */
@@ -72,6 +85,8 @@ typedef struct {
   double* nhat_prev_dev; /* [2M] DFT of the last explicit term, (re, im) interleaved      */
   double scal[8];        /* L, Xbar_x, Xbar_y, t, L_prev, M_prev, Qbar_prev_x, Qbar_prev_y */
   int n;                 /* steps taken                                                  */
+  int M;                 /* markers of the state (set_state: 0 = the current M; else a
+                            power of two in [16, max_M])                                 */
 } thetaL_state;
 
 /* Create an evolution object (and its KFBI context).  KFBI_E_INVALID on bad params. */
@@ -84,11 +99,15 @@ int thetaL_destroy(thetaL* th);
  * function), set eta, L, Xbar, time 0, step count 0, zero previous density.  Syncs. */
 int thetaL_init(thetaL* th, int Mi, const double* xy_dev);
 
+/* Current number of markers (changes only by refinement, thetaL_init keeps it). */
+int thetaL_size(const thetaL* th, int* M);
+
 /* One time step.  x0_dev: initial guess of the pressure density (M doubles) or NULL for
  * the previous step's density (zero at the first step); GMRES always runs to the same
  * FP64 residual tolerance, so the guess changes the iteration count only.  Re-installs
  * the interface in the KFBI context (its geometry workspaces may grow), solves, applies
- * once more for d_n(D phi), and advances the state.  Synchronises.  Errors: KFBI_E_NOCONV
+ * once more for d_n(D phi), advances the state, then refines the markers if due.
+ * Synchronises.  Errors: KFBI_E_NOCONV
  * (the state is left unchanged), KFBI_E_GEOMETRY (curve not resolvable, unchanged),
  * KFBI_E_NONFINITE (the new state is not finite). */
 int thetaL_step(thetaL* th, const double* x0_dev, thetaL_stats* stats);

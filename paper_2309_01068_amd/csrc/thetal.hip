@@ -500,6 +500,89 @@ __global__ void __launch_bounds__(kTLThreads)
   }
 }
 
+// Marker refinement M -> 2M: eta, phi, phi2 by trigonometric interpolation (FFT of length
+// M, Nyquist dropped, zero padding, inverse FFT of length 2M; the unnormalised DFT doubles),
+// the explicit-term history nhat (an unnormalised DFT of length M) by zero padding and
+// doubling.  tw holds the twiddles of length 2M; one workgroup.
+__global__ void __launch_bounds__(kTLThreads)
+    k_tl_refine(int M, const double* __restrict__ tw, double* __restrict__ eta,
+                double* __restrict__ phi, double* __restrict__ phi2,
+                double* __restrict__ nhat) {
+  extern __shared__ double lds[];
+  const int M2 = 2 * M, h = M / 2;
+  const int tid = threadIdx.x;
+  double* xr = lds;        // 2M each
+  double* xi = xr + M2;
+  double* yr = xi + M2;
+  double* yi = yr + M2;
+  double* t2r = yi + M2;   // twiddles of length 2M (M entries each)
+  double* t2i = t2r + M;
+  double* t1r = t2i + M;   // of length M (every other one)
+  double* t1i = t1r + h;
+  for (int k = tid; k < M; k += blockDim.x) {
+    t2r[k] = tw[2 * k];
+    t2i[k] = tw[2 * k + 1];
+    if (k < h) {
+      t1r[k] = tw[4 * k];
+      t1i[k] = tw[4 * k + 1];
+    }
+  }
+  // the history: new nhat [2M complex] from the old [M complex], doubled; read all first
+  double hr[2 * kTLMaxM / kTLThreads], hi[2 * kTLMaxM / kTLThreads];
+  constexpr int UH = 2 * kTLMaxM / kTLThreads;
+#pragma unroll
+  for (int u = 0; u < UH; ++u) {
+    const int q = tid + u * kTLThreads;  // index in the doubled spectrum
+    hr[u] = hi[u] = 0.0;
+    if (q < M2) {
+      int src = -1;
+      if (q < h) src = q;
+      else if (q > M2 - h) src = q - M;  // negative wavenumbers q - 2M = src - M
+      if (src >= 0) {
+        hr[u] = 2.0 * nhat[2 * src];
+        hi[u] = 2.0 * nhat[2 * src + 1];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < UH; ++u) {
+    const int q = tid + u * kTLThreads;
+    if (q < M2) {
+      nhat[2 * q] = hr[u];
+      nhat[2 * q + 1] = hi[u];
+    }
+  }
+  double* arrs[3] = {eta, phi, phi2};
+  for (int a = 0; a < 3; ++a) {
+    double* f = arrs[a];
+    double* pr = xr;
+    double* pi = xi;
+    double* qr = yr;
+    double* qi = yi;
+    for (int j = tid; j < M; j += blockDim.x) {
+      pr[j] = f[j];
+      pi[j] = 0.0;
+    }
+    __syncthreads();
+    fft_lds(pr, pi, qr, qi, t1r, t1i, M, false);
+    // spectrum of length 2M into (qr, qi): 2 F[q] on |k| < M/2, zero elsewhere
+    for (int q = tid; q < M2; q += blockDim.x) {
+      int src = -1;
+      if (q < h) src = q;
+      else if (q > M2 - h) src = q - M;
+      qr[q] = src >= 0 ? 2.0 * pr[src] : 0.0;
+      qi[q] = src >= 0 ? 2.0 * pi[src] : 0.0;
+    }
+    __syncthreads();
+    fft_lds(qr, qi, pr, pi, t2r, t2i, M2, true);
+    const double sc = 1.0 / M2;
+    for (int j = tid; j < M2; j += blockDim.x) f[j] = qr[j] * sc;
+    __syncthreads();
+  }
+}
+inline size_t refine_lds_bytes(int M) { return sizeof(double) * (8 * static_cast<size_t>(M) + 3 * M); }
+
 __global__ void k_twiddles(int M, double* __restrict__ tw) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M / 2) return;
@@ -542,6 +625,16 @@ static int tl_check(const thetaL* th, bool need_ready) {
   return KFBI_OK;
 }
 
+// Switch the object to M markers (twiddles of length M); state arrays are not touched.
+static int tl_set_M(thetaL* th, int M) {
+  if (M == th->M) return KFBI_OK;
+  hipLaunchKernelGGL(k_twiddles, dim3((M / 2 + 255) / 256), dim3(256), 0, th->stream, M,
+                     th->tw.as<double>());
+  KFBI_HIP(hipGetLastError());
+  th->M = M;
+  return KFBI_OK;
+}
+
 static void tl_free(thetaL* th) {
   for (DBuf* b : {&th->tw, &th->eta, &th->scal, &th->X, &th->rhs, &th->aux, &th->etahat, &th->nhat,
                   &th->phi, &th->phi2, &th->phiw, &th->dnp, &th->dnm, &th->init})
@@ -573,6 +666,11 @@ int thetaL_create(const thetaL_params* p, thetaL** out) {
     set_error("thetaL: need tau > 0, sigma >= 0, finite J");
     return KFBI_E_INVALID;
   }
+  const int Mcap = p->max_M > 0 ? p->max_M : M;
+  if (Mcap < M || Mcap > kTLMaxM || (Mcap & (Mcap - 1)) || !(p->refine >= 0.0)) {
+    set_error("thetaL: max_M must be a power of two in [M, %d] and refine >= 0", kTLMaxM);
+    return KFBI_E_INVALID;
+  }
   thetaL* th = new (std::nothrow) thetaL();
   if (!th) {
     set_error("out of host memory");
@@ -580,8 +678,9 @@ int thetaL_create(const thetaL_params* p, thetaL** out) {
   }
   th->prm = *p;
   th->M = M;
+  th->Mcap = Mcap;
   kfbi_grid g = p->grid;
-  g.max_markers = M;
+  g.max_markers = Mcap;
   int st = kfbi_create(&g, &th->kc);
   if (st != KFBI_OK) {
     delete th;
@@ -589,16 +688,17 @@ int thetaL_create(const thetaL_params* p, thetaL** out) {
   }
   th->stream = static_cast<hipStream_t>(g.stream);
   const int Mi = 4096;  // largest accepted input sampling of thetaL_init
-  if ((st = th->tw.ensure(sizeof(double) * M)) || (st = th->eta.ensure(sizeof(double) * M)) ||
+  const int C = Mcap;   // every per-marker buffer is sized for the refinement limit
+  if ((st = th->tw.ensure(sizeof(double) * C)) || (st = th->eta.ensure(sizeof(double) * C)) ||
       (st = th->scal.ensure(sizeof(double) * S_COUNT)) ||
-      (st = th->X.ensure(sizeof(double) * 2 * M)) || (st = th->rhs.ensure(sizeof(double) * M)) ||
-      (st = th->aux.ensure(sizeof(double) * A_COUNT * M)) ||
-      (st = th->etahat.ensure(sizeof(double) * 2 * M)) ||
-      (st = th->nhat.ensure(sizeof(double) * 2 * M)) ||
-      (st = th->phi.ensure(sizeof(double) * M)) || (st = th->phi2.ensure(sizeof(double) * M)) ||
-      (st = th->phiw.ensure(sizeof(double) * M)) ||
-      (st = th->dnp.ensure(sizeof(double) * M)) || (st = th->dnm.ensure(sizeof(double) * M)) ||
-      (st = th->init.ensure(sizeof(double) * (2 * Mi + 4 * Mi + 2 * Mi + 2 * Mi + Mi + 3 * M)))) {
+      (st = th->X.ensure(sizeof(double) * 2 * C)) || (st = th->rhs.ensure(sizeof(double) * C)) ||
+      (st = th->aux.ensure(sizeof(double) * A_COUNT * C)) ||
+      (st = th->etahat.ensure(sizeof(double) * 2 * C)) ||
+      (st = th->nhat.ensure(sizeof(double) * 2 * C)) ||
+      (st = th->phi.ensure(sizeof(double) * C)) || (st = th->phi2.ensure(sizeof(double) * C)) ||
+      (st = th->phiw.ensure(sizeof(double) * C)) ||
+      (st = th->dnp.ensure(sizeof(double) * C)) || (st = th->dnm.ensure(sizeof(double) * C)) ||
+      (st = th->init.ensure(sizeof(double) * (2 * Mi + 4 * Mi + 2 * Mi + 2 * Mi + Mi + 3 * C)))) {
     tl_free(th);
     delete th;
     return st;
@@ -619,13 +719,17 @@ int thetaL_create(const thetaL_params* p, thetaL** out) {
     set_error("thetaL: twiddle kernel failed");
     return KFBI_E_HIP;
   }
-  const size_t lds = tl_lds_bytes(M);
+  const size_t lds = tl_lds_bytes(Mcap);
   if (lds > 64 * 1024) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_pre),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_post),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   }
+  const size_t rlds = refine_lds_bytes(Mcap / 2);
+  if (rlds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_refine),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rlds));
   *out = th;
   return KFBI_OK;
 }
@@ -646,6 +750,7 @@ int thetaL_init(thetaL* th, int Mi, const double* xy) {
     set_error("thetaL_init: Mi must be even in [16, 4096] with a non-null xy (Mi=%d)", Mi);
     return KFBI_E_INVALID;
   }
+  KFBI_TRY(tl_set_M(th, th->prm.M));  // back to the initial markers
   const int M = th->M;
   hipStream_t s = th->stream;
   double* w = th->init.as<double>();
@@ -762,11 +867,37 @@ int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
     stats->ms_gmres = ms_gm;
     stats->ms_apply = ms_ap;
     stats->ms_update = ms_up;
+    stats->M = M;
+    stats->M_next = M;
   }
   if (th->hscal[S_BAD] != 0.0) {
     set_error("thetaL_step: the new state is not finite (step %d)", step);
     return KFBI_E_NONFINITE;
   }
+  // adaptive refinement: marker spacing of the new state against the grid spacing
+  const double hgrid = p.grid.side / p.grid.N;
+  if (p.refine > 0.0 && th->hscal[S_L] / M > p.refine * hgrid && 2 * M <= th->Mcap) {
+    KFBI_TRY(tl_set_M(th, 2 * M));  // twiddles of length 2M
+    hipLaunchKernelGGL(k_tl_refine, dim3(1), dim3(kTLThreads), refine_lds_bytes(M), s, M,
+                       th->tw.as<double>(), th->eta.as<double>(), th->phi.as<double>(),
+                       th->phi2.as<double>(), th->nhat.as<double>());
+    KFBI_HIP(hipGetLastError());
+    KFBI_HIP(hipStreamSynchronize(s));
+  }
+  if (stats) {
+    stats->M = M;
+    stats->M_next = th->M;
+  }
+  return KFBI_OK;
+}
+
+int thetaL_size(const thetaL* th, int* M) {
+  KFBI_TRY(tl_check(th, false));
+  if (!M) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  *M = th->M;
   return KFBI_OK;
 }
 
@@ -797,6 +928,7 @@ int thetaL_get_state(const thetaL* th, thetaL_state* st) {
   KFBI_HIP(hipStreamSynchronize(s));
   for (int q = 0; q < 8; ++q) st->scal[q] = th->hscal[q];
   st->n = th->n;
+  st->M = M;
   return KFBI_OK;
 }
 
@@ -811,6 +943,12 @@ int thetaL_set_state(thetaL* th, const thetaL_state* st) {
     set_error("thetaL_set_state: L must be positive");
     return KFBI_E_INVALID;
   }
+  const int Ms = st->M == 0 ? th->M : st->M;
+  if (Ms < 16 || Ms > th->Mcap || (Ms & (Ms - 1))) {
+    set_error("thetaL_set_state: M must be a power of two in [16, max_M] (M=%d)", Ms);
+    return KFBI_E_INVALID;
+  }
+  KFBI_TRY(tl_set_M(th, Ms));
   const int M = th->M;
   hipStream_t s = th->stream;
   KFBI_HIP(hipMemcpyAsync(th->eta.p, st->eta_dev, sizeof(double) * M, hipMemcpyDeviceToDevice, s));

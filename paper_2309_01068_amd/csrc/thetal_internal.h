@@ -17,7 +17,8 @@ struct thetaL {
   thetaL_params prm{};
   kfbi_ctx* kc = nullptr;
   hipStream_t stream = nullptr;
-  int M = 0;
+  int M = 0;           // current markers
+  int Mcap = 0;        // largest M (refinement limit); buffers are sized for it
   int n = 0;           // steps taken
   int ready = 0;       // thetaL_init or set_state done
   int have_phi = 0;    // phi_prev holds a density

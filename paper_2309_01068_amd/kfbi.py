@@ -27,6 +27,7 @@ EXPORTS = [
     "kfbi_profile_kernel",
     "thetaL_create", "thetaL_destroy", "thetaL_init", "thetaL_step", "thetaL_run",
     "thetaL_markers", "thetaL_density", "thetaL_kfbi", "thetaL_get_state", "thetaL_set_state",
+    "thetaL_size",
     "kfbi_ws_create", "kfbi_ws_destroy", "kfbi_ws_n_params", "kfbi_ws_get_weights",
     "kfbi_ws_set_weights", "kfbi_ws_predict", "kfbi_ws_record", "kfbi_ws_n_samples",
     "kfbi_ws_clear", "kfbi_ws_train", "kfbi_ws_eval", "kfbi_ws_forward", "kfbi_ws_backward",
@@ -77,14 +78,16 @@ class GmresStats(C.Structure):
 
 class ThetaLParams(C.Structure):
     _fields_ = [("grid", Grid), ("M", C.c_int), ("sigma", C.c_double), ("J", C.c_double),
-                ("tau", C.c_double), ("lambda2", C.c_double), ("gmres", GmresOpts)]
+                ("tau", C.c_double), ("lambda2", C.c_double), ("gmres", GmresOpts),
+                ("refine", C.c_double), ("max_M", C.c_int)]
 
 
 class ThetaLStats(C.Structure):
     _fields_ = [("step", C.c_int), ("t", C.c_double), ("iters", C.c_int), ("applies64", C.c_int),
                 ("applies32", C.c_int), ("relres", C.c_double), ("area", C.c_double),
                 ("length", C.c_double), ("ms_geometry", C.c_double), ("ms_gmres", C.c_double),
-                ("ms_apply", C.c_double), ("ms_update", C.c_double)]
+                ("ms_apply", C.c_double), ("ms_update", C.c_double), ("M", C.c_int),
+                ("M_next", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -93,7 +96,7 @@ class ThetaLStats(C.Structure):
 class ThetaLState(C.Structure):
     _fields_ = [("eta_dev", C.c_void_p), ("phi_prev_dev", C.c_void_p),
                 ("phi_prev2_dev", C.c_void_p), ("nhat_prev_dev", C.c_void_p),
-                ("scal", C.c_double * 8), ("n", C.c_int)]
+                ("scal", C.c_double * 8), ("n", C.c_int), ("M", C.c_int)]
 
 
 class WsCfg(C.Structure):
@@ -139,6 +142,7 @@ def load(path: str = LIBPATH):
     lib.thetaL_kfbi.restype = vp
     lib.thetaL_get_state.argtypes = [vp, C.POINTER(ThetaLState)]
     lib.thetaL_set_state.argtypes = [vp, C.POINTER(ThetaLState)]
+    lib.thetaL_size.argtypes = [vp, C.POINTER(C.c_int)]
     ip, fp = C.POINTER(C.c_int), C.POINTER(C.c_float)
     lib.kfbi_ws_create.argtypes = [C.POINTER(WsCfg), C.POINTER(vp)]
     lib.kfbi_ws_destroy.argtypes = [vp]
@@ -277,17 +281,23 @@ class ThetaL:
     """theta-L / SSD Hele-Shaw evolution (include/thetal.h) on the current torch stream."""
 
     def __init__(self, x0, y0, side, N, M, sigma, J, tau, lambda2=-1.0, tol=1e-10, restart=50,
-                 maxit=1000, precision=FP64, inner_tol=1e-5, stream=None):
+                 maxit=1000, precision=FP64, inner_tol=1e-5, stream=None, refine=0.0, max_M=0):
         self.lib = load()
         s = torch.cuda.current_stream() if stream is None else stream
         self.stream = s
         g = Grid(x0, y0, side, N, 0.0, BOX_FREESPACE, M, C.c_void_p(s.cuda_stream))
         p = ThetaLParams(g, M, sigma, J, tau, lambda2,
-                         GmresOpts(tol, restart, maxit, precision, inner_tol))
+                         GmresOpts(tol, restart, maxit, precision, inner_tol), refine, max_M)
         h = C.c_void_p()
         _check(self.lib.thetaL_create(C.byref(p), C.byref(h)))
         self.h = h
-        self.M = M
+
+    @property
+    def M(self) -> int:
+        """Current number of markers (refinement doubles it)."""
+        m = C.c_int()
+        _check(self.lib.thetaL_size(self.h, C.byref(m)))
+        return m.value
 
     def close(self):
         if self.h:
@@ -333,7 +343,7 @@ class ThetaL:
                          C.c_void_p(phi2.data_ptr()), C.c_void_p(nh.data_ptr()))
         _check(self.lib.thetaL_get_state(self.h, C.byref(st)))
         return {"eta": eta, "phi_prev": phi, "phi_prev2": phi2, "nhat_prev": nh,
-                "scal": list(st.scal), "n": st.n}
+                "scal": list(st.scal), "n": st.n, "M": st.M}
 
     def set_state(self, d: dict):
         st = ThetaLState(_ptr(d["eta"]), _ptr(d["phi_prev"]), _ptr(d["phi_prev2"]),
@@ -341,6 +351,7 @@ class ThetaL:
         for i in range(8):
             st.scal[i] = d["scal"][i]
         st.n = d["n"]
+        st.M = d.get("M", d["eta"].numel())
         _check(self.lib.thetaL_set_state(self.h, C.byref(st)))
 
 

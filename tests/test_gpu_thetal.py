@@ -188,3 +188,77 @@ def test_area_conserved_without_injection():
     lengths = np.array([r["length"] for r in recs])
     assert np.max(np.abs(areas - areas[0])) <= 1e-3 * areas[0]
     assert np.all(np.diff(lengths) < 0)
+
+
+# Refinement is tested with the ratio 2.1: doubling then lands at a spacing of about
+# 1.05 h.  At the paper's ratio 1.5 the doubled markers sit 0.75 h apart, where this
+# discretisation (and the oracle alike) lets grid-scale modes of eta grow.
+def test_refinement_parity():
+    """Adaptive refinement (marker spacing above 2.1 h doubles M): the GPU evolution
+    follows the oracle through a refinement from 64 to 128 markers."""
+    box = W.box(-2, 2, 128)
+    X = W.hs3(64)
+    st, prm = oracle_state(X, 64, box, 1e-3, 1.0, 1e-3)
+    from paper_2309_01068_amd import kfbi
+    th = kfbi.ThetaL(box.x0, box.y0, box.side, box.N, 64, 1e-3, 1.0, 1e-3, refine=2.1,
+                     max_M=512)
+    th.init(dev(X))
+    Ms = []
+    for k in range(4):
+        print(f"[case] refinement step {k}", flush=True)
+        st, info = T.hs_step(st, prm)
+        if T.refine_due(st, box.h, 2.1, 512):
+            st = T.refine(st)
+        g = th.step()
+        Ms.append((g["M"], g["M_next"]))
+        assert g["M_next"] == st.eta.size
+        s = th.get_state()
+        assert s["M"] == st.eta.size
+        assert np.max(np.abs(host(s["eta"]) - st.eta)) <= 1e-10, k
+        assert abs(s["scal"][0] - st.L) <= 1e-12 * st.L
+        assert np.max(np.abs(np.array(s["scal"][1:3]) - st.Xbar)) <= 1e-11
+        assert np.linalg.norm(host(s["phi_prev"]) - st.phi_prev) <= 1e-8 * np.linalg.norm(st.phi_prev)
+    assert Ms[0] == (64, 128) and Ms[1] == (128, 128)
+    assert th.M == 128 and th.markers().shape == (2, 128)
+
+
+def test_circle_growth_through_refinements():
+    """A growing circle keeps R = sqrt(R0^2 + 2 J t) while its markers double three times
+    (32 -> 64 -> 128 in the first steps, -> 256 once L/M exceeds 2.1 h again)."""
+    from paper_2309_01068_amd import kfbi
+    R0 = 0.5
+    box = W.box(-1.5, 1.5, 128)
+    th = kfbi.ThetaL(box.x0, box.y0, box.side, box.N, 32, 1e-3, 1.0, 2e-3, refine=2.1,
+                     max_M=256)
+    th.init(dev(W.circle(32, R0)))
+    recs = th.run(200)
+    Ms = [r["M"] for r in recs]
+    assert Ms[:3] == [32, 64, 128] and Ms[-1] == 256
+    k3 = Ms.index(256)
+    s = th.get_state()
+    R = s["scal"][0] / (2 * np.pi)
+    assert abs(R - np.sqrt(R0 ** 2 + 2 * s["scal"][3])) < 5e-5
+    assert np.std(host(s["eta"])) < 1e-8
+    # the last refinement came with the first step whose new spacing exceeded 2.1 h
+    Rt = lambda t: np.sqrt(R0 ** 2 + 2 * t)
+    assert 2 * np.pi * Rt(recs[k3 - 1]["t"]) / 128 > 2.1 * box.h
+    assert 2 * np.pi * Rt(recs[k3 - 2]["t"]) / 128 < 2.1 * box.h * 1.0001
+
+
+def test_checkpoint_keeps_the_refined_markers():
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-2, 2, 128)
+    mk = lambda: kfbi.ThetaL(box.x0, box.y0, box.side, box.N, 64, 1e-3, 1.0, 1e-3,
+                             refine=2.1, max_M=256)
+    a = mk()
+    a.init(dev(W.hs3(64)))
+    a.run(2)
+    ck = {k: (v.clone() if torch.is_tensor(v) else v) for k, v in a.get_state().items()}
+    assert ck["M"] == 128
+    a.run(2)
+    b = mk()
+    b.set_state(ck)
+    assert b.M == 128
+    b.run(2)
+    sa, sb = a.get_state(), b.get_state()
+    assert torch.equal(sa["eta"], sb["eta"]) and sa["scal"] == sb["scal"]
