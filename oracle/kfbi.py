@@ -13,6 +13,11 @@ Sec. 4.3: one-sided limits v+, grad v+ from the 6x6 corrected Taylor system on t
     operator = average of the one-sided limits.
 Sec. 4.1 (Hele-Shaw): box data for the free-space problem by the composite trapezoidal
     rule of the layer potential on the box nodes.
+Sec. 3.2 (Stefan): the box Green's function with zero normal derivative on the box.
+    Reading: the five-point scheme then holds at every node (i, j = 0..N) with the
+    ghost values mirrored across the box (v_{-1,j} = v_{1,j}, ...), which the 2-D DCT-I
+    diagonalises (eigenvalues as for the DST with p, q = 0..N); the right-hand side off
+    the irregular nodes is zero, also on the box.
 
 Readings (see geometry.py for the geometric ones): the correction of eq. (modified-fdm)
 is generalised to all four arm directions and both sides: for an arm P -> Q cut at the
@@ -23,7 +28,10 @@ and the 6x6 system is solved in h-scaled unknowns (v, h v_x, h v_y, h^2 v_xx, ..
 
 Pinned by: DST solve vs direct sparse solve / brute-force sums, exactness on piecewise
 harmonic quadratics, closed-form layer potentials on circles (second-order
-convergence), App. A formulas vs exact jumps (tests/test_oracle_kfbi.py).
+convergence), App. A formulas vs exact jumps (tests/test_oracle_kfbi.py); the DCT-I
+solve vs a direct sparse solve of the mirrored-ghost system and brute-force sums, and
+layer potentials with the zero-normal-derivative box vs the free-space closed forms
+when the box is many decay lengths 1/c away (tests/test_oracle_neumann.py).
 """
 from __future__ import annotations
 
@@ -37,7 +45,7 @@ from .geometry import Geometry, interpolate_at
 
 SINGLE, DOUBLE = 0, 1
 PLUS, MINUS, AVG = 0, 1, 2
-BOX_ZERO, BOX_USER, BOX_FREESPACE = 0, 1, 2
+BOX_ZERO, BOX_USER, BOX_FREESPACE, BOX_NEUMANN = 0, 1, 2, 3
 
 
 # ----------------------------------------------------------------------------- jumps
@@ -178,6 +186,30 @@ def solve_fivepoint(rhs: np.ndarray, h: float, c2: float) -> np.ndarray:
     return V
 
 
+def dct1w(a: np.ndarray, axis: int) -> np.ndarray:
+    """X_p = sum_{i=0}^{N} w_i a_i cos(pi p i / N), w_0 = w_N = 1/2, else 1 (scipy's DCT-I
+    is twice this); applied twice it gives (N/2) a."""
+    return 0.5 * sfft.dct(a, type=1, axis=axis)
+
+
+def solve_neumann(rhs: np.ndarray, h: float, c2: float) -> np.ndarray:
+    """Unique solution (c2 > 0) of (Delta_h - c^2) v = rhs on all (N+1)^2 nodes with the
+    mirrored ghost values of the zero-normal-derivative box, by the 2-D DCT-I."""
+    N = rhs.shape[0] - 1
+    p = np.arange(N + 1)
+    s2 = np.sin(0.5 * np.pi * p / N) ** 2
+    lam = -(4.0 / (h * h)) * (s2[:, None] + s2[None, :]) - c2
+    F = dct1w(dct1w(rhs, 0), 1)
+    return dct1w(dct1w(F / lam, 0), 1) * (2.0 / N) ** 2
+
+
+def fivepoint_apply_neumann(v: np.ndarray, h: float, c2: float) -> np.ndarray:
+    """(Delta_h - c^2) v on all nodes with mirrored ghost values (for pins)."""
+    p = np.pad(v, 1, mode="reflect")
+    return ((p[1:-1, 2:] + p[1:-1, :-2] + p[2:, 1:-1] + p[:-2, 1:-1] - 4.0 * v) / (h * h)
+            - c2 * v)
+
+
 def fivepoint_apply(v: np.ndarray, h: float, c2: float) -> np.ndarray:
     """(Delta_h - c^2) v on interior nodes with zero boundary values (for pins)."""
     p = np.pad(v, 1)
@@ -234,16 +266,24 @@ class ApplyResult:
     rhs: np.ndarray
 
 
-def solve_interface(g: Geometry, Phi, Psi, c2: float, ring: np.ndarray | None) -> ApplyResult:
-    """Solve the equivalent interface problem for given jumps (Phi, Psi) and box data."""
+def solve_interface(g: Geometry, Phi, Psi, c2: float, ring: np.ndarray | None,
+                    neumann: bool = False) -> ApplyResult:
+    """Solve the equivalent interface problem for given jumps (Phi, Psi) and box data
+    (Dirichlet values `ring`, or the zero-normal-derivative box when `neumann`)."""
     N, h = g.box.N, g.box.side / g.box.N
     mk = g.mk
     q = InterfaceData(*marker_quantities(np.asarray(Phi, float), np.asarray(Psi, float)))
-    rhs = corrected_rhs(g, q, c2, ring)
-    v = solve_fivepoint(rhs, h, c2)
-    grid = np.zeros((N + 1, N + 1))
-    grid[1:N, 1:N] = v
-    if ring is not None:
+    rhs = corrected_rhs(g, q, c2, None if neumann else ring)
+    if neumann:
+        full = np.zeros((N + 1, N + 1))
+        full[1:N, 1:N] = rhs
+        grid = solve_neumann(full, h, c2)
+        rhs = full
+    else:
+        v = solve_fivepoint(rhs, h, c2)
+        grid = np.zeros((N + 1, N + 1))
+        grid[1:N, 1:N] = v
+    if ring is not None and not neumann:
         bottom, top, left, right = ring
         grid[0, :], grid[N, :] = bottom, top
         grid[:, 0], grid[:, N] = left, right
@@ -265,6 +305,10 @@ def apply(g: Geometry, layer: int, density: np.ndarray, c2: float, box_bc: int =
         if c2 != 0.0:
             raise ValueError("free-space box data is defined for the Laplacian only")
         ringv = freespace_ring(g, layer, np.asarray(density, dtype=np.float64))
+    elif box_bc == BOX_NEUMANN:
+        if not c2 > 0.0:
+            raise ValueError("the zero-normal-derivative box needs c2 > 0")
+        return solve_interface(g, Phi, Psi, c2, None, neumann=True)
     else:
         raise ValueError("unknown box condition")
     return solve_interface(g, Phi, Psi, c2, ringv)
@@ -278,11 +322,14 @@ def trace(res: ApplyResult, side: int) -> np.ndarray:
     return 0.5 * (res.v_plus + res.v_minus)
 
 
-def operator(g: Geometry, x: np.ndarray, layer: int, side: int, a: float, b: float, q: float,
+def operator(g: Geometry, x: np.ndarray, layer: int, side: int, a, b: float, q: float,
              c2: float, box_bc: int = BOX_ZERO) -> np.ndarray:
-    """Discrete boundary operator A x = a x + b trace_side(layer[x]) + q sum_k x_k s_a,k 2pi/M.
+    """Discrete boundary operator A x = a x + b trace_side(layer[x]) + q sum_k x_k s_a,k 2pi/M
+    (a a scalar or one value per marker).
     Hele-Shaw (Sec. 3.1, eq. bie-HS): layer D, side -, a=0, b=1, q=1 gives
-    -phi/2 + D phi + int phi ds.  Interior Dirichlet: D, side +, a=0, b=1, q=0."""
+    -phi/2 + D phi + int phi ds.  Interior Dirichlet: D, side +, a=0, b=1, q=0.
+    Gibbs-Thomson (Sec. 3.2, eq. bie-GT): layer S, average, a = eps_V, b = -1, q = 0 with
+    the zero-normal-derivative box."""
     res = apply(g, layer, x, c2, box_bc)
     out = a * x + b * trace(res, side)
     if q != 0.0:
