@@ -53,6 +53,11 @@ extern "C" {
 #define KFBI_BOX_USER 1      /* caller supplies the box values with each apply               */
 #define KFBI_BOX_FREESPACE 2 /* free-space layer potential on the box by the trapezoidal rule
                                 (Sec. 4.1, Hele-Shaw); requires c2 == 0                     */
+#define KFBI_BOX_NEUMANN 3   /* zero normal derivative on the box (the Stefan problem's box
+                                Green's function, Sec. 3.2): the five-point scheme holds at
+                                every node (i, j = 0..N) with ghost values mirrored across
+                                the box, solved by the cosine transform; requires c2 > 0.
+                                The grid output then holds the solution on the box too. */
 /* arithmetic of the grid stages (jumps, corrections, solve, interpolation) */
 #define KFBI_FP64 0
 #define KFBI_FP32 1
@@ -143,11 +148,14 @@ int kfbi_apply_batch(kfbi_ctx* ctx, int layer, int precision, int B, const doubl
  *                                          + q * sum_k x_k s_a,k (2 pi / M).
  * Hele-Shaw (Sec. 3.1, eq. bie-HS): {DOUBLE, MINUS, a=0, b=1, q=1} with the free-space
  * box; interior Dirichlet: {DOUBLE, PLUS, 0, 1, 0}; Gibbs-Thomson (eq. bie-GT):
- * {SINGLE, AVG, eps_V, -1, 0}. */
+ * {SINGLE, AVG, eps_V, -1, 0} with the zero-normal-derivative box.  a_marker: NULL, or
+ * a device array of M doubles that replaces a by one value per marker (an anisotropic
+ * eps_V); it must stay valid while the operator is in use. */
 typedef struct {
   int layer;
   int side;
   double a, b, q;
+  const double* a_marker;
 } kfbi_bie;
 
 /* y_dev[M] = A x_dev (FP64 in/out; precision selects the grid arithmetic). */

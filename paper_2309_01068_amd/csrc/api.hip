@@ -68,7 +68,7 @@ static void release_all(kfbi_ctx* c) {
   DBuf* bufs[] = {&c->vraw, &c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
                   &c->vid,    &c->lab,    &c->armcnt, &c->rowsum,  &c->armrow, &c->armpk,
                   &c->armc,   &c->armk,   &c->colc,   &c->lanef,   &c->cnode,  &c->ccount,
-                  &c->mkloc,  &c->tmat,   &c->pdesc,  &c->rowpart, &c->ckoff, &c->cklist, &c->ckcoef, &c->ckmk,
+                  &c->mkloc,  &c->tmat,   &c->pdesc,  &c->rowpart, &c->ckoff, &c->cklist, &c->ckcoef, &c->ckmk, &c->mqz,
                   &c->armcoef, &c->intptr, &c->need,    &c->nodeidx, &c->nodei,
                   &c->rowptr, &c->rows,   &c->mknode, &c->ext,     &c->gstat,  &c->mq,
                   &c->armr,   &c->qpart,  &c->ring,   &c->sinT,    &c->sinT32, &c->gband,
@@ -106,12 +106,16 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
     set_error("invalid box or c2");
     return KFBI_E_INVALID;
   }
-  if (g->box_bc < KFBI_BOX_ZERO || g->box_bc > KFBI_BOX_FREESPACE) {
+  if (g->box_bc < KFBI_BOX_ZERO || g->box_bc > KFBI_BOX_NEUMANN) {
     set_error("invalid box_bc %d", g->box_bc);
     return KFBI_E_INVALID;
   }
   if (g->box_bc == KFBI_BOX_FREESPACE && g->c2 != 0.0) {
     set_error("free-space box data is defined for the Laplacian (c2 == 0) only");
+    return KFBI_E_INVALID;
+  }
+  if (g->box_bc == KFBI_BOX_NEUMANN && !(g->c2 > 0.0)) {
+    set_error("the zero-normal-derivative box needs c2 > 0");
     return KFBI_E_INVALID;
   }
   if (g->max_markers < 16 || g->max_markers > 4096) {
@@ -168,14 +172,18 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
       (st = c->ring.ensure(sizeof(double) * 8 * (N + 1) * Bx)) ||
       (st = c->sinT.ensure(sizeof(double) * 2 * N)) ||
       (st = c->sinT32.ensure(sizeof(float) * 2 * N)) ||
-      (st = c->gband.ensure(sizeof(double) * n * N * Bx)) ||
+      // band rows of G: the sine layout needs n N values, the cosine layout 4 ceil((N+1)/4)
+      // values per row for up to N+1 rows
+      (st = c->gband.ensure(sizeof(double) * (N + 4) * (N + 1) * Bx)) ||
+      (st = c->mqz.ensure(sizeof(double) * 5 * Mx)) ||
       (st = c->tmpM.ensure(sizeof(double) * (Bx > 4 ? Bx : 4) * Mx)))
     return fail(st);
   if (hipHostMalloc(&c->hpin, 4096, hipHostMallocDefault) != hipSuccess) {
     set_error("hipHostMalloc failed");
     return fail(KFBI_E_NOMEM);
   }
-  if (hipMemsetAsync(c->tmpM.p, 0, c->tmpM.bytes, c->stream) != hipSuccess) {
+  if (hipMemsetAsync(c->mqz.p, 0, c->mqz.bytes, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->tmpM.p, 0, c->tmpM.bytes, c->stream) != hipSuccess) {
     set_error("hipMemsetAsync failed");
     return fail(KFBI_E_HIP);
   }

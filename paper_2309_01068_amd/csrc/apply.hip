@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 #include "device_util.h"
@@ -375,7 +376,9 @@ __global__ void __launch_bounds__(256)
 // two-level table and advancing by the three-term sine recurrence in steps of i_a pi / N.
 // Parts of one row are summed in
 // part order by the solve kernel.
-template <class T, int PT>
+// COSB (zero-normal-derivative box): the cosine transform T[j][p] = sum_a r_a cos(p i_a pi/N)
+// over the modes p = 0..N instead (mode index p, not p - 1, in the column-group layout).
+template <class T, int PT, bool COSB>
 __global__ void __launch_bounds__(256)
     k_rowdst(int N, int P, const int4* __restrict__ pdesc, const double* __restrict__ rslot,
              const int* __restrict__ iR, const T* __restrict__ sinT, T* __restrict__ Tg,
@@ -400,7 +403,8 @@ __global__ void __launch_bounds__(256)
   }
   const int na = d.z - d.y;
   __syncthreads();
-  const int p0 = 1 + tid * PT;
+  const int p0 = (COSB ? 0 : 1) + tid * PT;
+  const int pmax = COSB ? N : n;  // last mode
   T acc[PT];
 #pragma unroll
   for (int k = 0; k < PT; ++k) acc[k] = T(0);
@@ -411,9 +415,16 @@ __global__ void __launch_bounds__(256)
     st2.get((p0 * i) & mask, s, c);
     st2.get(i & mask, sb, cb);
     // sin((p + 1) x) = 2 cos(x) sin(p x) - sin((p - 1) x), started from sin(p0 x) and
-    // sin((p0 - 1) x); over PT steps the rounding grows by at most a factor PT
+    // sin((p0 - 1) x); over PT steps the rounding grows by at most a factor PT.  The
+    // cosine obeys the same recurrence.
     const T c2 = cb + cb;
-    T sm = s * cb - c * sb;
+    T sm;
+    if constexpr (COSB) {
+      sm = c * cb + s * sb;  // cos((p0 - 1) x)
+      s = c;
+    } else {
+      sm = s * cb - c * sb;
+    }
     acc[0] += r * s;
 #pragma unroll
     for (int k = 1; k < PT; ++k) {
@@ -423,7 +434,7 @@ __global__ void __launch_bounds__(256)
       acc[k] += r * s;
     }
   }
-  if constexpr (PT % 4 == 0) {
+  if constexpr (PT % 4 == 0 && !COSB) {
     // whole groups of four modes: one 32-byte (FP64) or 16-byte (FP32) piece each; modes
     // beyond n land in the padding of the last group
 #pragma unroll
@@ -439,7 +450,7 @@ __global__ void __launch_bounds__(256)
   } else {
 #pragma unroll
     for (int k = 0; k < PT; ++k)
-      if (p0 + k <= n) Tg[grp_index(p0 + k, q, P)] = acc[k];
+      if (p0 + k <= pmax) Tg[grp_index(p0 + k + (COSB ? 1 : 0), q, P)] = acc[k];
   }
 }
 
@@ -670,13 +681,218 @@ __global__ void k_colconst(int N, double hc2, int E, double* __restrict__ colc,
   lanef[static_cast<size_t>(t) * 2 + 1] = exp(2.0 * j0 * lr);
 }
 
+// ------------------------------------------------------ K3 for the zero-normal-derivative box
+// Rows j = 0..N with mirrored ghosts: per cosine mode p = 0..N the system
+//     G_{j+1} - (2 + delta_p) G_j + G_{j-1} = b_j,  j = 0..N,  G_{-1} = G_1, G_{N+1} = G_{N-1},
+// b_j = h^2 (T[j][p] + ca Fa[j][p] + cb Fb[j][p]) (arm parts of the interior rows plus
+// optional dense right-hand sides in the column-group layout).  The two first-order
+// recurrences give a particular solution P_j = -rho z_j of the interior equations, valid
+// for all j with P_{-1} = 0 and P_{N+1} = rho P_N; the mirror conditions then fix the
+// homogeneous part:  G_j = P_j + A rho^j + B rho^{N-j} with
+//     A = (D0 + rho^N D1) / (d (1 - rho^{2N})),  B = (D1 + rho^N D0) / (d (1 - rho^{2N})),
+//     D0 = P_1,  D1 = P_{N-1} - rho P_N,  d = 1/rho - rho.
+// Lane l of the wavefront holds rows l E .. l E + E - 1.
+template <int E>
+__device__ __forceinline__ int slot0(int r) {  // row r (0-based) -> LDS slot, padded
+  return (r / E) * (E + 1) + (r % E);
+}
+
+template <class T, int E>
+__global__ void __launch_bounds__(256)
+    k_colsolve_neu(int N, double h, int P, const T* __restrict__ Tg,
+                   const int* __restrict__ rowpart, const T* __restrict__ Fa,
+                   const T* __restrict__ Fb, double ca, double cb,
+                   const double* __restrict__ colc, const double* __restrict__ lanef, int jlo,
+                   int jhi, T* __restrict__ Gg, int nblk_x, size_t tstride, size_t gstride) {
+  __shared__ T col[kColsPerBlock][64 * (E + 1)];
+  extern __shared__ double dynp[];  // the group's P part rows, 4 modes each
+  T* tp = reinterpret_cast<T*>(dynp);
+  const int nm = N + 1;  // modes and rows
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int bid = blockIdx.x;
+  const int per_xcd = (nblk_x + 7) / 8;
+  const int grp = (bid % 8) * per_xcd + bid / 8;
+  if (grp * kColsPerBlock > N) return;  // whole block beyond the last mode
+  Tg += static_cast<size_t>(blockIdx.y) * tstride;
+  Gg += static_cast<size_t>(blockIdx.y) * gstride;
+  const int m0 = grp * kColsPerBlock;
+  const int m = m0 + w;
+  const bool live = (m <= N);
+  double rho = 0.0, eps = 0.0, inv_den = 0.0, rN = 0.0, lr0 = 0.0, lr1 = 0.0;
+  if (live) {
+    rho = colc[4 * m];
+    eps = colc[4 * m + 1];
+    inv_den = colc[4 * m + 2];
+    rN = colc[4 * m + 3];
+    lr0 = lanef[(static_cast<size_t>(m) * 64 + lane) * 2];
+    lr1 = lanef[(static_cast<size_t>(m) * 64 + lane) * 2 + 1];
+  }
+  constexpr int R = (64 * E + 255) / 256;  // rows per thread in the row sums
+  int rq0[R], rq1[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = tid + 256 * u;
+    const bool in = (P > 0) && r >= 1 && r <= N - 1;  // arms sit on interior rows only
+    rq0[u] = in ? rowpart[r] : 0;
+    rq1[u] = in ? rowpart[r + 1] : 0;
+  }
+  if (P > 0) {
+    const T* src = Tg + static_cast<size_t>(grp) * P * 4;
+    constexpr int U = 8;
+    for (int e0 = tid; e0 < 4 * P; e0 += 256 * U) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 256 * u;
+        v[u] = (e < 4 * P) ? src[e] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < 4 * P) tp[e] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const T tca = static_cast<T>(ca), tcb = static_cast<T>(cb);
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int r = tid + 256 * u;
+      if (r >= 64 * E) continue;
+      T a4[kColsPerBlock] = {};
+      for (int qq = rq0[u]; qq < rq1[u]; ++qq)
+#pragma unroll
+        for (int c = 0; c < kColsPerBlock; ++c) a4[c] += tp[4 * qq + c];
+      if (Fa && r <= N) {
+        const size_t o = (static_cast<size_t>(grp) * nm + r) * 4;
+#pragma unroll
+        for (int c = 0; c < kColsPerBlock; ++c) {
+          T f = tca * Fa[o + c];
+          if (Fb) f += tcb * Fb[o + c];
+          a4[c] += f;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kColsPerBlock; ++c) col[c][slot0<E>(r)] = a4[c];
+    }
+  }
+  __syncthreads();
+  if (live) {
+    const T rhoT = static_cast<T>(rho), epsT = static_cast<T>(eps);
+    const T h2 = static_cast<T>(h * h);
+    double pw[E + 1];
+    pw[0] = 1.0;
+#pragma unroll
+    for (int e = 1; e <= E; ++e) pw[e] = pw[e - 1] * rho;
+    T y[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = h2 * col[w][lane * (E + 1) + e];
+    // backward recurrence y_j = b_j + rho y_{j+1} (rows beyond N carry zeros)
+#pragma unroll
+    for (int e = E - 2; e >= 0; --e) y[e] = (y[e] - epsT * y[e + 1]) + y[e + 1];
+    {
+      T v = y[0];
+      double fe = pw[E];
+#pragma unroll
+      for (int s = 1; s < 64; s <<= 1) {
+        const T o = __shfl_down(v, s, 64);
+        if (lane + s < 64) v += static_cast<T>(fe) * o;
+        fe *= fe;
+      }
+      T carry = __shfl_down(v, 1, 64);
+      if (lane == 63) carry = T(0);
+#pragma unroll
+      for (int e = 0; e < E; ++e) y[e] += static_cast<T>(pw[E - e]) * carry;
+    }
+    // forward recurrence z_j = y_j + rho z_{j-1}
+#pragma unroll
+    for (int e = 1; e < E; ++e) y[e] = (y[e] - epsT * y[e - 1]) + y[e - 1];
+    {
+      T v = y[E - 1];
+      double fe = pw[E];
+#pragma unroll
+      for (int s = 1; s < 64; s <<= 1) {
+        const T o = __shfl_up(v, s, 64);
+        if (lane >= s) v += static_cast<T>(fe) * o;
+        fe *= fe;
+      }
+      T carry = __shfl_up(v, 1, 64);
+      if (lane == 0) carry = T(0);
+#pragma unroll
+      for (int e = 0; e < E; ++e) y[e] += static_cast<T>(pw[e + 1]) * carry;
+    }
+    // P_j = -rho z_j; boundary differences from rows 1, N-1, N
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = -rhoT * y[e];
+    T s1 = T(0), sa = T(0), sb = T(0);
+    const int la = (N - 1) / E, ea = (N - 1) % E, lb = N / E, eb = N % E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (e == 1) s1 = y[e];
+      if (e == ea) sa = y[e];
+      if (e == eb) sb = y[e];
+    }
+    const double P1 = static_cast<double>(__shfl(s1, 0, 64));
+    const double PNm = static_cast<double>(__shfl(sa, la, 64));
+    const double PN = static_cast<double>(__shfl(sb, lb, 64));
+    const double D0 = P1, D1 = PNm - rho * PN;
+    const double A = (D0 + rN * D1) * inv_den, B = (D1 + rN * D0) * inv_den;
+    // rows j = lane E + e: rho^j = lr0 rho^e, rho^{N-j} = lr1 rho^{E-1-e}
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = lane * E + e;
+      if (j <= N) y[e] += static_cast<T>(A * lr0 * pw[e] + B * lr1 * pw[E - 1 - e]);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) col[w][lane * (E + 1) + e] = y[e];
+  }
+  __syncthreads();
+  // rows jlo..jhi, column-group-major: this block's rows are contiguous
+  const int nb = jhi - jlo + 1;
+  T* dst = Gg + static_cast<size_t>(grp) * nb * 4;
+  for (int e = tid; e < 4 * nb; e += 256) {
+    const int r = e >> 2, c = e & 3;
+    dst[e] = (m0 + c <= N) ? col[c][slot0<E>(jlo + r)] : T(0);
+  }
+}
+
+// Per-mode constants of the mirrored-ghost column solve (p = 0..N):
+//   colc[4p + {0,1,2,3}] = rho, 1 - rho, 1 / (d (1 - rho^{2N})), rho^N,  d = 1/rho - rho
+//   lanef[(p 64 + l) 2 + {0,1}] = rho^{j0}, rho^{N - (j0 + E - 1)},  j0 = l E
+__global__ void k_colconst_neu(int N, double hc2, int E, double* __restrict__ colc,
+                               double* __restrict__ lanef) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (N + 1) * 64) return;
+  const int p = t / 64, l = t % 64;
+  const double sp = sinpi(0.5 * p / N);
+  const double delta = 4.0 * sp * sp + hc2;
+  const double sq = sqrt(delta * (4.0 + delta));
+  const double rho = 2.0 / (2.0 + delta + sq);
+  const double eps = (delta + sq) / (2.0 + delta + sq);
+  const double lr = log1p(-eps);
+  if (l == 0) {
+    const double d = 1.0 / rho - rho;
+    colc[4 * p] = rho;
+    colc[4 * p + 1] = eps;
+    colc[4 * p + 2] = 1.0 / (d * (-expm1(2.0 * N * lr)));
+    colc[4 * p + 3] = exp(N * lr);
+  }
+  const int j0 = l * E;
+  lanef[static_cast<size_t>(t) * 2] = exp(static_cast<double>(j0) * lr);
+  lanef[static_cast<size_t>(t) * 2 + 1] = exp(static_cast<double>(N - (j0 + E - 1)) * lr);
+}
+
 // ---------------------------------------------------------------------------------- K4
 // One block per chunk of MC markers.  Its distinct stencil nodes (sorted by row) are
 // split over the four wavefronts; lane l of a wavefront keeps G[j][p] for
 // p = 1 + l + 64 e and advances sin(p i pi / N) over e by the three-term sine recurrence
 // with step 64 i pi / N.  Eight nodes are reduced together by recursive halving.  Then
 // MC threads apply the Sec. 4.3 corrected interpolation.
-template <class T, int E>
+// COSB (zero-normal-derivative box): v_ij = (2/N) sum_{p=0}^{N} w_p G[j][p] cos(p i pi / N)
+// with w_0 = w_N = 1/2; lane l keeps the modes p = l + 64 e.
+template <class T, int E, bool COSB>
 __global__ void __launch_bounds__(256)
     k_nodes_extract(int N, int M, int MC, int nch, const int* __restrict__ cnode,
                     const int* __restrict__ ccount, const int* __restrict__ mkloc,
@@ -685,7 +901,8 @@ __global__ void __launch_bounds__(256)
                     const double* __restrict__ qpart, int nq, double* __restrict__ vp_out,
                     double* __restrict__ vm_out, double* __restrict__ dnp_out,
                     double* __restrict__ dnm_out, int side, double oa, double ob, double oq,
-                    const double* __restrict__ xop, double* __restrict__ yop, size_t gstride) {
+                    const double* __restrict__ xop, double* __restrict__ yop, size_t gstride,
+                    const double* __restrict__ amk) {
   extern __shared__ double nval[];  // 6 * MC node values
   {  // density blockIdx.y of a batch
     const size_t bd = blockIdx.y;
@@ -755,19 +972,31 @@ __global__ void __launch_bounds__(256)
       if (key >= 0 && j != curj) {  // wave-uniform branch
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          const int pp = 1 + lane + 64 * e;
-          gv[e] = (pp <= n) ? G[grp_index(pp, j - jlo, nbr)] : T(0);
+          if constexpr (COSB) {
+            const int pp = lane + 64 * e;
+            const T wgt = (pp == 0 || pp == N) ? T(0.5) : T(1);
+            gv[e] = (pp <= N) ? wgt * G[grp_index(pp + 1, j - jlo, nbr)] : T(0);
+          } else {
+            const int pp = 1 + lane + 64 * e;
+            gv[e] = (pp <= n) ? G[grp_index(pp, j - jlo, nbr)] : T(0);
+          }
         }
         curj = j;
       }
       T sacc = T(0);
       if (key >= 0) {
         T a, c, sb, cb;
-        st2.get(((1 + lane) * i) & mask, a, c);
+        st2.get((((COSB ? 0 : 1) + lane) * i) & mask, a, c);
         st2.get((64 * i) & mask, sb, cb);
         // three-term recurrence in steps of 64 i pi / N (rounding grows at most E-fold)
         const T c2 = cb + cb;
-        T am = a * cb - c * sb;
+        T am;
+        if constexpr (COSB) {
+          am = c * cb + a * sb;  // cos((p - 64) x)
+          a = c;
+        } else {
+          am = a * cb - c * sb;
+        }
         sacc += gv[0] * a;
 #pragma unroll
         for (int e = 1; e < E; ++e) {
@@ -836,30 +1065,36 @@ __global__ void __launch_bounds__(256)
   if (dnm_out) dnm_out[k] = dnm;
   if (yop) {
     const double tr = (side == KFBI_PLUS) ? vp : (side == KFBI_MINUS ? vm : 0.5 * (vp + vm));
-    yop[k] = oa * xop[k] + ob * tr + oq * qs;
+    yop[k] = (amk ? amk[k] : oa) * xop[k] + ob * tr + oq * qs;
   }
 }
 
 // -------------------------------------------------------------------- full-grid evaluation
-// grid[j][i] = (2/N) sum_p G[j-1][p-1] sin(p i pi / N), 64x64 output tiles, 4x4 per thread.
-template <class T>
+// grid[j][i] = (2/N) sum_p G[j-1][p-1] sin(p i pi / N) on the interior, 64x64 output tiles,
+// 4x4 per thread.  COSB: grid[j][i] = (2/N) sum_{p=0}^{N} w_p G[j][p] cos(p i pi / N) on all
+// nodes (w_0 = w_N = 1/2).
+template <class T, bool COSB>
 __global__ void __launch_bounds__(256)
     k_fullgrid(int N, const T* __restrict__ G, int ldG, const T* __restrict__ sinT,
                double* __restrict__ grid) {
   __shared__ T As[16][65];
   __shared__ T Bs[16][65];
-  const int n = N - 1;
+  const int n = COSB ? N + 1 : N - 1;  // modes and output rows/columns
+  const int off = COSB ? 0 : 1;       // index of the first row/column/mode
   const int mask = 2 * N - 1;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;  // 0-based interior indices
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   T acc[4][4] = {};
   for (int k0 = 0; k0 < n; k0 += 16) {
     for (int t = threadIdx.x; t < 16 * 64; t += 256) {
       const int kk = t & 15, rr = t >> 4;
       const int jr = j0 + rr, kp = k0 + kk;
-      As[kk][rr] = (jr < n && kp < n) ? G[grp_index(kp + 1, jr, ldG)] : T(0);
+      T a = (jr < n && kp < n) ? G[grp_index(kp + 1, jr, ldG)] : T(0);
+      if (COSB && (kp == 0 || kp == N)) a *= T(0.5);
+      As[kk][rr] = a;
       const int ic = i0 + rr;
-      Bs[kk][rr] = (ic < n && kp < n) ? sinT[((kp + 1) * (ic + 1)) & mask] : T(0);
+      const int arg = (kp + off) * (ic + off) + (COSB ? N / 2 : 0);  // cos x = sin(x + pi/2)
+      Bs[kk][rr] = (ic < n && kp < n) ? sinT[arg & mask] : T(0);
     }
     __syncthreads();
 #pragma unroll
@@ -884,7 +1119,7 @@ __global__ void __launch_bounds__(256)
     for (int q = 0; q < 4; ++q) {
       const int jr = j0 + ty * 4 + r, ic = i0 + tx * 4 + q;
       if (jr < n && ic < n)
-        grid[static_cast<size_t>(jr + 1) * (N + 1) + (ic + 1)] =
+        grid[static_cast<size_t>(jr + off) * (N + 1) + (ic + off)] =
             sc * static_cast<double>(acc[r][q]);
     }
 }
@@ -931,7 +1166,7 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   const size_t tstride = 4 * static_cast<size_t>((n + 3) / 4) * (P + 1);
   const size_t gstride = static_cast<size_t>(n) * N;
   if (P > 0 && (stages & 2))
-    hipLaunchKernelGGL((k_rowdst<T, PT>), dim3(P, B), dim3(256), 0, s, N, P, c->pdesc.as<int4>(),
+    hipLaunchKernelGGL((k_rowdst<T, PT, false>), dim3(P, B), dim3(256), 0, s, N, P, c->pdesc.as<int4>(),
                        c->armr.as<double>(), c->armk.as<int>() + c->arm_cap, sinT, Tg, tstride);
   if (ev) hipEventRecord(ev[2], s);
   const int ngrp = nblk(n, kColsPerBlock);
@@ -945,8 +1180,8 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   if (ev) hipEventRecord(ev[3], s);
   const int nbr = jhi - jlo + 1;
   if (full) {  // single density only
-    hipLaunchKernelGGL((k_fullgrid<T>), dim3(nblk(n, 64), nblk(n, 64)), dim3(256), 0, s, N, G,
-                       nbr, sinT, grid);
+    hipLaunchKernelGGL((k_fullgrid<T, false>), dim3(nblk(n, 64), nblk(n, 64)), dim3(256), 0, s, N,
+                       G, nbr, sinT, grid);
     hipLaunchKernelGGL((k_grid_ring<T>), dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, ring, grid);
   }
   const int MC = c->mk_chunk;
@@ -954,13 +1189,83 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   const int side = op ? op->side : 0;
   const double oa = op ? op->a : 0.0, ob = op ? op->b : 0.0, oq = op ? op->q : 0.0;
   if (stages & 8)
-    hipLaunchKernelGGL((k_nodes_extract<T, E>), dim3(8 * nblk(nch, 8), B), dim3(256),
+    hipLaunchKernelGGL((k_nodes_extract<T, E, false>), dim3(8 * nblk(nch, 8), B), dim3(256),
                        sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(),
                        c->ccount.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G,
                        c->mq.as<double>(), c->ext.as<double>(), c->qpart.as<double>(),
                        c->n_mk_blocks, out ? out->v_plus : nullptr,
                        out ? out->v_minus : nullptr, out ? out->dn_plus : nullptr,
-                       out ? out->dn_minus : nullptr, side, oa, ob, oq, xop, yop, gstride);
+                       out ? out->dn_minus : nullptr, side, oa, ob, oq, xop, yop, gstride,
+                       op ? op->a_marker : nullptr);
+}
+
+// Grid stages of the zero-normal-derivative box: cosine row transform of the arm parts
+// (when `parts`), the mirrored-ghost column solve with optional dense right-hand sides
+// ca Fa + cb Fb (column-group layout, all N+1 rows), rows jlo..jhi of G, then the node
+// evaluation and extraction with the marker quantities mqv.
+struct NeuRhs {
+  const void* Fa = nullptr;
+  const void* Fb = nullptr;
+  double ca = 0.0, cb = 0.0;
+  bool parts = true;
+};
+
+template <class T, int E>
+static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, int jhi, T* Tg,
+                                   T* G, bool full, double* grid, hipEvent_t* ev,
+                                   const kfbi_out* out, const kfbi_bie* op, const double* xop,
+                                   double* yop, int stages, const NeuRhs& rr,
+                                   const double* mqv) {
+  const int N = c->N, M = c->M, nm = N + 1;
+  const int P = rr.parts ? c->st.n_parts : 0;
+  hipStream_t s = c->stream;
+  constexpr int PT = (64 * E + 255) / 256;
+  const int ngm = nblk(nm, 4);
+  const size_t tstride = 4 * static_cast<size_t>(ngm) * (c->st.n_parts + 1);
+  const size_t gstride = 4 * static_cast<size_t>(ngm) * nm;
+  if (P > 0 && (stages & 2))
+    hipLaunchKernelGGL((k_rowdst<T, PT, true>), dim3(P, B), dim3(256), 0, s, N, P,
+                       c->pdesc.as<int4>(), c->armr.as<double>(),
+                       c->armk.as<int>() + c->arm_cap, sinT, Tg, tstride);
+  if (ev) hipEventRecord(ev[2], s);
+  const int nb = ((ngm + 7) / 8) * 8;
+  const size_t lds_dyn = sizeof(T) * 4 * static_cast<size_t>(P > 0 ? P : 1);
+  allow_dyn_lds(k_colsolve_neu<T, E>, lds_dyn);
+  if (stages & 4)
+    hipLaunchKernelGGL((k_colsolve_neu<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P,
+                       Tg, c->rowpart.as<int>(), static_cast<const T*>(rr.Fa),
+                       static_cast<const T*>(rr.Fb), rr.ca, rr.cb, c->colc.as<double>(),
+                       c->lanef.as<double>(), jlo, jhi, G, nb, tstride, gstride);
+  if (ev) hipEventRecord(ev[3], s);
+  const int nbr = jhi - jlo + 1;
+  if (full)  // single density, all rows
+    hipLaunchKernelGGL((k_fullgrid<T, true>), dim3(nblk(nm, 64), nblk(nm, 64)), dim3(256), 0, s,
+                       N, G, nbr, sinT, grid);
+  const int MC = c->mk_chunk;
+  const int nch = nblk(M, MC);
+  const int side = op ? op->side : 0;
+  const double oa = op ? op->a : 0.0, ob = op ? op->b : 0.0, oq = op ? op->q : 0.0;
+  if (stages & 8)
+    hipLaunchKernelGGL((k_nodes_extract<T, E, true>), dim3(8 * nblk(nch, 8), B), dim3(256),
+                       sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(),
+                       c->ccount.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G, mqv,
+                       c->ext.as<double>(), c->qpart.as<double>(), c->n_mk_blocks,
+                       out ? out->v_plus : nullptr, out ? out->v_minus : nullptr,
+                       out ? out->dn_plus : nullptr, out ? out->dn_minus : nullptr, side, oa, ob,
+                       oq, xop, yop, gstride, op ? op->a_marker : nullptr);
+}
+
+// Dispatch on E = ceil((N+1)/64) for N = 64 .. 2048.
+template <class T, class F>
+static void neu_dispatch(int N, F&& f) {
+  switch ((N + 1 + 63) / 64) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 17: f(std::integral_constant<int, 17>{}); break;
+    default: f(std::integral_constant<int, 33>{}); break;
+  }
 }
 
 // FP32 copies of user box values for a batch: src [B][4(N+1)] -> dst with stride dstride.
@@ -1026,9 +1331,25 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
     }
   }
   if (ev) hipEventRecord(ev[1], s);
+  double* grid = full ? out->grid : nullptr;
+  if (c->box_bc == KFBI_BOX_NEUMANN) {
+    const int jlo = full ? 0 : c->st.row_lo;
+    const int jhi = full ? N : c->st.row_hi;
+    const NeuRhs rr;
+    neu_dispatch<T>(N, [&](auto EC) {
+      launch_grid_stages_neu<T, decltype(EC)::value>(c, B, sinT, jlo, jhi, Tg, G, full, grid, ev,
+                                                     out, op, xop, yop, stages, rr,
+                                                     c->mq.as<double>());
+    });
+    if (ev) hipEventRecord(ev[4], s);
+    KFBI_HIP(hipGetLastError());
+    c->last_layer = layer;
+    c->last_precision = sizeof(T) == 8 ? KFBI_FP64 : KFBI_FP32;
+    c->last_batch = B;
+    return KFBI_OK;
+  }
   const int jlo = full ? 1 : c->st.row_lo;
   const int jhi = full ? N - 1 : c->st.row_hi;
-  double* grid = full ? out->grid : nullptr;
   const int E = (N - 1 + 63) / 64;
   switch (E <= 1 ? 1 : E <= 2 ? 2 : E <= 4 ? 4 : E <= 8 ? 8 : E <= 16 ? 16 : 32) {
 #define KFBI_CASE(EE)                                                                         \
@@ -1072,6 +1393,15 @@ int prof_flush(kfbi_ctx* c) {
 
 int colconst_setup(kfbi_ctx* c) {
   const int N = c->N, n = N - 1;
+  if (c->box_bc == KFBI_BOX_NEUMANN) {
+    const int nm = N + 1, E = (nm + 63) / 64;
+    KFBI_TRY(c->colc.ensure(sizeof(double) * 4 * nm));
+    KFBI_TRY(c->lanef.ensure(sizeof(double) * 2 * 64 * nm));
+    hipLaunchKernelGGL(k_colconst_neu, dim3(nblk(64 * nm, 256)), dim3(256), 0, c->stream, N,
+                       c->h * c->h * c->c2, E, c->colc.as<double>(), c->lanef.as<double>());
+    KFBI_HIP(hipGetLastError());
+    return KFBI_OK;
+  }
   const int E0 = (n + 63) / 64;
   const int E = E0 <= 1 ? 1 : E0 <= 2 ? 2 : E0 <= 4 ? 4 : E0 <= 8 ? 8 : E0 <= 16 ? 16 : 32;
   KFBI_TRY(c->colc.ensure(sizeof(double) * 3 * n));

@@ -107,7 +107,7 @@ struct kfbi_ctx {
   // geometry buffers
   kfbi::DBuf X, geo, dvec, cnt, cross, hid, vid, vraw, lab, armcnt, rowsum, armrow, armpk, armcoef,
       intptr, need, nodeidx, nodei, rowptr, rows, mknode, ext, gstat, armc, armk,
-      colc, lanef, cnode, ccount, mkloc, tmat, pdesc, rowpart, ckoff, cklist, ckcoef, ckmk;
+      colc, lanef, cnode, ccount, mkloc, tmat, pdesc, rowpart, ckoff, cklist, ckcoef, ckmk, mqz;
   int arm_cap = 0;
   // per-apply buffers
   kfbi::DBuf mq, armr, qpart, ring, sinT, sinT32, gband, nodeval, tmpM;

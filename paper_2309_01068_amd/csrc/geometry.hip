@@ -901,7 +901,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
     KFBI_HIP(hipStreamSynchronize(s));
     const int P = hs->n_parts;
     KFBI_TRY(c->pdesc.ensure(sizeof(int4) * (P + 1)));
-    const int ng = (N - 1 + 3) / 4;
+    const int ng = (N + 1 + 3) / 4;  // mode groups (cosine layout; the sine one needs fewer)
     KFBI_TRY(c->tmat.ensure(sizeof(double) * 4 * static_cast<size_t>(ng) * (P + 1) *
                             c->max_batch));
     hipLaunchKernelGGL(k_part_fill, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart,

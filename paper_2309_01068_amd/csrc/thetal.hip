@@ -827,7 +827,7 @@ int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
   auto t1 = std::chrono::steady_clock::now();
   const double* guess = x0 ? x0 : th->phi.as<double>();
   KFBI_HIP(hipMemcpyAsync(th->phiw.p, guess, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
-  const kfbi_bie op{KFBI_DOUBLE, KFBI_MINUS, 0.0, 1.0, 1.0};
+  const kfbi_bie op{KFBI_DOUBLE, KFBI_MINUS, 0.0, 1.0, 1.0, nullptr};
   kfbi_gmres_stats gs{};
   st = kfbi_gmres_solve(th->kc, &op, th->rhs.as<double>(), th->phiw.as<double>(), &p.gmres, &gs);
   if (st != KFBI_OK) return st;

@@ -18,7 +18,7 @@ LIBPATH = os.path.join(HERE, "libkfbi.so")
 OK, E_INVALID, E_GEOMETRY, E_NOCONV, E_HIP, E_NOMEM, E_NONFINITE, E_STATE = range(8)
 SINGLE, DOUBLE = 0, 1
 PLUS, MINUS, AVG = 0, 1, 2
-BOX_ZERO, BOX_USER, BOX_FREESPACE = 0, 1, 2
+BOX_ZERO, BOX_USER, BOX_FREESPACE, BOX_NEUMANN = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 
 EXPORTS = [
@@ -60,7 +60,7 @@ class Out(C.Structure):
 
 class Bie(C.Structure):
     _fields_ = [("layer", C.c_int), ("side", C.c_int), ("a", C.c_double), ("b", C.c_double),
-                ("q", C.c_double)]
+                ("q", C.c_double), ("a_marker", C.c_void_p)]
 
 
 class GmresOpts(C.Structure):
@@ -242,9 +242,16 @@ class Context:
                                          C.byref(o)))
         return res
 
+    @staticmethod
+    def _bie(layer, side, a, b, q):
+        """a: a number, or a float64 device tensor of M per-marker values."""
+        if torch.is_tensor(a):
+            return Bie(layer, side, 0.0, b, q, _ptr(a))
+        return Bie(layer, side, a, b, q, None)
+
     def operator(self, x, layer, side, a, b, q, precision=FP64, y=None):
         y = torch.empty_like(x) if y is None else y
-        op = Bie(layer, side, a, b, q)
+        op = self._bie(layer, side, a, b, q)
         _check(self.lib.kfbi_operator(self.h, C.byref(op), precision, _ptr(x), _ptr(y)))
         return y
 
@@ -266,7 +273,7 @@ class Context:
 
     def gmres(self, rhs, x, layer, side, a, b, q, tol=1e-10, restart=50, maxit=1000,
               precision=FP64, inner_tol=1e-5, raise_noconv=True):
-        op = Bie(layer, side, a, b, q)
+        op = self._bie(layer, side, a, b, q)
         opts = GmresOpts(tol, restart, maxit, precision, inner_tol)
         st = GmresStats()
         code = self.lib.kfbi_gmres_solve(self.h, C.byref(op), _ptr(rhs), _ptr(x), C.byref(opts),

@@ -1,0 +1,141 @@
+"""GPU apply with the zero-normal-derivative box (KFBI_BOX_NEUMANN, the Stefan problem's
+box Green's function) against the CPU oracle, element by element.
+
+Bars as for the Dirichlet box: FP64 relative l2 <= 1e-10 per trace (and on the full
+grid), FP32 grid stages <= 5e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry as G
+from oracle import gmres as OG
+from oracle import kfbi as K
+from paper_2309_01068_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-10, 5e-5
+KEYS = ("v_plus", "v_minus", "dn_plus", "dn_minus")
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def ctx_for(box, c2, M, **kw):
+    from paper_2309_01068_amd import kfbi
+    return kfbi.Context(box.x0, box.y0, box.side, box.N, c2, kfbi.BOX_NEUMANN,
+                        max_markers=max(M, 64), **kw)
+
+
+CASES = [
+    ("star512_256", W.star(512), W.box(-1, 1, 256), 1000.0),
+    ("ellipse256_128", W.ellipse(256), W.box(-1, 1, 128), 40.0),
+    ("hs3_1024_512", W.hs3(1024), W.box(-2, 2, 512), 2000.0),
+    ("circle_64", W.circle(96, 0.45), W.box(-1, 1, 64), 9.0),
+]
+
+
+@pytest.mark.parametrize("name,X,box,c2", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("layer", [K.SINGLE, K.DOUBLE])
+def test_neumann_apply_parity_fp64(name, X, box, c2, layer):
+    print(f"[case] neumann {name} layer={layer}", flush=True)
+    M = X.shape[1]
+    dens = W.fourier_density(M, seed=4)
+    g = G.build_geometry(X, box)
+    ref = K.apply(g, layer, dens, c2, K.BOX_NEUMANN)
+    ctx = ctx_for(box, c2, M)
+    ctx.set_interface(dev(X))
+    out = ctx.apply(layer, dev(dens), grid=True)
+    torch.cuda.synchronize()
+    for k in KEYS:
+        e = rel(out[k].cpu().numpy(), getattr(ref, k))
+        print(f"  {k}: rel {e:.3e}")
+        assert e <= TOL64, (k, e)
+    e = rel(out["grid"].cpu().numpy(), ref.grid)
+    print(f"  grid: rel {e:.3e}")
+    assert e <= TOL64
+    # trace-only apply (band rows) after the full-grid one
+    out2 = ctx.apply(layer, dev(dens))
+    for k in KEYS:
+        assert rel(out2[k].cpu().numpy(), getattr(ref, k)) <= TOL64
+
+
+@pytest.mark.parametrize("name,X,box,c2", CASES[:2], ids=[c[0] for c in CASES[:2]])
+def test_neumann_apply_parity_fp32(name, X, box, c2):
+    M = X.shape[1]
+    dens = W.fourier_density(M, seed=5)
+    g = G.build_geometry(X, box)
+    ctx = ctx_for(box, c2, M)
+    ctx.set_interface(dev(X))
+    for layer in (K.SINGLE, K.DOUBLE):
+        ref = K.apply(g, layer, dens, c2, K.BOX_NEUMANN)
+        out = ctx.apply(layer, dev(dens), precision=1)
+        for k in ("v_plus", "v_minus"):
+            e = rel(out[k].cpu().numpy(), getattr(ref, k))
+            print(f"  fp32 {name} layer={layer} {k}: rel {e:.3e}")
+            assert e <= TOL32, (k, e)
+
+
+def test_neumann_full_size_star():
+    """The star workload (2048 markers, 1024^2) with the mirrored-ghost box, c^2 = 2000."""
+    box = W.box(-1, 1, 1024)
+    X = W.star(2048)
+    dens = W.fourier_density(2048, seed=0)
+    g = G.build_geometry(X, box)
+    ctx = ctx_for(box, 2000.0, 2048)
+    ctx.set_interface(dev(X))
+    for layer in (K.SINGLE, K.DOUBLE):
+        print(f"[case] neumann full size layer={layer}", flush=True)
+        ref = K.apply(g, layer, dens, 2000.0, K.BOX_NEUMANN)
+        out = ctx.apply(layer, dev(dens))
+        for k in KEYS:
+            assert rel(out[k].cpu().numpy(), getattr(ref, k)) <= TOL64, k
+
+
+def test_gibbs_thomson_gmres_with_per_marker_coefficient():
+    """eq. bie-GT: eps_V(x) psi - S psi = g with an anisotropic eps_V per marker."""
+    box = W.box(-1, 1, 128)
+    X = W.ellipse(128, 0.4, 0.3)
+    M = 128
+    c2 = 1000.0
+    g = G.build_geometry(X, box)
+    ang = np.arctan2(X[1], X[0])
+    epsV = 2e-3 * (1 + 0.5 * np.cos(4 * ang))
+    rhs = 0.5 + 0.1 * np.cos(2 * ang)
+    A = lambda x: K.operator(g, x, K.SINGLE, K.AVG, epsV, -1.0, 0.0, c2, K.BOX_NEUMANN)
+    ref, st = OG.gmres(A, rhs, np.zeros(M), 1e-12, 50, 500)
+    ctx = ctx_for(box, c2, M)
+    ctx.set_interface(dev(X))
+    a = dev(epsV)
+    y = ctx.operator(dev(ref), K.SINGLE, K.AVG, a, -1.0, 0.0)
+    assert rel(y.cpu().numpy(), A(ref)) <= TOL64
+    x = torch.zeros(M, dtype=torch.float64, device="cuda")
+    x, gs = ctx.gmres(dev(rhs), x, K.SINGLE, K.AVG, a, -1.0, 0.0, tol=1e-12)
+    assert gs["relres"] <= 1e-12
+    assert rel(x.cpu().numpy(), ref) <= 1e-8
+
+
+def test_neumann_batch_matches_single_applies():
+    box = W.box(-1, 1, 128)
+    X = W.star(256)
+    ctx = ctx_for(box, 500.0, 256, max_batch=4)
+    ctx.set_interface(dev(X))
+    D = np.stack([W.fourier_density(256, seed=s) for s in range(3)])
+    out = ctx.apply_batch(K.DOUBLE, dev(D))
+    for b in range(3):
+        one = ctx.apply(K.DOUBLE, dev(D[b]))
+        for k in KEYS:
+            assert torch.equal(out[k][b], one[k]), (b, k)
+
+
+def test_neumann_needs_positive_c2():
+    from paper_2309_01068_amd import kfbi
+    with pytest.raises(kfbi.KfbiError) as e:
+        kfbi.Context(-1, -1, 2, 128, 0.0, kfbi.BOX_NEUMANN)
+    assert e.value.code == kfbi.E_INVALID
