@@ -1376,6 +1376,128 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
   return KFBI_OK;
 }
 
+// ------------------------------------------------- zero-normal-derivative box: full fields
+// Forward cosine transform of grid rows into the column-group layout,
+//   Ghat[j][p] = sum_{i=0}^{N} w_i grid[j][i] cos(p i pi / N),  w_0 = w_N = 1/2,
+// as a tiled product with the cosine matrix (64x64 output tiles, 4x4 per thread).
+__global__ void __launch_bounds__(256)
+    k_rows_dct(int N, const double* __restrict__ grid, const double* __restrict__ sinT,
+               double* __restrict__ G) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int nm = N + 1;
+  const int mask = 2 * N - 1;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int p0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < nm; k0 += 16) {
+    for (int t = threadIdx.x; t < 16 * 64; t += 256) {
+      const int kk = t & 15, rr = t >> 4;
+      const int jr = j0 + rr, i = k0 + kk;
+      double a = (jr < nm && i < nm) ? grid[static_cast<size_t>(jr) * nm + i] : 0.0;
+      if (i == 0 || i == N) a *= 0.5;
+      As[kk][rr] = a;
+      const int pc = p0 + rr;
+      Bs[kk][rr] = (pc < nm && i < nm) ? sinT[(i * pc + N / 2) & mask] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[kk][ty * 4 + q];
+        bv[q] = Bs[kk][tx * 4 + q];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] += a[r] * bv[q];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jr = j0 + ty * 4 + r, pc = p0 + tx * 4 + q;
+      if (jr < nm && pc < nm) G[grp_index(pc + 1, jr, nm)] = acc[r][q];
+    }
+}
+
+// Full-field operations of the zero-normal-derivative box (FP64, one density).  A field
+// "Ghat" holds, for every row j = 0..N, the cosine coefficients along x in the column-group
+// layout: element (j, p) at ((p / 4) (N + 1) + j) 4 + p % 4.
+int neu_dense_solve(kfbi_ctx* c, const double* Fa, const double* Fb, double ca, double cb,
+                    double* Gout) {
+  const int N = c->N;
+  NeuRhs rr;
+  rr.Fa = Fa;
+  rr.Fb = Fb;
+  rr.ca = ca;
+  rr.cb = cb;
+  rr.parts = false;
+  const double* sinT = c->sinT.as<double>();
+  neu_dispatch<double>(N, [&](auto EC) {
+    launch_grid_stages_neu<double, decltype(EC)::value>(
+        c, 1, sinT, 0, N, c->tmat.as<double>(), Gout, false, nullptr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, 4, rr, c->mq.as<double>());
+  });
+  KFBI_HIP(hipGetLastError());
+  return KFBI_OK;
+}
+
+int neu_interp(kfbi_ctx* c, const double* Gfull, double* vout) {
+  const int N = c->N;
+  const NeuRhs rr;
+  const double* sinT = c->sinT.as<double>();
+  kfbi_out o{vout, nullptr, nullptr, nullptr, nullptr};
+  neu_dispatch<double>(N, [&](auto EC) {
+    launch_grid_stages_neu<double, decltype(EC)::value>(
+        c, 1, sinT, 0, N, c->tmat.as<double>(), const_cast<double*>(Gfull), false, nullptr,
+        nullptr, &o, nullptr, nullptr, nullptr, 8, rr, c->mqz.as<double>());
+  });
+  KFBI_HIP(hipGetLastError());
+  return KFBI_OK;
+}
+
+int neu_apply_full(kfbi_ctx* c, int layer, const double* dens, const double* Fa,
+                   const double* Fb, double ca, double cb, double* Gout) {
+  const int N = c->N;
+  KFBI_TRY(apply_t<double>(c, 1, layer, dens, nullptr, nullptr, nullptr, nullptr, nullptr, 1));
+  NeuRhs rr;
+  rr.Fa = Fa;
+  rr.Fb = Fb;
+  rr.ca = ca;
+  rr.cb = cb;
+  const double* sinT = c->sinT.as<double>();
+  neu_dispatch<double>(N, [&](auto EC) {
+    launch_grid_stages_neu<double, decltype(EC)::value>(
+        c, 1, sinT, 0, N, c->tmat.as<double>(), Gout, false, nullptr, nullptr, nullptr, nullptr,
+        nullptr, nullptr, 2 | 4, rr, c->mq.as<double>());
+  });
+  KFBI_HIP(hipGetLastError());
+  return KFBI_OK;
+}
+
+int neu_to_grid(kfbi_ctx* c, const double* Gfull, double* grid) {
+  const int N = c->N, nm = N + 1;
+  hipLaunchKernelGGL((k_fullgrid<double, true>), dim3(nblk(nm, 64), nblk(nm, 64)), dim3(256), 0,
+                     c->stream, N, Gfull, nm, c->sinT.as<double>(), grid);
+  KFBI_HIP(hipGetLastError());
+  return KFBI_OK;
+}
+
+int neu_from_grid(kfbi_ctx* c, const double* grid, double* Gfull) {
+  const int N = c->N, nm = N + 1;
+  // padding modes of the last group stay zero
+  KFBI_HIP(hipMemsetAsync(Gfull, 0, sizeof(double) * neu_field_size(N), c->stream));
+  hipLaunchKernelGGL(k_rows_dct, dim3(nblk(nm, 64), nblk(nm, 64)), dim3(256), 0, c->stream, N,
+                     grid, c->sinT.as<double>(), Gfull);
+  KFBI_HIP(hipGetLastError());
+  return KFBI_OK;
+}
+
 // Accumulate the elapsed times of the recorded applies (synchronises the stream).
 int prof_flush(kfbi_ctx* c) {
   KFBI_HIP(hipStreamSynchronize(c->stream));

@@ -140,6 +140,16 @@ struct kfbi_ctx {
 namespace kfbi {
 // stage entry points (implemented in the .hip files)
 int geometry_setup(kfbi_ctx* c, int M, const double* xy);
+// Zero-normal-derivative box, full fields (FP64): Ghat arrays of neu_field_size(N) doubles.
+inline size_t neu_field_size(int N) { return static_cast<size_t>(N + 4) * (N + 1); }
+int neu_dense_solve(kfbi_ctx* c, const double* Fa, const double* Fb, double ca, double cb,
+                    double* Gout);
+int neu_interp(kfbi_ctx* c, const double* Gfull, double* vout);
+int neu_apply_full(kfbi_ctx* c, int layer, const double* dens, const double* Fa,
+                   const double* Fb, double ca, double cb, double* Gout);
+int neu_to_grid(kfbi_ctx* c, const double* Gfull, double* grid);
+int neu_from_grid(kfbi_ctx* c, const double* grid, double* Gfull);
+
 int apply_impl(kfbi_ctx* c, int layer, int precision, const double* dens, const double* ring_user,
                const kfbi_out* out, const kfbi_bie* op, const double* x_for_op, double* y_op,
                int batch = 1);

@@ -78,6 +78,21 @@ struct TLShared {
 };
 inline size_t tl_lds_bytes(int M) { return sizeof(double) * (5 * static_cast<size_t>(M) + 32); }
 
+// Problem of the step: Hele-Shaw (stefan = 0: right-hand side -sigma kappa + J ln|x|, U from
+// the pressure) or Stefan (right-hand side -eps_C kappa, eps_V per marker, U = psi); pw = 3
+// for the L_2 term lambda (2pi/L)^3 H[theta_aaa], 2 for L_1 = lambda (2pi/L)^2 theta_aa.
+struct Aniso {
+  double e0, e1, e2, m, p0;
+  __device__ double at(double phi) const {
+    return e0 * (1.0 + e1 * cos(m * (phi - p0)) + e2 * cos(2.0 * m * (phi - p0)));
+  }
+};
+struct TLMode {
+  int stefan;
+  int pw;
+  Aniso ec, ev;
+};
+
 // ---------------------------------------------------------------------------- pre-step
 // Reconstruction (Sec. 5.1): theta = alpha + eta, X = Xbar + (L/2pi) A[exp(i theta)] with
 // the mean-free antiderivative A; eta_a and H[eta_aaa] (Sec. 5.2.1); curvature
@@ -86,7 +101,8 @@ inline size_t tl_lds_bytes(int M) { return sizeof(double) * (5 * static_cast<siz
 __global__ void __launch_bounds__(kTLThreads)
     k_tl_pre(int M, double sigma, double J, const double* __restrict__ tw,
              const double* __restrict__ eta, double* __restrict__ scal, double* __restrict__ X,
-             double* __restrict__ rhs, double* __restrict__ aux, double* __restrict__ etahat) {
+             double* __restrict__ rhs, double* __restrict__ aux, double* __restrict__ etahat,
+             TLMode md, double* __restrict__ amk) {
   extern __shared__ double lds[];
   TLShared sh;
   sh.setup(lds, M, tw);
@@ -166,7 +182,8 @@ __global__ void __launch_bounds__(kTLThreads)
       etahat[2 * q] = er;
       etahat[2 * q + 1] = ei;
       const double k = wavenum(q, M);
-      const double k3 = fabs(k) * k * k;
+      // H[eta_aaa] (multiplier -|k|^3) or eta_aa (multiplier -k^2)
+      const double k3 = md.pw == 2 ? k * k : fabs(k) * k * k;
       sh.yr[q] = -k * ei + k3 * ei;
       sh.yi[q] = k * er - k3 * er;
     }
@@ -185,7 +202,14 @@ __global__ void __launch_bounds__(kTLThreads)
       sincos(kTwoPi * j * invM + eta[j], &s, &c);
       X[j] = xs[u];
       X[M + j] = ys[u];
-      rhs[j] = -sigma * kappa + J * 0.5 * log(r2);
+      if (md.stefan) {
+        // angle of the outward normal n = (sin theta, -cos theta): theta - pi/2
+        const double nphi = kTwoPi * j * invM + eta[j] - 0.5 * M_PI;
+        rhs[j] = -md.ec.at(nphi) * kappa;
+        amk[j] = md.ev.at(nphi);
+      } else {
+        rhs[j] = -sigma * kappa + J * 0.5 * log(r2);
+      }
       aux[A_THA * M + j] = tha;
       aux[A_HETA * M + j] = heta;
       aux[A_NX * M + j] = s;
@@ -211,7 +235,7 @@ __global__ void __launch_bounds__(kTLThreads)
               double* __restrict__ aux, const double* __restrict__ dnp,
               const double* __restrict__ dnm, const double* __restrict__ etahat,
               double* __restrict__ nhat_prev, double* __restrict__ scal,
-              double* __restrict__ eta) {
+              double* __restrict__ eta, const double* __restrict__ psi, int pw) {
   extern __shared__ double lds[];
   TLShared sh;
   sh.setup(lds, M, tw);
@@ -231,7 +255,7 @@ __global__ void __launch_bounds__(kTLThreads)
       ny[u] = aux[A_NY * M + j];
       const double r2 = aux[A_R2 * M + j];
       const double x = X[j], y = X[M + j];
-      uu[u] = J * (x * nx[u] + y * ny[u]) / r2 - 0.5 * (dnp[j] + dnm[j]);
+      uu[u] = psi ? psi[j] : J * (x * nx[u] + y * ny[u]) / r2 - 0.5 * (dnp[j] + dnm[j]);
       aux[A_U * M + j] = uu[u];
       const double g = tha[u] * uu[u];
       sh.xr[j] = g;
@@ -271,7 +295,7 @@ __global__ void __launch_bounds__(kTLThreads)
       const double sx = -ny[u], sy = nx[u];
       qx += uu[u] * nx[u] + V * sx;
       qy += uu[u] * ny[u] + V * sy;
-      nv[u] = w * (tha[u] * V - Ua) - lam2 * w * w * w * he[u];
+      nv[u] = w * (tha[u] * V - Ua) - lam2 * (pw == 2 ? w * w : w * w * w) * he[u];
     }
   }
   __syncthreads();
@@ -301,16 +325,15 @@ __global__ void __launch_bounds__(kTLThreads)
     yn = xby + 0.5 * tau * (3.0 * qy - scal[S_QPY]);
   }
   const double Lp = scal[S_LPREV];
-  const double c1 = 0.5 * lam2 * tau * (1.0 / (L * L * L) + 1.0 / (Ln * Ln * Ln));
-  const double c2 = first ? 0.0
-                          : lam2 * tau * (0.5 / (Lp * Lp * Lp) + 1.0 / (L * L * L) +
-                                          0.5 / (Ln * Ln * Ln));
+  auto ipw = [pw](double x) { return pw == 2 ? 1.0 / (x * x) : 1.0 / (x * x * x); };
+  const double c1 = 0.5 * lam2 * tau * (ipw(L) + ipw(Ln));
+  const double c2 = first ? 0.0 : lam2 * tau * (0.5 * ipw(Lp) + ipw(L) + 0.5 * ipw(Ln));
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int q = tid + u * kTLThreads;
     if (q < M) {
       const double k = fabs(static_cast<double>(wavenum(q, M)));
-      const double tk3 = (kTwoPi * k) * (kTwoPi * k) * (kTwoPi * k);
+      const double tk3 = (kTwoPi * k) * (kTwoPi * k) * (pw == 2 ? 1.0 : kTwoPi * k);
       const double e1 = exp(-c1 * tk3);
       const double nr = sh.xr[q], ni = sh.xi[q];
       const double er = etahat[2 * q], ei = etahat[2 * q + 1];
@@ -592,6 +615,8 @@ __global__ void k_twiddles(int M, double* __restrict__ tw) {
   tw[2 * k + 1] = -s;
 }
 
+TLMode hs_mode() { return TLMode{0, 3, Aniso{}, Aniso{}}; }
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -607,7 +632,7 @@ int thetal_refresh(thetaL* th) {
   hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), th->stream, M,
                      th->prm.sigma, th->prm.J, th->tw.as<double>(), th->eta.as<double>(),
                      th->scal.as<double>(), th->X.as<double>(), th->rhs.as<double>(),
-                     th->aux.as<double>(), th->etahat.as<double>());
+                     th->aux.as<double>(), th->etahat.as<double>(), hs_mode(), nullptr);
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
 }
@@ -645,6 +670,60 @@ static void tl_free(thetaL* th) {
   th->kc = nullptr;
 }
 
+// Buffers, the KFBI context of the grid solves and the twiddles of an evolution object
+// whose parameters have been checked (on failure everything is released).
+static int tl_setup(thetaL* th, const thetaL_params* p, int M, int Mcap) {
+  th->prm = *p;
+  th->M = M;
+  th->Mcap = Mcap;
+  kfbi_grid g = p->grid;
+  g.max_markers = Mcap;
+  int st = kfbi_create(&g, &th->kc);
+  if (st != KFBI_OK) return st;
+  th->stream = static_cast<hipStream_t>(g.stream);
+  const int Mi = 4096;  // largest accepted input sampling of thetaL_init
+  const int C = Mcap;   // every per-marker buffer is sized for the refinement limit
+  if ((st = th->tw.ensure(sizeof(double) * C)) || (st = th->eta.ensure(sizeof(double) * C)) ||
+      (st = th->scal.ensure(sizeof(double) * S_COUNT)) ||
+      (st = th->X.ensure(sizeof(double) * 2 * C)) || (st = th->rhs.ensure(sizeof(double) * C)) ||
+      (st = th->aux.ensure(sizeof(double) * A_COUNT * C)) ||
+      (st = th->etahat.ensure(sizeof(double) * 2 * C)) ||
+      (st = th->nhat.ensure(sizeof(double) * 2 * C)) ||
+      (st = th->phi.ensure(sizeof(double) * C)) || (st = th->phi2.ensure(sizeof(double) * C)) ||
+      (st = th->phiw.ensure(sizeof(double) * C)) ||
+      (st = th->dnp.ensure(sizeof(double) * C)) || (st = th->dnm.ensure(sizeof(double) * C)) ||
+      (st = th->init.ensure(sizeof(double) * (2 * Mi + 4 * Mi + 2 * Mi + 2 * Mi + Mi + 3 * C)))) {
+    tl_free(th);
+    return st;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&th->hscal), sizeof(double) * S_COUNT,
+                    hipHostMallocDefault) != hipSuccess) {
+    th->hscal = nullptr;
+    tl_free(th);
+    set_error("hipHostMalloc failed");
+    return KFBI_E_NOMEM;
+  }
+  hipLaunchKernelGGL(k_twiddles, dim3((M / 2 + 255) / 256), dim3(256), 0, th->stream, M,
+                     th->tw.as<double>());
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(th->stream) != hipSuccess) {
+    tl_free(th);
+    set_error("thetaL: twiddle kernel failed");
+    return KFBI_E_HIP;
+  }
+  const size_t lds = tl_lds_bytes(Mcap);
+  if (lds > 64 * 1024) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_pre),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_post),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  }
+  const size_t rlds = refine_lds_bytes(Mcap / 2);
+  if (rlds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_refine),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rlds));
+  return KFBI_OK;
+}
+
 extern "C" {
 
 int thetaL_create(const thetaL_params* p, thetaL** out) {
@@ -676,60 +755,11 @@ int thetaL_create(const thetaL_params* p, thetaL** out) {
     set_error("out of host memory");
     return KFBI_E_NOMEM;
   }
-  th->prm = *p;
-  th->M = M;
-  th->Mcap = Mcap;
-  kfbi_grid g = p->grid;
-  g.max_markers = Mcap;
-  int st = kfbi_create(&g, &th->kc);
+  const int st = tl_setup(th, p, M, Mcap);
   if (st != KFBI_OK) {
     delete th;
     return st;
   }
-  th->stream = static_cast<hipStream_t>(g.stream);
-  const int Mi = 4096;  // largest accepted input sampling of thetaL_init
-  const int C = Mcap;   // every per-marker buffer is sized for the refinement limit
-  if ((st = th->tw.ensure(sizeof(double) * C)) || (st = th->eta.ensure(sizeof(double) * C)) ||
-      (st = th->scal.ensure(sizeof(double) * S_COUNT)) ||
-      (st = th->X.ensure(sizeof(double) * 2 * C)) || (st = th->rhs.ensure(sizeof(double) * C)) ||
-      (st = th->aux.ensure(sizeof(double) * A_COUNT * C)) ||
-      (st = th->etahat.ensure(sizeof(double) * 2 * C)) ||
-      (st = th->nhat.ensure(sizeof(double) * 2 * C)) ||
-      (st = th->phi.ensure(sizeof(double) * C)) || (st = th->phi2.ensure(sizeof(double) * C)) ||
-      (st = th->phiw.ensure(sizeof(double) * C)) ||
-      (st = th->dnp.ensure(sizeof(double) * C)) || (st = th->dnm.ensure(sizeof(double) * C)) ||
-      (st = th->init.ensure(sizeof(double) * (2 * Mi + 4 * Mi + 2 * Mi + 2 * Mi + Mi + 3 * C)))) {
-    tl_free(th);
-    delete th;
-    return st;
-  }
-  if (hipHostMalloc(reinterpret_cast<void**>(&th->hscal), sizeof(double) * S_COUNT,
-                    hipHostMallocDefault) != hipSuccess) {
-    th->hscal = nullptr;
-    tl_free(th);
-    delete th;
-    set_error("hipHostMalloc failed");
-    return KFBI_E_NOMEM;
-  }
-  hipLaunchKernelGGL(k_twiddles, dim3((M / 2 + 255) / 256), dim3(256), 0, th->stream, M,
-                     th->tw.as<double>());
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(th->stream) != hipSuccess) {
-    tl_free(th);
-    delete th;
-    set_error("thetaL: twiddle kernel failed");
-    return KFBI_E_HIP;
-  }
-  const size_t lds = tl_lds_bytes(Mcap);
-  if (lds > 64 * 1024) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_pre),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_post),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  }
-  const size_t rlds = refine_lds_bytes(Mcap / 2);
-  if (rlds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_refine),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rlds));
   *out = th;
   return KFBI_OK;
 }
@@ -793,7 +823,7 @@ int thetaL_markers(thetaL* th, double* xy) {
   hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), th->stream, M,
                      th->prm.sigma, th->prm.J, th->tw.as<double>(), th->eta.as<double>(),
                      th->scal.as<double>(), xy, th->rhs.as<double>(), th->aux.as<double>(),
-                     th->etahat.as<double>());
+                     th->etahat.as<double>(), hs_mode(), nullptr);
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
 }
@@ -818,7 +848,7 @@ int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
   hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), s, M, p.sigma, p.J,
                      th->tw.as<double>(), th->eta.as<double>(), th->scal.as<double>(),
                      th->X.as<double>(), th->rhs.as<double>(), th->aux.as<double>(),
-                     th->etahat.as<double>());
+                     th->etahat.as<double>(), hs_mode(), nullptr);
   KFBI_HIP(hipGetLastError());
   int st = kfbi_set_interface(th->kc, M, th->X.as<double>());
   if (st != KFBI_OK) return st;
@@ -844,7 +874,7 @@ int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
                      lam2, th->n == 0 ? 1 : 0, th->tw.as<double>(), th->X.as<double>(),
                      th->aux.as<double>(), th->dnp.as<double>(), th->dnm.as<double>(),
                      th->etahat.as<double>(), th->nhat.as<double>(), th->scal.as<double>(),
-                     th->eta.as<double>());
+                     th->eta.as<double>(), nullptr, 3);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(th->phi2.p, th->phi.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
   KFBI_HIP(hipMemcpyAsync(th->phi.p, th->phiw.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
@@ -962,6 +992,302 @@ int thetaL_set_state(thetaL* th, const thetaL_state* st) {
   th->n = st->n;
   th->have_phi = 1;
   th->ready = 1;
+  return KFBI_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ Stefan problem (stefan.h)
+#include "../../include/stefan.h"
+
+namespace kfbi {
+namespace {
+
+// seed field: 0 at nodes inside the interface (label 1), St outside
+__global__ void k_seed(int n, const int8_t* __restrict__ lab, double St, double* __restrict__ T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) T[t] = lab[t] ? 0.0 : St;
+}
+
+// y = a x + b y (n values)
+__global__ void k_axpby(int n, double a, const double* __restrict__ x, double b,
+                        double* __restrict__ y) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = a * x[t] + b * y[t];
+}
+
+Aniso to_aniso(const stefan_aniso& a) { return Aniso{a.e0, a.e1, a.e2, double(a.m), a.phi0}; }
+
+double aniso_host(const stefan_aniso& a, double phi) {
+  return a.e0 * (1.0 + a.e1 * std::cos(a.m * (phi - a.phi0)) +
+                 a.e2 * std::cos(2.0 * a.m * (phi - a.phi0)));
+}
+
+}  // namespace
+}  // namespace kfbi
+
+struct stefan {
+  stefan_params prm{};
+  thetaL tl;               // interface state; its KFBI context has the mirrored-ghost box
+  kfbi::DBuf That, Tprev, Tnew, T1, t1at, amk, neg, grid0;
+  kfbi::TLMode md{};
+  double lam = 0.0, c2 = 0.0;
+  int have_prev = 0;       // T^{n-1} exists (BDF2)
+};
+
+static void st_free(stefan* s) {
+  for (DBuf* b : {&s->That, &s->Tprev, &s->Tnew, &s->T1, &s->t1at, &s->amk, &s->neg, &s->grid0})
+    b->release();
+  tl_free(&s->tl);
+}
+
+extern "C" {
+
+int stefan_create(const stefan_params* p, stefan** out) {
+  if (!p || !out) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  *out = nullptr;
+  const int M = p->M;
+  if (M < 16 || M > kTLMaxM || (M & (M - 1))) {
+    set_error("stefan: M must be a power of two in [16, %d] (M=%d)", kTLMaxM, M);
+    return KFBI_E_INVALID;
+  }
+  if (!(p->tau > 0.0) || (p->ssd != 1 && p->ssd != 2) || !(p->eps_c.e0 >= 0.0) ||
+      !(p->eps_v.e0 >= 0.0) || (p->ssd == 1 && !(p->eps_v.e0 > 0.0))) {
+    set_error("stefan: need tau > 0, ssd 1 or 2, eps_C, eps_V >= 0 (eps_V > 0 with ssd 1)");
+    return KFBI_E_INVALID;
+  }
+  stefan* s = new (std::nothrow) stefan();
+  if (!s) {
+    set_error("out of host memory");
+    return KFBI_E_NOMEM;
+  }
+  s->prm = *p;
+  s->c2 = p->bdf2 ? 1.5 / p->tau : 1.0 / p->tau;
+  if (p->lambda > 0.0) {
+    s->lam = p->lambda;
+  } else {  // frozen-coefficient maxima over 4096 normal angles
+    double mx = 0.0;
+    for (int q = 0; q < 4096; ++q) {
+      const double phi = 2.0 * M_PI * q / 4096;
+      const double ec = aniso_host(p->eps_c, phi), ev = aniso_host(p->eps_v, phi);
+      mx = std::max(mx, p->ssd == 1 ? std::fabs(ec / ev) : std::fabs(2.0 * ec));
+    }
+    s->lam = mx;
+  }
+  s->md = TLMode{1, p->ssd == 1 ? 2 : 3, to_aniso(p->eps_c), to_aniso(p->eps_v)};
+  thetaL_params tp{};
+  tp.grid = kfbi_grid{p->x0, p->y0, p->side, p->N, s->c2, KFBI_BOX_NEUMANN, M, p->stream, 0};
+  tp.M = M;
+  tp.tau = p->tau;
+  tp.lambda2 = s->lam;
+  tp.gmres = p->gmres;
+  int st = tl_setup(&s->tl, &tp, M, M);
+  if (st != KFBI_OK) {
+    delete s;
+    return st;
+  }
+  const size_t nf = neu_field_size(p->N);
+  const size_t n1sq = static_cast<size_t>(p->N + 1) * (p->N + 1);
+  if ((st = s->That.ensure(sizeof(double) * nf)) || (st = s->Tprev.ensure(sizeof(double) * nf)) ||
+      (st = s->Tnew.ensure(sizeof(double) * nf)) || (st = s->T1.ensure(sizeof(double) * nf)) ||
+      (st = s->t1at.ensure(sizeof(double) * M)) || (st = s->amk.ensure(sizeof(double) * M)) ||
+      (st = s->neg.ensure(sizeof(double) * M)) || (st = s->grid0.ensure(sizeof(double) * n1sq))) {
+    st_free(s);
+    delete s;
+    return st;
+  }
+  *out = s;
+  return KFBI_OK;
+}
+
+int stefan_destroy(stefan* s) {
+  if (!s) return KFBI_OK;
+  (void)hipStreamSynchronize(s->tl.stream);
+  st_free(s);
+  delete s;
+  return KFBI_OK;
+}
+
+int stefan_init(stefan* s, int Mi, const double* xy, const double* T0, double St) {
+  if (!s) {
+    set_error("null stefan object");
+    return KFBI_E_INVALID;
+  }
+  thetaL* th = &s->tl;
+  KFBI_TRY(thetaL_init(th, Mi, xy));
+  hipStream_t hs = th->stream;
+  const int N = s->prm.N;
+  const int n1sq = (N + 1) * (N + 1);
+  if (!T0) {  // seed field from the labels of the resampled curve
+    hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(th->M), hs, th->M, 0.0,
+                       0.0, th->tw.as<double>(), th->eta.as<double>(), th->scal.as<double>(),
+                       th->X.as<double>(), th->rhs.as<double>(), th->aux.as<double>(),
+                       th->etahat.as<double>(), s->md, s->amk.as<double>());
+    KFBI_HIP(hipGetLastError());
+    KFBI_TRY(kfbi_set_interface(th->kc, th->M, th->X.as<double>()));
+    hipLaunchKernelGGL(k_seed, dim3((n1sq + 255) / 256), dim3(256), 0, hs, n1sq,
+                       th->kc->lab.as<int8_t>(), St, s->grid0.as<double>());
+    KFBI_HIP(hipGetLastError());
+    T0 = s->grid0.as<double>();
+  }
+  KFBI_TRY(neu_from_grid(th->kc, T0, s->That.as<double>()));
+  KFBI_HIP(hipStreamSynchronize(hs));
+  s->have_prev = 0;
+  return KFBI_OK;
+}
+
+int stefan_step(stefan* s, const double* x0, stefan_stats* stats) {
+  if (!s) {
+    set_error("null stefan object");
+    return KFBI_E_INVALID;
+  }
+  thetaL* th = &s->tl;
+  KFBI_TRY(tl_check(th, true));
+  const int M = th->M;
+  hipStream_t hs = th->stream;
+  const stefan_params& p = s->prm;
+  auto t0 = std::chrono::steady_clock::now();
+  hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), hs, M, 0.0, 0.0,
+                     th->tw.as<double>(), th->eta.as<double>(), th->scal.as<double>(),
+                     th->X.as<double>(), th->rhs.as<double>(), th->aux.as<double>(),
+                     th->etahat.as<double>(), s->md, s->amk.as<double>());
+  KFBI_HIP(hipGetLastError());
+  int st = kfbi_set_interface(th->kc, M, th->X.as<double>());
+  if (st != KFBI_OK) return st;
+  const double ms_geo = ms_since(t0);
+  // T1: the five-point problem with the time-discretisation right-hand side
+  auto t1 = std::chrono::steady_clock::now();
+  const double* Fa = s->That.as<double>();
+  const double* Fb = nullptr;
+  double ca = -1.0 / p.tau, cb = 0.0;
+  if (p.bdf2) {
+    Fb = s->have_prev ? s->Tprev.as<double>() : s->That.as<double>();
+    ca = -2.0 / p.tau;
+    cb = 0.5 / p.tau;
+  }
+  KFBI_TRY(neu_dense_solve(th->kc, Fa, Fb, ca, cb, s->T1.as<double>()));
+  KFBI_TRY(neu_interp(th->kc, s->T1.as<double>(), s->t1at.as<double>()));
+  hipLaunchKernelGGL(k_axpby, dim3((M + 255) / 256), dim3(256), 0, hs, M, -1.0,
+                     s->t1at.as<double>(), 1.0, th->rhs.as<double>());
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipStreamSynchronize(hs));
+  const double ms_t1 = ms_since(t1);
+  // eq. bie-GT
+  auto t2 = std::chrono::steady_clock::now();
+  const double* guess = x0 ? x0 : th->phi.as<double>();
+  KFBI_HIP(hipMemcpyAsync(th->phiw.p, guess, sizeof(double) * M, hipMemcpyDeviceToDevice, hs));
+  const kfbi_bie op{KFBI_SINGLE, KFBI_AVG, 0.0, -1.0, 0.0, s->amk.as<double>()};
+  kfbi_gmres_stats gs{};
+  st = kfbi_gmres_solve(th->kc, &op, th->rhs.as<double>(), th->phiw.as<double>(), &p.gmres, &gs);
+  if (st != KFBI_OK) return st;
+  const double ms_gm = ms_since(t2);
+  // T^{n+1} = T1 + T2, T2 = -S psi: one column solve of both right-hand sides; then theta-L
+  auto t3 = std::chrono::steady_clock::now();
+  hipLaunchKernelGGL(k_axpby, dim3((M + 255) / 256), dim3(256), 0, hs, M, -1.0,
+                     th->phiw.as<double>(), 0.0, s->neg.as<double>());
+  KFBI_TRY(neu_apply_full(th->kc, KFBI_SINGLE, s->neg.as<double>(), Fa, Fb, ca, cb,
+                          s->Tnew.as<double>()));
+  hipLaunchKernelGGL(k_tl_post, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), hs, M, 0.0, p.tau,
+                     s->lam, th->n == 0 ? 1 : 0, th->tw.as<double>(), th->X.as<double>(),
+                     th->aux.as<double>(), th->dnp.as<double>(), th->dnm.as<double>(),
+                     th->etahat.as<double>(), th->nhat.as<double>(), th->scal.as<double>(),
+                     th->eta.as<double>(), th->phiw.as<double>(), s->md.pw);
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipMemcpyAsync(th->phi2.p, th->phi.p, sizeof(double) * M, hipMemcpyDeviceToDevice, hs));
+  KFBI_HIP(hipMemcpyAsync(th->phi.p, th->phiw.p, sizeof(double) * M, hipMemcpyDeviceToDevice, hs));
+  KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, hs));
+  KFBI_HIP(hipStreamSynchronize(hs));
+  std::swap(s->Tprev, s->That);  // T^{n-1} <- T^n
+  std::swap(s->That, s->Tnew);   // T^n <- T^{n+1}
+  s->have_prev = 1;
+  const double ms_up = ms_since(t3);
+  const int step = th->n;
+  th->n += 1;
+  th->have_phi = 1;
+  if (stats) {
+    stats->step = step;
+    stats->t = th->hscal[S_T];
+    stats->iters = gs.iters;
+    stats->applies64 = gs.applies64;
+    stats->applies32 = gs.applies32;
+    stats->relres = gs.relres;
+    stats->area = th->hscal[S_AREA];
+    stats->length = th->hscal[S_LEN];
+    stats->ms_geometry = ms_geo;
+    stats->ms_temperature = ms_t1;
+    stats->ms_gmres = ms_gm;
+    stats->ms_update = ms_up;
+  }
+  if (th->hscal[S_BAD] != 0.0) {
+    set_error("stefan_step: the new state is not finite (step %d)", step);
+    return KFBI_E_NONFINITE;
+  }
+  return KFBI_OK;
+}
+
+int stefan_run(stefan* s, int nsteps, stefan_stats* stats) {
+  if (!s || nsteps < 0) {
+    set_error("null stefan object or nsteps < 0");
+    return KFBI_E_INVALID;
+  }
+  for (int i = 0; i < nsteps; ++i) KFBI_TRY(stefan_step(s, nullptr, stats ? stats + i : nullptr));
+  return KFBI_OK;
+}
+
+int stefan_temperature(stefan* s, double* grid) {
+  if (!s || !grid) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  KFBI_TRY(tl_check(&s->tl, true));
+  return neu_to_grid(s->tl.kc, s->That.as<double>(), grid);
+}
+
+int stefan_markers(stefan* s, double* xy) {
+  if (!s) {
+    set_error("null stefan object");
+    return KFBI_E_INVALID;
+  }
+  return thetaL_markers(&s->tl, xy);
+}
+
+int stefan_density(const stefan* s, double* psi) {
+  if (!s) {
+    set_error("null stefan object");
+    return KFBI_E_INVALID;
+  }
+  return thetaL_density(&s->tl, psi);
+}
+
+int stefan_interface(const stefan* s, double* eta, double* scal) {
+  if (!s || !eta || !scal) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  const thetaL* th = &s->tl;
+  KFBI_TRY(tl_check(th, true));
+  KFBI_HIP(hipMemcpyAsync(eta, th->eta.p, sizeof(double) * th->M, hipMemcpyDeviceToDevice,
+                          th->stream));
+  KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost,
+                          th->stream));
+  KFBI_HIP(hipStreamSynchronize(th->stream));
+  scal[0] = th->hscal[S_L];
+  scal[1] = th->hscal[S_XBX];
+  scal[2] = th->hscal[S_XBY];
+  scal[3] = th->hscal[S_T];
+  return KFBI_OK;
+}
+
+int stefan_constants(const stefan* s, double* lambda, double* c2) {
+  if (!s || !lambda || !c2) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  *lambda = s->lam;
+  *c2 = s->c2;
   return KFBI_OK;
 }
 

@@ -32,6 +32,9 @@ EXPORTS = [
     "kfbi_ws_set_weights", "kfbi_ws_predict", "kfbi_ws_record", "kfbi_ws_n_samples",
     "kfbi_ws_clear", "kfbi_ws_train", "kfbi_ws_eval", "kfbi_ws_forward", "kfbi_ws_backward",
     "kfbi_ws_target_scale",
+    "stefan_create", "stefan_destroy", "stefan_init", "stefan_step", "stefan_run",
+    "stefan_temperature", "stefan_markers", "stefan_density", "stefan_interface",
+    "stefan_constants",
 ]
 
 
@@ -99,6 +102,29 @@ class ThetaLState(C.Structure):
                 ("scal", C.c_double * 8), ("n", C.c_int), ("M", C.c_int)]
 
 
+class StefanAniso(C.Structure):
+    _fields_ = [("e0", C.c_double), ("e1", C.c_double), ("e2", C.c_double), ("m", C.c_int),
+                ("phi0", C.c_double)]
+
+
+class StefanParams(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("side", C.c_double), ("N", C.c_int),
+                ("M", C.c_int), ("tau", C.c_double), ("bdf2", C.c_int), ("ssd", C.c_int),
+                ("lambda_", C.c_double), ("eps_c", StefanAniso), ("eps_v", StefanAniso),
+                ("gmres", GmresOpts), ("stream", C.c_void_p)]
+
+
+class StefanStats(C.Structure):
+    _fields_ = [("step", C.c_int), ("t", C.c_double), ("iters", C.c_int), ("applies64", C.c_int),
+                ("applies32", C.c_int), ("relres", C.c_double), ("area", C.c_double),
+                ("length", C.c_double), ("ms_geometry", C.c_double),
+                ("ms_temperature", C.c_double), ("ms_gmres", C.c_double),
+                ("ms_update", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class WsCfg(C.Structure):
     _fields_ = [("M", C.c_int), ("max_batch", C.c_int), ("capacity", C.c_int),
                 ("L_ref", C.c_double), ("lr", C.c_float), ("beta1", C.c_float),
@@ -143,6 +169,16 @@ def load(path: str = LIBPATH):
     lib.thetaL_get_state.argtypes = [vp, C.POINTER(ThetaLState)]
     lib.thetaL_set_state.argtypes = [vp, C.POINTER(ThetaLState)]
     lib.thetaL_size.argtypes = [vp, C.POINTER(C.c_int)]
+    lib.stefan_create.argtypes = [C.POINTER(StefanParams), C.POINTER(vp)]
+    lib.stefan_destroy.argtypes = [vp]
+    lib.stefan_init.argtypes = [vp, C.c_int, vp, vp, C.c_double]
+    lib.stefan_step.argtypes = [vp, vp, C.POINTER(StefanStats)]
+    lib.stefan_run.argtypes = [vp, C.c_int, C.POINTER(StefanStats)]
+    lib.stefan_temperature.argtypes = [vp, vp]
+    lib.stefan_markers.argtypes = [vp, vp]
+    lib.stefan_density.argtypes = [vp, vp]
+    lib.stefan_interface.argtypes = [vp, vp, C.POINTER(C.c_double)]
+    lib.stefan_constants.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     ip, fp = C.POINTER(C.c_int), C.POINTER(C.c_float)
     lib.kfbi_ws_create.argtypes = [C.POINTER(WsCfg), C.POINTER(vp)]
     lib.kfbi_ws_destroy.argtypes = [vp]
@@ -360,6 +396,77 @@ class ThetaL:
         st.n = d["n"]
         st.M = d.get("M", d["eta"].numel())
         _check(self.lib.thetaL_set_state(self.h, C.byref(st)))
+
+
+class Stefan:
+    """Stefan problem (include/stefan.h) on the current torch stream.  eps_c, eps_v:
+    (e0, e1, e2, m, phi0) of eps(phi) = e0 (1 + e1 cos(m (phi - phi0)) + e2 cos(2 m (phi - phi0)))."""
+
+    def __init__(self, x0, y0, side, N, M, tau, eps_c, eps_v, bdf2=True, ssd=2, lam=0.0,
+                 tol=1e-10, restart=50, maxit=1000, precision=FP64, inner_tol=1e-5, stream=None):
+        self.lib = load()
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.stream = s
+        self.N, self.M = N, M
+        p = StefanParams(x0, y0, side, N, M, tau, 1 if bdf2 else 0, ssd, lam,
+                         StefanAniso(*eps_c), StefanAniso(*eps_v),
+                         GmresOpts(tol, restart, maxit, precision, inner_tol),
+                         C.c_void_p(s.cuda_stream))
+        h = C.c_void_p()
+        _check(self.lib.stefan_create(C.byref(p), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.stefan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, xy: torch.Tensor, T0: torch.Tensor | None = None, St: float = 0.0):
+        xy = xy.contiguous()
+        _check(self.lib.stefan_init(self.h, xy.shape[1], _ptr(xy),
+                                    None if T0 is None else _ptr(T0.contiguous()), St))
+
+    def step(self, x0=None) -> dict:
+        st = StefanStats()
+        _check(self.lib.stefan_step(self.h, _ptr(x0), C.byref(st)))
+        return st.as_dict()
+
+    def run(self, nsteps: int) -> list:
+        arr = (StefanStats * max(nsteps, 1))()
+        _check(self.lib.stefan_run(self.h, nsteps, arr))
+        return [arr[i].as_dict() for i in range(nsteps)]
+
+    def temperature(self) -> torch.Tensor:
+        g = torch.empty((self.N + 1, self.N + 1), dtype=torch.float64, device="cuda")
+        _check(self.lib.stefan_temperature(self.h, _ptr(g)))
+        return g
+
+    def markers(self) -> torch.Tensor:
+        xy = torch.empty((2, self.M), dtype=torch.float64, device="cuda")
+        _check(self.lib.stefan_markers(self.h, _ptr(xy)))
+        return xy
+
+    def density(self) -> torch.Tensor:
+        psi = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        _check(self.lib.stefan_density(self.h, _ptr(psi)))
+        return psi
+
+    def interface(self):
+        eta = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        sc = (C.c_double * 4)()
+        _check(self.lib.stefan_interface(self.h, _ptr(eta), sc))
+        return eta, list(sc)
+
+    def constants(self):
+        lam, c2 = C.c_double(), C.c_double()
+        _check(self.lib.stefan_constants(self.h, C.byref(lam), C.byref(c2)))
+        return lam.value, c2.value
 
 
 def _fptr(t):
