@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--ws-test-runs", type=int, default=4,
                     help="held-out evolutions for the learned warm start (8 = full set)")
     ap.add_argument("--ws-epochs", type=int, default=30)
+    ap.add_argument("--stefan-steps", type=int, default=60,
+                    help="Stefan steps timed (the dendrite workload runs 500)")
+    ap.add_argument("--only", default="",
+                    help="comma list of extra sections to run (extra, batched, interior_dirichlet, "
+                         "hele_shaw, warm_start, stefan); empty = all")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 10 times (the reference "
                          "kernel for scaling hardware byte counters) and exit")
@@ -221,11 +226,16 @@ def main():
             result["cpu_baseline"]["gpu_over_cpu"] = round(value / result["cpu_baseline"]["value"], 1)
 
     if not a.no_extra:
-        result["extra"] = extras(kf, W, torch, np, dev, dens, layer)
-        result["batched"] = batched(kf, W, torch, np, dev, a)
-        result["interior_dirichlet"] = interior_dirichlet(kf, W, torch, np, dev)
-        result["hele_shaw"] = hele_shaw(kf, W, torch, np, dev, a)
-        result["warm_start"] = warm_start(kf, W, torch, np, dev, a)
+        want = set(a.only.split(",")) if a.only else None
+        sections = [("extra", lambda: extras(kf, W, torch, np, dev, dens, layer)),
+                    ("batched", lambda: batched(kf, W, torch, np, dev, a)),
+                    ("interior_dirichlet", lambda: interior_dirichlet(kf, W, torch, np, dev)),
+                    ("hele_shaw", lambda: hele_shaw(kf, W, torch, np, dev, a)),
+                    ("warm_start", lambda: warm_start(kf, W, torch, np, dev, a)),
+                    ("stefan", lambda: stefan(kf, W, torch, np, dev, a))]
+        for name, fn in sections:
+            if want is None or name in want:
+                result[name] = fn()
     print(json.dumps(result), flush=True)
 
 
@@ -380,6 +390,52 @@ def hele_shaw(kf, W, torch, np, dev, a):
             "length_first_last": [recs[0]["length"], recs[-1]["length"]],
             "t_end": recs[-1]["t"]}
         th.close()
+    return out
+
+
+def stefan(kf, W, torch, np, dev, a):
+    """Stefan dendrite: seed circle of radius 0.1 in [-4,4]^2 with 2048^2 intervals, 128
+    markers (spacing 1.3 h), undercooling St = -0.5, backward Euler with tau = 5e-4
+    (c^2 = 1/tau), four-fold surface tension eps_C = 2e-3 (1 - 0.75 cos 4 phi) (anisotropy
+    strength 0.05 in the stiffness form 1 - 15 eps cos 4 phi), eps_V = 2e-3, third-order SSD;
+    GMRES to 1e-10 from the previous density, FP64 and FP32-inner.  Wall time per step and
+    its split, iterations, and the energy balance sum(T) h^2 - area over the run."""
+    N, M, tau, St = 2048, 128, 5e-4, -0.5
+    box = W.box(-4.0, 4.0, N)
+    eC = (2e-3, -0.75, 0.0, 4, 0.0)
+    eV = (2e-3, 0.0, 0.0, 4, 0.0)
+    w = np.ones(N + 1)
+    w[0] = w[-1] = 0.5
+    out = {"workload": f"stefan seed r=0.1 box [-4,4]^2 grid {N}^2 M={M} tau={tau} St={St} BE"}
+    for prec in (0, 1):
+        sf = kf.Stefan(box.x0, box.y0, box.side, N, M, tau, eC, eV, bdf2=False, ssd=2,
+                       precision=prec)
+        sf.init(torch.tensor(W.circle(M, 0.1), device=dev), None, St)
+
+        def energy():
+            Tg = sf.temperature()
+            xy = sf.markers().cpu().numpy()
+            e = float((torch.tensor(w[:, None] * w[None, :], device=dev) * Tg).sum()) * box.h ** 2
+            ar = 0.5 * float(np.sum(xy[0] * np.roll(xy[1], -1) - np.roll(xy[0], -1) * xy[1]))
+            return e - ar, ar
+        E0, A0 = energy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = sf.run(a.stefan_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        E1, A1 = energy()
+        n = len(recs)
+        out["f64" if prec == 0 else "f32ir"] = {
+            "steps": n, "ms_per_step": round(1e3 * el / n, 4),
+            "ms_split": {k: round(sum(r[k] for r in recs) / n, 4)
+                         for k in ("ms_geometry", "ms_temperature", "ms_gmres", "ms_update")},
+            "mean_iters": round(sum(r["iters"] for r in recs) / n, 3),
+            "max_relres": max(r["relres"] for r in recs),
+            "area_first_last": [recs[0]["area"], recs[-1]["area"]],
+            "energy_drift_over_area_change": round((E1 - E0) / (A1 - A0), 5),
+            "t_end": recs[-1]["t"]}
+        sf.close()
     return out
 
 
