@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--stefan-steps", type=int, default=60,
                     help="Stefan steps timed (the dendrite workload runs 500)")
+    ap.add_argument("--st-train-runs", type=int, default=16,
+                    help="training evolutions for the Stefan warm start")
+    ap.add_argument("--st-test-runs", type=int, default=4,
+                    help="held-out evolutions for the Stefan warm start")
     ap.add_argument("--only", default="",
                     help="comma list of extra sections to run (extra, batched, interior_dirichlet, "
                          "hele_shaw, warm_start, stefan); empty = all")
@@ -232,7 +236,8 @@ def main():
                     ("interior_dirichlet", lambda: interior_dirichlet(kf, W, torch, np, dev)),
                     ("hele_shaw", lambda: hele_shaw(kf, W, torch, np, dev, a)),
                     ("warm_start", lambda: warm_start(kf, W, torch, np, dev, a)),
-                    ("stefan", lambda: stefan(kf, W, torch, np, dev, a))]
+                    ("stefan", lambda: stefan(kf, W, torch, np, dev, a)),
+                    ("stefan_warm_start", lambda: stefan_warm_start(kf, W, torch, np, dev, a))]
         for name, fn in sections:
             if want is None or name in want:
                 result[name] = fn()
@@ -437,6 +442,80 @@ def stefan(kf, W, torch, np, dev, a):
             "t_end": recs[-1]["t"]}
         sf.close()
     return out
+
+
+def stefan_warm_start(kf, W, torch, np, dev, a):
+    """Learned initial guess of psi on the dendrite workload (as `stefan`, seeds scaled to
+    radius 0.1 from the perturbed curves r = 1 + sum_{m=2..8} a_m cos(m a + p_m)): data
+    from training evolutions, GPU training, then per-step GMRES iterations and wall time on
+    held-out evolutions for x0 = 0, the previous density and the learned guess, FP64 and
+    FP32-inner, all to the same 1e-10 FP64 residual."""
+    N, M, tau, St, nst = 2048, 128, 5e-4, -0.5, a.stefan_steps
+    box = W.box(-4.0, 4.0, N)
+    eC = (2e-3, -0.75, 0.0, 4, 0.0)
+    eV = (2e-3, 0.0, 0.0, 4, 0.0)
+
+    def seedc(sd):
+        return torch.tensor(0.1 * W.perturbed(M, sd), device=dev)
+
+    def make(prec=0):
+        return kf.Stefan(box.x0, box.y0, box.side, N, M, tau, eC, eV, bdf2=False, ssd=2,
+                         precision=prec)
+    ws = kf.WarmStart(M, max_batch=64, capacity=max(a.st_train_runs * nst, 64), seed=0)
+    t0 = time.perf_counter()
+    used, sd = 0, 0
+    while used < a.st_train_runs and sd < 4 * a.st_train_runs:
+        sf = make()
+        try:  # a seed whose curve the grid stops resolving is replaced by the next one
+            sf.init(seedc(sd), None, St)
+            th = sf.thetal
+            for _ in range(nst):
+                ws.predict(th)
+                sf.step()
+                ws.record(th)
+            used += 1
+        except kf.KfbiError:
+            pass
+        sf.close()
+        sd += 1
+    gen_s = time.perf_counter() - t0
+    n = ws.n_samples()
+    t0 = time.perf_counter()
+    losses = ws.train(n, a.ws_epochs, 64)
+    torch.cuda.synchronize()
+    res = {"train_runs": used, "seeds_tried": sd, "samples": n, "data_gen_s": round(gen_s, 2),
+           "train_s": round(time.perf_counter() - t0, 2), "epochs": a.ws_epochs,
+           "loss_first_last": [losses[0], losses[-1]] if losses else None}
+    x0 = torch.empty(M, dtype=torch.float64, device=dev)
+    for prec in (0, 1):
+        for mode in ("zero", "previous", "learned"):
+            its, tsum, nsteps = [], 0.0, 0
+            for k in range(a.st_test_runs):
+                sf = make(prec)
+                try:
+                    sf.init(seedc(1000 + k), None, St)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(nst):
+                        if mode == "zero":
+                            x0.zero_()
+                            r = sf.step(x0)
+                        elif mode == "previous":
+                            r = sf.step()
+                        else:
+                            ws.predict(sf.thetal, x0)
+                            r = sf.step(x0)
+                        its.append(r["iters"])
+                    torch.cuda.synchronize()
+                    tsum += time.perf_counter() - t0
+                    nsteps += nst
+                except kf.KfbiError:
+                    pass
+                sf.close()
+            res[f"{'f64' if prec == 0 else 'f32ir'}_{mode}"] = {
+                "mean_iters": round(float(np.mean(its)), 3) if its else None,
+                "ms_per_step": round(1e3 * tsum / max(nsteps, 1), 4), "steps": nsteps}
+    return res
 
 
 def warm_start(kf, W, torch, np, dev, a):

@@ -59,6 +59,8 @@ typedef struct {
   stefan_aniso eps_v;    /* kinetic coefficient eps_V (e0 > 0 with ssd = 1)                  */
   kfbi_gmres_opts gmres; /* options of the per-step GMRES solve                             */
   void* stream;          /* hipStream_t (NULL = default stream)                             */
+  double refine;         /* marker refinement ratio as thetaL_params.refine (0 = off)        */
+  int max_M;             /* refinement limit (power of two, M..2048; 0 = M)                 */
 } stefan_params;
 
 typedef struct {
@@ -68,6 +70,7 @@ typedef struct {
   double relres;         /* final true FP64 relative residual of eq. bie-GT                 */
   double area, length;   /* of the interface the step was solved on                         */
   double ms_geometry, ms_temperature, ms_gmres, ms_update;
+  int M, M_next;         /* markers of the step and after it (refinement doubles M)        */
 } stefan_stats;
 
 int stefan_create(const stefan_params* params, stefan** out);
@@ -94,6 +97,13 @@ int stefan_density(const stefan* st, double* psi_dev);
 int stefan_interface(const stefan* st, double* eta_dev, double* scal_host);
 /* The SSD constant in use, and the squared operator constant c^2 of the temperature step. */
 int stefan_constants(const stefan* st, double* lambda, double* c2);
+/* Current number of markers. */
+int stefan_size(const stefan* st, int* M);
+/* The theta-L state of the interface, owned by st: pass it to kfbi_ws_predict (before
+ * stefan_step, whose x0_dev then takes the guess) and kfbi_ws_record (after it) of
+ * warmstart.h for the learned initial guess of psi (the densities of the previous steps
+ * play the part of the Hele-Shaw phi). */
+thetaL* stefan_thetal(stefan* st);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,10 @@ Readings where the paper is silent:
 * the temperature is kept on the grid nodes (N+1)^2; the area of Omega+ for the energy
   balance is the curve's enclosed area.
 
+Marker refinement as for the Hele-Shaw state (oracle.thetal.refine): eta, the last density
+and the explicit-term history go to the doubled parameter grid by trigonometric
+interpolation; the temperature is untouched.
+
 Pinned by: the first-step density for a circle in a uniform field against the closed
 form of the free-space single layer, the energy balance sum(T) h^2 - area(Omega+) kept
 to discretisation error, the symmetry of a growing circle, and the two SSD propagators'
@@ -201,3 +205,14 @@ def energy(st: StefanState, box) -> float:
     w[0] = w[-1] = 0.5
     X, *_ = reconstruct(st.eta, st.L, st.Xbar)
     return float(np.sum(w[:, None] * w[None, :] * st.T) * h * h - area(X))
+
+
+def refine(st: StefanState) -> StefanState:
+    """Double the markers (trigonometric interpolation of eta, psi and the DFT history)."""
+    from .thetal import HSState, refine as hs_refine
+    r = hs_refine(HSState(st.eta, st.L, st.Xbar, st.n, st.t, st.Nhat_prev, st.Mdot_prev,
+                          np.zeros(2) if st.Q_prev is None else st.Q_prev, st.L_prev,
+                          st.psi_prev))
+    return StefanState(r.eta, st.L, st.Xbar.copy(), st.T, st.T_prev, st.n, st.t, r.Nhat_prev,
+                       st.Mdot_prev, None if st.Q_prev is None else st.Q_prev.copy(), st.L_prev,
+                       r.phi_prev)

@@ -81,6 +81,8 @@ static void release_all(kfbi_ctx* c) {
     if (c->gev[i]) (void)hipEventDestroy(c->gev[i]);
   if (c->hpin) (void)hipHostFree(c->hpin);
   c->hpin = nullptr;
+  if (c->hstat) (void)hipHostFree(c->hstat);
+  c->hstat = c->dstat = nullptr;
 }
 
 }  // namespace kfbi
@@ -178,6 +180,12 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
       (st = c->mqz.ensure(sizeof(double) * 5 * Mx)) ||
       (st = c->tmpM.ensure(sizeof(double) * (Bx > 4 ? Bx : 4) * Mx)))
     return fail(st);
+  if (hipHostMalloc(&c->hstat, 4096, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer(&c->dstat, c->hstat, 0) != hipSuccess) {
+    c->hstat = c->dstat = nullptr;
+    set_error("hipHostMalloc (coherent status ring) failed");
+    return fail(KFBI_E_NOMEM);
+  }
   if (hipHostMalloc(&c->hpin, 4096, hipHostMallocDefault) != hipSuccess) {
     set_error("hipHostMalloc failed");
     return fail(KFBI_E_NOMEM);

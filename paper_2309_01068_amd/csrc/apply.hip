@@ -270,6 +270,9 @@ __global__ void __launch_bounds__(256)
     }
     int q = kb;  // index of w[0]
     int m = mb;
+    double acc2[kReg];  // odd steps: two independent FMA chains per output
+#pragma unroll
+    for (int r = 0; r < kReg; ++r) acc2[r] = 0.0;
     for (; m + 8 <= me; m += 8) {
       double f[8], nw[8];
 #pragma unroll
@@ -282,7 +285,10 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
 #pragma unroll
-        for (int r = 0; r < kReg; ++r) acc[r] += w[r] * f[u];
+        for (int r = 0; r < kReg; ++r) {
+          if (u & 1) acc2[r] += w[r] * f[u];
+          else acc[r] += w[r] * f[u];
+        }
 #pragma unroll
         for (int r = kReg - 1; r > 0; --r) w[r] = w[r - 1];
         w[0] = nw[u];
@@ -290,6 +296,8 @@ __global__ void __launch_bounds__(256)
       q -= 8;
       q += (q < 0) ? M : 0;
     }
+#pragma unroll
+    for (int r = 0; r < kReg; ++r) acc[r] += acc2[r];
     for (; m < me; ++m) {
       const double f = ph[lpad(m)];
 #pragma unroll

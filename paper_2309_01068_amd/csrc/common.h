@@ -117,6 +117,8 @@ struct kfbi_ctx {
   hipEvent_t gev[kGmresRing] = {};
   // pinned host status
   void* hpin = nullptr;
+  void* hstat = nullptr;  // coherent pinned host memory the Arnoldi kernels write into
+  void* dstat = nullptr;  // its device address
 
   // stage profiling with HIP events (kfbi_profile)
   int prof_on = 0;

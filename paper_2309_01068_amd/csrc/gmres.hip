@@ -29,6 +29,16 @@ struct GmresStatus {
   int pad[11];
 };
 
+// Status of an Arnoldi step for the host: written straight into mapped host memory
+// (coherent pinned allocation) and pushed out at system scope, so that the host reads it
+// once the step's event has completed, with no copy in the stream.
+__device__ __forceinline__ void post_status(GmresStatus* hout, double resid, double hn) {
+  hout->resid = resid;
+  hout->hnext = hn;
+  hout->breakdown = (hn == 0.0);
+  __threadfence_system();
+}
+
 // Partial inner products <V_i, w> (i < nv) and optionally ||w||^2, after an optional
 // update w -= sum_i hprev_i V_i.  The last block to finish reduces the partials in block
 // order and writes out[0..nv) (and out[nv] = ||w||^2).
@@ -85,7 +95,7 @@ __global__ void __launch_bounds__(kRedBlock)
              double* __restrict__ part, unsigned int* __restrict__ counter,
              double* __restrict__ H /* (kMaxRestart+1) x kMaxRestart, column-major */,
              double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-             GmresStatus* __restrict__ st) {
+             GmresStatus* __restrict__ st, GmresStatus* __restrict__ hout) {
   __shared__ double red[4];
   __shared__ int is_last;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -133,6 +143,7 @@ __global__ void __launch_bounds__(kRedBlock)
   st->resid = fabs(g[j + 1]);
   st->hnext = hn;
   st->breakdown = (hn == 0.0);
+  post_status(hout, fabs(g[j + 1]), hn);
   *counter = 0u;
 }
 
@@ -145,7 +156,8 @@ constexpr int kArnPer = 4;  // elements per thread: M <= 4096
 __global__ void __launch_bounds__(kArnThreads)
     k_arnoldi(int M, int ldv, double* __restrict__ V, int j, const double* __restrict__ w,
               double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
-              double* __restrict__ g, GmresStatus* __restrict__ st) {
+              double* __restrict__ g, GmresStatus* __restrict__ st,
+              GmresStatus* __restrict__ hout) {
   __shared__ double red[kMaxRestart + 1][kArnThreads / 64];
   __shared__ double hv[2][kMaxRestart + 1];
   __shared__ double wsh[kArnThreads * kArnPer];
@@ -215,6 +227,7 @@ __global__ void __launch_bounds__(kArnThreads)
     st->resid = fabs(g[j + 1]);
     st->hnext = hn;
     st->breakdown = (hn == 0.0);
+    post_status(hout, fabs(g[j + 1]), hn);
     red[1][0] = hn;
   }
   __syncthreads();
@@ -317,7 +330,8 @@ struct GmresWork {
   GmresStatus* st;   // status of the last reduction (residual norms)
   GmresStatus* hst;  // pinned host copy
   GmresStatus* ring;   // per-iteration Arnoldi status, slot j % kRing (device)
-  GmresStatus* hring;  // pinned host copies
+  GmresStatus* hring;  // status ring in coherent pinned host memory (host view)
+  GmresStatus* dring;  // the same memory as the kernels address it
   hipEvent_t* ev;      // one event per ring slot, recorded after its copy
   double* r;
   double* d;
@@ -350,7 +364,8 @@ static int ensure_work(kfbi_ctx* c, int restart, GmresWork* gw) {
   gw->ring = gw->st + 1;
   gw->counter = reinterpret_cast<unsigned int*>(gw->st + 1 + kRing);
   gw->hst = reinterpret_cast<GmresStatus*>(reinterpret_cast<char*>(c->hpin) + 1024);
-  gw->hring = gw->hst + 1;
+  gw->hring = reinterpret_cast<GmresStatus*>(c->hstat);
+  gw->dring = reinterpret_cast<GmresStatus*>(c->dstat);
   gw->ev = c->gev;
   double* wb = c->gw.as<double>();
   gw->w = wb;
@@ -419,9 +434,10 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
         KFBI_TRY(apply_impl(c, op->layer, precision, vj, nullptr, nullptr, op, vj, gw->w));
         ++*applies;
         GmresStatus* sj = gw->ring + (j % kRing);
+        GmresStatus* hj = gw->dring + (j % kRing);  // device view of the host ring slot
         if (one_block) {
           hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(kArnThreads), 0, s, M, gw->ldv, gw->V, j,
-                             gw->w, gw->H, gw->cs, gw->sn, gw->g, sj);
+                             gw->w, gw->H, gw->cs, gw->sn, gw->g, sj, hj);
         } else {
           hipLaunchKernelGGL(k_cgs, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j + 1,
                              gw->w, nullptr, 0, gw->part, gw->counter, gw->h1);
@@ -429,12 +445,10 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
                              gw->w, gw->h1, 0, gw->part, gw->counter, gw->h2);
           hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j,
                              gw->w, gw->h1, gw->h2, gw->part, gw->counter, gw->H, gw->cs, gw->sn,
-                             gw->g, sj);
+                             gw->g, sj, hj);
           hipLaunchKernelGGL(k_scale, dim3(mb), dim3(256), 0, s, M, gw->w, &sj->hnext, vn);
         }
         KFBI_HIP(hipGetLastError());
-        KFBI_HIP(hipMemcpyAsync(gw->hring + (j % kRing), sj, sizeof(GmresStatus),
-                                hipMemcpyDeviceToHost, s));
         KFBI_HIP(hipEventRecord(gw->ev[j % kRing], s));
         ++launched;
       }
@@ -472,7 +486,7 @@ extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b
     return KFBI_E_STATE;
   }
   if (c->box_bc == KFBI_BOX_USER) {
-    set_error("GMRES needs box data defined by the density (ZERO or FREESPACE)");
+    set_error("GMRES needs box data defined by the density (ZERO, FREESPACE or NEUMANN)");
     return KFBI_E_INVALID;
   }
   if (o->restart < 1 || o->restart > kMaxRestart || o->maxit < 1 || !(o->tol > 0.0) ||

@@ -660,6 +660,21 @@ static int tl_set_M(thetaL* th, int M) {
   return KFBI_OK;
 }
 
+// Adaptive refinement after a step: double M when the marker spacing L/M of the new state
+// exceeds ratio * h and the buffers allow it (eta, the last two densities and the
+// explicit-term history are interpolated to the doubled grid).  Synchronises if it refines.
+static int tl_maybe_refine(thetaL* th, double ratio, double h) {
+  const int M = th->M;
+  if (!(ratio > 0.0) || !(th->hscal[S_L] / M > ratio * h) || 2 * M > th->Mcap) return KFBI_OK;
+  KFBI_TRY(tl_set_M(th, 2 * M));  // twiddles of length 2M
+  hipLaunchKernelGGL(k_tl_refine, dim3(1), dim3(kTLThreads), refine_lds_bytes(M), th->stream, M,
+                     th->tw.as<double>(), th->eta.as<double>(), th->phi.as<double>(),
+                     th->phi2.as<double>(), th->nhat.as<double>());
+  KFBI_HIP(hipGetLastError());
+  KFBI_HIP(hipStreamSynchronize(th->stream));
+  return KFBI_OK;
+}
+
 static void tl_free(thetaL* th) {
   for (DBuf* b : {&th->tw, &th->eta, &th->scal, &th->X, &th->rhs, &th->aux, &th->etahat, &th->nhat,
                   &th->phi, &th->phi2, &th->phiw, &th->dnp, &th->dnm, &th->init})
@@ -904,16 +919,7 @@ int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
     set_error("thetaL_step: the new state is not finite (step %d)", step);
     return KFBI_E_NONFINITE;
   }
-  // adaptive refinement: marker spacing of the new state against the grid spacing
-  const double hgrid = p.grid.side / p.grid.N;
-  if (p.refine > 0.0 && th->hscal[S_L] / M > p.refine * hgrid && 2 * M <= th->Mcap) {
-    KFBI_TRY(tl_set_M(th, 2 * M));  // twiddles of length 2M
-    hipLaunchKernelGGL(k_tl_refine, dim3(1), dim3(kTLThreads), refine_lds_bytes(M), s, M,
-                       th->tw.as<double>(), th->eta.as<double>(), th->phi.as<double>(),
-                       th->phi2.as<double>(), th->nhat.as<double>());
-    KFBI_HIP(hipGetLastError());
-    KFBI_HIP(hipStreamSynchronize(s));
-  }
+  KFBI_TRY(tl_maybe_refine(th, p.refine, p.grid.side / p.grid.N));
   if (stats) {
     stats->M = M;
     stats->M_next = th->M;
@@ -1084,7 +1090,13 @@ int stefan_create(const stefan_params* p, stefan** out) {
   tp.tau = p->tau;
   tp.lambda2 = s->lam;
   tp.gmres = p->gmres;
-  int st = tl_setup(&s->tl, &tp, M, M);
+  const int Mcap = p->max_M > 0 ? p->max_M : M;
+  if (Mcap < M || Mcap > kTLMaxM || (Mcap & (Mcap - 1)) || !(p->refine >= 0.0)) {
+    delete s;
+    set_error("stefan: max_M must be a power of two in [M, %d] and refine >= 0", kTLMaxM);
+    return KFBI_E_INVALID;
+  }
+  int st = tl_setup(&s->tl, &tp, M, Mcap);
   if (st != KFBI_OK) {
     delete s;
     return st;
@@ -1093,8 +1105,8 @@ int stefan_create(const stefan_params* p, stefan** out) {
   const size_t n1sq = static_cast<size_t>(p->N + 1) * (p->N + 1);
   if ((st = s->That.ensure(sizeof(double) * nf)) || (st = s->Tprev.ensure(sizeof(double) * nf)) ||
       (st = s->Tnew.ensure(sizeof(double) * nf)) || (st = s->T1.ensure(sizeof(double) * nf)) ||
-      (st = s->t1at.ensure(sizeof(double) * M)) || (st = s->amk.ensure(sizeof(double) * M)) ||
-      (st = s->neg.ensure(sizeof(double) * M)) || (st = s->grid0.ensure(sizeof(double) * n1sq))) {
+      (st = s->t1at.ensure(sizeof(double) * Mcap)) || (st = s->amk.ensure(sizeof(double) * Mcap)) ||
+      (st = s->neg.ensure(sizeof(double) * Mcap)) || (st = s->grid0.ensure(sizeof(double) * n1sq))) {
     st_free(s);
     delete s;
     return st;
@@ -1220,11 +1232,26 @@ int stefan_step(stefan* s, const double* x0, stefan_stats* stats) {
     stats->ms_temperature = ms_t1;
     stats->ms_gmres = ms_gm;
     stats->ms_update = ms_up;
+    stats->M = M;
+    stats->M_next = M;
   }
   if (th->hscal[S_BAD] != 0.0) {
     set_error("stefan_step: the new state is not finite (step %d)", step);
     return KFBI_E_NONFINITE;
   }
+  KFBI_TRY(tl_maybe_refine(th, p.refine, p.side / p.N));
+  if (stats) stats->M_next = th->M;
+  return KFBI_OK;
+}
+
+thetaL* stefan_thetal(stefan* s) { return s ? &s->tl : nullptr; }
+
+int stefan_size(const stefan* s, int* M) {
+  if (!s || !M) {
+    set_error("null argument");
+    return KFBI_E_INVALID;
+  }
+  *M = s->tl.M;
   return KFBI_OK;
 }
 

@@ -34,7 +34,7 @@ EXPORTS = [
     "kfbi_ws_target_scale",
     "stefan_create", "stefan_destroy", "stefan_init", "stefan_step", "stefan_run",
     "stefan_temperature", "stefan_markers", "stefan_density", "stefan_interface",
-    "stefan_constants",
+    "stefan_constants", "stefan_size", "stefan_thetal",
 ]
 
 
@@ -111,7 +111,8 @@ class StefanParams(C.Structure):
     _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("side", C.c_double), ("N", C.c_int),
                 ("M", C.c_int), ("tau", C.c_double), ("bdf2", C.c_int), ("ssd", C.c_int),
                 ("lambda_", C.c_double), ("eps_c", StefanAniso), ("eps_v", StefanAniso),
-                ("gmres", GmresOpts), ("stream", C.c_void_p)]
+                ("gmres", GmresOpts), ("stream", C.c_void_p), ("refine", C.c_double),
+                ("max_M", C.c_int)]
 
 
 class StefanStats(C.Structure):
@@ -119,7 +120,7 @@ class StefanStats(C.Structure):
                 ("applies32", C.c_int), ("relres", C.c_double), ("area", C.c_double),
                 ("length", C.c_double), ("ms_geometry", C.c_double),
                 ("ms_temperature", C.c_double), ("ms_gmres", C.c_double),
-                ("ms_update", C.c_double)]
+                ("ms_update", C.c_double), ("M", C.c_int), ("M_next", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -179,6 +180,9 @@ def load(path: str = LIBPATH):
     lib.stefan_density.argtypes = [vp, vp]
     lib.stefan_interface.argtypes = [vp, vp, C.POINTER(C.c_double)]
     lib.stefan_constants.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.stefan_size.argtypes = [vp, C.POINTER(C.c_int)]
+    lib.stefan_thetal.argtypes = [vp]
+    lib.stefan_thetal.restype = vp
     ip, fp = C.POINTER(C.c_int), C.POINTER(C.c_float)
     lib.kfbi_ws_create.argtypes = [C.POINTER(WsCfg), C.POINTER(vp)]
     lib.kfbi_ws_destroy.argtypes = [vp]
@@ -403,18 +407,30 @@ class Stefan:
     (e0, e1, e2, m, phi0) of eps(phi) = e0 (1 + e1 cos(m (phi - phi0)) + e2 cos(2 m (phi - phi0)))."""
 
     def __init__(self, x0, y0, side, N, M, tau, eps_c, eps_v, bdf2=True, ssd=2, lam=0.0,
-                 tol=1e-10, restart=50, maxit=1000, precision=FP64, inner_tol=1e-5, stream=None):
+                 tol=1e-10, restart=50, maxit=1000, precision=FP64, inner_tol=1e-5, stream=None,
+                 refine=0.0, max_M=0):
         self.lib = load()
         s = torch.cuda.current_stream() if stream is None else stream
         self.stream = s
-        self.N, self.M = N, M
+        self.N = N
         p = StefanParams(x0, y0, side, N, M, tau, 1 if bdf2 else 0, ssd, lam,
                          StefanAniso(*eps_c), StefanAniso(*eps_v),
                          GmresOpts(tol, restart, maxit, precision, inner_tol),
-                         C.c_void_p(s.cuda_stream))
+                         C.c_void_p(s.cuda_stream), refine, max_M)
         h = C.c_void_p()
         _check(self.lib.stefan_create(C.byref(p), C.byref(h)))
         self.h = h
+
+    @property
+    def M(self) -> int:
+        m = C.c_int()
+        _check(self.lib.stefan_size(self.h, C.byref(m)))
+        return m.value
+
+    @property
+    def thetal(self):
+        """A ThetaL-like view of the interface state for WarmStart.predict / record."""
+        return _ThetaLView(self.lib.stefan_thetal(self.h))
 
     def close(self):
         if self.h:
@@ -467,6 +483,13 @@ class Stefan:
         lam, c2 = C.c_double(), C.c_double()
         _check(self.lib.stefan_constants(self.h, C.byref(lam), C.byref(c2)))
         return lam.value, c2.value
+
+
+class _ThetaLView:
+    """The theta-L state owned by a Stefan object (not destroyed through this handle)."""
+
+    def __init__(self, h):
+        self.h = C.c_void_p(h)
 
 
 def _fptr(t):

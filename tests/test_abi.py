@@ -25,7 +25,9 @@ def test_header_declares_the_entry_points():
     names = declared_functions()
     for must in ("kfbi_create", "kfbi_destroy", "kfbi_set_interface", "kfbi_apply",
                  "kfbi_operator", "kfbi_gmres_solve", "kfbi_last_error", "thetaL_create",
-                 "thetaL_init", "thetaL_step", "thetaL_get_state", "thetaL_set_state"):
+                 "thetaL_init", "thetaL_step", "thetaL_get_state", "thetaL_set_state",
+                 "kfbi_apply_batch", "thetaL_size", "stefan_create", "stefan_init", "stefan_step",
+                 "stefan_temperature", "stefan_thetal"):
         assert must in names
 
 

@@ -142,3 +142,110 @@ def test_stefan_errors():
     with pytest.raises(kfbi.KfbiError) as e:
         g.step()                                                # before init
     assert e.value.code == kfbi.E_STATE
+
+
+def test_stefan_refinement_parity():
+    """A growing seed with 16 markers is refined to 32 after the first step (spacing
+    2.5 h > 2.1 h); the GPU follows the oracle through it."""
+    box = W.box(-1, 1, 64)
+    M, tau, St = 16, 1e-3, -0.5
+    X = W.circle(M, 0.2)
+    eta, L, Xb = T.equal_arclength_init(X, M)
+    Xr, *_ = T.reconstruct(eta, L, Xb)
+    T0 = S.seed_temperature(box, Xr, St)
+    prm = S.StefanParams(box=box, tau=tau, eC=ISO_C, eV=ISO_V, bdf2=True, ssd=2, tol=1e-12)
+    st = S.StefanState(eta, L, Xb, T0)
+    from paper_2309_01068_amd import kfbi
+    g = kfbi.Stefan(box.x0, box.y0, box.side, box.N, M, tau, ISO_C, ISO_V, bdf2=True, ssd=2,
+                    tol=1e-12, refine=2.1, max_M=64)
+    g.init(dev(X), dev(T0))
+    Ms = []
+    for k in range(3):
+        print(f"[case] stefan refinement step {k}", flush=True)
+        st, info = S.stefan_step(st, prm)
+        if st.L / st.eta.size > 2.1 * box.h and 2 * st.eta.size <= 64:
+            st = S.refine(st)
+        r = g.step()
+        Ms.append((r["M"], r["M_next"]))
+        assert g.M == st.eta.size
+        eta_g, sc = g.interface()
+        assert np.max(np.abs(eta_g.cpu().numpy() - st.eta)) <= 1e-9, k
+        assert abs(sc[0] - st.L) <= 1e-11 * st.L
+        assert rel(g.density().cpu().numpy(), st.psi_prev) <= 1e-8
+        assert rel(g.temperature().cpu().numpy(), st.T) <= 1e-8
+    assert Ms[0] == (16, 32) and Ms[1][0] == 32
+
+
+def test_stefan_learned_warm_start_plumbing():
+    """The warm start of warmstart.h works on the Stefan interface state: samples are
+    recorded, the network trains, and steps from the learned guess converge to the same
+    residual (128 markers, 256^2 box [-2,2]^2, seed radius 0.5)."""
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-2, 2, 256)
+    M = 128
+    ws = kfbi.WarmStart(M, max_batch=16, capacity=256, seed=1)
+    seedc = lambda s: W.polar_curve(lambda a: 0.5 * (1 + 0.05 * np.cos((3 + s) * a + 0.1 * s)), M)
+    for sd in range(3):
+        print(f"[case] stefan warm-start data run {sd}", flush=True)
+        g = make(box, M, 1e-3, ANI_C, ISO_V, True, 2, tol=1e-10)
+        g.init(dev(seedc(sd)), None, -0.5)
+        th = g.thetal
+        for _ in range(12):
+            ws.predict(th)
+            g.step()
+            ws.record(th)
+    n = ws.n_samples()
+    assert n == 3 * 10
+    losses = ws.train(n, 10, 8)
+    assert np.all(np.isfinite(losses))
+    g = make(box, M, 1e-3, ANI_C, ISO_V, True, 2, tol=1e-10)
+    g.init(dev(seedc(7)), None, -0.5)
+    x0 = torch.empty(M, dtype=torch.float64, device="cuda")
+    for _ in range(6):
+        ws.predict(g.thetal, x0)
+        r = g.step(x0)
+        assert r["relres"] <= 1e-10
+
+
+def test_stefan_fp32_inner_solve_gives_the_same_step():
+    """FP32 grid stages inside FP64 iterative refinement reach the same 1e-10 residual."""
+    box = W.box(-1, 1, 64)
+    M = 32
+    X = seed(M, "pert")
+    a = make(box, M, 1e-3, ANI_C, ISO_V, True, 2, tol=1e-10)
+    from paper_2309_01068_amd import kfbi
+    b = kfbi.Stefan(box.x0, box.y0, box.side, box.N, M, 1e-3, ANI_C, ISO_V, bdf2=True, ssd=2,
+                    tol=1e-10, precision=1)
+    a.init(dev(X), None, -0.5)
+    b.init(dev(X), None, -0.5)
+    for _ in range(3):
+        ra, rb = a.step(), b.step()
+        assert rb["relres"] <= 1e-10 and rb["applies32"] > 0
+    assert rel(b.density().cpu().numpy(), a.density().cpu().numpy()) <= 1e-7
+    assert rel(b.temperature().cpu().numpy(), a.temperature().cpu().numpy()) <= 1e-8
+
+
+def test_stefan_dendrite_workload_full_size():
+    """The dendrite workload at full size (2048^2 box [-4,4]^2, seed r = 0.1 with 128
+    markers, backward Euler, tau = 5e-4, St = -0.5, four-fold eps_C): two steps against
+    the oracle."""
+    box = W.box(-4, 4, 2048)
+    M, tau, St = 128, 5e-4, -0.5
+    eC = (2e-3, -0.75, 0.0, 4, 0.0)
+    X = W.circle(M, 0.1)
+    eta, L, Xb = T.equal_arclength_init(X, M)
+    Xr, *_ = T.reconstruct(eta, L, Xb)
+    T0 = S.seed_temperature(box, Xr, St)
+    prm = S.StefanParams(box=box, tau=tau, eC=eC, eV=ISO_V, bdf2=False, ssd=2, tol=1e-12)
+    st = S.StefanState(eta, L, Xb, T0)
+    g = make(box, M, tau, eC, ISO_V, False, 2)
+    g.init(dev(X), None, St)
+    assert rel(g.temperature().cpu().numpy(), T0) < 1e-12
+    for k in range(2):
+        print(f"[case] dendrite full size step {k}", flush=True)
+        st, info = S.stefan_step(st, prm)
+        g.step()
+        e_psi = rel(g.density().cpu().numpy(), info.psi)
+        e_T = rel(g.temperature().cpu().numpy(), st.T)
+        print(f"  psi {e_psi:.2e} T {e_T:.2e}")
+        assert e_psi <= 1e-8 and e_T <= 1e-8

@@ -79,3 +79,14 @@ def test_ssd_second_order_term_is_damping():
     a = 2 * np.pi * np.arange(M) / M
     for k in (1, 5, 20):
         assert np.allclose(spectral.diff(np.cos(k * a), 2), -k * k * np.cos(k * a), atol=1e-9)
+
+
+def test_refinement_keeps_the_temperature_and_interpolates_the_state():
+    box = W.box(-1, 1, 64)
+    X = W.circle(16, 0.2)
+    eta, L, Xb = T.equal_arclength_init(X, 16)
+    st = S.StefanState(eta, L, Xb, np.full((65, 65), -0.5), psi_prev=np.cos(2 * np.linspace(0, 2 * np.pi, 16, endpoint=False)))
+    r = S.refine(st)
+    assert r.eta.size == 32 and r.T is st.T and r.L == L
+    a2 = np.pi * np.arange(32) / 16
+    assert np.max(np.abs(r.psi_prev - np.cos(2 * a2))) < 1e-14
