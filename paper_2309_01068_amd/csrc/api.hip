@@ -28,13 +28,16 @@ int DBuf::ensure(size_t need) {
     bytes = 0;
   }
   if (need == 0) return KFBI_OK;
-  hipError_t e = hipMalloc(&p, need);
+  // a quarter of headroom: sizes that follow a slowly growing interface (crossings, arms,
+  // row parts) then reallocate rarely; hipFree synchronises the device
+  const size_t want = need + need / 4 + 256;
+  hipError_t e = hipMalloc(&p, want);
   if (e != hipSuccess) {
     p = nullptr;
-    set_error("hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
+    set_error("hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
     return KFBI_E_NOMEM;
   }
-  bytes = need;
+  bytes = want;
   return KFBI_OK;
 }
 

@@ -355,6 +355,27 @@ __global__ void k_mark_v(int nh, int nv, const Crossing* __restrict__ cr, int N,
 
 // Labels per row: node (i, j) is in Omega+ iff #{row-j crossings with seg < i} is odd
 // (seg < i  <=>  xi < x_i).  One block per row.
+// hid, vid, vraw = -1 and need = 0 on the nn nodes; rowoff[0..nr) = 0.
+__global__ void k_geo_clear(int nn, int nr, int* __restrict__ hid, int* __restrict__ vid,
+                            int* __restrict__ vraw, int* __restrict__ need,
+                            int* __restrict__ rowoff) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = 4 * t;
+  if (i + 3 < nn) {
+    const int4 m1 = make_int4(-1, -1, -1, -1), z = make_int4(0, 0, 0, 0);
+    reinterpret_cast<int4*>(hid)[t] = m1;
+    reinterpret_cast<int4*>(vid)[t] = m1;
+    reinterpret_cast<int4*>(vraw)[t] = m1;
+    reinterpret_cast<int4*>(need)[t] = z;
+  } else {
+    for (int k = i; k < nn; ++k) {
+      hid[k] = vid[k] = vraw[k] = -1;
+      need[k] = 0;
+    }
+  }
+  if (t < nr) rowoff[t] = 0;
+}
+
 __global__ void k_label(int N, const int* __restrict__ hid, int8_t* __restrict__ lab) {
   __shared__ int scratch[17];
   const int j = blockIdx.x;
@@ -839,10 +860,14 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
                        c->X.as<double>(), c->x0, c->y0, h, cr);
   int* hid = c->hid.as<int>();
   int* vid = c->vid.as<int>();
-  KFBI_HIP(hipMemsetAsync(hid, 0xff, sizeof(int) * n1 * n1, s));
-  KFBI_HIP(hipMemsetAsync(vid, 0xff, sizeof(int) * n1 * n1, s));
   int* vraw = c->vraw.as<int>();
-  KFBI_HIP(hipMemsetAsync(vraw, 0xff, sizeof(int) * n1 * n1, s));
+  int* need = c->need.as<int>();
+  int* rowoff = c->armrow.as<int>();  // N+2 entries
+  {  // the per-node maps and the arm row counts in one pass
+    const int nn = n1 * n1;
+    hipLaunchKernelGGL(k_geo_clear, dim3(nblk((nn + 3) / 4, 256)), dim3(256), 0, s, nn, N + 2,
+                       hid, vid, vraw, need, rowoff);
+  }
   if (nh > 0)
     hipLaunchKernelGGL(k_mark_h, dim3(nblk(nh, 256)), dim3(256), 0, s, nh, cr, N, hid, st);
   int8_t* lab = c->lab.as<int8_t>();
@@ -853,16 +878,12 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
                        lab, vraw, vid, st);
   }
   // arms
-  int* rowoff = c->armrow.as<int>();  // N+2 entries
-  KFBI_HIP(hipMemsetAsync(rowoff, 0, sizeof(int) * (N + 2), s));
   hipLaunchKernelGGL(k_arm_rowcount, dim3(N - 1), dim3(256), 0, s, N, lab, hid, vid, rowoff, st);
   hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, rowoff, &st->n_arms);
   hipLaunchKernelGGL(k_arm_fill, dim3(N - 1), dim3(256), 0, s, N, c->x0, c->y0, h, c->c2, M, lab,
                      hid, vid, rowoff, cr, c->geo.as<double>(), c->armpk.as<int>(),
                      c->armcoef.as<ArmCoef>(), st);
   // markers / nodes
-  int* need = c->need.as<int>();
-  KFBI_HIP(hipMemsetAsync(need, 0, sizeof(int) * n1 * n1, s));
   hipLaunchKernelGGL(k_marker_ext, dim3(nblk(M, 64)), dim3(64), 0, s, M, c->X.as<double>(),
                      c->geo.as<double>(), c->x0, c->y0, h, N, c->c2, lab, c->ext.as<double>(),
                      need, c->mknode.as<int>());
