@@ -901,6 +901,10 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   hipLaunchKernelGGL(k_chunk_nodes, dim3(nch), dim3(128), sizeof(int) * 12 * MC, s, M, MC,
                      c->mknode.as<int>(), c->cnode.as<int>(), c->ccount.as<int>(),
                      c->mkloc.as<int>());
+  // row parts of the row transform (counted here so that one read of the status gives them)
+  int* rowpart = c->rowpart.as<int>();
+  hipLaunchKernelGGL(k_part_count, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart);
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, rowpart, &st->n_parts);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipMemcpyAsync(hs, st, sizeof(GeoStatus), hipMemcpyDeviceToHost, s));
   KFBI_HIP(hipStreamSynchronize(s));
@@ -914,12 +918,6 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   }
   // row parts for the row transform kernel
   {
-    int* rowpart = c->rowpart.as<int>();
-    const int* rowoff = c->armrow.as<int>();
-    hipLaunchKernelGGL(k_part_count, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart);
-    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, rowpart, &st->n_parts);
-    KFBI_HIP(hipMemcpyAsync(hs, st, sizeof(GeoStatus), hipMemcpyDeviceToHost, s));
-    KFBI_HIP(hipStreamSynchronize(s));
     const int P = hs->n_parts;
     KFBI_TRY(c->pdesc.ensure(sizeof(int4) * (P + 1)));
     const int ng = (N + 1 + 3) / 4;  // mode groups (cosine layout; the sine one needs fewer)
