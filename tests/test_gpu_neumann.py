@@ -139,3 +139,34 @@ def test_neumann_needs_positive_c2():
     with pytest.raises(kfbi.KfbiError) as e:
         kfbi.Context(-1, -1, 2, 128, 0.0, kfbi.BOX_NEUMANN)
     assert e.value.code == kfbi.E_INVALID
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_neumann_batch_fp32_and_fp64_match_single(precision):
+    """Batched applies with the cosine basis, both precisions, small grid (E = 2)."""
+    box = W.box(-1, 1, 64)
+    X = W.circle(96, 0.45)
+    ctx = ctx_for(box, 30.0, 96, max_batch=3)
+    ctx.set_interface(dev(X))
+    D = np.stack([W.fourier_density(96, seed=s) for s in range(3)])
+    out = ctx.apply_batch(K.SINGLE, dev(D), precision)
+    for b in range(3):
+        one = ctx.apply(K.SINGLE, dev(D[b]), precision)
+        for k in KEYS:
+            assert torch.equal(out[k][b], one[k]), (b, k)
+
+
+def test_neumann_profile_kernel_replay():
+    """Replaying the cosine-basis kernels leaves the next apply's results unchanged."""
+    box = W.box(-1, 1, 128)
+    X = W.star(256)
+    g = G.build_geometry(X, box)
+    d = W.fourier_density(256, seed=3)
+    ref = K.apply(g, K.DOUBLE, d, 500.0, K.BOX_NEUMANN)
+    ctx = ctx_for(box, 500.0, 256)
+    ctx.set_interface(dev(X))
+    ctx.apply(K.DOUBLE, dev(d))
+    for q in range(4):
+        assert ctx.profile_kernel(q, reps=5) > 0.0
+    out = ctx.apply(K.DOUBLE, dev(d))
+    assert rel(out["v_plus"].cpu().numpy(), ref.v_plus) <= TOL64

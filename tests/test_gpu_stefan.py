@@ -249,3 +249,24 @@ def test_stefan_dendrite_workload_full_size():
         e_T = rel(g.temperature().cpu().numpy(), st.T)
         print(f"  psi {e_psi:.2e} T {e_T:.2e}")
         assert e_psi <= 1e-8 and e_T <= 1e-8
+
+
+def test_stefan_backward_euler_second_order_ssd_parity():
+    """Backward Euler with the second-order SSD term (eps_V = O(1) case)."""
+    box = W.box(-1, 1, 64)
+    M, tau, St = 32, 1e-3, -0.5
+    eV = (5e-2, 0.0, 0.0, 4, 0.0)
+    X = seed(M, "pert")
+    eta, L, Xb = T.equal_arclength_init(X, M)
+    Xr, *_ = T.reconstruct(eta, L, Xb)
+    T0 = S.seed_temperature(box, Xr, St)
+    prm = S.StefanParams(box=box, tau=tau, eC=ANI_C, eV=eV, bdf2=False, ssd=1, tol=1e-12)
+    st = S.StefanState(eta, L, Xb, T0)
+    g = make(box, M, tau, ANI_C, eV, False, 1)
+    g.init(dev(X), dev(T0))
+    for k in range(3):
+        st, info = S.stefan_step(st, prm)
+        g.step()
+        assert rel(g.density().cpu().numpy(), info.psi) <= 1e-8
+        eta_g, sc = g.interface()
+        assert np.max(np.abs(eta_g.cpu().numpy() - st.eta)) <= 1e-9

@@ -262,3 +262,21 @@ def test_checkpoint_keeps_the_refined_markers():
     b.run(2)
     sa, sb = a.get_state(), b.get_state()
     assert torch.equal(sa["eta"], sb["eta"]) and sa["scal"] == sb["scal"]
+
+
+def test_refinement_with_fp32_inner_solve():
+    """Refinement and the FP32 inner solve together: the same refinement steps and the
+    same state (to the 1e-10 residual) as the FP64 run."""
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-2, 2, 128)
+    mk = lambda prec: kfbi.ThetaL(box.x0, box.y0, box.side, box.N, 64, 1e-3, 1.0, 1e-3,
+                                  precision=prec, refine=2.1, max_M=256)
+    a, b = mk(0), mk(1)
+    a.init(dev(W.hs3(64)))
+    b.init(dev(W.hs3(64)))
+    for _ in range(3):
+        ra, rb = a.step(), b.step()
+        assert (ra["M"], ra["M_next"]) == (rb["M"], rb["M_next"])
+        assert rb["relres"] <= 1e-10
+    sa, sb = a.get_state(), b.get_state()
+    assert np.max(np.abs(host(sa["eta"]) - host(sb["eta"]))) <= 1e-9
