@@ -150,17 +150,20 @@ __global__ void __launch_bounds__(kRedBlock)
 // One Arnoldi step in a single workgroup (used while M (j+1) is small): CGS2 against
 // V_0..V_j, h_{j+1,j} = ||w||, the Hessenberg column with the previous Givens rotations,
 // the new rotation, g, the status word, and V_{j+1} = w / h_{j+1,j}.  All reductions are
-// fixed-order within the workgroup.
+// fixed-order within the workgroup.  When V_0..V_j fit (stage != 0) they are copied to LDS
+// once, with all loads in flight together, and both passes read them from there.
 constexpr int kArnThreads = 1024;
 constexpr int kArnPer = 4;  // elements per thread: M <= 4096
+constexpr size_t kArnStageBytes = 112 * 1024;  // LDS for the staged basis vectors (+40 KB static)
 __global__ void __launch_bounds__(kArnThreads)
     k_arnoldi(int M, int ldv, double* __restrict__ V, int j, const double* __restrict__ w,
               double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
               double* __restrict__ g, GmresStatus* __restrict__ st,
-              GmresStatus* __restrict__ hout) {
+              GmresStatus* __restrict__ hout, int stage) {
   __shared__ double red[kMaxRestart + 1][kArnThreads / 64];
   __shared__ double hv[2][kMaxRestart + 1];
   __shared__ double wsh[kArnThreads * kArnPer];
+  extern __shared__ double vsh[];  // (j+1) x M when staged
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = kArnThreads / 64;
   double wk[kArnPer];
@@ -168,6 +171,25 @@ __global__ void __launch_bounds__(kArnThreads)
   for (int u = 0; u < kArnPer; ++u) {
     const int k = tid + u * kArnThreads;
     wk[u] = (k < M) ? w[k] : 0.0;
+  }
+  if (stage) {
+    for (int i0 = 0; i0 <= j; i0 += 4) {
+      double t[4][kArnPer];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int u = 0; u < kArnPer; ++u) {
+          const int i = i0 + a, k = tid + u * kArnThreads;
+          t[a][u] = (i <= j && k < M) ? V[static_cast<size_t>(i) * ldv + k] : 0.0;
+        }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int u = 0; u < kArnPer; ++u) {
+          const int i = i0 + a, k = tid + u * kArnThreads;
+          if (i <= j && k < M) vsh[static_cast<size_t>(i) * M + k] = t[a][u];
+        }
+    }
   }
   for (int pass = 0; pass < 2; ++pass) {
     // stage w, then wavefront q takes the inner products <V_i, w> for i = q, q + 16, ...
@@ -179,7 +201,7 @@ __global__ void __launch_bounds__(kArnThreads)
     }
     __syncthreads();
     for (int i = wv; i <= j; i += NW) {
-      const double* vi = V + static_cast<size_t>(i) * ldv;
+      const double* vi = stage ? vsh + static_cast<size_t>(i) * M : V + static_cast<size_t>(i) * ldv;
       double p = 0.0;
       for (int k = lane; k < M; k += 64) p += vi[k] * wsh[k];
       p = wave_sum(p);
@@ -189,7 +211,7 @@ __global__ void __launch_bounds__(kArnThreads)
     // w -= sum_i h_i V_i
     for (int i = 0; i <= j; ++i) {
       const double hi = hv[pass][i];
-      const double* vi = V + static_cast<size_t>(i) * ldv;
+      const double* vi = stage ? vsh + static_cast<size_t>(i) * M : V + static_cast<size_t>(i) * ldv;
 #pragma unroll
       for (int u = 0; u < kArnPer; ++u) {
         const int k = tid + u * kArnThreads;
@@ -349,6 +371,13 @@ static int ensure_work(kfbi_ctx* c, int restart, GmresWork* gw) {
   KFBI_TRY(c->gcnt.ensure(sizeof(GmresStatus) * (1 + kRing) + 64));
   for (int q = 0; q < kRing; ++q)
     if (!c->gev[q]) KFBI_HIP(hipEventCreateWithFlags(&c->gev[q], hipEventDisableTiming));
+  static bool arn_lds = false;  // the attribute belongs to the kernel, set once per process
+  if (!arn_lds) {
+    KFBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_arnoldi),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 static_cast<int>(kArnStageBytes)));
+    arn_lds = true;
+  }
   KFBI_TRY(c->gw.ensure(sizeof(double) * ldv * 4));
   gw->V = c->gV.as<double>();
   gw->ldv = ldv;
@@ -436,8 +465,11 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
         GmresStatus* sj = gw->ring + (j % kRing);
         GmresStatus* hj = gw->dring + (j % kRing);  // device view of the host ring slot
         if (one_block) {
-          hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(kArnThreads), 0, s, M, gw->ldv, gw->V, j,
-                             gw->w, gw->H, gw->cs, gw->sn, gw->g, sj, hj);
+          const size_t vbytes = sizeof(double) * static_cast<size_t>(M) * (j + 1);
+          const int stage = vbytes <= kArnStageBytes ? 1 : 0;
+          hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(kArnThreads), stage ? vbytes : 0, s, M,
+                             gw->ldv, gw->V, j, gw->w, gw->H, gw->cs, gw->sn, gw->g, sj, hj,
+                             stage);
         } else {
           hipLaunchKernelGGL(k_cgs, dim3(nblk), dim3(kRedBlock), 0, s, M, gw->ldv, gw->V, j + 1,
                              gw->w, nullptr, 0, gw->part, gw->counter, gw->h1);
