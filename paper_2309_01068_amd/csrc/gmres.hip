@@ -449,14 +449,16 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
     // Iteration j is enqueued before the status of iteration j-1 is examined, so the GPU
     // always has work queued while the host waits; when j-1 turns out to be the last one,
     // iteration j was computed in vain (its Hessenberg column and g entries beyond j-1 are
-    // never used).
+    // never used).  (A lag of two iterations was measured slower: the host keeps up, and
+    // the second wasted iteration costs more than it hides.)
     const bool one_block = (M <= kArnThreads * kArnPer) &&
                            (static_cast<long long>(M) * restart <= (1 << 17));
     int m = 0;
     int launched = 0;
     const int base = *iters;  // iterations of earlier cycles (< maxit here)
     bool stop = false;
-    for (int j = 0; j <= restart && !stop; ++j) {
+    constexpr int kLag = 1;  // < kRing
+    for (int j = 0; !stop; ++j) {
       if (j < restart && base + launched < maxit) {
         double* vj = gw->V + static_cast<size_t>(j) * gw->ldv;
         double* vn = gw->V + static_cast<size_t>(j + 1) * gw->ldv;
@@ -484,9 +486,10 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
         KFBI_HIP(hipEventRecord(gw->ev[j % kRing], s));
         ++launched;
       }
-      if (j == 0) continue;
-      // examine iteration j-1
-      const int q = j - 1;
+      // examine iteration j - kLag
+      const int q = j - kLag;
+      if (q < 0) continue;
+      if (q >= launched) break;
       KFBI_HIP(hipEventSynchronize(gw->ev[q % kRing]));
       const GmresStatus& hs = gw->hring[q % kRing];
       ++*iters;
