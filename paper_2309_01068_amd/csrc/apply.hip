@@ -35,7 +35,7 @@
 namespace kfbi {
 
 constexpr int kColsPerBlock = 4;
-constexpr int kReg = 4;       // circulant outputs per thread in K1
+constexpr int kReg = 8;       // circulant outputs per thread in K1
 constexpr int kNodeBatch = 8; // nodes reduced together in K4
 constexpr int kRingNodes = 8;  // free-space box nodes per K1 block
 constexpr int kWinMax = 24;    // derivative window per K1 chunk: at most 16 + 5 markers
