@@ -39,6 +39,37 @@ __device__ __forceinline__ void post_status(GmresStatus* hout, double resid, dou
   __threadfence_system();
 }
 
+// Column j of the Hessenberg matrix, h_i = h1_i + h2_i (i <= j) and h_{j+1} = hn, rotated
+// by the previous Givens rotations (cs_i, sn_i, i < j), the new rotation j, the update of
+// g (gj = g_j on entry), and the status.  One thread; h1, h2, csh, snh are in LDS, so the
+// sequential loop over i waits on no memory round trip (H, cs, sn, g are only written).
+__device__ void hess_column(int j, const double* h1, const double* h2, double hn,
+                            const double* csh, const double* snh, double gj, double* H,
+                            double* cs, double* sn, double* g, GmresStatus* st,
+                            GmresStatus* hout) {
+  double* col = H + static_cast<size_t>(j) * (kMaxRestart + 1);
+  double a = h1[0] + h2[0];  // entry i of the column after rotations 0..i-1
+  for (int i = 0; i < j; ++i) {
+    const double b = h1[i + 1] + h2[i + 1];
+    const double c = csh[i], sv = snh[i];
+    col[i] = c * a + sv * b;
+    a = -sv * a + c * b;
+  }
+  const double den = hypot(a, hn);
+  const double c = a / den, sv = hn / den;
+  cs[j] = c;
+  sn[j] = sv;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  const double gn = -sv * gj;
+  g[j + 1] = gn;
+  g[j] = c * gj;
+  st->resid = fabs(gn);
+  st->hnext = hn;
+  st->breakdown = (hn == 0.0);
+  post_status(hout, fabs(gn), hn);
+}
+
 // Partial inner products <V_i, w> (i < nv) and optionally ||w||^2, after an optional
 // update w -= sum_i hprev_i V_i.  The last block to finish reduces the partials in block
 // order and writes out[0..nv) (and out[nv] = ||w||^2).
@@ -118,32 +149,22 @@ __global__ void __launch_bounds__(kRedBlock)
     is_last = (prev == static_cast<unsigned int>(nb - 1));
   }
   __syncthreads();
-  if (!is_last || threadIdx.x != 0) return;
+  if (!is_last) return;
+  __shared__ double hs1[kMaxRestart + 1], hs2[kMaxRestart + 1], csh[kMaxRestart], snh[kMaxRestart];
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    hs1[i] = h1[i];
+    hs2[i] = h2[i];
+    if (i < j) {
+      csh[i] = cs[i];
+      snh[i] = sn[i];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   __threadfence();
   double s = 0.0;
   for (int b = 0; b < nb; ++b) s += __builtin_nontemporal_load(&part[b]);
-  const double hn = sqrt(s);
-  const int ld = kMaxRestart + 1;
-  double* col = H + static_cast<size_t>(j) * ld;
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  col[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
-  }
-  const double den = hypot(col[j], col[j + 1]);
-  const double c = col[j] / den, sv = col[j + 1] / den;
-  cs[j] = c;
-  sn[j] = sv;
-  col[j] = den;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sv * g[j];
-  g[j] = c * g[j];
-  st->resid = fabs(g[j + 1]);
-  st->hnext = hn;
-  st->breakdown = (hn == 0.0);
-  post_status(hout, fabs(g[j + 1]), hn);
+  hess_column(j, hs1, hs2, sqrt(s), csh, snh, g[j], H, cs, sn, g, st, hout);
   *counter = 0u;
 }
 
@@ -163,9 +184,16 @@ __global__ void __launch_bounds__(kArnThreads)
   __shared__ double red[kMaxRestart + 1][kArnThreads / 64];
   __shared__ double hv[2][kMaxRestart + 1];
   __shared__ double wsh[kArnThreads * kArnPer];
+  __shared__ double csh[kMaxRestart], snh[kMaxRestart];
   extern __shared__ double vsh[];  // (j+1) x M when staged
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = kArnThreads / 64;
+  // the previous rotations and g_j, loaded now for the column update at the end
+  if (tid < j) {
+    csh[tid] = cs[tid];
+    snh[tid] = sn[tid];
+  }
+  const double gj = (tid == 0) ? g[j] : 0.0;
   double wk[kArnPer];
 #pragma unroll
   for (int u = 0; u < kArnPer; ++u) {
@@ -173,22 +201,26 @@ __global__ void __launch_bounds__(kArnThreads)
     wk[u] = (k < M) ? w[k] : 0.0;
   }
   if (stage) {
-    for (int i0 = 0; i0 <= j; i0 += 4) {
-      double t[4][kArnPer];
+    // V_0..V_j copied to LDS as one flat array of (j + 1) M values with sixteen loads in
+    // flight per thread: the vectors come from earlier launches, mostly not from this
+    // XCD's L2, so the copy is bound by memory latency
+    const int tot = (j + 1) * M;
+    constexpr int U = 16;
+    for (int e0 = tid; e0 < tot; e0 += kArnThreads * U) {
+      double t[U];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int u = 0; u < kArnPer; ++u) {
-          const int i = i0 + a, k = tid + u * kArnThreads;
-          t[a][u] = (i <= j && k < M) ? V[static_cast<size_t>(i) * ldv + k] : 0.0;
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kArnThreads;
+        if (e < tot) {
+          const int i = e / M, k = e - i * M;
+          t[u] = V[static_cast<size_t>(i) * ldv + k];
         }
+      }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int u = 0; u < kArnPer; ++u) {
-          const int i = i0 + a, k = tid + u * kArnThreads;
-          if (i <= j && k < M) vsh[static_cast<size_t>(i) * M + k] = t[a][u];
-        }
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kArnThreads;
+        if (e < tot) vsh[e] = t[u];
+      }
     }
   }
   for (int pass = 0; pass < 2; ++pass) {
@@ -229,27 +261,7 @@ __global__ void __launch_bounds__(kArnThreads)
     double s = 0.0;
     for (int q = 0; q < NW; ++q) s += red[0][q];
     const double hn = sqrt(s);
-    const int ld = kMaxRestart + 1;
-    double* col = H + static_cast<size_t>(j) * ld;
-    for (int i = 0; i <= j; ++i) col[i] = hv[0][i] + hv[1][i];
-    col[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-      col[i] = t;
-    }
-    const double den = hypot(col[j], col[j + 1]);
-    const double c = col[j] / den, sv = col[j + 1] / den;
-    cs[j] = c;
-    sn[j] = sv;
-    col[j] = den;
-    col[j + 1] = 0.0;
-    g[j + 1] = -sv * g[j];
-    g[j] = c * g[j];
-    st->resid = fabs(g[j + 1]);
-    st->hnext = hn;
-    st->breakdown = (hn == 0.0);
-    post_status(hout, fabs(g[j + 1]), hn);
+    hess_column(j, hv[0], hv[1], hn, csh, snh, gj, H, cs, sn, g, st, hout);
     red[1][0] = hn;
   }
   __syncthreads();
