@@ -284,7 +284,7 @@ __global__ void k_scale(int M, const double* __restrict__ w, const double* __res
 __global__ void __launch_bounds__(kRedBlock)
     k_residual(int M, const double* __restrict__ b, const double* __restrict__ y,
                double* __restrict__ r, double* __restrict__ part, unsigned int* __restrict__ counter,
-               GmresStatus* __restrict__ st) {
+               GmresStatus* __restrict__ st, GmresStatus* __restrict__ hout) {
   __shared__ double red[4];
   __shared__ int is_last;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,6 +311,7 @@ __global__ void __launch_bounds__(kRedBlock)
   double s = 0.0;
   for (int bb = 0; bb < nb; ++bb) s += __builtin_nontemporal_load(&part[bb]);
   st->resid = sqrt(s);
+  if (hout) post_status(hout, sqrt(s), 1.0);
   *counter = 0u;
 }
 
@@ -323,17 +324,27 @@ __global__ void k_start(int M, const double* __restrict__ r, const GmresStatus* 
   if (k <= kMaxRestart) g[k] = (k == 0) ? beta : 0.0;
 }
 
-// Back substitution H(0:m,0:m) y = g(0:m) and x += V y (y in LDS).
-__global__ void k_update_x(int M, int m, int ldv, const double* __restrict__ V,
-                           const double* __restrict__ H, const double* __restrict__ g,
-                           double* __restrict__ x) {
+// Back substitution H(0:m,0:m) y = g(0:m) and x += V y.  The triangle and g are first
+// loaded into LDS by the whole block (independent loads), so the sequential substitution
+// of thread 0 reads only LDS.
+__global__ void __launch_bounds__(256)
+    k_update_x(int M, int m, int ldv, const double* __restrict__ V,
+               const double* __restrict__ H, const double* __restrict__ g,
+               double* __restrict__ x) {
   __shared__ double y[kMaxRestart];
+  __shared__ double hs[kMaxRestart * kMaxRestart];  // column q, row i at q m + i
+  const int ld = kMaxRestart + 1;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int q = e / m, i = e - q * m;
+    hs[e] = (i <= q) ? H[static_cast<size_t>(q) * ld + i] : 0.0;
+  }
+  if (static_cast<int>(threadIdx.x) < m) y[threadIdx.x] = g[threadIdx.x];
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const int ld = kMaxRestart + 1;
     for (int i = m - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int q = i + 1; q < m; ++q) s -= H[static_cast<size_t>(q) * ld + i] * y[q];
-      y[i] = s / H[static_cast<size_t>(i) * ld + i];
+      double s = y[i];
+      for (int q = i + 1; q < m; ++q) s -= hs[q * m + i] * y[q];
+      y[i] = s / hs[i * m + i];
     }
   }
   __syncthreads();
@@ -362,9 +373,9 @@ struct GmresWork {
   double* part;
   unsigned int* counter;
   GmresStatus* st;   // status of the last reduction (residual norms)
-  GmresStatus* hst;  // pinned host copy
   GmresStatus* ring;   // per-iteration Arnoldi status, slot j % kRing (device)
-  GmresStatus* hring;  // status ring in coherent pinned host memory (host view)
+  GmresStatus* hring;  // status ring in coherent pinned host memory (host view), then the
+                       // residual slots kSlotRes, kSlotNb
   GmresStatus* dring;  // the same memory as the kernels address it
   hipEvent_t* ev;      // one event per ring slot, recorded after its copy
   double* r;
@@ -404,7 +415,6 @@ static int ensure_work(kfbi_ctx* c, int restart, GmresWork* gw) {
   gw->st = c->gcnt.as<GmresStatus>();
   gw->ring = gw->st + 1;
   gw->counter = reinterpret_cast<unsigned int*>(gw->st + 1 + kRing);
-  gw->hst = reinterpret_cast<GmresStatus*>(reinterpret_cast<char*>(c->hpin) + 1024);
   gw->hring = reinterpret_cast<GmresStatus*>(c->hstat);
   gw->dring = reinterpret_cast<GmresStatus*>(c->dstat);
   gw->ev = c->gev;
@@ -416,13 +426,12 @@ static int ensure_work(kfbi_ctx* c, int restart, GmresWork* gw) {
   return KFBI_OK;
 }
 
-static int read_status(kfbi_ctx* c, GmresWork* gw) {
-  KFBI_HIP(hipMemcpyAsync(gw->hst, gw->st, sizeof(GmresStatus), hipMemcpyDeviceToHost, c->stream));
-  KFBI_HIP(hipStreamSynchronize(c->stream));
-  return KFBI_OK;
-}
+// Host status slots after the Arnoldi ring: the last residual norm and ||b||.
+constexpr int kSlotRes = kRing, kSlotNb = kRing + 1;
 
-// ||b - A x|| with the operator at `precision`; leaves r in gw->r.
+// ||b - A x|| with the operator at `precision`; leaves r in gw->r and the norm in the
+// device status and host slot kSlotRes, and synchronises (which also makes every host
+// slot written before it readable).
 static int true_residual(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* b,
                          const double* x, GmresWork* gw, double* out, int* applies) {
   const int M = c->M;
@@ -430,25 +439,32 @@ static int true_residual(kfbi_ctx* c, const kfbi_bie* op, int precision, const d
   KFBI_TRY(apply_impl(c, op->layer, precision, x, nullptr, nullptr, op, x, gw->y));
   ++*applies;
   hipLaunchKernelGGL(k_residual, dim3(nblk), dim3(kRedBlock), 0, c->stream, M, b, gw->y, gw->r,
-                     gw->part, gw->counter, gw->st);
+                     gw->part, gw->counter, gw->st, gw->dring + kSlotRes);
   KFBI_HIP(hipGetLastError());
-  KFBI_TRY(read_status(c, gw));
-  *out = gw->hst->resid;
+  KFBI_HIP(hipStreamSynchronize(c->stream));
+  *out = gw->hring[kSlotRes].resid;
   return KFBI_OK;
 }
 
 // Restarted GMRES for A x = b with the operator at `precision`; stops when the true
 // residual (same precision) is <= tol * nb or after maxit Arnoldi steps.
+// With r_ready the residual of the incoming x is already in gw->r and the device status,
+// with norm rn0, and the first cycle starts from it.
 static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* b, double* x,
                       double nb, double tol, int restart, int maxit, GmresWork* gw, int* iters,
-                      int* cycles, int* applies, double* relres) {
+                      int* cycles, int* applies, double* relres, bool r_ready, double rn0) {
   const int M = c->M;
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   const int mb = (M + 255) / 256;
   hipStream_t s = c->stream;
   double rn = 0.0;
   for (;;) {
-    KFBI_TRY(true_residual(c, op, precision, b, x, gw, &rn, applies));
+    if (r_ready) {
+      rn = rn0;
+      r_ready = false;
+    } else {
+      KFBI_TRY(true_residual(c, op, precision, b, x, gw, &rn, applies));
+    }
     if (!std::isfinite(rn)) {
       set_error("non-finite residual in GMRES");
       return KFBI_E_NONFINITE;
@@ -549,12 +565,16 @@ extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   kfbi_gmres_stats loc{};
   KFBI_HIP(hipMemsetAsync(gw.counter, 0, sizeof(unsigned int), c->stream));
-  // ||b||
+  // ||b|| into its host slot, then the FP64 residual of the initial guess: one host
+  // synchronisation for both
   hipLaunchKernelGGL(k_residual, dim3(nblk), dim3(kRedBlock), 0, c->stream, M, b, nullptr, nullptr,
-                     gw.part, gw.counter, gw.st);
+                     gw.part, gw.counter, gw.st, gw.dring + kSlotNb);
   KFBI_HIP(hipGetLastError());
-  KFBI_TRY(read_status(c, &gw));
-  const double nb = gw.hst->resid;
+  double rn0 = 0.0;
+  int a0 = 0;
+  KFBI_TRY(true_residual(c, op, KFBI_FP64, b, x, &gw, &rn0, &a0));
+  loc.applies64 = a0;
+  const double nb = gw.hring[kSlotNb].resid;
   int status = KFBI_OK;
   if (nb == 0.0) {
     KFBI_HIP(hipMemsetAsync(x, 0, sizeof(double) * M, c->stream));
@@ -563,19 +583,23 @@ extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b
   } else if (o->precision == KFBI_FP64) {
     int applies = 0;
     status = gmres_core(c, op, KFBI_FP64, b, x, nb, o->tol, o->restart, o->maxit, &gw, &loc.iters,
-                        &loc.outer_iters, &applies, &loc.relres);
-    loc.applies64 = applies;
+                        &loc.outer_iters, &applies, &loc.relres, true, rn0);
+    loc.applies64 += applies;
     loc.converged = (status == KFBI_OK);
   } else {
     // iterative refinement: r = b - A64 x ; A32 d = r ; x += d
     const int mb = (M + 255) / 256;
     double prev = INFINITY;
+    bool first = true;
     for (;;) {
-      double rn;
-      int a64 = 0;
-      status = true_residual(c, op, KFBI_FP64, b, x, &gw, &rn, &a64);
-      loc.applies64 += a64;
-      if (status != KFBI_OK) break;
+      double rn = rn0;
+      if (!first) {
+        int a64 = 0;
+        status = true_residual(c, op, KFBI_FP64, b, x, &gw, &rn, &a64);
+        loc.applies64 += a64;
+        if (status != KFBI_OK) break;
+      }
+      first = false;
       loc.relres = rn / nb;
       if (!std::isfinite(rn)) {
         set_error("non-finite residual in refinement");
@@ -601,8 +625,11 @@ extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b
       int it_in = 0, cyc = 0, a32 = 0;
       double rel_in = 0.0;
       const double itol = o->inner_tol > 0.0 ? o->inner_tol : 1e-5;
+      // the correction starts from zero, so its first residual is r itself (still in gw.r
+      // and the device status)
       const int st_in = gmres_core(c, op, KFBI_FP32, rr, dcorr, rn, itol, o->restart,
-                                   o->maxit - loc.iters, &gw, &it_in, &cyc, &a32, &rel_in);
+                                   o->maxit - loc.iters, &gw, &it_in, &cyc, &a32, &rel_in, true,
+                                   rn);
       loc.iters += it_in;
       loc.applies32 += a32;
       if (st_in != KFBI_OK && st_in != KFBI_E_NOCONV) {
