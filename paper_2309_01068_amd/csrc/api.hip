@@ -82,8 +82,6 @@ static void release_all(kfbi_ctx* c) {
     if (c->prof_ev[i]) (void)hipEventDestroy(c->prof_ev[i]);
   for (int i = 0; i < kfbi_ctx::kGmresRing; ++i)
     if (c->gev[i]) (void)hipEventDestroy(c->gev[i]);
-  if (c->hpin) (void)hipHostFree(c->hpin);
-  c->hpin = nullptr;
   if (c->hstat) (void)hipHostFree(c->hstat);
   c->hstat = c->dstat = nullptr;
 }
@@ -187,10 +185,6 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
       hipHostGetDevicePointer(&c->dstat, c->hstat, 0) != hipSuccess) {
     c->hstat = c->dstat = nullptr;
     set_error("hipHostMalloc (coherent status ring) failed");
-    return fail(KFBI_E_NOMEM);
-  }
-  if (hipHostMalloc(&c->hpin, 4096, hipHostMallocDefault) != hipSuccess) {
-    set_error("hipHostMalloc failed");
     return fail(KFBI_E_NOMEM);
   }
   if (hipMemsetAsync(c->mqz.p, 0, c->mqz.bytes, c->stream) != hipSuccess ||

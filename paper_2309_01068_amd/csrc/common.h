@@ -73,6 +73,9 @@ struct ArmCoef {
   int pad;
 };
 
+// Byte offset of the geometry status in the context's mapped host status block.
+constexpr size_t kGeoStatusOffset = 2048;
+
 // Status words written by the geometry kernels.
 struct GeoStatus {
   int err;          // 0 or an error code (1: two crossings in a segment, 2: label mismatch,
@@ -115,9 +118,9 @@ struct kfbi_ctx {
   kfbi::DBuf gV, gH, gsc, gpart, gcnt, gw, gx, gr, gd;
   static constexpr int kGmresRing = 4;
   hipEvent_t gev[kGmresRing] = {};
-  // pinned host status
-  void* hpin = nullptr;
-  void* hstat = nullptr;  // coherent pinned host memory the Arnoldi kernels write into
+  // status words the kernels write straight into coherent pinned host memory (4 KB):
+  // the GMRES slots from offset 0 (under 1 KB), the geometry status at kGeoStatusOffset
+  void* hstat = nullptr;
   void* dstat = nullptr;  // its device address
 
   // stage profiling with HIP events (kfbi_profile)

@@ -132,10 +132,22 @@ __device__ inline void stencil_values(const double* v, int k, int M, double* cv)
   }
 }
 
-__global__ void k_count_cross(int M, const double* __restrict__ X, double x0, double y0, double h,
-                              int N, int* __restrict__ cnt) {
+// Also copies the markers xy into the context (X) and resets the status words (thread 0),
+// so that no copy precedes it.
+__global__ void k_count_cross(int M, const double* __restrict__ xy, double* __restrict__ Xc,
+                              double x0, double y0, double h, int N, int* __restrict__ cnt,
+                              GeoStatus* __restrict__ st) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
+  const double* X = xy;
+  Xc[k] = xy[k];
+  Xc[M + k] = xy[M + k];
+  if (k == 0) {
+    GeoStatus init{};
+    init.row_lo = 1 << 30;
+    init.row_hi = -1;
+    *st = init;
+  }
   for (int ax = 0; ax < 2; ++ax) {
     // ax = 0: rows y = y_j (compare y); ax = 1: columns x = x_i (compare x)
     const double* v = (ax == 0) ? X + M : X;
@@ -154,23 +166,43 @@ __global__ void k_count_cross(int M, const double* __restrict__ X, double x0, do
   }
 }
 
-// Single-block exclusive scan of n ints in place; total to *total.
-__global__ void k_scan_inplace(int n, int* __restrict__ a, int* __restrict__ total) {
+// Single-block exclusive scans in place of nseg consecutive segments of n ints; the total
+// of segment g to total[g] (when total is not null) and the scanned values also to copy_to
+// (when not null).  With hpost, total points into *st and thread 0 then writes the whole
+// status, with the new totals, to hpost (mapped host memory) at system scope.
+__global__ void k_scan_inplace(int n, int nseg, int* __restrict__ a, int* total,
+                               int* __restrict__ copy_to, const GeoStatus* st,
+                               GeoStatus* __restrict__ hpost) {
   __shared__ int scratch[17];
   const int T = blockDim.x;
   const int per = (n + T - 1) / T;
   const int b = threadIdx.x * per;
   const int e = min(n, b + per);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += a[i];
-  int tot;
-  int off = block_excl_scan(s, scratch, &tot);
-  for (int i = b; i < e; ++i) {
-    int v = a[i];
-    a[i] = off;
-    off += v;
+  int tots[2] = {0, 0};
+  for (int g = 0; g < nseg; ++g) {
+    int* ag = a + static_cast<size_t>(g) * n;
+    int s = 0;
+    for (int i = b; i < e; ++i) s += ag[i];
+    int tot;
+    int off = block_excl_scan(s, scratch, &tot);
+    for (int i = b; i < e; ++i) {
+      const int v = ag[i];
+      ag[i] = off;
+      if (copy_to) copy_to[static_cast<size_t>(g) * n + i] = off;
+      off += v;
+    }
+    if (threadIdx.x == 0 && total) total[g] = tot;
+    if (g < 2) tots[g] = tot;
+    __syncthreads();  // scratch is reused by the next segment
   }
-  if (threadIdx.x == 0 && total) *total = tot;
+  if (threadIdx.x == 0 && hpost) {
+    GeoStatus v = *st;
+    int* vf = reinterpret_cast<int*>(&v);
+    const int f0 = static_cast<int>(total - reinterpret_cast<const int*>(st));
+    for (int g = 0; g < nseg && g < 2; ++g) vf[f0 + g] = tots[g];
+    *hpost = v;
+    __threadfence_system();
+  }
 }
 
 // Safeguarded Newton for P(t) = g on [ta, tb], P the Lagrange polynomial with nodal values
@@ -507,12 +539,18 @@ __global__ void k_arm_fill(int N, double x0, double y0, double h, double c2, int
 // is arm pdesc[q].a0 + t, or an empty slot (zero coefficients) past the part's end.
 // Structure of arrays: coefR[c * cap + 16 q + t] (c = 0..10), kR[16 q + t] (first
 // stencil marker), iR = kR + cap (grid column of the arm's node), cap = 16 P.
-__global__ void k_part_soa(int P, const int4* __restrict__ pdesc, const ArmCoef* __restrict__ armc,
-                           const int* __restrict__ armpk, double* __restrict__ coefR,
-                           int* __restrict__ kR) {
+// The same launch zeroes the per-apply corrections r of every slot (nbatch copies) and
+// the nz chunk counters that k_chunk_arm_count fills next.
+__global__ void k_part_soa(int P, int cap, const int4* __restrict__ pdesc,
+                           const ArmCoef* __restrict__ armc, const int* __restrict__ armpk,
+                           double* __restrict__ coefR, int* __restrict__ kR,
+                           double* __restrict__ armr, int nbatch, int* __restrict__ cnt,
+                           int nz) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  const int cap = kArmsPerPart * P;
+  if (s < nz) cnt[s] = 0;
   if (s >= cap) return;
+  for (int b = 0; b < nbatch; ++b) armr[static_cast<size_t>(b) * cap + s] = 0.0;
+  if (P == 0) return;
   const int q = s / kArmsPerPart, t = s % kArmsPerPart;
   const int4 d = pdesc[q];
   const int a = d.y + t;
@@ -808,9 +846,6 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   const double h = c->h;
   hipStream_t s = c->stream;
   GeoStatus* st = c->gstat.as<GeoStatus>();
-  GeoStatus init{};
-  init.row_lo = 1 << 30;
-  init.row_hi = -1;
 
   KFBI_TRY(c->X.ensure(sizeof(double) * 2 * M));
   KFBI_TRY(c->geo.ensure(sizeof(double) * 6 * M));
@@ -820,25 +855,28 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   KFBI_TRY(c->ext.ensure(sizeof(double) * kExtCount * M));
   KFBI_TRY(c->mknode.ensure(sizeof(int) * 6 * M));
 
-  KFBI_HIP(hipMemcpyAsync(c->X.p, xy, sizeof(double) * 2 * M, hipMemcpyDeviceToDevice, s));
-  KFBI_HIP(hipMemcpyAsync(st, &init, sizeof(GeoStatus), hipMemcpyHostToDevice, s));
   double* d1 = c->dvec.as<double>();
   double* d2 = d1 + M;
   if (c->d_M != M) {
     hipLaunchKernelGGL(k_diffvec, dim3(nblk(M, 256)), dim3(256), 0, s, M, d1, d2);
     c->d_M = M;
   }
+  // crossing counts per marker interval (this launch also copies the markers into X and
+  // resets the status), the marker geometry with the margin test, and the two scans,
+  // which post the status to mapped host memory for the host to size the crossing list
+  int* cnt = c->cnt.as<int>();
+  hipLaunchKernelGGL(k_count_cross, dim3(nblk(M, 256)), dim3(256), 0, s, M, xy,
+                     c->X.as<double>(), c->x0, c->y0, h, N, cnt, st);
   const double mg = 3.0 * h;
   hipLaunchKernelGGL(k_marker_geo, dim3(M), dim3(256), 0, s, M, c->X.as<double>(), d1,
                      d2, c->geo.as<double>(), c->x0 + mg, c->x0 + c->side - mg, c->y0 + mg,
                      c->y0 + c->side - mg, st);
-  int* cnt = c->cnt.as<int>();
-  hipLaunchKernelGGL(k_count_cross, dim3(nblk(M, 256)), dim3(256), 0, s, M, c->X.as<double>(),
-                     c->x0, c->y0, h, N, cnt);
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, M, cnt, &st->n_cross_h);
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, M, cnt + M, &st->n_cross_v);
-  GeoStatus* hs = static_cast<GeoStatus*>(c->hpin);
-  KFBI_HIP(hipMemcpyAsync(hs, st, sizeof(GeoStatus), hipMemcpyDeviceToHost, s));
+  GeoStatus* hs = reinterpret_cast<GeoStatus*>(static_cast<char*>(c->hstat) + kGeoStatusOffset);
+  GeoStatus* hs_dev =
+      reinterpret_cast<GeoStatus*>(static_cast<char*>(c->dstat) + kGeoStatusOffset);
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, M, 2, cnt, &st->n_cross_h,
+                     nullptr, st, hs_dev);
+  KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipStreamSynchronize(s));
   if (hs->err == 3) {
     set_error("interface marker closer than 3h to the box boundary");
@@ -879,7 +917,8 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   }
   // arms
   hipLaunchKernelGGL(k_arm_rowcount, dim3(N - 1), dim3(256), 0, s, N, lab, hid, vid, rowoff, st);
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, rowoff, &st->n_arms);
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, 1, rowoff, &st->n_arms,
+                     nullptr, nullptr, nullptr);
   hipLaunchKernelGGL(k_arm_fill, dim3(N - 1), dim3(256), 0, s, N, c->x0, c->y0, h, c->c2, M, lab,
                      hid, vid, rowoff, cr, c->geo.as<double>(), c->armpk.as<int>(),
                      c->armcoef.as<ArmCoef>(), st);
@@ -904,9 +943,9 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   // row parts of the row transform (counted here so that one read of the status gives them)
   int* rowpart = c->rowpart.as<int>();
   hipLaunchKernelGGL(k_part_count, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart);
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, rowpart, &st->n_parts);
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, 1, rowpart, &st->n_parts,
+                     nullptr, st, hs_dev);
   KFBI_HIP(hipGetLastError());
-  KFBI_HIP(hipMemcpyAsync(hs, st, sizeof(GeoStatus), hipMemcpyDeviceToHost, s));
   KFBI_HIP(hipStreamSynchronize(s));
   if (hs->err != 0) {
     static const char* msg[] = {"", "a grid segment is cut twice by the interface",
@@ -925,30 +964,29 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
                             c->max_batch));
     hipLaunchKernelGGL(k_part_fill, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart,
                        c->pdesc.as<int4>());
-    // part-slot arm coefficients for the row transform kernel
+    // part-slot arm coefficients for the row transform kernel; the same launch zeroes the
+    // per-apply corrections r (one copy per density of a batch; empty slots stay zero)
+    // and the marker-chunk counters
     const int cap = kArmsPerPart * (P > 0 ? P : 1);
     KFBI_TRY(c->armc.ensure(sizeof(double) * kArmCoefCount * cap));
     KFBI_TRY(c->armk.ensure(sizeof(int) * 2 * cap));
-    c->arm_cap = cap;
-    if (P > 0)
-      hipLaunchKernelGGL(k_part_soa, dim3(nblk(cap, 256)), dim3(256), 0, s, P,
-                         c->pdesc.as<int4>(), c->armcoef.as<ArmCoef>(), c->armpk.as<int>(),
-                         c->armc.as<double>(), c->armk.as<int>());
-    // per-apply corrections r (zero in empty slots) and the marker-chunk lists of slots
-    // (one copy per density of a batch)
     KFBI_TRY(c->armr.ensure(sizeof(double) * cap * c->max_batch));
-    KFBI_HIP(hipMemsetAsync(c->armr.p, 0, sizeof(double) * cap * c->max_batch, s));
+    c->arm_cap = cap;
     const int nmk = c->n_mk_blocks;
     KFBI_TRY(c->ckoff.ensure(sizeof(int) * (2 * nmk + 2)));
     KFBI_TRY(c->cklist.ensure(sizeof(int) * cap));
     int* ckoff = c->ckoff.as<int>();
     int* ckcur = ckoff + nmk + 1;
-    KFBI_HIP(hipMemsetAsync(ckoff, 0, sizeof(int) * (nmk + 1), s));
+    hipLaunchKernelGGL(k_part_soa, dim3(nblk(cap > nmk + 1 ? cap : nmk + 1, 256)), dim3(256), 0,
+                       s, P, cap, c->pdesc.as<int4>(), c->armcoef.as<ArmCoef>(),
+                       c->armpk.as<int>(), c->armc.as<double>(), c->armk.as<int>(),
+                       c->armr.as<double>(), c->max_batch, ckoff, nmk + 1);
     if (P > 0)
       hipLaunchKernelGGL(k_chunk_arm_count, dim3(nblk(cap, 256)), dim3(256), 0, s, cap,
                          c->mk_chunk, c->armk.as<int>(), ckoff);
-    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, nmk + 1, ckoff, nullptr);
-    KFBI_HIP(hipMemcpyAsync(ckcur, ckoff, sizeof(int) * nmk, hipMemcpyDeviceToDevice, s));
+    // chunk offsets, and a copy of them as the fill cursors
+    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, nmk + 1, 1, ckoff, nullptr,
+                       ckcur, nullptr, nullptr);
     if (P > 0)
       hipLaunchKernelGGL(k_chunk_arm_fill, dim3(nblk(cap, 256)), dim3(256), 0, s, cap,
                          c->mk_chunk, c->armk.as<int>(), ckcur, c->cklist.as<int>());
