@@ -163,7 +163,13 @@ __global__ void __launch_bounds__(256)
 #pragma unroll 4
         for (int q = q0; q < q1; ++q) {
           const double dx = cx[q] - zx, dy = cy[q] - zy;
-          acc += (dx * ca[q] - dy * cb[q]) / (dx * dx + dy * dy);
+          // 1 / |d|^2 from the hardware reciprocal and two Newton steps (|d| >= 3h, far
+          // from the under- and overflow range), cheaper than the division sequence
+          const double d2 = dx * dx + dy * dy;
+          double rc = __builtin_amdgcn_rcp(d2);
+          rc = fma(fma(-d2, rc, 1.0), rc, rc);
+          rc = fma(fma(-d2, rc, 1.0), rc, rc);
+          acc += (dx * ca[q] - dy * cb[q]) * rc;
         }
       } else {
 #pragma unroll 4
@@ -1313,7 +1319,11 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
   float* ring32 = reinterpret_cast<float*>(ring64 + 4 * (N + 1));
   const int C = c->mk_chunk, nmk = c->n_mk_blocks;
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
-  const size_t lds = sizeof(double) * ((1 + nd) * (lpad(M - 1) + 1) + 256 * kReg);  // covers block_sum too
+  // marker blocks: the staged marker arrays, the partial sums (4 x 16 x kReg, also the
+  // block_sum scratch) and the window quantities; ring blocks: four chunks of 256 markers
+  const size_t lds_mk = static_cast<size_t>((1 + nd) * (lpad(M - 1) + 1) + 4 * 16 * kReg +
+                                            5 * kWinMax);
+  const size_t lds = sizeof(double) * (lds_mk > 4 * 256 ? lds_mk : 4 * 256);
   allow_dyn_lds(k_prep, lds);
   if (stages & 1)
     hipLaunchKernelGGL(k_prep, dim3(nmk + nring, B), dim3(256), lds, s, M, C, nmk, layer, dens,
