@@ -221,7 +221,7 @@ int kfbi_set_interface(kfbi_ctx* c, int M, const double* xy) {
   c->last_layer = -1;
   // markers per derivative / interpolation chunk; at most 16 (M <= 4096), so a chunk has
   // at most 96 stencil nodes, which the interpolation kernel keeps two per lane
-  c->mk_chunk = M >= 1024 ? M / 256 : 4;
+  c->mk_chunk = M >= 512 ? M / 256 : 1;
   c->n_mk_blocks = (M + c->mk_chunk - 1) / c->mk_chunk;
   const int st = geometry_setup(c, M, xy);
   if (st != KFBI_OK) return st;
