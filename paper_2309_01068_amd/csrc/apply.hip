@@ -85,6 +85,13 @@ __host__ __device__ __forceinline__ int lpad(int m) { return m + (m >> 5); }
 __device__ __forceinline__ size_t grp_index(int p, int r, int nrows) {
   return (static_cast<size_t>((p - 1) >> 2) * nrows + r) * 4 + ((p - 1) & 3);
 }
+// Element (mode slot q, row r) of a solve output: row-major with row stride ldr when
+// ldr > 0 (the band of rows that the node kernel reads: a lane-consecutive run of modes is
+// then one contiguous piece of a row), else the column-group layout of nrows rows
+// (full fields).  q = p - 1 for the sine modes p = 1..n, q = p for the cosine modes.
+__device__ __forceinline__ size_t band_index(int q, int r, int nrows, int ldr) {
+  return ldr > 0 ? static_cast<size_t>(r) * ldr + q : grp_index(q + 1, r, nrows);
+}
 
 // ---------------------------------------------------------------------------------- K1
 // Marker-chunk blocks [0, nmk): derivatives at markers k0..k1-1 with phi, d1, d2 staged
@@ -481,7 +488,7 @@ __global__ void __launch_bounds__(256)
                const T* __restrict__ sinTg, const T* __restrict__ ring,
                const double* __restrict__ colc, const double* __restrict__ lanef, int jlo,
                int jhi, T* __restrict__ Gg, int nblk_x, size_t tstride, size_t rstride,
-               size_t gstride) {
+               size_t gstride, int ldr) {
   __shared__ T col[kColsPerBlock][64 * (E + 1)];
   extern __shared__ double dynp[];  // the group's P part rows, 4 modes each
   T* tp = reinterpret_cast<T*>(dynp);
@@ -661,12 +668,11 @@ __global__ void __launch_bounds__(256)
     for (int e = 0; e < E; ++e) col[w][lane * (E + 1) + e] = y[e];
   }
   __syncthreads();
-  // rows jlo..jhi of G, column-group-major: this block's rows are contiguous
+  // rows jlo..jhi of G (band_index layout)
   const int nb = jhi - jlo + 1;
-  T* dst = Gg + static_cast<size_t>(grp) * nb * 4;
   for (int e = tid; e < 4 * nb; e += 256) {
     const int r = e >> 2, c = e & 3;
-    dst[e] = (p0 + c <= n) ? col[c][slot<E>(jlo + r)] : T(0);
+    Gg[band_index(p0 - 1 + c, r, nb, ldr)] = (p0 + c <= n) ? col[c][slot<E>(jlo + r)] : T(0);
   }
 }
 
@@ -717,7 +723,8 @@ __global__ void __launch_bounds__(256)
                    const int* __restrict__ rowpart, const T* __restrict__ Fa,
                    const T* __restrict__ Fb, double ca, double cb,
                    const double* __restrict__ colc, const double* __restrict__ lanef, int jlo,
-                   int jhi, T* __restrict__ Gg, int nblk_x, size_t tstride, size_t gstride) {
+                   int jhi, T* __restrict__ Gg, int nblk_x, size_t tstride, size_t gstride,
+                   int ldr) {
   __shared__ T col[kColsPerBlock][64 * (E + 1)];
   extern __shared__ double dynp[];  // the group's P part rows, 4 modes each
   T* tp = reinterpret_cast<T*>(dynp);
@@ -863,12 +870,11 @@ __global__ void __launch_bounds__(256)
     for (int e = 0; e < E; ++e) col[w][lane * (E + 1) + e] = y[e];
   }
   __syncthreads();
-  // rows jlo..jhi, column-group-major: this block's rows are contiguous
+  // rows jlo..jhi (band_index layout)
   const int nb = jhi - jlo + 1;
-  T* dst = Gg + static_cast<size_t>(grp) * nb * 4;
   for (int e = tid; e < 4 * nb; e += 256) {
     const int r = e >> 2, c = e & 3;
-    dst[e] = (m0 + c <= N) ? col[c][slot0<E>(jlo + r)] : T(0);
+    Gg[band_index(m0 + c, r, nb, ldr)] = (m0 + c <= N) ? col[c][slot0<E>(jlo + r)] : T(0);
   }
 }
 
@@ -916,7 +922,7 @@ __global__ void __launch_bounds__(256)
                     double* __restrict__ vm_out, double* __restrict__ dnp_out,
                     double* __restrict__ dnm_out, int side, double oa, double ob, double oq,
                     const double* __restrict__ xop, double* __restrict__ yop, size_t gstride,
-                    const double* __restrict__ amk) {
+                    const double* __restrict__ amk, int ldr) {
   extern __shared__ double nval[];  // 6 * MC node values
   {  // density blockIdx.y of a batch
     const size_t bd = blockIdx.y;
@@ -972,6 +978,11 @@ __global__ void __launch_bounds__(256)
   const int per = (nn + 3) / 4;
   const int qb = w * per, qe = min(nn, qb + per);
   int curj = -1;
+  // distance between groups of four mode slots: 4 in a row-major band, 4 nbr in the
+  // column-group layout
+  const size_t g_grp = ldr > 0 ? 4 : 4 * static_cast<size_t>(nbr);
+  const size_t g_lane = static_cast<size_t>(lane >> 2) * g_grp + (lane & 3);
+  const size_t g_step = 16 * g_grp;
   T gv[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) gv[e] = T(0);
@@ -984,15 +995,19 @@ __global__ void __launch_bounds__(256)
       const int key = (q < qe) ? kq : -1;
       const int i = key & 0xffff, j = key >> 16;
       if (key >= 0 && j != curj) {  // wave-uniform branch
+        // mode slot lane + 64 e of row j: one base per lane, a fixed step per e
+        // (band_index with q >> 2 = (lane >> 2) + 16 e and q & 3 = lane & 3)
+        const T* Gr = G + (ldr > 0 ? static_cast<size_t>(j - jlo) * ldr
+                                   : 4 * static_cast<size_t>(j - jlo)) + g_lane;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           if constexpr (COSB) {
             const int pp = lane + 64 * e;
             const T wgt = (pp == 0 || pp == N) ? T(0.5) : T(1);
-            gv[e] = (pp <= N) ? wgt * G[grp_index(pp + 1, j - jlo, nbr)] : T(0);
+            gv[e] = (pp <= N) ? wgt * Gr[e * g_step] : T(0);
           } else {
             const int pp = 1 + lane + 64 * e;
-            gv[e] = (pp <= n) ? G[grp_index(pp, j - jlo, nbr)] : T(0);
+            gv[e] = (pp <= n) ? Gr[e * g_step] : T(0);
           }
         }
         curj = j;
@@ -1179,6 +1194,9 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   constexpr int PT = (64 * E + 255) / 256;
   const size_t tstride = 4 * static_cast<size_t>((n + 3) / 4) * (P + 1);
   const size_t gstride = static_cast<size_t>(n) * N;
+  // band rows row-major (row stride: the modes rounded up to whole groups of four, so a
+  // band fits where the column-group one did); the full grid keeps the column groups
+  const int ldr = full ? 0 : 4 * ((n + 3) / 4);
   if (P > 0 && (stages & 2))
     hipLaunchKernelGGL((k_rowdst<T, PT, false>), dim3(P, B), dim3(256), 0, s, N, P, c->pdesc.as<int4>(),
                        c->armr.as<double>(), c->armk.as<int>() + c->arm_cap, sinT, Tg, tstride);
@@ -1190,7 +1208,7 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   if (stages & 4)
     hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P, Tg,
                        c->rowpart.as<int>(), sinT, ring, c->colc.as<double>(),
-                       c->lanef.as<double>(), jlo, jhi, G, nb, tstride, rstride, gstride);
+                       c->lanef.as<double>(), jlo, jhi, G, nb, tstride, rstride, gstride, ldr);
   if (ev) hipEventRecord(ev[3], s);
   const int nbr = jhi - jlo + 1;
   if (full) {  // single density only
@@ -1210,7 +1228,7 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
                        c->n_mk_blocks, out ? out->v_plus : nullptr,
                        out ? out->v_minus : nullptr, out ? out->dn_plus : nullptr,
                        out ? out->dn_minus : nullptr, side, oa, ob, oq, xop, yop, gstride,
-                       op ? op->a_marker : nullptr);
+                       op ? op->a_marker : nullptr, ldr);
 }
 
 // Grid stages of the zero-normal-derivative box: cosine row transform of the arm parts
@@ -1229,7 +1247,7 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
                                    T* G, bool full, double* grid, hipEvent_t* ev,
                                    const kfbi_out* out, const kfbi_bie* op, const double* xop,
                                    double* yop, int stages, const NeuRhs& rr,
-                                   const double* mqv) {
+                                   const double* mqv, int ldr) {
   const int N = c->N, M = c->M, nm = N + 1;
   const int P = rr.parts ? c->st.n_parts : 0;
   hipStream_t s = c->stream;
@@ -1249,7 +1267,7 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
     hipLaunchKernelGGL((k_colsolve_neu<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P,
                        Tg, c->rowpart.as<int>(), static_cast<const T*>(rr.Fa),
                        static_cast<const T*>(rr.Fb), rr.ca, rr.cb, c->colc.as<double>(),
-                       c->lanef.as<double>(), jlo, jhi, G, nb, tstride, gstride);
+                       c->lanef.as<double>(), jlo, jhi, G, nb, tstride, gstride, ldr);
   if (ev) hipEventRecord(ev[3], s);
   const int nbr = jhi - jlo + 1;
   if (full)  // single density, all rows
@@ -1266,7 +1284,7 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
                        c->ext.as<double>(), c->qpart.as<double>(), c->n_mk_blocks,
                        out ? out->v_plus : nullptr, out ? out->v_minus : nullptr,
                        out ? out->dn_plus : nullptr, out ? out->dn_minus : nullptr, side, oa, ob,
-                       oq, xop, yop, gstride, op ? op->a_marker : nullptr);
+                       oq, xop, yop, gstride, op ? op->a_marker : nullptr, ldr);
 }
 
 // Dispatch on E = ceil((N+1)/64) for N = 64 .. 2048.
@@ -1355,9 +1373,11 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
     const int jhi = full ? N : c->st.row_hi;
     const NeuRhs rr;
     neu_dispatch<T>(N, [&](auto EC) {
-      launch_grid_stages_neu<T, decltype(EC)::value>(c, B, sinT, jlo, jhi, Tg, G, full, grid, ev,
-                                                     out, op, xop, yop, stages, rr,
-                                                     c->mq.as<double>());
+      // band rows row-major (stride: the N + 1 modes rounded up to whole groups of four);
+      // the full grid keeps the column groups
+      launch_grid_stages_neu<T, decltype(EC)::value>(
+          c, B, sinT, jlo, jhi, Tg, G, full, grid, ev, out, op, xop, yop, stages, rr,
+          c->mq.as<double>(), full ? 0 : 4 * ((N + 4) / 4));
     });
     if (ev) hipEventRecord(ev[4], s);
     KFBI_HIP(hipGetLastError());
@@ -1459,7 +1479,7 @@ int neu_dense_solve(kfbi_ctx* c, const double* Fa, const double* Fb, double ca, 
   neu_dispatch<double>(N, [&](auto EC) {
     launch_grid_stages_neu<double, decltype(EC)::value>(
         c, 1, sinT, 0, N, c->tmat.as<double>(), Gout, false, nullptr, nullptr, nullptr, nullptr,
-        nullptr, nullptr, 4, rr, c->mq.as<double>());
+        nullptr, nullptr, 4, rr, c->mq.as<double>(), 0);
   });
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
@@ -1473,7 +1493,7 @@ int neu_interp(kfbi_ctx* c, const double* Gfull, double* vout) {
   neu_dispatch<double>(N, [&](auto EC) {
     launch_grid_stages_neu<double, decltype(EC)::value>(
         c, 1, sinT, 0, N, c->tmat.as<double>(), const_cast<double*>(Gfull), false, nullptr,
-        nullptr, &o, nullptr, nullptr, nullptr, 8, rr, c->mqz.as<double>());
+        nullptr, &o, nullptr, nullptr, nullptr, 8, rr, c->mqz.as<double>(), 0);
   });
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
@@ -1492,7 +1512,7 @@ int neu_apply_full(kfbi_ctx* c, int layer, const double* dens, const double* Fa,
   neu_dispatch<double>(N, [&](auto EC) {
     launch_grid_stages_neu<double, decltype(EC)::value>(
         c, 1, sinT, 0, N, c->tmat.as<double>(), Gout, false, nullptr, nullptr, nullptr, nullptr,
-        nullptr, nullptr, 2 | 4, rr, c->mq.as<double>());
+        nullptr, nullptr, 2 | 4, rr, c->mq.as<double>(), 0);
   });
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
