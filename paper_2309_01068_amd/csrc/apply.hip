@@ -85,13 +85,10 @@ __host__ __device__ __forceinline__ int lpad(int m) { return m + (m >> 5); }
 __device__ __forceinline__ size_t grp_index(int p, int r, int nrows) {
   return (static_cast<size_t>((p - 1) >> 2) * nrows + r) * 4 + ((p - 1) & 3);
 }
-// Element (mode slot q, row r) of a solve output: row-major with row stride ldr when
+// Band layout of a solve output, element (mode slot q, row r): r ldr + q, row-major, when
 // ldr > 0 (the band of rows that the node kernel reads: a lane-consecutive run of modes is
-// then one contiguous piece of a row), else the column-group layout of nrows rows
-// (full fields).  q = p - 1 for the sine modes p = 1..n, q = p for the cosine modes.
-__device__ __forceinline__ size_t band_index(int q, int r, int nrows, int ldr) {
-  return ldr > 0 ? static_cast<size_t>(r) * ldr + q : grp_index(q + 1, r, nrows);
-}
+// then one contiguous piece of a row), else grp_index(q + 1, r, nrows), the column-group
+// layout (full fields).  q = p - 1 for the sine modes p = 1..n, q = p for the cosine modes.
 
 // ---------------------------------------------------------------------------------- K1
 // Marker-chunk blocks [0, nmk): derivatives at markers k0..k1-1 with phi, d1, d2 staged
@@ -668,11 +665,14 @@ __global__ void __launch_bounds__(256)
     for (int e = 0; e < E; ++e) col[w][lane * (E + 1) + e] = y[e];
   }
   __syncthreads();
-  // rows jlo..jhi of G (band_index layout)
+  // rows jlo..jhi of G (band layout: this group's four slots of row r start at
+  // base + r rs)
   const int nb = jhi - jlo + 1;
+  const size_t base = ldr > 0 ? 4 * static_cast<size_t>(grp) : 4 * static_cast<size_t>(grp) * nb;
+  const size_t rs = ldr > 0 ? static_cast<size_t>(ldr) : 4;
   for (int e = tid; e < 4 * nb; e += 256) {
     const int r = e >> 2, c = e & 3;
-    Gg[band_index(p0 - 1 + c, r, nb, ldr)] = (p0 + c <= n) ? col[c][slot<E>(jlo + r)] : T(0);
+    Gg[base + r * rs + c] = (p0 + c <= n) ? col[c][slot<E>(jlo + r)] : T(0);
   }
 }
 
@@ -870,11 +870,14 @@ __global__ void __launch_bounds__(256)
     for (int e = 0; e < E; ++e) col[w][lane * (E + 1) + e] = y[e];
   }
   __syncthreads();
-  // rows jlo..jhi (band_index layout)
+  // rows jlo..jhi (band layout: this group's four slots of row r start at
+  // base + r rs)
   const int nb = jhi - jlo + 1;
+  const size_t base = ldr > 0 ? 4 * static_cast<size_t>(grp) : 4 * static_cast<size_t>(grp) * nb;
+  const size_t rs = ldr > 0 ? static_cast<size_t>(ldr) : 4;
   for (int e = tid; e < 4 * nb; e += 256) {
     const int r = e >> 2, c = e & 3;
-    Gg[band_index(m0 + c, r, nb, ldr)] = (m0 + c <= N) ? col[c][slot0<E>(jlo + r)] : T(0);
+    Gg[base + r * rs + c] = (m0 + c <= N) ? col[c][slot0<E>(jlo + r)] : T(0);
   }
 }
 
@@ -996,7 +999,7 @@ __global__ void __launch_bounds__(256)
       const int i = key & 0xffff, j = key >> 16;
       if (key >= 0 && j != curj) {  // wave-uniform branch
         // mode slot lane + 64 e of row j: one base per lane, a fixed step per e
-        // (band_index with q >> 2 = (lane >> 2) + 16 e and q & 3 = lane & 3)
+        // (band layout with q >> 2 = (lane >> 2) + 16 e and q & 3 = lane & 3)
         const T* Gr = G + (ldr > 0 ? static_cast<size_t>(j - jlo) * ldr
                                    : 4 * static_cast<size_t>(j - jlo)) + g_lane;
 #pragma unroll
