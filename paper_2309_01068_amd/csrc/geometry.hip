@@ -167,12 +167,11 @@ __global__ void k_count_cross(int M, const double* __restrict__ xy, double* __re
 }
 
 // Single-block exclusive scans in place of nseg consecutive segments of n ints; the total
-// of segment g to total[g] (when total is not null) and the scanned values also to copy_to
-// (when not null).  With hpost, total points into *st and thread 0 then writes the whole
-// status, with the new totals, to hpost (mapped host memory) at system scope.
+// of segment g to total[g] (when total is not null).  With hpost, total points into *st
+// and thread 0 then writes the whole status, with the new totals, to hpost (mapped host
+// memory) at system scope.
 __global__ void k_scan_inplace(int n, int nseg, int* __restrict__ a, int* total,
-                               int* __restrict__ copy_to, const GeoStatus* st,
-                               GeoStatus* __restrict__ hpost) {
+                               const GeoStatus* st, GeoStatus* __restrict__ hpost) {
   __shared__ int scratch[17];
   const int T = blockDim.x;
   const int per = (n + T - 1) / T;
@@ -188,7 +187,6 @@ __global__ void k_scan_inplace(int n, int nseg, int* __restrict__ a, int* total,
     for (int i = b; i < e; ++i) {
       const int v = ag[i];
       ag[i] = off;
-      if (copy_to) copy_to[static_cast<size_t>(g) * n + i] = off;
       off += v;
     }
     if (threadIdx.x == 0 && total) total[g] = tot;
@@ -539,15 +537,12 @@ __global__ void k_arm_fill(int N, double x0, double y0, double h, double c2, int
 // is arm pdesc[q].a0 + t, or an empty slot (zero coefficients) past the part's end.
 // Structure of arrays: coefR[c * cap + 16 q + t] (c = 0..10), kR[16 q + t] (first
 // stencil marker), iR = kR + cap (grid column of the arm's node), cap = 16 P.
-// The same launch zeroes the per-apply corrections r of every slot (nbatch copies) and
-// the nz chunk counters that k_chunk_arm_count fills next.
+// The same launch zeroes the per-apply corrections r of every slot (nbatch copies).
 __global__ void k_part_soa(int P, int cap, const int4* __restrict__ pdesc,
                            const ArmCoef* __restrict__ armc, const int* __restrict__ armpk,
                            double* __restrict__ coefR, int* __restrict__ kR,
-                           double* __restrict__ armr, int nbatch, int* __restrict__ cnt,
-                           int nz) {
+                           double* __restrict__ armr, int nbatch) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < nz) cnt[s] = 0;
   if (s >= cap) return;
   for (int b = 0; b < nbatch; ++b) armr[static_cast<size_t>(b) * cap + s] = 0.0;
   if (P == 0) return;
@@ -571,17 +566,36 @@ __global__ void k_part_soa(int P, int cap, const int4* __restrict__ pdesc,
 }
 
 // Arm slots grouped by the marker chunk of their interval (the chunks of the derivative
-// kernel, which forms their corrections): counts, then slots from a cursor per chunk
-// (order within a chunk is free).  Empty slots (column 0) are skipped.
-__global__ void k_chunk_arm_count(int cap, int MC, const int* __restrict__ kR,
-                                  int* __restrict__ cnt) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < cap && kR[cap + s] != 0) atomicAdd(&cnt[kR[s] / MC], 1);
-}
-__global__ void k_chunk_arm_fill(int cap, int MC, const int* __restrict__ kR,
-                                 int* __restrict__ cur, int* __restrict__ list) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < cap && kR[cap + s] != 0) list[atomicAdd(&cur[kR[s] / MC], 1)] = s;
+// kernel, which forms their corrections), in one block: counts per chunk (LDS atomics),
+// their exclusive scan into off[0..nmk] (off[nmk] = total), then every slot appended to
+// its chunk's range through an LDS cursor (order within a chunk is free).  Empty slots
+// (column 0) are skipped.
+__global__ void __launch_bounds__(1024)
+    k_chunk_arms(int cap, int MC, int nmk, const int* __restrict__ kR, int* __restrict__ off,
+                 int* __restrict__ list) {
+  extern __shared__ int cur[];  // nmk + 1 counters, then cursors
+  __shared__ int scratch[17];
+  const int T = blockDim.x;
+  for (int i = threadIdx.x; i <= nmk; i += T) cur[i] = 0;
+  __syncthreads();
+  for (int a = threadIdx.x; a < cap; a += T)
+    if (kR[cap + a] != 0) atomicAdd(&cur[kR[a] / MC], 1);
+  __syncthreads();
+  const int n = nmk + 1;
+  const int per = (n + T - 1) / T;
+  const int b = threadIdx.x * per, e = min(n, b + per);
+  int sum = 0;
+  for (int i = b; i < e; ++i) sum += cur[i];
+  int o = block_excl_scan(sum, scratch, nullptr);
+  for (int i = b; i < e; ++i) {
+    const int v = cur[i];
+    off[i] = o;
+    cur[i] = o;
+    o += v;
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < cap; a += T)
+    if (kR[cap + a] != 0) list[atomicAdd(&cur[kR[a] / MC], 1)] = a;
 }
 
 // The chunk lists' arm data in list order (coefficients [kArmCoefCount][cap], and the
@@ -599,19 +613,8 @@ __global__ void k_chunk_arm_pack(int cap, int MC, const int* __restrict__ total,
   ck[e] = kR[s] % MC;
 }
 
-// Rows split into parts of at most kArmsPerPart arms: parts per row, then descriptors
-// (row, first arm, end arm) in row order after an exclusive scan.
-__global__ void k_part_count(int N, const int* __restrict__ rowoff, int* __restrict__ rowpart) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > N) return;
-  int c = 0;
-  if (j >= 1 && j <= N - 1) {
-    const int na = rowoff[j + 1] - rowoff[j];
-    c = (na + kArmsPerPart - 1) / kArmsPerPart;
-  }
-  rowpart[j] = c;
-}
-
+// Part descriptors (row, first arm, end arm) in row order, from the part offsets of
+// k_rows_scan.
 __global__ void k_part_fill(int N, const int* __restrict__ rowoff,
                             const int* __restrict__ rowpart, int4* __restrict__ pdesc) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -795,46 +798,64 @@ __global__ void k_need_rowcount(int N, const int* __restrict__ need, int* __rest
   if (threadIdx.x == 0) rowcnt[j] = static_cast<int>(t);
 }
 
-__global__ void k_rows_scan(int N, const int* __restrict__ rowcnt, int* __restrict__ nodeoff,
-                            int* __restrict__ rows, int* __restrict__ rowptr, GeoStatus* st) {
-  // single block: exclusive scans of counts and of (count > 0)
+__global__ void __launch_bounds__(1024)
+    k_rows_scan(int N, const int* __restrict__ rowcnt, int* __restrict__ nodeoff,
+                int* __restrict__ rows, int* __restrict__ rowptr,
+                const int* __restrict__ rowoff, int* __restrict__ rowpart, GeoStatus* st,
+                GeoStatus* __restrict__ hpost) {
+  // single block: exclusive scans of the node counts and of (count > 0), the band, and the
+  // row parts of the row transform (ceil(arms / kArmsPerPart) per interior row); thread 0
+  // then posts the whole status to mapped host memory at system scope
   __shared__ int scratch[17];
+  __shared__ int band[2];
   const int n1 = N + 1;
   const int T = blockDim.x;
   const int per = (n1 + T - 1) / T;
   const int b = threadIdx.x * per, e = min(n1, b + per);
-  int s = 0, f = 0;
+  if (threadIdx.x == 0) {
+    band[0] = 1 << 30;
+    band[1] = -1;
+  }
+  int s = 0, f = 0, pc = 0;
   for (int j = b; j < e; ++j) {
     s += rowcnt[j];
     f += rowcnt[j] > 0;
+    if (j >= 1 && j <= N - 1) pc += (rowoff[j + 1] - rowoff[j] + kArmsPerPart - 1) / kArmsPerPart;
   }
-  int tot_nodes, tot_rows;
+  int tot_nodes, tot_rows, tot_parts;
   int off = block_excl_scan(s, scratch, &tot_nodes);
   int roff = block_excl_scan(f, scratch, &tot_rows);
+  int poff = block_excl_scan(pc, scratch, &tot_parts);
+  int lo = 1 << 30, hi = -1;
   for (int j = b; j < e; ++j) {
     nodeoff[j] = off;
     if (rowcnt[j] > 0) {
       rows[roff] = j;
       rowptr[roff] = off;
       ++roff;
-    }
-    off += rowcnt[j];
-  }
-  if (threadIdx.x == 0) {
-    st->n_nodes = tot_nodes;
-    st->n_rows = tot_rows;
-    rowptr[tot_rows] = tot_nodes;
-  }
-  // band
-  int lo = 1 << 30, hi = -1;
-  for (int j = b; j < e; ++j)
-    if (rowcnt[j] > 0) {
       lo = min(lo, j);
       hi = max(hi, j);
     }
+    off += rowcnt[j];
+    rowpart[j] = poff;
+    if (j >= 1 && j <= N - 1) poff += (rowoff[j + 1] - rowoff[j] + kArmsPerPart - 1) / kArmsPerPart;
+  }
   if (hi >= 0) {
-    atomicMin(&st->row_lo, lo);
-    atomicMax(&st->row_hi, hi);
+    atomicMin(&band[0], lo);
+    atomicMax(&band[1], hi);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rowptr[tot_rows] = tot_nodes;
+    GeoStatus v = *st;
+    v.n_nodes = tot_nodes;
+    v.n_rows = tot_rows;
+    v.n_parts = tot_parts;
+    v.row_lo = band[0];
+    v.row_hi = band[1];
+    *st = v;
+    *hpost = v;
+    __threadfence_system();
   }
 }
 
@@ -874,8 +895,8 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   GeoStatus* hs = reinterpret_cast<GeoStatus*>(static_cast<char*>(c->hstat) + kGeoStatusOffset);
   GeoStatus* hs_dev =
       reinterpret_cast<GeoStatus*>(static_cast<char*>(c->dstat) + kGeoStatusOffset);
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, M, 2, cnt, &st->n_cross_h,
-                     nullptr, st, hs_dev);
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, M, 2, cnt, &st->n_cross_h, st,
+                     hs_dev);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipStreamSynchronize(s));
   if (hs->err == 3) {
@@ -918,7 +939,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   // arms
   hipLaunchKernelGGL(k_arm_rowcount, dim3(N - 1), dim3(256), 0, s, N, lab, hid, vid, rowoff, st);
   hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, 1, rowoff, &st->n_arms,
-                     nullptr, nullptr, nullptr);
+                     nullptr, nullptr);
   hipLaunchKernelGGL(k_arm_fill, dim3(N - 1), dim3(256), 0, s, N, c->x0, c->y0, h, c->c2, M, lab,
                      hid, vid, rowoff, cr, c->geo.as<double>(), c->armpk.as<int>(),
                      c->armcoef.as<ArmCoef>(), st);
@@ -928,9 +949,6 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
                      need, c->mknode.as<int>());
   int* rowcnt = c->rowsum.as<int>();
   hipLaunchKernelGGL(k_need_rowcount, dim3(n1), dim3(256), 0, s, N, need, rowcnt);
-  int* nodeoff = rowcnt + n1 + 1;
-  hipLaunchKernelGGL(k_rows_scan, dim3(1), dim3(1024), 0, s, N, rowcnt, nodeoff, c->rows.as<int>(),
-                     c->rowptr.as<int>(), st);
   // per-chunk node lists for the node-transform + extraction kernel
   const int MC = c->mk_chunk;
   const int nch = (M + MC - 1) / MC;
@@ -940,11 +958,11 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   hipLaunchKernelGGL(k_chunk_nodes, dim3(nch), dim3(128), sizeof(int) * 12 * MC, s, M, MC,
                      c->mknode.as<int>(), c->cnode.as<int>(), c->ccount.as<int>(),
                      c->mkloc.as<int>());
-  // row parts of the row transform (counted here so that one read of the status gives them)
+  // node offsets, needed rows, band and row parts; posts the status for the host
+  int* nodeoff = rowcnt + n1 + 1;
   int* rowpart = c->rowpart.as<int>();
-  hipLaunchKernelGGL(k_part_count, dim3(nblk(N + 1, 256)), dim3(256), 0, s, N, rowoff, rowpart);
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, 1, rowpart, &st->n_parts,
-                     nullptr, st, hs_dev);
+  hipLaunchKernelGGL(k_rows_scan, dim3(1), dim3(1024), 0, s, N, rowcnt, nodeoff, c->rows.as<int>(),
+                     c->rowptr.as<int>(), rowoff, rowpart, st, hs_dev);
   KFBI_HIP(hipGetLastError());
   KFBI_HIP(hipStreamSynchronize(s));
   if (hs->err != 0) {
@@ -966,30 +984,23 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
                        c->pdesc.as<int4>());
     // part-slot arm coefficients for the row transform kernel; the same launch zeroes the
     // per-apply corrections r (one copy per density of a batch; empty slots stay zero)
-    // and the marker-chunk counters
     const int cap = kArmsPerPart * (P > 0 ? P : 1);
     KFBI_TRY(c->armc.ensure(sizeof(double) * kArmCoefCount * cap));
     KFBI_TRY(c->armk.ensure(sizeof(int) * 2 * cap));
     KFBI_TRY(c->armr.ensure(sizeof(double) * cap * c->max_batch));
     c->arm_cap = cap;
     const int nmk = c->n_mk_blocks;
-    KFBI_TRY(c->ckoff.ensure(sizeof(int) * (2 * nmk + 2)));
+    KFBI_TRY(c->ckoff.ensure(sizeof(int) * (nmk + 1)));
     KFBI_TRY(c->cklist.ensure(sizeof(int) * cap));
     int* ckoff = c->ckoff.as<int>();
-    int* ckcur = ckoff + nmk + 1;
-    hipLaunchKernelGGL(k_part_soa, dim3(nblk(cap > nmk + 1 ? cap : nmk + 1, 256)), dim3(256), 0,
-                       s, P, cap, c->pdesc.as<int4>(), c->armcoef.as<ArmCoef>(),
-                       c->armpk.as<int>(), c->armc.as<double>(), c->armk.as<int>(),
-                       c->armr.as<double>(), c->max_batch, ckoff, nmk + 1);
-    if (P > 0)
-      hipLaunchKernelGGL(k_chunk_arm_count, dim3(nblk(cap, 256)), dim3(256), 0, s, cap,
-                         c->mk_chunk, c->armk.as<int>(), ckoff);
-    // chunk offsets, and a copy of them as the fill cursors
-    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, nmk + 1, 1, ckoff, nullptr,
-                       ckcur, nullptr, nullptr);
-    if (P > 0)
-      hipLaunchKernelGGL(k_chunk_arm_fill, dim3(nblk(cap, 256)), dim3(256), 0, s, cap,
-                         c->mk_chunk, c->armk.as<int>(), ckcur, c->cklist.as<int>());
+    hipLaunchKernelGGL(k_part_soa, dim3(nblk(cap, 256)), dim3(256), 0, s, P, cap,
+                       c->pdesc.as<int4>(), c->armcoef.as<ArmCoef>(), c->armpk.as<int>(),
+                       c->armc.as<double>(), c->armk.as<int>(), c->armr.as<double>(),
+                       c->max_batch);
+    // chunk offsets (ckoff[nmk] = number of arms) and the slots of each chunk
+    hipLaunchKernelGGL(k_chunk_arms, dim3(1), dim3(1024), sizeof(int) * (nmk + 1), s,
+                       P > 0 ? cap : 0, c->mk_chunk, nmk, c->armk.as<int>(), ckoff,
+                       c->cklist.as<int>());
     KFBI_TRY(c->ckcoef.ensure(sizeof(double) * kArmCoefCount * cap));
     KFBI_TRY(c->ckmk.ensure(sizeof(int) * cap));
     if (P > 0)
