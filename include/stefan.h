@@ -69,7 +69,10 @@ typedef struct {
   int iters, applies64, applies32;
   double relres;         /* final true FP64 relative residual of eq. bie-GT                 */
   double area, length;   /* of the interface the step was solved on                         */
-  double ms_geometry, ms_temperature, ms_gmres, ms_update;
+  double ms_geometry, ms_temperature, ms_gmres, ms_update;  /* geometry, GMRES: host
+                            wall clock (GMRES also waits for the temperature kernels queued
+                            before it); temperature (T1 and its trace) and update (T^{n+1},
+                            theta-L): GPU time between events                               */
   int M, M_next;         /* markers of the step and after it (refinement doubles M)        */
 } stefan_stats;
 

@@ -62,8 +62,10 @@ typedef struct {
 } thetaL_params;
 
 /* Per-step record (host).  area and length describe the curve at the start of the step
- * (the curve the pressure was solved on); the ms_* fields split the host wall clock of
- * the step (each part ends with a stream synchronisation). */
+ * (the curve the pressure was solved on).  ms_geometry and ms_gmres are host wall clock
+ * (each ends with a stream synchronisation); ms_apply (the velocity apply) and ms_update
+ * are GPU time between events, since the step runs them back to back without a host
+ * synchronisation. */
 typedef struct {
   int step;              /* index n of the step just taken, from 0                       */
   double t;              /* time after the step                                          */

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <new>
+#include <utility>
 
 #include "common.h"
 #include "device_util.h"
@@ -102,11 +103,14 @@ __global__ void __launch_bounds__(kTLThreads)
     k_tl_pre(int M, double sigma, double J, const double* __restrict__ tw,
              const double* __restrict__ eta, double* __restrict__ scal, double* __restrict__ X,
              double* __restrict__ rhs, double* __restrict__ aux, double* __restrict__ etahat,
-             TLMode md, double* __restrict__ amk) {
+             TLMode md, double* __restrict__ amk, const double* __restrict__ guess,
+             double* __restrict__ xw) {
   extern __shared__ double lds[];
   TLShared sh;
   sh.setup(lds, M, tw);
   const int tid = threadIdx.x;
+  if (xw)  // the GMRES initial guess into the working density
+    for (int j = tid; j < M; j += blockDim.x) xw[j] = guess[j];
   const double L = scal[S_L], xbx = scal[S_XBX], xby = scal[S_XBY];
   const double invM = 1.0 / M;
   // exp(i theta)
@@ -235,7 +239,8 @@ __global__ void __launch_bounds__(kTLThreads)
               double* __restrict__ aux, const double* __restrict__ dnp,
               const double* __restrict__ dnm, const double* __restrict__ etahat,
               double* __restrict__ nhat_prev, double* __restrict__ scal,
-              double* __restrict__ eta, const double* __restrict__ psi, int pw) {
+              double* __restrict__ eta, const double* __restrict__ psi, int pw,
+              double* __restrict__ hscal) {
   extern __shared__ double lds[];
   TLShared sh;
   sh.setup(lds, M, tw);
@@ -364,15 +369,22 @@ __global__ void __launch_bounds__(kTLThreads)
   }
   bad = __syncthreads_or(bad);
   if (tid == 0) {
-    scal[S_LPREV] = L;
-    scal[S_MPREV] = Mdot;
-    scal[S_QPX] = qx;
-    scal[S_QPY] = qy;
-    scal[S_L] = Ln;
-    scal[S_XBX] = xn;
-    scal[S_XBY] = yn;
-    scal[S_T] += tau;
-    scal[S_BAD] = (bad || !isfinite(Ln) || !(Ln > 0.0) || !isfinite(xn) || !isfinite(yn)) ? 1.0 : 0.0;
+    double v[S_COUNT];
+    for (int q = 0; q < S_COUNT; ++q) v[q] = scal[q];
+    v[S_LPREV] = L;
+    v[S_MPREV] = Mdot;
+    v[S_QPX] = qx;
+    v[S_QPY] = qy;
+    v[S_L] = Ln;
+    v[S_XBX] = xn;
+    v[S_XBY] = yn;
+    v[S_T] += tau;
+    v[S_BAD] = (bad || !isfinite(Ln) || !(Ln > 0.0) || !isfinite(xn) || !isfinite(yn)) ? 1.0 : 0.0;
+    for (int q = 0; q < S_COUNT; ++q) scal[q] = v[q];
+    if (hscal) {  // the host's copy (mapped memory), pushed out at system scope
+      for (int q = 0; q < S_COUNT; ++q) hscal[q] = v[q];
+      __threadfence_system();
+    }
   }
 }
 
@@ -632,7 +644,8 @@ int thetal_refresh(thetaL* th) {
   hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), th->stream, M,
                      th->prm.sigma, th->prm.J, th->tw.as<double>(), th->eta.as<double>(),
                      th->scal.as<double>(), th->X.as<double>(), th->rhs.as<double>(),
-                     th->aux.as<double>(), th->etahat.as<double>(), hs_mode(), nullptr);
+                     th->aux.as<double>(), th->etahat.as<double>(), hs_mode(), nullptr, nullptr,
+                     nullptr);
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
 }
@@ -680,7 +693,11 @@ static void tl_free(thetaL* th) {
                   &th->phi, &th->phi2, &th->phiw, &th->dnp, &th->dnm, &th->init})
     b->release();
   if (th->hscal) (void)hipHostFree(th->hscal);
-  th->hscal = nullptr;
+  th->hscal = th->dscal = nullptr;
+  for (hipEvent_t& e : th->tev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   if (th->kc) kfbi_destroy(th->kc);
   th->kc = nullptr;
 }
@@ -712,12 +729,22 @@ static int tl_setup(thetaL* th, const thetaL_params* p, int M, int Mcap) {
     return st;
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&th->hscal), sizeof(double) * S_COUNT,
-                    hipHostMallocDefault) != hipSuccess) {
-    th->hscal = nullptr;
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&th->dscal), th->hscal, 0) !=
+          hipSuccess) {
+    if (th->hscal) (void)hipHostFree(th->hscal);
+    th->hscal = th->dscal = nullptr;
     tl_free(th);
-    set_error("hipHostMalloc failed");
+    set_error("hipHostMalloc (coherent scalars) failed");
     return KFBI_E_NOMEM;
   }
+  for (hipEvent_t& e : th->tev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      tl_free(th);
+      set_error("hipEventCreate failed");
+      return KFBI_E_HIP;
+    }
   hipLaunchKernelGGL(k_twiddles, dim3((M / 2 + 255) / 256), dim3(256), 0, th->stream, M,
                      th->tw.as<double>());
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(th->stream) != hipSuccess) {
@@ -838,7 +865,7 @@ int thetaL_markers(thetaL* th, double* xy) {
   hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), th->stream, M,
                      th->prm.sigma, th->prm.J, th->tw.as<double>(), th->eta.as<double>(),
                      th->scal.as<double>(), xy, th->rhs.as<double>(), th->aux.as<double>(),
-                     th->etahat.as<double>(), hs_mode(), nullptr);
+                     th->etahat.as<double>(), hs_mode(), nullptr, nullptr, nullptr);
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
 }
@@ -854,48 +881,56 @@ int thetaL_density(const thetaL* th, double* phi) {
   return KFBI_OK;
 }
 
+// After a solve: phi2 <- phi, phi <- phiw (the new density), phiw <- the old phi2 buffer.
+static void tl_rotate(thetaL* th) {
+  std::swap(th->phi2, th->phi);
+  std::swap(th->phi, th->phiw);
+}
+
 int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
   KFBI_TRY(tl_check(th, true));
   const int M = th->M;
   hipStream_t s = th->stream;
   const thetaL_params& p = th->prm;
   auto t0 = std::chrono::steady_clock::now();
+  // reconstruction, right-hand side, and the GMRES initial guess (x0, else the previous
+  // density, zero before the first solve) into the working density
+  const double* guess = x0 ? x0 : th->phi.as<double>();
   hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), s, M, p.sigma, p.J,
                      th->tw.as<double>(), th->eta.as<double>(), th->scal.as<double>(),
                      th->X.as<double>(), th->rhs.as<double>(), th->aux.as<double>(),
-                     th->etahat.as<double>(), hs_mode(), nullptr);
+                     th->etahat.as<double>(), hs_mode(), nullptr, guess, th->phiw.as<double>());
   KFBI_HIP(hipGetLastError());
   int st = kfbi_set_interface(th->kc, M, th->X.as<double>());
   if (st != KFBI_OK) return st;
   const double ms_geo = ms_since(t0);
-  // GMRES: initial guess = x0, else the previous density (zero before the first solve)
   auto t1 = std::chrono::steady_clock::now();
-  const double* guess = x0 ? x0 : th->phi.as<double>();
-  KFBI_HIP(hipMemcpyAsync(th->phiw.p, guess, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
   const kfbi_bie op{KFBI_DOUBLE, KFBI_MINUS, 0.0, 1.0, 1.0, nullptr};
   kfbi_gmres_stats gs{};
   st = kfbi_gmres_solve(th->kc, &op, th->rhs.as<double>(), th->phiw.as<double>(), &p.gmres, &gs);
   if (st != KFBI_OK) return st;
   const double ms_gm = ms_since(t1);
-  auto t2 = std::chrono::steady_clock::now();
+  // the velocity apply and the update run without a host synchronisation between them;
+  // their times come from events
+  KFBI_HIP(hipEventRecord(th->tev[0], s));
   kfbi_out o{nullptr, nullptr, th->dnp.as<double>(), th->dnm.as<double>(), nullptr};
   st = kfbi_apply(th->kc, KFBI_DOUBLE, KFBI_FP64, th->phiw.as<double>(), nullptr, &o);
   if (st != KFBI_OK) return st;
-  KFBI_HIP(hipStreamSynchronize(s));
-  const double ms_ap = ms_since(t2);
-  auto t3 = std::chrono::steady_clock::now();
+  KFBI_HIP(hipEventRecord(th->tev[1], s));
   const double lam2 = p.lambda2 < 0.0 ? p.sigma : p.lambda2;
   hipLaunchKernelGGL(k_tl_post, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), s, M, p.J, p.tau,
                      lam2, th->n == 0 ? 1 : 0, th->tw.as<double>(), th->X.as<double>(),
                      th->aux.as<double>(), th->dnp.as<double>(), th->dnm.as<double>(),
                      th->etahat.as<double>(), th->nhat.as<double>(), th->scal.as<double>(),
-                     th->eta.as<double>(), nullptr, 3);
+                     th->eta.as<double>(), nullptr, 3, th->dscal);
   KFBI_HIP(hipGetLastError());
-  KFBI_HIP(hipMemcpyAsync(th->phi2.p, th->phi.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
-  KFBI_HIP(hipMemcpyAsync(th->phi.p, th->phiw.p, sizeof(double) * M, hipMemcpyDeviceToDevice, s));
-  KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, s));
+  KFBI_HIP(hipEventRecord(th->tev[2], s));
   KFBI_HIP(hipStreamSynchronize(s));
-  const double ms_up = ms_since(t3);
+  tl_rotate(th);
+  float f_ap = 0.f, f_up = 0.f;
+  KFBI_HIP(hipEventElapsedTime(&f_ap, th->tev[0], th->tev[1]));
+  KFBI_HIP(hipEventElapsedTime(&f_up, th->tev[1], th->tev[2]));
+  const double ms_ap = f_ap, ms_up = f_up;
   const int step = th->n;
   th->n += 1;
   th->have_phi = 1;
@@ -1137,7 +1172,7 @@ int stefan_init(stefan* s, int Mi, const double* xy, const double* T0, double St
     hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(th->M), hs, th->M, 0.0,
                        0.0, th->tw.as<double>(), th->eta.as<double>(), th->scal.as<double>(),
                        th->X.as<double>(), th->rhs.as<double>(), th->aux.as<double>(),
-                       th->etahat.as<double>(), s->md, s->amk.as<double>());
+                       th->etahat.as<double>(), s->md, s->amk.as<double>(), nullptr, nullptr);
     KFBI_HIP(hipGetLastError());
     KFBI_TRY(kfbi_set_interface(th->kc, th->M, th->X.as<double>()));
     hipLaunchKernelGGL(k_seed, dim3((n1sq + 255) / 256), dim3(256), 0, hs, n1sq,
@@ -1162,16 +1197,21 @@ int stefan_step(stefan* s, const double* x0, stefan_stats* stats) {
   hipStream_t hs = th->stream;
   const stefan_params& p = s->prm;
   auto t0 = std::chrono::steady_clock::now();
+  // reconstruction, eps_C kappa and eps_V, and the GMRES initial guess (x0, else the last
+  // density) into the working density
+  const double* guess = x0 ? x0 : th->phi.as<double>();
   hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), hs, M, 0.0, 0.0,
                      th->tw.as<double>(), th->eta.as<double>(), th->scal.as<double>(),
                      th->X.as<double>(), th->rhs.as<double>(), th->aux.as<double>(),
-                     th->etahat.as<double>(), s->md, s->amk.as<double>());
+                     th->etahat.as<double>(), s->md, s->amk.as<double>(), guess,
+                     th->phiw.as<double>());
   KFBI_HIP(hipGetLastError());
   int st = kfbi_set_interface(th->kc, M, th->X.as<double>());
   if (st != KFBI_OK) return st;
   const double ms_geo = ms_since(t0);
-  // T1: the five-point problem with the time-discretisation right-hand side
-  auto t1 = std::chrono::steady_clock::now();
+  // T1: the five-point problem with the time-discretisation right-hand side (timed by
+  // events; GMRES starts behind it without a host synchronisation)
+  KFBI_HIP(hipEventRecord(th->tev[0], hs));
   const double* Fa = s->That.as<double>();
   const double* Fb = nullptr;
   double ca = -1.0 / p.tau, cb = 0.0;
@@ -1185,19 +1225,16 @@ int stefan_step(stefan* s, const double* x0, stefan_stats* stats) {
   hipLaunchKernelGGL(k_axpby, dim3((M + 255) / 256), dim3(256), 0, hs, M, -1.0,
                      s->t1at.as<double>(), 1.0, th->rhs.as<double>());
   KFBI_HIP(hipGetLastError());
-  KFBI_HIP(hipStreamSynchronize(hs));
-  const double ms_t1 = ms_since(t1);
+  KFBI_HIP(hipEventRecord(th->tev[1], hs));
   // eq. bie-GT
   auto t2 = std::chrono::steady_clock::now();
-  const double* guess = x0 ? x0 : th->phi.as<double>();
-  KFBI_HIP(hipMemcpyAsync(th->phiw.p, guess, sizeof(double) * M, hipMemcpyDeviceToDevice, hs));
   const kfbi_bie op{KFBI_SINGLE, KFBI_AVG, 0.0, -1.0, 0.0, s->amk.as<double>()};
   kfbi_gmres_stats gs{};
   st = kfbi_gmres_solve(th->kc, &op, th->rhs.as<double>(), th->phiw.as<double>(), &p.gmres, &gs);
   if (st != KFBI_OK) return st;
   const double ms_gm = ms_since(t2);
   // T^{n+1} = T1 + T2, T2 = -S psi: one column solve of both right-hand sides; then theta-L
-  auto t3 = std::chrono::steady_clock::now();
+  KFBI_HIP(hipEventRecord(th->tev[2], hs));
   hipLaunchKernelGGL(k_axpby, dim3((M + 255) / 256), dim3(256), 0, hs, M, -1.0,
                      th->phiw.as<double>(), 0.0, s->neg.as<double>());
   KFBI_TRY(neu_apply_full(th->kc, KFBI_SINGLE, s->neg.as<double>(), Fa, Fb, ca, cb,
@@ -1206,16 +1243,18 @@ int stefan_step(stefan* s, const double* x0, stefan_stats* stats) {
                      s->lam, th->n == 0 ? 1 : 0, th->tw.as<double>(), th->X.as<double>(),
                      th->aux.as<double>(), th->dnp.as<double>(), th->dnm.as<double>(),
                      th->etahat.as<double>(), th->nhat.as<double>(), th->scal.as<double>(),
-                     th->eta.as<double>(), th->phiw.as<double>(), s->md.pw);
+                     th->eta.as<double>(), th->phiw.as<double>(), s->md.pw, th->dscal);
   KFBI_HIP(hipGetLastError());
-  KFBI_HIP(hipMemcpyAsync(th->phi2.p, th->phi.p, sizeof(double) * M, hipMemcpyDeviceToDevice, hs));
-  KFBI_HIP(hipMemcpyAsync(th->phi.p, th->phiw.p, sizeof(double) * M, hipMemcpyDeviceToDevice, hs));
-  KFBI_HIP(hipMemcpyAsync(th->hscal, th->scal.p, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, hs));
+  KFBI_HIP(hipEventRecord(th->tev[3], hs));
   KFBI_HIP(hipStreamSynchronize(hs));
+  tl_rotate(th);
   std::swap(s->Tprev, s->That);  // T^{n-1} <- T^n
   std::swap(s->That, s->Tnew);   // T^n <- T^{n+1}
   s->have_prev = 1;
-  const double ms_up = ms_since(t3);
+  float f_t1 = 0.f, f_up = 0.f;
+  KFBI_HIP(hipEventElapsedTime(&f_t1, th->tev[0], th->tev[1]));
+  KFBI_HIP(hipEventElapsedTime(&f_up, th->tev[2], th->tev[3]));
+  const double ms_t1 = f_t1, ms_up = f_up;
   const int step = th->n;
   th->n += 1;
   th->have_phi = 1;

@@ -23,8 +23,11 @@ struct thetaL {
   int ready = 0;       // thetaL_init or set_state done
   int have_phi = 0;    // phi_prev holds a density
   // phi: density of the last solve, phi2: of the solve before it, phiw: working copy
+  // (a step rotates the three buffers instead of copying)
   kfbi::DBuf tw, eta, scal, X, rhs, aux, etahat, nhat, phi, phi2, phiw, dnp, dnm, init;
-  double* hscal = nullptr;  // pinned copy of scal
+  double* hscal = nullptr;  // copy of scal in coherent pinned host memory
+  double* dscal = nullptr;  // its device address (the step's last kernel writes it)
+  hipEvent_t tev[4] = {};   // timing of the phases that end without a host synchronisation
 };
 
 
