@@ -482,11 +482,40 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
     const bool one_block = (M <= kArnThreads * kArnPer) &&
                            (static_cast<long long>(M) * restart <= (1 << 17));
     int m = 0;
-    int launched = 0;
+    int launched = 0, examined = 0;
     const int base = *iters;  // iterations of earlier cycles (< maxit here)
     bool stop = false;
     constexpr int kLag = 1;  // < kRing
+    double r1 = rn, r2 = -1.0;  // residual estimates of the last two examined steps
+    // reads the status of step q (the next one not yet examined) and decides whether the
+    // cycle stops there
+    auto examine = [&](int q) -> int {
+      KFBI_HIP(hipEventSynchronize(gw->ev[q % kRing]));
+      const GmresStatus& hs = gw->hring[q % kRing];
+      ++*iters;
+      ++examined;
+      m = q + 1;
+      if (!std::isfinite(hs.resid)) {
+        KFBI_HIP(hipStreamSynchronize(s));
+        set_error("non-finite Arnoldi residual");
+        return KFBI_E_NONFINITE;
+      }
+      r2 = r1;
+      r1 = hs.resid;
+      if (hs.resid <= tol * nb || hs.breakdown || *iters >= maxit || m == restart) stop = true;
+      return KFBI_OK;
+    };
     for (int j = 0; !stop; ++j) {
+      // When the step in flight (j - 1) is predicted to converge (its residual extrapolated
+      // from the last two ratios of the estimate), its status is read before step j is
+      // launched: a correct prediction then costs one host round trip instead of a step
+      // computed in vain, a wrong one costs the round trip.  The step at which the cycle
+      // stops is the same either way.
+      if (j >= 1 && examined == j - 1 && j - 1 < launched && r2 > 0.0 &&
+          r1 * (r1 / r2) <= tol * nb) {
+        KFBI_TRY(examine(j - 1));
+        if (stop) break;
+      }
       if (j < restart && base + launched < maxit) {
         double* vj = gw->V + static_cast<size_t>(j) * gw->ldv;
         double* vn = gw->V + static_cast<size_t>(j + 1) * gw->ldv;
@@ -514,20 +543,11 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
         KFBI_HIP(hipEventRecord(gw->ev[j % kRing], s));
         ++launched;
       }
-      // examine iteration j - kLag
+      // examine step j - kLag (unless the prediction above already did)
       const int q = j - kLag;
       if (q < 0) continue;
       if (q >= launched) break;
-      KFBI_HIP(hipEventSynchronize(gw->ev[q % kRing]));
-      const GmresStatus& hs = gw->hring[q % kRing];
-      ++*iters;
-      m = q + 1;
-      if (!std::isfinite(hs.resid)) {
-        KFBI_HIP(hipStreamSynchronize(s));
-        set_error("non-finite Arnoldi residual");
-        return KFBI_E_NONFINITE;
-      }
-      if (hs.resid <= tol * nb || hs.breakdown || *iters >= maxit || m == restart) stop = true;
+      if (q >= examined) KFBI_TRY(examine(q));
     }
     hipLaunchKernelGGL(k_update_x, dim3(mb), dim3(256), 0, s, M, m, gw->ldv, gw->V, gw->H, gw->g, x);
     KFBI_HIP(hipGetLastError());
