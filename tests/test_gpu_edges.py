@@ -1,0 +1,155 @@
+"""Edge cases of the GPU path against the oracle: the largest and smallest marker counts,
+marker counts that leave a ragged last chunk in the derivative / interpolation kernels,
+and GMRES with a zero right-hand side, an initial guess that already solves the system,
+and short restarts.
+
+Bars as in test_gpu_apply.py (FP64 traces within 1e-10 relative of the oracle) and
+test_gpu_gmres.py (solutions of both solvers at tol 1e-12 within 1e-10 of each other).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import geometry as G
+from oracle import kfbi as K
+from oracle.gmres import gmres
+from paper_2309_01068_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def check_apply(X, box, c2, bc, layer, dens, max_markers=None):
+    from paper_2309_01068_amd import kfbi
+    M = X.shape[1]
+    print(f"[case] N={box.N} M={M} c2={c2} box={bc} layer={layer}", flush=True)
+    ref = K.apply(G.build_geometry(X, box), layer, dens, c2, bc)
+    ctx = kfbi.Context(box.x0, box.y0, box.side, box.N, c2, bc,
+                       max_markers=max_markers or max(M, 64))
+    ctx.set_interface(dev(X))
+    out = ctx.apply(layer, dev(dens))
+    torch.cuda.synchronize()
+    for k in ("v_plus", "v_minus", "dn_plus", "dn_minus"):
+        e = rel(out[k].cpu().numpy(), getattr(ref, k))
+        print(f"  {k}: rel {e:.3e}")
+        assert e <= TOL64, (k, e)
+    return ctx, ref
+
+
+@pytest.mark.parametrize("layer", [K.SINGLE, K.DOUBLE])
+def test_max_markers_4096_on_2048_grid(layer):
+    """The largest interface the kernels take (4096 markers: 16 per chunk, 96 stencil
+    nodes per chunk) on the largest grid."""
+    check_apply(W.star(4096), W.box(-1, 1, 2048), 1000.0, K.BOX_ZERO, layer,
+                W.fourier_density(4096, seed=5), max_markers=4096)
+
+
+@pytest.mark.parametrize("layer", [K.SINGLE, K.DOUBLE])
+@pytest.mark.parametrize("bc", [K.BOX_ZERO, K.BOX_FREESPACE])
+def test_ragged_last_chunk(layer, bc):
+    """1000 markers: chunks of 3 markers, the last one holding a single marker."""
+    c2 = 1000.0 if bc == K.BOX_ZERO else 0.0
+    check_apply(W.star(1000), W.box(-1, 1, 512), c2, bc, layer,
+                W.fourier_density(1000, seed=6))
+
+
+def test_ragged_last_chunk_batched():
+    """The batched apply with the ragged chunking equals single applies bit for bit and the
+    oracle to 1e-10."""
+    from paper_2309_01068_amd import kfbi
+    X = W.star(1000)
+    box = W.box(-1, 1, 512)
+    dens = np.stack([W.fourier_density(1000, seed=s) for s in range(3)])
+    ctx = kfbi.Context(box.x0, box.y0, box.side, box.N, 1000.0, K.BOX_ZERO, max_markers=1000,
+                       max_batch=3)
+    ctx.set_interface(dev(X))
+    out = ctx.apply_batch(K.SINGLE, dev(dens))
+    torch.cuda.synchronize()
+    g = G.build_geometry(X, box)
+    for b in range(3):
+        one = ctx.apply(K.SINGLE, dev(dens[b]))
+        ref = K.apply(g, K.SINGLE, dens[b], 1000.0)
+        for k in ("v_plus", "dn_minus"):
+            assert torch.equal(out[k][b], one[k])
+            assert rel(out[k][b].cpu().numpy(), getattr(ref, k)) <= TOL64
+
+
+@pytest.mark.parametrize("layer", [K.SINGLE, K.DOUBLE])
+def test_min_markers_16(layer):
+    """The smallest interface: 16 markers on a circle of radius 0.1 (1.25 h apart)."""
+    check_apply(W.circle(16, 0.1, (0.013, -0.021)), W.box(-1, 1, 64), 0.0, K.BOX_ZERO, layer,
+                W.fourier_density(16, seed=2, kmax=7))
+
+
+def _ellipse_system():
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-1, 1, 128)
+    X = W.ellipse(256)
+    g = G.build_geometry(X, box)
+    b = np.exp(X[0]) * np.sin(X[1])
+
+    def A(x):
+        return K.operator(g, x, K.DOUBLE, K.PLUS, 0.0, 1.0, 0.0, 0.0)
+    ctx = kfbi.Context(box.x0, box.y0, box.side, box.N, 0.0, kfbi.BOX_ZERO, 256)
+    ctx.set_interface(dev(X))
+    return ctx, A, b
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gmres_zero_rhs(precision):
+    """b = 0: x = 0 whatever the initial guess, converged without an Arnoldi step."""
+    from paper_2309_01068_amd import kfbi
+    ctx, A, b = _ellipse_system()
+    x = dev(np.linspace(-1.0, 1.0, 256))
+    x, gs = ctx.gmres(dev(np.zeros(256)), x, kfbi.DOUBLE, kfbi.PLUS, 0.0, 1.0, 0.0,
+                      tol=1e-10, precision=precision)
+    print(gs)
+    assert gs["converged"] and gs["iters"] == 0
+    assert torch.count_nonzero(x).item() == 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gmres_guess_already_solves(precision):
+    """An initial guess that meets the tolerance is returned unchanged, without an
+    Arnoldi step."""
+    from paper_2309_01068_amd import kfbi
+    ctx, A, b = _ellipse_system()
+    x = torch.zeros(256, dtype=torch.float64, device="cuda")
+    x, _ = ctx.gmres(dev(b), x, kfbi.DOUBLE, kfbi.PLUS, 0.0, 1.0, 0.0, tol=1e-12)
+    x0 = x.clone()
+    x, gs = ctx.gmres(dev(b), x, kfbi.DOUBLE, kfbi.PLUS, 0.0, 1.0, 0.0, tol=1e-10,
+                      precision=precision)
+    print(gs)
+    assert gs["converged"] and gs["iters"] == 0 and gs["relres"] <= 1e-10
+    assert torch.equal(x, x0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gmres_short_restart(precision):
+    """restart = 8 (about twenty cycles, and for FP32-inner several corrections of several
+    cycles; the oracle's GMRES(8) also converges, in 163 steps, where GMRES(4) stagnates
+    near 1e-9): the FP64 answer of the oracle's GMRES at the same tolerance."""
+    from paper_2309_01068_amd import kfbi
+    ctx, A, b = _ellipse_system()
+    xr, st = gmres(A, b, tol=1e-12, restart=50)
+    x = torch.zeros(256, dtype=torch.float64, device="cuda")
+    x, gs = ctx.gmres(dev(b), x, kfbi.DOUBLE, kfbi.PLUS, 0.0, 1.0, 0.0, tol=1e-12, restart=8,
+                      precision=precision)
+    print(gs, "oracle iters (restart 50)", st.iters)
+    xg = x.cpu().numpy()
+    assert gs["converged"] and gs["relres"] <= 1e-12
+    if precision == 0:
+        assert gs["outer_iters"] >= 2
+    assert np.linalg.norm(A(xg) - b) <= 2e-12 * np.linalg.norm(b)
+    assert rel(xg, xr) <= 1e-10
