@@ -308,9 +308,9 @@ def extras(kf, W, torch, np, dev, dens, layer):
 
 
 def batched(kf, W, torch, np, dev, a):
-    """Batched apply (one launch per kernel for B densities) on the headline workload:
-    densities/s for several B, and per-kernel replay durations with the algorithmic bytes
-    of B densities (the geometry-only terms counted once)."""
+    """Batched apply on the headline workload: densities/s for several B, and per-kernel
+    replay durations of one launch with the algorithmic bytes of its densities (the
+    geometry-only terms counted once)."""
     M, N, c2 = 2048, a.N, 1000.0
     box = W.box(-1.0, 1.0, N)
     ctx = kf.Context(box.x0, box.y0, box.side, N, c2, kf.BOX_ZERO, M, max_batch=64)
@@ -331,10 +331,15 @@ def batched(kf, W, torch, np, dev, a):
         e1.record()
         torch.cuda.synchronize()
         secs = e0.elapsed_time(e1) / 1e3
-        kern = [ctx.profile_kernel(q, reps=max(10, a.reps // B)) for q in range(4)]
-        byts = algorithmic_bytes(info, N, M, 8 if a.precision == 0 else 4, batch=B)
+        # the library runs B as nl launches of nearly equal size (sub_batch at most); the
+        # replay repeats the last launch, of B // nl densities
+        nl = -(-B // info["sub_batch"])
+        lb = B // nl
+        kern = [ctx.profile_kernel(q, reps=max(10, a.reps // lb)) for q in range(4)]
+        byts = algorithmic_bytes(info, N, M, 8 if a.precision == 0 else 4, batch=lb)
         out[f"B{B}"] = {
             "densities_per_s": round(B * reps / secs, 1), "us_per_batch": round(1e6 * secs / reps, 2),
+            "launches": nl, "launch_batch": lb,
             "kernels": {STAGES[q]: {"avg_us": round(kern[q], 3), "bytes": byts[STAGES[q]],
                                     "GB_s": round(byts[STAGES[q]] / kern[q] / 1e3, 1)}
                         for q in range(4)}}

@@ -90,6 +90,10 @@ typedef struct {
   int row_lo, row_hi; /* band of grid rows written by the fast solve      */
   int n_parts;      /* row parts (at most 16 arms of one row each) of the
                        row sine transform                                */
+  int sub_batch;    /* densities per launch of kfbi_apply_batch: a larger
+                       batch runs as consecutive launches of at most this
+                       many, so that each launch's row-transform output and
+                       band stay within the last-level cache              */
 } kfbi_info;
 
 /* Outputs of one apply.  Each pointer is a device array or NULL (not computed).
@@ -140,7 +144,9 @@ int kfbi_apply(kfbi_ctx* ctx, int layer, int precision, const double* density_de
  * [B][M] (row b = density b); ring_dev [B][4(N+1)] (KFBI_BOX_USER) or NULL; the outputs
  * v_plus, v_minus, dn_plus, dn_minus are [B][M] device arrays or NULL, and out->grid must
  * be NULL.  Each result equals, bit for bit, kfbi_apply on that density alone.
- * 1 <= B <= max_batch of the context (else KFBI_E_INVALID).  Asynchronous. */
+ * 1 <= B <= max_batch of the context (else KFBI_E_INVALID).  Batches larger than
+ * kfbi_info.sub_batch run as consecutive launches of at most that many densities.
+ * Asynchronous. */
 int kfbi_apply_batch(kfbi_ctx* ctx, int layer, int precision, int B, const double* density_dev,
                      const double* ring_dev, const kfbi_out* out);
 

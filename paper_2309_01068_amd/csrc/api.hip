@@ -229,6 +229,17 @@ int kfbi_set_interface(kfbi_ctx* c, int M, const double* xy) {
   return KFBI_OK;
 }
 
+// Densities per launch of a batched apply: as many as keep the launch's row-transform
+// output (P part rows) and band (the rows the node kernel reads), FP64, within the
+// 256 MB last-level cache; at least 1, at most max_batch.
+static int sub_batch(const kfbi_ctx* c) {
+  constexpr double kSubBatchBytes = 256.0 * 1024 * 1024;
+  const double per = 8.0 * 4 * ((c->N + 4) / 4) *
+                     (c->st.n_parts + (c->st.row_hi - c->st.row_lo + 1));
+  const int sb = per > 0.0 ? static_cast<int>(kSubBatchBytes / per) : c->max_batch;
+  return sb < 1 ? 1 : (sb > c->max_batch ? c->max_batch : sb);
+}
+
 int kfbi_get_info(const kfbi_ctx* c, kfbi_info* info) {
   KFBI_TRY(check_ctx(c, true));
   if (!info) {
@@ -244,6 +255,7 @@ int kfbi_get_info(const kfbi_ctx* c, kfbi_info* info) {
   info->row_lo = c->st.row_lo;
   info->row_hi = c->st.row_hi;
   info->n_parts = c->st.n_parts;
+  info->sub_batch = sub_batch(c);
   return KFBI_OK;
 }
 
@@ -296,7 +308,21 @@ int kfbi_apply_batch(kfbi_ctx* c, int layer, int precision, int B, const double*
     set_error("ring values must be given exactly when box_bc == KFBI_BOX_USER");
     return KFBI_E_INVALID;
   }
-  return apply_impl(c, layer, precision, dens, ring, out, nullptr, nullptr, nullptr, B);
+  // consecutive launches of at most sub_batch densities, sizes as equal as possible
+  // (slices of the same arrays)
+  const int SB = sub_batch(c);
+  const int nl = (B + SB - 1) / SB;
+  const size_t M = static_cast<size_t>(c->M), R = 4 * static_cast<size_t>(c->N + 1);
+  for (int l = 0, b0 = 0; l < nl; ++l) {
+    const int nb = B / nl + (l < B % nl ? 1 : 0);
+    auto at = [&](double* p) { return p ? p + b0 * M : nullptr; };
+    const kfbi_out o{at(out->v_plus), at(out->v_minus), at(out->dn_plus), at(out->dn_minus),
+                     nullptr};
+    KFBI_TRY(apply_impl(c, layer, precision, dens + b0 * M, ring ? ring + b0 * R : nullptr, &o,
+                        nullptr, nullptr, nullptr, nb));
+    b0 += nb;
+  }
+  return KFBI_OK;
 }
 
 int kfbi_operator(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* x, double* y) {

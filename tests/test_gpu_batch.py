@@ -89,6 +89,25 @@ def test_batch_full_size(precision):
     check_batch(ctx, K.DOUBLE, D, precision, None, oracle)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_split_into_launches(precision):
+    """64 densities of the full-size star: more than one launch holds (kfbi_info.sub_batch),
+    so the batch runs as several launches of nearly equal size; every result still equals
+    the single apply bit for bit (and the oracle, FP64, for the first and last)."""
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-1, 1, 1024)
+    X = W.star(2048)
+    ctx = kfbi.Context(box.x0, box.y0, box.side, box.N, 1000.0, K.BOX_ZERO, max_markers=2048,
+                       max_batch=64)
+    ctx.set_interface(dev(X))
+    sb = ctx.info()["sub_batch"]
+    print(f"[case] batch of 64 prec={precision}, sub_batch {sb}", flush=True)
+    assert 1 <= sb < 64
+    D = densities(2048, 64, 200)
+    oracle = (G.build_geometry(X, box), 1000.0, K.BOX_ZERO) if precision == 0 else None
+    check_batch(ctx, K.SINGLE, D, precision, None, oracle)
+
+
 def test_batch_after_reinstalling_a_larger_interface():
     """The per-density workspaces follow the geometry when a new interface needs more."""
     from paper_2309_01068_amd import kfbi
