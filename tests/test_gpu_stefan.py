@@ -270,3 +270,41 @@ def test_stefan_backward_euler_second_order_ssd_parity():
         assert rel(g.density().cpu().numpy(), info.psi) <= 1e-8
         eta_g, sc = g.interface()
         assert np.max(np.abs(eta_g.cpu().numpy() - st.eta)) <= 1e-9
+
+
+def test_stefan_dendrite_fifty_steps_parity():
+    """The dendrite set-up (seed r = 0.1, backward Euler, tau = 5e-4, St = -0.5, four-fold
+    eps_C = 2e-3 (1 - 0.75 cos 4 phi), eps_V = 2e-3, third-order SSD) on a 256^2 box
+    [-1,1]^2 with 64 markers and refinement at 2.1 h, 50 steps: the GPU state against the
+    oracle after 10, 25 and 50 steps (the long-run comparison of the dendrite
+    configuration, at a size the oracle finishes in seconds).  Both solve every step to
+    1e-12, so the states differ by rounding carried through the evolution."""
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-1, 1, 256)
+    M, tau, St = 64, 5e-4, -0.5
+    eC = (2e-3, -0.75, 0.0, 4, 0.0)
+    X = W.circle(M, 0.1)
+    eta, L, Xb = T.equal_arclength_init(X, M)
+    Xr, *_ = T.reconstruct(eta, L, Xb)
+    T0 = S.seed_temperature(box, Xr, St)
+    prm = S.StefanParams(box=box, tau=tau, eC=eC, eV=ISO_V, bdf2=False, ssd=2, tol=1e-12)
+    st = S.StefanState(eta, L, Xb, T0)
+    g = kfbi.Stefan(box.x0, box.y0, box.side, box.N, M, tau, eC, ISO_V, bdf2=False, ssd=2,
+                    tol=1e-12, refine=2.1, max_M=256)
+    g.init(dev(X), dev(T0))
+    for k in range(1, 51):
+        st, info = S.stefan_step(st, prm)
+        if st.L / st.eta.size > 2.1 * box.h and 2 * st.eta.size <= 256:
+            st = S.refine(st)
+        g.step()
+        assert g.M == st.eta.size, k
+        if k in (10, 25, 50):
+            eta_g, sc = g.interface()
+            e_eta = np.max(np.abs(eta_g.cpu().numpy() - st.eta))
+            e_psi = rel(g.density().cpu().numpy(), st.psi_prev)
+            e_T = rel(g.temperature().cpu().numpy(), st.T)
+            print(f"[case] dendrite 256^2 step {k}: M {g.M} L {sc[0]:.6f} eta {e_eta:.2e} "
+                  f"psi {e_psi:.2e} T {e_T:.2e}", flush=True)
+            assert e_eta <= 1e-9 and e_psi <= 1e-8 and e_T <= 1e-8, k
+            assert abs(sc[0] - st.L) <= 1e-11 * st.L, k
+            assert np.max(np.abs(np.array(sc[1:3]) - st.Xbar)) <= 1e-11, k
