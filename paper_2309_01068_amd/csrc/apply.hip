@@ -90,6 +90,13 @@ __device__ __forceinline__ size_t grp_index(int p, int r, int nrows) {
 // then one contiguous piece of a row), else grp_index(q + 1, r, nrows), the column-group
 // layout (full fields).  q = p - 1 for the sine modes p = 1..n, q = p for the cosine modes.
 
+// LDS doubles after ph in a K1 marker block: d1 (and d2) during the circulant sums, then
+// the 256 x kReg partial sums.
+__host__ __device__ __forceinline__ int kprep_region(int M, int nd) {
+  const int r = nd * (lpad(M - 1) + 1);
+  return r > 256 * kReg ? r : 256 * kReg;
+}
+
 // ---------------------------------------------------------------------------------- K1
 // Marker-chunk blocks [0, nmk): derivatives at markers k0..k1-1 with phi, d1, d2 staged
 // in LDS; every thread accumulates kReg consecutive outputs over a slice of m with a
@@ -217,8 +224,9 @@ __global__ void __launch_bounds__(256)
   double* ph = lds;              // Mp
   double* dl1 = ph + Mp;         // Mp
   double* dl2 = dl1 + Mp;        // Mp (double layer only)
-  double* part = dl1 + nd * Mp;  // 4 waves x ngp x kReg, then the window quantities
-  double* qw = part + 4 * 16 * kReg;  // 5 x kWinMax
+  double* red = dl1;             // after the sums: the 256 x kReg partial sums
+  double* part = dl1 + kprep_region(M, nd);  // 16 x kReg window sums (and block_sum)
+  double* qw = part + 16 * kReg;  // 5 x kWinMax
   // this chunk's arm records, in list order (issued first: the record loads below depend
   // on them and then overlap the circulant sums); ckk holds the window offset k_a - k0
   // of marker k_a - 2
@@ -318,25 +326,29 @@ __global__ void __launch_bounds__(256)
       w[0] = dd[lpad(q)];
     }
   }
-  for (int off = ngp; off < 64; off <<= 1) {
+  // slices summed through LDS: the partial sums replace d1, d2; output (g, r) is then
+  // summed by T2 = 32 / ngp threads, eight slices each, and a shuffle tree over them
+  __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kReg; ++r) acc[r] += __shfl_xor(acc[r], off, 64);
-  }
-  const int lane = tid & 63, wv = tid >> 6;
-  if (lane < ngp) {
+  for (int r = 0; r < kReg; ++r) red[tid * kReg + r] = acc[r];
+  __syncthreads();
+  {
+    const int T2 = 32 / ngp;  // threads per output (ngp * kReg outputs, 256 threads)
+    const int o = tid / T2, p = tid % T2;
+    const int go = o / kReg, ro = o % kReg;
+    double sacc = 0.0;
 #pragma unroll
-    for (int r = 0; r < kReg; ++r) part[(wv * ngp + lane) * kReg + r] = acc[r];
+    for (int u = 0; u < 8; ++u) sacc += red[((p + u * T2) * ngp + go) * kReg + ro];
+    for (int off = 1; off < T2; off <<= 1) sacc += __shfl_xor(sacc, off, 64);
+    if (p == 0) part[o] = sacc;
   }
   __syncthreads();
   // window quantities Q = (Phi, Phi_a, Phi_aa, Psi, Psi_a) at markers w0 + t
   double v1 = 0.0, v2 = 0.0, vph = 0.0;
   if (tid < HW) {
     const int gr = tid / kReg, r = tid % kReg;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      v1 += part[(u * ngp + gr) * kReg + r];
-      if (nd == 2) v2 += part[(u * ngp + ngr + gr) * kReg + r];
-    }
+    v1 = part[gr * kReg + r];
+    if (nd == 2) v2 = part[(ngr + gr) * kReg + r];
     int km = w0 + tid;
     km += (km < 0) ? M : 0;
     km -= (km >= M) ? M : 0;
@@ -1340,10 +1352,10 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
   float* ring32 = reinterpret_cast<float*>(ring64 + 4 * (N + 1));
   const int C = c->mk_chunk, nmk = c->n_mk_blocks;
   const int nd = (layer == KFBI_DOUBLE) ? 2 : 1;
-  // marker blocks: the staged marker arrays, the partial sums (4 x 16 x kReg, also the
+  // marker blocks: the density, d1 (and d2) or the partial sums, the window sums (also the
   // block_sum scratch) and the window quantities; ring blocks: four chunks of 256 markers
-  const size_t lds_mk = static_cast<size_t>((1 + nd) * (lpad(M - 1) + 1) + 4 * 16 * kReg +
-                                            5 * kWinMax);
+  const size_t lds_mk = static_cast<size_t>((lpad(M - 1) + 1) + kprep_region(M, nd) +
+                                            16 * kReg + 5 * kWinMax);
   const size_t lds = sizeof(double) * (lds_mk > 4 * 256 ? lds_mk : 4 * 256);
   allow_dyn_lds(k_prep, lds);
   if (stages & 1)
