@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(256)
   // on them and then overlap the circulant sums); ckk holds the window offset k_a - k0
   // of marker k_a - 2
   const int a0 = ckoff[b], a1 = ckoff[b + 1];
-  const double wmine = (k0 + tid < k1) ? wq[k0 + tid] : 0.0;
+  const double wmine = (wq && k0 + tid < k1) ? wq[k0 + tid] : 0.0;
   for (int m0 = tid; m0 < M; m0 += 256 * 8) {
     double a[8], bb[8], cc[8];
 #pragma unroll
@@ -360,9 +360,10 @@ __global__ void __launch_bounds__(256)
     qw[3 * kWinMax + tid] = dl ? 0.0 : -vph;  // Psi = -psi for the single layer
     qw[4 * kWinMax + tid] = dl ? 0.0 : -v1;
   }
-  // trapezoid partial sum of the density
-  double qs = (k0 + tid < k1) ? ph[lpad(k0 + tid)] * wmine : 0.0;
-  for (int k = k0 + 256 + tid; k < k1; k += 256) qs += ph[lpad(k)] * wq[k];
+  // trapezoid partial sum of the density (only for an operator with a q term: wq given)
+  double qs = (wq && k0 + tid < k1) ? ph[lpad(k0 + tid)] * wmine : 0.0;
+  if (wq)
+    for (int k = k0 + 256 + tid; k < k1; k += 256) qs += ph[lpad(k)] * wq[k];
   __syncthreads();
   // arm corrections r_a = sum_m l_m sum_q coef_q Q_q(k_a - 2 + m) (Sec. 4.2.1 with the
   // App. A.1 jumps; coefficients per arm from the interface setup)
@@ -389,14 +390,14 @@ __global__ void __launch_bounds__(256)
     }
     rarm[cklist[e]] = r;
   }
-  qs = block_sum<double>(qs, part);
+  if (wq) qs = block_sum<double>(qs, part);  // block-uniform condition
   // global stores last (no barrier waits on them)
   if (tid >= 2 && tid < 2 + H) {
     const int k = w0 + tid;
 #pragma unroll
     for (int qq = 0; qq < 5; ++qq) mq[qq * M + k] = qw[qq * kWinMax + tid];
   }
-  if (tid == 0) qpart[b] = qs;
+  if (wq && tid == 0) qpart[b] = qs;
 }
 
 // ---------------------------------------------------------------------------------- K2
@@ -1361,7 +1362,9 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
   if (stages & 1)
     hipLaunchKernelGGL(k_prep, dim3(nmk + nring, B), dim3(256), lds, s, M, C, nmk, layer, dens,
                        c->dvec.as<double>(), c->dvec.as<double>() + M, c->mq.as<double>(),
-                       c->qpart.as<double>(), c->ext.as<double>() + kExtQ * M, N, c->x0, c->y0,
+                       c->qpart.as<double>(),
+                       (op && op->q != 0.0) ? c->ext.as<double>() + kExtQ * M : nullptr, N,
+                       c->x0, c->y0,
                        c->h, c->X.as<double>(), c->geo.as<double>(), ring64,
                        sizeof(T) == 4 ? ring32 : nullptr, c->ckoff.as<int>(),
                        c->cklist.as<int>(), c->ckcoef.as<double>(), c->ckmk.as<int>(),
