@@ -119,6 +119,17 @@ def measured_traffic(kname, N, precision):
         return None
 
 
+def replay_kernels(ctx, reps, rounds=5):
+    """Average duration (us) of each of the four kernels of the last apply, replayed
+    back to back (reps per kernel in all), the kernels taking turns over `rounds` rounds."""
+    per = max(2, reps // rounds)
+    tot = [0.0] * 4
+    for _ in range(rounds):
+        for q in range(4):
+            tot[q] += ctx.profile_kernel(q, reps=per)
+    return [t / rounds for t in tot]
+
+
 def time_applies(ctx, kf, dens, outs, steps, warmup, layer, precision):
     import torch
     for i in range(warmup):
@@ -177,8 +188,9 @@ def main():
     ms_per_step = 1e3 * secs / a.steps
 
     # per-kernel durations: each kernel of the last apply replayed back to back on the
-    # context stream between two HIP events (no events between the launches)
-    kern_us = [ctx.profile_kernel(q, reps=a.reps) for q in range(4)]
+    # context stream between two HIP events (no events between the launches); the four
+    # kernels take turns over several rounds, so that all of them see the same clock state
+    kern_us = replay_kernels(ctx, a.reps)
     # in-apply stage times: HIP events around every kernel of the same applies
     ctx.profile(True)
     for i in range(min(a.steps, 1024)):
@@ -335,7 +347,7 @@ def batched(kf, W, torch, np, dev, a):
         # replay repeats the last launch, of B // nl densities
         nl = -(-B // info["sub_batch"])
         lb = B // nl
-        kern = [ctx.profile_kernel(q, reps=max(10, a.reps // lb)) for q in range(4)]
+        kern = replay_kernels(ctx, max(10, a.reps // lb))
         byts = algorithmic_bytes(info, N, M, 8 if a.precision == 0 else 4, batch=lb)
         out[f"B{B}"] = {
             "densities_per_s": round(B * reps / secs, 1), "us_per_batch": round(1e6 * secs / reps, 2),

@@ -412,10 +412,10 @@ __global__ void __launch_bounds__(256)
 template <class T, int PT, bool COSB>
 __global__ void __launch_bounds__(256)
     k_rowdst(int N, int P, const int4* __restrict__ pdesc, const double* __restrict__ rslot,
-             const int* __restrict__ iR, const T* __restrict__ sinT, T* __restrict__ Tg,
-             size_t tstride) {
+             const int* __restrict__ iR, const double* __restrict__ sc,
+             const T* __restrict__ sinT, T* __restrict__ Tg, size_t tstride) {
   __shared__ T tab[sintab2_size<T>(4096)];
-  __shared__ T rr[kArmsPerPart];
+  __shared__ T rr[kArmsPerPart], ssb[kArmsPerPart], scb[kArmsPerPart];
   __shared__ int ii[kArmsPerPart];
   const int n = N - 1;
   const int mask = 2 * N - 1;
@@ -431,6 +431,8 @@ __global__ void __launch_bounds__(256)
     const int a = q * kArmsPerPart + tid;
     rr[tid] = static_cast<T>(rslot[a]);
     ii[tid] = iR[a];
+    ssb[tid] = static_cast<T>(sc[a]);        // sin(i pi / N), the recurrence step
+    scb[tid] = static_cast<T>(sc[cap + a]);  // cos(i pi / N)
   }
   const int na = d.z - d.y;
   __syncthreads();
@@ -442,9 +444,9 @@ __global__ void __launch_bounds__(256)
   for (int t = 0; t < na; ++t) {
     const int i = ii[t];
     const T r = rr[t];
-    T s, c, sb, cb;
+    T s, c;
     st2.get((p0 * i) & mask, s, c);
-    st2.get(i & mask, sb, cb);
+    const T sb = ssb[t], cb = scb[t];
     // sin((p + 1) x) = 2 cos(x) sin(p x) - sin((p - 1) x), started from sin(p0 x) and
     // sin((p0 - 1) x); over PT steps the rounding grows by at most a factor PT.  The
     // cosine obeys the same recurrence.
@@ -1215,7 +1217,8 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   const int ldr = full ? 0 : 4 * ((n + 3) / 4);
   if (P > 0 && (stages & 2))
     hipLaunchKernelGGL((k_rowdst<T, PT, false>), dim3(P, B), dim3(256), 0, s, N, P, c->pdesc.as<int4>(),
-                       c->armr.as<double>(), c->armk.as<int>() + c->arm_cap, sinT, Tg, tstride);
+                       c->armr.as<double>(), c->armk.as<int>() + c->arm_cap,
+                       c->armsc.as<double>(), sinT, Tg, tstride);
   if (ev) hipEventRecord(ev[2], s);
   const int ngrp = nblk(n, kColsPerBlock);
   const int nb = ((ngrp + 7) / 8) * 8;
@@ -1274,7 +1277,8 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
   if (P > 0 && (stages & 2))
     hipLaunchKernelGGL((k_rowdst<T, PT, true>), dim3(P, B), dim3(256), 0, s, N, P,
                        c->pdesc.as<int4>(), c->armr.as<double>(),
-                       c->armk.as<int>() + c->arm_cap, sinT, Tg, tstride);
+                       c->armk.as<int>() + c->arm_cap, c->armsc.as<double>(), sinT, Tg,
+                       tstride);
   if (ev) hipEventRecord(ev[2], s);
   const int nb = ((ngm + 7) / 8) * 8;
   const size_t lds_dyn = sizeof(T) * 4 * static_cast<size_t>(P > 0 ? P : 1);

@@ -537,14 +537,20 @@ __global__ void k_arm_fill(int N, double x0, double y0, double h, double c2, int
 // is arm pdesc[q].a0 + t, or an empty slot (zero coefficients) past the part's end.
 // Structure of arrays: coefR[c * cap + 16 q + t] (c = 0..10), kR[16 q + t] (first
 // stencil marker), iR = kR + cap (grid column of the arm's node), cap = 16 P.
-// The same launch zeroes the per-apply corrections r of every slot (nbatch copies).
+// The same launch zeroes the per-apply corrections r of every slot (nbatch copies) and
+// writes sc[s], sc[cap + s] = sin, cos (i pi / N) of the slot's column i (the step of the
+// row transform's recurrence; 0 and 1 for an empty slot), from the sine table
+// sinT[t] = sin(t pi / N), t < 2N.
 __global__ void k_part_soa(int P, int cap, const int4* __restrict__ pdesc,
                            const ArmCoef* __restrict__ armc, const int* __restrict__ armpk,
                            double* __restrict__ coefR, int* __restrict__ kR,
-                           double* __restrict__ armr, int nbatch) {
+                           double* __restrict__ armr, int nbatch, int N,
+                           const double* __restrict__ sinT, double* __restrict__ sc) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= cap) return;
   for (int b = 0; b < nbatch; ++b) armr[static_cast<size_t>(b) * cap + s] = 0.0;
+  sc[s] = 0.0;
+  sc[cap + s] = 1.0;
   if (P == 0) return;
   const int q = s / kArmsPerPart, t = s % kArmsPerPart;
   const int4 d = pdesc[q];
@@ -556,7 +562,11 @@ __global__ void k_part_soa(int P, int cap, const int4* __restrict__ pdesc,
 #pragma unroll
     for (int c = 0; c < 5; ++c) coefR[(6 + c) * cap + s] = ac.coef[c];
     kR[s] = ac.k;
-    kR[cap + s] = armpk[a] & 0xffff;
+    const int i = armpk[a] & 0xffff;
+    kR[cap + s] = i;
+    const int mask = 2 * N - 1;
+    sc[s] = sinT[i & mask];
+    sc[cap + s] = sinT[(i + N / 2) & mask];
   } else {
 #pragma unroll
     for (int c = 0; c < kArmCoefCount; ++c) coefR[c * cap + s] = 0.0;
@@ -987,6 +997,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
     const int cap = kArmsPerPart * (P > 0 ? P : 1);
     KFBI_TRY(c->armc.ensure(sizeof(double) * kArmCoefCount * cap));
     KFBI_TRY(c->armk.ensure(sizeof(int) * 2 * cap));
+    KFBI_TRY(c->armsc.ensure(sizeof(double) * 2 * cap));
     KFBI_TRY(c->armr.ensure(sizeof(double) * cap * c->max_batch));
     c->arm_cap = cap;
     const int nmk = c->n_mk_blocks;
@@ -996,7 +1007,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
     hipLaunchKernelGGL(k_part_soa, dim3(nblk(cap, 256)), dim3(256), 0, s, P, cap,
                        c->pdesc.as<int4>(), c->armcoef.as<ArmCoef>(), c->armpk.as<int>(),
                        c->armc.as<double>(), c->armk.as<int>(), c->armr.as<double>(),
-                       c->max_batch);
+                       c->max_batch, N, c->sinT.as<double>(), c->armsc.as<double>());
     // chunk offsets (ckoff[nmk] = number of arms) and the slots of each chunk
     hipLaunchKernelGGL(k_chunk_arms, dim3(1), dim3(1024), sizeof(int) * (nmk + 1), s,
                        P > 0 ? cap : 0, c->mk_chunk, nmk, c->armk.as<int>(), ckoff,
