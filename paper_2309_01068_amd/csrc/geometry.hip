@@ -479,6 +479,9 @@ __global__ void k_arm_fill(int N, double x0, double y0, double h, double c2, int
                            int* __restrict__ armpk, ArmCoef* __restrict__ armc, GeoStatus* st) {
   __shared__ int scratch[17];
   const int j = blockIdx.x + 1;
+  // a row without arms has nothing to fill (k_arm_rowcount has checked it already); the
+  // condition is the same for the whole block
+  if (rowoff[j] == rowoff[j + 1]) return;
   const int n = N - 1;
   const int T = blockDim.x;
   const int per = (n + T - 1) / T;
