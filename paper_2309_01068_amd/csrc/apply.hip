@@ -539,7 +539,7 @@ __global__ void __launch_bounds__(256)
   // the group's part rows are contiguous: P x 4 values
   {
     const T* src = Tg + static_cast<size_t>(grp) * P * 4;
-    constexpr int U = 8;
+    constexpr int U = 16;
     for (int e0 = tid; e0 < 4 * P; e0 += 256 * U) {
       T v[U];
 #pragma unroll
@@ -775,7 +775,7 @@ __global__ void __launch_bounds__(256)
   }
   if (P > 0) {
     const T* src = Tg + static_cast<size_t>(grp) * P * 4;
-    constexpr int U = 8;
+    constexpr int U = 16;
     for (int e0 = tid; e0 < 4 * P; e0 += 256 * U) {
       T v[U];
 #pragma unroll
