@@ -933,7 +933,8 @@ __global__ void k_colconst_neu(int N, double hc2, int E, double* __restrict__ co
 template <class T, int E, bool COSB>
 __global__ void __launch_bounds__(256)
     k_nodes_extract(int N, int M, int MC, int nch, const int* __restrict__ cnode,
-                    const int* __restrict__ ccount, const int* __restrict__ mkloc,
+                    const int* __restrict__ ccount, const int* __restrict__ chpos,
+                    const int* __restrict__ mkloc,
                     const T* __restrict__ sinT, int jlo, int nbr, const T* __restrict__ G,
                     const double* __restrict__ mq, const double* __restrict__ ext,
                     const double* __restrict__ qpart, int nq, double* __restrict__ vp_out,
@@ -960,13 +961,15 @@ __global__ void __launch_bounds__(256)
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   // XCD-aware order: blocks resident on one XCD (ids congruent mod 8) take consecutive
-  // marker chunks, whose stencils share grid rows, so those rows are fetched into one L2
+  // positions of the chunk list, which the interface setup orders by grid row,
+  // so an XCD's chunks share grid rows and those rows are fetched into its L2 once
   const int per_xcd = gridDim.x / 8;  // the grid is 8 per_xcd blocks
   const int bx = blockIdx.x;
-  const int ch = (bx % 8) * per_xcd + bx / 8;
-  if (ch >= nch) return;
-  const int nn = ccount[ch];
-  const int* keys = cnode + static_cast<size_t>(ch) * 6 * MC;
+  const int pos = (bx % 8) * per_xcd + bx / 8;
+  if (pos >= nch) return;
+  const int ch = chpos[pos];  // the marker chunk at this position
+  const int nn = ccount[pos];
+  const int* keys = cnode + static_cast<size_t>(pos) * 6 * MC;
   // the chunk's node keys (at most 6 MC <= 128), two per lane, loaded with the table
   const int key_lo = (lane < 6 * MC) ? keys[lane] : -1;
   const int key_hi = (64 + lane < 6 * MC) ? keys[64 + lane] : -1;
@@ -1242,7 +1245,7 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   if (stages & 8)
     hipLaunchKernelGGL((k_nodes_extract<T, E, false>), dim3(8 * nblk(nch, 8), B), dim3(256),
                        sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(),
-                       c->ccount.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G,
+                       c->ccount.as<int>(), c->chpos.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G,
                        c->mq.as<double>(), c->ext.as<double>(), c->qpart.as<double>(),
                        c->n_mk_blocks, out ? out->v_plus : nullptr,
                        out ? out->v_minus : nullptr, out ? out->dn_plus : nullptr,
@@ -1300,7 +1303,7 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
   if (stages & 8)
     hipLaunchKernelGGL((k_nodes_extract<T, E, true>), dim3(8 * nblk(nch, 8), B), dim3(256),
                        sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(),
-                       c->ccount.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G, mqv,
+                       c->ccount.as<int>(), c->chpos.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G, mqv,
                        c->ext.as<double>(), c->qpart.as<double>(), c->n_mk_blocks,
                        out ? out->v_plus : nullptr, out ? out->v_minus : nullptr,
                        out ? out->dn_plus : nullptr, out ? out->dn_minus : nullptr, side, oa, ob,

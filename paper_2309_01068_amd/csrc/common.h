@@ -110,6 +110,7 @@ struct kfbi_ctx {
   // geometry buffers
   kfbi::DBuf X, geo, dvec, cnt, cross, hid, vid, vraw, lab, armcnt, rowsum, armrow, armpk, armcoef,
       intptr, need, nodeidx, nodei, rowptr, rows, mknode, ext, gstat, armc, armk, armsc,
+      chpos,
       colc, lanef, cnode, ccount, mkloc, tmat, pdesc, rowpart, ckoff, cklist, ckcoef, ckmk, mqz;
   int arm_cap = 0;
   // per-apply buffers

@@ -639,16 +639,33 @@ __global__ void k_part_fill(int N, const int* __restrict__ rowoff,
 
 // Distinct interpolation nodes of each chunk of MC consecutive markers, sorted by (row,
 // column), and each marker's six stencil slots as indices into its chunk's list.
+//
+// The chunk list is stored in the order of the grid row of the first stencil node of each
+// chunk's first marker (ties by chunk index): chunk ch goes to position pos, whose node keys and count
+// are cnode[pos * 6 MC ...] and ccount[pos], and chpos[pos] = ch.  The node kernel hands
+// consecutive positions to one XCD, so the chunks of an XCD share grid rows.  Any order
+// gives the same results; this one only saves L2 misses.
 __global__ void k_chunk_nodes(int M, int MC, const int* __restrict__ mkkey,
                               int* __restrict__ cnode, int* __restrict__ ccount,
-                              int* __restrict__ mkloc) {
+                              int* __restrict__ chpos, int* __restrict__ mkloc) {
   extern __shared__ int keys[];  // 2 * 6 * MC: keys, first-occurrence flags
+  __shared__ int rank;
   int* first = keys + 6 * MC;
-  const int ch = blockIdx.x;
+  const int ch = blockIdx.x, nch = gridDim.x;
   const int k0 = ch * MC, k1 = min(M, k0 + MC);
   const int ns = 6 * (k1 - k0);
+  if (threadIdx.x == 0) rank = 0;
   for (int t = threadIdx.x; t < ns; t += blockDim.x) keys[t] = mkkey[6 * k0 + t];
   __syncthreads();
+  {  // position of this chunk: chunks with a lower first row, or the same row and index
+    const int v = keys[0] >> 16;
+    int r = 0;
+    for (int o = threadIdx.x; o < nch; o += blockDim.x) {
+      const int u = mkkey[6 * o * MC] >> 16;
+      r += (u < v || (u == v && o < ch)) ? 1 : 0;
+    }
+    if (r) atomicAdd(&rank, r);
+  }
   // rank-based sort with duplicates removed: a key's slot is the number of distinct keys
   // below it (ns <= 96, one thread per stencil slot)
   for (int t = threadIdx.x; t < ns; t += blockDim.x) {
@@ -665,9 +682,12 @@ __global__ void k_chunk_nodes(int M, int MC, const int* __restrict__ mkkey,
     int r = 0;
     for (int a = 0; a < ns; ++a) r += (first[a] && keys[a] < v) ? 1 : 0;
     mkloc[6 * k0 + t] = r;
-    if (first[t]) cnode[ch * 6 * MC + r] = v;
+    if (first[t]) cnode[rank * 6 * MC + r] = v;
   }
-  if (threadIdx.x == 0) ccount[ch] = nu;
+  if (threadIdx.x == 0) {
+    ccount[rank] = nu;
+    chpos[rank] = ch;
+  }
 }
 
 // Gauss-Jordan inverse of a 6x6 matrix with partial pivoting.  Every loop is unrolled and
@@ -967,10 +987,11 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   const int nch = (M + MC - 1) / MC;
   KFBI_TRY(c->cnode.ensure(sizeof(int) * nch * 6 * MC));
   KFBI_TRY(c->ccount.ensure(sizeof(int) * nch));
+  KFBI_TRY(c->chpos.ensure(sizeof(int) * nch));
   KFBI_TRY(c->mkloc.ensure(sizeof(int) * 6 * M));
   hipLaunchKernelGGL(k_chunk_nodes, dim3(nch), dim3(128), sizeof(int) * 12 * MC, s, M, MC,
                      c->mknode.as<int>(), c->cnode.as<int>(), c->ccount.as<int>(),
-                     c->mkloc.as<int>());
+                     c->chpos.as<int>(), c->mkloc.as<int>());
   // node offsets, needed rows, band and row parts; posts the status for the host
   int* nodeoff = rowcnt + n1 + 1;
   int* rowpart = c->rowpart.as<int>();
