@@ -973,7 +973,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   hipLaunchKernelGGL(k_arm_rowcount, dim3(N - 1), dim3(256), 0, s, N, lab, hid, vid, rowoff, st);
   hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, 1, rowoff, &st->n_arms,
                      nullptr, nullptr);
-  hipLaunchKernelGGL(k_arm_fill, dim3(N - 1), dim3(256), 0, s, N, c->x0, c->y0, h, c->c2, M, lab,
+  hipLaunchKernelGGL(k_arm_fill, dim3(N - 1), dim3(1024), 0, s, N, c->x0, c->y0, h, c->c2, M, lab,
                      hid, vid, rowoff, cr, c->geo.as<double>(), c->armpk.as<int>(),
                      c->armcoef.as<ArmCoef>(), st);
   // markers / nodes
