@@ -38,7 +38,15 @@ constexpr int kColsPerBlock = 4;
 constexpr int kReg = 8;       // circulant outputs per thread in K1
 constexpr int kNodeBatch = 8; // nodes reduced together in K4
 constexpr int kRingNodes = 8;  // free-space box nodes per K1 block
-constexpr int kWinMax = 24;    // derivative window per K1 chunk: at most 16 + 5 markers
+constexpr int kWinMax = 24;
+// K4 block size for a single density: eight wavefronts share a chunk's nodes (fewer rows,
+// the long-latency loads of the node loop, per wavefront), four where the FP64 row of
+// E > 32 mode slots per lane would not fit the registers of eight.  A batch launches
+// four-wavefront blocks: with many blocks per CU they overlap better.
+template <class T, int E>
+__host__ __device__ constexpr int node_threads() {
+  return (sizeof(T) == 8 && E > 32) ? 256 : 512;
+}    // derivative window per K1 chunk: at most 16 + 5 markers
 
 // Two-level sine table in LDS: sin/cos(pi m / N) for m = 64 q + r from
 // hs/hc[q] = sin/cos(pi 64 q / N) and ls/lc[r] = sin/cos(pi r / N) by angle addition.
@@ -924,14 +932,14 @@ __global__ void k_colconst_neu(int N, double hc2, int E, double* __restrict__ co
 
 // ---------------------------------------------------------------------------------- K4
 // One block per chunk of MC markers.  Its distinct stencil nodes (sorted by row) are
-// split over the four wavefronts; lane l of a wavefront keeps G[j][p] for
+// split over the wavefronts; lane l of a wavefront keeps G[j][p] for
 // p = 1 + l + 64 e and advances sin(p i pi / N) over e by the three-term sine recurrence
 // with step 64 i pi / N.  Eight nodes are reduced together by recursive halving.  Then
 // MC threads apply the Sec. 4.3 corrected interpolation.
 // COSB (zero-normal-derivative box): v_ij = (2/N) sum_{p=0}^{N} w_p G[j][p] cos(p i pi / N)
 // with w_0 = w_N = 1/2; lane l keeps the modes p = l + 64 e.
-template <class T, int E, bool COSB>
-__global__ void __launch_bounds__(256)
+template <class T, int E, bool COSB, int NT>
+__global__ void __launch_bounds__(NT)
     k_nodes_extract(int N, int M, int MC, int nch, const int* __restrict__ cnode,
                     const int* __restrict__ ccount, const int* __restrict__ chpos,
                     const int* __restrict__ mkloc,
@@ -992,11 +1000,12 @@ __global__ void __launch_bounds__(256)
   double qs = 0.0;
   if (yop && oq != 0.0) {
     double s = 0.0;
-    for (int i = tid; i < nq; i += 256) s += qpart[i];
+    for (int i = tid; i < nq; i += NT) s += qpart[i];
     qs = block_sum<double>(s, red);
   }
   // this wavefront's nodes (contiguous in the sorted list, so rows repeat)
-  const int per = (nn + 3) / 4;
+  constexpr int NWV = NT / 64;
+  const int per = (nn + NWV - 1) / NWV;
   const int qb = w * per, qe = min(nn, qb + per);
   int curj = -1;
   // distance between groups of four mode slots: 4 in a row-major band, 4 nbr in the
@@ -1242,8 +1251,10 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   const int nch = nblk(M, MC);
   const int side = op ? op->side : 0;
   const double oa = op ? op->a : 0.0, ob = op ? op->b : 0.0, oq = op ? op->q : 0.0;
-  if (stages & 8)
-    hipLaunchKernelGGL((k_nodes_extract<T, E, false>), dim3(8 * nblk(nch, 8), B), dim3(256),
+  if (stages & 8) {
+    constexpr int NT1 = node_threads<T, E>();
+    auto kn = (B == 1) ? k_nodes_extract<T, E, false, NT1> : k_nodes_extract<T, E, false, 256>;
+    hipLaunchKernelGGL(kn, dim3(8 * nblk(nch, 8), B), dim3(B == 1 ? NT1 : 256),
                        sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(),
                        c->ccount.as<int>(), c->chpos.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G,
                        c->mq.as<double>(), c->ext.as<double>(), c->qpart.as<double>(),
@@ -1251,6 +1262,7 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
                        out ? out->v_minus : nullptr, out ? out->dn_plus : nullptr,
                        out ? out->dn_minus : nullptr, side, oa, ob, oq, xop, yop, gstride,
                        op ? op->a_marker : nullptr, ldr);
+  }
 }
 
 // Grid stages of the zero-normal-derivative box: cosine row transform of the arm parts
@@ -1300,14 +1312,17 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
   const int nch = nblk(M, MC);
   const int side = op ? op->side : 0;
   const double oa = op ? op->a : 0.0, ob = op ? op->b : 0.0, oq = op ? op->q : 0.0;
-  if (stages & 8)
-    hipLaunchKernelGGL((k_nodes_extract<T, E, true>), dim3(8 * nblk(nch, 8), B), dim3(256),
+  if (stages & 8) {
+    constexpr int NT1 = node_threads<T, E>();
+    auto kn = (B == 1) ? k_nodes_extract<T, E, true, NT1> : k_nodes_extract<T, E, true, 256>;
+    hipLaunchKernelGGL(kn, dim3(8 * nblk(nch, 8), B), dim3(B == 1 ? NT1 : 256),
                        sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(),
                        c->ccount.as<int>(), c->chpos.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G, mqv,
                        c->ext.as<double>(), c->qpart.as<double>(), c->n_mk_blocks,
                        out ? out->v_plus : nullptr, out ? out->v_minus : nullptr,
                        out ? out->dn_plus : nullptr, out ? out->dn_minus : nullptr, side, oa, ob,
                        oq, xop, yop, gstride, op ? op->a_marker : nullptr, ldr);
+  }
 }
 
 // Dispatch on E = ceil((N+1)/64) for N = 64 .. 2048.
