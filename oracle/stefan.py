@@ -33,10 +33,14 @@ Marker refinement as for the Hele-Shaw state (oracle.thetal.refine): eta, the la
 and the explicit-term history go to the doubled parameter grid by trigonometric
 interpolation; the temperature is untouched.
 
+The interface update is oracle.thetal.advance with U = psi, lambda of the chosen case
+and the second- or third-order small-scale term.
+
 Pinned by: the first-step density for a circle in a uniform field against the closed
 form of the free-space single layer, the energy balance sum(T) h^2 - area(Omega+) kept
 to discretisation error, the symmetry of a growing circle, and the two SSD propagators'
-Fourier symbols (tests/test_oracle_stefan.py).
+Fourier symbols (tests/test_oracle_stefan.py); the shared update's pins of both orders
+and the hand-over of U, lambda and the order (tests/test_oracle_thetal_time.py).
 """
 from __future__ import annotations
 
@@ -49,7 +53,7 @@ from . import geometry as geom
 from . import kfbi
 from . import spectral
 from .gmres import gmres
-from .thetal import reconstruct, area
+from .thetal import reconstruct, area, advance
 
 TWO_PI = 2.0 * math.pi
 N_LAMBDA = 4096
@@ -154,36 +158,8 @@ def stefan_step(st: StefanState, prm: StefanParams) -> tuple[StefanState, Stefan
     Tnew = T1 + T2
 
     U = psi
-    gfun = theta_a * U
-    Mdot = TWO_PI * np.mean(gfun)
-    V = -spectral.cumulative_meanfree(gfun)
-    Q = np.array([np.mean(U * n[0] + V * s[0]), np.mean(U * n[1] + V * s[1])])
-    lam = prm.lam
-    k = np.abs(spectral.wavenumbers(M))
-    if prm.ssd == 1:
-        Lterm = lam * (TWO_PI / L) ** 2 * spectral.diff(st.eta, 2)
-        pw = 2
-    else:
-        Lterm = lam * (TWO_PI / L) ** 3 * spectral.hilbert(spectral.diff(st.eta, 3))
-        pw = 3
-    Nfun = (TWO_PI / L) * (theta_a * V - spectral.diff(U, 1)) - Lterm
-    Nhat = np.fft.fft(Nfun)
+    eta_new, Lnew, Xnew, Nhat, Mdot, Q = advance(st, U, prm.lam, 1 + prm.ssd, prm.tau)
     tau = prm.tau
-    ehat = np.fft.fft(st.eta)
-    sym = (TWO_PI * k) ** pw
-    if st.n == 0:
-        Lnew = L + tau * Mdot
-        Xnew = st.Xbar + tau * Q
-        e1 = np.exp(-0.5 * lam * tau * sym * (1.0 / L ** pw + 1.0 / Lnew ** pw))
-        ehat_new = e1 * (ehat + tau * Nhat)
-    else:
-        Lnew = L + 0.5 * tau * (3.0 * Mdot - st.Mdot_prev)
-        Xnew = st.Xbar + 0.5 * tau * (3.0 * Q - st.Q_prev)
-        e1 = np.exp(-0.5 * lam * tau * sym * (1.0 / L ** pw + 1.0 / Lnew ** pw))
-        e2 = np.exp(-lam * tau * sym * (0.5 / st.L_prev ** pw + 1.0 / L ** pw + 0.5 / Lnew ** pw))
-        ehat_new = e1 * ehat + 0.5 * tau * (3.0 * e1 * Nhat - e2 * st.Nhat_prev)
-    ehat_new[M // 2] = 0.0
-    eta_new = np.real(np.fft.ifft(ehat_new))
     new = StefanState(eta_new, Lnew, Xnew, Tnew, st.T, st.n + 1, st.t + tau, Nhat, Mdot, Q, L,
                       psi)
     info = StefanInfo(gs.iters, gs.relres, area(X), L, psi, T1_at, rhs)

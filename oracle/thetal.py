@@ -30,7 +30,12 @@ gives only the criterion; the interpolation is this reading.
 Pinned by: a circle grows as R(t) = sqrt(R0^2 + 2 J t); J = 0 conserves area and
 shortens the curve; equal-arclength resampling of a circle/ellipse
 (tests/test_oracle_thetal.py); refinement keeps the curve, L, Xbar and the explicit-term
-history (tests/test_oracle_refine.py).
+history (tests/test_oracle_refine.py).  The time update `advance` (M, V, Q, the
+integrating-factor AB2) is pinned by the closed-form evolution of a non-circular curve
+under the velocity law U = c0 + c1 X.n, by second-order time convergence with the
+small-scale terms present, and, through hs_step, by the linear growth rate of a perturbed
+circle; each of these fails for a dropped V or a wrong integrating factor
+(tests/test_oracle_thetal_time.py).
 """
 from __future__ import annotations
 
@@ -160,6 +165,57 @@ class StepInfo:
     U: np.ndarray
 
 
+def advance(st, U: np.ndarray, lam: float, pw: int, tau: float):
+    """One theta-L time step given the normal velocity U at the markers (Sec. 5.1, 5.3).
+
+    st carries eta, L, Xbar, the step index n and the previous step's history
+    (Nhat_prev, Mdot_prev, Q_prev, L_prev).  With theta = alpha + eta and g = theta_a U:
+      M = int g da (eq. L-evo), V = (a/2pi) int g - int_0^a g (equal arclength, Sec. 5.1),
+      Q = (1/2pi) int (U n + V s) da (eq. ave-evo),
+      N = (2pi/L)(theta_a V - U_a) - lam (2pi/L)^pw P[eta]     (the explicit part),
+    with the stiff part P = H[d^3/da^3] (pw = 3, symbol -|k|^3) or d^2/da^2 (pw = 2,
+    symbol -k^2) moved into the integrating factor.  L and Xbar take explicit AB2; eta_hat
+    takes the integrating-factor AB2 of eq. Fourier-theta1/2 whose factors e_k integrate
+    the symbol over [t_n, t_n+1] and [t_n-1, t_n+1] by the trapezoidal rule in time with
+    L at the three levels.  The first step is the integrating-factor forward Euler.
+    Returns (eta_new, L_new, Xbar_new, Nhat, Mdot, Q), the last three being the history
+    of the next step."""
+    M = st.eta.size
+    L = st.L
+    alpha = TWO_PI * np.arange(M) / M
+    theta = alpha + st.eta
+    s = np.stack([np.cos(theta), np.sin(theta)])
+    n = np.stack([np.sin(theta), -np.cos(theta)])
+    theta_a = 1.0 + spectral.diff(st.eta, 1)
+    gfun = theta_a * U
+    Mdot = TWO_PI * np.mean(gfun)
+    V = -spectral.cumulative_meanfree(gfun)
+    Q = np.array([np.mean(U * n[0] + V * s[0]), np.mean(U * n[1] + V * s[1])])
+    if pw == 3:
+        Lterm = lam * (TWO_PI / L) ** 3 * spectral.hilbert(spectral.diff(st.eta, 3))
+    else:
+        Lterm = lam * (TWO_PI / L) ** 2 * spectral.diff(st.eta, 2)
+    Nfun = (TWO_PI / L) * (theta_a * V - spectral.diff(U, 1)) - Lterm
+    Nhat = np.fft.fft(Nfun)
+    k = np.abs(spectral.wavenumbers(M))
+    ehat = np.fft.fft(st.eta)
+    sym = (TWO_PI * k) ** pw
+    if st.n == 0:
+        Lnew = L + tau * Mdot
+        Xnew = st.Xbar + tau * Q
+        e1 = np.exp(-0.5 * lam * tau * sym * (1.0 / L ** pw + 1.0 / Lnew ** pw))
+        ehat_new = e1 * (ehat + tau * Nhat)
+    else:
+        Lnew = L + 0.5 * tau * (3.0 * Mdot - st.Mdot_prev)
+        Xnew = st.Xbar + 0.5 * tau * (3.0 * Q - st.Q_prev)
+        e1 = np.exp(-0.5 * lam * tau * sym * (1.0 / L ** pw + 1.0 / Lnew ** pw))
+        e2 = np.exp(-lam * tau * sym * (0.5 / st.L_prev ** pw + 1.0 / L ** pw + 0.5 / Lnew ** pw))
+        ehat_new = e1 * ehat + 0.5 * tau * (3.0 * e1 * Nhat - e2 * st.Nhat_prev)
+    ehat_new[M // 2] = 0.0
+    eta_new = np.real(np.fft.ifft(ehat_new))
+    return eta_new, Lnew, Xnew, Nhat, Mdot, Q
+
+
 def hs_step(st: HSState, prm: HSParams) -> tuple[HSState, StepInfo]:
     M = st.eta.size
     L = st.L
@@ -181,31 +237,8 @@ def hs_step(st: HSState, prm: HSParams) -> tuple[HSState, StepInfo]:
     dn = 0.5 * (res.dn_plus + res.dn_minus)
     U = prm.J * (X[0] * n[0] + X[1] * n[1]) / r2 - dn
 
-    gfun = theta_a * U
-    Mdot = TWO_PI * np.mean(gfun)
-    V = -spectral.cumulative_meanfree(gfun)
-    Q = np.array([np.mean(U * n[0] + V * s[0]), np.mean(U * n[1] + V * s[1])])
-    lam2 = prm.lambda2
-    Nfun = ((TWO_PI / L) * (theta_a * V - spectral.diff(U, 1))
-            - lam2 * (TWO_PI / L) ** 3 * spectral.hilbert(spectral.diff(st.eta, 3)))
-    Nhat = np.fft.fft(Nfun)
+    eta_new, Lnew, Xnew, Nhat, Mdot, Q = advance(st, U, prm.lambda2, 3, prm.tau)
     tau = prm.tau
-    k = np.abs(spectral.wavenumbers(M))
-    ehat = np.fft.fft(st.eta)
-    if st.n == 0:
-        Lnew = L + tau * Mdot
-        Xnew = st.Xbar + tau * Q
-        e1 = np.exp(-0.5 * lam2 * tau * (TWO_PI * k) ** 3 * (1.0 / L ** 3 + 1.0 / Lnew ** 3))
-        ehat_new = e1 * (ehat + tau * Nhat)
-    else:
-        Lnew = L + 0.5 * tau * (3.0 * Mdot - st.Mdot_prev)
-        Xnew = st.Xbar + 0.5 * tau * (3.0 * Q - st.Q_prev)
-        e1 = np.exp(-0.5 * lam2 * tau * (TWO_PI * k) ** 3 * (1.0 / L ** 3 + 1.0 / Lnew ** 3))
-        e2 = np.exp(-lam2 * tau * (TWO_PI * k) ** 3 *
-                    (0.5 / st.L_prev ** 3 + 1.0 / L ** 3 + 0.5 / Lnew ** 3))
-        ehat_new = e1 * ehat + 0.5 * tau * (3.0 * e1 * Nhat - e2 * st.Nhat_prev)
-    ehat_new[M // 2] = 0.0
-    eta_new = np.real(np.fft.ifft(ehat_new))
     new = HSState(eta_new, Lnew, Xnew, st.n + 1, st.t + tau, Nhat, Mdot, Q, L, phi)
     info = StepInfo(gs.iters, gs.relres, area(X), L, phi, U)
     return new, info
