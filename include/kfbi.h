@@ -18,8 +18,9 @@
  *  - All device work is enqueued on the context's HIP stream (kfbi_grid.stream; NULL
  *    = the default stream).  kfbi_apply is asynchronous; kfbi_set_interface,
  *    kfbi_gmres_solve and thetaL_step synchronise that stream before returning.
- *  - The library owns its workspaces: they are allocated in kfbi_create and grown
- *    only in kfbi_set_interface; kfbi_apply and kfbi_gmres_solve allocate nothing.
+ *  - The library owns its workspaces: they are allocated in kfbi_create (the GMRES
+ *    Krylov basis for max_markers and the largest restart among them) and grown only
+ *    in kfbi_set_interface; kfbi_apply and kfbi_gmres_solve allocate nothing.
  *  - Errors: every call returns a KFBI_* status; no exception crosses the ABI; outputs
  *    are unspecified on error; kfbi_last_error() gives a thread-local message.
  *  - A context is used by one host thread at a time.
@@ -94,6 +95,8 @@ typedef struct {
                        batch runs as consecutive launches of at most this
                        many, so that each launch's row-transform output and
                        band stay within the last-level cache              */
+  long long workspace_bytes; /* device memory the context holds (all its
+                       workspaces); unchanged by apply and GMRES calls   */
 } kfbi_info;
 
 /* Outputs of one apply.  Each pointer is a device array or NULL (not computed).
@@ -112,7 +115,8 @@ typedef struct {
 /* Thread-local message describing the last failing call of this thread. */
 const char* kfbi_last_error(void);
 
-/* Create a context on the current HIP device; allocates the grid workspaces. */
+/* Create a context on the current HIP device; allocates the grid workspaces and the
+ * GMRES workspace (Krylov basis of max_markers x 65 doubles, Hessenberg matrix, events). */
 int kfbi_create(const kfbi_grid* grid, kfbi_ctx** out);
 int kfbi_destroy(kfbi_ctx* ctx);
 
@@ -125,7 +129,9 @@ int kfbi_destroy(kfbi_ctx* ctx);
  * A column crossing within 1e-9 h of a grid node is assigned to the column segment
  * where the row-based labels change (interface through a node up to rounding).
  * Synchronises the stream.  Returns KFBI_E_GEOMETRY if a marker is within 3h of the
- * box boundary, a grid segment is cut twice, or labels and crossings disagree. */
+ * box boundary, a grid segment is cut twice, labels and crossings disagree, or the
+ * interface has more row parts than the column solve can hold in the LDS of one
+ * workgroup (the message gives both numbers). */
 int kfbi_set_interface(kfbi_ctx* ctx, int M, const double* xy_dev);
 int kfbi_get_info(const kfbi_ctx* ctx, kfbi_info* info);
 

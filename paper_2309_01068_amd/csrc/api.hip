@@ -5,11 +5,52 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <type_traits>
 #include <new>
+#include <vector>
 
 #include "common.h"
 
 namespace kfbi {
+
+static std::mutex g_attr_mu;
+static std::vector<int> g_attr_done;  // devices whose kernels carry their LDS attributes
+
+size_t dyn_lds_capacity(const void* kernel) {
+  int dev = 0, lim = 0;
+  hipFuncAttributes a{};
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      hipFuncGetAttributes(&a, kernel) != hipSuccess)
+    return 0;
+  return static_cast<size_t>(lim) > a.sharedSizeBytes ? static_cast<size_t>(lim) - a.sharedSizeBytes
+                                                      : 0;
+}
+
+int allow_full_dyn_lds(const void* kernel) {
+  const size_t cap = dyn_lds_capacity(kernel);
+  if (cap == 0) {
+    set_error("cannot query the LDS attributes of a kernel");
+    return KFBI_E_HIP;
+  }
+  KFBI_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(cap)));
+  return KFBI_OK;
+}
+
+int kernel_attributes() {
+  int dev = 0;
+  KFBI_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_attr_mu);
+  for (int d : g_attr_done)
+    if (d == dev) return KFBI_OK;
+  KFBI_TRY(apply_kernel_attrs());
+  KFBI_TRY(gmres_kernel_attrs());
+  KFBI_TRY(thetal_kernel_attrs());
+  g_attr_done.push_back(dev);
+  return KFBI_OK;
+}
 
 static thread_local char g_err[512] = "";
 
@@ -67,8 +108,11 @@ static int check_ctx(const kfbi_ctx* c, bool need_iface) {
   return KFBI_OK;
 }
 
-static void release_all(kfbi_ctx* c) {
-  DBuf* bufs[] = {&c->vraw, &c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
+// Every device workspace of a context.
+template <class Ctx, class F>
+static void for_each_buffer(Ctx* c, F&& f) {
+  using B = std::remove_reference_t<decltype((c->X))>;
+  B* bufs[] = {&c->vraw, &c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
                   &c->vid,    &c->lab,    &c->armcnt, &c->rowsum,  &c->armrow, &c->armpk,
                   &c->armc,   &c->armk,   &c->armsc,  &c->chpos,
                   &c->colc,   &c->lanef,   &c->cnode,  &c->ccount,
@@ -78,7 +122,17 @@ static void release_all(kfbi_ctx* c) {
                   &c->armr,   &c->qpart,  &c->ring,   &c->sinT,    &c->sinT32, &c->gband,
                   &c->nodeval, &c->tmpM,  &c->gV,     &c->gH,      &c->gsc,    &c->gpart,
                   &c->gcnt,   &c->gw,     &c->gx,     &c->gr,      &c->gd};
-  for (DBuf* b : bufs) b->release();
+  for (auto* b : bufs) f(*b);
+}
+
+static size_t workspace_bytes(const kfbi_ctx* c) {
+  size_t t = 0;
+  for_each_buffer(c, [&](const DBuf& b) { t += b.bytes; });
+  return t;
+}
+
+static void release_all(kfbi_ctx* c) {
+  for_each_buffer(c, [](DBuf& b) { b.release(); });
   for (int i = 0; i < kfbi_ctx::kProfPool; ++i)
     if (c->prof_ev[i]) (void)hipEventDestroy(c->prof_ev[i]);
   for (int i = 0; i < kfbi_ctx::kGmresRing; ++i)
@@ -155,6 +209,7 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
     set_error("hipGetDevice failed");
     return fail(KFBI_E_HIP);
   }
+  if ((st = kernel_attributes()) != KFBI_OK) return fail(st);
   const size_t n1sq = static_cast<size_t>(N + 1) * (N + 1);
   const size_t n = N - 1;
   const int Mx = g->max_markers;
@@ -180,7 +235,8 @@ int kfbi_create(const kfbi_grid* g, kfbi_ctx** out) {
       // values per row for up to N+1 rows
       (st = c->gband.ensure(sizeof(double) * (N + 4) * (N + 1) * Bx)) ||
       (st = c->mqz.ensure(sizeof(double) * 5 * Mx)) ||
-      (st = c->tmpM.ensure(sizeof(double) * (Bx > 4 ? Bx : 4) * Mx)))
+      (st = c->tmpM.ensure(sizeof(double) * (Bx > 4 ? Bx : 4) * Mx)) ||
+      (st = gmres_alloc(c)))
     return fail(st);
   if (hipHostMalloc(&c->hstat, 4096, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer(&c->dstat, c->hstat, 0) != hipSuccess) {
@@ -226,6 +282,15 @@ int kfbi_set_interface(kfbi_ctx* c, int M, const double* xy) {
   c->n_mk_blocks = (M + c->mk_chunk - 1) / c->mk_chunk;
   const int st = geometry_setup(c, M, xy);
   if (st != KFBI_OK) return st;
+  // the column solve keeps the four-mode slab of every row part of its column group in
+  // LDS: 32 bytes per part (FP64)
+  const size_t need = 32 * static_cast<size_t>(c->st.n_parts > 0 ? c->st.n_parts : 1);
+  const size_t cap = colsolve_lds_capacity(c);
+  if (need > cap) {
+    set_error("interface needs %d row parts; the column solve holds at most %zu in LDS",
+              c->st.n_parts, cap / 32);
+    return KFBI_E_GEOMETRY;
+  }
   c->have_interface = 1;
   return KFBI_OK;
 }
@@ -257,6 +322,7 @@ int kfbi_get_info(const kfbi_ctx* c, kfbi_info* info) {
   info->row_hi = c->st.row_hi;
   info->n_parts = c->st.n_parts;
   info->sub_batch = sub_batch(c);
+  info->workspace_bytes = static_cast<long long>(workspace_bytes(c));
   return KFBI_OK;
 }
 

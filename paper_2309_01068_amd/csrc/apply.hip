@@ -38,7 +38,7 @@ constexpr int kColsPerBlock = 4;
 constexpr int kReg = 8;       // circulant outputs per thread in K1
 constexpr int kNodeBatch = 8; // nodes reduced together in K4
 constexpr int kRingNodes = 8;  // free-space box nodes per K1 block
-constexpr int kWinMax = 24;
+constexpr int kWinMax = 24;     // derivative window per K1 chunk: at most 16 + 5 markers
 // K4 block size for a single density: eight wavefronts share a chunk's nodes (fewer rows,
 // the long-latency loads of the node loop, per wavefront), four where the FP64 row of
 // E > 32 mode slots per lane would not fit the registers of eight.  A batch launches
@@ -46,7 +46,7 @@ constexpr int kWinMax = 24;
 template <class T, int E>
 __host__ __device__ constexpr int node_threads() {
   return (sizeof(T) == 8 && E > 32) ? 256 : 512;
-}    // derivative window per K1 chunk: at most 16 + 5 markers
+}
 
 // Two-level sine table in LDS: sin/cos(pi m / N) for m = 64 q + r from
 // hs/hc[q] = sin/cos(pi 64 q / N) and ls/lc[r] = sin/cos(pi r / N) by angle addition.
@@ -1202,15 +1202,9 @@ __global__ void k_grid_ring(int N, const T* __restrict__ ring, double* __restric
 
 static inline int nblk(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
 
-// Allow a kernel more than the default dynamic LDS (done once per kernel and size class).
 template <class K>
-static void allow_dyn_lds(K kernel, size_t bytes) {
-  if (bytes <= 64 * 1024) return;
-  static size_t done = 0;
-  if (bytes <= done) return;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
-  done = bytes;
+static const void* kptr(K kernel) {
+  return reinterpret_cast<const void*>(kernel);
 }
 
 template <class T, int E>
@@ -1235,7 +1229,6 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   const int ngrp = nblk(n, kColsPerBlock);
   const int nb = ((ngrp + 7) / 8) * 8;
   const size_t lds_dyn = sizeof(T) * 4 * static_cast<size_t>(P > 0 ? P : 1);
-  allow_dyn_lds(k_colsolve<T, E>, lds_dyn);
   if (stages & 4)
     hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P, Tg,
                        c->rowpart.as<int>(), sinT, ring, c->colc.as<double>(),
@@ -1297,7 +1290,6 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
   if (ev) hipEventRecord(ev[2], s);
   const int nb = ((ngm + 7) / 8) * 8;
   const size_t lds_dyn = sizeof(T) * 4 * static_cast<size_t>(P > 0 ? P : 1);
-  allow_dyn_lds(k_colsolve_neu<T, E>, lds_dyn);
   if (stages & 4)
     hipLaunchKernelGGL((k_colsolve_neu<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P,
                        Tg, c->rowpart.as<int>(), static_cast<const T*>(rr.Fa),
@@ -1380,7 +1372,6 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
   const size_t lds_mk = static_cast<size_t>((lpad(M - 1) + 1) + kprep_region(M, nd) +
                                             16 * kReg + 5 * kWinMax);
   const size_t lds = sizeof(double) * (lds_mk > 4 * 256 ? lds_mk : 4 * 256);
-  allow_dyn_lds(k_prep, lds);
   if (stages & 1)
     hipLaunchKernelGGL(k_prep, dim3(nmk + nring, B), dim3(256), lds, s, M, C, nmk, layer, dens,
                        c->dvec.as<double>(), c->dvec.as<double>() + M, c->mq.as<double>(),
@@ -1649,6 +1640,46 @@ int replay_stage(kfbi_ctx* c, int stage, int reps, double* us_avg) {
   }
   *us_avg = 1e3 * static_cast<double>(ms) / reps;
   return KFBI_OK;
+}
+
+// Every instantiation that takes dynamic LDS may use all of a workgroup's LDS beyond its
+// static part (set once per device from kfbi_create).
+template <class T>
+static int colsolve_attrs() {
+  const void* ks[] = {kptr(k_colsolve<T, 1>),      kptr(k_colsolve<T, 2>),
+                      kptr(k_colsolve<T, 4>),      kptr(k_colsolve<T, 8>),
+                      kptr(k_colsolve<T, 16>),     kptr(k_colsolve<T, 32>),
+                      kptr(k_colsolve_neu<T, 2>),  kptr(k_colsolve_neu<T, 3>),
+                      kptr(k_colsolve_neu<T, 5>),  kptr(k_colsolve_neu<T, 9>),
+                      kptr(k_colsolve_neu<T, 17>), kptr(k_colsolve_neu<T, 33>)};
+  for (const void* k : ks) KFBI_TRY(allow_full_dyn_lds(k));
+  return KFBI_OK;
+}
+
+int apply_kernel_attrs() {
+  KFBI_TRY(allow_full_dyn_lds(kptr(k_prep)));
+  KFBI_TRY(colsolve_attrs<double>());
+  return colsolve_attrs<float>();
+}
+
+size_t colsolve_lds_capacity(const kfbi_ctx* c) {
+  const int N = c->N;
+  if (c->box_bc == KFBI_BOX_NEUMANN) {
+    size_t cap = 0;
+    neu_dispatch<double>(N, [&](auto EC) {
+      cap = dyn_lds_capacity(kptr(k_colsolve_neu<double, decltype(EC)::value>));
+    });
+    return cap;
+  }
+  const int E = (N - 1 + 63) / 64;
+  switch (E <= 1 ? 1 : E <= 2 ? 2 : E <= 4 ? 4 : E <= 8 ? 8 : E <= 16 ? 16 : 32) {
+    case 1: return dyn_lds_capacity(kptr(k_colsolve<double, 1>));
+    case 2: return dyn_lds_capacity(kptr(k_colsolve<double, 2>));
+    case 4: return dyn_lds_capacity(kptr(k_colsolve<double, 4>));
+    case 8: return dyn_lds_capacity(kptr(k_colsolve<double, 8>));
+    case 16: return dyn_lds_capacity(kptr(k_colsolve<double, 16>));
+    default: return dyn_lds_capacity(kptr(k_colsolve<double, 32>));
+  }
 }
 
 int apply_impl(kfbi_ctx* c, int layer, int precision, const double* dens, const double* ring_user,

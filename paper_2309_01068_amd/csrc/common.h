@@ -156,6 +156,20 @@ int neu_apply_full(kfbi_ctx* c, int layer, const double* dens, const double* Fa,
 int neu_to_grid(kfbi_ctx* c, const double* Gfull, double* grid);
 int neu_from_grid(kfbi_ctx* c, const double* grid, double* Gfull);
 
+// Dynamic LDS: every kernel launched with more than the default is allowed the whole LDS
+// of a workgroup beyond its static part, once per device (kernel_attributes, called by
+// kfbi_create under a lock); dyn_lds_capacity is that allowance.
+size_t dyn_lds_capacity(const void* kernel);
+int allow_full_dyn_lds(const void* kernel);
+int kernel_attributes();
+int apply_kernel_attrs();
+int gmres_kernel_attrs();
+int thetal_kernel_attrs();
+// Dynamic LDS the FP64 column solve of this grid and box may take (bytes).
+size_t colsolve_lds_capacity(const kfbi_ctx* c);
+// GMRES workspace for max_markers and the largest restart (kfbi_create).
+int gmres_alloc(kfbi_ctx* c);
+
 int apply_impl(kfbi_ctx* c, int layer, int precision, const double* dens, const double* ring_user,
                const kfbi_out* out, const kfbi_bie* op, const double* x_for_op, double* y_op,
                int batch = 1);

@@ -383,25 +383,30 @@ struct GmresWork {
   double* y;
 };
 
-static int ensure_work(kfbi_ctx* c, int restart, GmresWork* gw) {
-  const int M = c->M;
-  const int ldv = ((M + 63) / 64) * 64;
-  const int nblk = (M + kRedBlock - 1) / kRedBlock;
+int gmres_kernel_attrs() { return allow_full_dyn_lds(reinterpret_cast<const void*>(k_arnoldi)); }
+
+// The workspace for M <= max_markers and any restart <= kMaxRestart, allocated once by
+// kfbi_create: the Krylov basis (ldv x (kMaxRestart + 1)), the Hessenberg matrix, the
+// rotations, block partials, the status slots, four work vectors and the ring events.
+int gmres_alloc(kfbi_ctx* c) {
+  const int Mx = c->max_markers;
+  const int ldv = ((Mx + 63) / 64) * 64;
+  const int nblk = (Mx + kRedBlock - 1) / kRedBlock;
   KFBI_TRY(c->gV.ensure(sizeof(double) * static_cast<size_t>(ldv) * (kMaxRestart + 1)));
   KFBI_TRY(c->gH.ensure(sizeof(double) * (kMaxRestart + 1) * (kMaxRestart + 1)));
   KFBI_TRY(c->gsc.ensure(sizeof(double) * 5 * (kMaxRestart + 2)));
   KFBI_TRY(c->gpart.ensure(sizeof(double) * static_cast<size_t>(nblk) * (kMaxRestart + 2)));
   KFBI_TRY(c->gcnt.ensure(sizeof(GmresStatus) * (1 + kRing) + 64));
+  KFBI_TRY(c->gw.ensure(sizeof(double) * static_cast<size_t>(ldv) * 4));
   for (int q = 0; q < kRing; ++q)
     if (!c->gev[q]) KFBI_HIP(hipEventCreateWithFlags(&c->gev[q], hipEventDisableTiming));
-  static bool arn_lds = false;  // the attribute belongs to the kernel, set once per process
-  if (!arn_lds) {
-    KFBI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_arnoldi),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 static_cast<int>(kArnStageBytes)));
-    arn_lds = true;
-  }
-  KFBI_TRY(c->gw.ensure(sizeof(double) * ldv * 4));
+  return KFBI_OK;
+}
+
+// Pointers into the workspace for the installed interface (M <= max_markers).
+static void bind_work(kfbi_ctx* c, GmresWork* gw) {
+  const int M = c->M;
+  const int ldv = ((M + 63) / 64) * 64;
   gw->V = c->gV.as<double>();
   gw->ldv = ldv;
   gw->H = c->gH.as<double>();
@@ -423,7 +428,6 @@ static int ensure_work(kfbi_ctx* c, int restart, GmresWork* gw) {
   gw->r = wb + ldv;
   gw->d = wb + 2 * ldv;
   gw->y = wb + 3 * ldv;
-  return KFBI_OK;
 }
 
 // Host status slots after the Arnoldi ring: the last residual norm and ||b||.
@@ -580,7 +584,7 @@ extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b
     return KFBI_E_INVALID;
   }
   GmresWork gw;
-  KFBI_TRY(ensure_work(c, o->restart, &gw));
+  bind_work(c, &gw);
   const int M = c->M;
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   kfbi_gmres_stats loc{};

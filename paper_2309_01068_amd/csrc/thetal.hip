@@ -702,6 +702,14 @@ static void tl_free(thetaL* th) {
   th->kc = nullptr;
 }
 
+namespace kfbi {
+int thetal_kernel_attrs() {
+  KFBI_TRY(allow_full_dyn_lds(reinterpret_cast<const void*>(k_tl_pre)));
+  KFBI_TRY(allow_full_dyn_lds(reinterpret_cast<const void*>(k_tl_post)));
+  return allow_full_dyn_lds(reinterpret_cast<const void*>(k_tl_refine));
+}
+}  // namespace kfbi
+
 // Buffers, the KFBI context of the grid solves and the twiddles of an evolution object
 // whose parameters have been checked (on failure everything is released).
 static int tl_setup(thetaL* th, const thetaL_params* p, int M, int Mcap) {
@@ -752,17 +760,6 @@ static int tl_setup(thetaL* th, const thetaL_params* p, int M, int Mcap) {
     set_error("thetaL: twiddle kernel failed");
     return KFBI_E_HIP;
   }
-  const size_t lds = tl_lds_bytes(Mcap);
-  if (lds > 64 * 1024) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_pre),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_post),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  }
-  const size_t rlds = refine_lds_bytes(Mcap / 2);
-  if (rlds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tl_refine),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rlds));
   return KFBI_OK;
 }
 

@@ -54,7 +54,7 @@ class Info(C.Structure):
     _fields_ = [("M", C.c_int), ("n_cross_h", C.c_int), ("n_cross_v", C.c_int),
                 ("n_arms", C.c_int), ("n_nodes", C.c_int), ("n_rows", C.c_int),
                 ("row_lo", C.c_int), ("row_hi", C.c_int), ("n_parts", C.c_int),
-                ("sub_batch", C.c_int)]
+                ("sub_batch", C.c_int), ("workspace_bytes", C.c_longlong)]
 
 
 class Out(C.Structure):

@@ -87,3 +87,26 @@ def test_gmres_noconv_reports_status():
     with pytest.raises(kfbi.KfbiError) as e:
         ctx.gmres(b, x, kfbi.DOUBLE, kfbi.PLUS, 0.0, 1.0, 0.0, tol=1e-14, maxit=3)
     assert e.value.code == kfbi.E_NOCONV
+
+
+def test_solve_allocates_nothing():
+    """The GMRES workspace is sized for max_markers at context creation: the device memory
+    a context holds is the same before and after solves (FP64 and FP32 refinement, two
+    restart lengths), and after an interface with twice the markers (as after a marker
+    refinement) only kfbi_set_interface may have grown it.  (At 512 markers on this grid
+    the markers sit 0.8 h apart and GMRES stagnates near 1e-6, in the oracle too.)"""
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-2, 2, 256)
+    ctx = kfbi.Context(box.x0, box.y0, box.side, box.N, 0.0, kfbi.BOX_FREESPACE, 1024)
+    for M in (128, 256):
+        ctx.set_interface(dev(W.hs3(M)))
+        before = ctx.info()["workspace_bytes"]
+        assert before > 0
+        X = W.hs3(M)
+        rhs = dev(np.log(np.hypot(X[0], X[1])) - 1e-3)
+        for prec, restart in ((kfbi.FP64, 50), (kfbi.FP64, 20), (kfbi.FP32, 64)):
+            x = torch.zeros(M, dtype=torch.float64, device="cuda")
+            _, st = ctx.gmres(rhs, x, kfbi.DOUBLE, kfbi.MINUS, 0.0, 1.0, 1.0, tol=1e-10,
+                              restart=restart, precision=prec)
+            assert st["converged"] and st["relres"] <= 1e-10
+            assert ctx.info()["workspace_bytes"] == before, (M, prec, restart)

@@ -48,6 +48,8 @@ CASES = [  # (name, shape, eC, eV, bdf2, ssd)
     ("be_ssd2_iso", "pert", ISO_C, ISO_V, False, 2),
     ("bdf2_ssd1_aniso", "pert", ANI_C, (5e-2, 0.2, 0.0, 4, 0.0), True, 1),
     ("bdf2_circle", "circle", ISO_C, ISO_V, True, 2),
+    # eps_V = 0: eq. bie-GT is of the first kind, -S psi = -eps_C kappa - T1
+    ("bdf2_first_kind", "pert", ANI_C, (0.0, 0.0, 0.0, 4, 0.0), True, 2),
 ]
 
 
@@ -308,3 +310,71 @@ def test_stefan_dendrite_fifty_steps_parity():
             assert e_eta <= 1e-9 and e_psi <= 1e-8 and e_T <= 1e-8, k
             assert abs(sc[0] - st.L) <= 1e-11 * st.L, k
             assert np.max(np.abs(np.array(sc[1:3]) - st.Xbar)) <= 1e-11, k
+
+
+# Sec. 6.2.2 stability test: eps_V = 0, eps_C = 0.05, the circle r = 1 + 0.02 cos 4a with
+# 128 markers on a 256^2 grid of (-2,2)^2, BDF2 (c^2 = 3/(2 tau)).  The initial temperature
+# is not given; the uniform field -0.05 (the Gibbs-Thomson temperature of the unit circle)
+# is used.  The explicit scheme is the integrating-factor scheme with a vanishing SSD
+# constant, i.e. plain Adams-Bashforth 2.
+#
+# The paper finds the semi-implicit scheme stable at tau = 1e-2 and the explicit one
+# unstable at tau = 5e-5; both are reproduced.  It also finds the explicit scheme stable at
+# tau = 2.5e-5, which is not: with c^2 = 3/(2 tau) the single layer is local for the
+# marker modes (k <= 63 < cR), the linearised decay rate of mode k on the unit circle is
+# eps_C (k^2 - 1) / (I_k(cR) K_k(cR)) (about 1.0e5 for k = 63 at tau = 2.5e-5), and
+# Adams-Bashforth 2 needs tau times that below 1, which gives tau < 4.2e-6.  The explicit
+# runs below bracket that bound: stable at 2e-6, blown up at 8e-6.
+STAB_C = (0.05, 0.0, 0.0, 4, 0.0)
+STAB_V = (0.0, 0.0, 0.0, 4, 0.0)
+
+
+def high_mode_amplitude(g, kmin=32):
+    """Largest Fourier amplitude of eta at wavenumbers >= kmin (grid-scale content)."""
+    eta, _ = g.interface()
+    c = np.fft.rfft(eta.cpu().numpy()) / eta.numel()
+    return float(np.max(np.abs(c[kmin:])))
+
+
+def stability_run(tau, lam, nsteps, stop_at=1e-2):
+    """(stefan object, high-mode amplitude after every step, steps taken, blown up)."""
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-2, 2, 256)
+    M = 128
+    g = kfbi.Stefan(box.x0, box.y0, box.side, box.N, M, tau, STAB_C, STAB_V, bdf2=True, ssd=2,
+                    lam=lam, tol=1e-10)
+    T0 = torch.full((box.N + 1, box.N + 1), -0.05, dtype=torch.float64, device="cuda")
+    g.init(dev(W.polar_curve(lambda a: 1.0 + 0.02 * np.cos(4 * a), M)), T0)
+    amps = []
+    for k in range(nsteps):
+        try:
+            g.step()
+        except kfbi.KfbiError:                # a curve the grid no longer resolves
+            return g, amps, k + 1, True
+        amps.append(high_mode_amplitude(g))    # every step: growth is caught early
+        if amps[-1] > stop_at:               # blown up: stop before the curve leaves the grid
+            return g, amps, k + 1, True
+    return g, amps, nsteps, False
+
+
+def test_semi_implicit_scheme_is_stable_at_large_steps():
+    print("[case] stability semi-implicit tau=1e-2", flush=True)
+    g, amps, n, blown = stability_run(1e-2, 0.0, 10)
+    lam, _ = g.constants()
+    assert lam == 2 * STAB_C[0]
+    assert not blown and amps[-1] < 1e-12, amps
+    eta, sc = g.interface()
+    assert abs(sc[3] - 0.1) < 1e-12
+
+
+@pytest.mark.parametrize("tau", [5e-5, 8e-6])
+def test_explicit_scheme_blows_up_above_its_bound(tau):
+    print(f"[case] stability explicit tau={tau}", flush=True)
+    g, amps, n, blown = stability_run(tau, 1e-300, 200)
+    assert blown and n <= 100, (n, amps)
+
+
+def test_explicit_scheme_is_stable_below_its_bound():
+    print("[case] stability explicit tau=2e-6", flush=True)
+    g, amps, n, blown = stability_run(2e-6, 1e-300, 1000)
+    assert not blown and max(amps) < 2e-3, amps
