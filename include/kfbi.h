@@ -197,6 +197,20 @@ typedef struct {
 int kfbi_gmres_solve(kfbi_ctx* ctx, const kfbi_bie* op, const double* rhs_dev,
                      double* x_dev, const kfbi_gmres_opts* opts, kfbi_gmres_stats* stats);
 
+/* kfbi_gmres_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same solve, same
+ * arguments, same results, with the Krylov workspace (basis, Hessenberg matrix, rotations,
+ * partial sums, work vectors, status words) in one static device array of the library
+ * instead of the context's buffers.  Calls no hipMalloc, hipFree or other allocating
+ * routine.  Limit: M <= 4096 markers (else KFBI_E_INVALID); the array holds about 2.3 MB on
+ * every GPU the library runs on, from its first kfbi_create on that GPU until the process
+ * ends.  All calls on one GPU share that array and leave their last contents in it; calls
+ * that overlap in time on one GPU (several host threads or streams) race, so they must be
+ * serialised by the caller.  The operator applies inside still use the context's apply
+ * buffers (allocated by kfbi_create / kfbi_set_interface). */
+int kfbi_gmres_solve_static(kfbi_ctx* ctx, const kfbi_bie* op, const double* rhs_dev,
+                            double* x_dev, const kfbi_gmres_opts* opts, kfbi_gmres_stats* stats);
+
 /* Measurement hook: while on, every apply brackets its four kernels with HIP events on
  * the context stream (stage 0: density derivatives and marker jump quantities, k_prep;
  * 1: corrected right-hand sides and their row sine transform, k_rowdst; 2: column

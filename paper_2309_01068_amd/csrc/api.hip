@@ -15,7 +15,7 @@
 namespace kfbi {
 
 static std::mutex g_attr_mu;
-static std::vector<int> g_attr_done;  // devices whose kernels carry their LDS attributes
+static std::vector<int> g_attr_done;  // devices set up: kernel LDS attributes, static workspace
 
 size_t dyn_lds_capacity(const void* kernel) {
   int dev = 0, lim = 0;
@@ -48,6 +48,7 @@ int kernel_attributes() {
   KFBI_TRY(apply_kernel_attrs());
   KFBI_TRY(gmres_kernel_attrs());
   KFBI_TRY(thetal_kernel_attrs());
+  KFBI_TRY(static_scratch_setup());
   g_attr_done.push_back(dev);
   return KFBI_OK;
 }

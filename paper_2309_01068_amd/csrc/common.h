@@ -169,6 +169,8 @@ int thetal_kernel_attrs();
 size_t colsolve_lds_capacity(const kfbi_ctx* c);
 // GMRES workspace for max_markers and the largest restart (kfbi_create).
 int gmres_alloc(kfbi_ctx* c);
+// Device address of the static GMRES workspace on the current device (once per device).
+int static_scratch_setup();
 
 int apply_impl(kfbi_ctx* c, int layer, int precision, const double* dens, const double* ring_user,
                const kfbi_out* out, const kfbi_bie* op, const double* x_for_op, double* y_op,

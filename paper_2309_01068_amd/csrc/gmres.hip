@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -381,6 +382,7 @@ struct GmresWork {
   double* r;
   double* d;
   double* y;
+  double* dcorr;  // correction of one refinement step (FP32 mode)
 };
 
 int gmres_kernel_attrs() { return allow_full_dyn_lds(reinterpret_cast<const void*>(k_arnoldi)); }
@@ -428,6 +430,85 @@ static void bind_work(kfbi_ctx* c, GmresWork* gw) {
   gw->r = wb + ldv;
   gw->d = wb + 2 * ldv;
   gw->y = wb + 3 * ldv;
+  gw->dcorr = c->tmpM.as<double>();
+}
+
+// ------------------------------------------------------------ workspace without allocation
+// The variant kfbi_gmres_solve_static keeps its Krylov workspace in this file-scope device
+// array instead of the context's buffers.  Each GPU holds its own copy until the process
+// ends; host code addresses it only through the pointer hipGetSymbolAddress returns on
+// that device (static_scratch_setup, once per device from kfbi_create).
+constexpr int kStaticMaxM = 4096;
+constexpr int kStaticLdv = kStaticMaxM;  // a multiple of 64
+constexpr int kStaticNblk = (kStaticMaxM + kRedBlock - 1) / kRedBlock;
+constexpr size_t kStaticDoubles =
+    static_cast<size_t>(kStaticLdv) * (kMaxRestart + 1)     // V
+    + (kMaxRestart + 1) * (kMaxRestart + 1)                  // H
+    + 5 * (kMaxRestart + 2)                                  // cs, sn, g, h1, h2
+    + static_cast<size_t>(kStaticNblk) * (kMaxRestart + 2)   // block partials
+    + 5 * static_cast<size_t>(kStaticLdv)                    // w, r, d, y, dcorr
+    + (1 + kRing) * (sizeof(GmresStatus) / sizeof(double)) + 8;  // status slots, counter
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch[kMaxDevices] = {};
+
+int static_scratch_setup() {
+  int dev = 0;
+  KFBI_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d beyond the %d devices the static workspace supports", dev, kMaxDevices);
+    return KFBI_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return KFBI_OK;
+  void* p = nullptr;
+  KFBI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  g_scratch[dev] = static_cast<double*>(p);
+  return KFBI_OK;
+}
+
+// Pointers into the static workspace of the current device (M <= kStaticMaxM).
+static int bind_static(kfbi_ctx* c, GmresWork* gw) {
+  double* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (c->device >= 0 && c->device < kMaxDevices) base = g_scratch[c->device];
+  }
+  if (!base) {
+    set_error("static GMRES workspace not set up on device %d", c->device);
+    return KFBI_E_STATE;
+  }
+  const int M = c->M;
+  const int ldv = ((M + 63) / 64) * 64;
+  double* q = base;
+  gw->V = q;
+  gw->ldv = ldv;
+  q += static_cast<size_t>(kStaticLdv) * (kMaxRestart + 1);
+  gw->H = q;
+  q += (kMaxRestart + 1) * (kMaxRestart + 1);
+  gw->cs = q;
+  gw->sn = q + (kMaxRestart + 2);
+  gw->g = q + 2 * (kMaxRestart + 2);
+  gw->h1 = q + 3 * (kMaxRestart + 2);
+  gw->h2 = q + 4 * (kMaxRestart + 2);
+  q += 5 * (kMaxRestart + 2);
+  gw->part = q;
+  q += static_cast<size_t>(kStaticNblk) * (kMaxRestart + 2);
+  gw->w = q;
+  gw->r = q + kStaticLdv;
+  gw->d = q + 2 * kStaticLdv;
+  gw->y = q + 3 * kStaticLdv;
+  gw->dcorr = q + 4 * kStaticLdv;
+  q += 5 * static_cast<size_t>(kStaticLdv);
+  gw->st = reinterpret_cast<GmresStatus*>(q);
+  gw->ring = gw->st + 1;
+  gw->counter = reinterpret_cast<unsigned int*>(gw->st + 1 + kRing);
+  gw->hring = reinterpret_cast<GmresStatus*>(c->hstat);
+  gw->dring = reinterpret_cast<GmresStatus*>(c->dstat);
+  gw->ev = c->gev;
+  return KFBI_OK;
 }
 
 // Host status slots after the Arnoldi ring: the last residual norm and ||b||.
@@ -562,8 +643,9 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
 
 using namespace kfbi;
 
-extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b, double* x,
-                                const kfbi_gmres_opts* o, kfbi_gmres_stats* stats) {
+namespace kfbi {
+static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, double* x,
+                            const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, bool use_static) {
   if (!c || !op || !b || !x || !o) {
     set_error("null argument");
     return KFBI_E_INVALID;
@@ -584,7 +666,15 @@ extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b
     return KFBI_E_INVALID;
   }
   GmresWork gw;
-  bind_work(c, &gw);
+  if (use_static) {
+    if (c->M > kStaticMaxM) {
+      set_error("the static GMRES workspace holds at most %d markers (M = %d)", kStaticMaxM, c->M);
+      return KFBI_E_INVALID;
+    }
+    KFBI_TRY(bind_static(c, &gw));
+  } else {
+    bind_work(c, &gw);
+  }
   const int M = c->M;
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   kfbi_gmres_stats loc{};
@@ -644,7 +734,7 @@ extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b
       // rhs of the correction equation: keep r in gw.d, solve for the correction in gw.w+?
       double* rr = gw.d;
       KFBI_HIP(hipMemcpyAsync(rr, gw.r, sizeof(double) * M, hipMemcpyDeviceToDevice, c->stream));
-      double* dcorr = c->tmpM.as<double>();
+      double* dcorr = gw.dcorr;
       KFBI_HIP(hipMemsetAsync(dcorr, 0, sizeof(double) * M, c->stream));
       int it_in = 0, cyc = 0, a32 = 0;
       double rel_in = 0.0;
@@ -670,4 +760,16 @@ extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b
     set_error("GMRES did not reach tol %.3e in %d iterations (relres %.3e)", o->tol, loc.iters,
               loc.relres);
   return status;
+}
+}  // namespace kfbi
+
+extern "C" int kfbi_gmres_solve(kfbi_ctx* c, const kfbi_bie* op, const double* b, double* x,
+                                const kfbi_gmres_opts* o, kfbi_gmres_stats* stats) {
+  return gmres_solve_impl(c, op, b, x, o, stats, false);
+}
+
+extern "C" int kfbi_gmres_solve_static(kfbi_ctx* c, const kfbi_bie* op, const double* b,
+                                       double* x, const kfbi_gmres_opts* o,
+                                       kfbi_gmres_stats* stats) {
+  return gmres_solve_impl(c, op, b, x, o, stats, true);
 }

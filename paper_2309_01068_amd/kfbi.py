@@ -23,7 +23,8 @@ FP64, FP32 = 0, 1
 
 EXPORTS = [
     "kfbi_last_error", "kfbi_create", "kfbi_destroy", "kfbi_set_interface", "kfbi_get_info",
-    "kfbi_apply", "kfbi_apply_batch", "kfbi_operator", "kfbi_gmres_solve", "kfbi_profile", "kfbi_profile_read",
+    "kfbi_apply", "kfbi_apply_batch", "kfbi_operator", "kfbi_gmres_solve", "kfbi_gmres_solve_static",
+    "kfbi_profile", "kfbi_profile_read",
     "kfbi_profile_kernel",
     "thetaL_create", "thetaL_destroy", "thetaL_init", "thetaL_step", "thetaL_run",
     "thetaL_markers", "thetaL_density", "thetaL_kfbi", "thetaL_get_state", "thetaL_set_state",
@@ -156,6 +157,8 @@ def load(path: str = LIBPATH):
     lib.kfbi_operator.argtypes = [vp, C.POINTER(Bie), C.c_int, vp, vp]
     lib.kfbi_gmres_solve.argtypes = [vp, C.POINTER(Bie), vp, vp, C.POINTER(GmresOpts),
                                      C.POINTER(GmresStats)]
+    lib.kfbi_gmres_solve_static.argtypes = [vp, C.POINTER(Bie), vp, vp, C.POINTER(GmresOpts),
+                                            C.POINTER(GmresStats)]
     lib.kfbi_profile.argtypes = [vp, C.c_int]
     lib.kfbi_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_long)]
     lib.kfbi_profile_kernel.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
@@ -313,12 +316,14 @@ class Context:
         return us.value
 
     def gmres(self, rhs, x, layer, side, a, b, q, tol=1e-10, restart=50, maxit=1000,
-              precision=FP64, inner_tol=1e-5, raise_noconv=True):
+              precision=FP64, inner_tol=1e-5, raise_noconv=True, static_workspace=False):
+        """kfbi_gmres_solve, or kfbi_gmres_solve_static (the Krylov workspace in the
+        library's static device array, no allocation) with static_workspace=True."""
         op = self._bie(layer, side, a, b, q)
         opts = GmresOpts(tol, restart, maxit, precision, inner_tol)
         st = GmresStats()
-        code = self.lib.kfbi_gmres_solve(self.h, C.byref(op), _ptr(rhs), _ptr(x), C.byref(opts),
-                                         C.byref(st))
+        fn = self.lib.kfbi_gmres_solve_static if static_workspace else self.lib.kfbi_gmres_solve
+        code = fn(self.h, C.byref(op), _ptr(rhs), _ptr(x), C.byref(opts), C.byref(st))
         if code == E_NOCONV and not raise_noconv:
             return x, st.as_dict()
         _check(code)
