@@ -7,9 +7,10 @@ grid arithmetic, densities = seeded random Fourier series (modes 1..32, amplitud
 N(0,1)/k^2), eight densities cycled.  Inputs are resident in HBM before timing.
 
 Prints one JSON line with the headline value plus:
-  roofline      the slowest of the four kernels of an apply: algorithmic bytes over its
-                average duration (back-to-back replays between two HIP events), with the
-                per-kernel table and the in-apply stage times
+  roofline      the dominant kernel of an apply (the one the committed rocprofv3 summary
+                names): algorithmic bytes over its average duration measured live (HIP
+                events around each launch over the timed applies); the whole apply's
+                algorithmic bytes over its timed duration; the per-kernel table
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
   extra         2048^2 and FP32 rates, GMRES time to 1e-10 for plain FP64, FP32-inner
                 refinement (same true FP64 residual)
@@ -62,7 +63,7 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(info, N, M, wbytes, layer_double=False, batch=1):
+def algorithmic_bytes(info, N, M, wbytes, batch=1):
     """Bytes each kernel of one apply must move at least (per launch), from its inputs and
     outputs: n = N-1 sine modes, A arms, P row parts, nb = row_hi-row_lo+1 rows of G written
     by the column solve, R = rows holding interpolation nodes, w = 8 (FP64) or 4 (FP32).
@@ -96,7 +97,9 @@ def algorithmic_bytes(info, N, M, wbytes, layer_double=False, batch=1):
     }
 
 
-STAGES = ["k_prep", "k_rowdst", "k_colsolve", "k_nodes_extract"]
+# (stage index of kfbi_profile / kfbi_profile_kernel, kernel) of the launches of an apply
+KERNELS = [(0, "k_prep"), (1, "k_rowdst"), (2, "k_colsolve"), (3, "k_nodes_extract")]
+STAGES = [k for _, k in KERNELS]
 
 
 def measured_traffic(kname, N, precision):
@@ -104,9 +107,7 @@ def measured_traffic(kname, N, precision):
     FETCH_SIZE / WRITE_SIZE summary of this workload, scaled by the copy calibration; None
     when there is no summary for it or the kernel source changed after it was taken."""
     import hashlib
-    if N != 1024 or precision != 0:
-        return None
-    path = os.path.join(ROOT, "profiles", "kfbi_apply_star2048_1024_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"kfbi_apply_star2048_{N}_{'f64' if precision == 0 else 'f32'}_traffic.json")
     src = os.path.join(ROOT, "paper_2309_01068_amd", "csrc", "apply.hip")
     try:
         rec = json.load(open(path))
@@ -119,15 +120,26 @@ def measured_traffic(kname, N, precision):
         return None
 
 
+def profiled_dominant(N, precision):
+    """The kernel with the largest total time in the committed rocprofv3 kernel-trace
+    summary of this workload, or None."""
+    path = os.path.join(ROOT, "profiles", f"kfbi_apply_star2048_{N}_{'f64' if precision == 0 else 'f32'}_kernel_stats.json")
+    try:
+        rec = json.load(open(path))
+        return rec["dominant"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def replay_kernels(ctx, reps, rounds=5):
-    """Average duration (us) of each of the four kernels of the last apply, replayed
-    back to back (reps per kernel in all), the kernels taking turns over `rounds` rounds."""
+    """Average duration (us) of each kernel of the last apply, replayed back to back (reps
+    per kernel in all), the kernels taking turns over `rounds` rounds."""
     per = max(2, reps // rounds)
-    tot = [0.0] * 4
+    tot = {k: 0.0 for k in STAGES}
     for _ in range(rounds):
-        for q in range(4):
-            tot[q] += ctx.profile_kernel(q, reps=per)
-    return [t / rounds for t in tot]
+        for q, k in KERNELS:
+            tot[k] += ctx.profile_kernel(q, reps=per)
+    return {k: t / rounds for k, t in tot.items()}
 
 
 def time_applies(ctx, kf, dens, outs, steps, warmup, layer, precision):
@@ -145,6 +157,40 @@ def time_applies(ctx, kf, dens, outs, steps, warmup, layer, precision):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / 1e3, wall
+
+
+def time_graph_applies(kf, torch, X, box, c2, dens, layer, precision, steps, per_graph=8):
+    """Applies replayed from a HIP graph: per_graph consecutive kfbi_apply calls (the same
+    kernels and buffers as eager calls) captured once on a side stream, then replayed
+    steps / per_graph times between two events on that stream.  Returns (seconds, steps)."""
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = kf.Context(box.x0, box.y0, box.side, box.N, c2, kf.BOX_ZERO, X.shape[1], stream=s)
+        ctx.set_interface(torch.tensor(X, device="cuda"))
+        outs = {k: torch.empty(X.shape[1], dtype=torch.float64, device="cuda")
+                for k in ("v_plus", "v_minus", "dn_plus", "dn_minus")}
+        for i in range(16):
+            ctx.apply(layer, dens[i % len(dens)], precision, out=outs)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for i in range(per_graph):
+            ctx.apply(layer, dens[i % len(dens)], precision, out=outs)
+    torch.cuda.synchronize()
+    reps = max(1, steps // per_graph)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        for _ in range(4):
+            g.replay()
+        e0.record(s)
+        for _ in range(reps):
+            g.replay()
+        e1.record(s)
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    ctx.close()
+    return secs, reps * per_graph
 
 
 def main():
@@ -186,19 +232,19 @@ def main():
     secs, wall = time_applies(ctx, kf, dens, outs, a.steps, a.warmup, layer, a.precision)
     value = a.steps / secs
     ms_per_step = 1e3 * secs / a.steps
+    gsecs, gsteps = time_graph_applies(kf, torch, X, box, c2, dens, layer, a.precision, a.steps)
 
-    # per-kernel durations: each kernel of the last apply replayed back to back on the
-    # context stream between two HIP events (no events between the launches); the four
-    # kernels take turns over several rounds, so that all of them see the same clock state
-    kern_us = replay_kernels(ctx, a.reps)
-    # in-apply stage times: HIP events around every kernel of the same applies
+    # per-kernel durations, live: HIP events on the context stream around every kernel of
+    # the same applies (a second timed pass of the workload; kfbi_profile)
     ctx.profile(True)
-    for i in range(min(a.steps, 1024)):
+    for i in range(min(a.steps, 2048)):
         ctx.apply(layer, dens[i % 8], a.precision, out=outs)
     ms, napp = ctx.profile_read()
     ctx.profile(False)
-    stage_us = [1e3 * m / max(napp, 1) for m in ms]
-    # host cost of issuing one apply (Python binding + four launches), no synchronisation
+    live_us = {k: 1e3 * ms[q] / max(napp, 1) for q, k in KERNELS}
+    # and replayed back to back (no events between the launches)
+    replay_us = replay_kernels(ctx, a.reps)
+    # host cost of issuing one apply (Python binding + launches), no synchronisation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(200):
@@ -207,17 +253,23 @@ def main():
     torch.cuda.synchronize()
     wb = 8 if a.precision == 0 else 4
     byts = algorithmic_bytes(info, a.N, M, wb)
-    dom = max(range(4), key=lambda q: kern_us[q])
-    kname = STAGES[dom]
-    achieved = byts[kname] / (kern_us[dom] * 1e-6) / 1e9
-    traffic = measured_traffic(kname, a.N, a.precision)
+    prof_dom = profiled_dominant(a.N, a.precision)
+    kname = prof_dom if prof_dom in live_us else max(live_us, key=live_us.get)
+    achieved = byts[kname] / (live_us[kname] * 1e-6) / 1e9
+    whole = sum(byts.values())
+    whole_ach = whole / (ms_per_step * 1e-3) / 1e9
     roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "algorithmic_bytes": byts[kname], "avg_us": round(kern_us[dom], 3),
-            "kernels": {STAGES[q]: {"avg_us": round(kern_us[q], 3), "bytes": byts[STAGES[q]],
-                                    "GB_s": round(byts[STAGES[q]] / kern_us[q] / 1e3, 1)}
-                        for q in range(4)},
-            "in_apply_stage_us": {STAGES[q]: round(stage_us[q], 3) for q in range(4)},
+            "traffic": measured_traffic(kname, a.N, a.precision),
+            "algorithmic_bytes": byts[kname], "avg_us": round(live_us[kname], 3),
+            "dominant_from": "committed rocprofv3 summary" if prof_dom == kname else "live timing",
+            "whole_apply": {"algorithmic_bytes": whole, "us": round(ms_per_step * 1e3, 3),
+                            "achieved": round(whole_ach, 1),
+                            "frac": round(whole_ach / HBM_PEAK_GBS, 4)},
+            "kernels": {k: {"avg_us": round(live_us[k], 3), "replay_us": round(replay_us[k], 3),
+                            "bytes": byts[k], "GB_s": round(byts[k] / live_us[k] / 1e3, 1),
+                            "frac": round(byts[k] / live_us[k] / 1e3 / HBM_PEAK_GBS, 4)}
+                        for k in STAGES},
             "host_issue_us_per_apply": round(issue_us, 2)}
     result = {
         "metric": "KFBI applies/s at 1024^2 (single layer, modified Helmholtz, star, 2048 markers)"
@@ -233,6 +285,9 @@ def main():
                    "row_parts": info["n_parts"], "node_rows": info["n_rows"],
                    "band_rows": info["row_hi"] - info["row_lo"] + 1},
         "wall_s": round(wall, 4),
+        "graph": {"applies_per_s": round(gsteps / gsecs, 1),
+                  "us_per_apply": round(1e6 * gsecs / gsteps, 3), "steps": gsteps,
+                  "note": "the same applies replayed from a captured HIP graph (8 per graph)"},
         "roofline": roof,
     }
 
@@ -352,9 +407,8 @@ def batched(kf, W, torch, np, dev, a):
         out[f"B{B}"] = {
             "densities_per_s": round(B * reps / secs, 1), "us_per_batch": round(1e6 * secs / reps, 2),
             "launches": nl, "launch_batch": lb,
-            "kernels": {STAGES[q]: {"avg_us": round(kern[q], 3), "bytes": byts[STAGES[q]],
-                                    "GB_s": round(byts[STAGES[q]] / kern[q] / 1e3, 1)}
-                        for q in range(4)}}
+            "kernels": {k: {"replay_us": round(kern[k], 3), "bytes": byts[k],
+                            "GB_s": round(byts[k] / kern[k] / 1e3, 1)} for k in STAGES}}
     ctx.close()
     return out
 
