@@ -8,9 +8,9 @@ N(0,1)/k^2), eight densities cycled.  Inputs are resident in HBM before timing.
 
 Prints one JSON line with the headline value plus:
   roofline      the dominant kernel of an apply (the one the committed rocprofv3 summary
-                names): algorithmic bytes over its average duration measured live (HIP
-                events around each launch over the timed applies); the whole apply's
-                algorithmic bytes over its driver-timed duration; the per-kernel table
+                names): algorithmic bytes over its average duration (back-to-back replays
+                between two HIP events on the context stream); the whole apply's
+                algorithmic bytes over its timed duration; the per-kernel table
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
   extra         2048^2 and FP32 rates, GMRES time to 1e-10 for plain FP64, FP32-inner
                 refinement (same true FP64 residual)
@@ -43,10 +43,10 @@ def parse():
                     help="back-to-back replays per kernel for the per-kernel durations")
     ap.add_argument("--hs-steps", type=int, default=200,
                     help="Hele-Shaw steps timed per evolution (the workload runs 200)")
-    ap.add_argument("--ws-train-runs", type=int, default=24,
-                    help="training evolutions for the learned warm start (56 = full set)")
-    ap.add_argument("--ws-test-runs", type=int, default=4,
-                    help="held-out evolutions for the learned warm start (8 = full set)")
+    ap.add_argument("--ws-train-runs", type=int, default=56,
+                    help="training evolutions for the learned warm start (seeds 0..)")
+    ap.add_argument("--ws-test-runs", type=int, default=8,
+                    help="held-out evolutions for the learned warm start (seeds 56..)")
     ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--stefan-steps", type=int, default=60,
                     help="Stefan steps timed (the dendrite workload runs 500)")
@@ -100,6 +100,10 @@ def algorithmic_bytes(info, N, M, wbytes, batch=1):
 # (stage index of kfbi_profile / kfbi_profile_kernel, kernel) of the launches of an apply
 KERNELS = [(0, "k_prep"), (1, "k_rowdst"), (2, "k_colsolve"), (3, "k_nodes_extract")]
 STAGES = [k for _, k in KERNELS]
+# GMRES precision modes: FP64; FP32 operator inside FP64 iterative refinement; FP64 GMRES
+# whose applies are FP32 once the residual estimate is below MIXED_THRESH ||b||
+PREC_NAMES = {0: "f64", 1: "f32ir", 2: "mixed"}
+MIXED_THRESH = 1e-4
 
 
 def measured_traffic(kname, N, precision):
@@ -234,15 +238,15 @@ def main():
     ms_per_step = 1e3 * secs / a.steps
     gsecs, gsteps = time_graph_applies(kf, torch, X, box, c2, dens, layer, a.precision, a.steps)
 
-    # per-kernel durations, live: HIP events on the context stream around every kernel of
-    # the same applies (a second timed pass of the workload; kfbi_profile)
+    # per-kernel durations inside applies: HIP events on the context stream around every
+    # kernel of the same applies (a second timed pass; the events add to each kernel)
     ctx.profile(True)
     for i in range(min(a.steps, 2048)):
         ctx.apply(layer, dens[i % 8], a.precision, out=outs)
     ms, napp = ctx.profile_read()
     ctx.profile(False)
     live_us = {k: 1e3 * ms[q] / max(napp, 1) for q, k in KERNELS}
-    # and replayed back to back (no events between the launches)
+    # and replayed back to back (no events between the launches): the durations used
     replay_us = replay_kernels(ctx, a.reps)
     # host cost of issuing one apply (Python binding + launches), no synchronisation
     torch.cuda.synchronize()
@@ -254,21 +258,24 @@ def main():
     wb = 8 if a.precision == 0 else 4
     byts = algorithmic_bytes(info, a.N, M, wb)
     prof_dom = profiled_dominant(a.N, a.precision)
-    kname = prof_dom if prof_dom in live_us else max(live_us, key=live_us.get)
-    achieved = byts[kname] / (live_us[kname] * 1e-6) / 1e9
+    kname = prof_dom if prof_dom in replay_us else max(replay_us, key=replay_us.get)
+    achieved = byts[kname] / (replay_us[kname] * 1e-6) / 1e9
     whole = sum(byts.values())
     whole_ach = whole / (ms_per_step * 1e-3) / 1e9
     roof = {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(kname, a.N, a.precision),
-            "algorithmic_bytes": byts[kname], "avg_us": round(live_us[kname], 3),
-            "dominant_from": "committed rocprofv3 summary" if prof_dom == kname else "live timing",
+            "algorithmic_bytes": byts[kname], "avg_us": round(replay_us[kname], 3),
+            "avg_us_from": "the kernel replayed back to back between two HIP events on the "
+                           "context stream (kfbi_profile_kernel)",
+            "dominant_from": "committed rocprofv3 summary" if prof_dom == kname else "replay timing",
             "whole_apply": {"algorithmic_bytes": whole, "us": round(ms_per_step * 1e3, 3),
                             "achieved": round(whole_ach, 1),
                             "frac": round(whole_ach / HBM_PEAK_GBS, 4)},
-            "kernels": {k: {"avg_us": round(live_us[k], 3), "replay_us": round(replay_us[k], 3),
-                            "bytes": byts[k], "GB_s": round(byts[k] / live_us[k] / 1e3, 1),
-                            "frac": round(byts[k] / live_us[k] / 1e3 / HBM_PEAK_GBS, 4)}
+            "kernels": {k: {"avg_us": round(replay_us[k], 3),
+                            "in_apply_us": round(live_us[k], 3),
+                            "bytes": byts[k], "GB_s": round(byts[k] / replay_us[k] / 1e3, 1),
+                            "frac": round(byts[k] / replay_us[k] / 1e3 / HBM_PEAK_GBS, 4)}
                         for k in STAGES},
             "host_issue_us_per_apply": round(issue_us, 2)}
     result = {
@@ -311,32 +318,51 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(X, box, dens_np, c2, budget):
     """The FP64 numpy/scipy oracle (as it stands) on the same workload: geometry once,
-    then applies until about `budget` seconds have passed."""
+    then applies until about `budget` seconds have passed, first with one thread (BLAS
+    pools limited to one thread; scipy.fft at its default of one worker), then with every
+    host core given to scipy.fft and BLAS (numpy's elementwise work stays on one thread)."""
     try:
         from oracle import geometry as G
         from oracle import kfbi as K
+        import scipy.fft as sfft
+        import threadpoolctl
     except Exception as e:  # pragma: no cover
         return {"error": repr(e)}
     g = G.build_geometry(X, box)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        K.apply(g, K.SINGLE, dens_np[n % len(dens_np)], c2)
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget or n >= 2000:
-            break
-    try:
-        import threadpoolctl
-        pools = threadpoolctl.threadpool_info()
-        cores = max([p.get("num_threads", 1) for p in pools] + [1])
-    except Exception:
-        cores = 1
-    return {"value": round(n / el, 3), "unit": "applies/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} applies of the same {box.N}^2 workload (geometry excluded), {el:.1f} s",
-            "nproc": os.cpu_count()}
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+    def rate(seconds):
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            K.apply(g, K.SINGLE, dens_np[n % len(dens_np)], c2)
+            n += 1
+            el = time.perf_counter() - t0
+            if el > seconds or n >= 2000:
+                return n, el
+    with threadpoolctl.threadpool_limits(limits=1), sfft.set_workers(1):
+        n1, el1 = rate(0.6 * budget)
+    with threadpoolctl.threadpool_limits(limits=ncpu), sfft.set_workers(ncpu):
+        nn, eln = rate(0.4 * budget)
+    return {"value": round(n1 / el1, 3), "unit": "applies/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n1} applies of the same {box.N}^2 workload (geometry excluded), "
+                      f"{el1:.1f} s, one thread",
+            "all_cores": {"value": round(nn / eln, 3), "threads": ncpu,
+                          "sample": f"{nn} applies, {eln:.1f} s, scipy.fft and BLAS on "
+                                    f"{ncpu} threads"},
+            "cpu_model": cpu_model(), "nproc": ncpu}
 
 
 def extras(kf, W, torch, np, dev, dens, layer):
@@ -360,15 +386,18 @@ def extras(kf, W, torch, np, dev, dens, layer):
     ctx.set_interface(torch.tensor(Xh, device=dev))
     r2 = Xh[0] ** 2 + Xh[1] ** 2
     b = torch.tensor(-1e-3 + 0.5 * np.log(r2), device=dev)
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
+        itol = MIXED_THRESH if prec == 2 else 1e-5
         x = torch.zeros(1024, dtype=torch.float64, device=dev)
-        ctx.gmres(b, x, kf.DOUBLE, kf.MINUS, 0.0, 1.0, 1.0, tol=1e-10, precision=prec)
+        ctx.gmres(b, x, kf.DOUBLE, kf.MINUS, 0.0, 1.0, 1.0, tol=1e-10, precision=prec,
+                  inner_tol=itol)
         x.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, st = ctx.gmres(b, x, kf.DOUBLE, kf.MINUS, 0.0, 1.0, 1.0, tol=1e-10, precision=prec)
+        x, st = ctx.gmres(b, x, kf.DOUBLE, kf.MINUS, 0.0, 1.0, 1.0, tol=1e-10, precision=prec,
+                          inner_tol=itol)
         el = time.perf_counter() - t0
-        out[f"gmres_hs_{'f64' if prec == 0 else 'f32ir'}"] = {
+        out[f"gmres_hs_{PREC_NAMES[prec]}"] = {
             "seconds": round(el, 5), "iters": st["iters"], "relres": st["relres"],
             "applies64": st["applies64"], "applies32": st["applies32"]}
     return out
@@ -446,8 +475,9 @@ def hele_shaw(kf, W, torch, np, dev, a):
     split, iterations, area and length."""
     box = W.box(-2.0, 2.0, 1024)
     out = {}
-    for prec in (0, 1):
-        th = kf.ThetaL(box.x0, box.y0, box.side, 1024, 1024, 1e-3, 1.0, 1e-3, precision=prec)
+    for prec in (0, 1, 2):
+        th = kf.ThetaL(box.x0, box.y0, box.side, 1024, 1024, 1e-3, 1.0, 1e-3, precision=prec,
+                       inner_tol=MIXED_THRESH if prec == 2 else 1e-5)
         th.init(torch.tensor(W.hs3(1024), device=dev))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -455,12 +485,14 @@ def hele_shaw(kf, W, torch, np, dev, a):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         n = len(recs)
-        key = "f64" if prec == 0 else "f32ir"
+        key = PREC_NAMES[prec]
         out[key] = {
             "steps": n, "ms_per_step": round(1e3 * el / n, 4),
             "ms_split": {k: round(sum(r[k] for r in recs) / n, 4)
                          for k in ("ms_geometry", "ms_gmres", "ms_apply", "ms_update")},
             "mean_iters": round(sum(r["iters"] for r in recs) / n, 3),
+            "applies64": round(sum(r["applies64"] for r in recs) / n, 3),
+            "applies32": round(sum(r["applies32"] for r in recs) / n, 3),
             "max_relres": max(r["relres"] for r in recs),
             "area_first_last": [recs[0]["area"], recs[-1]["area"]],
             "length_first_last": [recs[0]["length"], recs[-1]["length"]],
@@ -483,9 +515,9 @@ def stefan(kf, W, torch, np, dev, a):
     w = np.ones(N + 1)
     w[0] = w[-1] = 0.5
     out = {"workload": f"stefan seed r=0.1 box [-4,4]^2 grid {N}^2 M={M} tau={tau} St={St} BE"}
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
         sf = kf.Stefan(box.x0, box.y0, box.side, N, M, tau, eC, eV, bdf2=False, ssd=2,
-                       precision=prec)
+                       precision=prec, inner_tol=MIXED_THRESH if prec == 2 else 1e-5)
         sf.init(torch.tensor(W.circle(M, 0.1), device=dev), None, St)
 
         def energy():
@@ -502,11 +534,13 @@ def stefan(kf, W, torch, np, dev, a):
         el = time.perf_counter() - t0
         E1, A1 = energy()
         n = len(recs)
-        out["f64" if prec == 0 else "f32ir"] = {
+        out[PREC_NAMES[prec]] = {
             "steps": n, "ms_per_step": round(1e3 * el / n, 4),
             "ms_split": {k: round(sum(r[k] for r in recs) / n, 4)
                          for k in ("ms_geometry", "ms_temperature", "ms_gmres", "ms_update")},
             "mean_iters": round(sum(r["iters"] for r in recs) / n, 3),
+            "applies64": round(sum(r["applies64"] for r in recs) / n, 3),
+            "applies32": round(sum(r["applies32"] for r in recs) / n, 3),
             "max_relres": max(r["relres"] for r in recs),
             "area_first_last": [recs[0]["area"], recs[-1]["area"]],
             "energy_drift_over_area_change": round((E1 - E0) / (A1 - A0), 5),
@@ -531,8 +565,9 @@ def stefan_warm_start(kf, W, torch, np, dev, a):
 
     def make(prec=0):
         return kf.Stefan(box.x0, box.y0, box.side, N, M, tau, eC, eV, bdf2=False, ssd=2,
-                         precision=prec)
+                         precision=prec, inner_tol=MIXED_THRESH if prec == 2 else 1e-5)
     ws = kf.WarmStart(M, max_batch=64, capacity=max(a.st_train_runs * nst, 64), seed=0)
+    extrap = kf.WarmStart(M, max_batch=1, capacity=1, seed=0)
     t0 = time.perf_counter()
     used, sd = 0, 0
     while used < a.st_train_runs and sd < 4 * a.st_train_runs:
@@ -558,8 +593,8 @@ def stefan_warm_start(kf, W, torch, np, dev, a):
            "train_s": round(time.perf_counter() - t0, 2), "epochs": a.ws_epochs,
            "loss_first_last": [losses[0], losses[-1]] if losses else None}
     x0 = torch.empty(M, dtype=torch.float64, device=dev)
-    for prec in (0, 1):
-        for mode in ("zero", "previous", "learned"):
+    for prec in (0, 1, 2):
+        for mode in ("zero", "previous", "extrapolation", "learned"):
             its, tsum, nsteps = [], 0.0, 0
             for k in range(a.st_test_runs):
                 sf = make(prec)
@@ -574,7 +609,7 @@ def stefan_warm_start(kf, W, torch, np, dev, a):
                         elif mode == "previous":
                             r = sf.step()
                         else:
-                            ws.predict(sf.thetal, x0)
+                            (ws if mode == "learned" else extrap).predict(sf.thetal, x0)
                             r = sf.step(x0)
                         its.append(r["iters"])
                     torch.cuda.synchronize()
@@ -583,7 +618,7 @@ def stefan_warm_start(kf, W, torch, np, dev, a):
                 except kf.KfbiError:
                     pass
                 sf.close()
-            res[f"{'f64' if prec == 0 else 'f32ir'}_{mode}"] = {
+            res[f"{PREC_NAMES[prec]}_{mode}"] = {
                 "mean_iters": round(float(np.mean(its)), 3) if its else None,
                 "ms_per_step": round(1e3 * tsum / max(nsteps, 1), 4), "steps": nsteps}
     return res
@@ -593,15 +628,17 @@ def warm_start(kf, W, torch, np, dev, a):
     """Learned initial guess on the Hele-Shaw setup with perturbed curves
     r = 1 + sum_{m=2..8} a_m cos(m a + p_m), a_m ~ U(0, 0.1): data from training
     evolutions (seeds 0..), training on the GPU, then per-step GMRES iterations and wall
-    time on held-out evolutions (seeds 56..) for x0 = 0, the previous density and the
-    learned guess, FP64 and FP32-inner GMRES, all to the same 1e-10 FP64 residual."""
+    time on held-out evolutions (seeds 56..) for x0 = 0, the previous density, the linear
+    extrapolation 2 phi1 - phi2 (the untrained network, whose output layer is zero) and the
+    learned guess, for each GMRES precision mode, all to the same 1e-10 FP64 residual."""
     box = W.box(-2.0, 2.0, 1024)
     M, nst = 1024, a.hs_steps
     args = (box.x0, box.y0, box.side, 1024, M, 1e-3, 1.0, 1e-3)
     cap = a.ws_train_runs * nst
     ws = kf.WarmStart(M, max_batch=64, capacity=max(cap, 64), seed=0)
+    extrap = kf.WarmStart(M, max_batch=1, capacity=1, seed=0)
     t0 = time.perf_counter()
-    used = []
+    used, skipped = [], []
     sd = 0
     while len(used) < a.ws_train_runs:
         th = kf.ThetaL(*args)
@@ -612,8 +649,8 @@ def warm_start(kf, W, torch, np, dev, a):
                 th.step()
                 ws.record(th)
             used.append(sd)
-        except kf.KfbiError:  # a curve that leaves the box: replaced by the next seed
-            pass
+        except kf.KfbiError:  # a curve the grid stops resolving: replaced by the next seed
+            skipped.append(sd)
         th.close()
         sd += 1
     gen_s = time.perf_counter() - t0
@@ -622,16 +659,17 @@ def warm_start(kf, W, torch, np, dev, a):
     losses = ws.train(n, a.ws_epochs, 64)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    res = {"train_runs": len(used), "samples": n, "data_gen_s": round(gen_s, 2),
-           "train_s": round(train_s, 2), "epochs": a.ws_epochs,
+    res = {"train_runs": len(used), "skipped_seeds": skipped, "samples": n,
+           "data_gen_s": round(gen_s, 2), "train_s": round(train_s, 2), "epochs": a.ws_epochs,
            "loss_first_last": [losses[0], losses[-1]] if losses else None,
            "target_scale": ws.target_scale()}
     x0 = torch.empty(M, dtype=torch.float64, device=dev)
-    for prec in (0, 1):
-        for mode in ("zero", "previous", "learned"):
+    for prec in (0, 1, 2):
+        for mode in ("zero", "previous", "extrapolation", "learned"):
             its, tsum, nsteps = [], 0.0, 0
             for k in range(a.ws_test_runs):
-                th = kf.ThetaL(*args, precision=prec)
+                th = kf.ThetaL(*args, precision=prec,
+                               inner_tol=MIXED_THRESH if prec == 2 else 1e-5)
                 th.init(torch.tensor(W.perturbed(M, 56 + k), device=dev))
                 try:
                     torch.cuda.synchronize()
@@ -643,7 +681,7 @@ def warm_start(kf, W, torch, np, dev, a):
                         elif mode == "previous":
                             r = th.step()
                         else:
-                            ws.predict(th, x0)
+                            (ws if mode == "learned" else extrap).predict(th, x0)
                             r = th.step(x0)
                         its.append(r["iters"])
                     torch.cuda.synchronize()
@@ -652,9 +690,9 @@ def warm_start(kf, W, torch, np, dev, a):
                 except kf.KfbiError:
                     pass
                 th.close()
-            key = f"{'f64' if prec == 0 else 'f32ir'}_{mode}"
-            res[key] = {"mean_iters": round(float(np.mean(its)), 3) if its else None,
-                        "ms_per_step": round(1e3 * tsum / max(nsteps, 1), 4), "steps": nsteps}
+            res[f"{PREC_NAMES[prec]}_{mode}"] = {
+                "mean_iters": round(float(np.mean(its)), 3) if its else None,
+                "ms_per_step": round(1e3 * tsum / max(nsteps, 1), 4), "steps": nsteps}
     return res
 
 

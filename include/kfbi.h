@@ -62,6 +62,8 @@ extern "C" {
 /* arithmetic of the grid stages (jumps, corrections, solve, interpolation) */
 #define KFBI_FP64 0
 #define KFBI_FP32 1
+/* GMRES only: FP64 GMRES whose operator applies switch to FP32 as the residual falls */
+#define KFBI_MIXED 2
 
 typedef struct kfbi_ctx kfbi_ctx;
 
@@ -179,8 +181,17 @@ typedef struct {
   int restart;       /* Krylov dimension before restart, 1..64                         */
   int maxit;         /* cap on inner iterations (all cycles)                           */
   int precision;     /* KFBI_FP64: plain GMRES; KFBI_FP32: FP32 operator inside FP64
-                        iterative refinement (residuals always with the FP64 operator) */
-  double inner_tol;  /* relative tolerance of each FP32 inner solve (KFBI_FP32 only)    */
+                        iterative refinement (residuals always with the FP64 operator);
+                        KFBI_MIXED: one FP64 GMRES (FP64 Krylov basis, Hessenberg matrix,
+                        rotations) whose Arnoldi applies run in FP32 once the residual
+                        estimate is at most inner_tol ||b||, the relaxation of inexact
+                        Krylov methods (an apply may be less accurate as the residual
+                        falls); convergence still on the true FP64 residual, and a cycle
+                        that used FP32 applies and ends above tol is followed by cycles
+                        with FP64 applies only                                          */
+  double inner_tol;  /* KFBI_FP32: relative tolerance of each FP32 inner solve (0: 1e-5);
+                        KFBI_MIXED: relative residual below which applies are FP32
+                        (0: 1e-5)                                                       */
 } kfbi_gmres_opts;
 
 typedef struct {

@@ -105,6 +105,101 @@ __host__ __device__ __forceinline__ int kprep_region(int M, int nd) {
   return r > 256 * kReg ? r : 256 * kReg;
 }
 
+// Free-space box data of one K1 ring block in arithmetic R: thread (node nd, slice sl) sums
+// the trapezoid terms of one slice of the markers, staged in LDS ((x, y, phi y_a, phi x_a)
+// for the double layer, (x, y, psi s_a / 2) for the single layer) kRingChunk markers at a
+// time, every thread's loads of a chunk in flight together; the slices are then added in
+// order.  Writes ring (FP64, when R is double) and ringT (FP32 copy, when given).
+constexpr int kRingChunk = 2048;
+template <class R>
+__device__ __forceinline__ void ring_sums(double* lds, int tid, int sl, int nd, int S, bool live,
+                                          int node, int M, int layer,
+                                          const double* __restrict__ X,
+                                          const double* __restrict__ geo,
+                                          const double* __restrict__ dens, R zx, R zy,
+                                          double* __restrict__ ring, float* __restrict__ ringT) {
+  const int CH = M < kRingChunk ? M : kRingChunk;
+  R* cx = reinterpret_cast<R*>(lds);
+  R* cy = cx + CH;
+  R* ca = cy + CH;
+  R* cb = ca + CH;
+  R acc = R(0);
+  constexpr int U = kRingChunk / 256;
+  for (int c0 = 0; c0 < M; c0 += CH) {
+    const int nk = min(CH, M - c0);
+    if (c0 > 0) __syncthreads();
+    {
+      R vx[U], vy[U], va[U], vb[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {  // loads first, all in flight
+        const int e = tid + 256 * u;
+        const int k = c0 + e;
+        vx[u] = vy[u] = va[u] = vb[u] = R(0);
+        if (e < nk) {
+          vx[u] = static_cast<R>(X[k]);
+          vy[u] = static_cast<R>(X[M + k]);
+          if (layer == KFBI_DOUBLE) {
+            const double f = dens[k];
+            va[u] = static_cast<R>(f * geo[M + k]);
+            vb[u] = static_cast<R>(f * geo[k]);
+          } else {
+            va[u] = static_cast<R>(0.5 * dens[k] * geo[4 * M + k]);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = tid + 256 * u;
+        if (e < nk) {
+          cx[e] = vx[u];
+          cy[e] = vy[u];
+          ca[e] = va[u];
+          cb[e] = vb[u];
+        }
+      }
+    }
+    __syncthreads();
+    // slice sl takes markers sl, sl + S, sl + 2S, ...: the slices of a wavefront read
+    // consecutive LDS entries (no bank conflicts)
+    if (layer == KFBI_DOUBLE) {
+#pragma unroll 4
+      for (int q = sl; q < nk; q += S) {
+        const R dx = cx[q] - zx, dy = cy[q] - zy;
+        // 1 / |d|^2 from the hardware reciprocal and Newton steps (|d| >= 3h, far from the
+        // under- and overflow range): two in FP64, one in FP32
+        const R d2 = dx * dx + dy * dy;
+        R rc;
+        if constexpr (sizeof(R) == 8) {
+          rc = __builtin_amdgcn_rcp(d2);
+          rc = fma(fma(-d2, rc, 1.0), rc, rc);
+          rc = fma(fma(-d2, rc, 1.0), rc, rc);
+        } else {
+          rc = __builtin_amdgcn_rcpf(d2);
+          rc = fmaf(fmaf(-d2, rc, 1.0f), rc, rc);
+        }
+        acc += (dx * ca[q] - dy * cb[q]) * rc;
+      }
+    } else {
+#pragma unroll 4
+      for (int q = sl; q < nk; q += S) {
+        const R dx = cx[q] - zx, dy = cy[q] - zy;
+        acc += ca[q] * log(dx * dx + dy * dy);
+      }
+    }
+  }
+  __syncthreads();
+  R* part = reinterpret_cast<R*>(lds);  // S x kRingNodes
+  part[sl * kRingNodes + nd] = acc;
+  __syncthreads();
+  if (tid < kRingNodes && live) {
+    R v = R(0);
+    for (int q = 0; q < S; ++q) v += part[q * kRingNodes + tid];
+    v /= static_cast<R>(M);
+    if constexpr (sizeof(R) == 8) ring[node] = v;
+    if (ringT) ringT[node] = static_cast<float>(v);
+  }
+}
+
 // ---------------------------------------------------------------------------------- K1
 // Marker-chunk blocks [0, nmk): derivatives at markers k0..k1-1 with phi, d1, d2 staged
 // in LDS; every thread accumulates kReg consecutive outputs over a slice of m with a
@@ -117,7 +212,7 @@ __global__ void __launch_bounds__(256)
            const double* __restrict__ geo, double* __restrict__ ring, float* __restrict__ ringT,
            const int* __restrict__ ckoff, const int* __restrict__ cklist,
            const double* __restrict__ ckc, const int* __restrict__ ckk, int cap,
-           double* __restrict__ rarm) {
+           double* __restrict__ rarm, int ring32) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
   {  // density blockIdx.y of a batch: its own slices of every per-density array
@@ -144,69 +239,12 @@ __global__ void __launch_bounds__(256)
       zx = (side == 2) ? x0 : (side == 3 ? x0 + N * h : x0 + r * h);
       zy = (side == 0) ? y0 : (side == 1 ? y0 + N * h : y0 + r * h);
     }
-    // markers staged in LDS in chunks of 256: (x, y, phi y_a, phi x_a) for the double
-    // layer, (x, y, psi s_a / 2) for the single layer; slice sl takes 256/S of each chunk
-    double* cx = lds;
-    double* cy = cx + 256;
-    double* ca = cy + 256;
-    double* cb = ca + 256;
-    double acc = 0.0;
-    // software pipeline: the next chunk's markers are loaded while this one is summed
-    double px = 0.0, py = 0.0, pa = 0.0, pb = 0.0;
-    auto fetch = [&](int c0) {
-      const int k = c0 + tid;
-      if (k < M) {
-        px = X[k];
-        py = X[M + k];
-        if (layer == KFBI_DOUBLE) {
-          const double f = dens[k];
-          pa = f * geo[M + k];
-          pb = f * geo[k];
-        } else {
-          pa = 0.5 * dens[k] * geo[4 * M + k];
-        }
-      }
-    };
-    fetch(0);
-    for (int c0 = 0; c0 < M; c0 += 256) {
-      __syncthreads();
-      cx[tid] = px;
-      cy[tid] = py;
-      ca[tid] = pa;
-      cb[tid] = pb;
-      __syncthreads();
-      if (c0 + 256 < M) fetch(c0 + 256);
-      const int nk = min(256, M - c0);
-      const int q0 = sl * (256 / S), q1 = min(nk, q0 + 256 / S);
-      if (layer == KFBI_DOUBLE) {
-#pragma unroll 4
-        for (int q = q0; q < q1; ++q) {
-          const double dx = cx[q] - zx, dy = cy[q] - zy;
-          // 1 / |d|^2 from the hardware reciprocal and two Newton steps (|d| >= 3h, far
-          // from the under- and overflow range), cheaper than the division sequence
-          const double d2 = dx * dx + dy * dy;
-          double rc = __builtin_amdgcn_rcp(d2);
-          rc = fma(fma(-d2, rc, 1.0), rc, rc);
-          rc = fma(fma(-d2, rc, 1.0), rc, rc);
-          acc += (dx * ca[q] - dy * cb[q]) * rc;
-        }
-      } else {
-#pragma unroll 4
-        for (int q = q0; q < q1; ++q) {
-          const double dx = cx[q] - zx, dy = cy[q] - zy;
-          acc += ca[q] * log(dx * dx + dy * dy);
-        }
-      }
-    }
-    __syncthreads();
-    double* part = lds;  // S x kRingNodes
-    part[sl * kRingNodes + nd] = acc;
-    __syncthreads();
-    if (tid < kRingNodes && live) {
-      double v = 0.0;
-      for (int q = 0; q < S; ++q) v += part[q * kRingNodes + tid];
-      ring[node] = v / M;
-      if (ringT) ringT[node] = static_cast<float>(v / M);
+    if (ring32) {  // an FP32 apply: the box data in FP32 (its only consumer is FP32)
+      ring_sums<float>(lds, tid, sl, nd, S, live, node, M, layer, X, geo, dens,
+                       static_cast<float>(zx), static_cast<float>(zy), ring, ringT);
+    } else {
+      ring_sums<double>(lds, tid, sl, nd, S, live, node, M, layer, X, geo, dens, zx, zy, ring,
+                        ringT);
     }
     return;
   }
@@ -544,6 +582,43 @@ __global__ void __launch_bounds__(256)
     rq0[u] = (j <= n) ? rowpart[j] : 0;
     rq1[u] = (j <= n) ? rowpart[j + 1] : 0;
   }
+  // box data (issued with the slab loads below, consumed after the row sums): the left
+  // (i=0) and right (i=N) box nodes next to (1, j) and (N-1, j) of this thread's rows, and
+  // this wavefront's sine sums of the bottom (j=0) and top (j=N) box rows
+  const int n1 = N + 1;
+  T gl[R], gr[R], s1[kColsPerBlock], sn[kColsPerBlock];
+  T sb = T(0), st = T(0);
+  if (ring) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int j = 1 + tid + 256 * u;
+      gl[u] = (j <= n) ? ring[2 * n1 + j] : T(0);
+      gr[u] = (j <= n) ? ring[3 * n1 + j] : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < kColsPerBlock; ++c) {
+      s1[c] = sinTg[(p0 + c) & mask];
+      sn[c] = sinTg[((p0 + c) * n) & mask];
+    }
+    // sin(p i pi / N) at i = 1 + lane + 64 u by the three-term recurrence in steps of
+    // 64 p pi / N from two table values per lane (rounding grows at most E-fold)
+    const int quarter = N / 2;
+    const int m0 = (p * (1 + lane)) & mask, m64 = (64 * p) & mask;
+    T a = sinTg[m0], c = sinTg[(m0 + quarter) & mask];
+    const T sb64 = sinTg[m64], cb64 = sinTg[(m64 + quarter) & mask];
+    const T c2 = cb64 + cb64;
+    T am = a * cb64 - c * sb64;  // sin(p (1 + lane - 64) pi / N)
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int i = 1 + lane + 64 * u;
+      const bool in = (i <= n);
+      sb += (in ? ring[i] : T(0)) * a;
+      st += (in ? ring[n1 + i] : T(0)) * a;
+      const T an = c2 * a - am;
+      am = a;
+      a = an;
+    }
+  }
   // the group's part rows are contiguous: P x 4 values
   {
     const T* src = Tg + static_cast<size_t>(grp) * P * 4;
@@ -563,7 +638,9 @@ __global__ void __launch_bounds__(256)
     }
   }
   __syncthreads();
-  // rows: sum of their parts in part order (rows without arms are zero)
+  // rows: sum of their parts in part order (rows without arms are zero), then the left
+  // and right box terms
+  const T ih2 = static_cast<T>(1.0 / (h * h));
   {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
@@ -574,49 +651,17 @@ __global__ void __launch_bounds__(256)
         for (int qq = rq0[u]; qq < rq1[u]; ++qq)
 #pragma unroll
           for (int c = 0; c < kColsPerBlock; ++c) a4[c] += tp[4 * qq + c];
+        if (ring)
+#pragma unroll
+          for (int c = 0; c < kColsPerBlock; ++c)
+            a4[c] -= ih2 * (gl[u] * s1[c] + gr[u] * sn[c]);
       }
 #pragma unroll
       for (int c = 0; c < kColsPerBlock; ++c) col[c][slot<E>(j)] = a4[c];
     }
   }
   __syncthreads();
-  if (ring) {
-    const T ih2 = static_cast<T>(1.0 / (h * h));
-    // left (i=0) and right (i=N) box nodes next to (1, j) and (N-1, j)
-    const int n1 = N + 1;
-    T s1[kColsPerBlock], sn[kColsPerBlock];
-#pragma unroll
-    for (int c = 0; c < kColsPerBlock; ++c) {
-      s1[c] = sinTg[(p0 + c) & mask];
-      sn[c] = sinTg[((p0 + c) * n) & mask];
-    }
-    constexpr int RJ = (64 * E + 255) / 256;
-    T gl[RJ], gr[RJ];
-#pragma unroll
-    for (int u = 0; u < RJ; ++u) {
-      const int j = 1 + tid + 256 * u;
-      gl[u] = (j <= n) ? ring[2 * n1 + j] : T(0);
-      gr[u] = (j <= n) ? ring[3 * n1 + j] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < RJ; ++u) {
-      const int j = 1 + tid + 256 * u;
-      if (j <= n)
-#pragma unroll
-        for (int c = 0; c < kColsPerBlock; ++c)
-          col[c][slot<E>(j)] -= ih2 * (gl[u] * s1[c] + gr[u] * sn[c]);
-    }
-    __syncthreads();
-    // bottom (j=0) and top (j=N) box rows: a full sine sum each, loads issued together
-    T sb = T(0), st = T(0);
-#pragma unroll
-    for (int u = 0; u < E; ++u) {
-      const int i = 1 + lane + 64 * u;
-      const bool in = (i <= n);
-      const T sv = in ? sinTg[(p * i) & mask] : T(0);
-      sb += (in ? ring[i] : T(0)) * sv;
-      st += (in ? ring[n1 + i] : T(0)) * sv;
-    }
+  if (ring) {  // bottom and top box rows: rows 1 and n of this wavefront's mode
     sb = wave_sum(sb);
     st = wave_sum(st);
     if (lane == 0) {
@@ -1371,7 +1416,9 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
   // block_sum scratch) and the window quantities; ring blocks: four chunks of 256 markers
   const size_t lds_mk = static_cast<size_t>((lpad(M - 1) + 1) + kprep_region(M, nd) +
                                             16 * kReg + 5 * kWinMax);
-  const size_t lds = sizeof(double) * (lds_mk > 4 * 256 ? lds_mk : 4 * 256);
+  // ring blocks: four arrays of min(M, kRingChunk) markers
+  const size_t lds_ring = nring > 0 ? 4 * static_cast<size_t>(M < kRingChunk ? M : kRingChunk) : 0;
+  const size_t lds = sizeof(double) * (lds_mk > lds_ring ? lds_mk : lds_ring);
   if (stages & 1)
     hipLaunchKernelGGL(k_prep, dim3(nmk + nring, B), dim3(256), lds, s, M, C, nmk, layer, dens,
                        c->dvec.as<double>(), c->dvec.as<double>() + M, c->mq.as<double>(),
@@ -1381,7 +1428,7 @@ static int apply_t(kfbi_ctx* c, int B, int layer, const double* dens, const doub
                        c->h, c->X.as<double>(), c->geo.as<double>(), ring64,
                        sizeof(T) == 4 ? ring32 : nullptr, c->ckoff.as<int>(),
                        c->cklist.as<int>(), c->ckcoef.as<double>(), c->ckmk.as<int>(),
-                       c->arm_cap, c->armr.as<double>());
+                       c->arm_cap, c->armr.as<double>(), sizeof(T) == 4 ? 1 : 0);
   if (c->box_bc == KFBI_BOX_FREESPACE) {
     ringT = sizeof(T) == 8 ? reinterpret_cast<T*>(ring64) : reinterpret_cast<T*>(ring32);
     rstride = sizeof(T) == 8 ? 8 * static_cast<size_t>(N + 1) : 16 * static_cast<size_t>(N + 1);

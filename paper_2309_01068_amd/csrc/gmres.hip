@@ -258,21 +258,18 @@ __global__ void __launch_bounds__(kArnThreads)
   p = wave_sum(p);
   if (lane == 0) red[0][wv] = p;
   __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int q = 0; q < NW; ++q) s += red[0][q];
-    const double hn = sqrt(s);
-    hess_column(j, hv[0], hv[1], hn, csh, snh, gj, H, cs, sn, g, st, hout);
-    red[1][0] = hn;
-  }
-  __syncthreads();
-  const double hn = red[1][0];
+  // every thread forms h_{j+1,j} from the same partials in the same order and stores its
+  // part of V_{j+1} at once; thread 0 meanwhile finishes the Hessenberg column
+  double s = 0.0;
+  for (int q = 0; q < NW; ++q) s += red[0][q];
+  const double hn = sqrt(s);
   double* vn = V + static_cast<size_t>(j + 1) * ldv;
 #pragma unroll
   for (int u = 0; u < kArnPer; ++u) {
     const int k = tid + u * kArnThreads;
     if (k < M) vn[k] = (hn != 0.0) ? wk[u] / hn : 0.0;
   }
+  if (tid == 0) hess_column(j, hv[0], hv[1], hn, csh, snh, gj, H, cs, sn, g, st, hout);
 }
 
 __global__ void k_scale(int M, const double* __restrict__ w, const double* __restrict__ hn,
@@ -535,15 +532,26 @@ static int true_residual(kfbi_ctx* c, const kfbi_bie* op, int precision, const d
 // residual (same precision) is <= tol * nb or after maxit Arnoldi steps.
 // With r_ready the residual of the incoming x is already in gw->r and the device status,
 // with norm rn0, and the first cycle starts from it.
+// Mixed mode (mixed_thresh > 0, precision FP64): the applies of the Arnoldi steps run in
+// FP32 once the last residual estimate the host has read is at most mixed_thresh * nb,
+// the Krylov basis, the Hessenberg matrix, the rotations and every true residual staying
+// FP64 (relaxed inexact Krylov: the perturbation an apply may carry grows as the
+// residual falls).  A cycle that used FP32 applies and ends above tol is followed by
+// cycles with FP64 applies only; applies32 counts the FP32 applies.
 static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* b, double* x,
                       double nb, double tol, int restart, int maxit, GmresWork* gw, int* iters,
-                      int* cycles, int* applies, double* relres, bool r_ready, double rn0) {
+                      int* cycles, int* applies, double* relres, bool r_ready, double rn0,
+                      double mixed_thresh = 0.0, int* applies32 = nullptr) {
   const int M = c->M;
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   const int mb = (M + 255) / 256;
   hipStream_t s = c->stream;
   double rn = 0.0;
+  bool allow32 = mixed_thresh > 0.0;
+  bool used32 = false;  // the cycle just finished ran FP32 applies
   for (;;) {
+    if (used32) allow32 = false;  // reached here: that cycle did not converge on its own
+    used32 = false;
     if (r_ready) {
       rn = rn0;
       r_ready = false;
@@ -604,8 +612,15 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
       if (j < restart && base + launched < maxit) {
         double* vj = gw->V + static_cast<size_t>(j) * gw->ldv;
         double* vn = gw->V + static_cast<size_t>(j + 1) * gw->ldv;
-        KFBI_TRY(apply_impl(c, op->layer, precision, vj, nullptr, nullptr, op, vj, gw->w));
-        ++*applies;
+        const bool as32 = allow32 && r1 <= mixed_thresh * nb;
+        KFBI_TRY(apply_impl(c, op->layer, as32 ? KFBI_FP32 : precision, vj, nullptr, nullptr, op,
+                            vj, gw->w));
+        if (as32) {
+          used32 = true;
+          if (applies32) ++*applies32;
+        } else {
+          ++*applies;
+        }
         GmresStatus* sj = gw->ring + (j % kRing);
         GmresStatus* hj = gw->dring + (j % kRing);  // device view of the host ring slot
         if (one_block) {
@@ -659,7 +674,7 @@ static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, do
     return KFBI_E_INVALID;
   }
   if (o->restart < 1 || o->restart > kMaxRestart || o->maxit < 1 || !(o->tol > 0.0) ||
-      (o->precision != KFBI_FP64 && o->precision != KFBI_FP32) ||
+      (o->precision != KFBI_FP64 && o->precision != KFBI_FP32 && o->precision != KFBI_MIXED) ||
       (op->layer != KFBI_SINGLE && op->layer != KFBI_DOUBLE) || op->side < KFBI_PLUS ||
       op->side > KFBI_AVG) {
     set_error("invalid GMRES options or operator");
@@ -694,11 +709,14 @@ static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, do
     KFBI_HIP(hipMemsetAsync(x, 0, sizeof(double) * M, c->stream));
     KFBI_HIP(hipStreamSynchronize(c->stream));
     loc.converged = 1;
-  } else if (o->precision == KFBI_FP64) {
-    int applies = 0;
+  } else if (o->precision == KFBI_FP64 || o->precision == KFBI_MIXED) {
+    int applies = 0, applies32 = 0;
+    const double thresh =
+        o->precision == KFBI_MIXED ? (o->inner_tol > 0.0 ? o->inner_tol : 1e-5) : 0.0;
     status = gmres_core(c, op, KFBI_FP64, b, x, nb, o->tol, o->restart, o->maxit, &gw, &loc.iters,
-                        &loc.outer_iters, &applies, &loc.relres, true, rn0);
+                        &loc.outer_iters, &applies, &loc.relres, true, rn0, thresh, &applies32);
     loc.applies64 += applies;
+    loc.applies32 += applies32;
     loc.converged = (status == KFBI_OK);
   } else {
     // iterative refinement: r = b - A64 x ; A32 d = r ; x += d

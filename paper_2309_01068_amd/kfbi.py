@@ -19,7 +19,7 @@ OK, E_INVALID, E_GEOMETRY, E_NOCONV, E_HIP, E_NOMEM, E_NONFINITE, E_STATE = rang
 SINGLE, DOUBLE = 0, 1
 PLUS, MINUS, AVG = 0, 1, 2
 BOX_ZERO, BOX_USER, BOX_FREESPACE, BOX_NEUMANN = 0, 1, 2, 3
-FP64, FP32 = 0, 1
+FP64, FP32, MIXED = 0, 1, 2
 
 EXPORTS = [
     "kfbi_last_error", "kfbi_create", "kfbi_destroy", "kfbi_set_interface", "kfbi_get_info",

@@ -13,16 +13,11 @@ from oracle import geometry as G
 from oracle import kfbi as K
 from paper_2309_01068_amd import workloads as W
 
+from parity import TOL32, check, rel
+
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-10
-TOL32 = 5e-5
-
-
-def rel(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
 def make_ctx(box, c2, box_bc, M):
@@ -70,9 +65,7 @@ def test_apply_parity_fp64(name, X, box, c2, bc, layer):
     assert info["n_cross_h"] == g.hx.line.size and info["n_cross_v"] == g.vx.line.size
     for k, r in (("v_plus", ref.v_plus), ("v_minus", ref.v_minus), ("dn_plus", ref.dn_plus),
                  ("dn_minus", ref.dn_minus)):
-        e = rel(out[k], r)
-        print(f"  {k}: rel {e:.3e}")
-        assert e <= TOL64, (k, e)
+        check(out[k], r, TOL64, k)
 
 
 @pytest.mark.parametrize("layer", [K.SINGLE, K.DOUBLE])
@@ -85,9 +78,7 @@ def test_apply_parity_user_ring(layer, c):
     g, ref, ctx, out = run_pair(X, box, c * c, K.BOX_USER, layer, dens, ring=ring, grid=True)
     for k, r in (("v_plus", ref.v_plus), ("v_minus", ref.v_minus), ("dn_plus", ref.dn_plus),
                  ("dn_minus", ref.dn_minus), ("grid", ref.grid)):
-        e = rel(out[k], r)
-        print(f"  {k}: rel {e:.3e}")
-        assert e <= TOL64, (k, e)
+        check(out[k], r, TOL64, k)
 
 
 def test_full_grid_parity():
@@ -95,10 +86,8 @@ def test_full_grid_parity():
     X = W.star(512)
     dens = W.fourier_density(512, seed=3)
     g, ref, ctx, out = run_pair(X, box, 1000.0, K.BOX_ZERO, K.DOUBLE, dens, grid=True)
-    e = rel(out["grid"], ref.grid)
-    print(f"  grid: rel {e:.3e}")
-    assert e <= TOL64
-    assert rel(out["v_plus"], ref.v_plus) <= TOL64
+    check(out["grid"], ref.grid, TOL64, "grid")
+    check(out["v_plus"], ref.v_plus, TOL64, "v_plus")
 
 
 @pytest.mark.parametrize("N", [1024, 2048])
@@ -113,20 +102,18 @@ def test_config2_full_size(N, precision):
         g, ref, ctx, out = run_pair(X, box, 1000.0, K.BOX_ZERO, layer, dens, precision=precision)
         for k, r in (("v_plus", ref.v_plus), ("v_minus", ref.v_minus), ("dn_plus", ref.dn_plus),
                      ("dn_minus", ref.dn_minus)):
-            e = rel(out[k], r)
-            print(f"  N={N} prec={precision} layer={layer} {k}: rel {e:.3e}")
-            assert e <= (TOL64 if precision == 0 else TOL32), (k, e)
+            check(out[k], r, TOL64 if precision == 0 else TOL32[k],
+                  f"N={N} prec={precision} layer={layer} {k}")
 
 
-@pytest.mark.parametrize("name,X,box,c2,bc", CASES[:3], ids=[c[0] for c in CASES[:3]])
+@pytest.mark.parametrize("name,X,box,c2,bc", CASES, ids=[c[0] for c in CASES])
 def test_apply_parity_fp32(name, X, box, c2, bc):
     dens = W.fourier_density(X.shape[1], seed=5)
     for layer in (K.SINGLE, K.DOUBLE):
         g, ref, ctx, out = run_pair(X, box, c2, bc, layer, dens, precision=1)
-        for k, r in (("v_plus", ref.v_plus), ("v_minus", ref.v_minus)):
-            e = rel(out[k], r)
-            print(f"  fp32 {name} layer={layer} {k}: rel {e:.3e}")
-            assert e <= TOL32, (k, e)
+        for k, r in (("v_plus", ref.v_plus), ("v_minus", ref.v_minus), ("dn_plus", ref.dn_plus),
+                     ("dn_minus", ref.dn_minus)):
+            check(out[k], r, TOL32[k], f"fp32 {name} layer={layer} {k}")
 
 
 def test_operator_parity_hele_shaw_and_dirichlet():
@@ -139,7 +126,7 @@ def test_operator_parity_hele_shaw_and_dirichlet():
     ctx = make_ctx(box, 0.0, K.BOX_FREESPACE, 256)
     ctx.set_interface(dev(X))
     y = host(ctx.operator(dev(x), kfbi.DOUBLE, kfbi.MINUS, 0.0, 1.0, 1.0))
-    assert rel(y, ref) <= TOL64
+    check(y, ref, TOL64, "operator")
     X = W.ellipse(256)
     box = W.box(-1, 1, 128)
     g = G.build_geometry(X, box)
@@ -147,7 +134,7 @@ def test_operator_parity_hele_shaw_and_dirichlet():
     ctx = make_ctx(box, 0.0, K.BOX_ZERO, 256)
     ctx.set_interface(dev(X))
     y = host(ctx.operator(dev(x), kfbi.DOUBLE, kfbi.PLUS, 0.25, 1.0, 0.0))
-    assert rel(y, ref) <= TOL64
+    check(y, ref, TOL64, "operator")
 
 
 def test_apply_is_bitwise_reproducible():
@@ -172,7 +159,7 @@ def test_reinstalling_a_smaller_interface():
         out = ctx.apply(K.DOUBLE, dev(d))
         g = G.build_geometry(X, box)
         ref = K.apply(g, K.DOUBLE, d, 1000.0)
-        assert rel(host(out["v_plus"]), ref.v_plus) <= TOL64
+        check(host(out["v_plus"]), ref.v_plus, TOL64, "v_plus")
 
 
 def test_error_paths():
@@ -200,7 +187,7 @@ def test_error_paths():
     ctx.set_interface(dev(X))
     d = W.fourier_density(256, seed=1)
     ref = K.apply(G.build_geometry(X, box), K.DOUBLE, d, 0.0)
-    assert rel(host(ctx.apply(K.DOUBLE, dev(d))["v_plus"]), ref.v_plus) <= TOL64
+    check(host(ctx.apply(K.DOUBLE, dev(d))["v_plus"]), ref.v_plus, TOL64, "v_plus")
 
 
 def test_profile_kernel_replay_leaves_results_intact():
@@ -225,7 +212,7 @@ def test_profile_kernel_replay_leaves_results_intact():
         ctx.profile_kernel(4, 8)
     assert e.value.code == kfbi.E_INVALID
     ref = K.apply(G.build_geometry(X, box), K.SINGLE, d, 1000.0)
-    assert rel(host(ctx.apply(K.SINGLE, dev(d))["v_plus"]), ref.v_plus) <= TOL64
+    check(host(ctx.apply(K.SINGLE, dev(d))["v_plus"]), ref.v_plus, TOL64, "v_plus")
 
 
 def _poke_circle(N, frac):

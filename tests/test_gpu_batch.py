@@ -13,6 +13,8 @@ from oracle import geometry as G
 from oracle import kfbi as K
 from paper_2309_01068_amd import workloads as W
 
+from parity import check, rel
+
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-10
@@ -45,8 +47,7 @@ def check_batch(ctx, layer, D, precision, rings=None, oracle=None):
         for b in (0, B - 1):
             ref = K.apply(g, layer, D[b], c2, bc, None if rings is None else rings[b])
             for k in KEYS:
-                e = rel(out[k][b].cpu().numpy(), getattr(ref, k))
-                assert e <= TOL64, (b, k, e)
+                check(out[k][b].cpu().numpy(), getattr(ref, k), TOL64, f"density {b} {k}")
     return out
 
 

@@ -15,15 +15,11 @@ from oracle import kfbi as K
 from oracle.gmres import gmres
 from paper_2309_01068_amd import workloads as W
 
+from parity import check, rel
+
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-10
-
-
-def rel(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
 def dev(a):
@@ -41,9 +37,7 @@ def check_apply(X, box, c2, bc, layer, dens, max_markers=None):
     out = ctx.apply(layer, dev(dens))
     torch.cuda.synchronize()
     for k in ("v_plus", "v_minus", "dn_plus", "dn_minus"):
-        e = rel(out[k].cpu().numpy(), getattr(ref, k))
-        print(f"  {k}: rel {e:.3e}")
-        assert e <= TOL64, (k, e)
+        check(out[k].cpu().numpy(), getattr(ref, k), TOL64, k)
     return ctx, ref
 
 
@@ -82,7 +76,7 @@ def test_ragged_last_chunk_batched():
         ref = K.apply(g, K.SINGLE, dens[b], 1000.0)
         for k in ("v_plus", "dn_minus"):
             assert torch.equal(out[k][b], one[k])
-            assert rel(out[k][b].cpu().numpy(), getattr(ref, k)) <= TOL64
+            check(out[k][b].cpu().numpy(), getattr(ref, k), TOL64, f"density {b} {k}")
 
 
 @pytest.mark.parametrize("layer", [K.SINGLE, K.DOUBLE])
