@@ -547,9 +547,11 @@ __global__ void __launch_bounds__(256)
                const double* __restrict__ colc, const double* __restrict__ lanef, int jlo,
                int jhi, T* __restrict__ Gg, int nblk_x, size_t tstride, size_t rstride,
                size_t gstride, int ldr) {
-  __shared__ T col[kColsPerBlock][64 * (E + 1)];
-  extern __shared__ double dynp[];  // the group's P part rows, 4 modes each
+  // dynamic LDS: the group's P part rows (4 modes each), then over the same bytes the
+  // four modes' columns (each lane's E rows padded to E + 1)
+  extern __shared__ double dynp[];
   T* tp = reinterpret_cast<T*>(dynp);
+  T (*col)[64 * (E + 1)] = reinterpret_cast<T (*)[64 * (E + 1)]>(dynp);
   const int n = N - 1;
   const int mask = 2 * N - 1;
   const int tid = threadIdx.x;
@@ -642,22 +644,29 @@ __global__ void __launch_bounds__(256)
   // and right box terms
   const T ih2 = static_cast<T>(1.0 / (h * h));
   {
+    T a4[R][kColsPerBlock];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int j = 1 + tid + 256 * u;
+#pragma unroll
+      for (int c = 0; c < kColsPerBlock; ++c) a4[u][c] = T(0);
+      if (j <= n) {
+        for (int qq = rq0[u]; qq < rq1[u]; ++qq)
+#pragma unroll
+          for (int c = 0; c < kColsPerBlock; ++c) a4[u][c] += tp[4 * qq + c];
+        if (ring)
+#pragma unroll
+          for (int c = 0; c < kColsPerBlock; ++c)
+            a4[u][c] -= ih2 * (gl[u] * s1[c] + gr[u] * sn[c]);
+      }
+    }
+    __syncthreads();  // the part rows are read: their bytes become the columns
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int j = 1 + tid + 256 * u;
       if (j > 64 * E) continue;
-      T a4[kColsPerBlock] = {};
-      if (j <= n) {
-        for (int qq = rq0[u]; qq < rq1[u]; ++qq)
 #pragma unroll
-          for (int c = 0; c < kColsPerBlock; ++c) a4[c] += tp[4 * qq + c];
-        if (ring)
-#pragma unroll
-          for (int c = 0; c < kColsPerBlock; ++c)
-            a4[c] -= ih2 * (gl[u] * s1[c] + gr[u] * sn[c]);
-      }
-#pragma unroll
-      for (int c = 0; c < kColsPerBlock; ++c) col[c][slot<E>(j)] = a4[c];
+      for (int c = 0; c < kColsPerBlock; ++c) col[c][slot<E>(j)] = a4[u][c];
     }
   }
   __syncthreads();
@@ -793,9 +802,11 @@ __global__ void __launch_bounds__(256)
                    const double* __restrict__ colc, const double* __restrict__ lanef, int jlo,
                    int jhi, T* __restrict__ Gg, int nblk_x, size_t tstride, size_t gstride,
                    int ldr) {
-  __shared__ T col[kColsPerBlock][64 * (E + 1)];
-  extern __shared__ double dynp[];  // the group's P part rows, 4 modes each
+  // dynamic LDS: the group's P part rows (4 modes each), then over the same bytes the
+  // four modes' columns (each lane's E rows padded to E + 1)
+  extern __shared__ double dynp[];
   T* tp = reinterpret_cast<T*>(dynp);
+  T (*col)[64 * (E + 1)] = reinterpret_cast<T (*)[64 * (E + 1)]>(dynp);
   const int nm = N + 1;  // modes and rows
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
@@ -846,25 +857,33 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
   {
     const T tca = static_cast<T>(ca), tcb = static_cast<T>(cb);
+    T a4[R][kColsPerBlock];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int r = tid + 256 * u;
+#pragma unroll
+      for (int c = 0; c < kColsPerBlock; ++c) a4[u][c] = T(0);
       if (r >= 64 * E) continue;
-      T a4[kColsPerBlock] = {};
       for (int qq = rq0[u]; qq < rq1[u]; ++qq)
 #pragma unroll
-        for (int c = 0; c < kColsPerBlock; ++c) a4[c] += tp[4 * qq + c];
+        for (int c = 0; c < kColsPerBlock; ++c) a4[u][c] += tp[4 * qq + c];
       if (Fa && r <= N) {
         const size_t o = (static_cast<size_t>(grp) * nm + r) * 4;
 #pragma unroll
         for (int c = 0; c < kColsPerBlock; ++c) {
           T f = tca * Fa[o + c];
           if (Fb) f += tcb * Fb[o + c];
-          a4[c] += f;
+          a4[u][c] += f;
         }
       }
+    }
+    __syncthreads();  // the part rows are read: their bytes become the columns
 #pragma unroll
-      for (int c = 0; c < kColsPerBlock; ++c) col[c][slot0<E>(r)] = a4[c];
+    for (int u = 0; u < R; ++u) {
+      const int r = tid + 256 * u;
+      if (r >= 64 * E) continue;
+#pragma unroll
+      for (int c = 0; c < kColsPerBlock; ++c) col[c][slot0<E>(r)] = a4[u][c];
     }
   }
   __syncthreads();
@@ -1247,6 +1266,14 @@ __global__ void k_grid_ring(int N, const T* __restrict__ ring, double* __restric
 
 static inline int nblk(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
 
+// Dynamic LDS elements of a column-solve block: the P part rows of its group (4 modes
+// each), later overwritten by its four columns of 64 (E + 1) rows.
+static inline size_t colsolve_lds_elems(int P, int E) {
+  const size_t parts = 4 * static_cast<size_t>(P > 0 ? P : 1);
+  const size_t cols = static_cast<size_t>(kColsPerBlock) * 64 * (E + 1);
+  return parts > cols ? parts : cols;
+}
+
 template <class K>
 static const void* kptr(K kernel) {
   return reinterpret_cast<const void*>(kernel);
@@ -1273,7 +1300,7 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   if (ev) hipEventRecord(ev[2], s);
   const int ngrp = nblk(n, kColsPerBlock);
   const int nb = ((ngrp + 7) / 8) * 8;
-  const size_t lds_dyn = sizeof(T) * 4 * static_cast<size_t>(P > 0 ? P : 1);
+  const size_t lds_dyn = sizeof(T) * colsolve_lds_elems(P, E);
   if (stages & 4)
     hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P, Tg,
                        c->rowpart.as<int>(), sinT, ring, c->colc.as<double>(),
@@ -1334,7 +1361,7 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
                        tstride);
   if (ev) hipEventRecord(ev[2], s);
   const int nb = ((ngm + 7) / 8) * 8;
-  const size_t lds_dyn = sizeof(T) * 4 * static_cast<size_t>(P > 0 ? P : 1);
+  const size_t lds_dyn = sizeof(T) * colsolve_lds_elems(P, E);
   if (stages & 4)
     hipLaunchKernelGGL((k_colsolve_neu<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P,
                        Tg, c->rowpart.as<int>(), static_cast<const T*>(rr.Fa),
