@@ -1,0 +1,159 @@
+"""The paper's numerical experiments that print no numbers, run on the GPU path as checks
+of the properties the paper states for them (Sec. 6.1.1 temporal convergence of the
+Hele-Shaw flow; Sec. 6.2.1 grid refinement of the Stefan problem; Sec. 6.2.4 anisotropic
+dendritic growth).  The paper shows these as figures only, so the assertions are the
+properties its text claims (second order in time; convergence under grid refinement and
+preserved symmetry; growth along the directions of vanishing surface tension), with
+margins measured on an MI355X noted next to each bound.
+
+The spatial order of Sec. 6.1.1 is not checked: with the paper's tau = 1e-3 the area error
+at T = 1 is 2e-6 to 8e-6 on 128^2 to 1024^2 grids (markers 1.1 h apart), set by the time
+step rather than the grid.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2309_01068_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def area(X):
+    """Enclosed area (1/2) int (x y_a - y x_a) da with spectral derivatives of the markers."""
+    x, y = X
+    M = x.size
+    k = np.fft.fftfreq(M, 1.0 / M)
+    k[M // 2] = 0
+    dy = np.real(np.fft.ifft(1j * k * np.fft.fft(y)))
+    dx = np.real(np.fft.ifft(1j * k * np.fft.fft(x)))
+    return 0.5 * np.mean(x * dy - y * dx) * 2 * math.pi
+
+
+def radius_at(X, angles):
+    """Distance from the origin of the closed curve through the markers along the polar
+    angles, from its trigonometric interpolant sampled 32 times more finely."""
+    x, y = X
+    M = x.size
+    F = 32 * M
+
+    def up(v):
+        V = np.fft.fft(v)
+        P = np.zeros(F, complex)
+        h = M // 2
+        P[:h] = V[:h]
+        P[-h:] = V[-h:]
+        return np.real(np.fft.ifft(P)) * F / M
+
+    xf, yf = up(x), up(y)
+    th = np.unwrap(np.arctan2(yf, xf))
+    rf = np.hypot(xf, yf)
+    thc = np.concatenate([th, th[:1] + 2 * math.pi])
+    rc = np.concatenate([rf, rf[:1]])
+    return np.array([np.interp((a - th[0]) % (2 * math.pi) + th[0], thc, rc) for a in angles])
+
+
+def nonsym_amplitude(eta, m):
+    """Largest Fourier amplitude of eta at wavenumbers that are not multiples of m, relative
+    to the largest at multiples of m."""
+    c = np.abs(np.fft.rfft(eta)) / eta.size
+    ks = np.arange(c.size)
+    return float(np.max(c[(ks % m) != 0][1:]) / max(np.max(c[(ks % m) == 0][1:]), 1e-300))
+
+
+def test_hele_shaw_time_stepping_is_second_order():
+    """Sec. 6.1.1: four-fold flower r = 0.8 + 0.2 cos 4a, surface tension 0.01, no injection,
+    box (-1.5, 1.5)^2; 512^2 grid, 1024 markers, T = 0.5 with tau = 2e-3, 1e-3, 5e-4.  The
+    enclosed area is conserved by the flow; its error and the differences of the radius
+    along a = 0 fall by about four per halving (measured: area 2.3e-5, 5.2e-6, 8.4e-7;
+    radius differences 1.05e-5, 3.3e-6)."""
+    from paper_2309_01068_amd import kfbi
+    box = W.box(-1.5, 1.5, 512)
+    X0 = W.polar_curve(lambda a: 0.8 + 0.2 * np.cos(4 * a), 1024)
+    errs, r0 = [], []
+    for tau in (2e-3, 1e-3, 5e-4):
+        print(f"[case] hele-shaw tau={tau}", flush=True)
+        th = kfbi.ThetaL(box.x0, box.y0, box.side, box.N, 1024, 0.01, 0.0, tau)
+        th.init(dev(X0))
+        A0 = area(th.markers().cpu().numpy())
+        th.run(int(round(0.5 / tau)))
+        X = th.markers().cpu().numpy()
+        errs.append(abs(area(X) - A0) / A0)
+        r0.append(radius_at(X, [0.0])[0])
+    print("area errors", errs, "radii", r0)
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
+    d1, d2 = r0[0] - r0[1], r0[1] - r0[2]
+    assert 2.5 < d1 / d2 < 6.5, (d1, d2)
+
+
+def test_stefan_grid_refinement():
+    """Sec. 6.2.1: flower seed r = 0.1 + 0.02 cos 4a in (-2, 2)^2, St = -0.5, isotropic
+    eps_C = eps_V = 2e-3, tau = 1e-3, BDF2; grids 128^2, 256^2 and 512^2 with 16, 32 and 64
+    markers (1.26 h apart) doubled as the crystal grows (refinement at 2.1 h), 400 steps.
+    The interface keeps its four-fold symmetry to round-off on every grid (measured: the
+    other Fourier amplitudes of eta at 2e-14 to 5e-14), and the 256^2 interface is much closer to the 512^2 one than
+    the 128^2 interface is (measured: max radius differences 2.9e-2 and 2.8e-3, enclosed
+    areas 3.912, 3.850 and 3.843)."""
+    from paper_2309_01068_amd import kfbi
+    ang = np.linspace(0, 2 * math.pi, 64, endpoint=False)
+    r, areas = {}, {}
+    for N, M in ((128, 16), (256, 32), (512, 64)):
+        print(f"[case] stefan grid N={N}", flush=True)
+        box = W.box(-2, 2, N)
+        iso = (2e-3, 0.0, 0.0, 4, 0.0)
+        g = kfbi.Stefan(box.x0, box.y0, box.side, box.N, M, 1e-3, iso, iso, bdf2=True, ssd=2,
+                        tol=1e-10, refine=2.1, max_M=2048)
+        g.init(dev(W.polar_curve(lambda a: 0.1 + 0.02 * np.cos(4 * a), M)), St=-0.5)
+        a_prev = area(g.markers().cpu().numpy())
+        for k in range(4):
+            g.run(100)
+            a_now = area(g.markers().cpu().numpy())
+            assert a_now > a_prev      # the undercooled liquid solidifies
+            a_prev = a_now
+        eta, _ = g.interface()
+        assert nonsym_amplitude(eta.cpu().numpy(), 4) < 1e-10
+        X = g.markers().cpu().numpy()
+        r[N] = radius_at(X, ang)
+        areas[N] = a_prev
+    e128 = np.max(np.abs(r[128] - r[512]))
+    e256 = np.max(np.abs(r[256] - r[512]))
+    print(f"max |r_N - r_512|: N=128 {e128:.3e}, N=256 {e256:.3e}; areas {areas}")
+    assert e256 < 5e-3 and e256 < e128 / 4
+    assert abs(areas[256] - areas[512]) < abs(areas[128] - areas[512]) / 4
+
+
+@pytest.mark.parametrize("name,lo,N,m,a0,St", [
+    ("fourfold_a0_0", 4.0, 512, 4, 0.0, -0.65),
+    ("fourfold_a0_pi4", 4.0, 512, 4, math.pi / 4, -0.65),
+    ("sixfold", 2.0, 256, 6, 0.0, -0.55),
+])
+def test_anisotropic_dendrite_grows_along_the_zero_tension_directions(name, lo, N, m, a0, St):
+    """Sec. 6.2.4: eps_C = 0.002 (8/3) sin^4(m/2 (phi - a0)) (= 0.002 (1 - 4/3 cos m(phi - a0)
+    + 1/3 cos 2m(phi - a0))), eps_V = 0.002, seed circle of radius 0.05 in (-lo, lo)^2,
+    tau = 5e-4 to t = 0.1, markers refined as the crystal grows.  The surface tension
+    vanishes along a0 + 2 pi k / m, so the crystal grows m tips there: the tips reach more
+    than twice (four-fold; measured 4.2) or 1.3 times (six-fold, measured 1.5) the radius
+    midway between them, for a0 = 0 and for a0 = pi/4 (tips along the grid diagonals)
+    alike, and the four-fold crystals keep their symmetry to round-off."""
+    from paper_2309_01068_amd import kfbi
+    print(f"[case] dendrite {name}", flush=True)
+    box = W.box(-lo, lo, N)
+    g = kfbi.Stefan(box.x0, box.y0, box.side, box.N, 16, 5e-4, (0.002, -4 / 3, 1 / 3, m, a0),
+                    (0.002, 0.0, 0.0, m, 0.0), bdf2=True, ssd=2, tol=1e-10, refine=2.1,
+                    max_M=2048)
+    g.init(dev(W.circle(16, 0.05)), St=St)
+    g.run(200)
+    X = g.markers().cpu().numpy()
+    rr = radius_at(X, a0 + np.arange(2 * m) * math.pi / m)
+    tips, mids = rr[0::2], rr[1::2]
+    print("tips", tips, "midway", mids, "markers", g.M)
+    assert np.min(tips) > (2.0 if m == 4 else 1.3) * np.max(mids)
+    if m == 4:
+        eta, _ = g.interface()
+        assert nonsym_amplitude(eta.cpu().numpy(), 4) < 1e-10
