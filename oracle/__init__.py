@@ -14,6 +14,8 @@ kfbi      jumps (App. A.1), corrected RHS (Sec. 4.2.1), DST-I solve, box data (S
           corrected interpolation (Sec. 4.3) -> one operator apply.
 gmres     restarted GMRES with modified Gram-Schmidt (Sec. 4 intro, matrix-free).
 thetal    theta-L / small-scale-decomposition Hele-Shaw step (Sec. 3.1, 5.1-5.3).
+stokes    modified Stokes interface problem on the MAC grid: App. A.2 jumps, corrected
+          scheme (Sec. 4.2.2), velocity traces, double-layer operator of eq. ms-bie.
 convnet   FP64 1-D convolutional warm-start network forward/backward (reference for
           gradient checks of the learned warm start; not part of the paper).
 
