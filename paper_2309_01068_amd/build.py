@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkfbi.so")
-SOURCES = ["api.hip", "geometry.hip", "apply.hip", "gmres.hip", "thetal.hip", "warmstart.hip"]
+SOURCES = ["api.hip", "geometry.hip", "apply.hip", "gmres.hip", "thetal.hip", "warmstart.hip",
+           "stokes.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

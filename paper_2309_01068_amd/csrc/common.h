@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <string>
 
 #include "../../include/kfbi.h"
@@ -169,6 +170,11 @@ int thetal_kernel_attrs();
 size_t colsolve_lds_capacity(const kfbi_ctx* c);
 // GMRES workspace for max_markers and the largest restart (kfbi_create).
 int gmres_alloc(kfbi_ctx* c);
+// y = A x for GMRES; the flag asks for the operator in FP32 (iterative refinement and
+// mixed modes).
+using GmresOp = std::function<int(const double* x, double* y, bool fp32)>;
+int gmres_solve_op(kfbi_ctx* c, int n, const GmresOp& op, const double* b, double* x,
+                   const kfbi_gmres_opts* o, kfbi_gmres_stats* stats);
 // Device address of the static GMRES workspace on the current device (once per device).
 int static_scratch_setup();
 

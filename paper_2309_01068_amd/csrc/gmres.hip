@@ -402,10 +402,9 @@ int gmres_alloc(kfbi_ctx* c) {
   return KFBI_OK;
 }
 
-// Pointers into the workspace for the installed interface (M <= max_markers).
-static void bind_work(kfbi_ctx* c, GmresWork* gw) {
-  const int M = c->M;
-  const int ldv = ((M + 63) / 64) * 64;
+// Pointers into the workspace for vectors of length n <= max_markers.
+static void bind_work(kfbi_ctx* c, GmresWork* gw, int n) {
+  const int ldv = ((n + 63) / 64) * 64;
   gw->V = c->gV.as<double>();
   gw->ldv = ldv;
   gw->H = c->gH.as<double>();
@@ -511,14 +510,13 @@ static int bind_static(kfbi_ctx* c, GmresWork* gw) {
 // Host status slots after the Arnoldi ring: the last residual norm and ||b||.
 constexpr int kSlotRes = kRing, kSlotNb = kRing + 1;
 
-// ||b - A x|| with the operator at `precision`; leaves r in gw->r and the norm in the
+// ||b - A x|| with the operator (in FP32 when fp32); leaves r in gw->r and the norm in the
 // device status and host slot kSlotRes, and synchronises (which also makes every host
 // slot written before it readable).
-static int true_residual(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* b,
+static int true_residual(kfbi_ctx* c, int M, const GmresOp& op, bool fp32, const double* b,
                          const double* x, GmresWork* gw, double* out, int* applies) {
-  const int M = c->M;
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
-  KFBI_TRY(apply_impl(c, op->layer, precision, x, nullptr, nullptr, op, x, gw->y));
+  KFBI_TRY(op(x, gw->y, fp32));
   ++*applies;
   hipLaunchKernelGGL(k_residual, dim3(nblk), dim3(kRedBlock), 0, c->stream, M, b, gw->y, gw->r,
                      gw->part, gw->counter, gw->st, gw->dring + kSlotRes);
@@ -538,11 +536,10 @@ static int true_residual(kfbi_ctx* c, const kfbi_bie* op, int precision, const d
 // FP64 (relaxed inexact Krylov: the perturbation an apply may carry grows as the
 // residual falls).  A cycle that used FP32 applies and ends above tol is followed by
 // cycles with FP64 applies only; applies32 counts the FP32 applies.
-static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const double* b, double* x,
-                      double nb, double tol, int restart, int maxit, GmresWork* gw, int* iters,
-                      int* cycles, int* applies, double* relres, bool r_ready, double rn0,
-                      double mixed_thresh = 0.0, int* applies32 = nullptr) {
-  const int M = c->M;
+static int gmres_core(kfbi_ctx* c, int M, const GmresOp& op, int precision, const double* b,
+                      double* x, double nb, double tol, int restart, int maxit, GmresWork* gw,
+                      int* iters, int* cycles, int* applies, double* relres, bool r_ready,
+                      double rn0, double mixed_thresh = 0.0, int* applies32 = nullptr) {
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   const int mb = (M + 255) / 256;
   hipStream_t s = c->stream;
@@ -556,7 +553,7 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
       rn = rn0;
       r_ready = false;
     } else {
-      KFBI_TRY(true_residual(c, op, precision, b, x, gw, &rn, applies));
+      KFBI_TRY(true_residual(c, M, op, precision == KFBI_FP32, b, x, gw, &rn, applies));
     }
     if (!std::isfinite(rn)) {
       set_error("non-finite residual in GMRES");
@@ -613,8 +610,7 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
         double* vj = gw->V + static_cast<size_t>(j) * gw->ldv;
         double* vn = gw->V + static_cast<size_t>(j + 1) * gw->ldv;
         const bool as32 = allow32 && r1 <= mixed_thresh * nb;
-        KFBI_TRY(apply_impl(c, op->layer, as32 ? KFBI_FP32 : precision, vj, nullptr, nullptr, op,
-                            vj, gw->w));
+        KFBI_TRY(op(vj, gw->w, as32 || precision == KFBI_FP32));
         if (as32) {
           used32 = true;
           if (applies32) ++*applies32;
@@ -659,6 +655,9 @@ static int gmres_core(kfbi_ctx* c, const kfbi_bie* op, int precision, const doub
 using namespace kfbi;
 
 namespace kfbi {
+static int gmres_run(kfbi_ctx* c, int M, const GmresOp& op, const double* b, double* x,
+                     const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, GmresWork* gwp);
+
 static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, double* x,
                             const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, bool use_static) {
   if (!c || !op || !b || !x || !o) {
@@ -688,9 +687,21 @@ static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, do
     }
     KFBI_TRY(bind_static(c, &gw));
   } else {
-    bind_work(c, &gw);
+    bind_work(c, &gw, c->M);
   }
-  const int M = c->M;
+  // the boundary operator a x + b trace(layer[x]) + q int x ds of the installed interface
+  const GmresOp op_fn = [c, op](const double* xin, double* yout, bool fp32) {
+    return apply_impl(c, op->layer, fp32 ? KFBI_FP32 : KFBI_FP64, xin, nullptr, nullptr, op, xin,
+                      yout);
+  };
+  return gmres_run(c, c->M, op_fn, b, x, o, stats, &gw);
+}
+
+// Restarted GMRES (FP64, FP32 iterative refinement or mixed) for the operator `op` on
+// vectors of length M, in the workspace gw, on the stream of c.
+static int gmres_run(kfbi_ctx* c, int M, const GmresOp& op, const double* b, double* x,
+                     const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, GmresWork* gwp) {
+  GmresWork& gw = *gwp;
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   kfbi_gmres_stats loc{};
   KFBI_HIP(hipMemsetAsync(gw.counter, 0, sizeof(unsigned int), c->stream));
@@ -701,7 +712,7 @@ static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, do
   KFBI_HIP(hipGetLastError());
   double rn0 = 0.0;
   int a0 = 0;
-  KFBI_TRY(true_residual(c, op, KFBI_FP64, b, x, &gw, &rn0, &a0));
+  KFBI_TRY(true_residual(c, M, op, false, b, x, &gw, &rn0, &a0));
   loc.applies64 = a0;
   const double nb = gw.hring[kSlotNb].resid;
   int status = KFBI_OK;
@@ -713,8 +724,9 @@ static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, do
     int applies = 0, applies32 = 0;
     const double thresh =
         o->precision == KFBI_MIXED ? (o->inner_tol > 0.0 ? o->inner_tol : 1e-5) : 0.0;
-    status = gmres_core(c, op, KFBI_FP64, b, x, nb, o->tol, o->restart, o->maxit, &gw, &loc.iters,
-                        &loc.outer_iters, &applies, &loc.relres, true, rn0, thresh, &applies32);
+    status = gmres_core(c, M, op, KFBI_FP64, b, x, nb, o->tol, o->restart, o->maxit, &gw,
+                        &loc.iters, &loc.outer_iters, &applies, &loc.relres, true, rn0, thresh,
+                        &applies32);
     loc.applies64 += applies;
     loc.applies32 += applies32;
     loc.converged = (status == KFBI_OK);
@@ -727,7 +739,7 @@ static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, do
       double rn = rn0;
       if (!first) {
         int a64 = 0;
-        status = true_residual(c, op, KFBI_FP64, b, x, &gw, &rn, &a64);
+        status = true_residual(c, M, op, false, b, x, &gw, &rn, &a64);
         loc.applies64 += a64;
         if (status != KFBI_OK) break;
       }
@@ -759,7 +771,7 @@ static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, do
       const double itol = o->inner_tol > 0.0 ? o->inner_tol : 1e-5;
       // the correction starts from zero, so its first residual is r itself (still in gw.r
       // and the device status)
-      const int st_in = gmres_core(c, op, KFBI_FP32, rr, dcorr, rn, itol, o->restart,
+      const int st_in = gmres_core(c, M, op, KFBI_FP32, rr, dcorr, rn, itol, o->restart,
                                    o->maxit - loc.iters, &gw, &it_in, &cyc, &a32, &rel_in, true,
                                    rn);
       loc.iters += it_in;
@@ -778,6 +790,26 @@ static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, do
     set_error("GMRES did not reach tol %.3e in %d iterations (relres %.3e)", o->tol, loc.iters,
               loc.relres);
   return status;
+}
+}  // namespace kfbi
+
+namespace kfbi {
+// GMRES with the workspace of c for an operator of the library on vectors of length
+// n <= max_markers of c (FP64 only).
+int gmres_solve_op(kfbi_ctx* c, int n, const GmresOp& op, const double* b, double* x,
+                   const kfbi_gmres_opts* o, kfbi_gmres_stats* stats) {
+  if (!b || !x || !o || n < 1 || n > c->max_markers) {
+    set_error("invalid GMRES arguments (n = %d)", n);
+    return KFBI_E_INVALID;
+  }
+  if (o->restart < 1 || o->restart > kMaxRestart || o->maxit < 1 || !(o->tol > 0.0) ||
+      o->precision != KFBI_FP64) {
+    set_error("invalid GMRES options (FP64 only for this operator)");
+    return KFBI_E_INVALID;
+  }
+  GmresWork gw;
+  bind_work(c, &gw, n);
+  return gmres_run(c, n, op, b, x, o, stats, &gw);
 }
 }  // namespace kfbi
 

@@ -36,6 +36,8 @@ EXPORTS = [
     "stefan_create", "stefan_destroy", "stefan_init", "stefan_step", "stefan_run",
     "stefan_temperature", "stefan_markers", "stefan_density", "stefan_interface",
     "stefan_constants", "stefan_size", "stefan_thetal",
+    "stokes_create", "stokes_destroy", "stokes_set_interface", "stokes_apply", "stokes_fields",
+    "stokes_operator", "stokes_gmres_solve", "stokes_get_info",
 ]
 
 
@@ -79,6 +81,17 @@ class GmresStats(C.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class StokesParams(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("side", C.c_double), ("N", C.c_int),
+                ("c2", C.c_double), ("max_markers", C.c_int), ("stream", C.c_void_p),
+                ("solve_tol", C.c_double), ("solve_maxit", C.c_int)]
+
+
+class StokesInfo(C.Structure):
+    _fields_ = [("M", C.c_int), ("n_crossings", C.c_int), ("cg_iters", C.c_int),
+                ("cg_relres", C.c_double)]
 
 
 class ThetaLParams(C.Structure):
@@ -187,6 +200,14 @@ def load(path: str = LIBPATH):
     lib.stefan_size.argtypes = [vp, C.POINTER(C.c_int)]
     lib.stefan_thetal.argtypes = [vp]
     lib.stefan_thetal.restype = vp
+    lib.stokes_create.argtypes = [C.POINTER(StokesParams), C.POINTER(vp)]
+    lib.stokes_destroy.argtypes = [vp]
+    lib.stokes_set_interface.argtypes = [vp, C.c_int, vp]
+    lib.stokes_apply.argtypes = [vp, vp, vp, vp]
+    lib.stokes_fields.argtypes = [vp, vp, vp, vp]
+    lib.stokes_operator.argtypes = [vp, vp, vp]
+    lib.stokes_gmres_solve.argtypes = [vp, vp, vp, C.POINTER(GmresOpts), C.POINTER(GmresStats)]
+    lib.stokes_get_info.argtypes = [vp, C.POINTER(StokesInfo)]
     ip, fp = C.POINTER(C.c_int), C.POINTER(C.c_float)
     lib.kfbi_ws_create.argtypes = [C.POINTER(WsCfg), C.POINTER(vp)]
     lib.kfbi_ws_destroy.argtypes = [vp]
@@ -489,6 +510,70 @@ class Stefan:
         lam, c2 = C.c_double(), C.c_double()
         _check(self.lib.stefan_constants(self.h, C.byref(lam), C.byref(c2)))
         return lam.value, c2.value
+
+
+class Stokes:
+    """Modified Stokes double-layer operator on the MAC grid (include/stokes.h) on the
+    current torch stream."""
+
+    def __init__(self, x0, y0, side, N, c2, max_markers=2048, tol=1e-13, maxit=500, stream=None):
+        self.lib = load()
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.stream = s
+        self.N = N
+        p = StokesParams(x0, y0, side, N, c2, max_markers, C.c_void_p(s.cuda_stream), tol, maxit)
+        h = C.c_void_p()
+        _check(self.lib.stokes_create(C.byref(p), C.byref(h)))
+        self.h = h
+        self.M = 0
+
+    def close(self):
+        if self.h:
+            self.lib.stokes_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_interface(self, xy: torch.Tensor):
+        xy = xy.contiguous()
+        _check(self.lib.stokes_set_interface(self.h, xy.shape[1], _ptr(xy)))
+        self.M = xy.shape[1]
+
+    def apply(self, phi: torch.Tensor):
+        """Traces of D phi from inside and outside, each (2, M)."""
+        phi = phi.contiguous()
+        up = torch.empty((2, self.M), dtype=torch.float64, device="cuda")
+        um = torch.empty_like(up)
+        _check(self.lib.stokes_apply(self.h, _ptr(phi), _ptr(up), _ptr(um)))
+        return up, um
+
+    def fields(self):
+        N = self.N
+        u = torch.empty((N, N + 1), dtype=torch.float64, device="cuda")
+        v = torch.empty((N + 1, N), dtype=torch.float64, device="cuda")
+        p = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        _check(self.lib.stokes_fields(self.h, _ptr(u), _ptr(v), _ptr(p)))
+        return u, v, p
+
+    def operator(self, x: torch.Tensor, y: torch.Tensor | None = None):
+        y = torch.empty_like(x) if y is None else y
+        _check(self.lib.stokes_operator(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    def gmres(self, rhs, x, tol=1e-10, restart=50, maxit=500):
+        opts = GmresOpts(tol, restart, maxit, FP64, 0.0)
+        st = GmresStats()
+        _check(self.lib.stokes_gmres_solve(self.h, _ptr(rhs), _ptr(x), C.byref(opts), C.byref(st)))
+        return x, st.as_dict()
+
+    def info(self) -> dict:
+        i = StokesInfo()
+        _check(self.lib.stokes_get_info(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in i._fields_}
 
 
 class _ThetaLView:

@@ -17,6 +17,7 @@ PAIRS = {
     "ThetaLParams": "thetaL_params", "ThetaLStats": "thetaL_stats",
     "ThetaLState": "thetaL_state", "StefanAniso": "stefan_aniso",
     "StefanParams": "stefan_params", "StefanStats": "stefan_stats", "WsCfg": "kfbi_ws_cfg",
+    "StokesParams": "stokes_params", "StokesInfo": "stokes_info",
 }
 
 
@@ -32,6 +33,7 @@ def c_layout(tmp_path_factory):
     import paper_2309_01068_amd.kfbi as kf
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "kfbi.h"',
              '#include "thetal.h"', '#include "stefan.h"', '#include "warmstart.h"',
+             '#include "stokes.h"',
              'int main(void) {']
     for py, c in PAIRS.items():
         lines.append(f'  printf("{py} size %zu\\n", sizeof({c}));')
