@@ -56,7 +56,7 @@ def parse():
                     help="held-out evolutions for the Stefan warm start")
     ap.add_argument("--only", default="",
                     help="comma list of extra sections to run (extra, batched, interior_dirichlet, "
-                         "hele_shaw, warm_start, stefan); empty = all")
+                         "hele_shaw, warm_start, stefan, stefan_warm_start, stokes); empty = all")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 10 times (the reference "
                          "kernel for scaling hardware byte counters) and exit")
@@ -311,7 +311,8 @@ def main():
                     ("hele_shaw", lambda: hele_shaw(kf, W, torch, np, dev, a)),
                     ("warm_start", lambda: warm_start(kf, W, torch, np, dev, a)),
                     ("stefan", lambda: stefan(kf, W, torch, np, dev, a)),
-                    ("stefan_warm_start", lambda: stefan_warm_start(kf, W, torch, np, dev, a))]
+                    ("stefan_warm_start", lambda: stefan_warm_start(kf, W, torch, np, dev, a)),
+                    ("stokes", lambda: stokes(kf, W, torch, np, dev, a))]
         for name, fn in sections:
             if want is None or name in want:
                 result[name] = fn()
@@ -466,6 +467,51 @@ def interior_dirichlet(kf, W, torch, np, dev):
     ctx.close()
     return {"iters": st["iters"], "relres": st["relres"], "solve_ms": round(1e3 * el, 4),
             "max_err_inside": float(err.max()), "l2_err_inside": float(np.sqrt(np.mean(err ** 2)))}
+
+
+def stokes(kf, W, torch, np, dev, a):
+    """Modified Stokes double layer (eq. ms-bie) on the MAC grid: the flower
+    r = 0.55 (1 + 0.12 cos 3a + 0.05 sin 5a) in [-1,1]^2, c^2 = 1/tau with tau = 1e-3 (the
+    flow step's 3/(2 tau) is of this size), markers about 1.6 h apart; per N the time of one
+    apply (fields and traces), its Schur-complement CG iterations, the dense-transform
+    product rate, and the GMRES solve of eq. ms-bie to 1e-10 for a smooth seeded
+    right-hand side from x0 = 0."""
+    out = {}
+    c2 = 1000.0
+    for N in (128, 256, 512):
+        box = W.box(-1.0, 1.0, N)
+        M = int(round(3.6 / (1.6 * box.h) / 2)) * 2
+        X = W.polar_curve(lambda t: 0.55 * (1 + 0.12 * np.cos(3 * t) + 0.05 * np.sin(5 * t)), M)
+        st = kf.Stokes(box.x0, box.y0, box.side, N, c2, max_markers=M, tol=1e-13)
+        st.set_interface(torch.tensor(X, device=dev))
+        phi = torch.tensor(np.stack([W.fourier_density(M, 1, kmax=8),
+                                     W.fourier_density(M, 2, kmax=8)]), device=dev)
+        st.apply(phi)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st.apply(phi)
+        torch.cuda.synchronize()
+        us = 1e6 * (time.perf_counter() - t0) / reps
+        info = st.info()
+        # dense transform products of one CG iteration: 12 products of about N^3
+        # multiply-adds (two velocity solves and the preconditioner, four each)
+        flops_it = 12 * 2.0 * N ** 3
+        g = np.stack([W.fourier_density(M, 9, kmax=8), W.fourier_density(M, 10, kmax=8)])
+        x = torch.zeros(2 * M, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, gst = st.gmres(torch.tensor(g.ravel(), device=dev), x, tol=1e-10)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"N{N}"] = {"markers": M, "apply_ms": round(us / 1e3, 3),
+                        "cg_iters": info["cg_iters"], "cg_relres": info["cg_relres"],
+                        "transform_tflops": round(flops_it * info["cg_iters"] / (us * 1e-6) / 1e12, 3),
+                        "gmres_iters": gst["iters"], "gmres_relres": gst["relres"],
+                        "gmres_ms": round(1e3 * el, 2)}
+        st.close()
+    return out
 
 
 def hele_shaw(kf, W, torch, np, dev, a):
