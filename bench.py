@@ -125,14 +125,16 @@ def measured_traffic(kname, N, precision):
 
 
 def profiled_dominant(N, precision):
-    """The kernel with the largest total time in the committed rocprofv3 kernel-trace
-    summary of this workload, or None."""
+    """(kernel with the largest in-apply total time, its mean replayed and in-apply
+    durations in us) from the committed rocprofv3 kernel-trace summary of this workload,
+    or (None, None, None)."""
     path = os.path.join(ROOT, "profiles", f"kfbi_apply_star2048_{N}_{'f64' if precision == 0 else 'f32'}_kernel_stats.json")
     try:
         rec = json.load(open(path))
-        return rec["dominant"]
+        k = rec["dominant"]
+        return k, rec["replay_avg_us"][k], rec["in_apply_avg_us"][k]
     except (OSError, ValueError, KeyError):
-        return None
+        return None, None, None
 
 
 def replay_kernels(ctx, reps, rounds=5):
@@ -257,7 +259,7 @@ def main():
     torch.cuda.synchronize()
     wb = 8 if a.precision == 0 else 4
     byts = algorithmic_bytes(info, a.N, M, wb)
-    prof_dom = profiled_dominant(a.N, a.precision)
+    prof_dom, prof_rep, prof_in = profiled_dominant(a.N, a.precision)
     kname = prof_dom if prof_dom in replay_us else max(replay_us, key=replay_us.get)
     achieved = byts[kname] / (replay_us[kname] * 1e-6) / 1e9
     whole = sum(byts.values())
@@ -269,6 +271,8 @@ def main():
             "avg_us_from": "the kernel replayed back to back between two HIP events on the "
                            "context stream (kfbi_profile_kernel)",
             "dominant_from": "committed rocprofv3 summary" if prof_dom == kname else "replay timing",
+            "profile_replay_avg_us": prof_rep if prof_dom == kname else None,
+            "profile_in_apply_avg_us": prof_in if prof_dom == kname else None,
             "whole_apply": {"algorithmic_bytes": whole, "us": round(ms_per_step * 1e3, 3),
                             "achieved": round(whole_ach, 1),
                             "frac": round(whole_ach / HBM_PEAK_GBS, 4)},
