@@ -15,7 +15,7 @@
 //                 S = G^T (c^2 - Delta_h)^-1 G (G the pressure gradient at the velocity
 //                 points), Cahouet-Chabard preconditioner c^2 L^-1 + I; the velocity
 //                 solves and L^-1 by orthonormal sine / cosine transforms applied as
-//                 dense products (k_st_gemm), divided by the eigenvalues
+//                 dense products on FP64 MFMA (k_st_gemm), divided by the eigenvalues
 //   k_st_extract  Sec. 4.3 on each velocity component's grid: six-point stencil, 6x6
 //                 Taylor system with the marker jumps -> traces from both sides
 // The labels and crossings of the u, v and p points come from the scalar geometry of a
@@ -42,7 +42,7 @@ struct stokes_ctx {
   int M = 0, nc = 0, have = 0;
   int cg_iters = 0;
   double cg_relres = 0.0;
-  DBuf Q, J, ru, rv, rp, u, v, p, S1, S2, C2, wk, part, sc, flag;
+  DBuf Q, J, ru, rv, rp, u, v, p, S1, S2, C2, S2T, C2T, wk, part, sc, flag;
 };
 
 namespace {
@@ -56,13 +56,15 @@ constexpr int kRedBlocks = 256;
 inline int nblk(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
 
 // ----------------------------------------------------------------- transform matrices
-// Orthonormal transform matrices (row = mode):
+// Orthonormal transform matrices (row = mode) and the transposes of S2 and C2 (every
+// product then reads its operands along rows):
 //   S1[k-1][i-1] = sqrt(2/N) sin(k i pi / N),            k, i = 1..N-1   (DST-I)
 //   S2[l-1][j-1] = w_l sin(l (j - 1/2) pi / N),          l, j = 1..N     (DST-II)
 //   C2[k][i-1]   = w_k cos(k (i - 1/2) pi / N),          k = 0..N-1      (DCT-II)
 // with w = sqrt(2/N), except sqrt(1/N) for l = N (DST-II) and k = 0 (DCT-II).
 __global__ void k_st_trmat(int N, double* __restrict__ S1, double* __restrict__ S2,
-                           double* __restrict__ C2) {
+                           double* __restrict__ C2, double* __restrict__ S2T,
+                           double* __restrict__ C2T) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N * N) return;
   const int r = e / N, c = e % N;
@@ -76,19 +78,23 @@ __global__ void k_st_trmat(int N, double* __restrict__ S1, double* __restrict__ 
   {  // S2: l = r + 1, j = c + 1: angle l (2j - 1) pi / (2N)
     const long long m = (static_cast<long long>(r + 1) * (2 * c + 1)) % (4 * N);
     sincospi(static_cast<double>(m) / (2 * N), &sn, &cs);
-    S2[r * N + c] = (r + 1 == N ? w1 : w) * sn;
+    S2[r * N + c] = S2T[c * N + r] = (r + 1 == N ? w1 : w) * sn;
   }
   {  // C2: k = r, i = c + 1
     const long long m = (static_cast<long long>(r) * (2 * c + 1)) % (4 * N);
     sincospi(static_cast<double>(m) / (2 * N), &sn, &cs);
-    C2[r * N + c] = (r == 0 ? w1 : w) * cs;
+    C2[r * N + c] = C2T[c * N + r] = (r == 0 ? w1 : w) * cs;
   }
 }
 
 // ---------------------------------------------------------------------- dense product
 // C (m x n, row-major, ldc) = A (m x k) B (k x n); element (r, c) of A at A[r sar + c sac]
-// and of B at B[r sbr + c sbc] (transposes by strides).  64 x 64 output tiles, 4 x 4 per
-// thread, k in chunks of 16 staged in LDS; the tile loads run along the contiguous index.
+// and of B at B[r sbr + c sbc] (transposes by strides).  64 x 64 output tiles per block of
+// four wavefronts, each wavefront 32 x 32 as 2 x 2 blocks of v_mfma_f64_16x16x4f64 (lane
+// l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step and holds
+// D[4 i + l / 16][l % 16] in element i of its accumulator); k in chunks of 16 staged in
+// LDS, the tile loads running along the contiguous index.
+typedef double v4d __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256)
     k_st_gemm(int m, int n, int k, const double* __restrict__ A, long long sar, long long sac,
               const double* __restrict__ B, long long sbr, long long sbc, double* __restrict__ C,
@@ -96,11 +102,17 @@ __global__ void __launch_bounds__(256)
   __shared__ double As[16][65];
   __shared__ double Bs[16][65];
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int lane = tid & 63, w = tid >> 6;
   const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-  double acc[4][4] = {};
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
   const bool a_kfast = (sac == 1);
   const bool b_cfast = (sbc == 1);
+  const int lr = lane & 15, lk = lane >> 4;
   for (int k0 = 0; k0 < k; k0 += 16) {
     for (int e = tid; e < 16 * 64; e += 256) {
       const int kk = a_kfast ? (e & 15) : (e >> 6);
@@ -114,27 +126,29 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
+    for (int kk = 0; kk < 16; kk += 4) {
+      double af[2], bf[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[kk][ty * 4 + q];
-        b[q] = Bs[kk][tx * 4 + q];
-      }
+      for (int a = 0; a < 2; ++a) af[a] = As[kk + lk][wr + 16 * a + lr];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int b = 0; b < 2; ++b) bf[b] = Bs[kk + lk][wc + 16 * b + lr];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[r][q] = fma(a[r], b[q], acc[r][q]);
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gr = r0 + ty * 4 + r, gc = c0 + tx * 4 + q;
-      if (gr < m && gc < n) C[static_cast<size_t>(gr) * ldc + gc] = acc[r][q];
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = r0 + wr + 16 * a + 4 * i + lk, gc = c0 + wc + 16 * b + lr;
+        if (gr < m && gc < n) C[static_cast<size_t>(gr) * ldc + gc] = acc[a][b][i];
+      }
 }
 
 // X[r][c] /= lambda: mode 0 (u: rows DST-II l = r + 1, columns DST-I k = c + 1), mode 1
@@ -589,20 +603,21 @@ void vel_solve(stokes_ctx* st, int comp, const double* f, double* z, double* t1)
   hipStream_t s = st->stream;
   const double* S1 = st->S1.as<double>();
   const double* S2 = st->S2.as<double>();
+  const double* S2T = st->S2T.as<double>();
   const double ih2 = 1.0 / (st->h * st->h);
   if (comp == 0) {  // rows: DST-II (N), columns: DST-I (N-1)
-    gemm(s, N, n, n, f, n, 1, S1, 1, n, t1, n);        // t1 = F S1^T
+    gemm(s, N, n, n, f, n, 1, S1, n, 1, t1, n);        // t1 = F S1^T (S1 symmetric)
     gemm(s, N, n, N, S2, N, 1, t1, n, 1, z, n);        // z = S2 t1
     hipLaunchKernelGGL(k_st_scale, dim3(nblk(N * n, 256)), dim3(256), 0, s, N, n, N, ih2, st->c2,
                        0, z);
-    gemm(s, N, n, N, S2, 1, N, z, n, 1, t1, n);        // t1 = S2^T z
+    gemm(s, N, n, N, S2T, N, 1, z, n, 1, t1, n);       // t1 = S2^T z
     gemm(s, N, n, n, t1, n, 1, S1, n, 1, z, n);        // z = t1 S1
   } else {  // rows: DST-I (N-1), columns: DST-II (N)
-    gemm(s, n, N, N, f, N, 1, S2, 1, N, t1, N);        // t1 = F S2^T
+    gemm(s, n, N, N, f, N, 1, S2T, N, 1, t1, N);       // t1 = F S2^T
     gemm(s, n, N, n, S1, n, 1, t1, N, 1, z, N);        // z = S1 t1
     hipLaunchKernelGGL(k_st_scale, dim3(nblk(N * n, 256)), dim3(256), 0, s, n, N, N, ih2, st->c2,
                        1, z);
-    gemm(s, n, N, n, S1, 1, n, z, N, 1, t1, N);        // t1 = S1^T z
+    gemm(s, n, N, n, S1, n, 1, z, N, 1, t1, N);        // t1 = S1^T z (S1 symmetric)
     gemm(s, n, N, N, t1, N, 1, S2, N, 1, z, N);        // z = t1 S2
   }
 }
@@ -618,11 +633,12 @@ void precond(stokes_ctx* st, const double* r, double* z, double* t1) {
     return;
   }
   const double* C2 = st->C2.as<double>();
-  gemm(s, N, N, N, r, N, 1, C2, 1, N, t1, N);          // t1 = R C2^T
+  const double* C2T = st->C2T.as<double>();
+  gemm(s, N, N, N, r, N, 1, C2T, N, 1, t1, N);         // t1 = R C2^T
   gemm(s, N, N, N, C2, N, 1, t1, N, 1, z, N);          // z = C2 t1
   hipLaunchKernelGGL(k_st_scale, dim3(nblk(NN, 256)), dim3(256), 0, s, N, N, N,
                      1.0 / (st->h * st->h), st->c2, 2, z);
-  gemm(s, N, N, N, C2, 1, N, z, N, 1, t1, N);          // t1 = C2^T z
+  gemm(s, N, N, N, C2T, N, 1, z, N, 1, t1, N);         // t1 = C2^T z
   gemm(s, N, N, N, t1, N, 1, C2, N, 1, z, N);          // z = t1 C2
   hipLaunchKernelGGL(k_st_axpby, dim3(nblk(NN, 256)), dim3(256), 0, s, static_cast<int>(NN), 1.0,
                      r, 1.0, z);
@@ -809,6 +825,7 @@ int stokes_create(const stokes_params* p, stokes_ctx** out) {
       (rc = st->v.ensure(sizeof(double) * N * (N + 1))) ||
       (rc = st->p.ensure(sizeof(double) * NN)) || (rc = st->S1.ensure(sizeof(double) * NN)) ||
       (rc = st->S2.ensure(sizeof(double) * NN)) || (rc = st->C2.ensure(sizeof(double) * NN)) ||
+      (rc = st->S2T.ensure(sizeof(double) * NN)) || (rc = st->C2T.ensure(sizeof(double) * NN)) ||
       (rc = st->wk.ensure(sizeof(double) * NN * kWorkFields)) ||
       (rc = st->part.ensure(sizeof(double) * kRedBlocks)) ||
       (rc = st->sc.ensure(sizeof(double) * SC_COUNT)) ||
@@ -816,7 +833,8 @@ int stokes_create(const stokes_params* p, stokes_ctx** out) {
       (rc = st->Q.ensure(sizeof(double) * 6 * p->max_markers)))
     return fail(rc);
   hipLaunchKernelGGL(k_st_trmat, dim3(nblk(NN, 256)), dim3(256), 0, st->stream, N,
-                     st->S1.as<double>(), st->S2.as<double>(), st->C2.as<double>());
+                     st->S1.as<double>(), st->S2.as<double>(), st->C2.as<double>(),
+                     st->S2T.as<double>(), st->C2T.as<double>());
   if (hipStreamSynchronize(st->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
     set_error("stokes: set-up kernels failed");
     return fail(KFBI_E_HIP);
@@ -829,7 +847,7 @@ int stokes_destroy(stokes_ctx* st) {
   if (!st) return KFBI_OK;
   if (st->g2) (void)hipStreamSynchronize(st->stream);
   for (DBuf* b : {&st->Q, &st->J, &st->ru, &st->rv, &st->rp, &st->u, &st->v, &st->p, &st->S1,
-                  &st->S2, &st->C2, &st->wk, &st->part, &st->sc, &st->flag})
+                  &st->S2, &st->C2, &st->S2T, &st->C2T, &st->wk, &st->part, &st->sc, &st->flag})
     b->release();
   if (st->g2) kfbi_destroy(st->g2);
   delete st;
