@@ -88,67 +88,60 @@ __global__ void k_st_trmat(int N, double* __restrict__ S1, double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------- dense product
-// C (m x n, row-major, ldc) = A (m x k) B (k x n); element (r, c) of A at A[r sar + c sac]
-// and of B at B[r sbr + c sbc] (transposes by strides).  64 x 64 output tiles per block of
-// four wavefronts, each wavefront 32 x 32 as 2 x 2 blocks of v_mfma_f64_16x16x4f64 (lane
-// l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step and holds
-// D[4 i + l / 16][l % 16] in element i of its accumulator); k in chunks of 16 staged in
-// LDS, the tile loads running along the contiguous index.
+// C (m x n, row-major, ldc) = A (m x k) B (k x n), A row-major with row stride lda, B with
+// row stride ldb.  32 x 32 output tiles per block of four wavefronts, each wavefront one
+// 16 x 16 quadrant by v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step and holds D[4 i + l / 16][l % 16] in element
+// i of its accumulator).  k runs in chunks of 32 through LDS; the loads of the next chunk
+// are issued before the products of the current one (every k-chunk would otherwise wait
+// for its own loads: the grids of these transforms are small).
 typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kGT = 32;  // output tile and k-chunk
 __global__ void __launch_bounds__(256)
-    k_st_gemm(int m, int n, int k, const double* __restrict__ A, long long sar, long long sac,
-              const double* __restrict__ B, long long sbr, long long sbc, double* __restrict__ C,
-              int ldc) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+    k_st_gemm(int m, int n, int k, const double* __restrict__ A, int lda,
+              const double* __restrict__ B, int ldb, double* __restrict__ C, int ldc) {
+  __shared__ double As[kGT][kGT + 1];  // [row][k]
+  __shared__ double Bs[kGT][kGT + 1];  // [k][col]
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
-  v4d acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-  const bool a_kfast = (sac == 1);
-  const bool b_cfast = (sbc == 1);
+  const int r0 = blockIdx.y * kGT, c0 = blockIdx.x * kGT;
+  const int wr = 16 * (w >> 1), wc = 16 * (w & 1);
   const int lr = lane & 15, lk = lane >> 4;
-  for (int k0 = 0; k0 < k; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = a_kfast ? (e & 15) : (e >> 6);
-      const int rr = a_kfast ? (e >> 4) : (e & 63);
-      const int gr = r0 + rr, gk = k0 + kk;
-      As[kk][rr] = (gr < m && gk < k) ? A[gr * sar + gk * sac] : 0.0;
-      const int kb = b_cfast ? (e >> 6) : (e & 15);
-      const int cc = b_cfast ? (e & 63) : (e >> 4);
-      const int gkb = k0 + kb, gc = c0 + cc;
-      Bs[kb][cc] = (gkb < k && gc < n) ? B[gkb * sbr + gc * sbc] : 0.0;
+  // this thread's four elements of each tile: row tid / 8 + 0..3 * 8 ... (e = tid + 256 q)
+  double pa[4], pb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 5, cc = e & 31;
+      const int gr = r0 + rr, gk = k0 + cc;
+      pa[q] = (gr < m && gk < k) ? A[static_cast<size_t>(gr) * lda + gk] : 0.0;
+      const int gkb = k0 + rr, gc = c0 + cc;
+      pb[q] = (gkb < k && gc < n) ? B[static_cast<size_t>(gkb) * ldb + gc] : 0.0;
+    }
+  };
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int k0 = 0; k0 < k; k0 += kGT) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      As[e >> 5][e & 31] = pa[q];
+      Bs[e >> 5][e & 31] = pb[q];
     }
     __syncthreads();
+    if (k0 + kGT < k) load(k0 + kGT);  // in flight during the products below
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
-      double af[2], bf[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) af[a] = As[kk + lk][wr + 16 * a + lr];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) bf[b] = Bs[kk + lk][wc + 16 * b + lr];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
-    }
+    for (int kk = 0; kk < kGT; kk += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[wr + lr][kk + lk], Bs[kk + lk][wc + lr], acc,
+                                                 0, 0, 0);
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = r0 + wr + 16 * a + 4 * i + lk, gc = c0 + wc + 16 * b + lr;
-        if (gr < m && gc < n) C[static_cast<size_t>(gr) * ldc + gc] = acc[a][b][i];
-      }
+  for (int i = 0; i < 4; ++i) {
+    const int gr = r0 + wr + 4 * i + lk, gc = c0 + wc + lr;
+    if (gr < m && gc < n) C[static_cast<size_t>(gr) * ldc + gc] = acc[i];
+  }
 }
 
 // X[r][c] /= lambda: mode 0 (u: rows DST-II l = r + 1, columns DST-I k = c + 1), mode 1
@@ -590,10 +583,11 @@ Work bind(stokes_ctx* st) {
 }
 constexpr int kWorkFields = 11;
 
-void gemm(hipStream_t s, int m, int n, int k, const double* A, long long sar, long long sac,
-          const double* B, long long sbr, long long sbc, double* C, int ldc) {
-  hipLaunchKernelGGL(k_st_gemm, dim3(nblk(n, 64), nblk(m, 64)), dim3(256), 0, s, m, n, k, A, sar,
-                     sac, B, sbr, sbc, C, ldc);
+// C = A B, row-major operands: A (m x k, row stride lda), B (k x n, row stride ldb)
+void gemm(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
+          double* C, int ldc) {
+  hipLaunchKernelGGL(k_st_gemm, dim3(nblk(n, kGT), nblk(m, kGT)), dim3(256), 0, s, m, n, k, A, lda,
+                     B, ldb, C, ldc);
 }
 
 // z = (c^2 - Delta_h)^-1 f for the u unknowns ([N][N-1]; comp 0) or the v unknowns
@@ -606,19 +600,19 @@ void vel_solve(stokes_ctx* st, int comp, const double* f, double* z, double* t1)
   const double* S2T = st->S2T.as<double>();
   const double ih2 = 1.0 / (st->h * st->h);
   if (comp == 0) {  // rows: DST-II (N), columns: DST-I (N-1)
-    gemm(s, N, n, n, f, n, 1, S1, n, 1, t1, n);        // t1 = F S1^T (S1 symmetric)
-    gemm(s, N, n, N, S2, N, 1, t1, n, 1, z, n);        // z = S2 t1
+    gemm(s, N, n, n, f, n, S1, n, t1, n);        // t1 = F S1^T (S1 symmetric)
+    gemm(s, N, n, N, S2, N, t1, n, z, n);        // z = S2 t1
     hipLaunchKernelGGL(k_st_scale, dim3(nblk(N * n, 256)), dim3(256), 0, s, N, n, N, ih2, st->c2,
                        0, z);
-    gemm(s, N, n, N, S2T, N, 1, z, n, 1, t1, n);       // t1 = S2^T z
-    gemm(s, N, n, n, t1, n, 1, S1, n, 1, z, n);        // z = t1 S1
+    gemm(s, N, n, N, S2T, N, z, n, t1, n);       // t1 = S2^T z
+    gemm(s, N, n, n, t1, n, S1, n, z, n);        // z = t1 S1
   } else {  // rows: DST-I (N-1), columns: DST-II (N)
-    gemm(s, n, N, N, f, N, 1, S2T, N, 1, t1, N);       // t1 = F S2^T
-    gemm(s, n, N, n, S1, n, 1, t1, N, 1, z, N);        // z = S1 t1
+    gemm(s, n, N, N, f, N, S2T, N, t1, N);       // t1 = F S2^T
+    gemm(s, n, N, n, S1, n, t1, N, z, N);        // z = S1 t1
     hipLaunchKernelGGL(k_st_scale, dim3(nblk(N * n, 256)), dim3(256), 0, s, n, N, N, ih2, st->c2,
                        1, z);
-    gemm(s, n, N, n, S1, n, 1, z, N, 1, t1, N);        // t1 = S1^T z (S1 symmetric)
-    gemm(s, n, N, N, t1, N, 1, S2, N, 1, z, N);        // z = t1 S2
+    gemm(s, n, N, n, S1, n, z, N, t1, N);        // t1 = S1^T z (S1 symmetric)
+    gemm(s, n, N, N, t1, N, S2, N, z, N);        // z = t1 S2
   }
 }
 
@@ -634,12 +628,12 @@ void precond(stokes_ctx* st, const double* r, double* z, double* t1) {
   }
   const double* C2 = st->C2.as<double>();
   const double* C2T = st->C2T.as<double>();
-  gemm(s, N, N, N, r, N, 1, C2T, N, 1, t1, N);         // t1 = R C2^T
-  gemm(s, N, N, N, C2, N, 1, t1, N, 1, z, N);          // z = C2 t1
+  gemm(s, N, N, N, r, N, C2T, N, t1, N);         // t1 = R C2^T
+  gemm(s, N, N, N, C2, N, t1, N, z, N);          // z = C2 t1
   hipLaunchKernelGGL(k_st_scale, dim3(nblk(NN, 256)), dim3(256), 0, s, N, N, N,
                      1.0 / (st->h * st->h), st->c2, 2, z);
-  gemm(s, N, N, N, C2T, N, 1, z, N, 1, t1, N);         // t1 = C2^T z
-  gemm(s, N, N, N, t1, N, 1, C2, N, 1, z, N);          // z = t1 C2
+  gemm(s, N, N, N, C2T, N, z, N, t1, N);         // t1 = C2^T z
+  gemm(s, N, N, N, t1, N, C2, N, z, N);          // z = t1 C2
   hipLaunchKernelGGL(k_st_axpby, dim3(nblk(NN, 256)), dim3(256), 0, s, static_cast<int>(NN), 1.0,
                      r, 1.0, z);
 }
