@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--only", default="",
                     help="comma list of extra sections to run (extra, batched, interior_dirichlet, "
                          "hele_shaw, warm_start, stefan, stefan_warm_start, stokes); empty = all")
+    ap.add_argument("--stokes-n", default="128,256,512",
+                    help="grid sizes of the modified Stokes section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 10 times (the reference "
                          "kernel for scaling hardware byte counters) and exit")
@@ -482,7 +484,7 @@ def stokes(kf, W, torch, np, dev, a):
     right-hand side from x0 = 0."""
     out = {}
     c2 = 1000.0
-    for N in (128, 256, 512):
+    for N in (int(v) for v in a.stokes_n.split(",") if v):
         box = W.box(-1.0, 1.0, N)
         M = int(round(3.6 / (1.6 * box.h) / 2)) * 2
         X = W.polar_curve(lambda t: 0.55 * (1 + 0.12 * np.cos(3 * t) + 0.05 * np.sin(5 * t)), M)

@@ -23,6 +23,7 @@
 // p (2i-1, 2j-1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -31,6 +32,13 @@
 #include "device_util.h"
 
 using namespace kfbi;
+
+// Host-visible record of one CG iteration of the MAC solve (coherent pinned memory).
+struct CgPost {
+  double rn2, bn2;  // ||r||^2 after the iteration, ||b||^2
+  int done, it;     // the residual test has passed; the iteration
+  double pad;
+};
 
 struct stokes_ctx {
   kfbi_ctx* g2 = nullptr;  // geometry on the half-spacing grid, GMRES workspace
@@ -43,6 +51,9 @@ struct stokes_ctx {
   int cg_iters = 0;
   double cg_relres = 0.0;
   DBuf Q, J, ru, rv, rp, u, v, p, S1, S2, C2, S2T, C2T, wk, part, sc, flag;
+  CgPost* hpost = nullptr;  // CG records: host view of coherent pinned memory
+  CgPost* dpost = nullptr;  // the same memory as the kernels address it
+  hipEvent_t ev[4] = {};           // one per record slot
 };
 
 namespace {
@@ -50,7 +61,8 @@ namespace {
 constexpr int kNJ = 15;  // jump values per point: u, ux, uy, uxx, uyy, uxy, v.., p, px, py
 enum { JU = 0, JUX, JUY, JUXX, JUYY, JUXY, JV, JVX, JVY, JVXX, JVYY, JVXY, JP, JPX, JPY };
 // device scalars of the CG recurrences
-enum { SC_RZ = 0, SC_RZN, SC_DQ, SC_RN, SC_BN, SC_MEAN, SC_COUNT = 8 };
+// (SC_RZ, SC_RZ + 1: r . z of even and odd iterations; SC_DONE: the residual test passed)
+enum { SC_RZ = 0, SC_DQ = 2, SC_RN, SC_BN, SC_MEAN, SC_DONE, SC_COUNT = 8 };
 constexpr int kRedBlocks = 256;
 
 inline int nblk(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
@@ -93,74 +105,148 @@ __global__ void k_st_trmat(int N, double* __restrict__ S1, double* __restrict__ 
 // 16 x 16 quadrant by v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step and holds D[4 i + l / 16][l % 16] in element
 // i of its accumulator).  k runs in chunks of 32 through LDS; the loads of the next chunk
-// are issued before the products of the current one (every k-chunk would otherwise wait
-// for its own loads: the grids of these transforms are small).
+// are issued before the products of the current one.  A block holds four such groups of
+// four wavefronts, each on its own quarter of k with its own chunk buffers, and adds their
+// tiles in group order at the end (deterministic): the grids of these transforms are
+// small (256 tiles at N = 512), and four wavefronts per SIMD instead of one keep the
+// matrix cores busy while the chunk loads are in flight.
+//
+// One launch computes up to two independent products (blockIdx.z selects the argument
+// set: the u and v velocity solves run side by side).  Operand A can be formed on the fly
+// as the pressure gradient of a cell array (amode), and the result can be divided by the
+// eigenvalues of a transform basis and have a matrix added (epi, D) as it is stored.
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int kGT = 32;  // output tile and k-chunk
-__global__ void __launch_bounds__(256)
-    k_st_gemm(int m, int n, int k, const double* __restrict__ A, int lda,
-              const double* __restrict__ B, int ldb, double* __restrict__ C, int ldc) {
-  __shared__ double As[kGT][kGT + 1];  // [row][k]
-  __shared__ double Bs[kGT][kGT + 1];  // [k][col]
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
+constexpr int kGT = 32;   // output tile
+constexpr int kGK = 32;   // k-chunk staged in LDS
+constexpr int kKS = 4;    // k-slices per block, four wavefronts each
+constexpr int kLdk = kGK + 2;  // LDS row of a chunk buffer: 16-byte reads of consecutive rows
+                               // land in different banks
+static_assert(kGK % 8 == 0 && kKS * 2 * kGT * kLdk >= (kKS - 1) * kGT * (kGT + 1),
+              "chunk buffers and the partial tiles share the LDS");
+enum { AM_PLAIN = 0, AM_GRAD_U, AM_GRAD_V };      // A = A, (G p) at u points, at v points
+enum { EP_NONE = 0, EP_VEL, EP_CELL };            // C = acc, acc / (lam + c^2), c^2 acc / lam
+struct GemmArgs {
+  int m, n, k, lda, ldb, ldc;
+  const double* A;  // AM_GRAD_*: the N x N cell array p
+  const double* B;
+  double* C;
+  const double* D;  // added to the result when not null (row stride ldc)
+  int amode, epi;
+};
+struct GemmConst {
+  int N;
+  double ih, ih2, c2;
+};
+
+__device__ __forceinline__ double gemm_a(const GemmArgs& g, const GemmConst& gc, int r, int c) {
+  if (g.amode == AM_GRAD_U)  // u point (c + 1, r + 1): (p(c + 2, r + 1) - p(c + 1, r + 1)) / h
+    return (g.A[r * gc.N + c + 1] - g.A[r * gc.N + c]) * gc.ih;
+  if (g.amode == AM_GRAD_V)  // v point (c + 1, r + 1): (p(c + 1, r + 2) - p(c + 1, r + 1)) / h
+    return (g.A[(r + 1) * gc.N + c] - g.A[r * gc.N + c]) * gc.ih;
+  return g.A[static_cast<size_t>(r) * g.lda + c];
+}
+
+// Eigenvalue factor of output (r, c): EP_VEL, both directions sine modes r + 1 and c + 1
+// (DST-I or DST-II, the same eigenvalues 4/h^2 sin^2(k pi / 2N)); EP_CELL, cosine modes r
+// and c (DCT-II), the (0, 0) mode set to zero.
+__device__ __forceinline__ double gemm_epi(int epi, const GemmConst& gc, int r, int c, double v) {
+  if (epi == EP_NONE) return v;
+  const int l = (epi == EP_CELL) ? r : r + 1, k = (epi == EP_CELL) ? c : c + 1;
+  const double sl = sinpi(static_cast<double>(l) / (2 * gc.N));
+  const double sk = sinpi(static_cast<double>(k) / (2 * gc.N));
+  const double lam = 4.0 * gc.ih2 * (sl * sl + sk * sk);
+  if (epi == EP_CELL) return (l == 0 && k == 0) ? 0.0 : v * (gc.c2 / lam);
+  return v / (lam + gc.c2);
+}
+
+__global__ void __launch_bounds__(256 * kKS)
+    k_st_gemm(GemmArgs g0, GemmArgs g1, GemmConst gc) {
+  const GemmArgs g = blockIdx.z ? g1 : g0;  // block-uniform
+  const int m = g.m, n = g.n, k = g.k;
   const int r0 = blockIdx.y * kGT, c0 = blockIdx.x * kGT;
+  if (r0 >= m || c0 >= n) return;  // the other product's grid is larger
+  // k-slice group ks of four wavefronts: its own chunk buffers, A as [row][k] and B
+  // transposed as [col][k], rows padded to kLdk doubles; after the loop the same LDS
+  // holds the groups' partial tiles
+  __shared__ __align__(16) double lds[kKS * 2 * kGT * kLdk];
+  const int tid = threadIdx.x & 255, ks = threadIdx.x >> 8;
+  double (*As)[kLdk] = reinterpret_cast<double (*)[kLdk]>(lds + ks * 2 * kGT * kLdk);
+  double (*Bt)[kLdk] = reinterpret_cast<double (*)[kLdk]>(lds + (ks * 2 + 1) * kGT * kLdk);
+  const int lane = tid & 63, w = tid >> 6;
   const int wr = 16 * (w >> 1), wc = 16 * (w & 1);
   const int lr = lane & 15, lk = lane >> 4;
-  // this thread's four elements of each tile: row tid / 8 + 0..3 * 8 ... (e = tid + 256 q)
-  double pa[4], pb[4];
+  // this group's k range: whole chunks
+  const int nch = (k + kGK - 1) / kGK;
+  const int per = (nch + kKS - 1) / kKS;
+  const int kb = ks * per * kGK, ke = min(k, (ks + 1) * per * kGK);
+  // this thread's elements of a chunk: A row e / kGK, k e % kGK; B k e / kGT, column
+  // e % kGT (e = tid + 256 q)
+  constexpr int QA = kGT * kGK / 256, QB = kGK * kGT / 256;
+  double pa[QA], pb[QB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QA; ++q) {
       const int e = tid + 256 * q;
-      const int rr = e >> 5, cc = e & 31;
-      const int gr = r0 + rr, gk = k0 + cc;
-      pa[q] = (gr < m && gk < k) ? A[static_cast<size_t>(gr) * lda + gk] : 0.0;
-      const int gkb = k0 + rr, gc = c0 + cc;
-      pb[q] = (gkb < k && gc < n) ? B[static_cast<size_t>(gkb) * ldb + gc] : 0.0;
+      const int gr = r0 + e / kGK, gk = k0 + e % kGK;
+      pa[q] = (gr < m && gk < ke) ? gemm_a(g, gc, gr, gk) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + 256 * q;
+      const int gkb = k0 + e / kGT, gcol = c0 + e % kGT;
+      pb[q] = (gkb < ke && gcol < n) ? g.B[static_cast<size_t>(gkb) * g.ldb + gcol] : 0.0;
     }
   };
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-  load(0);
-  for (int k0 = 0; k0 < k; k0 += kGT) {
+  load(kb);
+  // every group runs the same number of chunks (the last ones may be empty: zeros), so
+  // the block-wide barriers match
+  for (int c = 0; c < per; ++c) {
+    const int k0 = kb + c * kGK;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QA; ++q) {
       const int e = tid + 256 * q;
-      As[e >> 5][e & 31] = pa[q];
-      Bs[e >> 5][e & 31] = pb[q];
+      As[e / kGK][e % kGK] = pa[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + 256 * q;
+      Bt[e % kGT][e / kGT] = pb[q];
     }
     __syncthreads();
-    if (k0 + kGT < k) load(k0 + kGT);  // in flight during the products below
+    if (c + 1 < per) load(k0 + kGK);  // in flight during the products below
+    // two products per 16-byte read: lane (lr, lk) takes k = kk + 2 lk in the first and
+    // kk + 2 lk + 1 in the second, the same k for A and B (any assignment of the chunk's
+    // k to (product, lk) that A and B share gives the same sums)
 #pragma unroll
-    for (int kk = 0; kk < kGT; kk += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[wr + lr][kk + lk], Bs[kk + lk][wc + lr], acc,
-                                                 0, 0, 0);
+    for (int kk = 0; kk < kGK; kk += 8) {
+      const double2 a2 = *reinterpret_cast<const double2*>(&As[wr + lr][kk + 2 * lk]);
+      const double2 b2 = *reinterpret_cast<const double2*>(&Bt[wc + lr][kk + 2 * lk]);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.x, b2.x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.y, b2.y, acc, 0, 0, 0);
+    }
     __syncthreads();
   }
+  // the groups' tiles added in group order
+  double (*red)[kGT][kGT + 1] = reinterpret_cast<double (*)[kGT][kGT + 1]>(lds);
+  if (ks > 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[ks - 1][wr + 4 * i + lk][wc + lr] = acc[i];
+  }
+  __syncthreads();
+  if (ks > 0) return;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int gr = r0 + wr + 4 * i + lk, gc = c0 + wc + lr;
-    if (gr < m && gc < n) C[static_cast<size_t>(gr) * ldc + gc] = acc[i];
+    double v = acc[i];
+    for (int q = 1; q < kKS; ++q) v += red[q - 1][wr + 4 * i + lk][wc + lr];
+    const int gr = r0 + wr + 4 * i + lk, gcol = c0 + wc + lr;
+    if (gr < m && gcol < n) {
+      const size_t o = static_cast<size_t>(gr) * g.ldc + gcol;
+      v = gemm_epi(g.epi, gc, gr, gcol, v);
+      if (g.D) v += g.D[o];
+      g.C[o] = v;
+    }
   }
-}
-
-// X[r][c] /= lambda: mode 0 (u: rows DST-II l = r + 1, columns DST-I k = c + 1), mode 1
-// (v: rows DST-I, columns DST-II), both with lambda = (4/h^2)(sin^2(k pi/2N) +
-// sin^2(l pi/2N)) + c^2; mode 2 (cells, DCT-II k = c, l = r): X *= c^2 / ((4/h^2)(...)),
-// the (0, 0) mode set to zero.
-__global__ void k_st_scale(int rows, int cols, int N, double ih2, double c2, int mode,
-                           double* __restrict__ X) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= rows * cols) return;
-  const int r = e / cols, c = e % cols;
-  const int l = (mode == 2) ? r : r + 1, k = (mode == 2) ? c : c + 1;
-  const double sl = sinpi(static_cast<double>(l) / (2 * N));
-  const double sk = sinpi(static_cast<double>(k) / (2 * N));
-  const double lam = 4.0 * ih2 * (sl * sl + sk * sk);
-  if (mode == 2)
-    X[e] = (l == 0 && k == 0) ? 0.0 : X[e] * (c2 / lam);
-  else
-    X[e] = X[e] / (lam + c2);
 }
 
 // ------------------------------------------------------------------- pointwise stencils
@@ -200,8 +286,18 @@ __global__ void k_st_gradT(int N, double ih, const double* __restrict__ zu,
   out[e] = a * g + (base ? b * base[e] : 0.0);
 }
 
-// Block partial sums of a . b (a . a when b is null and sq, the sum of a when b is null and
-// not sq), then the ordered total.
+// Reductions in two steps without atomics or fences: a launch of at most kRedBlocks
+// blocks (grid-stride) stores one partial sum per block, and a later launch adds them in
+// block order (every block of it that needs the total forms it itself, so all of them
+// hold the same value whatever order the blocks run in).
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int np,
+                                            double* scratch) {
+  const double v = (static_cast<int>(threadIdx.x) < np) ? part[threadIdx.x] : 0.0;
+  return block_sum<double>(v, scratch);
+}
+
+// part[block] = partial sum of a . b (a . a when b is null and sq, of a when b is null and
+// not sq)
 __global__ void __launch_bounds__(256)
     k_st_dot(int n, const double* __restrict__ a, const double* __restrict__ b, int sq,
              double* __restrict__ part) {
@@ -213,12 +309,11 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// *out = scale * (sum of the np partials)
 __global__ void __launch_bounds__(256)
-    k_st_dot_fin(int nb, const double* __restrict__ part, double* __restrict__ out, double scale) {
+    k_st_dot_fin(int np, const double* __restrict__ part, double* __restrict__ out, double scale) {
   __shared__ double scratch[16];
-  double s = 0.0;
-  for (int e = threadIdx.x; e < nb; e += 256) s += part[e];
-  s = block_sum<double>(s, scratch);
+  const double s = sum_parts(part, np, scratch);
   if (threadIdx.x == 0) *out = s * scale;
 }
 
@@ -229,34 +324,90 @@ __global__ void k_st_sub_scalar(int n, const double* __restrict__ sc, int slot,
   if (e < n) y[e] = x[e] - sc[slot];
 }
 
-// p += alpha d, r -= alpha q with alpha = sc[RZ] / sc[DQ]
-__global__ void k_st_cg_step(int n, const double* __restrict__ sc, double* __restrict__ p,
-                             double* __restrict__ r, const double* __restrict__ d,
-                             const double* __restrict__ q) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const double alpha = sc[SC_RZ] / sc[SC_DQ];
-  p[e] += alpha * d[e];
-  r[e] -= alpha * q[e];
+// CG on the Schur complement, iteration it (rz_it = sc[SC_RZ + it % 2]).  Once the
+// residual test has passed (sc[SC_DONE] set) the updates are skipped, so iterations
+// launched ahead of the host's convergence check leave the solution unchanged.  The
+// partial sums of d . q, r . r and r . z sit at part + {0, 1, 2} kRedBlocks.
+//
+// q = G^T z (cells, zero velocity on the box faces) and the partials of d . q
+__global__ void __launch_bounds__(256)
+    k_st_gradT_dot(int N, double ih, const double* __restrict__ zu,
+                   const double* __restrict__ zv, const double* __restrict__ d,
+                   double* __restrict__ q, double* __restrict__ part) {
+  __shared__ double scratch[16];
+  double dq = 0.0;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < N * N; e += gridDim.x * 256) {
+    const int j = e / N, i = e % N;  // cell (i + 1, j + 1)
+    const double uw = (i >= 1) ? zu[j * (N - 1) + i - 1] : 0.0;
+    const double ue = (i <= N - 2) ? zu[j * (N - 1) + i] : 0.0;
+    const double vs = (j >= 1) ? zv[(j - 1) * N + i] : 0.0;
+    const double vn = (j <= N - 2) ? zv[j * N + i] : 0.0;
+    const double g = ((uw - ue) + (vs - vn)) * ih;
+    q[e] = g;
+    dq += d[e] * g;
+  }
+  dq = block_sum<double>(dq, scratch);
+  if (threadIdx.x == 0) part[blockIdx.x] = dq;
 }
 
-// d = z + beta d with beta = sc[RZN] / sc[RZ]
-__global__ void k_st_cg_dir(int n, const double* __restrict__ sc, const double* __restrict__ z,
-                            double* __restrict__ d) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  d[e] = z[e] + (sc[SC_RZN] / sc[SC_RZ]) * d[e];
+// p += alpha d, r -= alpha q (alpha = rz_it / (d . q)) unless done; partials of r . r
+__global__ void __launch_bounds__(256)
+    k_st_cg_step(int n, int it, int np, const double* __restrict__ sc, double* __restrict__ p,
+                 double* __restrict__ r, const double* __restrict__ d,
+                 const double* __restrict__ q, double* __restrict__ part) {
+  __shared__ double scratch[16];
+  const bool done = sc[SC_DONE] != 0.0;
+  const double dq = sum_parts(part, np, scratch);
+  const double alpha = sc[SC_RZ + (it & 1)] / dq;
+  double rr = 0.0;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    double re = r[e];
+    if (!done) {
+      p[e] += alpha * d[e];
+      re -= alpha * q[e];
+      r[e] = re;
+    }
+    rr += re * re;
+  }
+  rr = block_sum<double>(rr, scratch);
+  if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = rr;
 }
 
-__global__ void k_st_shift(double* __restrict__ sc) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) sc[SC_RZ] = sc[SC_RZN];
+// The residual test ||r||^2 <= tol2 ||b||^2 (sticky in sc[SC_DONE]), then, unless it has
+// passed, d = z + beta d (beta = rz_{it+1} / rz_it); block 0 stores the new flag and
+// rz_{it+1} and writes the record for the host.  Every block forms the test from the same
+// partials, so all agree, and a block that reads the flag block 0 has already updated
+// reaches the same decision (the flag only ever turns on, with this test).
+__global__ void __launch_bounds__(256)
+    k_st_cg_dir(int n, int it, int np, double tol2, double* __restrict__ sc,
+                const double* __restrict__ z, double* __restrict__ d,
+                const double* __restrict__ part, CgPost* __restrict__ post) {
+  __shared__ double scratch[16];
+  const double rn2 = sum_parts(part + kRedBlocks, np, scratch);
+  const double rz = sum_parts(part + 2 * kRedBlocks, np, scratch);
+  const double bn2 = sc[SC_BN];
+  const double rz_old = sc[SC_RZ + (it & 1)];
+  const bool done = (sc[SC_DONE] != 0.0) || rn2 <= tol2 * bn2;
+  __syncthreads();  // every thread has read the scalars before block 0 replaces them
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[SC_RZ + ((it + 1) & 1)] = rz;
+    sc[SC_RN] = rn2;
+    sc[SC_DONE] = done ? 1.0 : 0.0;
+    post->rn2 = rn2;
+    post->bn2 = bn2;
+    post->done = done ? 1 : 0;
+    post->it = it;
+    __threadfence_system();
+  }
+  if (done) return;
+  const double beta = rz / rz_old;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256)
+    d[e] = z[e] + beta * d[e];
 }
 
-// y = a x + b y (y is not read when b = 0)
-__global__ void k_st_axpby(int n, double a, const double* __restrict__ x, double b,
-                           double* __restrict__ y) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) y[e] = a * x[e] + (b != 0.0 ? b * y[e] : 0.0);
+// Start of the CG: done at once for a zero right-hand side.
+__global__ void k_st_cg_init(double* __restrict__ sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc[SC_DONE] = (sc[SC_BN] > 0.0) ? 0.0 : 1.0;
 }
 
 // Full velocity fields from the interior unknowns (sign s): u [N][N+1] with u = 0 on the
@@ -561,102 +712,107 @@ __global__ void k_st_extract(int M, int N, double h, double x0, double y0,
 
 // ------------------------------------------------------------------------- host side
 struct Work {
-  double *zu, *zv, *gu, *gv, *t1, *pv, *r, *z, *d, *q, *b;
+  double *zu, *zv, *gu, *gv, *t1, *t1v, *pv, *r, *z, *d, *q, *b;
 };
 
 Work bind(stokes_ctx* st) {
   const size_t NN = static_cast<size_t>(st->N) * st->N;
   double* w = st->wk.as<double>();
   Work k;
-  k.zu = w;
-  k.zv = w + NN;
-  k.gu = w + 2 * NN;
-  k.gv = w + 3 * NN;
-  k.t1 = w + 4 * NN;
-  k.pv = w + 5 * NN;
-  k.r = w + 6 * NN;
-  k.z = w + 7 * NN;
-  k.d = w + 8 * NN;
-  k.q = w + 9 * NN;
-  k.b = w + 10 * NN;
+  double** f[] = {&k.zu, &k.zv, &k.gu, &k.gv, &k.t1, &k.t1v, &k.pv, &k.r, &k.z, &k.d, &k.q, &k.b};
+  for (size_t i = 0; i < sizeof(f) / sizeof(f[0]); ++i) *f[i] = w + i * NN;
   return k;
 }
-constexpr int kWorkFields = 11;
+constexpr int kWorkFields = 12;
+constexpr int kPostRing = 4;  // CG records in flight (at most two iterations are unexamined)
+static_assert(sizeof(stokes_ctx::ev) / sizeof(hipEvent_t) == kPostRing, "one event per record");
 
-// C = A B, row-major operands: A (m x k, row stride lda), B (k x n, row stride ldb)
-void gemm(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
-          double* C, int ldc) {
-  hipLaunchKernelGGL(k_st_gemm, dim3(nblk(n, kGT), nblk(m, kGT)), dim3(256), 0, s, m, n, k, A, lda,
-                     B, ldb, C, ldc);
+GemmArgs ga(int m, int n, int k, const double* A, int lda, const double* B, int ldb, double* C,
+            int ldc, int epi = EP_NONE, int amode = AM_PLAIN, const double* D = nullptr) {
+  GemmArgs g;
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.D = D;
+  g.amode = amode;
+  g.epi = epi;
+  return g;
 }
 
-// z = (c^2 - Delta_h)^-1 f for the u unknowns ([N][N-1]; comp 0) or the v unknowns
-// ([N-1][N]; comp 1): forward transforms, division by the eigenvalues, inverse.
-void vel_solve(stokes_ctx* st, int comp, const double* f, double* z, double* t1) {
+GemmConst gconst(const stokes_ctx* st) {
+  return GemmConst{st->N, 1.0 / st->h, 1.0 / (st->h * st->h), st->c2};
+}
+
+// One product, or two independent ones in the same launch.
+void gemm(stokes_ctx* st, const GemmArgs& a, const GemmArgs* b = nullptr) {
+  int gx = nblk(a.n, kGT), gy = nblk(a.m, kGT);
+  if (b) {
+    gx = std::max(gx, nblk(b->n, kGT));
+    gy = std::max(gy, nblk(b->m, kGT));
+  }
+  hipLaunchKernelGGL(k_st_gemm, dim3(gx, gy, b ? 2 : 1), dim3(256 * kKS), 0, st->stream, a,
+                     b ? *b : a,
+                     gconst(st));
+}
+
+// z = (c^2 - Delta_h)^-1 f for both velocity components at once: the u unknowns ([N][N-1]:
+// rows DST-II, columns DST-I) and the v unknowns ([N-1][N]: rows DST-I, columns DST-II);
+// forward transforms, division by the eigenvalues (with the second product), inverse.
+// With grad, f is the pressure gradient of the cell array fu (fv unused).
+void vel_solve(stokes_ctx* st, const double* fu, const double* fv, bool grad, double* zu,
+               double* zv, double* t1u, double* t1v) {
   const int N = st->N, n = N - 1;
-  hipStream_t s = st->stream;
   const double* S1 = st->S1.as<double>();
   const double* S2 = st->S2.as<double>();
   const double* S2T = st->S2T.as<double>();
-  const double ih2 = 1.0 / (st->h * st->h);
-  if (comp == 0) {  // rows: DST-II (N), columns: DST-I (N-1)
-    gemm(s, N, n, n, f, n, S1, n, t1, n);        // t1 = F S1^T (S1 symmetric)
-    gemm(s, N, n, N, S2, N, t1, n, z, n);        // z = S2 t1
-    hipLaunchKernelGGL(k_st_scale, dim3(nblk(N * n, 256)), dim3(256), 0, s, N, n, N, ih2, st->c2,
-                       0, z);
-    gemm(s, N, n, N, S2T, N, z, n, t1, n);       // t1 = S2^T z
-    gemm(s, N, n, n, t1, n, S1, n, z, n);        // z = t1 S1
-  } else {  // rows: DST-I (N-1), columns: DST-II (N)
-    gemm(s, n, N, N, f, N, S2T, N, t1, N);       // t1 = F S2^T
-    gemm(s, n, N, n, S1, n, t1, N, z, N);        // z = S1 t1
-    hipLaunchKernelGGL(k_st_scale, dim3(nblk(N * n, 256)), dim3(256), 0, s, n, N, N, ih2, st->c2,
-                       1, z);
-    gemm(s, n, N, n, S1, n, z, N, t1, N);        // t1 = S1^T z (S1 symmetric)
-    gemm(s, n, N, N, t1, N, S2, N, z, N);        // z = t1 S2
-  }
+  GemmArgs u, v;
+  u = ga(N, n, n, fu, n, S1, n, t1u, n, EP_NONE, grad ? AM_GRAD_U : AM_PLAIN);  // F S1^T
+  v = ga(n, N, N, grad ? fu : fv, N, S2T, N, t1v, N, EP_NONE, grad ? AM_GRAD_V : AM_PLAIN);
+  gemm(st, u, &v);
+  u = ga(N, n, N, S2, N, t1u, n, zu, n, EP_VEL);  // S2 t1 / lambda
+  v = ga(n, N, n, S1, n, t1v, N, zv, N, EP_VEL);  // S1 t1 / lambda
+  gemm(st, u, &v);
+  u = ga(N, n, N, S2T, N, zu, n, t1u, n);         // S2^T z
+  v = ga(n, N, n, S1, n, zv, N, t1v, N);          // S1^T z (S1 symmetric)
+  gemm(st, u, &v);
+  u = ga(N, n, n, t1u, n, S1, n, zu, n);          // t1 S1
+  v = ga(n, N, N, t1v, N, S2, N, zv, N);          // t1 S2
+  gemm(st, u, &v);
 }
 
-// z = r + c^2 L^-1 r (cells; L the zero-flux cell Laplacian, mean-free part)
+// z = r + c^2 L^-1 r (cells; L the zero-flux cell Laplacian, mean-free part); c^2 > 0
 void precond(stokes_ctx* st, const double* r, double* z, double* t1) {
   const int N = st->N;
-  const size_t NN = static_cast<size_t>(N) * N;
-  hipStream_t s = st->stream;
-  if (st->c2 == 0.0) {
-    hipLaunchKernelGGL(k_st_axpby, dim3(nblk(NN, 256)), dim3(256), 0, s, static_cast<int>(NN),
-                       1.0, r, 0.0, z);
-    return;
-  }
   const double* C2 = st->C2.as<double>();
   const double* C2T = st->C2T.as<double>();
-  gemm(s, N, N, N, r, N, C2T, N, t1, N);         // t1 = R C2^T
-  gemm(s, N, N, N, C2, N, t1, N, z, N);          // z = C2 t1
-  hipLaunchKernelGGL(k_st_scale, dim3(nblk(NN, 256)), dim3(256), 0, s, N, N, N,
-                     1.0 / (st->h * st->h), st->c2, 2, z);
-  gemm(s, N, N, N, C2T, N, z, N, t1, N);         // t1 = C2^T z
-  gemm(s, N, N, N, t1, N, C2, N, z, N);          // z = t1 C2
-  hipLaunchKernelGGL(k_st_axpby, dim3(nblk(NN, 256)), dim3(256), 0, s, static_cast<int>(NN), 1.0,
-                     r, 1.0, z);
+  gemm(st, ga(N, N, N, r, N, C2T, N, t1, N));                      // R C2^T
+  gemm(st, ga(N, N, N, C2, N, t1, N, z, N, EP_CELL));              // c^2 C2 t1 / lambda
+  gemm(st, ga(N, N, N, C2T, N, z, N, t1, N));                      // C2^T z
+  gemm(st, ga(N, N, N, t1, N, C2, N, z, N, EP_NONE, AM_PLAIN, r)); // t1 C2 + r
 }
+
+int red_blocks(int n) { return std::min(kRedBlocks, nblk(n, 256)); }
 
 // sc[slot] = scale * (a . b), or scale * sum(a) when b is null and sq is 0
 void dot(stokes_ctx* st, int n, const double* a, const double* b, int slot, double scale = 1.0,
          int sq = 1) {
-  hipStream_t s = st->stream;
-  const int nb = std::min(kRedBlocks, nblk(n, 256));
-  hipLaunchKernelGGL(k_st_dot, dim3(nb), dim3(256), 0, s, n, a, b, sq, st->part.as<double>());
-  hipLaunchKernelGGL(k_st_dot_fin, dim3(1), dim3(256), 0, s, nb, st->part.as<double>(),
+  const int nb = red_blocks(n);
+  double* part = st->part.as<double>();
+  hipLaunchKernelGGL(k_st_dot, dim3(nb), dim3(256), 0, st->stream, n, a, b, sq, part);
+  hipLaunchKernelGGL(k_st_dot_fin, dim3(1), dim3(256), 0, st->stream, nb, part,
                      st->sc.as<double>() + slot, scale);
-}
-
-int read_scalar(stokes_ctx* st, int slot, double* out) {
-  KFBI_HIP(hipMemcpyAsync(out, st->sc.as<double>() + slot, sizeof(double), hipMemcpyDeviceToHost,
-                          st->stream));
-  KFBI_HIP(hipStreamSynchronize(st->stream));
-  return KFBI_OK;
 }
 
 // The MAC system with right-hand sides ru, rv, rp (zero box data): CG on
 // S p = (rp - mean rp) - G^T (c^2 - Delta)^-1 F, then u = -(c^2 - Delta)^-1 (F + G p).
+// The host checks convergence one iteration behind the GPU: iteration it + 1 is queued
+// before the record of iteration it is read, and runs without effect when it was the last.
 int mac_solve(stokes_ctx* st) {
   const int N = st->N;
   const int NN = N * N, nu = N * (N - 1);
@@ -664,68 +820,77 @@ int mac_solve(stokes_ctx* st) {
   Work w = bind(st);
   const double ih = 1.0 / st->h;
   double* sc = st->sc.as<double>();
+  double* part = st->part.as<double>();
   const double* ru = st->ru.as<double>();
   const double* rv = st->rv.as<double>();
   const double* rp = st->rp.as<double>();
+  const bool pre = st->c2 > 0.0;  // with c^2 = 0 the preconditioner is the identity
+  double* z = pre ? w.z : w.r;
   // b = (rp - mean) - G^T (c^2 - Delta)^-1 F
-  vel_solve(st, 0, ru, w.zu, w.t1);
-  vel_solve(st, 1, rv, w.zv, w.t1);
+  vel_solve(st, ru, rv, false, w.zu, w.zv, w.t1, w.t1v);
   dot(st, NN, rp, nullptr, SC_MEAN, 1.0 / NN, 0);  // mean of the continuity right-hand side
   hipLaunchKernelGGL(k_st_sub_scalar, dim3(nblk(NN, 256)), dim3(256), 0, s, NN, sc, SC_MEAN, rp,
                      w.t1);
   hipLaunchKernelGGL(k_st_gradT, dim3(nblk(NN, 256)), dim3(256), 0, s, N, ih, w.zu, w.zv, -1.0,
                      w.t1, 1.0, w.b);
-  // CG from p = 0
+  // CG from p = 0: r = b, z = M^-1 r, d = z
   KFBI_HIP(hipMemsetAsync(w.pv, 0, sizeof(double) * NN, s));
   KFBI_HIP(hipMemcpyAsync(w.r, w.b, sizeof(double) * NN, hipMemcpyDeviceToDevice, s));
   dot(st, NN, w.b, nullptr, SC_BN);
-  precond(st, w.r, w.z, w.t1);
-  KFBI_HIP(hipMemcpyAsync(w.d, w.z, sizeof(double) * NN, hipMemcpyDeviceToDevice, s));
-  dot(st, NN, w.r, w.z, SC_RZ);
-  double bn2 = 0.0;
-  KFBI_TRY(read_scalar(st, SC_BN, &bn2));
-  const double bn = sqrt(bn2);
-  int it = 0;
+  hipLaunchKernelGGL(k_st_cg_init, dim3(1), dim3(64), 0, s, sc);
+  if (pre) precond(st, w.r, w.z, w.t1);
+  KFBI_HIP(hipMemcpyAsync(w.d, z, sizeof(double) * NN, hipMemcpyDeviceToDevice, s));
+  dot(st, NN, w.r, z, SC_RZ);
+  const double tol2 = st->tol * st->tol;
+  const int G = red_blocks(NN);  // blocks of the reduction launches, partials per sum
+  int launched = 0, examined = 0, it = 0;
+  bool done = false;
   double rel = 0.0;
-  if (bn > 0.0) {
-    for (; it < st->maxit;) {
-      // q = S d = G^T (c^2 - Delta)^-1 G d
-      hipLaunchKernelGGL(k_st_grad, dim3(nblk(2 * nu, 256)), dim3(256), 0, s, N, ih, w.d, nullptr,
-                         nullptr, w.gu, w.gv);
-      vel_solve(st, 0, w.gu, w.zu, w.t1);
-      vel_solve(st, 1, w.gv, w.zv, w.t1);
-      hipLaunchKernelGGL(k_st_gradT, dim3(nblk(NN, 256)), dim3(256), 0, s, N, ih, w.zu, w.zv, 1.0,
-                         nullptr, 0.0, w.q);
-      dot(st, NN, w.d, w.q, SC_DQ);
-      hipLaunchKernelGGL(k_st_cg_step, dim3(nblk(NN, 256)), dim3(256), 0, s, NN, sc, w.pv, w.r,
-                         w.d, w.q);
-      ++it;
-      dot(st, NN, w.r, nullptr, SC_RN);
-      double rn2 = 0.0;
-      KFBI_TRY(read_scalar(st, SC_RN, &rn2));
-      rel = sqrt(rn2) / bn;
+  while (!done && examined < st->maxit) {
+    if (launched < st->maxit) {
+      const int k = launched;
+      // q = S d = G^T (c^2 - Delta)^-1 G d, and d . q
+      vel_solve(st, w.d, nullptr, true, w.zu, w.zv, w.t1, w.t1v);
+      hipLaunchKernelGGL(k_st_gradT_dot, dim3(G), dim3(256), 0, s, N, ih, w.zu, w.zv, w.d, w.q,
+                         part);
+      hipLaunchKernelGGL(k_st_cg_step, dim3(G), dim3(256), 0, s, NN, k, G, sc, w.pv, w.r, w.d,
+                         w.q, part);
+      if (pre) precond(st, w.r, w.z, w.t1);
+      hipLaunchKernelGGL(k_st_dot, dim3(G), dim3(256), 0, s, NN, w.r, z, 1, part + 2 * kRedBlocks);
+      hipLaunchKernelGGL(k_st_cg_dir, dim3(G), dim3(256), 0, s, NN, k, G, tol2, sc, z, w.d, part,
+                         st->dpost + (k % kPostRing));
+      KFBI_HIP(hipGetLastError());
+      KFBI_HIP(hipEventRecord(st->ev[k % kPostRing], s));
+      ++launched;
+    }
+    // examine every launched iteration but the newest (all of them once no more launch)
+    const int upto = (launched < st->maxit) ? launched - 1 : launched;
+    while (!done && examined < upto) {
+      KFBI_HIP(hipEventSynchronize(st->ev[examined % kPostRing]));
+      const CgPost& rec = st->hpost[examined % kPostRing];
+      ++examined;
+      it = examined;
+      rel = rec.bn2 > 0.0 ? sqrt(rec.rn2 / rec.bn2) : 0.0;
+      if (rec.bn2 == 0.0) it = 0;
       if (!std::isfinite(rel)) {
+        KFBI_HIP(hipStreamSynchronize(s));
         set_error("stokes: non-finite CG residual");
         return KFBI_E_NONFINITE;
       }
-      if (rel <= st->tol) break;
-      precond(st, w.r, w.z, w.t1);
-      dot(st, NN, w.r, w.z, SC_RZN);
-      hipLaunchKernelGGL(k_st_cg_dir, dim3(nblk(NN, 256)), dim3(256), 0, s, NN, sc, w.z, w.d);
-      hipLaunchKernelGGL(k_st_shift, dim3(1), dim3(1), 0, s, sc);
+      done = rec.done != 0;
     }
   }
   st->cg_iters = it;
   st->cg_relres = rel;
-  if (bn > 0.0 && rel > st->tol) {
+  if (!done) {
+    KFBI_HIP(hipStreamSynchronize(s));
     set_error("stokes: CG did not reach %.3e in %d iterations (relres %.3e)", st->tol, it, rel);
     return KFBI_E_NOCONV;
   }
   // velocities u = -(c^2 - Delta)^-1 (F + G p); pressure p
   hipLaunchKernelGGL(k_st_grad, dim3(nblk(2 * nu, 256)), dim3(256), 0, s, N, ih, w.pv, ru, rv,
                      w.gu, w.gv);
-  vel_solve(st, 0, w.gu, w.zu, w.t1);
-  vel_solve(st, 1, w.gv, w.zv, w.t1);
+  vel_solve(st, w.gu, w.gv, false, w.zu, w.zv, w.t1, w.t1v);
   hipLaunchKernelGGL(k_st_fields, dim3(nblk(2 * N * (N + 1), 256)), dim3(256), 0, s, N, -1.0, w.zu,
                      w.zv, st->u.as<double>(), st->v.as<double>());
   KFBI_HIP(hipMemcpyAsync(st->p.as<double>(), w.pv, sizeof(double) * NN, hipMemcpyDeviceToDevice,
@@ -821,11 +986,29 @@ int stokes_create(const stokes_params* p, stokes_ctx** out) {
       (rc = st->S2.ensure(sizeof(double) * NN)) || (rc = st->C2.ensure(sizeof(double) * NN)) ||
       (rc = st->S2T.ensure(sizeof(double) * NN)) || (rc = st->C2T.ensure(sizeof(double) * NN)) ||
       (rc = st->wk.ensure(sizeof(double) * NN * kWorkFields)) ||
-      (rc = st->part.ensure(sizeof(double) * kRedBlocks)) ||
+      (rc = st->part.ensure(sizeof(double) * 3 * kRedBlocks)) ||
       (rc = st->sc.ensure(sizeof(double) * SC_COUNT)) ||
       (rc = st->flag.ensure(sizeof(int))) ||
       (rc = st->Q.ensure(sizeof(double) * 6 * p->max_markers)))
     return fail(rc);
+  void* hp = nullptr;
+  if (hipHostMalloc(&hp, sizeof(CgPost) * kPostRing, hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess) {
+    set_error("stokes: pinned host memory for the CG records");
+    return fail(KFBI_E_HIP);
+  }
+  st->hpost = static_cast<CgPost*>(hp);
+  void* dp = nullptr;
+  if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess) {
+    set_error("stokes: device view of the CG records");
+    return fail(KFBI_E_HIP);
+  }
+  st->dpost = static_cast<CgPost*>(dp);
+  for (int q = 0; q < kPostRing; ++q)
+    if (hipEventCreateWithFlags(&st->ev[q], hipEventDisableTiming) != hipSuccess) {
+      set_error("stokes: CG events");
+      return fail(KFBI_E_HIP);
+    }
   hipLaunchKernelGGL(k_st_trmat, dim3(nblk(NN, 256)), dim3(256), 0, st->stream, N,
                      st->S1.as<double>(), st->S2.as<double>(), st->C2.as<double>(),
                      st->S2T.as<double>(), st->C2T.as<double>());
@@ -843,6 +1026,9 @@ int stokes_destroy(stokes_ctx* st) {
   for (DBuf* b : {&st->Q, &st->J, &st->ru, &st->rv, &st->rp, &st->u, &st->v, &st->p, &st->S1,
                   &st->S2, &st->C2, &st->S2T, &st->C2T, &st->wk, &st->part, &st->sc, &st->flag})
     b->release();
+  for (hipEvent_t& e : st->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (st->hpost) (void)hipHostFree(st->hpost);
   if (st->g2) kfbi_destroy(st->g2);
   delete st;
   return KFBI_OK;
