@@ -466,7 +466,11 @@ __global__ void __launch_bounds__(256)
   const int n = N - 1;
   const int mask = 2 * N - 1;
   const int tid = threadIdx.x;
-  const int q = blockIdx.x;
+  // XCD-aware order: blocks resident on one XCD (ids congruent mod 8) take consecutive
+  // parts, so the four parts that share each 128-byte line of the output meet in one L2
+  const int per_xcd = static_cast<int>(gridDim.x) / 8;
+  const int q = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (q >= P) return;
   const int cap = kArmsPerPart * P;
   rslot += static_cast<size_t>(blockIdx.y) * cap;
   Tg += static_cast<size_t>(blockIdx.y) * tstride;
@@ -1294,7 +1298,7 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   // band fits where the column-group one did); the full grid keeps the column groups
   const int ldr = full ? 0 : 4 * ((n + 3) / 4);
   if (P > 0 && (stages & 2))
-    hipLaunchKernelGGL((k_rowdst<T, PT, false>), dim3(P, B), dim3(256), 0, s, N, P, c->pdesc.as<int4>(),
+    hipLaunchKernelGGL((k_rowdst<T, PT, false>), dim3(8 * nblk(P, 8), B), dim3(256), 0, s, N, P, c->pdesc.as<int4>(),
                        c->armr.as<double>(), c->armk.as<int>() + c->arm_cap,
                        c->armsc.as<double>(), sinT, Tg, tstride);
   if (ev) hipEventRecord(ev[2], s);
@@ -1355,7 +1359,7 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
   const size_t tstride = 4 * static_cast<size_t>(ngm) * (c->st.n_parts + 1);
   const size_t gstride = 4 * static_cast<size_t>(ngm) * nm;
   if (P > 0 && (stages & 2))
-    hipLaunchKernelGGL((k_rowdst<T, PT, true>), dim3(P, B), dim3(256), 0, s, N, P,
+    hipLaunchKernelGGL((k_rowdst<T, PT, true>), dim3(8 * nblk(P, 8), B), dim3(256), 0, s, N, P,
                        c->pdesc.as<int4>(), c->armr.as<double>(),
                        c->armk.as<int>() + c->arm_cap, c->armsc.as<double>(), sinT, Tg,
                        tstride);
