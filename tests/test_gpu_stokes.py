@@ -121,3 +121,32 @@ def test_errors():
     with pytest.raises(kfbi.KfbiError) as e:
         kfbi.Stokes(-1, -1, 2, 48, 1.0)                     # N not a power of two
     assert e.value.code == kfbi.E_INVALID
+
+
+def test_traces_converge_up_to_the_largest_grid():
+    """Grid refinement to N = 1024, the largest grid the context accepts (no oracle at these
+    sizes: a property that holds at any size).  One continuous density (the same Fourier
+    series sampled at M = 288, 576, 1152 markers, about 1.6 h apart) on the flower; the
+    outside traces at the markers the three runs share converge at about second order
+    (Sec. 4.2.2 / 4.3: second-order scheme and interpolation; pre-asymptotic orders of 1.5 to
+    1.75 on the oracle's coarser grids), and every CG solve reaches its tolerance."""
+    c2 = 1000.0
+    traces = []
+    for N in (256, 512, 1024):
+        box = W.box(-1, 1, N)
+        M = int(round(3.6 / (1.6 * box.h) / 2)) * 2
+        print(f"[case] stokes refinement flower N={N} M={M}", flush=True)
+        st = make(box, c2, Mx=M)
+        st.set_interface(dev(curve("flower", M)))
+        _, um = st.apply(dev(density(M, 7)))
+        info = st.info()
+        print("  CG iterations", info["cg_iters"], "relres", info["cg_relres"])
+        assert info["cg_relres"] <= 1e-13
+        u = host(um)
+        assert np.all(np.isfinite(u))
+        traces.append(u[:, :: M // 288])
+        st.close()
+    e1 = np.max(np.abs(traces[1] - traces[0]))
+    e2 = np.max(np.abs(traces[2] - traces[1]))
+    print(f"  successive differences {e1:.3e} {e2:.3e} ratio {e1 / e2:.2f}")
+    assert e2 < e1 / 2.5
