@@ -110,3 +110,33 @@ def test_solve_allocates_nothing():
                               restart=restart, precision=prec)
             assert st["converged"] and st["relres"] <= 1e-10
             assert ctx.info()["workspace_bytes"] == before, (M, prec, restart)
+
+
+def test_interior_dirichlet_refinement_to_512():
+    """Config 1 under grid refinement on the GPU (N = 64 .. 512, M = N markers, about 1.6 h
+    apart; beyond N = 128 the oracle is not run: a property that holds at any size): the
+    GMRES solution's grid values approximate exp(x) sin(y) at the inside nodes with an error
+    that falls at about second order (Sec. 4.2 / 4.3), as the oracle's does on 32..128."""
+    from paper_2309_01068_amd import kfbi
+    errs = []
+    for N in (64, 128, 256, 512):
+        print(f"[case] interior Dirichlet ellipse N={N} M={N}", flush=True)
+        box = W.box(-1, 1, N)
+        X = W.ellipse(N)
+        ctx = kfbi.Context(box.x0, box.y0, box.side, N, 0.0, kfbi.BOX_ZERO, N)
+        ctx.set_interface(dev(X))
+        b = dev(np.exp(X[0]) * np.sin(X[1]))
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        x, gs = ctx.gmres(b, x, kfbi.DOUBLE, kfbi.PLUS, 0.0, 1.0, 0.0, tol=1e-12, restart=50)
+        assert gs["converged"], gs
+        grid = ctx.apply(kfbi.DOUBLE, x, grid=True)["grid"].cpu().numpy()
+        xs = box.x0 + box.h * np.arange(N + 1)
+        XX, YY = np.meshgrid(xs, xs)  # [j, i]
+        inside = (XX / 0.6) ** 2 + (YY / 0.4) ** 2 < 1.0
+        errs.append(np.abs(grid - np.exp(XX) * np.sin(YY))[inside].max())
+        ctx.close()
+    errs = np.array(errs)
+    orders = np.log2(errs[:-1] / errs[1:])
+    print("max errors", errs, "orders", orders)
+    assert np.all(orders > 1.6), (errs, orders)
+    assert errs[-1] < 5e-6
