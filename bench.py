@@ -386,6 +386,16 @@ def extras(kf, W, torch, np, dev, dens, layer):
         secs, _ = time_applies(ctx, kf, dens, outs, 500, 50, layer, prec)
         out[f"applies_per_s_{N}_{'f64' if prec == 0 else 'f32'}"] = round(500 / secs, 1)
         ctx.close()
+    # the double layer (two density derivatives per marker instead of one), FP64
+    for N in (1024, 2048):
+        box = W.box(-1.0, 1.0, N)
+        ctx = kf.Context(box.x0, box.y0, box.side, N, 1000.0, kf.BOX_ZERO, M)
+        ctx.set_interface(torch.tensor(X, device=dev))
+        outs = {k: torch.empty(M, dtype=torch.float64, device=dev)
+                for k in ("v_plus", "v_minus", "dn_plus", "dn_minus")}
+        secs, _ = time_applies(ctx, kf, dens, outs, 500, 50, kf.DOUBLE, 0)
+        out[f"applies_per_s_{N}_f64_double_layer"] = round(500 / secs, 1)
+        ctx.close()
     # GMRES: Hele-Shaw boundary integral equation on the initial curve, 1024^2, 1024 markers
     box = W.box(-2.0, 2.0, 1024)
     Xh = W.hs3(1024)

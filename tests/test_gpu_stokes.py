@@ -123,6 +123,30 @@ def test_errors():
     assert e.value.code == kfbi.E_INVALID
 
 
+@pytest.mark.parametrize("maxit", [1, 3])
+def test_cg_iteration_limit(maxit):
+    """The Schur-complement CG stops at its iteration limit with E_NOCONV (the host checks
+    convergence one iteration behind the GPU, so the limit path ends the lagged loop), the
+    info reports the iterations taken, and the context solves again afterwards."""
+    from paper_2309_01068_amd import kfbi
+    print(f"[case] stokes CG limit maxit={maxit}", flush=True)
+    box = W.box(-1, 1, 64)
+    X = curve("ellipse", 64)
+    st = kfbi.Stokes(box.x0, box.y0, box.side, box.N, 50.0, max_markers=64, tol=1e-13,
+                     maxit=maxit)
+    st.set_interface(dev(X))
+    with pytest.raises(kfbi.KfbiError) as e:
+        st.apply(dev(density(64, 3)))
+    assert e.value.code == kfbi.E_NOCONV
+    info = st.info()
+    assert info["cg_iters"] == maxit and info["cg_relres"] > 1e-13
+    # a zero density: the right-hand side is zero and the solve ends at once
+    up, um = st.apply(torch.zeros((2, 64), dtype=torch.float64, device="cuda"))
+    assert st.info()["cg_iters"] == 0
+    assert torch.count_nonzero(up) == 0 and torch.count_nonzero(um) == 0
+    st.close()
+
+
 def test_traces_converge_up_to_the_largest_grid():
     """Grid refinement to N = 1024, the largest grid the context accepts (no oracle at these
     sizes: a property that holds at any size).  One continuous density (the same Fourier
