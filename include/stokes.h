@@ -38,7 +38,7 @@ typedef struct stokes_ctx stokes_ctx;
 
 typedef struct {
   double x0, y0, side; /* box [x0, x0 + side] x [y0, y0 + side] */
-  int N;               /* intervals per side, 16 <= N <= 1024 */
+  int N;               /* intervals per side, a power of two, 32 <= N <= 1024 */
   double c2;           /* c^2 >= 0 of (Delta - c^2) */
   int max_markers;     /* largest M of stokes_set_interface, <= 2048 */
   void* stream;        /* hipStream_t, or NULL for the null stream */
@@ -53,6 +53,9 @@ typedef struct {
   double cg_relres;     /* its final relative residual */
 } stokes_info;
 
+/* KFBI_E_INVALID for parameters outside the ranges above (or c2 < 0, side <= 0,
+ * solve_tol <= 0, solve_maxit < 1); KFBI_E_HIP when a device or pinned host allocation
+ * fails.  *out is NULL on error. */
 int stokes_create(const stokes_params* p, stokes_ctx** out);
 int stokes_destroy(stokes_ctx* st);
 
@@ -67,6 +70,11 @@ int stokes_set_interface(stokes_ctx* st, int M, const double* xy_dev);
  * The MAC fields of the solution stay in the context (stokes_fields). */
 int stokes_apply(stokes_ctx* st, const double* phi_dev, double* u_plus_dev,
                  double* u_minus_dev);
+/* Errors of stokes_apply (and of stokes_operator, stokes_gmres_solve): KFBI_E_STATE with no
+ * interface installed; KFBI_E_NOCONV when the CG reaches solve_maxit iterations above
+ * solve_tol (stokes_get_info reports the iterations and the residual reached);
+ * KFBI_E_NONFINITE for a non-finite CG residual; KFBI_E_GEOMETRY when a MAC stencil pair and
+ * the interface crossings disagree.  The call returns after the GPU work has finished. */
 
 /* The MAC fields of the last apply: u_dev [N][N+1] (row j - 1, column i = 0..N), v_dev
  * [N+1][N] (row j = 0..N, column i - 1), p_dev [N][N] (row j - 1, column i - 1, mean
