@@ -105,11 +105,11 @@ __global__ void k_st_trmat(int N, double* __restrict__ S1, double* __restrict__ 
 // 16 x 16 quadrant by v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step and holds D[4 i + l / 16][l % 16] in element
 // i of its accumulator).  k runs in chunks of 32 through LDS; the loads of the next chunk
-// are issued before the products of the current one.  A block holds four such groups of
-// four wavefronts, each on its own quarter of k with its own chunk buffers, and adds their
-// tiles in group order at the end (deterministic): the grids of these transforms are
-// small (256 tiles at N = 512), and four wavefronts per SIMD instead of one keep the
-// matrix cores busy while the chunk loads are in flight.
+// are issued before the products of the current one.  A block holds two or four such
+// groups of four wavefronts, each on its own share of k with its own chunk buffers, and
+// adds their tiles in group order at the end (deterministic): the grids of these
+// transforms are small (256 tiles at N = 512), and several wavefronts per SIMD instead of
+// one keep the matrix cores busy while the chunk loads are in flight.
 //
 // One launch computes up to two independent products (blockIdx.z selects the argument
 // set: the u and v velocity solves run side by side).  Operand A can be formed on the fly
@@ -118,11 +118,10 @@ __global__ void k_st_trmat(int N, double* __restrict__ S1, double* __restrict__ 
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kGT = 32;   // output tile
 constexpr int kGK = 32;   // k-chunk staged in LDS
-constexpr int kKS = 4;    // k-slices per block, four wavefronts each
 constexpr int kLdk = kGK + 2;  // LDS row of a chunk buffer: 16-byte reads of consecutive rows
                                // land in different banks
-static_assert(kGK % 8 == 0 && kKS * 2 * kGT * kLdk >= (kKS - 1) * kGT * (kGT + 1),
-              "chunk buffers and the partial tiles share the LDS");
+static_assert(kGK % 8 == 0 && 2 * kGT * kLdk >= kGT * (kGT + 1),
+              "a group's chunk buffers hold at least one partial tile");
 enum { AM_PLAIN = 0, AM_GRAD_U, AM_GRAD_V };      // A = A, (G p) at u points, at v points
 enum { EP_NONE = 0, EP_VEL, EP_CELL };            // C = acc, acc / (lam + c^2), c^2 acc / lam
 struct GemmArgs {
@@ -159,6 +158,7 @@ __device__ __forceinline__ double gemm_epi(int epi, const GemmConst& gc, int r, 
   return v / (lam + gc.c2);
 }
 
+template <int kKS>  // k-slice groups per block
 __global__ void __launch_bounds__(256 * kKS)
     k_st_gemm(GemmArgs g0, GemmArgs g1, GemmConst gc) {
   const GemmArgs g = blockIdx.z ? g1 : g0;  // block-uniform
@@ -756,9 +756,15 @@ void gemm(stokes_ctx* st, const GemmArgs& a, const GemmArgs* b = nullptr) {
     gx = std::max(gx, nblk(b->n, kGT));
     gy = std::max(gy, nblk(b->m, kGT));
   }
-  hipLaunchKernelGGL(k_st_gemm, dim3(gx, gy, b ? 2 : 1), dim3(256 * kKS), 0, st->stream, a,
-                     b ? *b : a,
-                     gconst(st));
+  // a single product: four k-groups per block (one block per CU, four wavefronts per
+  // SIMD); a pair: two k-groups, so two blocks share a CU and the twice larger grid runs
+  // in one round
+  if (b)
+    hipLaunchKernelGGL(k_st_gemm<2>, dim3(gx, gy, 2), dim3(512), 0, st->stream, a, *b,
+                       gconst(st));
+  else
+    hipLaunchKernelGGL(k_st_gemm<4>, dim3(gx, gy, 1), dim3(1024), 0, st->stream, a, a,
+                       gconst(st));
 }
 
 // z = (c^2 - Delta_h)^-1 f for both velocity components at once: the u unknowns ([N][N-1]:
