@@ -440,22 +440,61 @@ __global__ void k_st_margin(int M, const double* __restrict__ X, double xlo, dou
 // Q[c][k], c = 0..5: phi_1, its first and second Fourier derivatives, then phi_2's, with
 // f'(a_k) = sum_m d1[(k - m) mod M] f_m and f'' by d2 (differentiation vectors of the
 // geometry context).
-__global__ void k_st_quant(int M, const double* __restrict__ phi, const double* __restrict__ d1,
-                           const double* __restrict__ d2, double* __restrict__ Q) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 2 * M) return;
-  const int comp = e / M, k = e % M;
+// Block (g, comp): the derivatives of component comp at markers 8g .. 8g + 7.  The
+// density and both circulant coefficient rows are staged in LDS; thread t sums the terms
+// m = t, t + 256, ... of all sixteen outputs, and the partial sums are added in a fixed
+// order (wavefront shuffles, then the four wavefronts).
+constexpr int kQuantOut = 8;
+__global__ void __launch_bounds__(256)
+    k_st_quant(int M, const double* __restrict__ phi, const double* __restrict__ d1,
+               const double* __restrict__ d2, double* __restrict__ Q) {
+  extern __shared__ double qs[];  // f, d1, d2: 3M
+  __shared__ double red[4][2 * kQuantOut];
+  const int comp = blockIdx.y, k0 = blockIdx.x * kQuantOut;
   const double* f = phi + comp * M;
-  double s1 = 0.0, s2 = 0.0;
-  for (int m = 0; m < M; ++m) {
-    int q = k - m;
-    q += (q < 0) ? M : 0;
-    s1 += d1[q] * f[m];
-    s2 += d2[q] * f[m];
+  double* fs = qs;
+  double* c1 = qs + M;
+  double* c2 = qs + 2 * M;
+  for (int m = threadIdx.x; m < M; m += 256) {
+    fs[m] = f[m];
+    c1[m] = d1[m];
+    c2[m] = d2[m];
   }
-  Q[(3 * comp) * M + k] = f[k];
-  Q[(3 * comp + 1) * M + k] = s1;
-  Q[(3 * comp + 2) * M + k] = s2;
+  __syncthreads();
+  double s1[kQuantOut], s2[kQuantOut];
+#pragma unroll
+  for (int r = 0; r < kQuantOut; ++r) s1[r] = s2[r] = 0.0;
+  for (int m = threadIdx.x; m < M; m += 256) {
+    const double fm = fs[m];
+#pragma unroll
+    for (int r = 0; r < kQuantOut; ++r) {
+      int q = k0 + r - m;
+      q += (q < 0) ? M : 0;
+      q -= (q >= M) ? M : 0;
+      s1[r] += c1[q] * fm;
+      s2[r] += c2[q] * fm;
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < kQuantOut; ++r) {
+    const double a = wave_sum(s1[r]), b = wave_sum(s2[r]);
+    if (lane == 0) {
+      red[w][r] = a;
+      red[w][kQuantOut + r] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kQuantOut) {
+    const int r = threadIdx.x, k = k0 + r;
+    if (k < M) {
+      Q[(3 * comp) * M + k] = fs[k];
+      Q[(3 * comp + 1) * M + k] = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
+      Q[(3 * comp + 2) * M + k] =
+          ((red[0][kQuantOut + r] + red[1][kQuantOut + r]) + red[2][kQuantOut + r]) +
+          red[3][kQuantOut + r];
+    }
+  }
 }
 
 // Gaussian elimination with partial pivoting of an n x n system in registers (b
@@ -919,8 +958,8 @@ int apply_impl(stokes_ctx* st, const double* phi, double* plus, double* minus) {
   hipStream_t s = st->stream;
   const double* d1 = g->dvec.as<double>();
   const double* d2 = d1 + M;
-  hipLaunchKernelGGL(k_st_quant, dim3(nblk(2 * M, 128)), dim3(128), 0, s, M, phi, d1, d2,
-                     st->Q.as<double>());
+  hipLaunchKernelGGL(k_st_quant, dim3(nblk(M, kQuantOut), 2), dim3(256), sizeof(double) * 3 * M,
+                     s, M, phi, d1, d2, st->Q.as<double>());
   hipLaunchKernelGGL(k_st_jumps, dim3(nblk(npt, 64)), dim3(64), 0, s, M, nc, g->cross.as<Crossing>(),
                      g->geo.as<double>(), st->Q.as<double>(), st->c2, st->J.as<double>());
   KFBI_HIP(hipMemsetAsync(st->flag.p, 0, sizeof(int), s));
