@@ -1047,11 +1047,12 @@ __global__ void k_seed(int n, const int8_t* __restrict__ lab, double St, double*
   if (t < n) T[t] = lab[t] ? 0.0 : St;
 }
 
-// y = a x + b y (n values)
+// y = a x + b y (n values); with b = 0, y is only written (its old contents may be
+// uninitialised memory, and 0 times a NaN there would be NaN)
 __global__ void k_axpby(int n, double a, const double* __restrict__ x, double b,
                         double* __restrict__ y) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) y[t] = a * x[t] + b * y[t];
+  if (t < n) y[t] = (b != 0.0) ? a * x[t] + b * y[t] : a * x[t];
 }
 
 Aniso to_aniso(const stefan_aniso& a) { return Aniso{a.e0, a.e1, a.e2, double(a.m), a.phi0}; }
