@@ -37,16 +37,24 @@ namespace kfbi {
 constexpr int kColsPerBlock = 4;
 constexpr int kReg = 8;       // circulant outputs per thread in K1
 constexpr int kNodeBatch = 8; // nodes reduced together in K4
+constexpr int kMaxChunk = 16;  // markers per K1/K4 chunk: M / 256 for M <= 4096
 constexpr int kRingNodes = 8;  // free-space box nodes per K1 block
 constexpr int kWinMax = 24;     // derivative window per K1 chunk: at most 16 + 5 markers
 // K4 block size for a single density: eight wavefronts share a chunk's nodes (fewer rows,
-// the long-latency loads of the node loop, per wavefront), four where the FP64 row of
-// E > 32 mode slots per lane would not fit the registers of eight.  A batch launches
-// four-wavefront blocks: with many blocks per CU they overlap better.
+// the long-latency loads of the node loop, per wavefront).  The FP64 row of E > 32 mode
+// slots per lane fits the registers of eight only when the chunk's extraction weights are
+// staged in LDS instead of being held in registers through the node loop
+// (node_stage_ext).  A batch launches four-wavefront blocks: with many blocks per CU they
+// overlap better.
+template <class T, int E>
+__host__ __device__ constexpr bool node_stage_ext() {
+  return sizeof(T) == 8 && E > 32;
+}
 template <class T, int E>
 __host__ __device__ constexpr int node_threads() {
-  return (sizeof(T) == 8 && E > 32) ? 256 : 512;
+  return 512;
 }
+static_assert(kMaxChunk * 256 >= 4096, "chunks of M / 256 markers for M up to 4096");
 
 // Two-level sine table in LDS: sin/cos(pi m / N) for m = 64 q + r from
 // hs/hc[q] = sin/cos(pi 64 q / N) and ls/lc[r] = sin/cos(pi r / N) by angle addition.
@@ -1052,18 +1060,31 @@ __global__ void __launch_bounds__(NT)
   SinTab2<T> st2;
   st2.stage(tab, N, sinT);
   __syncthreads();
-  // prefetch the extraction data of this thread's marker (used after the node phase)
+  // prefetch the extraction data of this thread's marker (used after the node phase): in
+  // the registers of thread m < MC, except the weights of the FP64 rows of more than 32
+  // mode slots per lane, which the block stages in LDS (their registers would otherwise
+  // keep the kernel at four wavefronts)
+  constexpr bool kStageX = node_stage_ext<T, E>();
   const int kx = ch * MC + tid;
   const bool xmk = (tid < MC && kx < M);
   int loc[6];
   double Q[5], xw[kExtCount - 1];
+  __shared__ double xs[kStageX ? (kExtCount - 1) * kMaxChunk : 1];
   if (xmk) {
 #pragma unroll
     for (int m = 0; m < 6; ++m) loc[m] = mkloc[6 * kx + m];
 #pragma unroll
     for (int q = 0; q < 5; ++q) Q[q] = mq[q * M + kx];
+    if constexpr (!kStageX) {
 #pragma unroll
-    for (int q = 0; q < kExtCount - 1; ++q) xw[q] = ext[q * M + kx];
+      for (int q = 0; q < kExtCount - 1; ++q) xw[q] = ext[q * M + kx];
+    }
+  }
+  if constexpr (kStageX) {
+    for (int e = tid; e < (kExtCount - 1) * MC; e += NT) {
+      const int q = e / MC, m = e - q * MC, km = ch * MC + m;
+      if (km < M) xs[q * MC + m] = ext[q * M + km];
+    }
   }
   double qs = 0.0;
   if (yop && oq != 0.0) {
@@ -1165,6 +1186,10 @@ __global__ void __launch_bounds__(NT)
   __syncthreads();
   if (!xmk) return;
   const int k = kx;
+  if constexpr (kStageX) {
+#pragma unroll
+    for (int q = 0; q < kExtCount - 1; ++q) xw[q] = xs[q * MC + tid];
+  }
   double v[6];
 #pragma unroll
   for (int m = 0; m < 6; ++m) v[m] = nval[loc[m]];
