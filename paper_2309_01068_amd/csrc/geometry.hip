@@ -406,19 +406,42 @@ __global__ void k_geo_clear(int nn, int nr, int* __restrict__ hid, int* __restri
   if (t < nr) rowoff[t] = 0;
 }
 
-__global__ void k_label(int N, const int* __restrict__ hid, int8_t* __restrict__ lab) {
-  __shared__ int scratch[17];
+// Labels of row j: node i is inside iff the row's crossings on the segments left of it are
+// odd in number.  Each wavefront takes consecutive chunks of 64 nodes: one coalesced load
+// per lane and chunk, the chunk's crossings as a ballot mask, the parity before a lane by
+// a popcount of the mask's lower bits, the parity carried in from the wavefronts to the
+// left through LDS.  One block of 256 threads per row, N + 1 <= 64 * 4 * kLabelChunks.
+constexpr int kLabelChunks = 9;
+static_assert(64 * 4 * kLabelChunks >= 2049, "rows of up to 2049 nodes (N <= 2048)");
+__global__ void __launch_bounds__(256) k_label(int N, const int* __restrict__ hid,
+                                               int8_t* __restrict__ lab) {
+  __shared__ int wpar[4];
   const int j = blockIdx.x;
   const int n1 = N + 1;
-  const int T = blockDim.x;
-  const int per = (n1 + T - 1) / T;
-  const int b = threadIdx.x * per, e = min(n1, b + per);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += (hid[j * n1 + i] >= 0);
-  int acc = block_excl_scan(s, scratch, nullptr);
-  for (int i = b; i < e; ++i) {
-    lab[j * n1 + i] = static_cast<int8_t>(acc & 1);
-    acc += (hid[j * n1 + i] >= 0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nch = (n1 + 63) >> 6;
+  const int per = (nch + 3) >> 2;
+  const int c0 = w * per, c1 = min(nch, c0 + per);
+  unsigned long long mask[kLabelChunks];
+  int par = 0;
+#pragma unroll
+  for (int u = 0; u < kLabelChunks; ++u) {
+    const int i = (c0 + u) * 64 + lane;
+    const bool x = (c0 + u < c1) && i < n1 && hid[j * n1 + i] >= 0;
+    mask[u] = __ballot(x);
+    par ^= __popcll(mask[u]) & 1;
+  }
+  if (lane == 0) wpar[w] = par;
+  __syncthreads();
+  int carry = 0;
+  for (int q = 0; q < w; ++q) carry ^= wpar[q];
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int u = 0; u < kLabelChunks; ++u) {
+    const int i = (c0 + u) * 64 + lane;
+    if (c0 + u < c1 && i < n1)
+      lab[j * n1 + i] = static_cast<int8_t>(carry ^ (__popcll(mask[u] & below) & 1));
+    carry ^= __popcll(mask[u]) & 1;
   }
 }
 
