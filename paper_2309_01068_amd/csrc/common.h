@@ -173,6 +173,11 @@ int gmres_alloc(kfbi_ctx* c);
 // y = A x for GMRES; the flag asks for the operator in FP32 (iterative refinement and
 // mixed modes).
 using GmresOp = std::function<int(const double* x, double* y, bool fp32)>;
+// kfbi_gmres_solve whose FP64 applies also write the outputs `side`; *side_at_x tells
+// whether they belong to the returned solution.
+int gmres_solve_side(kfbi_ctx* c, const kfbi_bie* op, const double* b, double* x,
+                     const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, const kfbi_out* side,
+                     bool* side_at_x);
 int gmres_solve_op(kfbi_ctx* c, int n, const GmresOp& op, const double* b, double* x,
                    const kfbi_gmres_opts* o, kfbi_gmres_stats* stats);
 // Device address of the static GMRES workspace on the current device (once per device).

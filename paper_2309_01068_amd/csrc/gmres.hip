@@ -656,10 +656,12 @@ using namespace kfbi;
 
 namespace kfbi {
 static int gmres_run(kfbi_ctx* c, int M, const GmresOp& op, const double* b, double* x,
-                     const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, GmresWork* gwp);
+                     const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, GmresWork* gwp,
+                     bool* last_at_x = nullptr);
 
 static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, double* x,
-                            const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, bool use_static) {
+                            const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, bool use_static,
+                            const kfbi_out* side = nullptr, bool* side_at_x = nullptr) {
   if (!c || !op || !b || !x || !o) {
     set_error("null argument");
     return KFBI_E_INVALID;
@@ -689,19 +691,25 @@ static int gmres_solve_impl(kfbi_ctx* c, const kfbi_bie* op, const double* b, do
   } else {
     bind_work(c, &gw, c->M);
   }
-  // the boundary operator a x + b trace(layer[x]) + q int x ds of the installed interface
-  const GmresOp op_fn = [c, op](const double* xin, double* yout, bool fp32) {
-    return apply_impl(c, op->layer, fp32 ? KFBI_FP32 : KFBI_FP64, xin, nullptr, nullptr, op, xin,
-                      yout);
+  // the boundary operator a x + b trace(layer[x]) + q int x ds of the installed interface;
+  // FP64 applies also write the side outputs (traces, normal derivatives) when asked
+  const GmresOp op_fn = [c, op, side](const double* xin, double* yout, bool fp32) {
+    return apply_impl(c, op->layer, fp32 ? KFBI_FP32 : KFBI_FP64, xin, nullptr,
+                      fp32 ? nullptr : side, op, xin, yout);
   };
-  return gmres_run(c, c->M, op_fn, b, x, o, stats, &gw);
+  return gmres_run(c, c->M, op_fn, b, x, o, stats, &gw, side_at_x);
 }
 
 // Restarted GMRES (FP64, FP32 iterative refinement or mixed) for the operator `op` on
 // vectors of length M, in the workspace gw, on the stream of c.
+// last_at_x (when given) tells whether the last FP64 operator call was at the returned x:
+// true after a converged solve (its final true residual), false for a zero right-hand
+// side (x set to zero after the residual of the initial guess) or an error.
 static int gmres_run(kfbi_ctx* c, int M, const GmresOp& op, const double* b, double* x,
-                     const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, GmresWork* gwp) {
+                     const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, GmresWork* gwp,
+                     bool* last_at_x) {
   GmresWork& gw = *gwp;
+  if (last_at_x) *last_at_x = false;
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   kfbi_gmres_stats loc{};
   KFBI_HIP(hipMemsetAsync(gw.counter, 0, sizeof(unsigned int), c->stream));
@@ -786,6 +794,7 @@ static int gmres_run(kfbi_ctx* c, int M, const GmresOp& op, const double* b, dou
   }
   KFBI_HIP(hipStreamSynchronize(c->stream));
   if (stats) *stats = loc;
+  if (last_at_x) *last_at_x = (status == KFBI_OK && loc.converged && nb != 0.0);
   if (status == KFBI_E_NOCONV)
     set_error("GMRES did not reach tol %.3e in %d iterations (relres %.3e)", o->tol, loc.iters,
               loc.relres);
@@ -794,6 +803,15 @@ static int gmres_run(kfbi_ctx* c, int M, const GmresOp& op, const double* b, dou
 }  // namespace kfbi
 
 namespace kfbi {
+// kfbi_gmres_solve whose FP64 applies also write the outputs `side` of the layer potential
+// of their argument; on return *side_at_x tells whether those outputs belong to the
+// returned solution (the last FP64 apply of a converged solve is its final true residual).
+int gmres_solve_side(kfbi_ctx* c, const kfbi_bie* op, const double* b, double* x,
+                     const kfbi_gmres_opts* o, kfbi_gmres_stats* stats, const kfbi_out* side,
+                     bool* side_at_x) {
+  return gmres_solve_impl(c, op, b, x, o, stats, false, side, side_at_x);
+}
+
 // GMRES with the workspace of c for an operator of the library on vectors of length
 // n <= max_markers of c (FP64 only).
 int gmres_solve_op(kfbi_ctx* c, int n, const GmresOp& op, const double* b, double* x,

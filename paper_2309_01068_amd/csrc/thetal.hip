@@ -3,7 +3,8 @@
 //
 // Per step: k_tl_pre (one workgroup) reconstructs the markers from (eta, L, Xbar) and
 // forms the right-hand side -sigma kappa - v; kfbi_set_interface rebuilds the grid
-// geometry; kfbi_gmres_solve finds the density; one more apply gives d_n(D phi);
+// geometry; GMRES finds the density, its last apply (the true residual at the solution)
+// also gives d_n(D phi);
 // k_tl_post (one workgroup) forms U, V, the explicit term, and advances eta (integrating
 // factor AB2 in Fourier space), L and Xbar (AB2).  All spectral operations are radix-2
 // Stockham FFTs of length M held in LDS, FP64.
@@ -904,15 +905,21 @@ int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
   auto t1 = std::chrono::steady_clock::now();
   const kfbi_bie op{KFBI_DOUBLE, KFBI_MINUS, 0.0, 1.0, 1.0, nullptr};
   kfbi_gmres_stats gs{};
-  st = kfbi_gmres_solve(th->kc, &op, th->rhs.as<double>(), th->phiw.as<double>(), &p.gmres, &gs);
+  // the FP64 applies of the solve also write d_n(D x); the last one is the final true
+  // residual at the solution, so d_n(D phi) comes with the solve
+  kfbi_out o{nullptr, nullptr, th->dnp.as<double>(), th->dnm.as<double>(), nullptr};
+  bool dn_ready = false;
+  st = gmres_solve_side(th->kc, &op, th->rhs.as<double>(), th->phiw.as<double>(), &p.gmres, &gs,
+                        &o, &dn_ready);
   if (st != KFBI_OK) return st;
   const double ms_gm = ms_since(t1);
-  // the velocity apply and the update run without a host synchronisation between them;
-  // their times come from events
+  // the velocity apply (only when the solve did not end with one at the solution) and the
+  // update run without a host synchronisation between them; their times come from events
   KFBI_HIP(hipEventRecord(th->tev[0], s));
-  kfbi_out o{nullptr, nullptr, th->dnp.as<double>(), th->dnm.as<double>(), nullptr};
-  st = kfbi_apply(th->kc, KFBI_DOUBLE, KFBI_FP64, th->phiw.as<double>(), nullptr, &o);
-  if (st != KFBI_OK) return st;
+  if (!dn_ready) {
+    st = kfbi_apply(th->kc, KFBI_DOUBLE, KFBI_FP64, th->phiw.as<double>(), nullptr, &o);
+    if (st != KFBI_OK) return st;
+  }
   KFBI_HIP(hipEventRecord(th->tev[1], s));
   const double lam2 = p.lambda2 < 0.0 ? p.sigma : p.lambda2;
   hipLaunchKernelGGL(k_tl_post, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), s, M, p.J, p.tau,
