@@ -514,13 +514,15 @@ constexpr int kSlotRes = kRing, kSlotNb = kRing + 1;
 // device status and host slot kSlotRes, and synchronises (which also makes every host
 // slot written before it readable).
 static int true_residual(kfbi_ctx* c, int M, const GmresOp& op, bool fp32, const double* b,
-                         const double* x, GmresWork* gw, double* out, int* applies) {
+                         const double* x, GmresWork* gw, double* out, int* applies,
+                         bool sync = true) {
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   KFBI_TRY(op(x, gw->y, fp32));
   ++*applies;
   hipLaunchKernelGGL(k_residual, dim3(nblk), dim3(kRedBlock), 0, c->stream, M, b, gw->y, gw->r,
                      gw->part, gw->counter, gw->st, gw->dring + kSlotRes);
   KFBI_HIP(hipGetLastError());
+  if (!sync) return KFBI_OK;  // the caller reads the host slot after a later event
   KFBI_HIP(hipStreamSynchronize(c->stream));
   *out = gw->hring[kSlotRes].resid;
   return KFBI_OK;
@@ -529,7 +531,11 @@ static int true_residual(kfbi_ctx* c, int M, const GmresOp& op, bool fp32, const
 // Restarted GMRES for A x = b with the operator at `precision`; stops when the true
 // residual (same precision) is <= tol * nb or after maxit Arnoldi steps.
 // With r_ready the residual of the incoming x is already in gw->r and the device status,
-// with norm rn0, and the first cycle starts from it.
+// with norm rn0, and the first cycle starts from it.  With pending as well, rn0 and the
+// norm nb of the right-hand side are not known on the host yet: the first cycle starts at
+// once and reads both from their host slots when it examines its first step (which was
+// queued behind them); a right-hand side of zero then ends the solve (*zero_rhs) and an
+// initial guess that already meets the tolerance ends the cycle with no update.
 // Mixed mode (mixed_thresh > 0, precision FP64): the applies of the Arnoldi steps run in
 // FP32 once the last residual estimate the host has read is at most mixed_thresh * nb,
 // the Krylov basis, the Hessenberg matrix, the rotations and every true residual staying
@@ -539,7 +545,9 @@ static int true_residual(kfbi_ctx* c, int M, const GmresOp& op, bool fp32, const
 static int gmres_core(kfbi_ctx* c, int M, const GmresOp& op, int precision, const double* b,
                       double* x, double nb, double tol, int restart, int maxit, GmresWork* gw,
                       int* iters, int* cycles, int* applies, double* relres, bool r_ready,
-                      double rn0, double mixed_thresh = 0.0, int* applies32 = nullptr) {
+                      double rn0, double mixed_thresh = 0.0, int* applies32 = nullptr,
+                      bool pending = false, double* nb_out = nullptr,
+                      bool* zero_rhs = nullptr) {
   const int nblk = (M + kRedBlock - 1) / kRedBlock;
   const int mb = (M + 255) / 256;
   hipStream_t s = c->stream;
@@ -555,12 +563,14 @@ static int gmres_core(kfbi_ctx* c, int M, const GmresOp& op, int precision, cons
     } else {
       KFBI_TRY(true_residual(c, M, op, precision == KFBI_FP32, b, x, gw, &rn, applies));
     }
-    if (!std::isfinite(rn)) {
-      set_error("non-finite residual in GMRES");
-      return KFBI_E_NONFINITE;
+    if (!pending) {
+      if (!std::isfinite(rn)) {
+        set_error("non-finite residual in GMRES");
+        return KFBI_E_NONFINITE;
+      }
+      *relres = rn / nb;
+      if (rn <= tol * nb) return KFBI_OK;
     }
-    *relres = rn / nb;
-    if (rn <= tol * nb) return KFBI_OK;
     if (*iters >= maxit) return KFBI_E_NOCONV;
     ++*cycles;
     hipLaunchKernelGGL(k_start, dim3(mb), dim3(256), 0, s, M, gw->r, gw->st, gw->V, gw->g);
@@ -576,11 +586,34 @@ static int gmres_core(kfbi_ctx* c, int M, const GmresOp& op, int precision, cons
     const int base = *iters;  // iterations of earlier cycles (< maxit here)
     bool stop = false;
     constexpr int kLag = 1;  // < kRing
-    double r1 = rn, r2 = -1.0;  // residual estimates of the last two examined steps
+    // residual estimates of the last two examined steps (unknown while pending: no
+    // prediction and no FP32 apply before the first step is examined)
+    double r1 = pending ? INFINITY : rn, r2 = -1.0;
+    bool zero = false;
     // reads the status of step q (the next one not yet examined) and decides whether the
     // cycle stops there
     auto examine = [&](int q) -> int {
       KFBI_HIP(hipEventSynchronize(gw->ev[q % kRing]));
+      if (pending) {  // ||b|| and the initial residual, posted before this step was queued
+        pending = false;
+        nb = gw->hring[kSlotNb].resid;
+        const double r0 = gw->hring[kSlotRes].resid;
+        if (nb_out) *nb_out = nb;
+        if (!std::isfinite(r0) || !std::isfinite(nb)) {
+          KFBI_HIP(hipStreamSynchronize(s));
+          set_error("non-finite residual in GMRES");
+          return KFBI_E_NONFINITE;
+        }
+        if (nb == 0.0 || r0 <= tol * nb) {  // nothing to do: no step counts, no update
+          zero = (nb == 0.0);
+          *relres = zero ? 0.0 : r0 / nb;
+          stop = true;
+          m = 0;
+          return KFBI_OK;
+        }
+        *relres = r0 / nb;
+        r1 = r0;
+      }
       const GmresStatus& hs = gw->hring[q % kRing];
       ++*iters;
       ++examined;
@@ -644,6 +677,10 @@ static int gmres_core(kfbi_ctx* c, int M, const GmresOp& op, int precision, cons
       if (q < 0) continue;
       if (q >= launched) break;
       if (q >= examined) KFBI_TRY(examine(q));
+    }
+    if (zero) {
+      if (zero_rhs) *zero_rhs = true;
+      return KFBI_OK;
     }
     hipLaunchKernelGGL(k_update_x, dim3(mb), dim3(256), 0, s, M, m, gw->ldv, gw->V, gw->H, gw->g, x);
     KFBI_HIP(hipGetLastError());
@@ -720,24 +757,32 @@ static int gmres_run(kfbi_ctx* c, int M, const GmresOp& op, const double* b, dou
   KFBI_HIP(hipGetLastError());
   double rn0 = 0.0;
   int a0 = 0;
-  KFBI_TRY(true_residual(c, M, op, false, b, x, &gw, &rn0, &a0));
+  // FP64 and mixed: the first Arnoldi step is queued behind the initial residual without a
+  // host synchronisation; the refinement loop needs the residual at once
+  const bool lazy = (o->precision == KFBI_FP64 || o->precision == KFBI_MIXED);
+  KFBI_TRY(true_residual(c, M, op, false, b, x, &gw, &rn0, &a0, !lazy));
   loc.applies64 = a0;
-  const double nb = gw.hring[kSlotNb].resid;
+  double nb = lazy ? NAN : gw.hring[kSlotNb].resid;
   int status = KFBI_OK;
-  if (nb == 0.0) {
-    KFBI_HIP(hipMemsetAsync(x, 0, sizeof(double) * M, c->stream));
-    KFBI_HIP(hipStreamSynchronize(c->stream));
-    loc.converged = 1;
-  } else if (o->precision == KFBI_FP64 || o->precision == KFBI_MIXED) {
+  if (lazy) {
     int applies = 0, applies32 = 0;
+    bool zero_rhs = false;
     const double thresh =
         o->precision == KFBI_MIXED ? (o->inner_tol > 0.0 ? o->inner_tol : 1e-5) : 0.0;
     status = gmres_core(c, M, op, KFBI_FP64, b, x, nb, o->tol, o->restart, o->maxit, &gw,
                         &loc.iters, &loc.outer_iters, &applies, &loc.relres, true, rn0, thresh,
-                        &applies32);
+                        &applies32, true, &nb, &zero_rhs);
     loc.applies64 += applies;
     loc.applies32 += applies32;
+    if (zero_rhs) {
+      KFBI_HIP(hipMemsetAsync(x, 0, sizeof(double) * M, c->stream));
+      nb = 0.0;
+    }
     loc.converged = (status == KFBI_OK);
+  } else if (nb == 0.0) {
+    KFBI_HIP(hipMemsetAsync(x, 0, sizeof(double) * M, c->stream));
+    KFBI_HIP(hipStreamSynchronize(c->stream));
+    loc.converged = 1;
   } else {
     // iterative refinement: r = b - A64 x ; A32 d = r ; x += d
     const int mb = (M + 255) / 256;
