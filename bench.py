@@ -76,7 +76,9 @@ def algorithmic_bytes(info, N, M, wbytes, batch=1):
       k_rowdst         per arm the correction and its column (8 + 4 B), per part its
                        descriptor (16 B) in; per part one row of n transformed values out
       k_colsolve       the P n w part rows in, the nb n w rows of G out, per-mode constants
-                       (3 + 128 doubles per mode) and the row-to-part offsets
+                       (3 + 128 doubles per mode) and the row-to-part offsets (an interface
+                       whose rows span at most half the grid runs k_colsolve_band instead,
+                       which reads 3 per mode; the star workloads here span more)
       k_nodes_extract  each of the R node rows of G once (R n w), per marker the 51
                        extraction values and 5 marker quantities (8 B), 6 stencil slots (4 B),
                        four traces out (8 B each)

@@ -14,7 +14,10 @@
 //                    delta_p = 4 sin^2(p pi / 2N) + h^2 c^2,  G_0 = G_N = 0,
 //                solved per wavefront by two first-order recurrences (root rho_p of
 //                rho + 1/rho = 2 + delta_p) and a rank-one boundary correction; four modes
-//                per block, output rows row_lo..row_hi of G.
+//                per block, output rows row_lo..row_hi of G.  When the arm rows carry the
+//                whole right-hand side (zero box), k_colsolve_band solves only the band of
+//                rows between the first and last arm or node row, with the exact
+//                condition of the empty rows beyond it at each end.
 //  K4 k_nodes_extract  per chunk of markers: inverse transform along x at the chunk's
 //                interpolation nodes, v_ij = (2/N) sum_p G[j][p] sin(p i pi / N), then the
 //                Sec. 4.3 corrected interpolation with precomputed weights -> v+-,
@@ -1006,6 +1009,199 @@ __global__ void k_colconst_neu(int N, double hc2, int E, double* __restrict__ co
   lanef[static_cast<size_t>(t) * 2 + 1] = exp(static_cast<double>(N - (j0 + E - 1)) * lr);
 }
 
+// ------------------------------------------------- K3 on the band of rows that carry data
+// When the only right-hand sides are the arm rows (zero box, or the zero-normal-derivative
+// box inside the boundary operator), rows below lo and above hi = lo + nr - 1 carry none,
+// and the solve is needed only on rows lo..hi (lo <= every arm row and node row <= hi).
+// Outside that band the solution is the homogeneous one that meets the box condition, so
+// the rows next to the band obey G_{lo-1} = kL G_lo and G_{hi+1} = kR G_hi with
+//     zero box:    kL = rho (1 - rho^(2 lo - 2)) / (1 - rho^(2 lo))
+//     mirror box:  kL = rho (1 + rho^(2 lo - 2)) / (1 + rho^(2 lo))
+// (kR likewise with N - hi in place of lo); the mirror box keeps G_{-1} = G_1 when lo = 0
+// and G_{N+1} = G_{N-1} when hi = N.  With the particular solution P of the two recurrences
+// on the band (local rows i = 0..nr-1, P_{-1} = 0, P_nr = rho P_{nr-1}) the band solution is
+// G_i = P_i + A rho^i + B rho^(nr-1-i), and the two conditions reduce to
+//     A - cL B = RL,  B - cR A = RR,  cL cR = rho^(2N),
+// zero box:   cL = -rho^(nr-1+2lo),  RL = rho (1 - rho^(2lo-2)) P_0 / d,
+//             cR = -rho^(nr-1+2hb),  RR = -rho^(2hb) P_{nr-1}          (hb = N - hi)
+// mirror box: cL = rho^(nr-1+2lo),   RL = rho (1 + rho^(2lo-2)) P_0 / d  (P_1 / d if lo = 0),
+//             cR = rho^(nr-1+2hb),   RR = rho^(2hb) P_{nr-1}  ((P_{nr-2} - rho P_{nr-1}) / d
+//                                                             if hb = 0),
+// d = 1/rho - rho.  The result equals the full solve up to rounding; E rows per lane cover
+// the band instead of the whole column.
+template <class T, int E, bool NEU>
+__global__ void __launch_bounds__(256)
+    k_colsolve_band(int N, double h, int P, const T* __restrict__ Tg,
+                    const int* __restrict__ rowpart, const double* __restrict__ colc, int lo,
+                    int nr, int jlo, int jhi, T* __restrict__ Gg, int nblk_x, size_t tstride,
+                    size_t gstride, int ldr) {
+  extern __shared__ double dynp[];
+  T* tp = reinterpret_cast<T*>(dynp);
+  T (*col)[64 * (E + 1)] = reinterpret_cast<T (*)[64 * (E + 1)]>(dynp);
+  const int nmodes = NEU ? N + 1 : N - 1;  // mirror box: cosine modes 0..N; zero box: 1..N-1
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int bid = blockIdx.x;
+  const int per_xcd = (nblk_x + 7) / 8;
+  const int grp = (bid % 8) * per_xcd + bid / 8;
+  if (grp * kColsPerBlock >= nmodes) return;  // whole block beyond the last mode
+  Tg += static_cast<size_t>(blockIdx.y) * tstride;
+  Gg += static_cast<size_t>(blockIdx.y) * gstride;
+  const int q = grp * kColsPerBlock + w;  // this wavefront's mode slot
+  const bool live = q < nmodes;
+  double rho = 0.0, eps = 0.0, id = 0.0;
+  if (live) {
+    rho = colc[(NEU ? 4 : 3) * q];
+    eps = colc[(NEU ? 4 : 3) * q + 1];
+    id = colc[(NEU ? 4 : 3) * q + 2];  // 1 / (1 - rho^(2N)), divided by d for the mirror box
+  }
+  // the band conditions' constants, formed while the part rows load: RL = gL P_0 (P_1 / d
+  // for the mirror box at lo = 0), RR = gR P_{nr-1} (mirror box at hi = N:
+  // (P_{nr-2} - rho P_{nr-1}) / d); rho^(lane E) and rho^(nr - 1 - (lane E + E - 1)) for the
+  // homogeneous terms of this lane's rows (zero for lanes wholly past the band)
+  const int hb = N - (lo + nr - 1);
+  const double lr = log1p(-eps);
+  const double invd = rho / (eps * (2.0 - eps));  // 1 / (1/rho - rho)
+  const double cL = exp(static_cast<double>(nr - 1 + 2 * lo) * lr);
+  const double cR = exp(static_cast<double>(nr - 1 + 2 * hb) * lr);
+  const double gL = NEU ? ((lo == 0) ? invd
+                                     : rho * (1.0 + exp(static_cast<double>(2 * lo - 2) * lr)) * invd)
+                        : rho * (-expm1(static_cast<double>(2 * lo - 2) * lr)) * invd;
+  const double gR = (NEU ? 1.0 : -1.0) * exp(static_cast<double>(2 * hb) * lr);
+  if (NEU) id *= eps * (2.0 - eps) / rho;
+  const int k1 = nr - lane * E - E;
+  const double f0 = (lane * E < nr) ? exp(static_cast<double>(lane * E) * lr) : 0.0;
+  const double f1 = (k1 > -E) ? exp(static_cast<double>(k1) * lr) : 0.0;
+  constexpr int R = (64 * E + 255) / 256;  // band rows per thread in the row sums
+  int rq0[R], rq1[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = tid + 256 * u;
+    const int r = lo + i;
+    const bool in = (P > 0) && i < nr && r >= 1 && r <= N - 1;  // arms: interior rows only
+    rq0[u] = in ? rowpart[r] : 0;
+    rq1[u] = in ? rowpart[r + 1] : 0;
+  }
+  if (P > 0) {
+    const T* src = Tg + static_cast<size_t>(grp) * P * 4;
+    constexpr int U = 16;
+    for (int e0 = tid; e0 < 4 * P; e0 += 256 * U) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 256 * u;
+        v[u] = (e < 4 * P) ? src[e] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < 4 * P) tp[e] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  {
+    T a4[R][kColsPerBlock];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+#pragma unroll
+      for (int c = 0; c < kColsPerBlock; ++c) a4[u][c] = T(0);
+      for (int qq = rq0[u]; qq < rq1[u]; ++qq)
+#pragma unroll
+        for (int c = 0; c < kColsPerBlock; ++c) a4[u][c] += tp[4 * qq + c];
+    }
+    __syncthreads();  // the part rows are read: their bytes become the columns
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = tid + 256 * u;
+      if (i >= 64 * E) continue;
+#pragma unroll
+      for (int c = 0; c < kColsPerBlock; ++c) col[c][slot0<E>(i)] = a4[u][c];
+    }
+  }
+  __syncthreads();
+  if (live) {
+    const T rhoT = static_cast<T>(rho), epsT = static_cast<T>(eps);
+    const T h2 = static_cast<T>(h * h);
+    double pw[E + 1];
+    pw[0] = 1.0;
+#pragma unroll
+    for (int e = 1; e <= E; ++e) pw[e] = pw[e - 1] * rho;
+    T y[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = h2 * col[w][lane * (E + 1) + e];
+    // backward recurrence y_i = b_i + rho y_{i+1} (rows past the band are zero)
+#pragma unroll
+    for (int e = E - 2; e >= 0; --e) y[e] = (y[e] - epsT * y[e + 1]) + y[e + 1];
+    {
+      T v = y[0];
+      double fe = pw[E];
+#pragma unroll
+      for (int s = 1; s < 64; s <<= 1) {
+        const T o = __shfl_down(v, s, 64);
+        if (lane + s < 64) v += static_cast<T>(fe) * o;
+        fe *= fe;
+      }
+      T carry = __shfl_down(v, 1, 64);
+      if (lane == 63) carry = T(0);
+#pragma unroll
+      for (int e = 0; e < E; ++e) y[e] += static_cast<T>(pw[E - e]) * carry;
+    }
+    // forward recurrence z_i = y_i + rho z_{i-1}
+#pragma unroll
+    for (int e = 1; e < E; ++e) y[e] = (y[e] - epsT * y[e - 1]) + y[e - 1];
+    {
+      T v = y[E - 1];
+      double fe = pw[E];
+#pragma unroll
+      for (int s = 1; s < 64; s <<= 1) {
+        const T o = __shfl_up(v, s, 64);
+        if (lane >= s) v += static_cast<T>(fe) * o;
+        fe *= fe;
+      }
+      T carry = __shfl_up(v, 1, 64);
+      if (lane == 0) carry = T(0);
+#pragma unroll
+      for (int e = 0; e < E; ++e) y[e] += static_cast<T>(pw[e + 1]) * carry;
+    }
+    // P_i = -rho z_i; P_0, P_1, P_{nr-2}, P_{nr-1} for the band conditions
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = -rhoT * y[e];
+    const int ib = nr - 2, ic = nr - 1;
+    T s0 = T(0), s1 = T(0), sb = T(0), sc = T(0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (e == 0) s0 = y[e];
+      if (e == 1 % E) s1 = y[e];
+      if (e == ib % E) sb = y[e];
+      if (e == ic % E) sc = y[e];
+    }
+    const double P0 = static_cast<double>(__shfl(s0, 0, 64));
+    const double P1 = static_cast<double>(__shfl(s1, 1 / E, 64));
+    const double Pb = static_cast<double>(__shfl(sb, ib / E, 64));
+    const double Pc = static_cast<double>(__shfl(sc, ic / E, 64));
+    const double RL = gL * ((NEU && lo == 0) ? P1 : P0);
+    const double RR = (NEU && hb == 0) ? (Pb - rho * Pc) * invd : gR * Pc;
+    const double A = (NEU ? RL + cL * RR : RL - cL * RR) * id;
+    const double B = (NEU ? RR + cR * RL : RR - cR * RL) * id;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      y[e] += static_cast<T>(A * (f0 * pw[e]) + B * (f1 * pw[E - 1 - e]));
+#pragma unroll
+    for (int e = 0; e < E; ++e) col[w][lane * (E + 1) + e] = y[e];
+  }
+  __syncthreads();
+  // rows jlo..jhi (band layout: this group's four slots of row r start at base + r rs)
+  const int nb = jhi - jlo + 1;
+  const size_t base = ldr > 0 ? 4 * static_cast<size_t>(grp) : 4 * static_cast<size_t>(grp) * nb;
+  const size_t rs = ldr > 0 ? static_cast<size_t>(ldr) : 4;
+  const int q0 = grp * kColsPerBlock;
+  for (int e = tid; e < 4 * nb; e += 256) {
+    const int r = e >> 2, c = e & 3;
+    Gg[base + r * rs + c] = (q0 + c < nmodes) ? col[c][slot0<E>(jlo + r - lo)] : T(0);
+  }
+}
+
 // ---------------------------------------------------------------------------------- K4
 // One block per chunk of MC markers.  Its distinct stencil nodes (sorted by row) are
 // split over the wavefronts; lane l of a wavefront keeps G[j][p] for
@@ -1308,6 +1504,48 @@ static const void* kptr(K kernel) {
   return reinterpret_cast<const void*>(kernel);
 }
 
+// Rows per lane of the band column solve: E >= ceil(nr / 64) from a short list.
+template <class F>
+static void band_dispatch(int nr, F&& f) {
+  const int e = (nr + 63) / 64;
+  if (e <= 2) f(std::integral_constant<int, 2>{});
+  else if (e <= 4) f(std::integral_constant<int, 4>{});
+  else if (e <= 8) f(std::integral_constant<int, 8>{});
+  else if (e <= 12) f(std::integral_constant<int, 12>{});
+  else if (e <= 16) f(std::integral_constant<int, 16>{});
+  else if (e <= 24) f(std::integral_constant<int, 24>{});
+  else f(std::integral_constant<int, 33>{});
+}
+
+// The band of rows lo .. lo + nr - 1 that holds every arm row and every node row (at least
+// two rows, inside the rows of the box condition); false when the interface has neither, or
+// when the band spans more than half of the rows: the band solve forms its row constants
+// from exp and log per lane, which costs about what the shorter recurrences save once the
+// band is that wide (measured: a band of 60% of the rows ran 1-2% slower per apply).
+static bool solve_band(const kfbi_ctx* c, bool neu, int* lo, int* nr) {
+  const int N = c->N;
+  const GeoStatus& g = c->st;
+  if (g.row_lo > g.row_hi) return false;
+  int a = g.row_lo, b = g.row_hi;
+  if (g.arm_lo <= g.arm_hi) {
+    a = std::min(a, g.arm_lo);
+    b = std::max(b, g.arm_hi);
+  }
+  const int rmin = neu ? 0 : 1, rmax = neu ? N : N - 1;
+  if (g.row_lo < rmin || g.row_hi > rmax) return false;  // output rows must lie in the band
+  a = std::max(a, rmin);
+  b = std::min(b, rmax);
+  if (b - a + 1 < 2) {
+    if (b < rmax) b = a + 1;
+    else a = b - 1;
+  }
+  if (a < rmin || b > rmax || a > b) return false;
+  if (2 * (b - a + 1) > rmax - rmin + 1) return false;
+  *lo = a;
+  *nr = b - a + 1;
+  return true;
+}
+
 template <class T, int E>
 static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring, size_t rstride,
                                int jlo, int jhi, T* Tg, T* G, bool full, double* grid,
@@ -1329,11 +1567,22 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   if (ev) hipEventRecord(ev[2], s);
   const int ngrp = nblk(n, kColsPerBlock);
   const int nb = ((ngrp + 7) / 8) * 8;
-  const size_t lds_dyn = sizeof(T) * colsolve_lds_elems(P, E);
-  if (stages & 4)
+  int blo = 0, bnr = 0;
+  if ((stages & 4) && !full && !ring && solve_band(c, false, &blo, &bnr)) {
+    // zero box: the right-hand side lives on the arm rows only
+    band_dispatch(bnr, [&](auto EC) {
+      constexpr int EB = decltype(EC)::value;
+      hipLaunchKernelGGL((k_colsolve_band<T, EB, false>), dim3(nb, B), dim3(256),
+                         sizeof(T) * colsolve_lds_elems(P, EB), s, N, c->h, P, Tg,
+                         c->rowpart.as<int>(), c->colc.as<double>(), blo, bnr, jlo, jhi, G, nb,
+                         tstride, gstride, ldr);
+    });
+  } else if (stages & 4) {
+    const size_t lds_dyn = sizeof(T) * colsolve_lds_elems(P, E);
     hipLaunchKernelGGL((k_colsolve<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P, Tg,
                        c->rowpart.as<int>(), sinT, ring, c->colc.as<double>(),
                        c->lanef.as<double>(), jlo, jhi, G, nb, tstride, rstride, gstride, ldr);
+  }
   if (ev) hipEventRecord(ev[3], s);
   const int nbr = jhi - jlo + 1;
   if (full) {  // single density only
@@ -1390,12 +1639,23 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
                        tstride);
   if (ev) hipEventRecord(ev[2], s);
   const int nb = ((ngm + 7) / 8) * 8;
-  const size_t lds_dyn = sizeof(T) * colsolve_lds_elems(P, E);
-  if (stages & 4)
+  int blo = 0, bnr = 0;
+  if ((stages & 4) && !full && !rr.Fa && solve_band(c, true, &blo, &bnr)) {
+    // no dense right-hand side: the arm rows carry all of it
+    band_dispatch(bnr, [&](auto EC) {
+      constexpr int EB = decltype(EC)::value;
+      hipLaunchKernelGGL((k_colsolve_band<T, EB, true>), dim3(nb, B), dim3(256),
+                         sizeof(T) * colsolve_lds_elems(P, EB), s, N, c->h, P, Tg,
+                         c->rowpart.as<int>(), c->colc.as<double>(), blo, bnr, jlo, jhi, G, nb,
+                         tstride, gstride, ldr);
+    });
+  } else if (stages & 4) {
+    const size_t lds_dyn = sizeof(T) * colsolve_lds_elems(P, E);
     hipLaunchKernelGGL((k_colsolve_neu<T, E>), dim3(nb, B), dim3(256), lds_dyn, s, N, c->h, P,
                        Tg, c->rowpart.as<int>(), static_cast<const T*>(rr.Fa),
                        static_cast<const T*>(rr.Fb), rr.ca, rr.cb, c->colc.as<double>(),
                        c->lanef.as<double>(), jlo, jhi, G, nb, tstride, gstride, ldr);
+  }
   if (ev) hipEventRecord(ev[3], s);
   const int nbr = jhi - jlo + 1;
   if (full)  // single density, all rows
@@ -1754,7 +2014,14 @@ static int colsolve_attrs() {
                       kptr(k_colsolve<T, 16>),     kptr(k_colsolve<T, 32>),
                       kptr(k_colsolve_neu<T, 2>),  kptr(k_colsolve_neu<T, 3>),
                       kptr(k_colsolve_neu<T, 5>),  kptr(k_colsolve_neu<T, 9>),
-                      kptr(k_colsolve_neu<T, 17>), kptr(k_colsolve_neu<T, 33>)};
+                      kptr(k_colsolve_neu<T, 17>), kptr(k_colsolve_neu<T, 33>),
+                      kptr(k_colsolve_band<T, 2, false>),  kptr(k_colsolve_band<T, 4, false>),
+                      kptr(k_colsolve_band<T, 8, false>),  kptr(k_colsolve_band<T, 12, false>),
+                      kptr(k_colsolve_band<T, 16, false>), kptr(k_colsolve_band<T, 24, false>),
+                      kptr(k_colsolve_band<T, 33, false>), kptr(k_colsolve_band<T, 2, true>),
+                      kptr(k_colsolve_band<T, 4, true>),   kptr(k_colsolve_band<T, 8, true>),
+                      kptr(k_colsolve_band<T, 12, true>),  kptr(k_colsolve_band<T, 16, true>),
+                      kptr(k_colsolve_band<T, 24, true>),  kptr(k_colsolve_band<T, 33, true>)};
   for (const void* k : ks) KFBI_TRY(allow_full_dyn_lds(k));
   return KFBI_OK;
 }

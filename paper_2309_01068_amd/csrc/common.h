@@ -87,6 +87,7 @@ struct GeoStatus {
   int n_rows;
   int row_lo, row_hi;
   int n_parts;
+  int arm_lo, arm_hi;  // first and last grid rows holding arms (arm_lo > arm_hi: none)
 };
 
 }  // namespace kfbi

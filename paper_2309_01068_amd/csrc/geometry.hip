@@ -146,6 +146,8 @@ __global__ void k_count_cross(int M, const double* __restrict__ xy, double* __re
     GeoStatus init{};
     init.row_lo = 1 << 30;
     init.row_hi = -1;
+    init.arm_lo = 1 << 30;
+    init.arm_hi = -1;
     *st = init;
   }
   for (int ax = 0; ax < 2; ++ax) {
@@ -859,18 +861,19 @@ __global__ void __launch_bounds__(1024)
                 int* __restrict__ rows, int* __restrict__ rowptr,
                 const int* __restrict__ rowoff, int* __restrict__ rowpart, GeoStatus* st,
                 GeoStatus* __restrict__ hpost) {
-  // single block: exclusive scans of the node counts and of (count > 0), the band, and the
-  // row parts of the row transform (ceil(arms / kArmsPerPart) per interior row); thread 0
-  // then posts the whole status to mapped host memory at system scope
+  // single block: exclusive scans of the node counts and of (count > 0), the band of node
+  // rows, the first and last rows holding arms, and the row parts of the row transform
+  // (ceil(arms / kArmsPerPart) per interior row); thread 0 then posts the whole status to
+  // mapped host memory at system scope
   __shared__ int scratch[17];
-  __shared__ int band[2];
+  __shared__ int band[4];
   const int n1 = N + 1;
   const int T = blockDim.x;
   const int per = (n1 + T - 1) / T;
   const int b = threadIdx.x * per, e = min(n1, b + per);
   if (threadIdx.x == 0) {
-    band[0] = 1 << 30;
-    band[1] = -1;
+    band[0] = band[2] = 1 << 30;
+    band[1] = band[3] = -1;
   }
   int s = 0, f = 0, pc = 0;
   for (int j = b; j < e; ++j) {
@@ -882,9 +885,13 @@ __global__ void __launch_bounds__(1024)
   int off = block_excl_scan(s, scratch, &tot_nodes);
   int roff = block_excl_scan(f, scratch, &tot_rows);
   int poff = block_excl_scan(pc, scratch, &tot_parts);
-  int lo = 1 << 30, hi = -1;
+  int lo = 1 << 30, hi = -1, alo = 1 << 30, ahi = -1;
   for (int j = b; j < e; ++j) {
     nodeoff[j] = off;
+    if (j >= 1 && j <= N - 1 && rowoff[j + 1] > rowoff[j]) {
+      alo = min(alo, j);
+      ahi = max(ahi, j);
+    }
     if (rowcnt[j] > 0) {
       rows[roff] = j;
       rowptr[roff] = off;
@@ -900,6 +907,10 @@ __global__ void __launch_bounds__(1024)
     atomicMin(&band[0], lo);
     atomicMax(&band[1], hi);
   }
+  if (ahi >= 0) {
+    atomicMin(&band[2], alo);
+    atomicMax(&band[3], ahi);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     rowptr[tot_rows] = tot_nodes;
@@ -909,6 +920,8 @@ __global__ void __launch_bounds__(1024)
     v.n_parts = tot_parts;
     v.row_lo = band[0];
     v.row_hi = band[1];
+    v.arm_lo = band[2];
+    v.arm_hi = band[3];
     *st = v;
     *hpost = v;
     __threadfence_system();
