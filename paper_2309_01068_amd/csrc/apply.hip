@@ -40,6 +40,9 @@ namespace kfbi {
 constexpr int kColsPerBlock = 4;
 constexpr int kReg = 8;       // circulant outputs per thread in K1
 constexpr int kNodeBatch = 8; // nodes reduced together in K4
+// K4 for chunks of one marker (M < 512, at most six nodes) splits the mode slots of every
+// node among its eight wavefronts once each lane holds at least this many slots
+constexpr int kModeSplitMinE = 9;
 constexpr int kMaxChunk = 16;  // markers per K1/K4 chunk: M / 256 for M <= 4096
 constexpr int kRingNodes = 8;  // free-space box nodes per K1 block
 constexpr int kWinMax = 24;     // derivative window per K1 chunk: at most 16 + 5 markers
@@ -1210,7 +1213,36 @@ __global__ void __launch_bounds__(256)
 // MC threads apply the Sec. 4.3 corrected interpolation.
 // COSB (zero-normal-derivative box): v_ij = (2/N) sum_{p=0}^{N} w_p G[j][p] cos(p i pi / N)
 // with w_0 = w_N = 1/2; lane l keeps the modes p = l + 64 e.
-template <class T, int E, bool COSB, int NT>
+// Recursive-halving reduction of eight per-lane values over the 64 lanes of a wavefront:
+// lane l ends with the sum of value (l >> 3) & 7.
+template <class T>
+__device__ __forceinline__ T batch_reduce8(const T (&part)[kNodeBatch], int lane) {
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  T h4[4], h2[2], h1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const T keep = b5 ? part[q + 4] : part[q];
+    const T send = b5 ? part[q] : part[q + 4];
+    h4[q] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const T keep = b4 ? h4[q + 2] : h4[q];
+    const T send = b4 ? h4[q] : h4[q + 2];
+    h2[q] = keep + __shfl_xor(send, 16, 64);
+  }
+  {
+    const T keep = b3 ? h2[1] : h2[0];
+    const T send = b3 ? h2[0] : h2[1];
+    h1 = keep + __shfl_xor(send, 8, 64);
+  }
+  h1 += __shfl_xor(h1, 4, 64);
+  h1 += __shfl_xor(h1, 2, 64);
+  h1 += __shfl_xor(h1, 1, 64);
+  return h1;
+}
+
+template <class T, int E, bool COSB, int NT, bool MS = false>
 __global__ void __launch_bounds__(NT)
     k_nodes_extract(int N, int M, int MC, int nch, const int* __restrict__ cnode,
                     const int* __restrict__ ccount, const int* __restrict__ chpos,
@@ -1288,62 +1320,63 @@ __global__ void __launch_bounds__(NT)
     for (int i = tid; i < nq; i += NT) s += qpart[i];
     qs = block_sum<double>(s, red);
   }
-  // this wavefront's nodes (contiguous in the sorted list, so rows repeat)
-  constexpr int NWV = NT / 64;
-  const int per = (nn + NWV - 1) / NWV;
-  const int qb = w * per, qe = min(nn, qb + per);
-  int curj = -1;
   // distance between groups of four mode slots: 4 in a row-major band, 4 nbr in the
   // column-group layout
   const size_t g_grp = ldr > 0 ? 4 : 4 * static_cast<size_t>(nbr);
   const size_t g_lane = static_cast<size_t>(lane >> 2) * g_grp + (lane & 3);
   const size_t g_step = 16 * g_grp;
-  T gv[E];
+  constexpr int NWV = NT / 64;
+  if constexpr (MS) {
+    // chunks of one marker (at most six nodes): wavefront w takes the mode slots
+    // e = w EW .. w EW + EW - 1 of every node, so the block reads each distinct node row
+    // once (each wavefront its slice) instead of once per node; a node's NWV partial sums
+    // are then added in wavefront order
+    constexpr int EW = (E + NWV - 1) / NWV;
+    __shared__ T wsum[NWV][kNodeBatch];
+    const int e0 = w * EW;
+    int curj = -1;
+    T gv[EW];
 #pragma unroll
-  for (int e = 0; e < E; ++e) gv[e] = T(0);
-  for (int q0 = qb; q0 < qe; q0 += kNodeBatch) {
+    for (int e = 0; e < EW; ++e) gv[e] = T(0);
     T part[kNodeBatch];
 #pragma unroll
     for (int u = 0; u < kNodeBatch; ++u) {
-      const int q = q0 + u;
-      const int kq = __shfl(q < 64 ? key_lo : key_hi, q & 63, 64);
-      const int key = (q < qe) ? kq : -1;
+      const int kq = __shfl(key_lo, u, 64);
+      const int key = (u < nn) ? kq : -1;
       const int i = key & 0xffff, j = key >> 16;
       if (key >= 0 && j != curj) {  // wave-uniform branch
-        // mode slot lane + 64 e of row j: one base per lane, a fixed step per e
-        // (band layout with q >> 2 = (lane >> 2) + 16 e and q & 3 = lane & 3)
         const T* Gr = G + (ldr > 0 ? static_cast<size_t>(j - jlo) * ldr
                                    : 4 * static_cast<size_t>(j - jlo)) + g_lane;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
+        for (int e = 0; e < EW; ++e) {
+          const int ee = e0 + e;
           if constexpr (COSB) {
-            const int pp = lane + 64 * e;
+            const int pp = lane + 64 * ee;
             const T wgt = (pp == 0 || pp == N) ? T(0.5) : T(1);
-            gv[e] = (pp <= N) ? wgt * Gr[e * g_step] : T(0);
+            gv[e] = (ee < E && pp <= N) ? wgt * Gr[static_cast<size_t>(ee) * g_step] : T(0);
           } else {
-            const int pp = 1 + lane + 64 * e;
-            gv[e] = (pp <= n) ? Gr[e * g_step] : T(0);
+            const int pp = 1 + lane + 64 * ee;
+            gv[e] = (ee < E && pp <= n) ? Gr[static_cast<size_t>(ee) * g_step] : T(0);
           }
         }
         curj = j;
       }
       T sacc = T(0);
-      if (key >= 0) {
+      if (key >= 0 && e0 < E) {
         T a, c, sb, cb;
-        st2.get((((COSB ? 0 : 1) + lane) * i) & mask, a, c);
+        st2.get((((COSB ? 0 : 1) + lane + 64 * e0) * i) & mask, a, c);
         st2.get((64 * i) & mask, sb, cb);
-        // three-term recurrence in steps of 64 i pi / N (rounding grows at most E-fold)
         const T c2 = cb + cb;
         T am;
         if constexpr (COSB) {
-          am = c * cb + a * sb;  // cos((p - 64) x)
+          am = c * cb + a * sb;
           a = c;
         } else {
           am = a * cb - c * sb;
         }
         sacc += gv[0] * a;
 #pragma unroll
-        for (int e = 1; e < E; ++e) {
+        for (int e = 1; e < EW; ++e) {
           const T an = c2 * a - am;
           am = a;
           a = an;
@@ -1352,32 +1385,78 @@ __global__ void __launch_bounds__(NT)
       }
       part[u] = sacc;
     }
-    // recursive-halving reduction of 8 values over 64 lanes; lane l ends with node
-    // (l >> 3) & 7 of the batch
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
-    T h4[4], h2[2], h1;
+    const T h1 = batch_reduce8<T>(part, lane);
+    if ((lane & 7) == 0) wsum[w][(lane >> 3) & 7] = h1;
+    __syncthreads();
+    if (tid < nn) {
+      double sum = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T keep = b5 ? part[q + 4] : part[q];
-      const T send = b5 ? part[q] : part[q + 4];
-      h4[q] = keep + __shfl_xor(send, 32, 64);
+      for (int ww = 0; ww < NWV; ++ww) sum += static_cast<double>(wsum[ww][tid]);
+      nval[tid] = sum * (2.0 / N);
     }
+  } else {
+    // this wavefront's nodes (contiguous in the sorted list, so rows repeat)
+    const int per = (nn + NWV - 1) / NWV;
+    const int qb = w * per, qe = min(nn, qb + per);
+    int curj = -1;
+    T gv[E];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const T keep = b4 ? h4[q + 2] : h4[q];
-      const T send = b4 ? h4[q] : h4[q + 2];
-      h2[q] = keep + __shfl_xor(send, 16, 64);
+    for (int e = 0; e < E; ++e) gv[e] = T(0);
+    for (int q0 = qb; q0 < qe; q0 += kNodeBatch) {
+      T part[kNodeBatch];
+#pragma unroll
+      for (int u = 0; u < kNodeBatch; ++u) {
+        const int q = q0 + u;
+        const int kq = __shfl(q < 64 ? key_lo : key_hi, q & 63, 64);
+        const int key = (q < qe) ? kq : -1;
+        const int i = key & 0xffff, j = key >> 16;
+        if (key >= 0 && j != curj) {  // wave-uniform branch
+          // mode slot lane + 64 e of row j: one base per lane, a fixed step per e
+          // (band layout with q >> 2 = (lane >> 2) + 16 e and q & 3 = lane & 3)
+          const T* Gr = G + (ldr > 0 ? static_cast<size_t>(j - jlo) * ldr
+                                     : 4 * static_cast<size_t>(j - jlo)) + g_lane;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if constexpr (COSB) {
+              const int pp = lane + 64 * e;
+              const T wgt = (pp == 0 || pp == N) ? T(0.5) : T(1);
+              gv[e] = (pp <= N) ? wgt * Gr[e * g_step] : T(0);
+            } else {
+              const int pp = 1 + lane + 64 * e;
+              gv[e] = (pp <= n) ? Gr[e * g_step] : T(0);
+            }
+          }
+          curj = j;
+        }
+        T sacc = T(0);
+        if (key >= 0) {
+          T a, c, sb, cb;
+          st2.get((((COSB ? 0 : 1) + lane) * i) & mask, a, c);
+          st2.get((64 * i) & mask, sb, cb);
+          // three-term recurrence in steps of 64 i pi / N (rounding grows at most E-fold)
+          const T c2 = cb + cb;
+          T am;
+          if constexpr (COSB) {
+            am = c * cb + a * sb;  // cos((p - 64) x)
+            a = c;
+          } else {
+            am = a * cb - c * sb;
+          }
+          sacc += gv[0] * a;
+#pragma unroll
+          for (int e = 1; e < E; ++e) {
+            const T an = c2 * a - am;
+            am = a;
+            a = an;
+            sacc += gv[e] * a;
+          }
+        }
+        part[u] = sacc;
+      }
+      const T h1 = batch_reduce8<T>(part, lane);
+      const int u = (lane >> 3) & 7;
+      if ((lane & 7) == 0 && q0 + u < qe) nval[q0 + u] = static_cast<double>(h1) * (2.0 / N);
     }
-    {
-      const T keep = b3 ? h2[1] : h2[0];
-      const T send = b3 ? h2[0] : h2[1];
-      h1 = keep + __shfl_xor(send, 8, 64);
-    }
-    h1 += __shfl_xor(h1, 4, 64);
-    h1 += __shfl_xor(h1, 2, 64);
-    h1 += __shfl_xor(h1, 1, 64);
-    const int u = (lane >> 3) & 7;
-    if ((lane & 7) == 0 && q0 + u < qe) nval[q0 + u] = static_cast<double>(h1) * (2.0 / N);
   }
   __syncthreads();
   if (!xmk) return;
@@ -1505,6 +1584,10 @@ static const void* kptr(K kernel) {
 }
 
 // Rows per lane of the band column solve: E >= ceil(nr / 64) from a short list.
+static int band_rows_per_lane(int nr) {
+  const int e = (nr + 63) / 64;
+  return e <= 2 ? 2 : e <= 4 ? 4 : e <= 8 ? 8 : e <= 12 ? 12 : e <= 16 ? 16 : e <= 24 ? 24 : 33;
+}
 template <class F>
 static void band_dispatch(int nr, F&& f) {
   const int e = (nr + 63) / 64;
@@ -1541,6 +1624,11 @@ static bool solve_band(const kfbi_ctx* c, bool neu, int* lo, int* nr) {
   }
   if (a < rmin || b > rmax || a > b) return false;
   if (2 * (b - a + 1) > rmax - rmin + 1) return false;
+  // nothing to gain unless the band needs fewer rows per lane than the whole column
+  const int rows = rmax - rmin + 1, ef = (rows + 63) / 64;
+  const int efull = neu ? (ef <= 2 ? 2 : ef <= 3 ? 3 : ef <= 5 ? 5 : ef <= 9 ? 9 : ef <= 17 ? 17 : 33)
+                        : (ef <= 1 ? 1 : ef <= 2 ? 2 : ef <= 4 ? 4 : ef <= 8 ? 8 : ef <= 16 ? 16 : 32);
+  if (band_rows_per_lane(b - a + 1) >= efull) return false;
   *lo = a;
   *nr = b - a + 1;
   return true;
@@ -1597,6 +1685,8 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
   if (stages & 8) {
     constexpr int NT1 = node_threads<T, E>();
     auto kn = (B == 1) ? k_nodes_extract<T, E, false, NT1> : k_nodes_extract<T, E, false, 256>;
+    if constexpr (E >= kModeSplitMinE)
+      if (B == 1 && MC == 1) kn = k_nodes_extract<T, E, false, 512, true>;
     hipLaunchKernelGGL(kn, dim3(8 * nblk(nch, 8), B), dim3(B == 1 ? NT1 : 256),
                        sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(),
                        c->ccount.as<int>(), c->chpos.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G,
@@ -1668,6 +1758,8 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
   if (stages & 8) {
     constexpr int NT1 = node_threads<T, E>();
     auto kn = (B == 1) ? k_nodes_extract<T, E, true, NT1> : k_nodes_extract<T, E, true, 256>;
+    if constexpr (E >= kModeSplitMinE)
+      if (B == 1 && MC == 1) kn = k_nodes_extract<T, E, true, 512, true>;
     hipLaunchKernelGGL(kn, dim3(8 * nblk(nch, 8), B), dim3(B == 1 ? NT1 : 256),
                        sizeof(double) * 6 * MC, s, N, M, MC, nch, c->cnode.as<int>(),
                        c->ccount.as<int>(), c->chpos.as<int>(), c->mkloc.as<int>(), sinT, jlo, nbr, G, mqv,

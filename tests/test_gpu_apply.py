@@ -52,6 +52,10 @@ CASES = [
     ("ellipse128", W.ellipse(256), W.box(-1, 1, 128), 0.0, K.BOX_ZERO),
     ("hs3_free", W.hs3(256), W.box(-2, 2, 256), 0.0, K.BOX_FREESPACE),
     ("pert_free", W.perturbed(384, 3), W.box(-2, 2, 128), 0.0, K.BOX_FREESPACE),
+    # fewer than 512 markers on a fine grid: one-marker chunks with the mode slots of each
+    # node split among the wavefronts (the second also solves only the band of rows)
+    ("star1024_m256", W.star(256), W.box(-1, 1, 1024), 1000.0, K.BOX_ZERO),
+    ("ellipse1024_m200", W.ellipse(200), W.box(-1, 1, 1024), 1000.0, K.BOX_ZERO),
 ]
 
 

@@ -40,6 +40,8 @@ CASES = [
     ("ellipse256_128", W.ellipse(256), W.box(-1, 1, 128), 40.0),
     ("hs3_1024_512", W.hs3(1024), W.box(-2, 2, 512), 2000.0),
     ("circle_64", W.circle(96, 0.45), W.box(-1, 1, 64), 9.0),
+    # one-marker chunks on a 512^2 grid: mode-split node sums, band column solve
+    ("circle_m128_512", W.circle(128, 0.3), W.box(-1, 1, 512), 500.0),
 ]
 
 
