@@ -88,6 +88,7 @@ struct GeoStatus {
   int row_lo, row_hi;
   int n_parts;
   int arm_lo, arm_hi;  // first and last grid rows holding arms (arm_lo > arm_hi: none)
+  int cr_lo, cr_hi;    // rows between which the sampled curve lies (row lines it may cut)
 };
 
 }  // namespace kfbi
@@ -107,6 +108,9 @@ struct kfbi_ctx {
   int M = 0;
   int have_interface = 0;
   kfbi::GeoStatus st{};
+  // rows whose node maps and labels the last geometry set-up may have written (all rows
+  // until the first one: the maps start uninitialised)
+  int gb_lo = 0, gb_hi = 1 << 30;
   int d_M = 0;  // M for which the differentiation vectors are built
 
   // geometry buffers

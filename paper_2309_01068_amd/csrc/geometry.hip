@@ -13,6 +13,7 @@
 // of kept row-j crossings lie strictly left of x_i; closest node = floor(t + 1/2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -46,9 +47,14 @@ __global__ void k_diffvec(int M, double* __restrict__ d1, double* __restrict__ d
 __global__ void __launch_bounds__(256)
     k_marker_geo(int M, const double* __restrict__ X, const double* __restrict__ d1,
                  const double* __restrict__ d2, double* __restrict__ geo, double lox,
-                 double hix, double loy, double hiy, GeoStatus* st) {
+                 double hix, double loy, double hiy, const int* __restrict__ rng,
+                 GeoStatus* st) {
   __shared__ double red[4][4];
   const int k = blockIdx.x;
+  if (threadIdx.x == 0) {  // the row range of marker interval k (from k_count_cross)
+    atomicMin(&st->cr_lo, rng[k]);
+    atomicMax(&st->cr_hi, rng[M + k]);
+  }
   const double* x = X;
   const double* y = X + M;
   double xa = 0, ya = 0, xaa = 0, yaa = 0;
@@ -134,9 +140,10 @@ __device__ inline void stencil_values(const double* v, int k, int M, double* cv)
 
 // Also copies the markers xy into the context (X) and resets the status words (thread 0),
 // so that no copy precedes it.
+// rng[k], rng[M + k]: the first and last row lines that the samples of interval k may cut.
 __global__ void k_count_cross(int M, const double* __restrict__ xy, double* __restrict__ Xc,
                               double x0, double y0, double h, int N, int* __restrict__ cnt,
-                              GeoStatus* __restrict__ st) {
+                              int* __restrict__ rng, GeoStatus* __restrict__ st) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
   const double* X = xy;
@@ -148,6 +155,8 @@ __global__ void k_count_cross(int M, const double* __restrict__ xy, double* __re
     init.row_hi = -1;
     init.arm_lo = 1 << 30;
     init.arm_hi = -1;
+    init.cr_lo = 1 << 30;
+    init.cr_hi = -1;
     *st = init;
   }
   for (int ax = 0; ax < 2; ++ax) {
@@ -159,6 +168,10 @@ __global__ void k_count_cross(int M, const double* __restrict__ xy, double* __re
     sub_values(cv, vals);
     int jb, je, c = 0;
     line_range(vals, lo, h, N, &jb, &je);
+    if (ax == 0) {
+      rng[k] = jb;
+      rng[M + k] = je;
+    }
     for (int j = jb; j <= je; ++j) {
       const double g = lo + j * h;
 #pragma unroll
@@ -388,10 +401,18 @@ __global__ void k_mark_v(int nh, int nv, const Crossing* __restrict__ cr, int N,
 // Labels per row: node (i, j) is in Omega+ iff #{row-j crossings with seg < i} is odd
 // (seg < i  <=>  xi < x_i).  One block per row.
 // hid, vid, vraw = -1 and need = 0 on the nn nodes; rowoff[0..nr) = 0.
-__global__ void k_geo_clear(int nn, int nr, int* __restrict__ hid, int* __restrict__ vid,
-                            int* __restrict__ vraw, int* __restrict__ need,
-                            int* __restrict__ rowoff) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// Node maps cleared over node indices [4 t0, 4 t1) (whole rows, rounded out to groups of
+// four: the extra nodes lie in rows that are clear already), rowoff[0..nr) and
+// rowcnt[0..nc) zeroed.
+__global__ void k_geo_clear(int nn, int t0, int t1, int nr, int nc, int* __restrict__ hid,
+                            int* __restrict__ vid, int* __restrict__ vraw,
+                            int* __restrict__ need, int* __restrict__ rowoff,
+                            int* __restrict__ rowcnt) {
+  const int tt = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tt < nr) rowoff[tt] = 0;
+  if (tt < nc) rowcnt[tt] = 0;
+  const int t = t0 + tt;
+  if (t >= t1) return;
   const int i = 4 * t;
   if (i + 3 < nn) {
     const int4 m1 = make_int4(-1, -1, -1, -1), z = make_int4(0, 0, 0, 0);
@@ -405,7 +426,6 @@ __global__ void k_geo_clear(int nn, int nr, int* __restrict__ hid, int* __restri
       need[k] = 0;
     }
   }
-  if (t < nr) rowoff[t] = 0;
 }
 
 // Labels of row j: node i is inside iff the row's crossings on the segments left of it are
@@ -415,10 +435,10 @@ __global__ void k_geo_clear(int nn, int nr, int* __restrict__ hid, int* __restri
 // left through LDS.  One block of 256 threads per row, N + 1 <= 64 * 4 * kLabelChunks.
 constexpr int kLabelChunks = 9;
 static_assert(64 * 4 * kLabelChunks >= 2049, "rows of up to 2049 nodes (N <= 2048)");
-__global__ void __launch_bounds__(256) k_label(int N, const int* __restrict__ hid,
+__global__ void __launch_bounds__(256) k_label(int N, int j0, const int* __restrict__ hid,
                                                int8_t* __restrict__ lab) {
   __shared__ int wpar[4];
-  const int j = blockIdx.x;
+  const int j = j0 + blockIdx.x;
   const int n1 = N + 1;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nch = (n1 + 63) >> 6;
@@ -481,10 +501,11 @@ __device__ inline int node_arms(int i, int j, int N, const int8_t* lab, const in
   return na;
 }
 
-__global__ void k_arm_rowcount(int N, const int8_t* __restrict__ lab, const int* __restrict__ hid,
-                               const int* __restrict__ vid, int* __restrict__ rowcnt, GeoStatus* st) {
+__global__ void k_arm_rowcount(int N, int j0, const int8_t* __restrict__ lab,
+                               const int* __restrict__ hid, const int* __restrict__ vid,
+                               int* __restrict__ rowcnt, GeoStatus* st) {
   __shared__ double scratch[16];
-  const int j = blockIdx.x + 1;  // interior rows 1..N-1
+  const int j = j0 + blockIdx.x;  // interior rows j0.. (1 <= j0, last <= N - 1)
   int s = 0;
   for (int i = 1 + threadIdx.x; i <= N - 1; i += blockDim.x)
     s += node_arms(i, j, N, lab, hid, vid, nullptr, nullptr, nullptr, st);
@@ -497,13 +518,13 @@ __global__ void k_arm_rowcount(int N, const int8_t* __restrict__ lab, const int*
 //   T = [u] + d [u_s] + d^2/2 [u_ss],  RHS_P += -T/h^2 (P inside) or +T/h^2 (P outside),
 // T linear in (Phi, Phi_a, Phi_aa, Psi, Psi_a) at the crossing (App. A.1), each of which
 // is the 6-point Lagrange combination of marker values.
-__global__ void k_arm_fill(int N, double x0, double y0, double h, double c2, int M,
+__global__ void k_arm_fill(int N, int j0, double x0, double y0, double h, double c2, int M,
                            const int8_t* __restrict__ lab, const int* __restrict__ hid,
                            const int* __restrict__ vid, const int* __restrict__ rowoff,
                            const Crossing* __restrict__ cr, const double* __restrict__ geo,
                            int* __restrict__ armpk, ArmCoef* __restrict__ armc, GeoStatus* st) {
   __shared__ int scratch[17];
-  const int j = blockIdx.x + 1;
+  const int j = j0 + blockIdx.x;
   // a row without arms has nothing to fill (k_arm_rowcount has checked it already); the
   // condition is the same for the whole block
   if (rowoff[j] == rowoff[j + 1]) return;
@@ -847,9 +868,10 @@ __global__ void __launch_bounds__(64) k_marker_ext(int M, const double* __restri
 
 // Node numbering: per row count of needed nodes, then scan over rows (single block):
 // node offsets, compact list of needed rows, band [row_lo, row_hi].
-__global__ void k_need_rowcount(int N, const int* __restrict__ need, int* __restrict__ rowcnt) {
+__global__ void k_need_rowcount(int N, int j0, const int* __restrict__ need,
+                                int* __restrict__ rowcnt) {
   __shared__ double scratch[16];
-  const int j = blockIdx.x;
+  const int j = j0 + blockIdx.x;
   int s = 0;
   for (int i = threadIdx.x; i <= N; i += blockDim.x) s += need[j * (N + 1) + i];
   const double t = block_sum<double>(static_cast<double>(s), scratch);
@@ -930,6 +952,10 @@ __global__ void __launch_bounds__(1024)
 
 static inline int nblk(long long n, int b) { return static_cast<int>((n + b - 1) / b); }
 
+// Rows beyond the curve's sampled rows that a set-up may touch: vertical crossings and arms
+// one row out, stencil nodes two rows out of their marker; the rest is slack.
+constexpr int kGeoBandMargin = 6;
+
 int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   const int N = c->N;
   const int n1 = N + 1;
@@ -955,12 +981,13 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   // resets the status), the marker geometry with the margin test, and the two scans,
   // which post the status to mapped host memory for the host to size the crossing list
   int* cnt = c->cnt.as<int>();
+  int* rng = c->intptr.as<int>();
   hipLaunchKernelGGL(k_count_cross, dim3(nblk(M, 256)), dim3(256), 0, s, M, xy,
-                     c->X.as<double>(), c->x0, c->y0, h, N, cnt, st);
+                     c->X.as<double>(), c->x0, c->y0, h, N, cnt, rng, st);
   const double mg = 3.0 * h;
   hipLaunchKernelGGL(k_marker_geo, dim3(M), dim3(256), 0, s, M, c->X.as<double>(), d1,
                      d2, c->geo.as<double>(), c->x0 + mg, c->x0 + c->side - mg, c->y0 + mg,
-                     c->y0 + c->side - mg, st);
+                     c->y0 + c->side - mg, rng, st);
   GeoStatus* hs = reinterpret_cast<GeoStatus*>(static_cast<char*>(c->hstat) + kGeoStatusOffset);
   GeoStatus* hs_dev =
       reinterpret_cast<GeoStatus*>(static_cast<char*>(c->dstat) + kGeoStatusOffset);
@@ -991,33 +1018,47 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   int* vraw = c->vraw.as<int>();
   int* need = c->need.as<int>();
   int* rowoff = c->armrow.as<int>();  // N+2 entries
-  {  // the per-node maps and the arm row counts in one pass
+  int* rowcnt = c->rowsum.as<int>();
+  // The rows that can hold crossings, labels, arms or stencil nodes: the rows of the
+  // curve's samples and kGeoBandMargin more on each side.  The node maps and labels of the
+  // rows that the previous interface used (c->gb_lo..c->gb_hi) are cleared as well; every
+  // row outside both keeps cleared maps and zero labels from before.
+  const int glo = std::max(0, hs->cr_lo - kGeoBandMargin);
+  const int ghi = std::min(N, hs->cr_hi + kGeoBandMargin);
+  const int ulo = std::min(glo, c->gb_lo), uhi = std::min(N, std::max(ghi, c->gb_hi));
+  c->gb_lo = ulo;  // until this interface is in place: the union may hold old entries
+  c->gb_hi = uhi;
+  {  // the per-node maps of those rows, the arm and node row counts
     const int nn = n1 * n1;
-    hipLaunchKernelGGL(k_geo_clear, dim3(nblk((nn + 3) / 4, 256)), dim3(256), 0, s, nn, N + 2,
-                       hid, vid, vraw, need, rowoff);
+    const int t0 = (ulo * n1) / 4, t1 = std::min((nn + 3) / 4, ((uhi + 1) * n1 + 3) / 4);
+    const int nt = std::max(t1 - t0, N + 2);
+    hipLaunchKernelGGL(k_geo_clear, dim3(nblk(nt, 256)), dim3(256), 0, s, nn, t0, t1, N + 2,
+                       n1, hid, vid, vraw, need, rowoff, rowcnt);
   }
   if (nh > 0)
     hipLaunchKernelGGL(k_mark_h, dim3(nblk(nh, 256)), dim3(256), 0, s, nh, cr, N, hid, st);
   int8_t* lab = c->lab.as<int8_t>();
-  hipLaunchKernelGGL(k_label, dim3(n1), dim3(256), 0, s, N, hid, lab);
+  hipLaunchKernelGGL(k_label, dim3(uhi - ulo + 1), dim3(256), 0, s, N, ulo, hid, lab);
   if (nv > 0) {
     hipLaunchKernelGGL(k_pair_v, dim3(nblk(nv, 256)), dim3(256), 0, s, nh, nv, cr, N, vraw, st);
     hipLaunchKernelGGL(k_mark_v, dim3(nblk(nv, 256)), dim3(256), 0, s, nh, nv, cr, N, c->y0, h,
                        lab, vraw, vid, st);
   }
   // arms
-  hipLaunchKernelGGL(k_arm_rowcount, dim3(N - 1), dim3(256), 0, s, N, lab, hid, vid, rowoff, st);
+  const int alo = std::max(1, glo), ahi = std::min(N - 1, ghi);  // interior rows of the band
+  hipLaunchKernelGGL(k_arm_rowcount, dim3(ahi - alo + 1), dim3(256), 0, s, N, alo, lab, hid, vid,
+                     rowoff, st);
   hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, 1, rowoff, &st->n_arms,
                      nullptr, nullptr);
-  hipLaunchKernelGGL(k_arm_fill, dim3(N - 1), dim3(1024), 0, s, N, c->x0, c->y0, h, c->c2, M, lab,
+  hipLaunchKernelGGL(k_arm_fill, dim3(ahi - alo + 1), dim3(1024), 0, s, N, alo, c->x0, c->y0, h,
+                     c->c2, M, lab,
                      hid, vid, rowoff, cr, c->geo.as<double>(), c->armpk.as<int>(),
                      c->armcoef.as<ArmCoef>(), st);
   // markers / nodes
   hipLaunchKernelGGL(k_marker_ext, dim3(nblk(M, 64)), dim3(64), 0, s, M, c->X.as<double>(),
                      c->geo.as<double>(), c->x0, c->y0, h, N, c->c2, lab, c->ext.as<double>(),
                      need, c->mknode.as<int>());
-  int* rowcnt = c->rowsum.as<int>();
-  hipLaunchKernelGGL(k_need_rowcount, dim3(n1), dim3(256), 0, s, N, need, rowcnt);
+  hipLaunchKernelGGL(k_need_rowcount, dim3(ghi - glo + 1), dim3(256), 0, s, N, glo, need, rowcnt);
   // per-chunk node lists for the node-transform + extraction kernel
   const int MC = c->mk_chunk;
   const int nch = (M + MC - 1) / MC;
@@ -1082,6 +1123,8 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   KFBI_HIP(hipGetLastError());
   c->st = *hs;
   c->M = M;
+  c->gb_lo = glo;  // every entry this interface wrote lies in rows glo..ghi
+  c->gb_hi = ghi;
   return KFBI_OK;
 }
 
