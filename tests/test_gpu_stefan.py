@@ -378,3 +378,28 @@ def test_explicit_scheme_is_stable_below_its_bound():
     print("[case] stability explicit tau=2e-6", flush=True)
     g, amps, n, blown = stability_run(2e-6, 1e-300, 1000)
     assert not blown and max(amps) < 2e-3, amps
+
+
+def test_seed_temperature_after_the_seed_moves():
+    """The seed field (T = 0 on nodes inside the crystal, St outside) after a second init
+    with a seed far from the first: nodes the first seed covered read St again (the
+    interface set-up clears the rows the previous interface used), and the nodes inside
+    the new circle are exactly those the oracle's labels mark (the field is held as
+    cosine coefficients, so values are compared to 1e-9)."""
+    from oracle import geometry as G
+    box = W.box(-1, 1, 256)
+    g = make(box, 64, 1e-3, ISO_C, ISO_V, True, 2)
+    St = -0.5
+    top = W.circle(64, 0.2, (0.1, 0.55))
+    bottom = W.circle(64, 0.15, (-0.2, -0.6))
+    g.init(dev(top), St=St)
+    g.init(dev(bottom), St=St)
+    T0 = g.temperature().cpu().numpy().reshape(box.N + 1, box.N + 1)
+    # the field is held as cosine coefficients, so the values come back to rounding
+    inside = G.build_geometry(bottom, box).inside  # [j, i], True inside
+    solid = np.abs(T0) < 1e-9
+    liquid = np.abs(T0 - St) < 1e-9
+    bad = np.argwhere(solid != inside)
+    print("nodes that disagree:", len(bad), bad[:5])
+    assert len(bad) == 0
+    assert np.all(solid | liquid)
