@@ -89,6 +89,7 @@ struct GeoStatus {
   int n_parts;
   int arm_lo, arm_hi;  // first and last grid rows holding arms (arm_lo > arm_hi: none)
   int cr_lo, cr_hi;    // rows between which the sampled curve lies (row lines it may cut)
+  int cc_lo, cc_hi;    // the same for the columns
 };
 
 }  // namespace kfbi

@@ -51,9 +51,11 @@ __global__ void __launch_bounds__(256)
                  GeoStatus* st) {
   __shared__ double red[4][4];
   const int k = blockIdx.x;
-  if (threadIdx.x == 0) {  // the row range of marker interval k (from k_count_cross)
-    atomicMin(&st->cr_lo, rng[k]);
-    atomicMax(&st->cr_hi, rng[M + k]);
+  if (threadIdx.x == 0 && k < (M + 255) / 256) {  // ranges of the k_count_cross blocks
+    atomicMin(&st->cr_lo, rng[4 * k]);
+    atomicMax(&st->cr_hi, rng[4 * k + 1]);
+    atomicMin(&st->cc_lo, rng[4 * k + 2]);
+    atomicMax(&st->cc_hi, rng[4 * k + 3]);
   }
   const double* x = X;
   const double* y = X + M;
@@ -140,44 +142,67 @@ __device__ inline void stencil_values(const double* v, int k, int M, double* cv)
 
 // Also copies the markers xy into the context (X) and resets the status words (thread 0),
 // so that no copy precedes it.
-// rng[k], rng[M + k]: the first and last row lines that the samples of interval k may cut.
-__global__ void k_count_cross(int M, const double* __restrict__ xy, double* __restrict__ Xc,
-                              double x0, double y0, double h, int N, int* __restrict__ cnt,
-                              int* __restrict__ rng, GeoStatus* __restrict__ st) {
+// rng[4 b + {0, 1, 2, 3}]: over the intervals of block b, the first and last row lines and
+// the first and last column lines that their samples may cut (reduced in the block, so
+// that few atomics fold them into the status afterwards).
+__global__ void __launch_bounds__(256)
+    k_count_cross(int M, const double* __restrict__ xy, double* __restrict__ Xc, double x0,
+                  double y0, double h, int N, int* __restrict__ cnt, int* __restrict__ rng,
+                  GeoStatus* __restrict__ st) {
+  __shared__ int wr[4][4];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M) return;
-  const double* X = xy;
-  Xc[k] = xy[k];
-  Xc[M + k] = xy[M + k];
-  if (k == 0) {
-    GeoStatus init{};
-    init.row_lo = 1 << 30;
-    init.row_hi = -1;
-    init.arm_lo = 1 << 30;
-    init.arm_hi = -1;
-    init.cr_lo = 1 << 30;
-    init.cr_hi = -1;
-    *st = init;
-  }
-  for (int ax = 0; ax < 2; ++ax) {
-    // ax = 0: rows y = y_j (compare y); ax = 1: columns x = x_i (compare x)
-    const double* v = (ax == 0) ? X + M : X;
-    const double lo = (ax == 0) ? y0 : x0;
-    double cv[6], vals[kSub + 1];
-    stencil_values(v, k, M, cv);
-    sub_values(cv, vals);
-    int jb, je, c = 0;
-    line_range(vals, lo, h, N, &jb, &je);
-    if (ax == 0) {
-      rng[k] = jb;
-      rng[M + k] = je;
+  const bool live = k < M;
+  int lo_hi[4] = {1 << 30, -1, 1 << 30, -1};  // row lo, row hi, column lo, column hi
+  if (live) {
+    const double* X = xy;
+    Xc[k] = xy[k];
+    Xc[M + k] = xy[M + k];
+    if (k == 0) {
+      GeoStatus init{};
+      init.row_lo = 1 << 30;
+      init.row_hi = -1;
+      init.arm_lo = 1 << 30;
+      init.arm_hi = -1;
+      init.cr_lo = init.cc_lo = 1 << 30;
+      init.cr_hi = init.cc_hi = -1;
+      *st = init;
     }
-    for (int j = jb; j <= je; ++j) {
-      const double g = lo + j * h;
+    for (int ax = 0; ax < 2; ++ax) {
+      // ax = 0: rows y = y_j (compare y); ax = 1: columns x = x_i (compare x)
+      const double* v = (ax == 0) ? X + M : X;
+      const double lo = (ax == 0) ? y0 : x0;
+      double cv[6], vals[kSub + 1];
+      stencil_values(v, k, M, cv);
+      sub_values(cv, vals);
+      int jb, je, c = 0;
+      line_range(vals, lo, h, N, &jb, &je);
+      lo_hi[2 * ax] = jb;
+      lo_hi[2 * ax + 1] = je;
+      for (int j = jb; j <= je; ++j) {
+        const double g = lo + j * h;
 #pragma unroll
-      for (int s = 0; s < kSub; ++s) c += ((vals[s] >= g) != (vals[s + 1] >= g)) ? 1 : 0;
+        for (int s = 0; s < kSub; ++s) c += ((vals[s] >= g) != (vals[s + 1] >= g)) ? 1 : 0;
+      }
+      cnt[ax * M + k] = c;
     }
-    cnt[ax * M + k] = c;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int v = lo_hi[q];
+    for (int off = 32; off > 0; off >>= 1) {
+      const int o = __shfl_xor(v, off, 64);
+      v = (q & 1) ? max(v, o) : min(v, o);
+    }
+    if (lane == 0) wr[q][w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int q = threadIdx.x;
+    int v = wr[q][0];
+    for (int u = 1; u < static_cast<int>(blockDim.x) / 64; ++u)
+      v = (q & 1) ? max(v, wr[q][u]) : min(v, wr[q][u]);
+    rng[4 * blockIdx.x + q] = v;
   }
 }
 
@@ -501,13 +526,15 @@ __device__ inline int node_arms(int i, int j, int N, const int8_t* lab, const in
   return na;
 }
 
-__global__ void k_arm_rowcount(int N, int j0, const int8_t* __restrict__ lab,
+// Arms of the interior nodes i0..i1 of row j0 + blockIdx.x (the nodes outside have no
+// label change around them).
+__global__ void k_arm_rowcount(int N, int j0, int i0, int i1, const int8_t* __restrict__ lab,
                                const int* __restrict__ hid, const int* __restrict__ vid,
                                int* __restrict__ rowcnt, GeoStatus* st) {
   __shared__ double scratch[16];
   const int j = j0 + blockIdx.x;  // interior rows j0.. (1 <= j0, last <= N - 1)
   int s = 0;
-  for (int i = 1 + threadIdx.x; i <= N - 1; i += blockDim.x)
+  for (int i = i0 + threadIdx.x; i <= i1; i += blockDim.x)
     s += node_arms(i, j, N, lab, hid, vid, nullptr, nullptr, nullptr, st);
   const double tot = block_sum<double>(static_cast<double>(s), scratch);
   if (threadIdx.x == 0) rowcnt[j] = static_cast<int>(tot);
@@ -518,7 +545,8 @@ __global__ void k_arm_rowcount(int N, int j0, const int8_t* __restrict__ lab,
 //   T = [u] + d [u_s] + d^2/2 [u_ss],  RHS_P += -T/h^2 (P inside) or +T/h^2 (P outside),
 // T linear in (Phi, Phi_a, Phi_aa, Psi, Psi_a) at the crossing (App. A.1), each of which
 // is the 6-point Lagrange combination of marker values.
-__global__ void k_arm_fill(int N, int j0, double x0, double y0, double h, double c2, int M,
+__global__ void k_arm_fill(int N, int j0, int i0, int i1, double x0, double y0, double h,
+                           double c2, int M,
                            const int8_t* __restrict__ lab, const int* __restrict__ hid,
                            const int* __restrict__ vid, const int* __restrict__ rowoff,
                            const Crossing* __restrict__ cr, const double* __restrict__ geo,
@@ -528,10 +556,10 @@ __global__ void k_arm_fill(int N, int j0, double x0, double y0, double h, double
   // a row without arms has nothing to fill (k_arm_rowcount has checked it already); the
   // condition is the same for the whole block
   if (rowoff[j] == rowoff[j + 1]) return;
-  const int n = N - 1;
+  const int n = i1 - i0 + 1;  // the row's nodes i0..i1, as in k_arm_rowcount
   const int T = blockDim.x;
   const int per = (n + T - 1) / T;
-  const int b = 1 + threadIdx.x * per, e = min(N, b + per);  // i in [b, e)
+  const int b = i0 + threadIdx.x * per, e = min(i1 + 1, b + per);  // i in [b, e)
   int cnt = 0;
   for (int i = b; i < e; ++i) cnt += node_arms(i, j, N, lab, hid, vid, nullptr, nullptr, nullptr, st);
   int slot = rowoff[j] + block_excl_scan(cnt, scratch, nullptr);
@@ -868,12 +896,12 @@ __global__ void __launch_bounds__(64) k_marker_ext(int M, const double* __restri
 
 // Node numbering: per row count of needed nodes, then scan over rows (single block):
 // node offsets, compact list of needed rows, band [row_lo, row_hi].
-__global__ void k_need_rowcount(int N, int j0, const int* __restrict__ need,
+__global__ void k_need_rowcount(int N, int j0, int i0, int i1, const int* __restrict__ need,
                                 int* __restrict__ rowcnt) {
   __shared__ double scratch[16];
   const int j = j0 + blockIdx.x;
   int s = 0;
-  for (int i = threadIdx.x; i <= N; i += blockDim.x) s += need[j * (N + 1) + i];
+  for (int i = i0 + threadIdx.x; i <= i1; i += blockDim.x) s += need[j * (N + 1) + i];
   const double t = block_sum<double>(static_cast<double>(s), scratch);
   if (threadIdx.x == 0) rowcnt[j] = static_cast<int>(t);
 }
@@ -967,7 +995,7 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   KFBI_TRY(c->geo.ensure(sizeof(double) * 6 * M));
   KFBI_TRY(c->dvec.ensure(sizeof(double) * 2 * M));
   KFBI_TRY(c->cnt.ensure(sizeof(int) * (2 * M + 2)));
-  KFBI_TRY(c->intptr.ensure(sizeof(int) * (2 * M + 2)));
+  KFBI_TRY(c->intptr.ensure(sizeof(int) * (4 * ((M + 255) / 256) + 2)));
   KFBI_TRY(c->ext.ensure(sizeof(double) * kExtCount * M));
   KFBI_TRY(c->mknode.ensure(sizeof(int) * 6 * M));
 
@@ -1025,6 +1053,8 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   // row outside both keeps cleared maps and zero labels from before.
   const int glo = std::max(0, hs->cr_lo - kGeoBandMargin);
   const int ghi = std::min(N, hs->cr_hi + kGeoBandMargin);
+  const int clo = std::max(0, hs->cc_lo - kGeoBandMargin);  // columns likewise (the node
+  const int chi = std::min(N, hs->cc_hi + kGeoBandMargin);  // sweeps inside the rows)
   const int ulo = std::min(glo, c->gb_lo), uhi = std::min(N, std::max(ghi, c->gb_hi));
   c->gb_lo = ulo;  // until this interface is in place: the union may hold old entries
   c->gb_hi = uhi;
@@ -1046,19 +1076,21 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   }
   // arms
   const int alo = std::max(1, glo), ahi = std::min(N - 1, ghi);  // interior rows of the band
-  hipLaunchKernelGGL(k_arm_rowcount, dim3(ahi - alo + 1), dim3(256), 0, s, N, alo, lab, hid, vid,
-                     rowoff, st);
+  const int ilo = std::max(1, clo), ihi = std::min(N - 1, chi);  // interior columns
+  hipLaunchKernelGGL(k_arm_rowcount, dim3(ahi - alo + 1), dim3(256), 0, s, N, alo, ilo, ihi, lab,
+                     hid, vid, rowoff, st);
   hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, 1, rowoff, &st->n_arms,
                      nullptr, nullptr);
-  hipLaunchKernelGGL(k_arm_fill, dim3(ahi - alo + 1), dim3(1024), 0, s, N, alo, c->x0, c->y0, h,
-                     c->c2, M, lab,
+  hipLaunchKernelGGL(k_arm_fill, dim3(ahi - alo + 1), dim3(1024), 0, s, N, alo, ilo, ihi, c->x0,
+                     c->y0, h, c->c2, M, lab,
                      hid, vid, rowoff, cr, c->geo.as<double>(), c->armpk.as<int>(),
                      c->armcoef.as<ArmCoef>(), st);
   // markers / nodes
   hipLaunchKernelGGL(k_marker_ext, dim3(nblk(M, 64)), dim3(64), 0, s, M, c->X.as<double>(),
                      c->geo.as<double>(), c->x0, c->y0, h, N, c->c2, lab, c->ext.as<double>(),
                      need, c->mknode.as<int>());
-  hipLaunchKernelGGL(k_need_rowcount, dim3(ghi - glo + 1), dim3(256), 0, s, N, glo, need, rowcnt);
+  hipLaunchKernelGGL(k_need_rowcount, dim3(ghi - glo + 1), dim3(256), 0, s, N, glo, clo, chi, need,
+                     rowcnt);
   // per-chunk node lists for the node-transform + extraction kernel
   const int MC = c->mk_chunk;
   const int nch = (M + MC - 1) / MC;
