@@ -540,13 +540,13 @@ __global__ void k_arm_rowcount(int N, int j0, int i0, int i1, const int8_t* __re
   if (threadIdx.x == 0) rowcnt[j] = static_cast<int>(tot);
 }
 
-// Write arms of row j in (i, direction) order with their correction coefficients.
+// Write arms of row j in (i, direction) order with the data of their correction
+// coefficients (formed by k_arm_coef).
 // For arm P -> Q cut at the crossing with signed offset d = coord(Q) - crossing coord:
 //   T = [u] + d [u_s] + d^2/2 [u_ss],  RHS_P += -T/h^2 (P inside) or +T/h^2 (P outside),
 // T linear in (Phi, Phi_a, Phi_aa, Psi, Psi_a) at the crossing (App. A.1), each of which
 // is the 6-point Lagrange combination of marker values.
-__global__ void k_arm_fill(int N, int j0, int i0, int i1, double x0, double y0, double h,
-                           double c2, int M,
+__global__ void k_arm_fill(int N, int j0, int i0, int i1, double x0, double y0, double h, int M,
                            const int8_t* __restrict__ lab, const int* __restrict__ hid,
                            const int* __restrict__ vid, const int* __restrict__ rowoff,
                            const Crossing* __restrict__ cr, const double* __restrict__ geo,
@@ -588,25 +588,50 @@ __global__ void k_arm_fill(int N, int j0, int i0, int i1, double x0, double y0, 
       }
       const bool hz = x.horiz;
       const double d = hz ? (x0 + qi[a] * h) - x.pos : (y0 + qj[a] * h) - x.pos;
+      // the correction coefficients are formed by k_arm_coef, one thread per arm: here the
+      // record holds the crossing's tangent and its derivative, d, and the side and
+      // direction flags
       ArmCoef ac;
 #pragma unroll
       for (int m = 0; m < 6; ++m) ac.l[m] = w[m];
-      for (int qv = 0; qv < 5; ++qv) {
-        double u[5] = {0, 0, 0, 0, 0};
-        u[qv] = 1.0;
-        double J[6];
-        jumps_closed(g[0], g[1], g[2], g[3], u[0], u[1], u[2], u[3], u[4], c2, J);
-        const double Tv = hz ? J[0] + d * J[1] + 0.5 * d * d * J[3]
-                             : J[0] + d * J[2] + 0.5 * d * d * J[4];
-        ac.coef[qv] = sgn * Tv;
-      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ac.coef[q] = g[q];
+      ac.coef[4] = d;
       ac.k = x.k;
-      ac.pad = 0;
+      ac.pad = (hz ? 1 : 0) | (sgn < 0.0 ? 2 : 0);
       armpk[slot] = i | (j << 16);
       armc[slot] = ac;
       ++slot;
     }
   }
+}
+
+// The five correction coefficients of arm a (Sec. 4.2.1 eq. modified-fdm with the App. A.1
+// jumps): the jump T = [u] + d [u_s] + d^2/2 [u_ss] along the arm for each unit vector of
+// (Phi, Phi_a, Phi_aa, Psi, Psi_a), with the sign of P's side and 1/h^2; the record's
+// geometry fields (written by k_arm_fill) are replaced by the coefficients.  One thread
+// per arm, so an arm-rich node no longer holds up its row's block.
+__global__ void k_arm_coef(int cap, const int* __restrict__ narms, double h, double c2,
+                           ArmCoef* __restrict__ armc) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= cap || a >= *narms) return;
+  ArmCoef ac = armc[a];
+  const double g0 = ac.coef[0], g1 = ac.coef[1], g2 = ac.coef[2], g3 = ac.coef[3];
+  const double d = ac.coef[4];
+  const bool hz = ac.pad & 1;
+  const double ih2 = 1.0 / (h * h);
+  const double sgn = (ac.pad & 2) ? -ih2 : ih2;
+  for (int qv = 0; qv < 5; ++qv) {
+    double u[5] = {0, 0, 0, 0, 0};
+    u[qv] = 1.0;
+    double J[6];
+    jumps_closed(g0, g1, g2, g3, u[0], u[1], u[2], u[3], u[4], c2, J);
+    const double Tv = hz ? J[0] + d * J[1] + 0.5 * d * d * J[3]
+                         : J[0] + d * J[2] + 0.5 * d * d * J[4];
+    ac.coef[qv] = sgn * Tv;
+  }
+  ac.pad = 0;
+  armc[a] = ac;
 }
 
 // Row-ordered arm coefficients as structure of arrays (coefR[q * cap + a], kR[a]).
@@ -1082,9 +1107,11 @@ int geometry_setup(kfbi_ctx* c, int M, const double* xy) {
   hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, N + 1, 1, rowoff, &st->n_arms,
                      nullptr, nullptr);
   hipLaunchKernelGGL(k_arm_fill, dim3(ahi - alo + 1), dim3(1024), 0, s, N, alo, ilo, ihi, c->x0,
-                     c->y0, h, c->c2, M, lab,
+                     c->y0, h, M, lab,
                      hid, vid, rowoff, cr, c->geo.as<double>(), c->armpk.as<int>(),
                      c->armcoef.as<ArmCoef>(), st);
+  hipLaunchKernelGGL(k_arm_coef, dim3(nblk(narm_cap, 256)), dim3(256), 0, s, narm_cap,
+                     &st->n_arms, h, c->c2, c->armcoef.as<ArmCoef>());
   // markers / nodes
   hipLaunchKernelGGL(k_marker_ext, dim3(nblk(M, 64)), dim3(64), 0, s, M, c->X.as<double>(),
                      c->geo.as<double>(), c->x0, c->y0, h, N, c->c2, lab, c->ext.as<double>(),
