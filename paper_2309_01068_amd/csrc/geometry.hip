@@ -941,15 +941,11 @@ __global__ void __launch_bounds__(1024)
   // (ceil(arms / kArmsPerPart) per interior row); thread 0 then posts the whole status to
   // mapped host memory at system scope
   __shared__ int scratch[17];
-  __shared__ int band[4];
+  __shared__ int band[4][32];  // per wavefront: node rows lo, hi, arm rows lo, hi
   const int n1 = N + 1;
   const int T = blockDim.x;
   const int per = (n1 + T - 1) / T;
   const int b = threadIdx.x * per, e = min(n1, b + per);
-  if (threadIdx.x == 0) {
-    band[0] = band[2] = 1 << 30;
-    band[1] = band[3] = -1;
-  }
   int s = 0, f = 0, pc = 0;
   for (int j = b; j < e; ++j) {
     s += rowcnt[j];
@@ -978,25 +974,33 @@ __global__ void __launch_bounds__(1024)
     rowpart[j] = poff;
     if (j >= 1 && j <= N - 1) poff += (rowoff[j + 1] - rowoff[j] + kArmsPerPart - 1) / kArmsPerPart;
   }
-  if (hi >= 0) {
-    atomicMin(&band[0], lo);
-    atomicMax(&band[1], hi);
-  }
-  if (ahi >= 0) {
-    atomicMin(&band[2], alo);
-    atomicMax(&band[3], ahi);
+  // the bands by shuffles within each wavefront, then over the wavefronts (atomics on
+  // one LDS word from every thread serialise)
+  int bv[4] = {lo, hi, alo, ahi};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    for (int o = 32; o > 0; o >>= 1) {
+      const int x = __shfl_xor(bv[q], o, 64);
+      bv[q] = (q & 1) ? max(bv[q], x) : min(bv[q], x);
+    }
+    if (lane == 0) band[q][wv] = bv[q];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    int r[4] = {band[0][0], band[1][0], band[2][0], band[3][0]};
+    for (int u = 1; u < T / 64; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r[q] = (q & 1) ? max(r[q], band[q][u]) : min(r[q], band[q][u]);
     rowptr[tot_rows] = tot_nodes;
     GeoStatus v = *st;
     v.n_nodes = tot_nodes;
     v.n_rows = tot_rows;
     v.n_parts = tot_parts;
-    v.row_lo = band[0];
-    v.row_hi = band[1];
-    v.arm_lo = band[2];
-    v.arm_hi = band[3];
+    v.row_lo = r[0];
+    v.row_hi = r[1];
+    v.arm_lo = r[2];
+    v.arm_hi = r[3];
     *st = v;
     *hpost = v;
     __threadfence_system();
