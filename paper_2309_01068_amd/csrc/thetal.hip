@@ -639,14 +639,27 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 using namespace kfbi;
 
+// defined after the Stefan object, whose coefficients it may use
+static void tl_pre_launch(thetaL* th, const double* guess, double* xw);
+
 namespace kfbi {
 int thetal_refresh(thetaL* th) {
-  const int M = th->M;
-  hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), th->stream, M,
-                     th->prm.sigma, th->prm.J, th->tw.as<double>(), th->eta.as<double>(),
-                     th->scal.as<double>(), th->X.as<double>(), th->rhs.as<double>(),
-                     th->aux.as<double>(), th->etahat.as<double>(), hs_mode(), nullptr, nullptr,
-                     nullptr);
+  tl_pre_launch(th, nullptr, nullptr);
+  KFBI_HIP(hipGetLastError());
+  th->pre_n = th->n;  // the next step of this state need not run the pass again
+  return KFBI_OK;
+}
+
+// Opens a step: the shape pass with the initial guess copied into the working density,
+// or only the copy when a learned guess has just run the pass for this state.
+static int tl_open_step(thetaL* th, const double* guess) {
+  if (th->pre_n == th->n) {
+    KFBI_HIP(hipMemcpyAsync(th->phiw.p, guess, sizeof(double) * th->M, hipMemcpyDeviceToDevice,
+                            th->stream));
+  } else {
+    tl_pre_launch(th, guess, th->phiw.as<double>());
+  }
+  th->pre_n = -1;
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
 }
@@ -847,6 +860,7 @@ int thetaL_init(thetaL* th, int Mi, const double* xy) {
     return KFBI_E_NONFINITE;
   }
   th->n = 0;
+  th->pre_n = -1;
   th->have_phi = 0;
   th->ready = 1;
   return KFBI_OK;
@@ -894,11 +908,7 @@ int thetaL_step(thetaL* th, const double* x0, thetaL_stats* stats) {
   // reconstruction, right-hand side, and the GMRES initial guess (x0, else the previous
   // density, zero before the first solve) into the working density
   const double* guess = x0 ? x0 : th->phi.as<double>();
-  hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), s, M, p.sigma, p.J,
-                     th->tw.as<double>(), th->eta.as<double>(), th->scal.as<double>(),
-                     th->X.as<double>(), th->rhs.as<double>(), th->aux.as<double>(),
-                     th->etahat.as<double>(), hs_mode(), nullptr, guess, th->phiw.as<double>());
-  KFBI_HIP(hipGetLastError());
+  KFBI_TRY(tl_open_step(th, guess));
   int st = kfbi_set_interface(th->kc, M, th->X.as<double>());
   if (st != KFBI_OK) return st;
   const double ms_geo = ms_since(t0);
@@ -1035,6 +1045,7 @@ int thetaL_set_state(thetaL* th, const thetaL_state* st) {
   KFBI_HIP(hipMemcpyAsync(th->scal.p, th->hscal, sizeof(double) * S_COUNT, hipMemcpyHostToDevice, s));
   KFBI_HIP(hipStreamSynchronize(s));
   th->n = st->n;
+  th->pre_n = -1;
   th->have_phi = 1;
   th->ready = 1;
   return KFBI_OK;
@@ -1080,6 +1091,19 @@ struct stefan {
   double lam = 0.0, c2 = 0.0;
   int have_prev = 0;       // T^{n-1} exists (BDF2)
 };
+
+// The shape pass of the step of th: the Hele-Shaw right-hand side -sigma kappa + J ln|x|,
+// or the Stefan problem's -eps_C kappa with eps_V per marker when th belongs to one.
+static void tl_pre_launch(thetaL* th, const double* guess, double* xw) {
+  const int M = th->M;
+  stefan* o = th->owner;
+  hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), th->stream, M,
+                     o ? 0.0 : th->prm.sigma, o ? 0.0 : th->prm.J, th->tw.as<double>(),
+                     th->eta.as<double>(), th->scal.as<double>(), th->X.as<double>(),
+                     th->rhs.as<double>(), th->aux.as<double>(), th->etahat.as<double>(),
+                     o ? o->md : hs_mode(), o ? o->amk.as<double>() : nullptr,
+                     guess, xw);
+}
 
 static void st_free(stefan* s) {
   for (DBuf* b : {&s->That, &s->Tprev, &s->Tnew, &s->T1, &s->t1at, &s->amk, &s->neg, &s->grid0})
@@ -1141,6 +1165,7 @@ int stefan_create(const stefan_params* p, stefan** out) {
     delete s;
     return st;
   }
+  s->tl.owner = s;  // its steps and learned guesses use the Stefan coefficients
   const size_t nf = neu_field_size(p->N);
   const size_t n1sq = static_cast<size_t>(p->N + 1) * (p->N + 1);
   if ((st = s->That.ensure(sizeof(double) * nf)) || (st = s->Tprev.ensure(sizeof(double) * nf)) ||
@@ -1205,12 +1230,7 @@ int stefan_step(stefan* s, const double* x0, stefan_stats* stats) {
   // reconstruction, eps_C kappa and eps_V, and the GMRES initial guess (x0, else the last
   // density) into the working density
   const double* guess = x0 ? x0 : th->phi.as<double>();
-  hipLaunchKernelGGL(k_tl_pre, dim3(1), dim3(kTLThreads), tl_lds_bytes(M), hs, M, 0.0, 0.0,
-                     th->tw.as<double>(), th->eta.as<double>(), th->scal.as<double>(),
-                     th->X.as<double>(), th->rhs.as<double>(), th->aux.as<double>(),
-                     th->etahat.as<double>(), s->md, s->amk.as<double>(), guess,
-                     th->phiw.as<double>());
-  KFBI_HIP(hipGetLastError());
+  KFBI_TRY(tl_open_step(th, guess));
   int st = kfbi_set_interface(th->kc, M, th->X.as<double>());
   if (st != KFBI_OK) return st;
   const double ms_geo = ms_since(t0);

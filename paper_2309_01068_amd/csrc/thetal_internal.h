@@ -4,6 +4,8 @@
 #include "../../include/thetal.h"
 #include "common.h"
 
+struct stefan;
+
 namespace kfbi {
 constexpr int kTLThreads = 1024;
 constexpr int kTLMaxM = 2048;
@@ -28,6 +30,12 @@ struct thetaL {
   double* hscal = nullptr;  // copy of scal in coherent pinned host memory
   double* dscal = nullptr;  // its device address (the step's last kernel writes it)
   hipEvent_t tev[4] = {};   // timing of the phases that end without a host synchronisation
+  // The shape pass that opens a step (reconstruction, right-hand side, shape data) is the
+  // Stefan problem's when owner is set.  pre_n is the step count for which its outputs are
+  // current because a learned guess has just formed them (the step then only copies its
+  // initial guess), else -1.
+  stefan* owner = nullptr;
+  int pre_n = -1;
 };
 
 
