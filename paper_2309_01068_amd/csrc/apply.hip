@@ -1953,7 +1953,7 @@ __global__ void __launch_bounds__(256)
 // "Ghat" holds, for every row j = 0..N, the cosine coefficients along x in the column-group
 // layout: element (j, p) at ((p / 4) (N + 1) + j) 4 + p % 4.
 int neu_dense_solve(kfbi_ctx* c, const double* Fa, const double* Fb, double ca, double cb,
-                    double* Gout) {
+                    double* Gout, int jlo, int jhi) {
   const int N = c->N;
   NeuRhs rr;
   rr.Fa = Fa;
@@ -1964,21 +1964,21 @@ int neu_dense_solve(kfbi_ctx* c, const double* Fa, const double* Fb, double ca, 
   const double* sinT = c->sinT.as<double>();
   neu_dispatch<double>(N, [&](auto EC) {
     launch_grid_stages_neu<double, decltype(EC)::value>(
-        c, 1, sinT, 0, N, c->tmat.as<double>(), Gout, false, nullptr, nullptr, nullptr, nullptr,
-        nullptr, nullptr, 4, rr, c->mq.as<double>(), 0);
+        c, 1, sinT, jlo, jhi, c->tmat.as<double>(), Gout, false, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, 4, rr, c->mq.as<double>(), 0);
   });
   KFBI_HIP(hipGetLastError());
   return KFBI_OK;
 }
 
-int neu_interp(kfbi_ctx* c, const double* Gfull, double* vout) {
+int neu_interp(kfbi_ctx* c, const double* G, int jlo, int jhi, double* vout) {
   const int N = c->N;
   const NeuRhs rr;
   const double* sinT = c->sinT.as<double>();
   kfbi_out o{vout, nullptr, nullptr, nullptr, nullptr};
   neu_dispatch<double>(N, [&](auto EC) {
     launch_grid_stages_neu<double, decltype(EC)::value>(
-        c, 1, sinT, 0, N, c->tmat.as<double>(), const_cast<double*>(Gfull), false, nullptr,
+        c, 1, sinT, jlo, jhi, c->tmat.as<double>(), const_cast<double*>(G), false, nullptr,
         nullptr, &o, nullptr, nullptr, nullptr, 8, rr, c->mqz.as<double>(), 0);
   });
   KFBI_HIP(hipGetLastError());

@@ -155,9 +155,12 @@ namespace kfbi {
 int geometry_setup(kfbi_ctx* c, int M, const double* xy);
 // Zero-normal-derivative box, full fields (FP64): Ghat arrays of neu_field_size(N) doubles.
 inline size_t neu_field_size(int N) { return static_cast<size_t>(N + 4) * (N + 1); }
+// rows jlo..jhi of the solution of the dense right-hand side ca Fa + cb Fb (column-group
+// layout of those rows: element (j, p) at ((p / 4) nb + j - jlo) 4 + p % 4, nb = jhi-jlo+1),
+// and the values at the markers from such rows (they must hold every node row)
 int neu_dense_solve(kfbi_ctx* c, const double* Fa, const double* Fb, double ca, double cb,
-                    double* Gout);
-int neu_interp(kfbi_ctx* c, const double* Gfull, double* vout);
+                    double* Gout, int jlo, int jhi);
+int neu_interp(kfbi_ctx* c, const double* G, int jlo, int jhi, double* vout);
 int neu_apply_full(kfbi_ctx* c, int layer, const double* dens, const double* Fa,
                    const double* Fb, double ca, double cb, double* Gout);
 int neu_to_grid(kfbi_ctx* c, const double* Gfull, double* grid);

@@ -1245,8 +1245,10 @@ int stefan_step(stefan* s, const double* x0, stefan_stats* stats) {
     ca = -2.0 / p.tau;
     cb = 0.5 / p.tau;
   }
-  KFBI_TRY(neu_dense_solve(th->kc, Fa, Fb, ca, cb, s->T1.as<double>()));
-  KFBI_TRY(neu_interp(th->kc, s->T1.as<double>(), s->t1at.as<double>()));
+  // only T1 at the markers is needed: the solve writes the node rows alone
+  const int jlo = th->kc->st.row_lo, jhi = th->kc->st.row_hi;
+  KFBI_TRY(neu_dense_solve(th->kc, Fa, Fb, ca, cb, s->T1.as<double>(), jlo, jhi));
+  KFBI_TRY(neu_interp(th->kc, s->T1.as<double>(), jlo, jhi, s->t1at.as<double>()));
   hipLaunchKernelGGL(k_axpby, dim3((M + 255) / 256), dim3(256), 0, hs, M, -1.0,
                      s->t1at.as<double>(), 1.0, th->rhs.as<double>());
   KFBI_HIP(hipGetLastError());
