@@ -56,6 +56,12 @@ CASES = [
     # node split among the wavefronts (the second also solves only the band of rows)
     ("star1024_m256", W.star(256), W.box(-1, 1, 1024), 1000.0, K.BOX_ZERO),
     ("ellipse1024_m200", W.ellipse(200), W.box(-1, 1, 1024), 1000.0, K.BOX_ZERO),
+    # a small circle near the top of the box: the band ends about 20 rows below the box
+    # row, where the condition of the empty rows above it matters (most for Laplace, whose
+    # low modes decay slowly)
+    ("circle_top_1024", W.circle(128, 0.05, (0.1, 0.9)), W.box(-1, 1, 1024), 1000.0, K.BOX_ZERO),
+    ("circle_top_1024_lap", W.circle(128, 0.05, (0.1, 0.9)), W.box(-1, 1, 1024), 0.0,
+     K.BOX_ZERO),
 ]
 
 

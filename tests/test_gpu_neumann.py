@@ -42,6 +42,8 @@ CASES = [
     ("circle_64", W.circle(96, 0.45), W.box(-1, 1, 64), 9.0),
     # one-marker chunks on a 512^2 grid: mode-split node sums, band column solve
     ("circle_m128_512", W.circle(128, 0.3), W.box(-1, 1, 512), 500.0),
+    # near the top of the box: the band ends a few rows below the mirrored box row
+    ("circle_top_512", W.circle(128, 0.05, (0.1, 0.9)), W.box(-1, 1, 512), 500.0),
 ]
 
 
