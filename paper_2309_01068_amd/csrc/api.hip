@@ -116,7 +116,7 @@ static void for_each_buffer(Ctx* c, F&& f) {
   B* bufs[] = {&c->vraw, &c->X,      &c->geo,    &c->dvec,   &c->cnt,     &c->cross,  &c->hid,
                   &c->vid,    &c->lab,    &c->armcnt, &c->rowsum,  &c->armrow, &c->armpk,
                   &c->armc,   &c->armk,   &c->armsc,  &c->chpos,
-                  &c->colc,   &c->lanef,   &c->cnode,  &c->ccount,
+                  &c->colc,   &c->lanef,  &c->bandc,  &c->cnode,  &c->ccount,
                   &c->mkloc,  &c->tmat,   &c->pdesc,  &c->rowpart, &c->ckoff, &c->cklist, &c->ckcoef, &c->ckmk, &c->mqz,
                   &c->armcoef, &c->intptr, &c->need,    &c->nodeidx, &c->nodei,
                   &c->rowptr, &c->rows,   &c->mknode, &c->ext,     &c->gstat,  &c->mq,

@@ -1032,12 +1032,48 @@ __global__ void k_colconst_neu(int N, double hc2, int E, double* __restrict__ co
 //                                                             if hb = 0),
 // d = 1/rho - rho.  The result equals the full solve up to rounding; E rows per lane cover
 // the band instead of the whole column.
+// Per-mode constants of the band column solve for the band lo .. lo + nr - 1 with E rows
+// per lane (formed once per band instead of in every solve): bc[kBandModeConsts q + {0..5}]
+// = cL, cR, gL, gR, 1 / (1 - rho^(2N)), 1 / (1/rho - rho) of mode slot q, then per (q, lane)
+// rho^(lane E) and rho^(nr - lane E - E) (zero for lanes wholly past the band).
+constexpr int kBandModeConsts = 8;
+template <bool NEU>
+__global__ void k_band_const(int N, int lo, int nr, int E, const double* __restrict__ colc,
+                             double* __restrict__ bc) {
+  const int nmodes = NEU ? N + 1 : N - 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nmodes * 64) return;
+  const int q = t / 64, lane = t % 64;
+  const double rho = colc[(NEU ? 4 : 3) * q];
+  const double eps = colc[(NEU ? 4 : 3) * q + 1];
+  double id = colc[(NEU ? 4 : 3) * q + 2];  // 1 / (1 - rho^(2N)), divided by d for the mirror box
+  const int hb = N - (lo + nr - 1);
+  const double lr = log1p(-eps);
+  const int k1 = nr - lane * E - E;
+  double* lf = bc + static_cast<size_t>(kBandModeConsts) * nmodes;
+  lf[static_cast<size_t>(t) * 2] = (lane * E < nr) ? exp(static_cast<double>(lane * E) * lr) : 0.0;
+  lf[static_cast<size_t>(t) * 2 + 1] = (k1 > -E) ? exp(static_cast<double>(k1) * lr) : 0.0;
+  if (lane != 0) return;
+  const double invd = rho / (eps * (2.0 - eps));  // 1 / (1/rho - rho)
+  const double gL = NEU ? ((lo == 0) ? invd
+                                     : rho * (1.0 + exp(static_cast<double>(2 * lo - 2) * lr)) * invd)
+                        : rho * (-expm1(static_cast<double>(2 * lo - 2) * lr)) * invd;
+  if (NEU) id *= eps * (2.0 - eps) / rho;
+  double* m = bc + static_cast<size_t>(kBandModeConsts) * q;
+  m[0] = exp(static_cast<double>(nr - 1 + 2 * lo) * lr);
+  m[1] = exp(static_cast<double>(nr - 1 + 2 * hb) * lr);
+  m[2] = gL;
+  m[3] = (NEU ? 1.0 : -1.0) * exp(static_cast<double>(2 * hb) * lr);
+  m[4] = id;
+  m[5] = invd;
+}
+
 template <class T, int E, bool NEU>
 __global__ void __launch_bounds__(256)
     k_colsolve_band(int N, double h, int P, const T* __restrict__ Tg,
-                    const int* __restrict__ rowpart, const double* __restrict__ colc, int lo,
-                    int nr, int jlo, int jhi, T* __restrict__ Gg, int nblk_x, size_t tstride,
-                    size_t gstride, int ldr) {
+                    const int* __restrict__ rowpart, const double* __restrict__ colc,
+                    const double* __restrict__ bc, int lo, int nr, int jlo, int jhi,
+                    T* __restrict__ Gg, int nblk_x, size_t tstride, size_t gstride, int ldr) {
   extern __shared__ double dynp[];
   T* tp = reinterpret_cast<T*>(dynp);
   T (*col)[64 * (E + 1)] = reinterpret_cast<T (*)[64 * (E + 1)]>(dynp);
@@ -1052,29 +1088,25 @@ __global__ void __launch_bounds__(256)
   Gg += static_cast<size_t>(blockIdx.y) * gstride;
   const int q = grp * kColsPerBlock + w;  // this wavefront's mode slot
   const bool live = q < nmodes;
-  double rho = 0.0, eps = 0.0, id = 0.0;
+  const int hb = N - (lo + nr - 1);
+  // the band conditions' constants (k_band_const): RL = gL P_0 (P_1 / d for the mirror box
+  // at lo = 0), RR = gR P_{nr-1} (mirror box at hi = N: (P_{nr-2} - rho P_{nr-1}) / d), and
+  // this lane's rho^(lane E) and rho^(nr - 1 - (lane E + E - 1))
+  double rho = 0.0, eps = 0.0, id = 0.0, invd = 0.0, cL = 0.0, cR = 0.0, gL = 0.0, gR = 0.0;
+  double f0 = 0.0, f1 = 0.0;
   if (live) {
     rho = colc[(NEU ? 4 : 3) * q];
     eps = colc[(NEU ? 4 : 3) * q + 1];
-    id = colc[(NEU ? 4 : 3) * q + 2];  // 1 / (1 - rho^(2N)), divided by d for the mirror box
+    cL = bc[kBandModeConsts * q];
+    cR = bc[kBandModeConsts * q + 1];
+    gL = bc[kBandModeConsts * q + 2];
+    gR = bc[kBandModeConsts * q + 3];
+    id = bc[kBandModeConsts * q + 4];
+    invd = bc[kBandModeConsts * q + 5];
+    const double* lf = bc + static_cast<size_t>(kBandModeConsts) * nmodes;
+    f0 = lf[(static_cast<size_t>(q) * 64 + lane) * 2];
+    f1 = lf[(static_cast<size_t>(q) * 64 + lane) * 2 + 1];
   }
-  // the band conditions' constants, formed while the part rows load: RL = gL P_0 (P_1 / d
-  // for the mirror box at lo = 0), RR = gR P_{nr-1} (mirror box at hi = N:
-  // (P_{nr-2} - rho P_{nr-1}) / d); rho^(lane E) and rho^(nr - 1 - (lane E + E - 1)) for the
-  // homogeneous terms of this lane's rows (zero for lanes wholly past the band)
-  const int hb = N - (lo + nr - 1);
-  const double lr = log1p(-eps);
-  const double invd = rho / (eps * (2.0 - eps));  // 1 / (1/rho - rho)
-  const double cL = exp(static_cast<double>(nr - 1 + 2 * lo) * lr);
-  const double cR = exp(static_cast<double>(nr - 1 + 2 * hb) * lr);
-  const double gL = NEU ? ((lo == 0) ? invd
-                                     : rho * (1.0 + exp(static_cast<double>(2 * lo - 2) * lr)) * invd)
-                        : rho * (-expm1(static_cast<double>(2 * lo - 2) * lr)) * invd;
-  const double gR = (NEU ? 1.0 : -1.0) * exp(static_cast<double>(2 * hb) * lr);
-  if (NEU) id *= eps * (2.0 - eps) / rho;
-  const int k1 = nr - lane * E - E;
-  const double f0 = (lane * E < nr) ? exp(static_cast<double>(lane * E) * lr) : 0.0;
-  const double f1 = (k1 > -E) ? exp(static_cast<double>(k1) * lr) : 0.0;
   constexpr int R = (64 * E + 255) / 256;  // band rows per thread in the row sums
   int rq0[R], rq1[R];
 #pragma unroll
@@ -1634,6 +1666,19 @@ static bool solve_band(const kfbi_ctx* c, bool neu, int* lo, int* nr) {
   return true;
 }
 
+// The band solve's constants for (lo, nr, E), formed when the band differs from the one
+// bandc holds (once per interface, not per apply).
+template <bool NEU>
+static void band_constants(kfbi_ctx* c, int lo, int nr, int E) {
+  if (c->bc_nr == nr && c->bc_lo == lo && c->bc_E == E) return;
+  const int nmodes = NEU ? c->N + 1 : c->N - 1;
+  hipLaunchKernelGGL((k_band_const<NEU>), dim3(nblk(64LL * nmodes, 256)), dim3(256), 0, c->stream,
+                     c->N, lo, nr, E, c->colc.as<double>(), c->bandc.as<double>());
+  c->bc_lo = lo;
+  c->bc_nr = nr;
+  c->bc_E = E;
+}
+
 template <class T, int E>
 static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring, size_t rstride,
                                int jlo, int jhi, T* Tg, T* G, bool full, double* grid,
@@ -1660,10 +1705,11 @@ static void launch_grid_stages(kfbi_ctx* c, int B, const T* sinT, const T* ring,
     // zero box: the right-hand side lives on the arm rows only
     band_dispatch(bnr, [&](auto EC) {
       constexpr int EB = decltype(EC)::value;
+      band_constants<false>(c, blo, bnr, EB);
       hipLaunchKernelGGL((k_colsolve_band<T, EB, false>), dim3(nb, B), dim3(256),
                          sizeof(T) * colsolve_lds_elems(P, EB), s, N, c->h, P, Tg,
-                         c->rowpart.as<int>(), c->colc.as<double>(), blo, bnr, jlo, jhi, G, nb,
-                         tstride, gstride, ldr);
+                         c->rowpart.as<int>(), c->colc.as<double>(), c->bandc.as<double>(), blo,
+                         bnr, jlo, jhi, G, nb, tstride, gstride, ldr);
     });
   } else if (stages & 4) {
     const size_t lds_dyn = sizeof(T) * colsolve_lds_elems(P, E);
@@ -1734,10 +1780,11 @@ static void launch_grid_stages_neu(kfbi_ctx* c, int B, const T* sinT, int jlo, i
     // no dense right-hand side: the arm rows carry all of it
     band_dispatch(bnr, [&](auto EC) {
       constexpr int EB = decltype(EC)::value;
+      band_constants<true>(c, blo, bnr, EB);
       hipLaunchKernelGGL((k_colsolve_band<T, EB, true>), dim3(nb, B), dim3(256),
                          sizeof(T) * colsolve_lds_elems(P, EB), s, N, c->h, P, Tg,
-                         c->rowpart.as<int>(), c->colc.as<double>(), blo, bnr, jlo, jhi, G, nb,
-                         tstride, gstride, ldr);
+                         c->rowpart.as<int>(), c->colc.as<double>(), c->bandc.as<double>(), blo,
+                         bnr, jlo, jhi, G, nb, tstride, gstride, ldr);
     });
   } else if (stages & 4) {
     const size_t lds_dyn = sizeof(T) * colsolve_lds_elems(P, E);
@@ -2043,6 +2090,8 @@ int colconst_setup(kfbi_ctx* c) {
     const int nm = N + 1, E = (nm + 63) / 64;
     KFBI_TRY(c->colc.ensure(sizeof(double) * 4 * nm));
     KFBI_TRY(c->lanef.ensure(sizeof(double) * 2 * 64 * nm));
+    KFBI_TRY(c->bandc.ensure(sizeof(double) * (kBandModeConsts + 2 * 64) * nm));
+    c->bc_nr = 0;
     hipLaunchKernelGGL(k_colconst_neu, dim3(nblk(64 * nm, 256)), dim3(256), 0, c->stream, N,
                        c->h * c->h * c->c2, E, c->colc.as<double>(), c->lanef.as<double>());
     KFBI_HIP(hipGetLastError());
@@ -2052,6 +2101,8 @@ int colconst_setup(kfbi_ctx* c) {
   const int E = E0 <= 1 ? 1 : E0 <= 2 ? 2 : E0 <= 4 ? 4 : E0 <= 8 ? 8 : E0 <= 16 ? 16 : 32;
   KFBI_TRY(c->colc.ensure(sizeof(double) * 3 * n));
   KFBI_TRY(c->lanef.ensure(sizeof(double) * 2 * 64 * n));
+  KFBI_TRY(c->bandc.ensure(sizeof(double) * (kBandModeConsts + 2 * 64) * n));
+  c->bc_nr = 0;
   hipLaunchKernelGGL(k_colconst, dim3(nblk(64 * n, 256)), dim3(256), 0, c->stream, N,
                      c->h * c->h * c->c2, E, c->colc.as<double>(), c->lanef.as<double>());
   KFBI_HIP(hipGetLastError());

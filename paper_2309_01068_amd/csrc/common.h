@@ -118,8 +118,12 @@ struct kfbi_ctx {
   kfbi::DBuf X, geo, dvec, cnt, cross, hid, vid, vraw, lab, armcnt, rowsum, armrow, armpk, armcoef,
       intptr, need, nodeidx, nodei, rowptr, rows, mknode, ext, gstat, armc, armk, armsc,
       chpos,
-      colc, lanef, cnode, ccount, mkloc, tmat, pdesc, rowpart, ckoff, cklist, ckcoef, ckmk, mqz;
+      colc, lanef, bandc, cnode, ccount, mkloc, tmat, pdesc, rowpart, ckoff, cklist, ckcoef, ckmk,
+      mqz;
   int arm_cap = 0;
+  // the band of rows (first row, rows, rows per lane) that bandc holds the column-solve
+  // constants of (bc_nr = 0: none yet)
+  int bc_lo = 0, bc_nr = 0, bc_E = 0;
   // per-apply buffers
   kfbi::DBuf mq, armr, qpart, ring, sinT, sinT32, gband, nodeval, tmpM;
   // gmres buffers
