@@ -76,9 +76,8 @@ def algorithmic_bytes(info, N, M, wbytes, batch=1):
       k_rowdst         per arm the correction and its column (8 + 4 B), per part its
                        descriptor (16 B) in; per part one row of n transformed values out
       k_colsolve       the P n w part rows in, the nb n w rows of G out, per-mode constants
-                       (3 + 128 doubles per mode) and the row-to-part offsets (an interface
-                       whose rows span at most half the grid runs k_colsolve_band instead,
-                       which reads 3 per mode; the star workloads here span more)
+                       and the row-to-part offsets; the zero box runs the band solve
+                       (k_colsolve_band: 2 + 6 doubles per mode and 2 per lane of its 64)
       k_nodes_extract  each of the R node rows of G once (R n w), per marker the 51
                        extraction values and 5 marker quantities (8 B), 6 stencil slots (4 B),
                        four traces out (8 B each)
@@ -96,7 +95,7 @@ def algorithmic_bytes(info, N, M, wbytes, batch=1):
         "k_prep": B * (M * 8 * (1 + 5) + 8 * (M // 8 + 1) + A * 8)
         + M * 8 * (2 + 1) + A * (11 * 8 + 4 + 4),
         "k_rowdst": B * (A * 8 + P * n * wbytes) + A * 4 + P * 16,
-        "k_colsolve": B * (P * n * wbytes + nb * n * wbytes) + n * 8 * (3 + 128) + (N + 2) * 4,
+        "k_colsolve": B * (P * n * wbytes + nb * n * wbytes) + n * 8 * (2 + 6 + 128) + (N + 2) * 4,
         "k_nodes_extract": B * (R * n * wbytes + M * (5 * 8 + 4 * 8)) + M * (51 * 8 + 6 * 4),
     }
 

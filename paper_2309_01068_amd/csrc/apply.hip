@@ -1634,9 +1634,7 @@ static void band_dispatch(int nr, F&& f) {
 
 // The band of rows lo .. lo + nr - 1 that holds every arm row and every node row (at least
 // two rows, inside the rows of the box condition); false when the interface has neither, or
-// when the band spans more than half of the rows: the band solve forms its row constants
-// from exp and log per lane, which costs about what the shorter recurrences save once the
-// band is that wide (measured: a band of 60% of the rows ran 1-2% slower per apply).
+// when the band needs as many rows per lane as the whole column.
 static bool solve_band(const kfbi_ctx* c, bool neu, int* lo, int* nr) {
   const int N = c->N;
   const GeoStatus& g = c->st;
@@ -1655,7 +1653,6 @@ static bool solve_band(const kfbi_ctx* c, bool neu, int* lo, int* nr) {
     else a = b - 1;
   }
   if (a < rmin || b > rmax || a > b) return false;
-  if (2 * (b - a + 1) > rmax - rmin + 1) return false;
   // nothing to gain unless the band needs fewer rows per lane than the whole column
   const int rows = rmax - rmin + 1, ef = (rows + 63) / 64;
   const int efull = neu ? (ef <= 2 ? 2 : ef <= 3 ? 3 : ef <= 5 ? 5 : ef <= 9 ? 9 : ef <= 17 ? 17 : 33)
